@@ -1,0 +1,454 @@
+/*
+ * Plain binary64 CPU reference for the dense Krylov solvers.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg do.  It shares no code, header, table or
+ * constant with the GPU library.
+ *
+ * Everything is written for a reader to check against the paper by eye:
+ * straight loops in the order the algorithms state, no blocking, no fusion.
+ * The only concession to speed is an OpenMP "parallel for" over the rows of
+ * the dense matrix-vector product; each row's sum is still the plain
+ * left-to-right loop, so the result does not depend on the thread count.
+ *
+ * Matrices are row-major: element (i, j) of A is A[i * lda + j].
+ *
+ * Status codes: 0 converged, 1 iteration limit, 2 breakdown, 3 stagnation,
+ * 4 non-finite value met, -1 invalid argument.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KO_OK 0
+#define KO_MAXITER 1
+#define KO_BREAKDOWN 2
+#define KO_STAGNATED 3
+#define KO_NONFINITE 4
+#define KO_EINVAL (-1)
+
+/* CG is restarted from its current iterate when the recursive residual says
+ * "converged" but the true residual b - A x does not; after this many
+ * restarts without meeting the tolerance the solve reports stagnation. */
+#define KO_CG_MAX_RESTARTS 16
+
+/* GMRES happy breakdown: h(k+1,k) <= this factor times ||A v(k)||. */
+#define KO_HAPPY 1e-14
+
+void ko_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+int ko_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------- BLAS-like */
+
+/* inner product x'y, summed left to right */
+double ko_dot(int n, const double *x, const double *y) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+double ko_nrm2(int n, const double *x) { return sqrt(ko_dot(n, x, x)); }
+
+/* y = A x, one row at a time (the matrix-vector product of every Krylov step) */
+void ko_matvec(int n, const double *A, long lda, const double *x, double *y) {
+#pragma omp parallel for schedule(static) if (n >= 256)
+    for (int i = 0; i < n; ++i) {
+        const double *a = A + (long)i * lda;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += a[j] * x[j];
+        y[i] = s;
+    }
+}
+
+/* r = b - A x */
+void ko_residual(int n, const double *A, long lda, const double *b, const double *x,
+                 double *r) {
+#pragma omp parallel for schedule(static) if (n >= 256)
+    for (int i = 0; i < n; ++i) {
+        const double *a = A + (long)i * lda;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += a[j] * x[j];
+        r[i] = b[i] - s;
+    }
+}
+
+/* ||A||_inf = max over rows of the row's absolute sum */
+double ko_norm_inf_mat(int n, const double *A, long lda) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += fabs(A[(long)i * lda + j]);
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+static double norm_inf_vec(int n, const double *x) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (fabs(x[i]) > m) m = fabs(x[i]);
+    return m;
+}
+
+/* out[0] = ||b - A x||_2 / ||b||_2
+ * out[1] = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf)   (normwise
+ *          backward error in the infinity norm, Rigal and Gaches)
+ * out[2] = ||b - A x||_2
+ * Returns 0, or -1 on bad arguments. */
+int ko_metrics(int n, const double *A, long lda, const double *b, const double *x,
+               double *out) {
+    if (n <= 0 || !A || !b || !x || !out || lda < n) return KO_EINVAL;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r) return KO_EINVAL;
+    ko_residual(n, A, lda, b, x, r);
+    double rn = ko_nrm2(n, r), bn = ko_nrm2(n, b);
+    out[0] = bn > 0.0 ? rn / bn : rn;
+    double den = ko_norm_inf_mat(n, A, lda) * norm_inf_vec(n, x) + norm_inf_vec(n, b);
+    double rinf = norm_inf_vec(n, r);
+    out[1] = den > 0.0 ? rinf / den : rinf;
+    out[2] = rn;
+    free(r);
+    return 0;
+}
+
+/* ------------------------------------------------------------ conjugate gradient
+ *
+ * Conjugate gradient for SPD A, Hestenes-Stiefel form (the method the paper
+ * describes in prose in its Krylov section: one matrix-vector product per
+ * iteration, A-orthogonal search directions, at most n steps in exact
+ * arithmetic; full statement in Golub and Van Loan).
+ *
+ *   r = b - A x, p = r, rho = r'r
+ *   repeat:  q = A p;  sigma = p'q  (sigma <= 0 means A is not SPD)
+ *            alpha = rho / sigma;  x = x + alpha p;  r = r - alpha q
+ *            rho' = r'r;  stop when sqrt(rho') <= tol ||b||
+ *            p = r + (rho'/rho) p;  rho = rho'
+ *
+ * When the recursive residual meets the tolerance the true residual b - A x
+ * is recomputed; if it does not meet it, CG starts again from the current x.
+ * max_iter bounds the number of products q = A p.  hist (optional) receives
+ * sqrt(rho') after every iteration.
+ */
+int ko_cg(int n, const double *A, long lda, const double *b, double *x, double tol,
+          int max_iter, int *iters_out, int *restarts_out, double *rel_res_out,
+          double *hist, int hist_cap) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || max_iter < 0)
+        return KO_EINVAL;
+    int iters = 0, restarts = 0, status = KO_MAXITER;
+    double bnorm = ko_nrm2(n, b), res = 0.0;
+    if (!isfinite(bnorm)) {
+        status = KO_NONFINITE;
+        goto done_noalloc;
+    }
+    if (bnorm == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        status = KO_OK;
+        goto done_noalloc;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r || !p || !q) {
+        free(r); free(p); free(q);
+        return KO_EINVAL;
+    }
+    int first = 1;
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        double rho = ko_dot(n, r, r);
+        res = sqrt(rho);
+        if (!isfinite(res)) { status = KO_NONFINITE; break; }
+        if (res <= tol * bnorm) { status = KO_OK; break; }
+        if (iters >= max_iter) { status = KO_MAXITER; break; }
+        if (!first) {
+            if (restarts >= KO_CG_MAX_RESTARTS) { status = KO_STAGNATED; break; }
+            ++restarts;
+        }
+        first = 0;
+        for (int i = 0; i < n; ++i) p[i] = r[i];
+        int stop = 0;
+        while (!stop) {
+            ko_matvec(n, A, lda, p, q);
+            ++iters;
+            double sigma = ko_dot(n, p, q);
+            if (!isfinite(sigma)) { status = KO_NONFINITE; stop = 2; break; }
+            if (sigma <= 0.0) { status = KO_BREAKDOWN; stop = 2; break; }
+            double alpha = rho / sigma;
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            double rho_new = ko_dot(n, r, r);
+            if (hist && iters <= hist_cap) hist[iters - 1] = sqrt(rho_new);
+            if (!isfinite(rho_new)) { status = KO_NONFINITE; stop = 2; break; }
+            if (sqrt(rho_new) <= tol * bnorm) stop = 1;
+            else if (iters >= max_iter) stop = 1;
+            else {
+                double beta = rho_new / rho;
+                for (int i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+                rho = rho_new;
+            }
+        }
+        if (stop == 2) {
+            /* breakdown / non-finite: report the true residual of the last x */
+            ko_residual(n, A, lda, b, x, r);
+            res = ko_nrm2(n, r);
+            break;
+        }
+    }
+    free(r); free(p); free(q);
+done_noalloc:
+    if (iters_out) *iters_out = iters;
+    if (restarts_out) *restarts_out = restarts;
+    if (rel_res_out) *rel_res_out = (bnorm > 0.0 && isfinite(bnorm)) ? res / bnorm : 0.0;
+    return status;
+}
+
+/* ---------------------------------------------------------------- GMRES(m)
+ *
+ * Arnoldi step as the paper prints it: project A v(k) on every v(j), j <= k,
+ * subtract, normalise by h(k+1,k) (the printed "v(k+1,k)" is read as
+ * v(k+1)).  The oracle does the projection as modified Gram-Schmidt, twice
+ * (every h(j,k) accumulates both passes); in exact arithmetic this is the
+ * same H and V as the printed classical form.
+ *
+ * Least squares: the paper stops at the basis; the minimal-residual update
+ * (Saad) is used: Givens rotations G_i = [c s; -s c] reduce H to upper
+ * triangular R, with rho = hypot(a, b) >= 0, c = a/rho, s = b/rho, applied to
+ * g = beta e1; |g(k+1)| is the residual estimate; at the end of a cycle
+ * R y = g is back-substituted and x = x0 + V y.
+ *
+ * Restart after m steps from the current x (the paper's "intermediate
+ * results as a new starting point"): r = b - A x is recomputed.  max_iter
+ * bounds the total number of Arnoldi steps over all cycles.  est (optional)
+ * receives |g(k+1)| after every step; cres (optional) the true residual norm
+ * at the start of every cycle and at exit.
+ */
+int ko_gmres(int n, const double *A, long lda, const double *b, double *x, double tol,
+             int max_iter, int m, int *iters_out, int *cycles_out, double *rel_res_out,
+             double *est, int est_cap, double *cres, int cres_cap) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || max_iter < 0 || m < 1)
+        return KO_EINVAL;
+    int steps = 0, cycles = 0, status = KO_MAXITER, ncres = 0;
+    double bnorm = ko_nrm2(n, b), res = 0.0;
+    if (!isfinite(bnorm)) {
+        if (iters_out) *iters_out = 0;
+        if (cycles_out) *cycles_out = 0;
+        if (rel_res_out) *rel_res_out = 0.0;
+        return KO_NONFINITE;
+    }
+    if (bnorm == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        if (iters_out) *iters_out = 0;
+        if (cycles_out) *cycles_out = 0;
+        if (rel_res_out) *rel_res_out = 0.0;
+        return KO_OK;
+    }
+    size_t nn = (size_t)n;
+    double *V = (double *)calloc(nn * (size_t)(m + 1), sizeof(double));
+    double *w = (double *)malloc(sizeof(double) * nn);
+    double *r = (double *)malloc(sizeof(double) * nn);
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double *R = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double *cs = (double *)calloc((size_t)m, sizeof(double));
+    double *sn = (double *)calloc((size_t)m, sizeof(double));
+    double *g = (double *)calloc((size_t)m + 1, sizeof(double));
+    double *y = (double *)calloc((size_t)m, sizeof(double));
+    if (!V || !w || !r || !H || !R || !cs || !sn || !g || !y) {
+        status = KO_EINVAL;
+        goto out;
+    }
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+#define RR(i, j) R[(size_t)(i) * (size_t)m + (size_t)(j)]
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        double beta = ko_nrm2(n, r);
+        res = beta;
+        if (cres && ncres < cres_cap) cres[ncres++] = beta;
+        if (!isfinite(beta)) { status = KO_NONFINITE; break; }
+        if (beta <= tol * bnorm) { status = KO_OK; break; }
+        if (steps >= max_iter) { status = KO_MAXITER; break; }
+        for (int i = 0; i < n; ++i) V[i] = r[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int kd = 0, fail = 0;
+        for (int k = 0; k < m; ++k) {
+            const double *vk = V + (size_t)k * nn;
+            ko_matvec(n, A, lda, vk, w);
+            ++steps;
+            double avk = ko_nrm2(n, w);
+            for (int j = 0; j <= k; ++j) HH(j, k) = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j = 0; j <= k; ++j) {
+                    const double *vj = V + (size_t)j * nn;
+                    double t = ko_dot(n, vj, w);
+                    HH(j, k) += t;
+                    for (int i = 0; i < n; ++i) w[i] = w[i] - t * vj[i];
+                }
+            }
+            double hk1 = ko_nrm2(n, w);
+            HH(k + 1, k) = hk1;
+            for (int j = 0; j <= k + 1; ++j) RR(j, k) = HH(j, k);
+            for (int i = 0; i < k; ++i) {
+                double a = RR(i, k), bb = RR(i + 1, k);
+                RR(i, k) = cs[i] * a + sn[i] * bb;
+                RR(i + 1, k) = -sn[i] * a + cs[i] * bb;
+            }
+            double rho = hypot(RR(k, k), RR(k + 1, k));
+            if (!isfinite(rho) || !isfinite(avk)) { status = KO_NONFINITE; fail = 1; break; }
+            if (rho == 0.0) { status = KO_BREAKDOWN; fail = 1; break; }
+            cs[k] = RR(k, k) / rho;
+            sn[k] = RR(k + 1, k) / rho;
+            RR(k, k) = rho;
+            RR(k + 1, k) = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            kd = k + 1;
+            if (est && steps <= est_cap) est[steps - 1] = fabs(g[k + 1]);
+            if (hk1 <= KO_HAPPY * avk) break;                 /* happy breakdown */
+            double *vn = V + (size_t)(k + 1) * nn;
+            for (int i = 0; i < n; ++i) vn[i] = w[i] / hk1;
+            if (fabs(g[k + 1]) <= tol * bnorm || steps >= max_iter) break;
+        }
+        if (kd > 0) {
+            for (int i = kd - 1; i >= 0; --i) {
+                double s = g[i];
+                for (int j = i + 1; j < kd; ++j) s -= RR(i, j) * y[j];
+                y[i] = s / RR(i, i);
+            }
+            for (int j = 0; j < kd; ++j) {
+                const double *vj = V + (size_t)j * nn;
+                for (int i = 0; i < n; ++i) x[i] = x[i] + y[j] * vj[i];
+            }
+        }
+        ++cycles;
+        if (fail) {
+            ko_residual(n, A, lda, b, x, r);
+            res = ko_nrm2(n, r);
+            break;
+        }
+    }
+#undef HH
+#undef RR
+out:
+    free(V); free(w); free(r); free(H); free(R); free(cs); free(sn); free(g); free(y);
+    if (iters_out) *iters_out = steps;
+    if (cycles_out) *cycles_out = cycles;
+    if (rel_res_out) *rel_res_out = res / bnorm;
+    return status;
+}
+
+/* k Arnoldi steps from v0 (normalised first), modified Gram-Schmidt twice.
+ * V: n x (k+1), vector j stored contiguously at V + j*n.  H: (k+1) x k
+ * row-major, the unrotated Hessenberg matrix.  Returns the number of steps
+ * completed (fewer than k after a happy breakdown), or -1. */
+int ko_arnoldi(int n, const double *A, long lda, const double *v0, int k, double *V,
+               double *H) {
+    if (n <= 0 || !A || !v0 || !V || !H || lda < n || k < 1) return KO_EINVAL;
+    size_t nn = (size_t)n;
+    double nv = ko_nrm2(n, v0);
+    if (!(nv > 0.0)) return KO_EINVAL;
+    memset(H, 0, sizeof(double) * (size_t)(k + 1) * (size_t)k);
+    for (int i = 0; i < n; ++i) V[i] = v0[i] / nv;
+    double *w = (double *)malloc(sizeof(double) * nn);
+    if (!w) return KO_EINVAL;
+    int done = 0;
+    for (int c = 0; c < k; ++c) {
+        ko_matvec(n, A, lda, V + (size_t)c * nn, w);
+        double avk = ko_nrm2(n, w);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j <= c; ++j) {
+                const double *vj = V + (size_t)j * nn;
+                double t = ko_dot(n, vj, w);
+                H[(size_t)j * (size_t)k + (size_t)c] += t;
+                for (int i = 0; i < n; ++i) w[i] = w[i] - t * vj[i];
+            }
+        double h = ko_nrm2(n, w);
+        H[(size_t)(c + 1) * (size_t)k + (size_t)c] = h;
+        done = c + 1;
+        if (h <= KO_HAPPY * avk) break;
+        for (int i = 0; i < n; ++i) V[(size_t)(c + 1) * nn + i] = w[i] / h;
+    }
+    free(w);
+    return done;
+}
+
+/* ------------------------------------------------- Gaussian elimination (GEPP)
+ *
+ * Right-looking LU with partial pivoting as the paper lists it in its direct
+ * methods section: at step k pick the row v >= k with the largest |A(v,k)|,
+ * swap A(k,k:n) with A(v,k:n), record p(k) = v, divide the column below the
+ * pivot by it and apply the rank-1 update to the trailing block.  Only the
+ * columns k:n are swapped, so the forward substitution applies the
+ * interchanges step by step.  A is overwritten by L (unit, below the
+ * diagonal) and U.  Returns 0, or k+1 if U(k,k) == 0 (singular). */
+int ko_lu_factor(int n, double *A, long lda, int *piv) {
+    if (n <= 0 || !A || !piv || lda < n) return KO_EINVAL;
+    int sing = 0;
+    for (int k = 0; k < n - 1; ++k) {
+        int v = k;
+        double best = fabs(A[(long)k * lda + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double a = fabs(A[(long)i * lda + k]);
+            if (a > best) { best = a; v = i; }
+        }
+        if (v != k)
+            for (int j = k; j < n; ++j) {
+                double t = A[(long)k * lda + j];
+                A[(long)k * lda + j] = A[(long)v * lda + j];
+                A[(long)v * lda + j] = t;
+            }
+        piv[k] = v;
+        double akk = A[(long)k * lda + k];
+        if (akk != 0.0) {
+            for (int i = k + 1; i < n; ++i) A[(long)i * lda + k] /= akk;
+            for (int i = k + 1; i < n; ++i) {
+                double lik = A[(long)i * lda + k];
+                for (int j = k + 1; j < n; ++j)
+                    A[(long)i * lda + j] -= lik * A[(long)k * lda + j];
+            }
+        } else if (!sing) {
+            sing = k + 1;
+        }
+    }
+    piv[n - 1] = n - 1;
+    if (!sing && A[(long)(n - 1) * lda + (n - 1)] == 0.0) sing = n;
+    return sing;
+}
+
+/* Solve with the factors of ko_lu_factor: L y = P b (interchanges applied in
+ * step order), then U x = y by back substitution. */
+int ko_lu_solve(int n, const double *LU, long lda, const int *piv, const double *b,
+                double *x) {
+    if (n <= 0 || !LU || !piv || !b || !x || lda < n) return KO_EINVAL;
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!y) return KO_EINVAL;
+    for (int i = 0; i < n; ++i) y[i] = b[i];
+    for (int k = 0; k < n - 1; ++k) {
+        int v = piv[k];
+        if (v != k) { double t = y[k]; y[k] = y[v]; y[v] = t; }
+        for (int i = k + 1; i < n; ++i) y[i] -= LU[(long)i * lda + k] * y[k];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int j = i + 1; j < n; ++j) s -= LU[(long)i * lda + j] * x[j];
+        x[i] = s / LU[(long)i * lda + i];
+    }
+    free(y);
+    return 0;
+}

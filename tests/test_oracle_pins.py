@@ -1,0 +1,387 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself.
+
+* exact-rational brute force of the Krylov iterates (CG: the A-norm minimiser
+  over x0 + K_k; GMRES: the residual minimiser over x0 + K_k), solved with
+  Python fractions, never with the oracle's own arithmetic;
+* finite termination (CG in at most n steps, and in d steps for d distinct
+  eigenvalues; full GMRES likewise) from the Krylov section's claims;
+* the Arnoldi relation A V_k = V_{k+1} Hbar_k with orthonormal V;
+* GMRES's non-increasing residual, and full GMRES <= CG on SPD systems;
+* LAPACK (numpy.linalg.solve) and hand-worked fixtures for GEPP;
+* special cases and the hand-worked backward-error example.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import nonsym_problem, spd_problem
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ exact helpers
+
+def _fr_solve(M, v):
+    """Solve M y = v exactly (Gauss-Jordan over Fractions, nonzero pivot)."""
+    k = len(v)
+    aug = [list(M[i]) + [v[i]] for i in range(k)]
+    for c in range(k):
+        p = next(r for r in range(c, k) if aug[r][c] != 0)
+        aug[c], aug[p] = aug[p], aug[c]
+        piv = aug[c][c]
+        aug[c] = [e / piv for e in aug[c]]
+        for r in range(k):
+            if r != c and aug[r][c] != 0:
+                f = aug[r][c]
+                aug[r] = [a - f * b for a, b in zip(aug[r], aug[c])]
+    return [aug[i][k] for i in range(k)]
+
+
+def _fr_matvec(A, x):
+    return [sum((a * b for a, b in zip(row, x)), Fraction(0)) for row in A]
+
+
+def _fr_krylov(A, r0, k):
+    K = [r0]
+    for _ in range(k - 1):
+        K.append(_fr_matvec(A, K[-1]))
+    return K  # list of k vectors
+
+
+def _fr_dot(x, y):
+    return sum((a * b for a, b in zip(x, y)), Fraction(0))
+
+
+def exact_cg_iterate(A, b, k):
+    """argmin over x in K_k(A, b) of ||x - x*||_A  (x0 = 0): (K'AK) y = K'b."""
+    Af = [[Fraction(int(a)) for a in row] for row in A]
+    bf = [Fraction(int(v)) for v in b]
+    K = _fr_krylov(Af, bf, k)
+    AK = [_fr_matvec(Af, kv) for kv in K]
+    M = [[_fr_dot(K[i], AK[j]) for j in range(k)] for i in range(k)]
+    rhs = [_fr_dot(K[i], bf) for i in range(k)]
+    y = _fr_solve(M, rhs)
+    n = len(bf)
+    return np.array([float(sum((y[j] * K[j][i] for j in range(k)), Fraction(0))) for i in range(n)])
+
+
+def exact_gmres_iterate(Af, bf, x0f, k):
+    """argmin over x in x0 + K_k(A, r0) of ||b - A x||_2: (AK)'(AK) y = (AK)' r0."""
+    r0 = [bi - ai for bi, ai in zip(bf, _fr_matvec(Af, x0f))]
+    K = _fr_krylov(Af, r0, k)
+    AK = [_fr_matvec(Af, kv) for kv in K]
+    M = [[_fr_dot(AK[i], AK[j]) for j in range(k)] for i in range(k)]
+    rhs = [_fr_dot(AK[i], r0) for i in range(k)]
+    y = _fr_solve(M, rhs)
+    n = len(bf)
+    return [x0f[i] + sum((y[j] * K[j][i] for j in range(k)), Fraction(0)) for i in range(n)]
+
+
+def _int_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.integers(-3, 4, size=(n, n))
+    return M.T @ M + 2 * np.eye(n, dtype=np.int64)
+
+
+def _int_nonsym(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.integers(-2, 3, size=(n, n))
+    return M + 6 * np.eye(n, dtype=np.int64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+TINY = 1e-300  # a tolerance the iteration never meets: runs exactly max_iter steps
+
+
+# ---------------------------------------------------------------- CG pins
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3)])
+def test_cg_iterates_match_exact_rational_minimiser(n, seed):
+    A = _int_spd(n, seed)
+    b = np.random.default_rng(seed + 10).integers(-5, 6, size=n)
+    for k in range(1, n + 1):
+        x, info = oracle.cg(A.astype(float), b.astype(float), tol=TINY, max_iter=k)
+        assert info["iters"] == k
+        xe = exact_cg_iterate(A, b, k)
+        assert _rel(x, xe) <= 1e-12, (k, _rel(x, xe))
+
+
+def test_cg_finite_termination_at_most_n_steps():
+    # exact arithmetic ends in <= n steps; with a spread spectrum rounding can
+    # delay it by a few steps, so the pin uses a mild condition number
+    for seed in range(3):
+        p = spd_problem(16, 4.0, seed=seed, config_id=90)
+        x, info = oracle.cg(p.A, p.b, tol=1e-10, max_iter=100)
+        assert info["status"] == 0
+        assert info["iters"] <= 16
+        assert info["rel_res"] <= 1e-10
+
+
+def test_cg_two_distinct_eigenvalues_two_steps():
+    rng = np.random.default_rng(5)
+    n = 40
+    u = rng.standard_normal(n)
+    A = np.eye(n) + np.outer(u, u)          # eigenvalues 1 and 1 + u'u
+    b = rng.standard_normal(n)
+    x, info = oracle.cg(A, b, tol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 2
+    assert _rel(x, np.linalg.solve(A, b)) <= 1e-12
+
+
+def test_cg_diagonal_d_distinct_values_d_steps():
+    vals = np.array([1.0, 2.0, 5.0, 9.0])
+    n = 32
+    d = np.tile(vals, n // 4)
+    A = np.diag(d)
+    b = np.ones(n)
+    x, info = oracle.cg(A, b, tol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 4
+    assert _rel(x, b / d) <= 1e-13
+
+
+def test_cg_energy_norm_strictly_decreasing():
+    p = spd_problem(40, 1e3, seed=4, config_id=91)
+    xs = np.linalg.solve(p.A, p.b)
+    prev = np.inf
+    for k in range(1, 30):
+        x, _ = oracle.cg(p.A, p.b, tol=TINY, max_iter=k)
+        e = x - xs
+        en = float(e @ p.A @ e)
+        assert en < prev
+        prev = en
+
+
+def test_cg_residuals_mutually_orthogonal():
+    # r_i' r_j = 0 for i != j (exact arithmetic); checked on the first steps
+    p = spd_problem(60, 50.0, seed=6, config_id=92)
+    rs = []
+    for k in range(0, 6):
+        if k == 0:
+            x = np.zeros(60)
+        else:
+            x, _ = oracle.cg(p.A, p.b, tol=TINY, max_iter=k)
+        r = p.b - p.A @ x
+        rs.append(r / np.linalg.norm(r))
+    G = np.array([[a @ b for b in rs] for a in rs])
+    assert np.max(np.abs(G - np.eye(len(rs)))) <= 1e-10
+
+
+def test_cg_breakdown_on_indefinite():
+    A = np.diag([1.0, -1.0, 2.0])
+    b = np.array([1.0, 1.0, 0.0])   # p'Ap = 0 at step 1
+    x, info = oracle.cg(A, b, tol=1e-10)
+    assert info["status"] == 2
+
+
+# ------------------------------------------------------------- GMRES pins
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3)])
+def test_gmres_iterates_match_exact_least_squares(n, seed):
+    A = _int_nonsym(n, seed)
+    b = np.random.default_rng(seed + 20).integers(-5, 6, size=n)
+    Af = [[Fraction(int(a)) for a in row] for row in A]
+    bf = [Fraction(int(v)) for v in b]
+    zero = [Fraction(0)] * n
+    for k in range(1, n + 1):
+        x, info = oracle.gmres(A.astype(float), b.astype(float), tol=TINY, max_iter=k, restart=n)
+        assert info["iters"] == k
+        xe = np.array([float(v) for v in exact_gmres_iterate(Af, bf, zero, k)])
+        assert _rel(x, xe) <= 1e-12, (k, _rel(x, xe))
+
+
+def test_gmres_restarted_iterates_match_composed_exact_minimisers():
+    n, m = 6, 2
+    A = _int_nonsym(n, 7)
+    b = np.random.default_rng(8).integers(-5, 6, size=n)
+    Af = [[Fraction(int(a)) for a in row] for row in A]
+    bf = [Fraction(int(v)) for v in b]
+    xe = [Fraction(0)] * n
+    for cyc in range(1, 4):
+        xe = exact_gmres_iterate(Af, bf, xe, m)
+        x, info = oracle.gmres(A.astype(float), b.astype(float), tol=TINY, max_iter=m * cyc,
+                               restart=m)
+        assert info["cycles"] == cyc
+        assert _rel(x, np.array([float(v) for v in xe])) <= 1e-12
+
+
+def test_full_gmres_terminates_in_n_steps():
+    p = nonsym_problem(24, seed=2, config_id=93)
+    x, info = oracle.gmres(p.A, p.b, tol=1e-12, restart=24, max_iter=24)
+    assert info["status"] == 0 and info["iters"] <= 24
+
+
+def test_gmres_rank_one_perturbation_two_steps():
+    rng = np.random.default_rng(9)
+    n = 50
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    A = np.eye(n) + np.outer(u, v)
+    assert abs(1 + v @ u) > 1e-3
+    b = rng.standard_normal(n)
+    x, info = oracle.gmres(A, b, tol=1e-10, restart=30)
+    assert info["status"] == 0 and info["iters"] <= 2
+    assert _rel(x, np.linalg.solve(A, b)) <= 1e-11
+
+
+def test_arnoldi_relation_and_orthonormality():
+    p = nonsym_problem(200, seed=3, config_id=94)
+    v0 = np.random.default_rng(1).standard_normal(200)
+    V, H, k = oracle.arnoldi(p.A, v0, 30)
+    assert k == 30 and V.shape == (200, 31) and H.shape == (31, 30)
+    AF = np.linalg.norm(p.A)
+    assert np.linalg.norm(p.A @ V[:, :30] - V @ H) <= 1e-13 * AF
+    assert np.linalg.norm(V.T @ V - np.eye(31)) <= 1e-13
+    assert np.allclose(np.tril(H, -2), 0.0)               # upper Hessenberg
+    assert np.all(np.diag(H, -1) > 0)
+    # the first vector is v0 normalised
+    assert _rel(V[:, 0], v0 / np.linalg.norm(v0)) <= 1e-15
+
+
+def test_gmres_residual_non_increasing():
+    p = nonsym_problem(300, seed=4, config_id=95)
+    x, info = oracle.gmres(p.A, p.b, tol=1e-12, restart=5, max_iter=400, hist=True)
+    assert info["status"] == 0
+    cres = info["cres"]
+    assert len(cres) >= 3
+    assert np.all(cres[1:] <= cres[:-1] * (1 + 1e-12))
+    est = info["est"]
+    m = 5
+    for c in range(info["cycles"]):
+        seg = est[c * m:(c + 1) * m]
+        assert np.all(seg[1:] <= seg[:-1] * (1 + 1e-12))
+
+
+def test_full_gmres_residual_below_cg_on_spd():
+    p = spd_problem(50, 200.0, seed=5, config_id=96)
+    for k in range(1, 20):
+        xc, _ = oracle.cg(p.A, p.b, tol=TINY, max_iter=k)
+        xg, _ = oracle.gmres(p.A, p.b, tol=TINY, max_iter=k, restart=50)
+        rc = np.linalg.norm(p.b - p.A @ xc)
+        rg = np.linalg.norm(p.b - p.A @ xg)
+        assert rg <= rc * (1 + 1e-10), k
+
+
+# ---------------------------------------------------------- GEPP and solves
+
+def _read_fixture(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows.setdefault(key, []).append([float(v) for v in vals])
+    return rows
+
+
+def test_gepp_hand_worked_3x3():
+    fx = _read_fixture("gepp_3x3.txt")
+    A, b = np.array(fx["A"]), np.array(fx["b"][0])
+    LU, piv, s = oracle.lu_factor(A)
+    assert s == 0
+    assert list(piv) == [int(v) for v in fx["piv"][0]]
+    assert np.array_equal(LU, np.array(fx["LU"]))
+    assert np.array_equal(oracle.lu_solve(LU, piv, b), np.array(fx["x"][0]))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 100])
+def test_gepp_matches_lapack(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    x = oracle.gepp_solve(A, b)
+    xl = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A)
+    assert _rel(x, xl) <= 10 * kappa * n * np.finfo(float).eps
+
+
+def test_gepp_detects_singular():
+    A = np.array([[1.0, 2.0], [2.0, 4.0]])
+    _, _, s = oracle.lu_factor(A)
+    assert s == 2
+
+
+def test_krylov_agrees_with_gepp_on_small_systems():
+    p = spd_problem(64, 1e2, seed=7, config_id=97)
+    xg = oracle.gepp_solve(p.A, p.b)
+    x, info = oracle.cg(p.A, p.b, tol=1e-12)
+    assert info["status"] == 0
+    assert _rel(x, xg) <= 1e2 * 1e-12 * 10
+    q = nonsym_problem(64, seed=7, config_id=97)
+    xg = oracle.gepp_solve(q.A, q.b)
+    x, info = oracle.gmres(q.A, q.b, tol=1e-12, restart=30)
+    assert info["status"] == 0
+    assert _rel(x, xg) <= 10 * np.linalg.cond(q.A) * 1e-12
+
+
+def test_known_solution_error_bound():
+    kappa = 1e3
+    p = spd_problem(256, kappa, seed=8, config_id=98)
+    x, info = oracle.cg(p.A, p.b, tol=1e-10)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10
+    u = np.finfo(float).eps / 2
+    assert _rel(x, p.x_true) <= kappa * info["rel_res"] + kappa * 256 * u
+
+
+# --------------------------------------------------------- special cases
+
+def test_n_equals_one():
+    A = np.array([[4.0]])
+    b = np.array([3.0])
+    x, info = oracle.cg(A, b, tol=1e-12)
+    assert info["iters"] == 1 and abs(x[0] - 0.75) <= 1e-16
+    x, info = oracle.gmres(A, b, tol=1e-12)
+    assert info["iters"] == 1 and abs(x[0] - 0.75) <= 1e-16
+
+
+def test_identity_one_step():
+    b = np.random.default_rng(0).standard_normal(17)
+    for solve in (oracle.cg, oracle.gmres):
+        x, info = solve(np.eye(17), b, tol=1e-12)
+        assert info["iters"] == 1 and np.array_equal(x, b)
+
+
+def test_zero_rhs_returns_zero():
+    A = np.eye(5) * 3
+    for solve in (oracle.cg, oracle.gmres):
+        x, info = solve(A, np.zeros(5), x0=np.ones(5))
+        assert info["status"] == 0 and info["iters"] == 0 and np.all(x == 0)
+
+
+def test_exact_initial_guess_zero_iterations():
+    p = spd_problem(30, 10.0, seed=1, config_id=99)
+    for solve in (oracle.cg, oracle.gmres):
+        x, info = solve(p.A, p.b, x0=p.x_true, tol=1e-10)
+        assert info["iters"] == 0 and info["status"] == 0
+
+
+def test_nonfinite_rhs():
+    b = np.array([1.0, np.nan, 0.0])
+    for solve in (oracle.cg, oracle.gmres):
+        _, info = solve(np.eye(3), b)
+        assert info["status"] == 4
+
+
+def test_maxiter_status():
+    p = spd_problem(100, 1e4, seed=2, config_id=99)
+    _, info = oracle.cg(p.A, p.b, tol=1e-12, max_iter=5)
+    assert info["status"] == 1 and info["iters"] == 5
+    q = nonsym_problem(100, seed=2, config_id=99)
+    _, info = oracle.gmres(q.A, q.b, tol=1e-14, max_iter=7, restart=3)
+    assert info["status"] == 1 and info["iters"] == 7 and info["cycles"] == 3
+
+
+def test_backward_error_hand_worked_2x2():
+    fx = _read_fixture("eta_inf_2x2.txt")
+    A, b, x = np.array(fx["A"]), np.array(fx["b"][0]), np.array(fx["x"][0])
+    m = oracle.metrics(A, b, x)
+    assert m["eta_inf"] == fx["eta_inf"][0][0]
+    assert abs(m["rel_res"] ** 2 - fx["rel_res_sq"][0][0]) <= 1e-16
