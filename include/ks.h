@@ -1,0 +1,178 @@
+/*
+ * ks.h - dense Krylov solvers for MI355X (gfx950), C ABI.
+ *
+ * Solves A x = b for a dense n x n matrix A (the linear system of the paper's
+ * Krylov section) with
+ *   - conjugate gradient (CG) when A is symmetric positive definite, and
+ *   - restarted GMRES(m) otherwise (Arnoldi step of the paper's GMRES
+ *     pseudo-code, restart after m steps from the current iterate),
+ * in binary64, or with an inner solve on a binary32 / bfloat16 copy of A and
+ * binary64 iterative refinement around it.
+ *
+ * The call sequence follows the host flow of the paper's "parallel
+ * implementation" section (allocate device memory, copy, pick the launch
+ * grid, run the kernels, copy back, clean up), reduced to
+ *     ks_workspace_bytes -> ks_create -> ks_solve ... -> ks_free.
+ *
+ * Memory model
+ *   - Every pointer argument named d_* is a device pointer (hipMalloc or a
+ *     torch tensor's data_ptr) on the current HIP device.  A, b, x and the
+ *     workspace are owned by the caller; the library never frees them.
+ *   - A is row-major: element (i, j) is dA[i * lda + j], lda >= n.  When A is
+ *     16-byte aligned and lda * 8 is a multiple of 16 the solver reads A in
+ *     place ("borrowed"; it must stay valid and unmodified until ks_free);
+ *     otherwise ks_create copies it into the workspace with a padded lda.
+ *   - All work is enqueued on the HIP stream given to ks_create (NULL = the
+ *     null stream).  ks_solve returns after the solve has finished on that
+ *     stream, with x and *info final.
+ *   - A solver is not re-entrant: one ks_solve at a time per solver.
+ *     Distinct solvers may run concurrently on distinct streams.
+ *
+ * Errors: every int-returning call returns KS_OK (0), a positive numerical
+ * outcome (x then holds the last iterate) or a negative usage / system error
+ * (outputs untouched).  No C++ exception crosses this interface.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define KS_OK 0
+#define KS_MAXITER 1     /* iteration limit reached before the tolerance        */
+#define KS_BREAKDOWN 2   /* CG: p'Ap <= 0 (A not SPD); GMRES: singular H        */
+#define KS_STAGNATED 3   /* refinement / restarts stopped making progress       */
+#define KS_NONFINITE 4   /* a NaN or Inf appeared (in b, x0, A or an iterate)    */
+#define KS_EINVAL (-1)   /* bad argument (n <= 0, lda < n, NULL, tol <= 0, ...) */
+#define KS_ENOMEM (-2)   /* workspace too small, or allocation failed           */
+#define KS_EHIP (-3)     /* a HIP runtime call failed                            */
+#define KS_EDEVICE (-4)  /* current device is not gfx950                         */
+
+/* ---- method / precision ---------------------------------------------- */
+#define KS_CG 0
+#define KS_GMRES 1
+
+#define KS_FP64 0        /* everything in binary64                               */
+#define KS_IR_FP32 1     /* inner solve on binary32 A, binary64 refinement       */
+#define KS_IR_BF16 2     /* inner solve on bfloat16 A (fp32 accumulation)        */
+
+/* element types for the kernel-level entry points */
+#define KS_DT_F64 0
+#define KS_DT_F32 1
+#define KS_DT_BF16 2
+
+/* ks_params.flags */
+#define KS_FLAG_TIMING 1 /* time every A*v launch with HIP events (info->gemv_ms) */
+
+typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
+
+typedef struct {
+    int32_t n;          /* order of A, >= 1                                       */
+    int32_t method;     /* KS_CG or KS_GMRES                                      */
+    int64_t lda;        /* leading dimension of A in elements, >= n               */
+    int32_t precision;  /* KS_FP64, KS_IR_FP32 or KS_IR_BF16                      */
+    int32_t max_iter;   /* FP64: A*v products in the Krylov loop over the whole
+                           solve; IR: per inner solve                              */
+    double tol;         /* FP64: stop at ||b - A x||_2 <= tol ||b||_2 (checked on
+                           the true residual); IR: stop at the normwise backward
+                           error ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf)      */
+    int32_t restart;    /* m of GMRES(m), 1..KS_MAX_RESTART; ignored by CG        */
+    int32_t max_outer;  /* IR: refinement steps (default 30)                     */
+    double inner_tol;   /* IR: relative tolerance of each inner solve (1e-4)     */
+    int32_t poll_every; /* host checks the device's stop flag every this many
+                           iterations (0 = chosen from n)                          */
+    int32_t flags;      /* KS_FLAG_*                                              */
+} ks_params;
+
+#define KS_MAX_RESTART 128
+
+typedef struct {
+    int32_t status;        /* KS_OK or a positive outcome                           */
+    int32_t iters;         /* A*v products inside the Krylov loops (all levels)     */
+    int32_t outer_iters;   /* IR refinement steps (0 for KS_FP64)                   */
+    int32_t restarts;      /* GMRES cycles beyond the first / CG restarts            */
+    double rel_res;        /* ||b - A x||_2 / ||b||_2 of the returned x (binary64)  */
+    double backward_err;   /* ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf)    */
+    double elapsed_ms;     /* device time of the solve (HIP events on the stream)   */
+    double gemv_ms;        /* with KS_FLAG_TIMING: summed time of the A*v launches  */
+    int32_t gemv_calls;    /* with KS_FLAG_TIMING: number of timed A*v launches     */
+    int32_t precision_used;/* IR: precision of the last inner solve after fallback  */
+} ks_info;
+
+/* Fill *p with defaults for an n x n system (lda = n, tol 1e-10, max_iter
+ * 10 n, restart 30, KS_FP64, inner_tol 1e-4, max_outer 30).  KS_EINVAL if
+ * p is NULL, n < 1 or method unknown. */
+int ks_params_init(ks_params *p, int32_t n, int32_t method);
+
+/* Bytes of device workspace ks_create needs for these parameters (including
+ * room for a padded copy of A in case it cannot be borrowed, and the binary32 /
+ * bfloat16 copy for the IR precisions).  *bytes is written on KS_OK. */
+int ks_workspace_bytes(const ks_params *p, size_t *bytes);
+
+/* Bytes needed when A is borrowed (aligned, see above): smaller than
+ * ks_workspace_bytes by the size of the binary64 copy. */
+int ks_workspace_bytes_borrowed(const ks_params *p, size_t *bytes);
+
+/* Create a solver for A.  d_ws must be 256-byte aligned and ws_bytes at least
+ * what ks_workspace_bytes (or ks_workspace_bytes_borrowed, when A can be
+ * borrowed) returned; d_ws == NULL with ws_bytes == 0 makes the library
+ * allocate (and later free) its own workspace.  Enqueues the set-up work
+ * (padding copy, ||A||_inf, low-precision copy) on `stream` and returns
+ * without waiting.  Errors: KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_EDEVICE. */
+int ks_create(ks_solver **out, const ks_params *p, const double *d_A, void *d_ws,
+              size_t ws_bytes, void *stream);
+
+/* Solve A x = b.  d_b: n binary64 values; d_x: n binary64 values, x0 on
+ * entry, the solution on return (the last iterate for a positive status).
+ * Both must be 16-byte aligned (KS_EINVAL otherwise).
+ * Returns the status (also in info->status); info may be NULL. */
+int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info);
+
+/* Run k Arnoldi steps (classical Gram-Schmidt applied twice) from d_v0,
+ * which is normalised first.  d_V receives the basis, vector j at
+ * d_V + j * n (n x (k+1)); d_H the unrotated (k+1) x k Hessenberg matrix,
+ * row-major; *k_done the number of steps completed (< k after a happy
+ * breakdown).  Uses the solver's workspace; the solver must have been
+ * created with method KS_GMRES, precision KS_FP64 and restart >= k. */
+int ks_arnoldi(ks_solver *s, const double *d_v0, int32_t k, double *d_V, double *d_H,
+               int32_t *k_done);
+
+/* Release the handle and any memory the library allocated itself.  NULL-safe.
+ * Waits for the solver's stream. */
+void ks_free(ks_solver *s);
+
+/* Static English text for a status code. */
+const char *ks_strerror(int status);
+
+/* ---- kernel-level entry points ------------------------------------------
+ * The solvers' own kernels, exposed for tests and measurement.  All enqueue
+ * on `stream` and return without waiting. */
+
+/* y = A v with A n x n row-major of element type a_dtype (KS_DT_*).  For
+ * KS_DT_F64 v and y are binary64 with binary64 accumulation; for KS_DT_F32 and
+ * KS_DT_BF16 they are binary32 with binary32 accumulation.  d_A must be
+ * 16-byte aligned and lda * sizeof(element) a multiple of 16 (else KS_EINVAL);
+ * d_v and d_y 16-byte aligned. */
+int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *d_A, const void *d_v,
+            void *d_y, void *stream);
+
+/* Convert an n x n binary64 matrix (lda_src) into dst_dtype (KS_DT_F32:
+ * round to nearest even; KS_DT_BF16: round to binary32, then to bfloat16,
+ * both nearest even) with leading dimension lda_dst. */
+int ks_convert(int32_t n, int64_t lda_src, const double *d_src, int32_t dst_dtype,
+               int64_t lda_dst, void *d_dst, void *stream);
+
+/* Streaming read of `bytes` bytes (multiple of 16) from d_src, with a
+ * checksum written to d_sink[0]: the read ceiling of the memory system that
+ * the GEMV is measured against. */
+int ks_read_ceiling(const void *d_src, size_t bytes, double *d_sink, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

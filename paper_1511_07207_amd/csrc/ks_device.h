@@ -1,0 +1,135 @@
+// Device helpers shared by the kernels: wave64 DPP reductions, block
+// reductions, deterministic cross-block reductions and bfloat16 conversion.
+// gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ks_internal.h"
+
+namespace ks {
+
+// ---------------------------------------------------------------- DPP moves
+// dpp_ctrl encodings (GFX9 DPP): quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
+// row_ror:4 = 0x124, row_ror:8 = 0x128.  Every source lane is valid for these
+// patterns, so bound_ctrl does not matter.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    uint64_t u = __builtin_bit_cast(uint64_t, x);
+    int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wave.  The result is exact-order deterministic
+// and is read from lane 0 (other lanes may differ in the last bit).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    x += dpp<0x124>(x);
+    x += dpp<0x128>(x);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+    x = fmax(x, dpp<0xB1>(x));
+    x = fmax(x, dpp<0x4E>(x));
+    x = fmax(x, dpp<0x124>(x));
+    x = fmax(x, dpp<0x128>(x));
+    x = fmax(x, __shfl_xor(x, 16));
+    x = fmax(x, __shfl_xor(x, 32));
+    return x;
+}
+
+// Block sum; the result is valid in thread 0 only.  smem: NT/64 entries.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *smem) {
+    constexpr int NW = NT / WAVE;
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    if (lane == 0) smem[w] = v;
+    __syncthreads();
+    T s = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) s += smem[i];
+    }
+    return s;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_max(T v, T *smem) {
+    constexpr int NW = NT / WAVE;
+    v = wave_max(v);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    if (lane == 0) smem[w] = v;
+    __syncthreads();
+    T s = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) s = fmax(s, smem[i]);
+    }
+    return s;
+}
+
+// ------------------------------------------------- cross-block reductions
+// A kernel writes one partial per block; the *next* kernel reduces them.  The
+// kernel boundary makes the partials visible device-wide, so no atomics or
+// device-scope fences are needed (on gfx950 such a fence writes back and
+// invalidates the XCD's L2, which costs more than the GEMV itself when every
+// block does it).  Every consumer block sums the partials in the same fixed
+// order, so all blocks obtain bitwise the same scalar and the result is
+// reproducible run to run.
+
+// Sum of partial[i * stride], i < count, returned to every thread of the block.
+template <int NT>
+__device__ __forceinline__ double reduce_partials_all(const double *partial, int count, int stride) {
+    __shared__ double sm_r[NT / WAVE];
+    __shared__ double sm_out;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += NT) s += partial[(size_t)i * stride];
+    s = block_sum<NT>(s, sm_r);
+    if (threadIdx.x == 0) sm_out = s;
+    __syncthreads();
+    return sm_out;
+}
+
+template <int NT>
+__device__ __forceinline__ double reduce_partials_max_all(const double *partial, int count,
+                                                          int stride) {
+    __shared__ double sm_r[NT / WAVE];
+    __shared__ double sm_out;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += NT) s = fmax(s, partial[(size_t)i * stride]);
+    s = block_max<NT>(s, sm_r);
+    if (threadIdx.x == 0) sm_out = s;
+    __syncthreads();
+    return sm_out;
+}
+
+// ------------------------------------------------------------- conversions
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// binary32 -> bfloat16, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
+
+}  // namespace ks

@@ -1,0 +1,783 @@
+// Host side of the dense Krylov library: workspace layout, the CG / GMRES(m)
+// / iterative-refinement drivers and the C ABI of ks.h.
+//
+// The drivers follow the host flow of the paper's parallel-implementation
+// section (device memory, launch grid, kernels, copy back), with every
+// per-iteration scalar kept on the device: the host enqueues a chunk of
+// iterations, then reads the 256-byte State once to decide whether to go on.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ks.h"
+#include "ks_internal.h"
+
+using namespace ks;
+
+#define HIPCHK(expr)                          \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) return KS_EHIP; \
+    } while (0)
+
+namespace {
+
+constexpr int CG_MAX_RESTARTS = 16;  // true-residual restarts before "stagnated"
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    int ldv = 0;
+    int m = 0;
+    size_t st_off = 0;      // two State structs: [0] outer / plain, [1] inner
+    size_t gm_off = 0;      // GMRES small arrays (binary64)
+    size_t part_off = 0;    // block partials (regions of Partials)
+    size_t part_count = 0;
+    size_t pg = 0, pv = 0, ph = 0, pn = 0;  // region sizes in doubles
+    size_t v64_off = 0;     // binary64 vectors
+    int nv64 = 0;
+    size_t v32_off = 0;     // binary32 vectors (IR inner solve)
+    int nv32 = 0;
+    size_t acopy_off = 0;   // padded binary64 copy of A (when not borrowed)
+    size_t acopy_bytes = 0;
+    int64_t lda_pad = 0;
+    size_t alow_off = 0;    // binary32 / bfloat16 copy of A (IR)
+    size_t alow_bytes = 0;
+    size_t afb_off = 0;     // binary32 copy used after a bfloat16 -> binary32 fallback
+    size_t afb_bytes = 0;
+    int64_t lda_low = 0;
+    size_t total = 0;
+    size_t total_borrowed = 0;
+};
+
+size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m + (m + 1) + m + (m + 1); }
+
+bool valid_params(const ks_params *p) {
+    if (!p) return false;
+    if (p->n < 1 || p->lda < p->n) return false;
+    if (p->method != KS_CG && p->method != KS_GMRES) return false;
+    if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
+    if (p->max_iter < 0) return false;
+    if (p->method == KS_GMRES && (p->restart < 1 || p->restart > KS_MAX_RESTART)) return false;
+    if (p->precision != KS_FP64) {
+        if (!(p->inner_tol > 0.0) || p->max_outer < 1) return false;
+    }
+    return true;
+}
+
+Layout make_layout(const ks_params *p) {
+    Layout L;
+    const int n = p->n;
+    L.ldv = (int)round_up(n, 64);
+    L.m = (p->method == KS_GMRES) ? p->restart : 1;
+    size_t off = 0;
+    L.st_off = off;
+    off = align_up(off + 2 * sizeof(State));
+    L.gm_off = off;
+    off = align_up(off + gm_doubles(L.m) * sizeof(double));
+    L.pg = (size_t)round_up(gemv_blocks(n) * 3, 32);
+    L.pv = (size_t)round_up(vec_blocks(n), 32);
+    L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
+    L.pn = (size_t)round_up(cgs_blocks(n), 32);
+    L.part_count = L.pg + L.pv + 2 * L.ph + L.pn;
+    L.part_off = off;
+    off = align_up(off + L.part_count * sizeof(double));
+    // binary64 vectors: CG r, p, q; GMRES w, V(0..m); IR adds the outer residual
+    L.nv64 = (p->method == KS_CG) ? 3 : 1 + (L.m + 1);
+    if (p->precision != KS_FP64) L.nv64 += 1;
+    L.v64_off = off;
+    off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
+    // binary32 vectors of the inner solve: rhs, d, then CG r, p, q or GMRES w, V(0..m)
+    L.nv32 = 0;
+    if (p->precision != KS_FP64) L.nv32 = 2 + ((p->method == KS_CG) ? 3 : 1 + (L.m + 1));
+    L.v32_off = off;
+    off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
+    L.lda_low = round_up(n, 64);
+    if (p->precision == KS_IR_FP32) {
+        L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
+    } else if (p->precision == KS_IR_BF16) {
+        L.alow_bytes = (size_t)n * L.lda_low * sizeof(uint16_t);
+        L.afb_bytes = (size_t)n * L.lda_low * sizeof(float);
+    }
+    L.alow_off = off;
+    off = align_up(off + L.alow_bytes);
+    L.afb_off = off;
+    off = align_up(off + L.afb_bytes);
+    L.total_borrowed = off;
+    L.lda_pad = round_up(n, 64);
+    L.acopy_bytes = (size_t)n * L.lda_pad * sizeof(double);
+    L.acopy_off = off;
+    off = align_up(off + L.acopy_bytes);
+    L.total = off;
+    return L;
+}
+
+bool a_borrowable(const double *A, int64_t lda) {
+    return ((uintptr_t)A % 16 == 0) && ((lda * 8) % 16 == 0);
+}
+
+}  // namespace
+
+struct ks_solver {
+    ks_params p{};
+    Layout L;
+    int n = 0;
+    int64_t lda = 0;
+    const double *A = nullptr;
+    void *A_low = nullptr;
+    float *A_fb = nullptr;
+    bool fb_ready = false;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    bool own_ws = false;
+    State *st = nullptr;     // outer / plain solve
+    State *st_in = nullptr;  // IR inner solve
+    State *host = nullptr;   // pinned mirror of both
+    Partials P{};
+    GmArrays ga{};
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> tev;  // timing event pairs of A*v launches
+    int tev_used = 0;
+    double gemv_ms = 0.0;
+    int gemv_calls = 0;
+    double anorm_inf = 0.0;
+
+    double *vec64(int i) const { return v64 + (size_t)i * L.ldv; }
+    float *vec32(int i) const { return v32 + (size_t)i * L.ldv; }
+    bool timing() const { return (p.flags & KS_FLAG_TIMING) != 0; }
+};
+
+namespace {
+
+int check_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KS_EHIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return KS_EHIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return KS_EDEVICE;
+    return KS_OK;
+}
+
+int sync_state(ks_solver *s) {
+    HIPCHK(hipMemcpyAsync(s->host, s->st, 2 * sizeof(State), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return KS_OK;
+}
+
+// Timing of A*v launches: an event pair around each; after a sync only the
+// first `real` pairs of the chunk did work (the rest returned at once).
+int timing_pair(ks_solver *s, hipEvent_t *a, hipEvent_t *b) {
+    *a = *b = nullptr;
+    if (!s->timing()) return KS_OK;
+    while ((int)s->tev.size() < 2 * (s->tev_used + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        s->tev.push_back(e);
+    }
+    *a = s->tev[2 * s->tev_used];
+    *b = s->tev[2 * s->tev_used + 1];
+    s->tev_used++;
+    return KS_OK;
+}
+
+int timed_collect(ks_solver *s, int real) {
+    if (!s->timing()) return KS_OK;
+    real = std::min(real, s->tev_used);
+    for (int i = 0; i < real; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->tev[2 * i], s->tev[2 * i + 1]));
+        s->gemv_ms += ms;
+        s->gemv_calls++;
+    }
+    s->tev_used = 0;
+    return KS_OK;
+}
+
+int poll_chunk(const ks_solver *s) {
+    if (s->p.poll_every > 0) return s->p.poll_every;
+    if (s->n >= 8192) return 8;
+    if (s->n >= 2048) return 16;
+    return 32;
+}
+
+struct Outcome {
+    int status = KS_OK;
+    int iters = 0;
+    int restarts = 0;
+};
+
+// ------------------------------------------------------------------ CG
+// Plain conjugate gradient (binary64 or, as the inner solve, binary32 on a
+// low-precision A).  `outer` = true: confirm on the true residual and restart
+// from the current x when it fails (binary64 solve); false: one pass, stop on
+// the recursive residual (inner solve).
+template <typename TA, typename T>
+int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, const T *b, T *x,
+           T *r, T *p, T *q, double tol, int max_iter, bool outer, Outcome *out) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm));
+    HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 0, sm)));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const State *h = &s->host[state_index];
+    if (h->bnorm == 0.0) {
+        HIPCHK(launch_fill<T>(n, x, T(0), sm));
+        out->status = KS_OK;
+        out->iters = 0;
+        return KS_OK;
+    }
+    int restarts = 0;
+    bool first = true;
+    for (;;) {
+        const int f = h->flags;
+        if (f & F_TRUE_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (f & F_TRUE_OK) {
+            out->status = KS_OK;
+            break;
+        }
+        if (h->iters >= max_iter) {
+            out->status = KS_MAXITER;
+            break;
+        }
+        if (!first) {
+            if (restarts >= CG_MAX_RESTARTS) {
+                out->status = KS_STAGNATED;
+                break;
+            }
+            ++restarts;
+        }
+        first = false;
+        HIPCHK(launch_cg_begin<T>(n, r, p, st, sm));
+        bool done = false;
+        while (!done) {
+            const int it0 = h->iters;
+            const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0));
+            for (int c = 0; c < chunk; ++c) {
+                hipEvent_t e0, e1;
+                if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                if (e0) HIPCHK(hipEventRecord(e0, sm));
+                HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                if (e1) HIPCHK(hipEventRecord(e1, sm));
+                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, sm));
+                HIPCHK(launch_cg_pupdate<T>(n, r, p, st, s->P, max_iter, sm));
+            }
+            if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
+            if ((rc = sync_state(s))) return rc;
+            if ((rc = timed_collect(s, h->iters - it0))) return rc;
+            done = (h->flags & F_STOP) != 0;
+        }
+        const int f2 = h->flags;
+        if (f2 & F_BREAK) {
+            out->status = KS_BREAKDOWN;
+            break;
+        }
+        if (f2 & F_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (!outer) {
+            out->status = (f2 & F_CONV) ? KS_OK : KS_MAXITER;
+            break;
+        }
+        // F_CONV or F_MAXIT: the gated residual kernel has refreshed F_TRUE_OK
+    }
+    out->iters = h->iters;
+    out->restarts = restarts;
+    return KS_OK;
+}
+
+// ---------------------------------------------------------------- GMRES
+template <typename TA, typename T>
+int run_gmres(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, const T *b,
+              T *x, T *w, T *V, double tol, int max_iter, Outcome *out) {
+    const int n = s->n, m = s->ga.m, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm));
+    HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, w, st, s->P, 0, sm)));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const State *h = &s->host[state_index];
+    if (h->bnorm == 0.0) {
+        HIPCHK(launch_fill<T>(n, x, T(0), sm));
+        out->status = KS_OK;
+        out->iters = 0;
+        return KS_OK;
+    }
+    int cycles = 0;
+    for (;;) {
+        const int f = h->flags;
+        if (f & F_TRUE_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (f & F_TRUE_OK) {
+            out->status = KS_OK;
+            break;
+        }
+        if (h->iters >= max_iter) {
+            out->status = KS_MAXITER;
+            break;
+        }
+        HIPCHK(launch_gm_begin<T>(n, w, V, st, s->ga, sm));
+        const int chunk = poll_chunk(s);
+        int k = 0;
+        bool stopped = false;
+        while (k < m && !stopped) {
+            const int it0 = h->iters;
+            const int kend = std::min(m, k + chunk);
+            for (; k < kend; ++k) {
+                hipEvent_t e0, e1;
+                if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                HIPCHK((launch_gm_step<TA, T>(n, lda, A, ldv, V, w, k, st, s->ga, s->P, max_iter,
+                                              sm, e0, e1)));
+            }
+            if (kend < m) {
+                if ((rc = sync_state(s))) return rc;
+                if ((rc = timed_collect(s, h->iters - it0))) return rc;
+                stopped = (h->flags & F_STOP) != 0;
+            } else {
+                // last chunk of the cycle: finish, residual, then one sync
+                HIPCHK(launch_gm_finish<T>(n, ldv, V, x, st, s->ga, sm));
+                HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, w, st, s->P, 0, sm)));
+                if ((rc = sync_state(s))) return rc;
+                if ((rc = timed_collect(s, h->iters - it0))) return rc;
+                stopped = true;
+                k = m;
+            }
+        }
+        if (k < m) {
+            // cycle ended early: finish it
+            HIPCHK(launch_gm_finish<T>(n, ldv, V, x, st, s->ga, sm));
+            HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, w, st, s->P, 0, sm)));
+            if ((rc = sync_state(s))) return rc;
+        }
+        ++cycles;
+        const int f2 = h->flags;
+        if (f2 & F_BREAK) {
+            out->status = KS_BREAKDOWN;
+            break;
+        }
+        if (f2 & F_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+    }
+    out->iters = h->iters;
+    out->restarts = std::max(0, cycles - 1);
+    return KS_OK;
+}
+
+// Metrics of the returned x from the State the solve left behind: every exit
+// path of the drivers ends with a true-residual kernel and a sync, so the
+// host mirror holds ||b||, ||r|| and the infinity norms of r, x and b.
+void metrics_from_state(const ks_solver *s, ks_info *info) {
+    const State &h = s->host[0];
+    if (!(h.bnorm > 0.0)) {
+        info->rel_res = 0.0;
+        info->backward_err = 0.0;
+        return;
+    }
+    const double den = h.anorm_inf * h.xinf + h.binf;
+    info->rel_res = h.res / h.bnorm;
+    info->backward_err = den > 0.0 ? h.resinf / den : h.resinf;
+}
+
+int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_iter, Outcome *o) {
+    if (s->p.method == KS_CG)
+        return run_cg<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
+                                      s->vec64(2), tol, max_iter, true, o);
+    return run_gmres<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
+                                     tol, max_iter, o);
+}
+
+// ------------------------------------------------- iterative refinement
+// Outer binary64 loop: r = b - A x; stop at eta_inf <= tol; inner solve of
+// A_low d = r/||r|| (binary32 vectors); x += ||r|| d.  Precision is promoted
+// bfloat16 -> binary32 -> binary64 when the backward error fails to halve
+// twice, or the inner solve breaks down.
+int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o) {
+    const int n = s->n, m = s->ga.m;
+    hipStream_t sm = s->stream;
+    double *r64 = s->vec64(s->L.nv64 - 1);
+    float *rhs = s->vec32(0), *d = s->vec32(1);
+    int prec = s->p.precision;
+    int total_iters = 0, outer = 0, bad = 0, rc;
+    double eta_prev = INFINITY;
+    HIPCHK(launch_vec_stats<double>(n, b, 1.0, s->st, sm));
+    HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0, sm)));
+    if ((rc = sync_state(s))) return rc;
+    const State *h = &s->host[0];
+    if (h->bnorm == 0.0) {
+        HIPCHK(launch_fill<double>(n, x, 0.0, sm));
+        o->status = KS_OK;
+        info->rel_res = 0.0;
+        info->backward_err = 0.0;
+        info->precision_used = prec;
+        return KS_OK;
+    }
+    const double binf = h->binf, bnorm = h->bnorm;
+    s->anorm_inf = h->anorm_inf;
+    for (;;) {
+        const double den = s->anorm_inf * h->xinf + binf;
+        const double eta = den > 0.0 ? h->resinf / den : h->resinf;
+        info->rel_res = h->res / bnorm;
+        info->backward_err = eta;
+        if (!std::isfinite(eta) || (h->flags & F_TRUE_NONFIN)) {
+            o->status = KS_NONFINITE;
+            break;
+        }
+        if (eta <= s->p.tol) {
+            o->status = KS_OK;
+            break;
+        }
+        if (outer >= s->p.max_outer) {
+            o->status = KS_STAGNATED;
+            break;
+        }
+        if (eta > 0.5 * eta_prev) {
+            if (++bad >= 2 && prec != KS_FP64) {
+                prec = (prec == KS_IR_BF16) ? KS_IR_FP32 : KS_FP64;
+                bad = 0;
+            }
+        } else {
+            bad = 0;
+        }
+        eta_prev = eta;
+        if (prec == KS_FP64) {
+            // finish in binary64 from the current x: ||r||_2 <= tol * den
+            // implies eta_inf <= tol
+            const double tol2 = s->p.tol * den / bnorm;
+            Outcome o64;
+            if ((rc = solve_fp64(s, b, x, tol2, std::max(1, s->p.max_iter), &o64))) return rc;
+            total_iters += o64.iters;
+            ++outer;
+            HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0,
+                                                    sm)));
+            if ((rc = sync_state(s))) return rc;
+            const double den2 = s->anorm_inf * h->xinf + binf;
+            info->rel_res = h->res / bnorm;
+            info->backward_err = den2 > 0.0 ? h->resinf / den2 : h->resinf;
+            o->status = (info->backward_err <= s->p.tol) ? KS_OK : o64.status;
+            if (o->status == KS_OK && o64.status != KS_OK && info->backward_err > s->p.tol)
+                o->status = o64.status;
+            break;
+        }
+        if (prec == KS_IR_FP32 && s->p.precision == KS_IR_BF16 && !s->fb_ready) {
+            HIPCHK(launch_convert(n, s->lda, s->A, KS_DT_F32, s->L.lda_low, s->A_fb, sm));
+            s->fb_ready = true;
+        }
+        // inner solve on the low-precision copy
+        HIPCHK(launch_ir_scale_cast(n, r64, rhs, s->st, sm));
+        HIPCHK(launch_fill<float>(n, d, 0.0f, sm));
+        Outcome oi;
+        const int64_t ll = s->L.lda_low;
+        if (s->p.method == KS_CG) {
+            float *ri = s->vec32(2), *pi = s->vec32(3), *qi = s->vec32(4);
+            if (prec == KS_IR_BF16)
+                rc = run_cg<bf16_t, float>(s, s->st_in, 1, (const bf16_t *)s->A_low, ll, rhs, d, ri, pi,
+                                           qi, s->p.inner_tol, s->p.max_iter, false, &oi);
+            else
+                rc = run_cg<float, float>(s, s->st_in, 1,
+                                          (s->p.precision == KS_IR_BF16) ? s->A_fb : (const float *)s->A_low,
+                                          ll, rhs, d, ri, pi, qi, s->p.inner_tol, s->p.max_iter, false,
+                                          &oi);
+        } else {
+            float *wi = s->vec32(2), *Vi = s->vec32(3);
+            if (prec == KS_IR_BF16)
+                rc = run_gmres<bf16_t, float>(s, s->st_in, 1, (const bf16_t *)s->A_low, ll, rhs, d, wi, Vi,
+                                              s->p.inner_tol, s->p.max_iter, &oi);
+            else
+                rc = run_gmres<float, float>(s, s->st_in, 1,
+                                             (s->p.precision == KS_IR_BF16) ? s->A_fb
+                                                                            : (const float *)s->A_low,
+                                             ll, rhs, d, wi, Vi, s->p.inner_tol, s->p.max_iter, &oi);
+        }
+        (void)m;
+        if (rc) return rc;
+        total_iters += oi.iters;
+        ++outer;
+        if (oi.status == KS_BREAKDOWN || oi.status == KS_NONFINITE) {
+            // the low-precision copy is not usable (e.g. indefinite): promote
+            prec = (prec == KS_IR_BF16) ? KS_IR_FP32 : KS_FP64;
+            bad = 0;
+            eta_prev = INFINITY;
+            continue;
+        }
+        HIPCHK(launch_ir_update(n, x, d, &s->st->res, sm));
+        HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0, sm)));
+        if ((rc = sync_state(s))) return rc;
+    }
+    o->iters = total_iters;
+    info->outer_iters = outer;
+    info->precision_used = prec;
+    return KS_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int ks_params_init(ks_params *p, int32_t n, int32_t method) {
+    if (!p || n < 1 || (method != KS_CG && method != KS_GMRES)) return KS_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->n = n;
+    p->method = method;
+    p->lda = n;
+    p->precision = KS_FP64;
+    p->max_iter = 10 * n;
+    p->tol = 1e-10;
+    p->restart = 30;
+    p->max_outer = 30;
+    p->inner_tol = 1e-4;
+    p->poll_every = 0;
+    p->flags = 0;
+    return KS_OK;
+}
+
+int ks_workspace_bytes(const ks_params *p, size_t *bytes) {
+    if (!valid_params(p) || !bytes) return KS_EINVAL;
+    *bytes = make_layout(p).total;
+    return KS_OK;
+}
+
+int ks_workspace_bytes_borrowed(const ks_params *p, size_t *bytes) {
+    if (!valid_params(p) || !bytes) return KS_EINVAL;
+    *bytes = make_layout(p).total_borrowed;
+    return KS_OK;
+}
+
+int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws, size_t ws_bytes,
+              void *stream) {
+    if (!out || !valid_params(p) || !dA) return KS_EINVAL;
+    if (d_ws && ((uintptr_t)d_ws % ALIGN) != 0) return KS_EINVAL;
+    if (!d_ws && ws_bytes != 0) return KS_EINVAL;
+    int rc = check_device();
+    if (rc) return rc;
+    Layout L = make_layout(p);
+    const bool borrow = a_borrowable(dA, p->lda);
+    const size_t need = borrow ? L.total_borrowed : L.total;
+    ks_solver *s = new (std::nothrow) ks_solver();
+    if (!s) return KS_ENOMEM;
+    s->p = *p;
+    s->L = L;
+    s->n = p->n;
+    s->stream = (hipStream_t)stream;
+    if (d_ws) {
+        if (ws_bytes < need) {
+            delete s;
+            return KS_ENOMEM;
+        }
+        s->ws = (char *)d_ws;
+    } else {
+        if (hipMalloc((void **)&s->ws, need) != hipSuccess) {
+            delete s;
+            return KS_ENOMEM;
+        }
+        s->own_ws = true;
+    }
+    if (hipHostMalloc((void **)&s->host, 2 * sizeof(State), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
+        ks_free(s);
+        return KS_EHIP;
+    }
+    s->st = (State *)(s->ws + L.st_off);
+    s->st_in = s->st + 1;
+    double *g = (double *)(s->ws + L.gm_off);
+    const int m = L.m;
+    s->ga.m = m;
+    s->ga.H = g;
+    g += (size_t)(m + 1) * m;
+    s->ga.R = g;
+    g += (size_t)(m + 1) * m;
+    s->ga.cs = g;
+    g += m;
+    s->ga.sn = g;
+    g += m;
+    s->ga.g = g;
+    g += m + 1;
+    s->ga.y = g;
+    g += m;
+    s->ga.h1 = g;
+
+    {
+        double *pp = (double *)(s->ws + L.part_off);
+        s->P.g = pp;
+        pp += L.pg;
+        s->P.v = pp;
+        pp += L.pv;
+        s->P.h1 = pp;
+        pp += L.ph;
+        s->P.h2 = pp;
+        pp += L.ph;
+        s->P.nrm = pp;
+    }
+    s->v64 = (double *)(s->ws + L.v64_off);
+    s->v32 = (float *)(s->ws + L.v32_off);
+    hipStream_t sm = s->stream;
+    // zero the states (tickets must start at 0) and the small arrays
+    if (hipMemsetAsync(s->ws, 0, L.part_off, sm) != hipSuccess) {
+        ks_free(s);
+        return KS_EHIP;
+    }
+    if (borrow) {
+        s->A = dA;
+        s->lda = p->lda;
+    } else {
+        double *Ac = (double *)(s->ws + L.acopy_off);
+        if (launch_copy_pad(p->n, p->lda, dA, L.lda_pad, Ac, sm) != hipSuccess) {
+            ks_free(s);
+            return KS_EHIP;
+        }
+        s->A = Ac;
+        s->lda = L.lda_pad;
+    }
+    if (launch_norm_inf(p->n, s->lda, s->A, s->st, s->P, sm) != hipSuccess) {
+        ks_free(s);
+        return KS_EHIP;
+    }
+    if (p->precision != KS_FP64) {
+        s->A_low = s->ws + L.alow_off;
+        if (p->precision == KS_IR_BF16) s->A_fb = (float *)(s->ws + L.afb_off);
+        const int dt = (p->precision == KS_IR_FP32) ? KS_DT_F32 : KS_DT_BF16;
+        if (launch_convert(p->n, s->lda, s->A, dt, L.lda_low, s->A_low, sm) != hipSuccess) {
+            ks_free(s);
+            return KS_EHIP;
+        }
+    }
+    *out = s;
+    return KS_OK;
+}
+
+int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info) {
+    if (!s || !d_b || !d_x) return KS_EINVAL;
+    if ((uintptr_t)d_b % 16 || (uintptr_t)d_x % 16) return KS_EINVAL;
+    ks_info local;
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    info->precision_used = s->p.precision;
+    s->gemv_ms = 0.0;
+    s->gemv_calls = 0;
+    s->tev_used = 0;
+    HIPCHK(hipEventRecord(s->ev0, s->stream));
+    Outcome o;
+    int rc;
+    if (s->p.precision == KS_FP64) {
+        rc = solve_fp64(s, d_b, d_x, s->p.tol, s->p.max_iter, &o);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(s->ev1, s->stream));
+        metrics_from_state(s, info);
+    } else {
+        rc = solve_ir(s, d_b, d_x, info, &o);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(s->ev1, s->stream));
+    }
+    HIPCHK(hipEventSynchronize(s->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    info->elapsed_ms = ms;
+    info->status = o.status;
+    info->iters = o.iters;
+    info->restarts = o.restarts;
+    info->gemv_ms = s->gemv_ms;
+    info->gemv_calls = s->gemv_calls;
+    return o.status;
+}
+
+int ks_arnoldi(ks_solver *s, const double *d_v0, int32_t k, double *d_V, double *d_H,
+               int32_t *k_done) {
+    if (!s || !d_v0 || !d_V || !d_H || !k_done) return KS_EINVAL;
+    if ((uintptr_t)d_v0 % 16) return KS_EINVAL;
+    if (s->p.method != KS_GMRES || s->p.precision != KS_FP64 || k < 1 || k > s->ga.m)
+        return KS_EINVAL;
+    const int n = s->n, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    double *w = s->vec64(0), *V = s->vec64(1);
+    HIPCHK(launch_vec_stats<double>(n, d_v0, 0.0, s->st, sm));
+    HIPCHK(hipMemcpyAsync(&s->st->res, &s->st->bnorm, sizeof(double), hipMemcpyDeviceToDevice, sm));
+    HIPCHK(hipMemsetAsync(s->ga.H, 0, sizeof(double) * (size_t)(s->ga.m + 1) * s->ga.m, sm));
+    HIPCHK(launch_gm_begin<double>(n, d_v0, V, s->st, s->ga, sm));
+    const int big = 0x7fffffff;
+    for (int c = 0; c < k; ++c)
+        HIPCHK((launch_gm_step<double, double>(n, s->lda, s->A, ldv, V, w, c, s->st, s->ga, s->P,
+                                               big, sm, nullptr, nullptr)));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const int kd = s->host[0].k_done;
+    *k_done = kd;
+    HIPCHK(hipMemcpy2DAsync(d_V, (size_t)n * sizeof(double), V, (size_t)ldv * sizeof(double),
+                            (size_t)n * sizeof(double), (size_t)kd + 1, hipMemcpyDeviceToDevice, sm));
+    if (kd > 0)
+        HIPCHK(hipMemcpy2DAsync(d_H, (size_t)k * sizeof(double), s->ga.H,
+                                (size_t)s->ga.m * sizeof(double), (size_t)k * sizeof(double),
+                                (size_t)kd + 1, hipMemcpyDeviceToDevice, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    return KS_OK;
+}
+
+void ks_free(ks_solver *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->tev) (void)hipEventDestroy(e);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->host) (void)hipHostFree(s->host);
+    if (s->own_ws && s->ws) (void)hipFree(s->ws);
+    delete s;
+}
+
+const char *ks_strerror(int status) {
+    switch (status) {
+        case KS_OK: return "converged";
+        case KS_MAXITER: return "iteration limit reached";
+        case KS_BREAKDOWN: return "breakdown (CG: p'Ap <= 0; GMRES: singular Hessenberg)";
+        case KS_STAGNATED: return "stagnated";
+        case KS_NONFINITE: return "non-finite value";
+        case KS_EINVAL: return "invalid argument";
+        case KS_ENOMEM: return "workspace too small or allocation failed";
+        case KS_EHIP: return "HIP runtime error";
+        case KS_EDEVICE: return "device is not gfx950";
+        default: return "unknown status";
+    }
+}
+
+int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *dA, const void *d_v, void *d_y,
+            void *stream) {
+    if (n < 1 || lda < n || !dA || !d_v || !d_y) return KS_EINVAL;
+    size_t es = (a_dtype == KS_DT_F64) ? 8 : (a_dtype == KS_DT_F32) ? 4 : (a_dtype == KS_DT_BF16) ? 2 : 0;
+    if (!es) return KS_EINVAL;
+    if ((uintptr_t)dA % 16 || (lda * es) % 16 || (uintptr_t)d_v % 16 || (uintptr_t)d_y % 16)
+        return KS_EINVAL;
+    HIPCHK(launch_gemv(n, lda, a_dtype, dA, d_v, d_y, (hipStream_t)stream));
+    return KS_OK;
+}
+
+int ks_convert(int32_t n, int64_t lda_src, const double *d_src, int32_t dst_dtype, int64_t lda_dst,
+               void *d_dst, void *stream) {
+    if (n < 1 || lda_src < n || lda_dst < n || !d_src || !d_dst) return KS_EINVAL;
+    if (dst_dtype != KS_DT_F32 && dst_dtype != KS_DT_BF16 && dst_dtype != KS_DT_F64) return KS_EINVAL;
+    HIPCHK(launch_convert(n, lda_src, d_src, dst_dtype, lda_dst, d_dst, (hipStream_t)stream));
+    return KS_OK;
+}
+
+int ks_read_ceiling(const void *d_src, size_t bytes, double *d_sink, void *stream) {
+    if (!d_src || !d_sink || bytes == 0 || bytes % 16) return KS_EINVAL;
+    if ((uintptr_t)d_src % 16) return KS_EINVAL;
+    HIPCHK(launch_read_ceiling(d_src, bytes, d_sink, (hipStream_t)stream));
+    return KS_OK;
+}
+
+}  // extern "C"

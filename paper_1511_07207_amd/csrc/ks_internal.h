@@ -1,0 +1,159 @@
+// Internal declarations of the dense Krylov library: the device-resident
+// solver state, the workspace regions and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ks.h"
+
+namespace ks {
+
+constexpr int WAVE = 64;
+
+// Flags word of State (device-resident; the host reads it after a sync).
+enum : int32_t {
+    F_STOP = 1,         // the inner Krylov loop is over: its kernels return at once
+    F_CONV = 2,         // recursive residual / GMRES estimate met the tolerance
+    F_MAXIT = 4,        // iteration limit
+    F_BREAK = 8,        // CG p'Ap <= 0, or a zero Givens norm in GMRES
+    F_NONFIN = 16,      // non-finite scalar inside the Krylov loop
+    F_HAPPY = 32,       // GMRES happy breakdown (exact solution in the space)
+    F_TRUE_OK = 64,     // last true residual met the tolerance
+    F_TRUE_NONFIN = 128 // last true residual (or ||b||) not finite
+};
+constexpr int32_t INNER_FLAGS = F_STOP | F_CONV | F_MAXIT | F_BREAK | F_NONFIN | F_HAPPY;
+
+// Scalars of one solve, kept on the device so that no iteration needs the host.
+// Within one kernel a field is either read by every block or written by
+// block 0, never both (the next kernel sees the write at the kernel boundary).
+struct alignas(256) State {
+    double bnorm, binf;        // ||b||_2, ||b||_inf
+    double thresh;             // tol * ||b||_2 (absolute residual threshold)
+    double rho, rho_prev;      // CG r'r: current, and the value before the update
+    double sigma, alpha, beta; // CG scalars
+    double res, resinf, xinf;  // last true residual: ||r||_2, ||r||_inf, ||x||_inf
+    double avk, hk1;           // GMRES: ||A v_k||, h(k+1,k)
+    double anorm_inf;          // ||A||_inf
+    double spare[2];
+    int32_t iters;             // A*v products in the Krylov loop
+    int32_t flags;
+    int32_t k_done;            // GMRES: steps in the current cycle
+    int32_t pad;
+};
+
+// Per-block partial results, one region per producing kernel kind.
+struct Partials {
+    double *g;    // GEMV-shaped kernels: 3 per block
+    double *v;    // vector kernels: 1 per block
+    double *h1;   // Gram-Schmidt pass 1: (m+1) per block
+    double *h2;   // Gram-Schmidt pass 2: (m+1) per block
+    double *nrm;  // ||w||^2 after pass 2: 1 per block
+};
+
+// Tuning of the dense matrix-vector product: ROWS rows per block of NT threads,
+// the block's threads split each row's columns in 16-byte chunks.
+constexpr int GEMV_NT = 256;
+constexpr int GEMV_ROWS = 8;
+// Vector kernels: threads per block, elements per thread.
+constexpr int VEC_NT = 256;
+constexpr int VEC_EPT = 4;
+// Gram-Schmidt kernels: one row per thread.
+constexpr int CGS_NT = 256;
+// Single-block reductions (||b||, finishing kernels).
+constexpr int ONE_NT = 1024;
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+inline int gemv_blocks(int n) { return div_up(n, GEMV_ROWS); }
+inline int vec_blocks(int n) { return div_up(n, VEC_NT * VEC_EPT); }
+inline int cgs_blocks(int n) { return div_up(n, CGS_NT); }
+
+struct bf16_t {
+    uint16_t bits;
+};
+
+// GMRES small dense arrays (binary64 always).
+struct GmArrays {
+    double *H;   // (m+1) x m unrotated Hessenberg, row-major, ld m
+    double *R;   // (m+1) x m rotated copy (upper triangular after rotations)
+    double *cs, *sn;  // m rotations
+    double *g;   // m+1
+    double *y;   // m
+    double *h1;  // m+1: first Gram-Schmidt coefficients
+    int m;
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.
+
+// y = A v  (a_dtype: KS_DT_*)
+hipError_t launch_gemv(int n, int64_t lda, int a_dtype, const void *A, const void *v, void *y,
+                       hipStream_t s);
+
+// ||b||_2, ||b||_inf into st; thresh = tol * ||b||_2; flags, iters, k_done reset.
+template <typename T>
+hipError_t launch_vec_stats(int n, const T *b, double tol, State *st, hipStream_t s);
+
+// r = b - A x, then st->rho = r'r, res, resinf, xinf and F_TRUE_OK /
+// F_TRUE_NONFIN.  gate 1: only when the inner loop has stopped (F_STOP).
+template <typename TA, typename T>
+hipError_t launch_residual(int n, int64_t lda, const TA *A, const T *b, const T *x, T *r,
+                           State *st, Partials P, int gate, hipStream_t s);
+
+// CG iteration, three kernels:
+//   q = A p (sigma partials);  x += alpha p, r -= alpha q (rho' partials);
+//   convergence / limit checks, p = r + beta p.
+template <typename TA, typename T>
+hipError_t launch_cg_matvec(int n, int64_t lda, const TA *A, const T *p, T *q, State *st,
+                            Partials P, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(int n, T *x, T *r, const T *p, const T *q, State *st, Partials P,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int max_iter,
+                             hipStream_t s);
+// p = r, inner flags cleared (rho comes from the residual kernel).
+template <typename T>
+hipError_t launch_cg_begin(int n, const T *r, T *p, State *st, hipStream_t s);
+
+// GMRES: cycle start, one Arnoldi step (matrix-vector product, two Gram-Schmidt
+// passes, Givens update and normalisation), cycle end.  ev_before / ev_after
+// (may be null) are recorded around the matrix-vector product.
+template <typename T>
+hipError_t launch_gm_begin(int n, const T *r, T *V, State *st, GmArrays ga, hipStream_t s);
+template <typename TA, typename T>
+hipError_t launch_gm_step(int n, int64_t lda, const TA *A, int ldv, T *V, T *w, int k,
+                          State *st, GmArrays ga, Partials P, int max_iter, hipStream_t s,
+                          hipEvent_t ev_before, hipEvent_t ev_after);
+// w = A v_k with ||w||^2 partials (first kernel of the step)
+template <typename TA, typename T>
+hipError_t launch_gm_matvec(int n, int64_t lda, const TA *A, const T *vk, T *w, State *st,
+                            Partials P, hipStream_t s);
+template <typename T>
+hipError_t launch_gm_finish(int n, int ldv, const T *V, T *x, State *st, GmArrays ga,
+                            hipStream_t s);
+
+// ||A||_inf into st->anorm_inf
+hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,
+                           hipStream_t s);
+// dst = convert(src), padding columns zeroed
+hipError_t launch_convert(int n, int64_t lda_src, const double *src, int dst_dtype,
+                          int64_t lda_dst, void *dst, hipStream_t s);
+hipError_t launch_copy_pad(int n, int64_t lda_src, const double *src, int64_t lda_dst,
+                           double *dst, hipStream_t s);
+
+// IR helpers
+// r32 = (float)(r / st->res)
+hipError_t launch_ir_scale_cast(int n, const double *r, float *r32, const State *st,
+                                hipStream_t s);
+// x += (*scale) * (double)d32
+hipError_t launch_ir_update(int n, double *x, const float *d32, const double *scale,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_fill(int n, T *x, T value, hipStream_t s);
+
+hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipStream_t s);
+
+}  // namespace ks

@@ -1,0 +1,168 @@
+"""Python front end of the dense Krylov library.
+
+Tensors are torch tensors on the GPU (torch supplies device memory and the
+current stream); all arithmetic happens in libks.so's HIP kernels.
+
+    x, info = solve(A, b)                       # CG, binary64, tol 1e-10
+    x, info = solve(A, b, method="gmres", restart=30)
+    x, info = solve(A, b, precision="fp32", tol=1e-12)   # FP32 inner + FP64 IR
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as N
+
+_METHODS = {"cg": N.KS_CG, "gmres": N.KS_GMRES}
+_PRECISIONS = {"fp64": N.KS_FP64, "fp32": N.KS_IR_FP32, "bf16": N.KS_IR_BF16}
+_PREC_NAMES = {v: k for k, v in _PRECISIONS.items()}
+
+
+def _stream_handle() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_matrix(A: torch.Tensor) -> int:
+    if not (isinstance(A, torch.Tensor) and A.is_cuda and A.dtype == torch.float64):
+        raise TypeError("A must be a float64 CUDA tensor")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        raise ValueError("A must be row-major with unit column stride")
+    return int(A.stride(0))
+
+
+def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float = 1e-10,
+                max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
+                inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
+                timing: bool = False) -> N.KsParams:
+    p = N.KsParams()
+    N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
+    p.lda = int(lda if lda is not None else n)
+    p.tol = float(tol)
+    if max_iter is not None:
+        p.max_iter = int(max_iter)
+    p.restart = int(restart)
+    p.precision = _PRECISIONS[precision]
+    p.inner_tol = float(inner_tol)
+    p.max_outer = int(max_outer)
+    p.poll_every = int(poll_every)
+    p.flags = N.KS_FLAG_TIMING if timing else 0
+    return p
+
+
+class Solver:
+    """A solver bound to one matrix A (create once, solve many right-hand sides).
+
+    The workspace is a torch uint8 tensor owned by this object; A must stay
+    alive and unmodified while the solver exists (it is read in place when
+    aligned).
+    """
+
+    def __init__(self, A: torch.Tensor, method: str = "cg", **kw):
+        lda = _check_matrix(A)
+        n = A.shape[0]
+        self.A = A
+        self.n = n
+        self.params = make_params(n, method=method, lda=lda, **kw)
+        L = N.lib()
+        need = ctypes.c_size_t(0)
+        aligned = A.data_ptr() % 16 == 0 and (lda * 8) % 16 == 0
+        fn = L.ks_workspace_bytes_borrowed if aligned else L.ks_workspace_bytes
+        N.check(fn(ctypes.byref(self.params), ctypes.byref(need)), "ks_workspace_bytes")
+        nbytes = int(need.value) + 256
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = ctypes.c_void_p(base + off)
+        self._ws_bytes = nbytes - off
+        h = ctypes.c_void_p()
+        N.check(L.ks_create(ctypes.byref(h), ctypes.byref(self.params), _ptr(A), self._ws_ptr,
+                            self._ws_bytes, _stream_handle()), "ks_create")
+        self._h = h
+
+    def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        """Solve A x = b; returns (x, info dict).  x is a new tensor unless `out` is given."""
+        if not (b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n and b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 CUDA vector of length n")
+        if out is None:
+            out = torch.zeros(self.n, dtype=torch.float64, device=b.device)
+            if x0 is not None:
+                out.copy_(x0.reshape(-1))
+        elif x0 is not None:
+            out.copy_(x0.reshape(-1))
+        info = N.KsInfo()
+        rc = N.lib().ks_solve(self._h, _ptr(b), _ptr(out), ctypes.byref(info))
+        N.check(rc, "ks_solve")
+        d = info.as_dict()
+        d["precision_used"] = _PREC_NAMES.get(d["precision_used"], d["precision_used"])
+        return out, d
+
+    def arnoldi(self, v0: torch.Tensor, k: int):
+        """k Arnoldi steps from v0: returns (V n x (k'+1), H (k'+1) x k', k')."""
+        V = torch.zeros((k + 1, self.n), dtype=torch.float64, device=v0.device)
+        H = torch.zeros((k + 1, k), dtype=torch.float64, device=v0.device)
+        kd = ctypes.c_int32(0)
+        N.check(N.lib().ks_arnoldi(self._h, _ptr(v0.contiguous()), int(k), _ptr(V), _ptr(H),
+                                   ctypes.byref(kd)), "ks_arnoldi")
+        kd = kd.value
+        return V[: kd + 1].T, H[: kd + 1, :kd], kd
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().ks_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(A: torch.Tensor, b: torch.Tensor, x0: torch.Tensor | None = None, method: str = "cg",
+          **kw):
+    """One-shot solve of A x = b (see Solver for the keyword arguments)."""
+    s = Solver(A, method=method, **kw)
+    try:
+        return s.solve(b, x0=x0)
+    finally:
+        s.close()
+
+
+def gemv(A: torch.Tensor, v: torch.Tensor, y: torch.Tensor | None = None,
+         lda: int | None = None, n: int | None = None) -> torch.Tensor:
+    """y = A v with the solvers' GEMV kernel.  A: float64 / float32 / bfloat16 row-major."""
+    dt = {torch.float64: N.KS_DT_F64, torch.float32: N.KS_DT_F32,
+          torch.bfloat16: N.KS_DT_BF16}[A.dtype]
+    n = A.shape[0] if n is None else n
+    lda = A.stride(0) if lda is None else lda
+    vdt = torch.float64 if A.dtype == torch.float64 else torch.float32
+    if y is None:
+        y = torch.empty(n, dtype=vdt, device=A.device)
+    N.check(N.lib().ks_gemv(int(n), int(lda), dt, _ptr(A), _ptr(v), _ptr(y), _stream_handle()),
+            "ks_gemv")
+    return y
+
+
+def convert(A: torch.Tensor, dtype: torch.dtype, lda_dst: int | None = None) -> torch.Tensor:
+    """Low-precision copy of a float64 matrix with the library's rounding rule."""
+    n = A.shape[0]
+    lda_dst = n if lda_dst is None else lda_dst
+    dt = {torch.float32: N.KS_DT_F32, torch.bfloat16: N.KS_DT_BF16, torch.float64: N.KS_DT_F64}[dtype]
+    out = torch.empty((n, lda_dst), dtype=dtype, device=A.device)
+    N.check(N.lib().ks_convert(int(n), int(A.stride(0)), _ptr(A), dt, int(lda_dst), _ptr(out),
+                               _stream_handle()), "ks_convert")
+    return out
+
+
+def read_ceiling(buf: torch.Tensor, sink: torch.Tensor) -> None:
+    """Stream-read every byte of buf (the memory read ceiling kernel)."""
+    N.check(N.lib().ks_read_ceiling(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink),
+                                    _stream_handle()), "ks_read_ceiling")

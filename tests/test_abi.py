@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every function include/ks.h declares (CPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ks.h")
+LIB = os.path.join(ROOT, "paper_1511_07207_amd", "libks.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ks_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_documented_entry_points():
+    names = declared_functions()
+    for must in ("ks_create", "ks_solve", "ks_free", "ks_workspace_bytes", "ks_strerror",
+                 "ks_gemv", "ks_arnoldi"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_binding_lists_the_same_symbols():
+    from paper_1511_07207_amd._native import EXPORTS
+
+    assert sorted(EXPORTS) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_host_only_entry_points_without_gpu():
+    # parameter defaults, workspace sizing and argument validation run on the
+    # host and need no device
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    p = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(p), 1000, N.KS_GMRES) == 0
+    assert p.n == 1000 and p.lda == 1000 and p.restart == 30 and p.tol == 1e-10
+    sz = ctypes.c_size_t(0)
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == 0
+    full = sz.value
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+    assert full - sz.value >= 1000 * 1000 * 8
+    p.restart = 0
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.restart = 30
+    p.tol = 0.0
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    assert L.ks_params_init(ctypes.byref(p), 0, N.KS_CG) == N.KS_EINVAL
+    assert L.ks_strerror(0) == b"converged"
+    assert L.ks_gemv(0, 0, 0, None, None, None, None) == N.KS_EINVAL
+    L.ks_free(None)

@@ -1,0 +1,241 @@
+"""Solver parity on the GPU against the CPU oracle, through the C ABI.
+
+Bars: true relative residual <= tol; ||x - x_oracle|| / ||x_oracle|| <= 1e-8
+(at condition number 1e4 and below); iteration counts within 1% (at least 2)
+of the oracle's; mixed precision at normwise backward error <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import nonsym_problem, nonsym_swept_problem, spd_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, device):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _iters_close(a, b):
+    return abs(a - b) <= max(2, int(0.01 * b))
+
+
+@pytest.mark.parametrize("n,kappa,seed", [(512, 1e3, 0), (1000, 1e4, 1), (2048, 1e4, 2), (257, 1e2, 3)])
+def test_cg_matches_oracle(device, n, kappa, seed):
+    from paper_1511_07207_amd import krylov
+
+    print(f"cg n={n} kappa={kappa} seed={seed}", flush=True)
+    p = spd_problem(n, kappa, seed=seed, config_id=0)
+    xo, io = oracle.cg(p.A, p.b, tol=1e-10, max_iter=n if n == 512 else 10 * n)
+    assert io["status"] == 0
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="cg", tol=1e-10,
+                           max_iter=n if n == 512 else 10 * n)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    m = oracle.metrics(p.A, p.b, x)
+    assert m["rel_res"] <= 1e-10
+    # the two residuals differ only by the rounding of b - A x (order sqrt(n) u)
+    slack = np.sqrt(n) * 2.0 ** -53
+    assert abs(info["rel_res"] - m["rel_res"]) <= 1e-3 * m["rel_res"] + slack
+    assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + slack
+    assert _rel(x, xo) <= 1e-8
+    assert _iters_close(info["iters"], io["iters"]), (info["iters"], io["iters"])
+
+
+@pytest.mark.parametrize("n,m,seed", [(512, 30, 0), (2048, 30, 1), (1000, 5, 2), (300, 50, 3)])
+def test_gmres_matches_oracle(device, n, m, seed):
+    from paper_1511_07207_amd import krylov
+
+    print(f"gmres n={n} m={m} seed={seed}", flush=True)
+    p = nonsym_problem(n, seed=seed, config_id=1)
+    xo, io = oracle.gmres(p.A, p.b, tol=1e-10, restart=m, max_iter=10 * n)
+    assert io["status"] == 0
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="gmres", tol=1e-10,
+                           restart=m, max_iter=10 * n)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    met = oracle.metrics(p.A, p.b, x)
+    assert met["rel_res"] <= 1e-10
+    assert _rel(x, xo) <= 1e-8
+    assert _iters_close(info["iters"], io["iters"]), (info["iters"], io["iters"])
+    assert info["restarts"] == io["cycles"] - 1
+
+
+def test_gmres_swept_kappa_matches_oracle(device):
+    from paper_1511_07207_amd import krylov
+
+    p = nonsym_swept_problem(600, 1e2, seed=4, config_id=2)
+    xo, io = oracle.gmres(p.A, p.b, tol=1e-10, restart=50, max_iter=20000)
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="gmres", tol=1e-10,
+                           restart=50, max_iter=20000)
+    assert info["status"] == 0 and io["status"] == 0
+    assert _rel(x.cpu().numpy(), xo) <= 1e-8
+    assert _iters_close(info["iters"], io["iters"])
+
+
+def test_arnoldi_relation_on_gpu(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n, k = 700, 30
+    p = nonsym_problem(n, seed=5, config_id=1)
+    v0 = np.random.default_rng(3).standard_normal(n)
+    s = krylov.Solver(_t(p.A, device), method="gmres", restart=k)
+    V, H, kd = s.arnoldi(_t(v0, device), k)
+    torch.cuda.synchronize()
+    s.close()
+    V, H = V.cpu().numpy(), H.cpu().numpy()
+    assert kd == k
+    AF = np.linalg.norm(p.A)
+    assert np.linalg.norm(p.A @ V[:, :k] - V @ H) <= 1e-13 * AF
+    assert np.linalg.norm(V.T @ V - np.eye(k + 1)) <= 1e-13
+    Vo, Ho, ko = oracle.arnoldi(p.A, v0, k)
+    assert ko == k
+    assert np.linalg.norm(H - Ho) <= 1e-12 * np.linalg.norm(Ho)
+    assert np.linalg.norm(V - Vo) <= 1e-11 * np.sqrt(k + 1)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_n_equals_one(device):
+    from paper_1511_07207_amd import krylov
+
+    A = np.array([[4.0]])
+    b = np.array([3.0])
+    for method in ("cg", "gmres"):
+        x, info = krylov.solve(_t(A, device), _t(b, device), method=method, tol=1e-12)
+        assert info["status"] == 0 and info["iters"] == 1
+        assert abs(x.item() - 0.75) <= 1e-16
+
+
+def test_zero_rhs_and_exact_guess(device):
+    from paper_1511_07207_amd import krylov
+
+    p = spd_problem(100, 10.0, seed=1, config_id=0)
+    for method in ("cg", "gmres"):
+        x, info = krylov.solve(_t(p.A, device), _t(np.zeros(100), device),
+                               x0=_t(np.ones(100), device), method=method)
+        assert info["status"] == 0 and info["iters"] == 0
+        assert float(x.abs().max()) == 0.0
+        x, info = krylov.solve(_t(p.A, device), _t(p.b, device), x0=_t(p.x_true, device),
+                               method=method, tol=1e-10)
+        assert info["status"] == 0 and info["iters"] == 0
+
+
+def test_nonfinite_rhs(device):
+    from paper_1511_07207_amd import krylov
+
+    b = np.array([1.0, np.nan, 0.0])
+    for method in ("cg", "gmres"):
+        _, info = krylov.solve(_t(np.eye(3), device), _t(b, device), method=method)
+        assert info["status"] == 4, info
+
+
+def test_cg_breakdown_indefinite(device):
+    from paper_1511_07207_amd import krylov
+
+    A = np.diag([1.0, -1.0, 2.0])
+    b = np.array([1.0, 1.0, 0.0])
+    _, info = krylov.solve(_t(A, device), _t(b, device), method="cg")
+    _, io = oracle.cg(A, b)
+    assert info["status"] == io["status"] == 2
+
+
+def test_maxiter(device):
+    from paper_1511_07207_amd import krylov
+
+    p = spd_problem(300, 1e4, seed=2, config_id=0)
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="cg", tol=1e-12, max_iter=5)
+    xo, io = oracle.cg(p.A, p.b, tol=1e-12, max_iter=5)
+    assert info["status"] == io["status"] == 1 and info["iters"] == 5
+    assert _rel(x.cpu().numpy(), xo) <= 1e-12
+    q = nonsym_problem(300, seed=2, config_id=1)
+    x, info = krylov.solve(_t(q.A, device), _t(q.b, device), method="gmres", tol=1e-14,
+                           max_iter=7, restart=3)
+    xo, io = oracle.gmres(q.A, q.b, tol=1e-14, max_iter=7, restart=3)
+    assert info["status"] == io["status"] == 1 and info["iters"] == 7
+    assert info["restarts"] == io["cycles"] - 1 == 2
+    assert _rel(x.cpu().numpy(), xo) <= 1e-12
+
+
+def test_unaligned_lda_is_copied(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n = 333
+    p = spd_problem(n, 100.0, seed=3, config_id=0)
+    big = np.zeros((n, n + 2))
+    big[:, :n] = p.A
+    big[:, n:] = np.nan  # padding the solver must never read
+    At = torch.from_numpy(big).to(device)[:, :n]
+    assert At.stride(0) == n + 2  # odd: rows are not 16-byte aligned -> padded copy
+    x, info = krylov.solve(At, _t(p.b, device), method="cg", tol=1e-10)
+    xo, _ = oracle.cg(p.A, p.b, tol=1e-10)
+    assert info["status"] == 0
+    assert _rel(x.cpu().numpy(), xo) <= 1e-8
+
+
+def test_repeated_solves_are_bitwise_identical(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    p = spd_problem(1500, 1e3, seed=4, config_id=0)
+    s = krylov.Solver(_t(p.A, device), method="cg", tol=1e-10)
+    b = _t(p.b, device)
+    x1, i1 = s.solve(b)
+    x2, i2 = s.solve(b)
+    torch.cuda.synchronize()
+    s.close()
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+
+
+# ------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("method,prec,kappa", [("cg", "fp32", 1e2), ("cg", "fp32", 1e4),
+                                               ("cg", "bf16", 1e2), ("gmres", "fp32", None),
+                                               ("gmres", "bf16", None)])
+def test_ir_reaches_backward_error(device, method, prec, kappa):
+    from paper_1511_07207_amd import krylov
+
+    print(f"ir {method} {prec} kappa={kappa}", flush=True)
+    n = 1024
+    if method == "cg":
+        p = spd_problem(n, kappa, seed=5, config_id=2)
+    else:
+        p = nonsym_problem(n, seed=5, config_id=2)
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method=method, precision=prec,
+                           tol=1e-12, max_iter=4 * n, restart=50)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    m = oracle.metrics(p.A, p.b, x)
+    assert m["eta_inf"] <= 1e-12
+    assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + np.sqrt(n) * 2.0 ** -53
+    # forward error against the binary64 oracle run to its attainable accuracy
+    if method == "cg":
+        xo, _ = oracle.cg(p.A, p.b, tol=1e-14, max_iter=20 * n)
+    else:
+        xo, _ = oracle.gmres(p.A, p.b, tol=1e-14, restart=50, max_iter=20 * n)
+    k = kappa if kappa else 10.0
+    assert _rel(x, xo) <= max(1e-8, 100 * k * 1e-14)
+
+
+def test_ir_bf16_spd_high_kappa_falls_back(device):
+    from paper_1511_07207_amd import krylov
+
+    n = 1024
+    p = spd_problem(n, 1e5, seed=6, config_id=2)
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="cg", precision="bf16",
+                           tol=1e-12, max_iter=4 * n)
+    assert info["status"] == 0, info
+    assert info["precision_used"] in ("fp32", "fp64")
+    assert oracle.metrics(p.A, p.b, x.cpu().numpy())["eta_inf"] <= 1e-12
