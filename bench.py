@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the dense Krylov solvers on one MI355X.
+
+One step = one pass of the binary64 hot path over one batch of synthetic
+input: a CG solve of the SPD system (n = 16384, cond_2 = 1e4) and a GMRES(30)
+solve of the nonsymmetric system A = D + G/sqrt(n) (n = 16384), both from
+x0 = 0 to relative residual 1e-10.  The matrices and right-hand sides are
+generated on the device before timing (seeded; see workloads/gen.py) and the
+solvers are created (A borrowed in place, ||A||_inf computed) before timing.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384]
+
+Prints one JSON line (metric, value = solves/s, ...) with
+  roofline:      the FP64 GEMV of the CG loop (the dominant kernel):
+                 algorithmic bytes per launch / mean launch time measured with
+                 HIP events on the library's stream during the timed steps;
+  cpu_baseline:  the CPU oracle timed on a bounded sample of the same
+                 systems (a few hundred iterations), scaled to the
+                 iteration counts of a full step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("ks_gemv.hip", "ks_device.h", "ks_internal.h"):
+        with open(os.path.join(ROOT, "paper_1511_07207_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n: int):
+    """HBM bytes per GEMV launch from the committed rocprofv3 PMC summary, or
+    None if there is none for this size or the kernel source changed since."""
+    path = os.path.join(PROFILES, f"cg_matvec_f64_n{n}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"^TRAFFIC_JSON (\{.*\})$", txt, re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spd, ns, cg_iters, gm_iters, steps_done):
+    """Time the oracle on a bounded sample and scale to one step's iterations."""
+    import numpy as np
+
+    import oracle
+
+    A1 = spd.A.cpu().numpy()
+    b1 = spd.b.cpu().numpy()
+    A2 = ns.A.cpu().numpy()
+    b2 = ns.b.cpu().numpy()
+    threads = oracle.get_threads()
+    # about 10 s of oracle work on a 16-core host: a whole GMRES solve and up
+    # to 1000 CG iterations
+    s_cg = max(1, min(cg_iters, 1000))
+    s_gm = max(1, gm_iters)
+    t = time.perf_counter()
+    _, i1 = oracle.cg(A1, b1, tol=1e-300, max_iter=s_cg)
+    t_cg = time.perf_counter() - t
+    t = time.perf_counter()
+    _, i2 = oracle.gmres(A2, b2, tol=1e-300, max_iter=s_gm, restart=30)
+    t_gm = time.perf_counter() - t
+    est_step = t_cg * cg_iters / i1["iters"] + t_gm * gm_iters / i2["iters"]
+    return {
+        "value": 2.0 / est_step,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{i1['iters']} CG iterations ({t_cg:.1f} s) and {i2['iters']} GMRES(30) "
+                   f"steps ({t_gm:.1f} s) of the same n={spd.n} systems, scaled to one step "
+                   f"({cg_iters} CG + {gm_iters} GMRES iterations)"),
+        "est_step_s": est_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
+                    help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
+                         "(same spectrum and bytes; for hardware-counter runs)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="before timing, copy A once with the library's binary64 copy kernel "
+                         "(known bytes: 8 n^2 read + 8 n^2 written) to calibrate HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem, spd_problem
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t0 = time.perf_counter()
+    spd = spd_problem(n, 1e4, seed=0, config_id=1, backend="torch", device="cuda",
+                      q_form=args.spd_form)
+    ns = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated n={n} systems in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True)
+    gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    xcg = torch.zeros(n, dtype=torch.float64, device=dev)
+    xgm = torch.zeros(n, dtype=torch.float64, device=dev)
+    if args.calibration_copy:
+        copy = krylov.convert(spd.A, torch.float64)
+        torch.cuda.synchronize()
+        del copy
+
+    def step():
+        xcg.zero_()
+        t = time.perf_counter()
+        _, icg = cg.solve(spd.b, out=xcg)
+        t1 = time.perf_counter()
+        xgm.zero_()
+        _, igm = gm.solve(ns.b, out=xgm)
+        t2 = time.perf_counter()
+        return icg, igm, (t1 - t) * 1e3, (t2 - t1) * 1e3
+
+    for w in range(args.warmup):
+        step()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for k in range(args.steps):
+        recs.append(step())
+        print(f"[bench] step {k + 1}/{args.steps}: cg {recs[-1][2]:.1f} ms "
+              f"({recs[-1][0]['iters']} it), gmres {recs[-1][3]:.1f} ms "
+              f"({recs[-1][1]['iters']} it)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ok = all(r[0]["status"] == 0 and r[1]["status"] == 0 and r[0]["rel_res"] <= 1e-10
+             and r[1]["rel_res"] <= 1e-10 for r in recs)
+    solves = 2 * args.steps
+    value = solves / elapsed
+    ms_step = elapsed * 1e3 / args.steps
+    # dominant kernel: the FP64 GEMV of the CG loop, q = A p
+    gemv_ms = sum(r[0]["gemv_ms"] for r in recs)
+    gemv_calls = sum(r[0]["gemv_calls"] for r in recs)
+    gm_gemv_ms = sum(r[1]["gemv_ms"] for r in recs)
+    gm_gemv_calls = sum(r[1]["gemv_calls"] for r in recs)
+    bytes_per_launch = 8.0 * n * n + 2 * 8.0 * n   # A once, p in, q out
+    avg_ms = gemv_ms / max(gemv_calls, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(n)
+    cg_iters = recs[-1][0]["iters"]
+    gm_iters = recs[-1][1]["iters"]
+    out = {
+        "metric": "solves/s (FP64 CG + GMRES(30), n=16384, rel. residual 1e-10)",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"CG on SPD n={n} (Q diag(lambda) Q^T, lambda log-uniform [1,1e4]) + "
+                         f"GMRES(30) on D + G/sqrt(n), n={n}; x0=0, tol 1e-10; one of each per step"),
+            "n": n, "kappa_spd": 1e4, "restart": 30, "tol": 1e-10, "spd_q": args.spd_form,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "cg_matvec_kernel<double> (q = A p, p'q partials)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": round(avg_ms, 5),
+            "launches": gemv_calls,
+        },
+        "valid": ok,
+        "solves": {
+            "cg": {"iters": cg_iters, "rel_res": recs[-1][0]["rel_res"],
+                   "backward_err": recs[-1][0]["backward_err"],
+                   "p50_ms": round(_pct([r[2] for r in recs], 0.5), 3),
+                   "p99_ms": round(_pct([r[2] for r in recs], 0.99), 3)},
+            "gmres": {"iters": gm_iters, "rel_res": recs[-1][1]["rel_res"],
+                      "backward_err": recs[-1][1]["backward_err"],
+                      "p50_ms": round(_pct([r[3] for r in recs], 0.5), 3),
+                      "p99_ms": round(_pct([r[3] for r in recs], 0.99), 3),
+                      "gemv_gbs": round(bytes_per_launch / (gm_gemv_ms / max(gm_gemv_calls, 1) * 1e-3) / 1e9, 1)},
+        },
+        "iterations_per_s": round((cg_iters + gm_iters) * args.steps / elapsed, 1),
+        "create_ms": round(create_ms, 2),
+        "generate_s": round(gen_s, 2),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spd, ns, cg_iters, gm_iters, args.steps)
+    else:
+        out["cpu_baseline"] = None
+    cg.close()
+    gm.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

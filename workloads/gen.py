@@ -129,8 +129,26 @@ def _lam_torch(n, kappa, seed, config_id, key, device):
 
 def spd_problem(n: int, kappa: float, seed: int = 0, config_id: int = 0,
                 key: Sequence[int] = (), nrhs: int = 1, backend: str = "numpy",
-                device: str = "cuda") -> Problem:
-    """SPD system with cond_2(A) = kappa (recipe in the module docstring)."""
+                device: str = "cuda", q_form: str = "qr") -> Problem:
+    """SPD system with cond_2(A) = kappa (recipe in the module docstring).
+
+    q_form="identity" takes Q = I, i.e. A = diag(lambda) stored densely: the
+    same spectrum and the same bytes per matrix-vector product, for hardware
+    counter runs in which the QR library call cannot run under the profiler.
+    """
+    if q_form == "identity":
+        if backend == "numpy":
+            lam = _log_uniform(_np_rng(seed, config_id, key, ROLE_LAM), n, kappa)
+            A = np.diag(lam)
+            x, b = _rhs_numpy(A, n, nrhs, seed, config_id, key)
+        else:
+            torch = _torch()
+            lam = _lam_torch(n, kappa, seed, config_id, key, device)
+            A = torch.diag(lam).contiguous()
+            x, b = _rhs_torch(A, n, nrhs, seed, config_id, key, device)
+        return Problem(A, b, x, "spd", n, float(kappa),
+                       dict(seed=seed, config_id=config_id, key=list(key), backend=backend,
+                            q_form=q_form))
     if backend == "numpy":
         lam = _log_uniform(_np_rng(seed, config_id, key, ROLE_LAM), n, kappa)
         G = _np_rng(seed, config_id, key, ROLE_G).standard_normal((n, n))
