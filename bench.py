@@ -145,6 +145,16 @@ def main():
     create_ms = (time.perf_counter() - t0) * 1e3
     xcg = torch.zeros(n, dtype=torch.float64, device=dev)
     xgm = torch.zeros(n, dtype=torch.float64, device=dev)
+    # measured HBM read ceiling: the library's streaming-read kernel over A
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    krylov.read_ceiling(spd.A, sink)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        krylov.read_ceiling(spd.A, sink)
+    ev1.record()
+    torch.cuda.synchronize()
+    read_ceiling_gbs = 8.0 * n * n / (ev0.elapsed_time(ev1) / 10 * 1e-3) / 1e9
     if args.calibration_copy:
         copy = krylov.convert(spd.A, torch.float64)
         torch.cuda.synchronize()
@@ -216,6 +226,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "read_ceiling_gbs": round(read_ceiling_gbs, 1),
+            "frac_of_read_ceiling": round(achieved / read_ceiling_gbs, 4),
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": round(avg_ms, 5),

@@ -82,7 +82,7 @@ Layout make_layout(const ks_params *p) {
     off = align_up(off + 2 * sizeof(State));
     L.gm_off = off;
     off = align_up(off + gm_doubles(L.m) * sizeof(double));
-    L.pg = (size_t)round_up(gemv_blocks(n) * 3, 32);
+    L.pg = (size_t)round_up((int64_t)gemv_blocks_max(n) * 3, 32);
     L.pv = (size_t)round_up(vec_blocks(n), 32);
     L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
     L.pn = (size_t)round_up(cgs_blocks(n), 32);
@@ -271,7 +271,7 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
                 if (e0) HIPCHK(hipEventRecord(e0, sm));
                 HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
                 if (e1) HIPCHK(hipEventRecord(e1, sm));
-                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, sm));
+                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, gemv_blocks<TA>(n), sm));
                 HIPCHK(launch_cg_pupdate<T>(n, r, p, st, s->P, max_iter, sm));
             }
             if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));

@@ -51,10 +51,11 @@ struct Partials {
     double *nrm;  // ||w||^2 after pass 2: 1 per block
 };
 
-// Tuning of the dense matrix-vector product: ROWS rows per block of NT threads,
-// the block's threads split each row's columns in 16-byte chunks.
+// Tuning of the dense matrix-vector product: a block of GEMV_NT threads owns
+// GemvShape<TA>::ROWS rows and its threads split each row's columns in 16-byte
+// chunks, UNR chunks in flight per lane (values from a sweep on MI355X: rows
+// in {1,2,4,8,16}, threads in {128,256,512}, unroll in {1,2,4,8}).
 constexpr int GEMV_NT = 256;
-constexpr int GEMV_ROWS = 8;
 // Vector kernels: threads per block, elements per thread.
 constexpr int VEC_NT = 256;
 constexpr int VEC_EPT = 4;
@@ -66,13 +67,34 @@ constexpr int ONE_NT = 1024;
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-inline int gemv_blocks(int n) { return div_up(n, GEMV_ROWS); }
 inline int vec_blocks(int n) { return div_up(n, VEC_NT * VEC_EPT); }
 inline int cgs_blocks(int n) { return div_up(n, CGS_NT); }
 
 struct bf16_t {
     uint16_t bits;
 };
+
+template <typename TA>
+struct GemvShape;
+template <>
+struct GemvShape<double> {
+    static constexpr int ROWS = 2, UNR = 4;
+};
+template <>
+struct GemvShape<float> {
+    static constexpr int ROWS = 2, UNR = 4;
+};
+template <>
+struct GemvShape<bf16_t> {
+    static constexpr int ROWS = 4, UNR = 4;
+};
+// blocks (= partials) of a GEMV-shaped launch on element type TA
+template <typename TA>
+inline int gemv_blocks(int n) {
+    return div_up(n, GemvShape<TA>::ROWS);
+}
+// the largest of them, for sizing the partial region
+inline int gemv_blocks_max(int n) { return div_up(n, 2); }
 
 // GMRES small dense arrays (binary64 always).
 struct GmArrays {
@@ -108,9 +130,10 @@ hipError_t launch_residual(int n, int64_t lda, const TA *A, const T *b, const T 
 template <typename TA, typename T>
 hipError_t launch_cg_matvec(int n, int64_t lda, const TA *A, const T *p, T *q, State *st,
                             Partials P, hipStream_t s);
+// nsigma: number of partials the matrix-vector product left (gemv_blocks<TA>)
 template <typename T>
 hipError_t launch_cg_update(int n, T *x, T *r, const T *p, const T *q, State *st, Partials P,
-                            hipStream_t s);
+                            int nsigma, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int max_iter,
                              hipStream_t s);
