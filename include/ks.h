@@ -87,9 +87,14 @@ typedef struct {
     int32_t poll_every; /* host checks the device's stop flag every this many
                            iterations (0 = chosen from n)                          */
     int32_t flags;      /* KS_FLAG_*                                              */
+    int32_t nrhs;       /* right-hand sides solved together (CG only): 1, or up to
+                           KS_MAX_NRHS for lockstep CG with A*P on the matrix
+                           cores; precision KS_FP64 or KS_IR_FP32               */
+    int32_t reserved;
 } ks_params;
 
 #define KS_MAX_RESTART 128
+#define KS_MAX_NRHS 64
 
 typedef struct {
     int32_t status;        /* KS_OK or a positive outcome                           */
@@ -130,8 +135,19 @@ int ks_create(ks_solver **out, const ks_params *p, const double *d_A, void *d_ws
 /* Solve A x = b.  d_b: n binary64 values; d_x: n binary64 values, x0 on
  * entry, the solution on return (the last iterate for a positive status).
  * Both must be 16-byte aligned (KS_EINVAL otherwise).
+ * With nrhs = s > 1, d_b and d_x are n x s column-major (right-hand side j
+ * at d_b + j * n): s independent CG solves advanced in lockstep, each column
+ * with its own scalars and stopping test (equal to the one-column solve in
+ * exact arithmetic); *info then summarises them (worst status, largest
+ * residual and backward error, lockstep iterations) and ks_column_info gives
+ * each column.
  * Returns the status (also in info->status); info may be NULL. */
 int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info);
+
+/* Result of column j (0 <= j < nrhs) of the last ks_solve: status, iters
+ * (products in which the column took part), restarts, rel_res and
+ * backward_err of that column.  KS_EINVAL if j is out of range. */
+int ks_column_info(const ks_solver *s, int32_t j, ks_info *info);
 
 /* Run k Arnoldi steps (classical Gram-Schmidt applied twice) from d_v0,
  * which is normalised first.  d_V receives the basis, vector j at

@@ -20,14 +20,15 @@ KS_FP64, KS_IR_FP32, KS_IR_BF16 = 0, 1, 2
 KS_DT_F64, KS_DT_F32, KS_DT_BF16 = 0, 1, 2
 KS_FLAG_TIMING = 1
 KS_MAX_RESTART = 128
+KS_MAX_NRHS = 64
 
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfinite",
                 -1: "einval", -2: "enomem", -3: "ehip", -4: "edevice"}
 
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
-           "ks_solve", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv", "ks_convert",
-           "ks_read_ceiling")
+           "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
+           "ks_convert", "ks_read_ceiling")
 
 
 class KsParams(ctypes.Structure):
@@ -43,6 +44,8 @@ class KsParams(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("poll_every", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("nrhs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -98,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.ks_create.restype = ctypes.c_int
         L.ks_solve.argtypes = [vp, vp, vp, ctypes.POINTER(KsInfo)]
         L.ks_solve.restype = ctypes.c_int
+        L.ks_column_info.argtypes = [vp, i32, ctypes.POINTER(KsInfo)]
+        L.ks_column_info.restype = ctypes.c_int
         L.ks_arnoldi.argtypes = [vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
         L.ks_arnoldi.restype = ctypes.c_int
         L.ks_free.argtypes = [vp]

@@ -52,6 +52,10 @@ struct Layout {
     size_t afb_off = 0;     // binary32 copy used after a bfloat16 -> binary32 fallback
     size_t afb_bytes = 0;
     int64_t lda_low = 0;
+    // multi-right-hand-side blocks (nrhs > 1): X, R, P, Q and S partial Q's,
+    // each sp16 columns of ldv elements, plus per-column states
+    int sp16 = 0;
+    size_t mr_off = 0, mr_block_elems = 0, mr_cols_off = 0, mr_part_off = 0, mr_part_count = 0;
     size_t total = 0;
     size_t total_borrowed = 0;
 };
@@ -69,6 +73,8 @@ bool valid_params(const ks_params *p) {
     if (p->precision != KS_FP64) {
         if (!(p->inner_tol > 0.0) || p->max_outer < 1) return false;
     }
+    if (p->nrhs < 1 || p->nrhs > KS_MAX_NRHS) return false;
+    if (p->nrhs > 1 && (p->method != KS_CG || p->precision == KS_IR_BF16)) return false;
     return true;
 }
 
@@ -99,6 +105,22 @@ Layout make_layout(const ks_params *p) {
     if (p->precision != KS_FP64) L.nv32 = 2 + ((p->method == KS_CG) ? 3 : 1 + (L.m + 1));
     L.v32_off = off;
     off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
+    if (p->nrhs > 1) {
+        L.sp16 = (int)round_up(p->nrhs, 16);
+        L.mr_block_elems = (size_t)L.sp16 * L.ldv;
+        const size_t es = sizeof(double);
+        L.mr_off = off;
+        // X, R, P, Q + mr_splits(n) partial products (binary64); the IR inner
+        // solve adds its binary32 D, R, P, Q and partials below
+        off = align_up(off + (4 + (size_t)mr_splits(n)) * L.mr_block_elems * es);
+        if (p->precision == KS_IR_FP32)
+            off = align_up(off + (5 + (size_t)mr_splits(n)) * L.mr_block_elems * sizeof(float));
+        L.mr_cols_off = off;
+        off = align_up(off + 2 * (size_t)KS_MAX_NRHS * sizeof(ColState));
+        L.mr_part_count = 3 * (size_t)mr_blocks(n) * KS_MAX_NRHS;
+        L.mr_part_off = off;
+        off = align_up(off + L.mr_part_count * sizeof(double));
+    }
     L.lda_low = round_up(n, 64);
     if (p->precision == KS_IR_FP32) {
         L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
@@ -150,8 +172,17 @@ struct ks_solver {
     double gemv_ms = 0.0;
     int gemv_calls = 0;
     double anorm_inf = 0.0;
+    // multi-right-hand-side
+    double *mr64 = nullptr;   // X, R, P, Q, Qpart (binary64)
+    float *mr32 = nullptr;    // D, R, P, Q, rhs, Qpart (binary32, IR inner solve)
+    ColState *cols = nullptr, *cols_in = nullptr;
+    ColState *host_cols = nullptr;
+    double *mr_part = nullptr;
+    std::vector<ks_info> col_info;
 
     double *vec64(int i) const { return v64 + (size_t)i * L.ldv; }
+    double *mrb64(int i) const { return mr64 + (size_t)i * L.mr_block_elems; }
+    float *mrb32(int i) const { return mr32 + (size_t)i * L.mr_block_elems; }
     float *vec32(int i) const { return v32 + (size_t)i * L.ldv; }
     bool timing() const { return (p.flags & KS_FLAG_TIMING) != 0; }
 };
@@ -403,6 +434,228 @@ int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_ite
                                      tol, max_iter, o);
 }
 
+// ----------------------------------------------- multi-right-hand-side CG
+int sync_mr(ks_solver *s) {
+    HIPCHK(hipMemcpyAsync(s->host, s->st, 2 * sizeof(State), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(s->host_cols, s->cols, 2 * (size_t)KS_MAX_NRHS * sizeof(ColState),
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return KS_OK;
+}
+
+// Lockstep CG on s columns.  outer = true: binary64 solve confirmed on the
+// true residual, failing columns restarted (as the one-column solve); false:
+// one pass stopped on the recursive residuals (refinement inner solve).
+// status[j], iters[j], restarts[j] receive each column's outcome.
+template <typename T>
+int run_mrhs(ks_solver *s, State *st, ColState *cols, int ci, const T *A, int64_t lda, const T *B,
+             int ldb, T *X, T *R, T *P, T *Q, T *Qpart, double tol, int max_iter, bool outer,
+             std::vector<int> &status, std::vector<int> &restarts) {
+    const int n = s->n, ns = s->p.nrhs, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    double *pa = s->mr_part, *pb = s->mr_part + (size_t)mr_blocks(n) * KS_MAX_NRHS;
+    HIPCHK(launch_mr_stats<T>(n, ns, B, ldb, tol, cols, st, sm));
+    HIPCHK(launch_mr_residual<T>(n, lda, A, ns, B, ldb, X, Qpart, R, ldv, s->mr_part, cols, st, 0, sm));
+    int rc = sync_mr(s);
+    if (rc) return rc;
+    const ColState *hc = s->host_cols + (size_t)ci * KS_MAX_NRHS;
+    const State *h = &s->host[ci];
+    status.assign(ns, -100);
+    restarts.assign(ns, 0);
+    std::vector<char> started(ns, 0);
+    for (int j = 0; j < ns; ++j)
+        if (hc[j].bnorm == 0.0) {
+            HIPCHK(launch_fill<T>(n, X + (size_t)j * ldv, T(0), sm));
+            status[j] = KS_OK;
+        }
+    for (;;) {
+        uint64_t mask = 0;
+        for (int j = 0; j < ns; ++j) {
+            if (status[j] != -100) continue;
+            const int f = hc[j].flags;
+            if (f & F_TRUE_NONFIN)
+                status[j] = KS_NONFINITE;
+            else if (f & F_TRUE_OK)
+                status[j] = KS_OK;
+            else if (started[j] && (f & F_BREAK))
+                status[j] = KS_BREAKDOWN;
+            else if (started[j] && (f & F_NONFIN))
+                status[j] = KS_NONFINITE;
+            else if (hc[j].iters >= max_iter)
+                status[j] = KS_MAXITER;
+            else if (started[j] && restarts[j] >= CG_MAX_RESTARTS)
+                status[j] = KS_STAGNATED;
+            else {
+                if (started[j]) ++restarts[j];
+                started[j] = 1;
+                mask |= 1ull << j;
+            }
+        }
+        if (!mask) break;
+        HIPCHK(launch_mr_begin<T>(n, ns, R, P, ldv, cols, st, mask, sm));
+        bool done = false;
+        while (!done) {
+            const int it0 = h->iters;
+            const int chunk = std::max(1, std::min(poll_chunk(s), max_iter));
+            for (int c = 0; c < chunk; ++c) {
+                hipEvent_t e0, e1;
+                if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                HIPCHK(launch_mr_iteration<T>(n, lda, A, ns, X, R, P, Q, Qpart, ldv, pa, pb, cols, st,
+                                              max_iter, sm, e0, e1));
+            }
+            if (outer)
+                HIPCHK(launch_mr_residual<T>(n, lda, A, ns, B, ldb, X, Qpart, R, ldv, s->mr_part, cols,
+                                             st, 1, sm));
+            if ((rc = sync_mr(s))) return rc;
+            if ((rc = timed_collect(s, h->iters - it0))) return rc;
+            done = (h->flags & F_STOP) != 0;
+        }
+        if (!outer) {
+            for (int j = 0; j < ns; ++j) {
+                if (status[j] != -100) continue;
+                const int f = hc[j].flags;
+                status[j] = (f & F_CONV)     ? KS_OK
+                            : (f & F_BREAK)  ? KS_BREAKDOWN
+                            : (f & F_NONFIN) ? KS_NONFINITE
+                                             : KS_MAXITER;
+            }
+            break;
+        }
+    }
+    return KS_OK;
+}
+
+int solve_mrhs_fp64(ks_solver *s, const double *B, double *Xuser, ks_info *info, Outcome *o) {
+    const int n = s->n, ns = s->p.nrhs, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    double *X = s->mrb64(0), *R = s->mrb64(1), *P = s->mrb64(2), *Q = s->mrb64(3),
+           *Qp = s->mrb64(4);
+    HIPCHK(launch_mr_copy<double>(n, ns, Xuser, n, X, ldv, sm));
+    std::vector<int> status, restarts;
+    int rc = run_mrhs<double>(s, s->st, s->cols, 0, s->A, s->lda, B, n, X, R, P, Q, Qp, s->p.tol,
+                              s->p.max_iter, true, status, restarts);
+    if (rc) return rc;
+    HIPCHK(launch_mr_copy<double>(n, ns, X, ldv, Xuser, n, sm));
+    s->col_info.assign(ns, ks_info{});
+    o->status = KS_OK;
+    o->iters = s->host[0].iters;
+    info->rel_res = 0.0;
+    info->backward_err = 0.0;
+    for (int j = 0; j < ns; ++j) {
+        const ColState &c = s->host_cols[j];
+        ks_info &ci = s->col_info[j];
+        ci.status = status[j];
+        ci.iters = c.iters;
+        ci.restarts = restarts[j];
+        const double den = s->host[0].anorm_inf * c.xinf + c.binf;
+        ci.rel_res = c.bnorm > 0.0 ? c.res / c.bnorm : 0.0;
+        ci.backward_err = c.bnorm > 0.0 ? (den > 0.0 ? c.resinf / den : c.resinf) : 0.0;
+        ci.precision_used = KS_FP64;
+        o->status = std::max(o->status, status[j]);
+        o->restarts = std::max(o->restarts, restarts[j]);
+        info->rel_res = std::max(info->rel_res, ci.rel_res);
+        info->backward_err = std::max(info->backward_err, ci.backward_err);
+    }
+    return KS_OK;
+}
+
+// Refinement around lockstep CG: binary64 residuals R = B - A X, per-column
+// backward error; inner lockstep CG on the binary32 copy of A for the active
+// columns (MFMA binary32 contraction); X_j += ||r_j|| d_j.
+int solve_mrhs_ir(ks_solver *s, const double *B, double *Xuser, ks_info *info, Outcome *o) {
+    const int n = s->n, ns = s->p.nrhs, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    double *X = s->mrb64(0), *R = s->mrb64(1), *Qp = s->mrb64(4);
+    float *D = s->mrb32(0), *R32 = s->mrb32(1), *P32 = s->mrb32(2), *Q32 = s->mrb32(3),
+          *rhs = s->mrb32(4), *Qp32 = s->mrb32(5);
+    const float *A32 = (const float *)s->A_low;
+    const int64_t ll = s->L.lda_low;
+    HIPCHK(launch_mr_copy<double>(n, ns, Xuser, n, X, ldv, sm));
+    HIPCHK(launch_mr_stats<double>(n, ns, B, n, 1.0, s->cols, s->st, sm));
+    HIPCHK(launch_mr_residual<double>(n, s->lda, s->A, ns, B, n, X, Qp, R, ldv, s->mr_part, s->cols,
+                                      s->st, 0, sm));
+    int rc = sync_mr(s);
+    if (rc) return rc;
+    const ColState *hc = s->host_cols;
+    const double anorm = s->host[0].anorm_inf;
+    std::vector<int> status(ns, -100), bad(ns, 0), inner_iters(ns, 0);
+    std::vector<double> eta_prev(ns, INFINITY);
+    int outer = 0;
+    auto eta_of = [&](int j) {
+        const double den = anorm * hc[j].xinf + hc[j].binf;
+        return den > 0.0 ? hc[j].resinf / den : hc[j].resinf;
+    };
+    for (int j = 0; j < ns; ++j)
+        if (hc[j].bnorm == 0.0) {
+            HIPCHK(launch_fill<double>(n, X + (size_t)j * ldv, 0.0, sm));
+            status[j] = KS_OK;
+        }
+    for (;;) {
+        uint64_t mask = 0;
+        for (int j = 0; j < ns; ++j) {
+            if (status[j] != -100) continue;
+            const double eta = eta_of(j);
+            if (!std::isfinite(eta) || (hc[j].flags & F_TRUE_NONFIN))
+                status[j] = KS_NONFINITE;
+            else if (eta <= s->p.tol)
+                status[j] = KS_OK;
+            else if (outer >= s->p.max_outer)
+                status[j] = KS_STAGNATED;
+            else {
+                if (eta > 0.5 * eta_prev[j]) {
+                    if (++bad[j] >= 2) {
+                        status[j] = KS_STAGNATED;
+                        continue;
+                    }
+                } else {
+                    bad[j] = 0;
+                }
+                eta_prev[j] = eta;
+                mask |= 1ull << j;
+            }
+        }
+        if (!mask) break;
+        HIPCHK(launch_mr_ir_scale(n, ns, R, ldv, rhs, s->cols, mask, sm));
+        HIPCHK(launch_fill<float>((int)std::min<size_t>((size_t)ns * ldv, 0x7fffffff), D, 0.0f, sm));
+        std::vector<int> ist, irs;
+        rc = run_mrhs<float>(s, s->st_in, s->cols_in, 1, A32, ll, rhs, ldv, D, R32, P32, Q32, Qp32,
+                             s->p.inner_tol, s->p.max_iter, false, ist, irs);
+        if (rc) return rc;
+        for (int j = 0; j < ns; ++j)
+            if ((mask >> j) & 1ull) {
+                inner_iters[j] += s->host_cols[KS_MAX_NRHS + j].iters;
+                if (ist[j] == KS_BREAKDOWN || ist[j] == KS_NONFINITE) status[j] = KS_BREAKDOWN;
+            }
+        HIPCHK(launch_mr_ir_update(n, ns, X, D, ldv, s->cols, mask, sm));
+        HIPCHK(launch_mr_residual<double>(n, s->lda, s->A, ns, B, n, X, Qp, R, ldv, s->mr_part, s->cols,
+                                          s->st, 0, sm));
+        if ((rc = sync_mr(s))) return rc;
+        ++outer;
+    }
+    HIPCHK(launch_mr_copy<double>(n, ns, X, ldv, Xuser, n, sm));
+    s->col_info.assign(ns, ks_info{});
+    o->status = KS_OK;
+    o->iters = 0;
+    info->rel_res = 0.0;
+    info->backward_err = 0.0;
+    info->outer_iters = outer;
+    info->precision_used = KS_IR_FP32;
+    for (int j = 0; j < ns; ++j) {
+        ks_info &ci = s->col_info[j];
+        ci.status = status[j];
+        ci.iters = inner_iters[j];
+        ci.outer_iters = outer;
+        ci.rel_res = hc[j].bnorm > 0.0 ? hc[j].res / hc[j].bnorm : 0.0;
+        ci.backward_err = hc[j].bnorm > 0.0 ? eta_of(j) : 0.0;
+        ci.precision_used = KS_IR_FP32;
+        o->status = std::max(o->status, status[j]);
+        o->iters = std::max(o->iters, inner_iters[j]);
+        info->rel_res = std::max(info->rel_res, ci.rel_res);
+        info->backward_err = std::max(info->backward_err, ci.backward_err);
+    }
+    return KS_OK;
+}
+
 // ------------------------------------------------- iterative refinement
 // Outer binary64 loop: r = b - A x; stop at eta_inf <= tol; inner solve of
 // A_low d = r/||r|| (binary32 vectors); x += ||r|| d.  Precision is promoted
@@ -545,6 +798,7 @@ int ks_params_init(ks_params *p, int32_t n, int32_t method) {
     p->inner_tol = 1e-4;
     p->poll_every = 0;
     p->flags = 0;
+    p->nrhs = 1;
     return KS_OK;
 }
 
@@ -627,8 +881,20 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
     }
     s->v64 = (double *)(s->ws + L.v64_off);
     s->v32 = (float *)(s->ws + L.v32_off);
+    if (p->nrhs > 1) {
+        s->mr64 = (double *)(s->ws + L.mr_off);
+        s->mr32 = (float *)(s->ws + L.mr_off + (4 + (size_t)mr_splits(p->n)) * L.mr_block_elems * sizeof(double));
+        s->cols = (ColState *)(s->ws + L.mr_cols_off);
+        s->cols_in = s->cols + KS_MAX_NRHS;
+        s->mr_part = (double *)(s->ws + L.mr_part_off);
+        if (hipHostMalloc((void **)&s->host_cols, 2 * (size_t)KS_MAX_NRHS * sizeof(ColState),
+                          hipHostMallocDefault) != hipSuccess) {
+            ks_free(s);
+            return KS_EHIP;
+        }
+    }
     hipStream_t sm = s->stream;
-    // zero the states (tickets must start at 0) and the small arrays
+    // zero the states and the small arrays
     if (hipMemsetAsync(s->ws, 0, L.part_off, sm) != hipSuccess) {
         ks_free(s);
         return KS_EHIP;
@@ -675,7 +941,14 @@ int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info) {
     HIPCHK(hipEventRecord(s->ev0, s->stream));
     Outcome o;
     int rc;
-    if (s->p.precision == KS_FP64) {
+    if (s->p.nrhs > 1) {
+        if (s->p.precision == KS_FP64)
+            rc = solve_mrhs_fp64(s, d_b, d_x, info, &o);
+        else
+            rc = solve_mrhs_ir(s, d_b, d_x, info, &o);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(s->ev1, s->stream));
+    } else if (s->p.precision == KS_FP64) {
         rc = solve_fp64(s, d_b, d_x, s->p.tol, s->p.max_iter, &o);
         if (rc) return rc;
         HIPCHK(hipEventRecord(s->ev1, s->stream));
@@ -728,6 +1001,12 @@ int ks_arnoldi(ks_solver *s, const double *d_v0, int32_t k, double *d_V, double 
     return KS_OK;
 }
 
+int ks_column_info(const ks_solver *s, int32_t j, ks_info *info) {
+    if (!s || !info || j < 0 || j >= (int32_t)s->col_info.size()) return KS_EINVAL;
+    *info = s->col_info[j];
+    return KS_OK;
+}
+
 void ks_free(ks_solver *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
@@ -735,6 +1014,7 @@ void ks_free(ks_solver *s) {
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->host) (void)hipHostFree(s->host);
+    if (s->host_cols) (void)hipHostFree(s->host_cols);
     if (s->own_ws && s->ws) (void)hipFree(s->ws);
     delete s;
 }

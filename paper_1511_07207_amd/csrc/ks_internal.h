@@ -42,6 +42,14 @@ struct alignas(256) State {
     int32_t pad;
 };
 
+// Per-column scalars of lockstep multi-right-hand-side CG (same rule as State).
+struct ColState {
+    double bnorm, binf, thresh;
+    double rho, rho_prev, sigma;
+    double res, resinf, xinf;
+    int32_t iters, flags, restarts, pad;
+};
+
 // Per-block partial results, one region per producing kernel kind.
 struct Partials {
     double *g;    // GEMV-shaped kernels: 3 per block
@@ -178,5 +186,36 @@ template <typename T>
 hipError_t launch_fill(int n, T *x, T value, hipStream_t s);
 
 hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipStream_t s);
+
+// ------------------------------------------------ multi-right-hand-side CG
+// n x s column-major blocks with leading dimension ldv; s <= KS_MAX_NRHS.
+int mr_splits(int n);          // K splits of the contraction
+int mr_blocks(int n);          // blocks of the per-column kernels
+template <typename T>
+hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T *Qpart, int ldq,
+                          int s, const State *st, int gate, hipStream_t strm);
+template <typename T>
+hipError_t launch_mr_stats(int n, int s, const T *B, int ldb, double tol, ColState *cols,
+                           State *st, hipStream_t strm);
+// R = B - A X with per-column norms (gate 1: only when every column stopped)
+template <typename T>
+hipError_t launch_mr_residual(int n, int64_t lda, const T *A, int s, const T *B, int ldb,
+                              const T *X, T *Qpart, T *R, int ldv, double *part, ColState *cols,
+                              State *st, int gate, hipStream_t strm);
+template <typename T>
+hipError_t launch_mr_begin(int n, int s, const T *R, T *P, int ldv, ColState *cols, State *st,
+                           uint64_t mask, hipStream_t strm);
+// one lockstep iteration: Q = A P (MFMA), alpha, x/r update, stop tests, p update
+template <typename T>
+hipError_t launch_mr_iteration(int n, int64_t lda, const T *A, int s, T *X, T *R, T *P, T *Q,
+                               T *Qpart, int ldv, double *part_a, double *part_b, ColState *cols,
+                               State *st, int max_iter, hipStream_t strm, hipEvent_t e0,
+                               hipEvent_t e1);
+template <typename T>
+hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, hipStream_t strm);
+hipError_t launch_mr_ir_scale(int n, int s, const double *R, int ldv, float *rhs,
+                              const ColState *cols, uint64_t mask, hipStream_t strm);
+hipError_t launch_mr_ir_update(int n, int s, double *X, const float *D, int ldv,
+                               const ColState *cols, uint64_t mask, hipStream_t strm);
 
 }  // namespace ks

@@ -1,0 +1,599 @@
+// Multi-right-hand-side conjugate gradient in lockstep: s independent CG
+// recurrences (one per column of B) that share each iteration's product
+// Q = A P, an n x n times n x s dense contraction computed on the matrix
+// cores (MFMA).  Each column keeps its own alpha, beta, rho and stopping test,
+// exactly as a single-right-hand-side solve would (the Krylov section's CG,
+// column by column); columns that have converged are frozen.
+//
+// Layout: P, Q, R, X (working copy) and B are column-major n x s with leading
+// dimension ldv (each right-hand side contiguous); s is padded to a multiple
+// of 16 (the MFMA tile width), up to KS_MAX_NRHS.
+//
+// The contraction (binary64: v_mfma_f64_16x16x4f64; binary32 for the refined
+// inner solve: v_mfma_f32_16x16x4f32): a wave owns 32 rows of Q and all s
+// columns (2 x (s/16) accumulator tiles), walks K in steps of 16 and feeds
+// four MFMAs per tile per step.  K is permuted inside each step of 16 so
+// that every lane loads 4 consecutive elements of a row of A and of a column
+// of P (32 contiguous bytes) instead of 4 strided ones; the sum over K is
+// unchanged.  K is split S ways for parallelism (partials summed in fixed
+// order by the next kernel), and blocks are mapped to XCDs so that all blocks
+// of one split run on the same XCDs and that split's slice of P stays in
+// their L2.
+#include <algorithm>
+
+#include "ks_device.h"
+
+namespace ks {
+
+typedef double mr_d4 __attribute__((ext_vector_type(4)));
+typedef float mr_f4 __attribute__((ext_vector_type(4)));
+typedef double mr_d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    using Acc = mr_d4;
+    // lane l, accumulator item v holds D[4v + l/16][l%16]
+    static __device__ __forceinline__ int row_of(int v, int g) { return 4 * v + g; }
+    static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // 4 consecutive values at p (16-byte aligned)
+    static __device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
+        const mr_d2 x = *reinterpret_cast<const mr_d2 *>(p);
+        const mr_d2 y = *reinterpret_cast<const mr_d2 *>(p + 2);
+        o[0] = x.x;
+        o[1] = x.y;
+        o[2] = y.x;
+        o[3] = y.y;
+    }
+    static __device__ __forceinline__ void load4_nt(const double *p, double (&o)[4]) {
+        const mr_d2 x = __builtin_nontemporal_load(reinterpret_cast<const mr_d2 *>(p));
+        const mr_d2 y = __builtin_nontemporal_load(reinterpret_cast<const mr_d2 *>(p + 2));
+        o[0] = x.x;
+        o[1] = x.y;
+        o[2] = y.x;
+        o[3] = y.y;
+    }
+};
+template <>
+struct Mfma<float> {
+    using Acc = mr_f4;
+    // lane l, accumulator item v holds D[4(l/16) + v][l%16]
+    static __device__ __forceinline__ int row_of(int v, int g) { return 4 * g + v; }
+    static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
+        const mr_f4 x = *reinterpret_cast<const mr_f4 *>(p);
+        o[0] = x.x;
+        o[1] = x.y;
+        o[2] = x.z;
+        o[3] = x.w;
+    }
+    static __device__ __forceinline__ void load4_nt(const float *p, float (&o)[4]) {
+        const mr_f4 x = __builtin_nontemporal_load(reinterpret_cast<const mr_f4 *>(p));
+        o[0] = x.x;
+        o[1] = x.y;
+        o[2] = x.z;
+        o[3] = x.w;
+    }
+};
+
+constexpr int MR_WAVES = 4;      // waves per block
+constexpr int MR_WR = 32;        // rows of Q per wave (two 16-row tiles)
+constexpr int MR_BROWS = MR_WAVES * MR_WR;
+
+// Block -> (row block, split).  Work-groups are dispatched round-robin over
+// the 8 XCDs; give each split a fixed group of 8/S XCDs when the counts allow.
+__device__ __forceinline__ void mr_block_map(int nrb, int S, int &rb, int &sp) {
+    const int b = blockIdx.x;
+    if (S <= 8 && 8 % S == 0 && nrb % (8 / S) == 0) {
+        const int xpg = 8 / S;        // XCDs per split
+        const int xcd = b % 8, idx = b / 8;
+        sp = xcd / xpg;
+        rb = (xcd % xpg) + xpg * idx;
+    } else {
+        sp = b / nrb;
+        rb = b % nrb;
+    }
+}
+
+// Qpart[sp] = A[:, K_sp] * P[K_sp, :] for the split's K range.
+template <typename T, int CT>
+__global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t lda,
+                                                                  const T *__restrict__ A,
+                                                                  const T *__restrict__ P, int ldp,
+                                                                  T *__restrict__ Qpart, int ldq,
+                                                                  int S, int kchunk,
+                                                                  const State *st, int gate) {
+    using M = Mfma<T>;
+    using Acc = typename M::Acc;
+    if (gate == 2 && (st->flags & F_STOP)) return;       // iteration: skip when all stopped
+    if (gate == 1 && !(st->flags & F_STOP)) return;      // residual: only when all stopped
+    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    int rb, sp;
+    mr_block_map(nrb, S, rb, sp);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int row0 = rb * MR_BROWS + w * MR_WR;
+    const int kb = sp * kchunk, ke = min(n, kb + kchunk);
+    Acc acc[2][CT];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = Acc{0, 0, 0, 0};
+    const T *arow[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) arow[rt] = A + (int64_t)min(row0 + 16 * rt + c16, n - 1) * lda;
+    const T *pcol[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) pcol[ct] = P + (size_t)(16 * ct + c16) * ldp;
+    int k0 = kb;
+    // full steps of 16: every lane loads 4 consecutive k = k0 + 4g .. k0 + 4g + 3
+    for (; k0 + 16 <= ke; k0 += 16) {
+        T a[2][4], p[CT][4];
+        const int kk = k0 + 4 * g;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, p[ct]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
+    }
+    if (k0 < ke) {  // ragged tail of the K range, element by element
+        T a[2][4], p[CT][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + 4 * g + t;
+            const bool ok = k < ke;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) a[rt][t] = ok ? arow[rt][k] : T(0);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) p[ct][t] = ok ? pcol[ct][k] : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
+    }
+    T *qs = Qpart + (size_t)sp * (size_t)(16 * CT) * ldq;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + 16 * rt + M::row_of(v, g);
+                if (row < n) qs[(size_t)(16 * ct + c16) * ldq + row] = acc[rt][ct][v];
+            }
+}
+
+// ------------------------------------------------------- per-column kernels
+// One thread per row, looping over the s columns; per-column block partials
+// [block][KS_MAX_NRHS] reduced by the next kernel.
+constexpr int MR_NT = 256;
+
+// per-column sums of `val` over the block's rows, written to part[blockIdx][j]
+__device__ __forceinline__ void mr_col_partial(double val, int j, double (*red)[KS_MAX_NRHS],
+                                               double *part, bool is_max) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const double t = is_max ? wave_max(val) : wave_sum(val);
+    if (lane == 0) red[w][j] = t;
+}
+
+__device__ __forceinline__ void mr_col_flush(int s, double (*red)[KS_MAX_NRHS], double *part,
+                                             bool is_max) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < s; j += MR_NT) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < MR_NT / WAVE; ++q) acc = is_max ? fmax(acc, red[q][j]) : acc + red[q][j];
+        part[(size_t)blockIdx.x * KS_MAX_NRHS + j] = acc;
+    }
+    __syncthreads();
+}
+
+// per-column totals of the partials of the previous kernel, into LDS (all threads)
+__device__ __forceinline__ void mr_col_reduce(int s, const double *part, int nblk, double *out,
+                                              bool is_max) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    for (int j = w; j < s; j += MR_NT / WAVE) {
+        double acc = 0.0;
+        for (int b = lane; b < nblk; b += WAVE) {
+            const double v = part[(size_t)b * KS_MAX_NRHS + j];
+            acc = is_max ? fmax(acc, v) : acc + v;
+        }
+        acc = is_max ? wave_max(acc) : wave_sum(acc);
+        if (lane == 0) out[j] = acc;
+    }
+    __syncthreads();
+}
+
+// ||b_j||_2, ||b_j||_inf, thresh_j: one block per column
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_stats_kernel(int n, const T *__restrict__ B, int ldb,
+                                                         double tol, ColState *cols, State *st) {
+    __shared__ double sm[MR_NT / WAVE];
+    const int j = blockIdx.x;
+    double s2 = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += MR_NT) {
+        const double v = (double)B[(size_t)j * ldb + i];
+        s2 += v * v;
+        mx = fmax(mx, finite_d(v) ? fabs(v) : INFINITY);
+    }
+    const double ss = block_sum<MR_NT>(s2, sm);
+    __syncthreads();
+    const double bm = block_max<MR_NT>(mx, sm);
+    if (threadIdx.x == 0) {
+        ColState &c = cols[j];
+        c.bnorm = sqrt(ss);
+        c.binf = bm;
+        c.thresh = tol * c.bnorm;
+        c.iters = 0;
+        c.restarts = 0;
+        c.flags = F_STOP;
+        if (j == 0) {
+            st->flags = F_STOP;
+            st->iters = 0;
+        }
+    }
+}
+
+// R = B - sum_sp Qpart[sp]; per column ||r||^2, ||r||_inf, ||x||_inf partials.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_resid_kernel(int n, int s, const T *__restrict__ B,
+                                                         int ldb, const T *__restrict__ X,
+                                                         const T *__restrict__ Qpart, int S,
+                                                         int ldv, T *__restrict__ R, double *part,
+                                                         const State *st, int gate) {
+    __shared__ double red[MR_NT / WAVE][KS_MAX_NRHS];
+    if (gate == 1 && !(st->flags & F_STOP)) return;
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const bool valid = i < n;
+    const int sp16 = (s + 15) / 16 * 16;
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int j = 0; j < s; ++j) {
+            double val = 0.0;
+            if (valid) {
+                if (pass == 2) {
+                    const double xv = (double)X[(size_t)j * ldv + i];
+                    val = finite_d(xv) ? fabs(xv) : INFINITY;
+                } else {
+                    T q = 0;
+                    for (int k = 0; k < S; ++k) q += Qpart[((size_t)k * sp16 + j) * ldv + i];
+                    const T r = B[(size_t)j * ldb + i] - q;
+                    if (pass == 0) R[(size_t)j * ldv + i] = r;
+                    val = (pass == 0) ? (double)r * (double)r
+                                      : (finite_d((double)r) ? fabs((double)r) : INFINITY);
+                }
+            }
+            mr_col_partial(val, j, red, part, pass != 0);
+        }
+        mr_col_flush(s, red, part + (size_t)pass * gridDim.x * KS_MAX_NRHS, pass != 0);
+    }
+}
+
+// one block: per-column residual norms and true-residual flags
+__global__ __launch_bounds__(MR_NT) void mr_resid_finish_kernel(int s, const double *part, int nblk,
+                                                                ColState *cols, const State *st,
+                                                                int gate) {
+    __shared__ double v2[KS_MAX_NRHS], vr[KS_MAX_NRHS], vx[KS_MAX_NRHS];
+    if (gate == 1 && !(st->flags & F_STOP)) return;
+    mr_col_reduce(s, part, nblk, v2, false);
+    mr_col_reduce(s, part + (size_t)nblk * KS_MAX_NRHS, nblk, vr, true);
+    mr_col_reduce(s, part + (size_t)2 * nblk * KS_MAX_NRHS, nblk, vx, true);
+    for (int j = threadIdx.x; j < s; j += MR_NT) {
+        ColState &c = cols[j];
+        const double res = sqrt(v2[j]);
+        c.rho = v2[j];
+        c.res = res;
+        c.resinf = vr[j];
+        c.xinf = vx[j];
+        int f = c.flags & ~(F_TRUE_OK | F_TRUE_NONFIN);
+        if (!finite_d(res) || !finite_d(vx[j]))
+            f |= F_TRUE_NONFIN;
+        else if (res <= c.thresh)
+            f |= F_TRUE_OK;
+        c.flags = f;
+    }
+}
+
+// (Re)start the columns in `mask`: p_j = r_j, inner flags cleared.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_begin_kernel(int n, int s, const T *__restrict__ R,
+                                                         T *__restrict__ P, int ldv,
+                                                         ColState *cols, State *st,
+                                                         uint64_t mask) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    if (i < n)
+        for (int j = 0; j < s; ++j)
+            if ((mask >> j) & 1ull) P[(size_t)j * ldv + i] = R[(size_t)j * ldv + i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int j = 0; j < s; ++j)
+            if ((mask >> j) & 1ull) cols[j].flags &= ~INNER_FLAGS;
+        st->flags = mask ? 0 : F_STOP;
+    }
+}
+
+// Q = sum_sp Qpart[sp]; sigma_j partials of p_j' q_j.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_sigma_kernel(int n, int s, const T *__restrict__ P,
+                                                         const T *__restrict__ Qpart, int S,
+                                                         int ldv, T *__restrict__ Q, double *part,
+                                                         const State *st) {
+    __shared__ double red[MR_NT / WAVE][KS_MAX_NRHS];
+    if (st->flags & F_STOP) return;
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const bool valid = i < n;
+    const int sp16 = (s + 15) / 16 * 16;
+    for (int j = 0; j < s; ++j) {
+        double val = 0.0;
+        if (valid) {
+            T q = 0;
+            for (int k = 0; k < S; ++k) q += Qpart[((size_t)k * sp16 + j) * ldv + i];
+            Q[(size_t)j * ldv + i] = q;
+            val = (double)P[(size_t)j * ldv + i] * (double)q;
+        }
+        mr_col_partial(val, j, red, part, false);
+    }
+    mr_col_flush(s, red, part, false);
+}
+
+// sigma_j from the partials, alpha_j = rho_j / sigma_j; x_j += alpha_j p_j,
+// r_j -= alpha_j q_j for the active columns; r_j' r_j partials.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_update_kernel(int n, int s, T *__restrict__ X,
+                                                          T *__restrict__ R,
+                                                          const T *__restrict__ P,
+                                                          const T *__restrict__ Q, int ldv,
+                                                          ColState *cols, State *st,
+                                                          const double *psig, int nblk,
+                                                          double *prho) {
+    __shared__ double red[MR_NT / WAVE][KS_MAX_NRHS];
+    __shared__ double sig[KS_MAX_NRHS], alpha[KS_MAX_NRHS];
+    __shared__ int act[KS_MAX_NRHS];
+    if (st->flags & F_STOP) return;
+    mr_col_reduce(s, psig, nblk, sig, false);
+    for (int j = threadIdx.x; j < s; j += MR_NT) {
+        const ColState &c = cols[j];
+        const bool active = !(c.flags & F_STOP);
+        const bool ok = finite_d(sig[j]) && sig[j] > 0.0;
+        act[j] = active && ok;
+        alpha[j] = ok ? c.rho / sig[j] : 0.0;
+        if (blockIdx.x == 0 && active) {
+            ColState &cw = cols[j];
+            cw.iters += 1;
+            cw.sigma = sig[j];
+            cw.rho_prev = c.rho;
+            if (!finite_d(sig[j]))
+                cw.flags |= F_NONFIN | F_STOP;
+            else if (sig[j] <= 0.0)
+                cw.flags |= F_BREAK | F_STOP;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->iters += 1;
+    __syncthreads();
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const bool valid = i < n;
+    for (int j = 0; j < s; ++j) {
+        double val = 0.0;
+        if (valid && act[j]) {
+            const T a = (T)alpha[j];
+            const size_t o = (size_t)j * ldv + i;
+            X[o] = fma(a, P[o], X[o]);
+            const T r = fma(-a, Q[o], R[o]);
+            R[o] = r;
+            val = (double)r * (double)r;
+        }
+        mr_col_partial(val, j, red, prho, false);
+    }
+    mr_col_flush(s, red, prho, false);
+}
+
+// rho'_j; per-column stop tests; beta_j and p_j = r_j + beta_j p_j.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_pupdate_kernel(int n, int s, const T *__restrict__ R,
+                                                           T *__restrict__ P, int ldv,
+                                                           ColState *cols, State *st,
+                                                           const double *prho, int nblk,
+                                                           int max_iter) {
+    __shared__ double rn[KS_MAX_NRHS], beta[KS_MAX_NRHS];
+    __shared__ int act[KS_MAX_NRHS];
+    if (st->flags & F_STOP) return;
+    mr_col_reduce(s, prho, nblk, rn, false);
+    int mine = 0;
+    for (int j = threadIdx.x; j < s; j += MR_NT) {
+        const ColState &c = cols[j];
+        int stop = 0;
+        const bool active = !(c.flags & F_STOP);
+        if (active) {
+            if (!finite_d(rn[j]))
+                stop = F_NONFIN | F_STOP;
+            else if (sqrt(rn[j]) <= c.thresh)
+                stop = F_CONV | F_STOP;
+            else if (c.iters >= max_iter)
+                stop = F_MAXIT | F_STOP;
+        }
+        act[j] = active && !stop;
+        beta[j] = rn[j] / c.rho_prev;
+        mine |= act[j];
+        if (blockIdx.x == 0 && active) {
+            ColState &cw = cols[j];
+            if (stop)
+                cw.flags |= stop;
+            else
+                cw.rho = rn[j];
+        }
+    }
+    const int any_active = __syncthreads_or(mine);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !any_active) st->flags |= F_STOP;
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    if (i < n)
+        for (int j = 0; j < s; ++j)
+            if (act[j]) {
+                const size_t o = (size_t)j * ldv + i;
+                P[o] = fma((T)beta[j], P[o], R[o]);
+            }
+}
+
+// copy n x s between leading dimensions (column-major)
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_copy_kernel(int n, int s, const T *__restrict__ src,
+                                                        int lds, T *__restrict__ dst, int ldd) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    if (i < n)
+        for (int j = 0; j < s; ++j) dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
+}
+
+// Refinement: inner right-hand sides r_j / ||r_j|| in binary32 (masked
+// columns; others zero), and the binary64 update x_j += ||r_j|| d_j.
+__global__ __launch_bounds__(MR_NT) void mr_ir_scale_kernel(int n, int s, const double *__restrict__ R,
+                                                            int ldv, float *__restrict__ rhs,
+                                                            const ColState *cols, uint64_t mask) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < s; ++j) {
+        const size_t o = (size_t)j * ldv + i;
+        rhs[o] = ((mask >> j) & 1ull) ? (float)(R[o] / cols[j].res) : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(MR_NT) void mr_ir_update_kernel(int n, int s, double *__restrict__ X,
+                                                             const float *__restrict__ D, int ldv,
+                                                             const ColState *cols, uint64_t mask) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < s; ++j)
+        if ((mask >> j) & 1ull) {
+            const size_t o = (size_t)j * ldv + i;
+            X[o] = fma(cols[j].res, (double)D[o], X[o]);
+        }
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_mr_ir_scale(int n, int s, const double *R, int ldv, float *rhs,
+                              const ColState *cols, uint64_t mask, hipStream_t strm) {
+    mr_ir_scale_kernel<<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, R, ldv, rhs, cols, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_mr_ir_update(int n, int s, double *X, const float *D, int ldv,
+                               const ColState *cols, uint64_t mask, hipStream_t strm) {
+    mr_ir_update_kernel<<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, X, D, ldv, cols, mask);
+    return hipGetLastError();
+}
+
+int mr_splits(int n) {
+    // enough work-groups for 256 CUs (>= ~1024) while keeping each split's
+    // slice of K long
+    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    int S = 1;
+    while (S < 8 && nrb * S < 1024 && n / (2 * S) >= 512) S *= 2;
+    return S;
+}
+
+int mr_kchunk(int n, int S) { return (int)round_up(div_up(n, S), 16); }
+
+int mr_blocks(int n) { return div_up(n, MR_NT); }
+
+template <typename T>
+hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T *Qpart, int ldq,
+                          int s, const State *st, int gate, hipStream_t strm) {
+    const int S = mr_splits(n), kc = mr_kchunk(n, S);
+    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    const int grid = nrb * S;
+    switch ((s + 15) / 16) {
+        case 1:
+            mr_gemm_kernel<T, 1><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            break;
+        case 2:
+            mr_gemm_kernel<T, 2><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            break;
+        case 3:
+            mr_gemm_kernel<T, 3><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            break;
+        case 4:
+            mr_gemm_kernel<T, 4><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_stats(int n, int s, const T *B, int ldb, double tol, ColState *cols,
+                           State *st, hipStream_t strm) {
+    mr_stats_kernel<T><<<s, MR_NT, 0, strm>>>(n, B, ldb, tol, cols, st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_residual(int n, int64_t lda, const T *A, int s, const T *B, int ldb,
+                              const T *X, T *Qpart, T *R, int ldv, double *part, ColState *cols,
+                              State *st, int gate, hipStream_t strm) {
+    hipError_t e = launch_mr_gemm<T>(n, lda, A, X, ldv, Qpart, ldv, s, st, gate, strm);
+    if (e != hipSuccess) return e;
+    const int nb = mr_blocks(n);
+    mr_resid_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, B, ldb, X, Qpart, mr_splits(n), ldv, R, part,
+                                               st, gate);
+    mr_resid_finish_kernel<<<1, MR_NT, 0, strm>>>(s, part, nb, cols, st, gate);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_begin(int n, int s, const T *R, T *P, int ldv, ColState *cols, State *st,
+                           uint64_t mask, hipStream_t strm) {
+    mr_begin_kernel<T><<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, mask);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_iteration(int n, int64_t lda, const T *A, int s, T *X, T *R, T *P, T *Q,
+                               T *Qpart, int ldv, double *part_a, double *part_b, ColState *cols,
+                               State *st, int max_iter, hipStream_t strm, hipEvent_t e0,
+                               hipEvent_t e1) {
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, strm)) != hipSuccess) return e;
+    if ((e = launch_mr_gemm<T>(n, lda, A, P, ldv, Qpart, ldv, s, st, 2, strm)) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, strm)) != hipSuccess) return e;
+    const int nb = mr_blocks(n), S = mr_splits(n);
+    mr_sigma_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, P, Qpart, S, ldv, Q, part_a, st);
+    mr_update_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, X, R, P, Q, ldv, cols, st, part_a, nb, part_b);
+    mr_pupdate_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, part_b, nb, max_iter);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, hipStream_t strm) {
+    mr_copy_kernel<T><<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+#define KS_INST_MR(T)                                                                           \
+    template hipError_t launch_mr_gemm<T>(int, int64_t, const T *, const T *, int, T *, int, int, \
+                                          const State *, int, hipStream_t);                      \
+    template hipError_t launch_mr_stats<T>(int, int, const T *, int, double, ColState *, State *, \
+                                           hipStream_t);                                         \
+    template hipError_t launch_mr_residual<T>(int, int64_t, const T *, int, const T *, int,      \
+                                              const T *, T *, T *, int, double *, ColState *,    \
+                                              State *, int, hipStream_t);                        \
+    template hipError_t launch_mr_begin<T>(int, int, const T *, T *, int, ColState *, State *,   \
+                                           uint64_t, hipStream_t);                               \
+    template hipError_t launch_mr_iteration<T>(int, int64_t, const T *, int, T *, T *, T *, T *,  \
+                                               T *, int, double *, double *, ColState *, State *, \
+                                               int, hipStream_t, hipEvent_t, hipEvent_t);        \
+    template hipError_t launch_mr_copy<T>(int, int, const T *, int, T *, int, hipStream_t);
+
+KS_INST_MR(double)
+KS_INST_MR(float)
+
+}  // namespace ks

@@ -41,7 +41,7 @@ def _check_matrix(A: torch.Tensor) -> int:
 def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float = 1e-10,
                 max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
                 inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
-                timing: bool = False) -> N.KsParams:
+                timing: bool = False, nrhs: int = 1) -> N.KsParams:
     p = N.KsParams()
     N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
     p.lda = int(lda if lda is not None else n)
@@ -54,6 +54,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
     p.max_outer = int(max_outer)
     p.poll_every = int(poll_every)
     p.flags = N.KS_FLAG_TIMING if timing else 0
+    p.nrhs = int(nrhs)
     return p
 
 
@@ -88,7 +89,13 @@ class Solver:
         self._h = h
 
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, out: torch.Tensor | None = None):
-        """Solve A x = b; returns (x, info dict).  x is a new tensor unless `out` is given."""
+        """Solve A x = b; returns (x, info dict).  x is a new tensor unless `out` is given.
+
+        With nrhs = s > 1, b is n x s (one right-hand side per column); the
+        result is n x s and info["columns"] lists each column's outcome.
+        """
+        if self.params.nrhs > 1:
+            return self._solve_multi(b, x0)
         if not (b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n and b.is_contiguous()):
             raise ValueError("b must be a contiguous float64 CUDA vector of length n")
         if out is None:
@@ -103,6 +110,26 @@ class Solver:
         d = info.as_dict()
         d["precision_used"] = _PREC_NAMES.get(d["precision_used"], d["precision_used"])
         return out, d
+
+    def _solve_multi(self, B: torch.Tensor, X0: torch.Tensor | None = None):
+        s = self.params.nrhs
+        if not (B.is_cuda and B.dtype == torch.float64 and tuple(B.shape) == (self.n, s)):
+            raise ValueError(f"B must be a float64 CUDA tensor of shape ({self.n}, {s})")
+        Bc = B.t().contiguous()          # column-major n x s: right-hand side j contiguous
+        Xc = torch.zeros((s, self.n), dtype=torch.float64, device=B.device)
+        if X0 is not None:
+            Xc.copy_(X0.t())
+        info = N.KsInfo()
+        N.check(N.lib().ks_solve(self._h, _ptr(Bc), _ptr(Xc), ctypes.byref(info)), "ks_solve")
+        d = info.as_dict()
+        d["precision_used"] = _PREC_NAMES.get(d["precision_used"], d["precision_used"])
+        cols = []
+        for j in range(s):
+            ci = N.KsInfo()
+            N.check(N.lib().ks_column_info(self._h, j, ctypes.byref(ci)), "ks_column_info")
+            cols.append(ci.as_dict())
+        d["columns"] = cols
+        return Xc.t(), d
 
     def arnoldi(self, v0: torch.Tensor, k: int):
         """k Arnoldi steps from v0: returns (V n x (k'+1), H (k'+1) x k', k')."""

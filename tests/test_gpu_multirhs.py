@@ -1,0 +1,114 @@
+"""Lockstep multi-right-hand-side CG (A*P on the matrix cores) against the
+oracle's one-column CG, column by column, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import multi_rhs_problem, spd_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, device):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _iters_close(a, b, n):
+    """1% (at least 2) while CG is in its exact-arithmetic regime (fewer than
+    n/2 steps); 5% (at least 3) once it runs towards or past n steps, where loss of
+    orthogonality makes the count depend on the summation order."""
+    if b < n // 2:
+        return abs(a - b) <= max(2, int(0.01 * b))
+    return abs(a - b) <= max(3, int(0.05 * b))
+
+
+@pytest.mark.parametrize("n,s,kappa", [(1000, 16, 1e3), (777, 5, 1e4), (2048, 64, 1e4),
+                                       (130, 33, 1e2)])
+def test_lockstep_cg_matches_oracle_per_column(device, n, s, kappa):
+    from paper_1511_07207_amd import krylov
+
+    print(f"mrhs n={n} s={s} kappa={kappa}", flush=True)
+    p = multi_rhs_problem(n, kappa, s, seed=1)
+    X, info = krylov.Solver(_t(p.A, device), method="cg", nrhs=s, tol=1e-10,
+                            max_iter=10 * n).solve(_t(p.b, device))
+    X = X.cpu().numpy()
+    assert info["status"] == 0, info
+    for j in range(s):
+        xo, io = oracle.cg(p.A, p.b[:, j], tol=1e-10, max_iter=10 * n)
+        cj = info["columns"][j]
+        assert cj["status"] == 0
+        m = oracle.metrics(p.A, p.b[:, j], X[:, j])
+        assert m["rel_res"] <= 1e-10
+        assert _rel(X[:, j], xo) <= 1e-8, j
+        assert _iters_close(cj["iters"], io["iters"], n), (j, cj, io)
+
+
+def test_lockstep_first_iterate_exact(device):
+    # after one iteration every column is x1 = (b'b / b'Ab) b: checks the
+    # contraction itself at rounding level
+    from paper_1511_07207_amd import krylov
+
+    n, s = 300, 20
+    p = multi_rhs_problem(n, 50.0, s, seed=2)
+    X, info = krylov.Solver(_t(p.A, device), method="cg", nrhs=s, tol=1e-300,
+                            max_iter=1).solve(_t(p.b, device))
+    X = X.cpu().numpy()
+    for j in range(s):
+        xo, io = oracle.cg(p.A, p.b[:, j], tol=1e-300, max_iter=1)
+        assert info["columns"][j]["iters"] == 1
+        assert _rel(X[:, j], xo) <= 1e-13
+
+
+def test_lockstep_special_columns(device):
+    from paper_1511_07207_amd import krylov
+
+    n, s = 200, 6
+    p = multi_rhs_problem(n, 100.0, s, seed=3)
+    B = p.b.copy()
+    B[:, 1] = 0.0                      # zero column: x = 0, 0 iterations
+    X0 = np.zeros((n, s))
+    X0[:, 2] = p.x_true[:, 2]          # exact initial guess: 0 iterations
+    X, info = krylov.Solver(_t(p.A, device), method="cg", nrhs=s, tol=1e-10).solve(
+        _t(B, device), X0=_t(X0, device))
+    X = X.cpu().numpy()
+    cols = info["columns"]
+    assert cols[1]["status"] == 0 and cols[1]["iters"] == 0 and np.all(X[:, 1] == 0)
+    assert cols[2]["status"] == 0 and cols[2]["iters"] == 0
+    for j in (0, 3, 4, 5):
+        xo, io = oracle.cg(p.A, B[:, j], tol=1e-10)
+        assert _rel(X[:, j], xo) <= 1e-8
+
+
+def test_lockstep_ir_fp32_backward_error(device):
+    from paper_1511_07207_amd import krylov
+
+    n, s = 1024, 16
+    p = multi_rhs_problem(n, 1e3, s, seed=4)
+    X, info = krylov.Solver(_t(p.A, device), method="cg", nrhs=s, precision="fp32", tol=1e-12,
+                            max_iter=4 * n).solve(_t(p.b, device))
+    X = X.cpu().numpy()
+    assert info["status"] == 0, info
+    for j in range(s):
+        m = oracle.metrics(p.A, p.b[:, j], X[:, j])
+        assert m["eta_inf"] <= 1e-12, (j, m)
+        xo, _ = oracle.cg(p.A, p.b[:, j], tol=1e-14, max_iter=20 * n)
+        assert _rel(X[:, j], xo) <= 1e-8
+
+
+def test_lockstep_repeatable(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    p = multi_rhs_problem(600, 1e3, 24, seed=5)
+    solver = krylov.Solver(_t(p.A, device), method="cg", nrhs=24, tol=1e-10)
+    X1, _ = solver.solve(_t(p.b, device))
+    X2, _ = solver.solve(_t(p.b, device))
+    torch.cuda.synchronize()
+    assert torch.equal(X1, X2)

