@@ -48,7 +48,7 @@ def kernel_source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("ks_gemv.hip", "ks_device.h", "ks_internal.h"):
+    for f in ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"):
         with open(os.path.join(ROOT, "paper_1511_07207_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

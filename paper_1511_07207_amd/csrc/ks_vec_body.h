@@ -1,0 +1,305 @@
+// Device bodies of the vector kernels (inner products, saxpy updates,
+// Gram-Schmidt, Givens least squares), called with an explicit block index by
+// the single-solve kernels and by the server's batched kernels.
+#pragma once
+#include "ks_device.h"
+
+namespace ks {
+
+constexpr double HAPPY_FACTOR = 1e-14;  // h(k+1,k) <= this * ||A v_k||
+
+// ------------------------------------------------- ||b||_2 and ||b||_inf
+template <typename T>
+__device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, double tol, State *st) {
+    __shared__ double sm[ONE_NT / WAVE];
+    double s2 = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += ONE_NT) {
+        const double v = (double)b[i];
+        s2 += v * v;
+        mx = fmax(mx, finite_d(v) ? fabs(v) : INFINITY);
+    }
+    const double ss = block_sum<ONE_NT>(s2, sm);
+    __syncthreads();
+    const double bm = block_max<ONE_NT>(mx, sm);
+    if (threadIdx.x == 0) {
+        const double bn = sqrt(ss);
+        st->bnorm = bn;
+        st->binf = bm;
+        st->thresh = tol * bn;
+        st->iters = 0;
+        st->k_done = 0;
+        st->flags = finite_d(bn) ? 0 : (F_TRUE_NONFIN | F_STOP);
+    }
+}
+
+// ------------------------------------------------------------------- CG
+// x += alpha p, r -= alpha q with alpha = rho / sigma, sigma = p'q reduced
+// from the matrix-vector product's partials; r'r partials for the next kernel.
+template <typename T>
+__device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__restrict__ r,
+                                               const T *__restrict__ p, const T *__restrict__ q,
+                                               State *st, const double *__restrict__ psigma,
+                                               int nsigma, double *__restrict__ prho, int bid) {
+    __shared__ double sm[VEC_NT / WAVE];
+    if (st->flags & F_STOP) return;
+    const double sigma = reduce_partials_all<VEC_NT>(psigma, nsigma, 1);
+    const double rho = st->rho;
+    const bool ok = finite_d(sigma) && sigma > 0.0;
+    if (bid == 0 && threadIdx.x == 0) {
+        st->iters += 1;
+        st->sigma = sigma;
+        st->rho_prev = rho;
+        if (!finite_d(sigma))
+            st->flags |= F_NONFIN | F_STOP;
+        else if (sigma <= 0.0)
+            st->flags |= F_BREAK | F_STOP;
+        else
+            st->alpha = rho / sigma;
+    }
+    if (!ok) return;
+    const T a = (T)(rho / sigma);
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) {
+            x[i] = fma(a, p[i], x[i]);
+            const T ri = fma(-a, q[i], r[i]);
+            r[i] = ri;
+            s2 += (double)ri * (double)ri;
+        }
+    }
+    const double t = block_sum<VEC_NT>(s2, sm);
+    if (threadIdx.x == 0) prho[bid] = t;
+}
+
+// rho' = r'r; stop on the recursive residual or the iteration limit;
+// otherwise beta = rho' / rho and p = r + beta p.
+template <typename T>
+__device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, T *__restrict__ p,
+                                                State *st, const double *__restrict__ prho, int nrho,
+                                                int max_iter, int bid) {
+    if (st->flags & F_STOP) return;
+    const double rho_new = reduce_partials_all<VEC_NT>(prho, nrho, 1);
+    const double rho_prev = st->rho_prev;
+    int stop = 0;
+    if (!finite_d(rho_new))
+        stop = F_NONFIN | F_STOP;
+    else if (sqrt(rho_new) <= st->thresh)
+        stop = F_CONV | F_STOP;
+    else if (st->iters >= max_iter)
+        stop = F_MAXIT | F_STOP;
+    const double beta = rho_new / rho_prev;
+    if (bid == 0 && threadIdx.x == 0) {
+        if (stop) {
+            st->flags |= stop;
+        } else {
+            st->beta = beta;
+            st->rho = rho_new;
+        }
+    }
+    if (stop) return;
+    const T bt = (T)beta;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) p[i] = fma(bt, p[i], r[i]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void cg_begin_body(int n, const T *__restrict__ r, T *__restrict__ p,
+                                              State *st, int bid) {
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) p[i] = r[i];
+    }
+    if (bid == 0 && threadIdx.x == 0) st->flags &= ~INNER_FLAGS;
+}
+
+// ---------------------------------------------------------------- GMRES
+// v_0 = r / beta, g = beta e_1 (beta = ||r|| from the residual kernel).
+template <typename T>
+__device__ __forceinline__ void gm_begin_body(int n, const T *__restrict__ r, T *__restrict__ v0,
+                                              State *st, GmArrays ga, int bid) {
+    const double beta = st->res;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) v0[i] = (T)((double)r[i] / beta);
+    }
+    if (bid == 0) {
+        for (int j = threadIdx.x; j <= ga.m; j += VEC_NT) ga.g[j] = (j == 0) ? beta : 0.0;
+        if (threadIdx.x == 0) {
+            st->k_done = 0;
+            st->flags &= ~INNER_FLAGS;
+        }
+    }
+}
+
+// Classical Gram-Schmidt against the k+1 basis vectors V_0..V_k, one row per
+// thread (the projection of the paper's GMRES pseudo-code, applied twice).
+// MODE 0: partials of h1 = V'w (block 0 also finishes ||A v_k|| and counts the
+//         step).
+// MODE 1: h1 from the partials; w -= V h1; partials of h2 = V'w.
+// MODE 2: h2 from the partials; w -= V h2; H(:,k) = h1 + h2; partials of ||w||^2.
+template <typename T, int MODE>
+__device__ __forceinline__ void gm_cgs_body(int n, int ldv, const T *__restrict__ V, T *__restrict__ w,
+                                            int k, State *st, GmArrays ga, Partials P, int ngemv,
+                                            int bid, int nb) {
+    constexpr int NW = CGS_NT / WAVE;
+    __shared__ double red[NW][KS_MAX_RESTART + 1];
+    __shared__ double hs[KS_MAX_RESTART + 1];
+    __shared__ double sm[NW];
+    if (st->flags & F_STOP) return;
+    const int kk = k + 1;
+    const int stride = ga.m + 1;
+    const int i = bid * CGS_NT + threadIdx.x;
+    const bool valid = i < n;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    if constexpr (MODE == 0) {
+        if (bid == 0) {
+            const double s2 = reduce_partials_all<CGS_NT>(P.g, ngemv, 1);
+            if (threadIdx.x == 0) {
+                st->avk = sqrt(s2);
+                st->iters += 1;
+            }
+        }
+    }
+    double wi = valid ? (double)w[i] : 0.0;
+    if constexpr (MODE >= 1) {
+        const double *src = (MODE == 1) ? P.h1 : P.h2;
+        // one wave per coefficient: lanes take blocks lane, lane+64, ... in order
+        for (int j = wv; j < kk; j += NW) {
+            double s = 0.0;
+            for (int b = lane; b < nb; b += WAVE) s += src[(size_t)b * stride + j];
+            s = wave_sum(s);
+            if (lane == 0) hs[j] = s;
+        }
+        __syncthreads();
+        if (bid == 0) {
+            for (int j = threadIdx.x; j < kk; j += CGS_NT) {
+                if (MODE == 1)
+                    ga.h1[j] = hs[j];
+                else
+                    ga.H[(size_t)j * ga.m + k] = ga.h1[j] + hs[j];
+            }
+        }
+        if (valid) {
+            double s = 0.0;
+            for (int j = 0; j < kk; ++j) s = fma((double)V[(size_t)j * ldv + i], hs[j], s);
+            const T wn = (T)(wi - s);
+            w[i] = wn;
+            wi = (double)wn;
+        }
+    }
+    if constexpr (MODE <= 1) {
+        double *dst = (MODE == 0) ? P.h1 : P.h2;
+        for (int j = 0; j < kk; ++j) {
+            const double prod = valid ? (double)V[(size_t)j * ldv + i] * wi : 0.0;
+            const double t = wave_sum(prod);
+            if (lane == 0) red[wv][j] = t;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < kk; j += CGS_NT) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += red[q][j];
+            dst[(size_t)bid * stride + j] = s;
+        }
+    } else {
+        const double t = block_sum<CGS_NT>(wi * wi, sm);
+        if (threadIdx.x == 0) P.nrm[bid] = t;
+    }
+}
+
+// h(k+1,k) = ||w|| from the partials; v_{k+1} = w / h(k+1,k) unless the step
+// is a happy breakdown; block 0 applies the Givens rotations to column k of H,
+// forms the new rotation, updates g and decides whether the cycle stops.
+template <typename T>
+__device__ __forceinline__ void gm_givens_body(int n, const T *__restrict__ w, T *__restrict__ vnext,
+                                               int k, State *st, GmArrays ga,
+                                               const double *__restrict__ pnrm, int nnrm,
+                                               int max_iter, int bid) {
+    if (st->flags & F_STOP) return;
+    const double hk1 = sqrt(reduce_partials_all<VEC_NT>(pnrm, nnrm, 1));
+    const double avk = st->avk;
+    if (finite_d(hk1) && finite_d(avk) && hk1 > HAPPY_FACTOR * avk) {
+        const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+        for (int e = 0; e < VEC_EPT; ++e) {
+            const int i = base + e * VEC_NT;
+            if (i < n) vnext[i] = (T)((double)w[i] / hk1);
+        }
+    }
+    if (bid != 0 || threadIdx.x != 0) return;
+    const int m = ga.m;
+    double *H = ga.H, *R = ga.R;
+    H[(size_t)(k + 1) * m + k] = hk1;
+    for (int j = 0; j <= k; ++j) R[(size_t)j * m + k] = H[(size_t)j * m + k];
+    R[(size_t)(k + 1) * m + k] = hk1;
+    for (int q = 0; q < k; ++q) {
+        const double a = R[(size_t)q * m + k], bb = R[(size_t)(q + 1) * m + k];
+        R[(size_t)q * m + k] = ga.cs[q] * a + ga.sn[q] * bb;
+        R[(size_t)(q + 1) * m + k] = -ga.sn[q] * a + ga.cs[q] * bb;
+    }
+    const double akk = R[(size_t)k * m + k], bk = R[(size_t)(k + 1) * m + k];
+    const double rho = hypot(akk, bk);
+    st->hk1 = hk1;
+    if (!finite_d(rho) || !finite_d(avk)) {
+        st->flags |= F_NONFIN | F_STOP;
+    } else if (rho == 0.0) {
+        st->flags |= F_BREAK | F_STOP;
+    } else {
+        const double c = akk / rho, sn = bk / rho;
+        ga.cs[k] = c;
+        ga.sn[k] = sn;
+        R[(size_t)k * m + k] = rho;
+        R[(size_t)(k + 1) * m + k] = 0.0;
+        const double gk = ga.g[k];
+        ga.g[k + 1] = -sn * gk;
+        ga.g[k] = c * gk;
+        st->k_done = k + 1;
+        if (hk1 <= HAPPY_FACTOR * avk)
+            st->flags |= F_HAPPY | F_STOP;
+        else if (fabs(ga.g[k + 1]) <= st->thresh)
+            st->flags |= F_CONV | F_STOP;
+        else if (st->iters >= max_iter)
+            st->flags |= F_MAXIT | F_STOP;
+    }
+}
+
+// End of a cycle: R y = g by back substitution (each block redundantly, it is
+// at most m x m), then x += V y for the block's rows.
+template <typename T>
+__device__ __forceinline__ void gm_finish_body(int n, int ldv, const T *__restrict__ V,
+                                               T *__restrict__ x, const State *st, GmArrays ga,
+                                               int bid) {
+    __shared__ double y[KS_MAX_RESTART];
+    const int kd = st->k_done;
+    if (kd <= 0) return;
+    if (threadIdx.x == 0) {
+        const int m = ga.m;
+        for (int r = kd - 1; r >= 0; --r) {
+            double s = ga.g[r];
+            for (int j = r + 1; j < kd; ++j) s -= ga.R[(size_t)r * m + j] * y[j];
+            y[r] = s / ga.R[(size_t)r * m + r];
+        }
+        if (bid == 0)
+            for (int j = 0; j < kd; ++j) ga.y[j] = y[j];
+    }
+    __syncthreads();
+    const int i = bid * CGS_NT + threadIdx.x;
+    if (i < n) {
+        double s = 0.0;
+        for (int j = 0; j < kd; ++j) s = fma((double)V[(size_t)j * ldv + i], y[j], s);
+        x[i] = (T)((double)x[i] + s);
+    }
+}
+
+}  // namespace ks

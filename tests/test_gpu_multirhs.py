@@ -75,7 +75,7 @@ def test_lockstep_special_columns(device):
     X0 = np.zeros((n, s))
     X0[:, 2] = p.x_true[:, 2]          # exact initial guess: 0 iterations
     X, info = krylov.Solver(_t(p.A, device), method="cg", nrhs=s, tol=1e-10).solve(
-        _t(B, device), X0=_t(X0, device))
+        _t(B, device), x0=_t(X0, device))
     X = X.cpu().numpy()
     cols = info["columns"]
     assert cols[1]["status"] == 0 and cols[1]["iters"] == 0 and np.all(X[:, 1] == 0)
