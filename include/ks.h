@@ -52,6 +52,7 @@ extern "C" {
 #define KS_ENOMEM (-2)   /* workspace too small, or allocation failed           */
 #define KS_EHIP (-3)     /* a HIP runtime call failed                            */
 #define KS_EDEVICE (-4)  /* current device is not gfx950                         */
+#define KS_ETOOLARGE (-5) /* server: request larger than the memory budget       */
 
 /* ---- method / precision ---------------------------------------------- */
 #define KS_CG 0
@@ -68,6 +69,10 @@ extern "C" {
 
 /* ks_params.flags */
 #define KS_FLAG_TIMING 1 /* time every A*v launch with HIP events (info->gemv_ms) */
+#define KS_FLAG_STOP_BACKWARD 2 /* binary64 solves: tol bounds the normwise backward
+                                   error eta_inf instead of ||r||_2 / ||b||_2: stop
+                                   when ||r||_2 <= tol (||A||_inf ||x||_inf +
+                                   ||b||_inf), confirmed on the true residual */
 
 typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
@@ -164,6 +169,48 @@ void ks_free(ks_solver *s);
 
 /* Static English text for a status code. */
 const char *ks_strerror(int status);
+
+/* ---- request server (continuous batching) ------------------------------
+ * Many binary64 CG / GMRES(m) solves of different sizes, submitted as they
+ * arrive.  Each ks_server_step admits queued requests first come first served
+ * while the memory budget (8 n lda bytes of the request's A plus its solve
+ * workspace) and the in-flight slot count allow, then advances every
+ * in-flight solve by `chunk` iterations with one batched launch per phase (a
+ * launch covers all solves at once), and retires the finished ones.  A
+ * request's x is the same, bit for bit, whatever else is in flight with it
+ * and equal to what ks_solve computes for it alone.  The caller keeps A, b, x
+ * valid and unmodified until the ticket is returned by ks_server_poll (an A
+ * that is not 16-byte aligned with lda * 8 a multiple of 16 is copied into
+ * the server's workspace at admission, like ks_create does).  b and x must be
+ * 16-byte aligned.  One thread drives a server; all work runs on its stream. */
+typedef struct ks_server ks_server;
+
+/* Create a server with a device-memory admission budget (bytes), at most
+ * max_inflight concurrent solves and `chunk` iterations per step (0 = 16).
+ * The server allocates its own workspace arena (min(budget, 4 GiB)). */
+int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_inflight, int32_t chunk,
+                     void *stream);
+
+/* Queue a solve (precision KS_FP64, nrhs 1).  d_x holds x0 and receives x.
+ * *ticket identifies it in ks_server_poll.  KS_ETOOLARGE if it can never
+ * fit the budget. */
+int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const double *d_b,
+                     double *d_x, uint64_t *ticket);
+
+/* One scheduling tick (admit, advance all in-flight solves, retire); waits
+ * for the tick's device work.  Optional outputs: solves in flight and queued. */
+int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued);
+
+/* Up to cap finished requests: their tickets and infos (elapsed_ms = time
+ * from submission to completion on the host clock).  *n_done = count. */
+int ks_server_poll(ks_server *sv, uint64_t *tickets, ks_info *infos, int32_t cap, int32_t *n_done);
+
+/* Budget bytes charged to admitted requests, in-flight and queued counts. */
+int ks_server_stats(const ks_server *sv, size_t *bytes_in_use, int32_t *n_inflight,
+                    int32_t *n_queued);
+
+/* Free the server (waits for its stream; unfinished requests are dropped). */
+void ks_server_free(ks_server *sv);
 
 /* ---- kernel-level entry points ------------------------------------------
  * The solvers' own kernels, exposed for tests and measurement.  All enqueue

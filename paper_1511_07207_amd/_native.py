@@ -14,21 +14,23 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libks.so")
 
 KS_OK, KS_MAXITER, KS_BREAKDOWN, KS_STAGNATED, KS_NONFINITE = 0, 1, 2, 3, 4
-KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_EDEVICE = -1, -2, -3, -4
+KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_EDEVICE, KS_ETOOLARGE = -1, -2, -3, -4, -5
 KS_CG, KS_GMRES = 0, 1
 KS_FP64, KS_IR_FP32, KS_IR_BF16 = 0, 1, 2
 KS_DT_F64, KS_DT_F32, KS_DT_BF16 = 0, 1, 2
 KS_FLAG_TIMING = 1
+KS_FLAG_STOP_BACKWARD = 2
 KS_MAX_RESTART = 128
 KS_MAX_NRHS = 64
 
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfinite",
-                -1: "einval", -2: "enomem", -3: "ehip", -4: "edevice"}
+                -1: "einval", -2: "enomem", -3: "ehip", -4: "edevice", -5: "etoolarge"}
 
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
            "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
-           "ks_convert", "ks_read_ceiling")
+           "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
+           "ks_server_step", "ks_server_poll", "ks_server_stats", "ks_server_free")
 
 
 class KsParams(ctypes.Structure):
@@ -115,6 +117,19 @@ def lib() -> ctypes.CDLL:
         L.ks_convert.restype = ctypes.c_int
         L.ks_read_ceiling.argtypes = [vp, sz, vp, vp]
         L.ks_read_ceiling.restype = ctypes.c_int
+        L.ks_server_create.argtypes = [ctypes.POINTER(vp), sz, i32, i32, vp]
+        L.ks_server_create.restype = ctypes.c_int
+        L.ks_server_submit.argtypes = [vp, PP, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.ks_server_submit.restype = ctypes.c_int
+        L.ks_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ks_server_step.restype = ctypes.c_int
+        L.ks_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(KsInfo),
+                                     i32, ctypes.POINTER(i32)]
+        L.ks_server_poll.restype = ctypes.c_int
+        L.ks_server_stats.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ks_server_stats.restype = ctypes.c_int
+        L.ks_server_free.argtypes = [vp]
+        L.ks_server_free.restype = None
         _lib = L
         return L
 

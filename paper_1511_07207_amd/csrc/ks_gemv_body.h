@@ -321,9 +321,12 @@ __device__ __forceinline__ void residual_finish_body(int nblocks, State *st, con
         st->resinf = rinf;
         st->xinf = xinf;
         int f = st->flags & ~(F_TRUE_OK | F_TRUE_NONFIN);
+        const bool ok = st->eta_tol > 0.0
+                            ? rinf <= st->eta_tol * (st->anorm_inf * xinf + st->binf)
+                            : res <= st->thresh;
         if (!finite_d(res) || !finite_d(xinf))
             f |= F_TRUE_NONFIN;
-        else if (res <= st->thresh)
+        else if (ok)
             f |= F_TRUE_OK;
         st->flags = f;
     }

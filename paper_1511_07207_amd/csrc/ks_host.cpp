@@ -16,6 +16,7 @@
 
 #include "ks.h"
 #include "ks_internal.h"
+#include "ks_layout.h"
 
 using namespace ks;
 
@@ -24,128 +25,6 @@ using namespace ks;
         hipError_t e_ = (expr);               \
         if (e_ != hipSuccess) return KS_EHIP; \
     } while (0)
-
-namespace {
-
-constexpr int CG_MAX_RESTARTS = 16;  // true-residual restarts before "stagnated"
-constexpr size_t ALIGN = 256;
-
-size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
-
-struct Layout {
-    int ldv = 0;
-    int m = 0;
-    size_t st_off = 0;      // two State structs: [0] outer / plain, [1] inner
-    size_t gm_off = 0;      // GMRES small arrays (binary64)
-    size_t part_off = 0;    // block partials (regions of Partials)
-    size_t part_count = 0;
-    size_t pg = 0, pv = 0, ph = 0, pn = 0;  // region sizes in doubles
-    size_t v64_off = 0;     // binary64 vectors
-    int nv64 = 0;
-    size_t v32_off = 0;     // binary32 vectors (IR inner solve)
-    int nv32 = 0;
-    size_t acopy_off = 0;   // padded binary64 copy of A (when not borrowed)
-    size_t acopy_bytes = 0;
-    int64_t lda_pad = 0;
-    size_t alow_off = 0;    // binary32 / bfloat16 copy of A (IR)
-    size_t alow_bytes = 0;
-    size_t afb_off = 0;     // binary32 copy used after a bfloat16 -> binary32 fallback
-    size_t afb_bytes = 0;
-    int64_t lda_low = 0;
-    // multi-right-hand-side blocks (nrhs > 1): X, R, P, Q and S partial Q's,
-    // each sp16 columns of ldv elements, plus per-column states
-    int sp16 = 0;
-    size_t mr_off = 0, mr_block_elems = 0, mr_cols_off = 0, mr_part_off = 0, mr_part_count = 0;
-    size_t total = 0;
-    size_t total_borrowed = 0;
-};
-
-size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m + (m + 1) + m + (m + 1); }
-
-bool valid_params(const ks_params *p) {
-    if (!p) return false;
-    if (p->n < 1 || p->lda < p->n) return false;
-    if (p->method != KS_CG && p->method != KS_GMRES) return false;
-    if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
-    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
-    if (p->max_iter < 0) return false;
-    if (p->method == KS_GMRES && (p->restart < 1 || p->restart > KS_MAX_RESTART)) return false;
-    if (p->precision != KS_FP64) {
-        if (!(p->inner_tol > 0.0) || p->max_outer < 1) return false;
-    }
-    if (p->nrhs < 1 || p->nrhs > KS_MAX_NRHS) return false;
-    if (p->nrhs > 1 && (p->method != KS_CG || p->precision == KS_IR_BF16)) return false;
-    return true;
-}
-
-Layout make_layout(const ks_params *p) {
-    Layout L;
-    const int n = p->n;
-    L.ldv = (int)round_up(n, 64);
-    L.m = (p->method == KS_GMRES) ? p->restart : 1;
-    size_t off = 0;
-    L.st_off = off;
-    off = align_up(off + 2 * sizeof(State));
-    L.gm_off = off;
-    off = align_up(off + gm_doubles(L.m) * sizeof(double));
-    L.pg = (size_t)round_up((int64_t)gemv_blocks_max(n) * 3, 32);
-    L.pv = (size_t)round_up(vec_blocks(n), 32);
-    L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
-    L.pn = (size_t)round_up(cgs_blocks(n), 32);
-    L.part_count = L.pg + L.pv + 2 * L.ph + L.pn;
-    L.part_off = off;
-    off = align_up(off + L.part_count * sizeof(double));
-    // binary64 vectors: CG r, p, q; GMRES w, V(0..m); IR adds the outer residual
-    L.nv64 = (p->method == KS_CG) ? 3 : 1 + (L.m + 1);
-    if (p->precision != KS_FP64) L.nv64 += 1;
-    L.v64_off = off;
-    off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
-    // binary32 vectors of the inner solve: rhs, d, then CG r, p, q or GMRES w, V(0..m)
-    L.nv32 = 0;
-    if (p->precision != KS_FP64) L.nv32 = 2 + ((p->method == KS_CG) ? 3 : 1 + (L.m + 1));
-    L.v32_off = off;
-    off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
-    if (p->nrhs > 1) {
-        L.sp16 = (int)round_up(p->nrhs, 16);
-        L.mr_block_elems = (size_t)L.sp16 * L.ldv;
-        const size_t es = sizeof(double);
-        L.mr_off = off;
-        // X, R, P, Q + mr_splits(n) partial products (binary64); the IR inner
-        // solve adds its binary32 D, R, P, Q and partials below
-        off = align_up(off + (4 + (size_t)mr_splits(n)) * L.mr_block_elems * es);
-        if (p->precision == KS_IR_FP32)
-            off = align_up(off + (5 + (size_t)mr_splits(n)) * L.mr_block_elems * sizeof(float));
-        L.mr_cols_off = off;
-        off = align_up(off + 2 * (size_t)KS_MAX_NRHS * sizeof(ColState));
-        L.mr_part_count = 3 * (size_t)mr_blocks(n) * KS_MAX_NRHS;
-        L.mr_part_off = off;
-        off = align_up(off + L.mr_part_count * sizeof(double));
-    }
-    L.lda_low = round_up(n, 64);
-    if (p->precision == KS_IR_FP32) {
-        L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
-    } else if (p->precision == KS_IR_BF16) {
-        L.alow_bytes = (size_t)n * L.lda_low * sizeof(uint16_t);
-        L.afb_bytes = (size_t)n * L.lda_low * sizeof(float);
-    }
-    L.alow_off = off;
-    off = align_up(off + L.alow_bytes);
-    L.afb_off = off;
-    off = align_up(off + L.afb_bytes);
-    L.total_borrowed = off;
-    L.lda_pad = round_up(n, 64);
-    L.acopy_bytes = (size_t)n * L.lda_pad * sizeof(double);
-    L.acopy_off = off;
-    off = align_up(off + L.acopy_bytes);
-    L.total = off;
-    return L;
-}
-
-bool a_borrowable(const double *A, int64_t lda) {
-    return ((uintptr_t)A % 16 == 0) && ((lda * 8) % 16 == 0);
-}
-
-}  // namespace
 
 struct ks_solver {
     ks_params p{};
@@ -253,10 +132,10 @@ struct Outcome {
 // the recursive residual (inner solve).
 template <typename TA, typename T>
 int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, const T *b, T *x,
-           T *r, T *p, T *q, double tol, int max_iter, bool outer, Outcome *out) {
+           T *r, T *p, T *q, double tol, int max_iter, bool outer, Outcome *out, int eta = 0) {
     const int n = s->n;
     hipStream_t sm = s->stream;
-    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm));
+    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm, eta));
     HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 0, sm)));
     int rc = sync_state(s);
     if (rc) return rc;
@@ -333,10 +212,10 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
 // ---------------------------------------------------------------- GMRES
 template <typename TA, typename T>
 int run_gmres(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, const T *b,
-              T *x, T *w, T *V, double tol, int max_iter, Outcome *out) {
+              T *x, T *w, T *V, double tol, int max_iter, Outcome *out, int eta = 0) {
     const int n = s->n, m = s->ga.m, ldv = s->L.ldv;
     hipStream_t sm = s->stream;
-    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm));
+    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm, eta));
     HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, w, st, s->P, 0, sm)));
     int rc = sync_state(s);
     if (rc) return rc;
@@ -426,12 +305,13 @@ void metrics_from_state(const ks_solver *s, ks_info *info) {
     info->backward_err = den > 0.0 ? h.resinf / den : h.resinf;
 }
 
-int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_iter, Outcome *o) {
+int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_iter, Outcome *o,
+               int eta) {
     if (s->p.method == KS_CG)
         return run_cg<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
-                                      s->vec64(2), tol, max_iter, true, o);
+                                      s->vec64(2), tol, max_iter, true, o, eta);
     return run_gmres<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
-                                     tol, max_iter, o);
+                                     tol, max_iter, o, eta);
 }
 
 // ----------------------------------------------- multi-right-hand-side CG
@@ -710,11 +590,9 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
         }
         eta_prev = eta;
         if (prec == KS_FP64) {
-            // finish in binary64 from the current x: ||r||_2 <= tol * den
-            // implies eta_inf <= tol
-            const double tol2 = s->p.tol * den / bnorm;
+            // finish in binary64 from the current x, stopping on the backward error
             Outcome o64;
-            if ((rc = solve_fp64(s, b, x, tol2, std::max(1, s->p.max_iter), &o64))) return rc;
+            if ((rc = solve_fp64(s, b, x, s->p.tol, std::max(1, s->p.max_iter), &o64, 1))) return rc;
             total_iters += o64.iters;
             ++outer;
             HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0,
@@ -848,39 +726,15 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
         ks_free(s);
         return KS_EHIP;
     }
-    s->st = (State *)(s->ws + L.st_off);
-    s->st_in = s->st + 1;
-    double *g = (double *)(s->ws + L.gm_off);
-    const int m = L.m;
-    s->ga.m = m;
-    s->ga.H = g;
-    g += (size_t)(m + 1) * m;
-    s->ga.R = g;
-    g += (size_t)(m + 1) * m;
-    s->ga.cs = g;
-    g += m;
-    s->ga.sn = g;
-    g += m;
-    s->ga.g = g;
-    g += m + 1;
-    s->ga.y = g;
-    g += m;
-    s->ga.h1 = g;
-
     {
-        double *pp = (double *)(s->ws + L.part_off);
-        s->P.g = pp;
-        pp += L.pg;
-        s->P.v = pp;
-        pp += L.pv;
-        s->P.h1 = pp;
-        pp += L.ph;
-        s->P.h2 = pp;
-        pp += L.ph;
-        s->P.nrm = pp;
+        const Carved c = carve(L, s->ws);
+        s->st = c.st;
+        s->st_in = c.st + 1;
+        s->ga = c.ga;
+        s->P = c.P;
+        s->v64 = c.v64;
+        s->v32 = c.v32;
     }
-    s->v64 = (double *)(s->ws + L.v64_off);
-    s->v32 = (float *)(s->ws + L.v32_off);
     if (p->nrhs > 1) {
         s->mr64 = (double *)(s->ws + L.mr_off);
         s->mr32 = (float *)(s->ws + L.mr_off + (4 + (size_t)mr_splits(p->n)) * L.mr_block_elems * sizeof(double));
@@ -949,7 +803,8 @@ int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info) {
         if (rc) return rc;
         HIPCHK(hipEventRecord(s->ev1, s->stream));
     } else if (s->p.precision == KS_FP64) {
-        rc = solve_fp64(s, d_b, d_x, s->p.tol, s->p.max_iter, &o);
+        rc = solve_fp64(s, d_b, d_x, s->p.tol, s->p.max_iter, &o,
+                        (s->p.flags & KS_FLAG_STOP_BACKWARD) ? 1 : 0);
         if (rc) return rc;
         HIPCHK(hipEventRecord(s->ev1, s->stream));
         metrics_from_state(s, info);

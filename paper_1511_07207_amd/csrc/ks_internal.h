@@ -35,11 +35,12 @@ struct alignas(256) State {
     double res, resinf, xinf;  // last true residual: ||r||_2, ||r||_inf, ||x||_inf
     double avk, hk1;           // GMRES: ||A v_k||, h(k+1,k)
     double anorm_inf;          // ||A||_inf
-    double spare[2];
+    double eta_tol;            // > 0: stop on the backward error eta_inf <= eta_tol
+    double xinf_it;            // ||x||_inf of the CG iterate (backward-error stopping)
     int32_t iters;             // A*v products in the Krylov loop
     int32_t flags;
     int32_t k_done;            // GMRES: steps in the current cycle
-    int32_t pad;
+    int32_t kcur;              // GMRES step counter of batched launches
 };
 
 // Per-column scalars of lockstep multi-right-hand-side CG (same rule as State).
@@ -53,7 +54,7 @@ struct ColState {
 // Per-block partial results, one region per producing kernel kind.
 struct Partials {
     double *g;    // GEMV-shaped kernels: 3 per block
-    double *v;    // vector kernels: 1 per block
+    double *v;    // vector kernels: 2 per block (r'r, then ||x||_inf)
     double *h1;   // Gram-Schmidt pass 1: (m+1) per block
     double *h2;   // Gram-Schmidt pass 2: (m+1) per block
     double *nrm;  // ||w||^2 after pass 2: 1 per block
@@ -72,11 +73,11 @@ constexpr int CGS_NT = 256;
 // Single-block reductions (||b||, finishing kernels).
 constexpr int ONE_NT = 1024;
 
-inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-inline int vec_blocks(int n) { return div_up(n, VEC_NT * VEC_EPT); }
-inline int cgs_blocks(int n) { return div_up(n, CGS_NT); }
+__host__ __device__ inline int vec_blocks(int n) { return div_up(n, VEC_NT * VEC_EPT); }
+__host__ __device__ inline int cgs_blocks(int n) { return div_up(n, CGS_NT); }
 
 struct bf16_t {
     uint16_t bits;
@@ -98,11 +99,11 @@ struct GemvShape<bf16_t> {
 };
 // blocks (= partials) of a GEMV-shaped launch on element type TA
 template <typename TA>
-inline int gemv_blocks(int n) {
+__host__ __device__ inline int gemv_blocks(int n) {
     return div_up(n, GemvShape<TA>::ROWS);
 }
 // the largest of them, for sizing the partial region
-inline int gemv_blocks_max(int n) { return div_up(n, 2); }
+__host__ __device__ inline int gemv_blocks_max(int n) { return div_up(n, 2); }
 
 // GMRES small dense arrays (binary64 always).
 struct GmArrays {
@@ -122,9 +123,10 @@ struct GmArrays {
 hipError_t launch_gemv(int n, int64_t lda, int a_dtype, const void *A, const void *v, void *y,
                        hipStream_t s);
 
-// ||b||_2, ||b||_inf into st; thresh = tol * ||b||_2; flags, iters, k_done reset.
+// ||b||_2, ||b||_inf into st; thresh = tol * ||b||_2; flags, iters, k_done
+// reset; eta_tol = eta ? tol : 0 (stop on the normwise backward error).
 template <typename T>
-hipError_t launch_vec_stats(int n, const T *b, double tol, State *st, hipStream_t s);
+hipError_t launch_vec_stats(int n, const T *b, double tol, State *st, hipStream_t s, int eta = 0);
 
 // r = b - A x, then st->rho = r'r, res, resinf, xinf and F_TRUE_OK /
 // F_TRUE_NONFIN.  gate 1: only when the inner loop has stopped (F_STOP).
@@ -186,6 +188,40 @@ template <typename T>
 hipError_t launch_fill(int n, T *x, T value, hipStream_t s);
 
 hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipStream_t s);
+
+// ------------------------------------------------------- batched launches
+// One in-flight binary64 solve of the request server.
+struct BatchItem {
+    const double *A;
+    int64_t lda;
+    int n, ldv, m, max_iter;
+    double tol;
+    int eta;            // stop on the backward error
+    int pad;
+    const double *b;
+    double *x;
+    double *resid;      // r (CG) or w (GMRES): the residual kernel's output
+    double *p, *q, *V;  // CG search direction and product; GMRES basis
+    State *st;
+    Partials P;
+    GmArrays ga;
+};
+// A subset of items for one launch: offs[i] = first block of idx[i]'s grid.
+struct BatchSet {
+    const BatchItem *items;
+    const int *idx;
+    const int *offs;
+    int count;
+};
+enum BatchKernel {
+    BK_VEC_STATS, BK_NORM_INF, BK_NORM_INF_FINISH, BK_RESIDUAL, BK_RESIDUAL_FINISH,
+    BK_CG_BEGIN, BK_CG_MATVEC, BK_CG_UPDATE, BK_CG_PUPDATE,
+    BK_GM_BEGIN, BK_GM_MATVEC, BK_GM_CGS0, BK_GM_CGS1, BK_GM_CGS2, BK_GM_GIVENS,
+    BK_GM_ADVANCE, BK_GM_FINISH, BK_GATHER
+};
+// blocks = offs[count]; gate for the residual / finish kernels
+hipError_t batch_launch(BatchKernel kind, const BatchSet &bs, int blocks, int gate, hipStream_t s,
+                        State *staging);
 
 // ------------------------------------------------ multi-right-hand-side CG
 // n x s column-major blocks with leading dimension ldv; s <= KS_MAX_NRHS.

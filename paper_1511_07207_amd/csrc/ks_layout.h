@@ -1,0 +1,175 @@
+// Workspace layout of one solve (shared by the single-solve API and the
+// request server): validation of the parameters and the byte offsets of every
+// region inside the caller's (or the server's) device workspace.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "ks.h"
+#include "ks_internal.h"
+
+namespace ks {
+constexpr int CG_MAX_RESTARTS = 16;  // true-residual restarts before "stagnated"
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    int ldv = 0;
+    int m = 0;
+    size_t st_off = 0;      // two State structs: [0] outer / plain, [1] inner
+    size_t gm_off = 0;      // GMRES small arrays (binary64)
+    size_t part_off = 0;    // block partials (regions of Partials)
+    size_t part_count = 0;
+    size_t pg = 0, pv = 0, ph = 0, pn = 0;  // region sizes in doubles
+    size_t v64_off = 0;     // binary64 vectors
+    int nv64 = 0;
+    size_t v32_off = 0;     // binary32 vectors (IR inner solve)
+    int nv32 = 0;
+    size_t acopy_off = 0;   // padded binary64 copy of A (when not borrowed)
+    size_t acopy_bytes = 0;
+    int64_t lda_pad = 0;
+    size_t alow_off = 0;    // binary32 / bfloat16 copy of A (IR)
+    size_t alow_bytes = 0;
+    size_t afb_off = 0;     // binary32 copy used after a bfloat16 -> binary32 fallback
+    size_t afb_bytes = 0;
+    int64_t lda_low = 0;
+    // multi-right-hand-side blocks (nrhs > 1): X, R, P, Q and S partial Q's,
+    // each sp16 columns of ldv elements, plus per-column states
+    int sp16 = 0;
+    size_t mr_off = 0, mr_block_elems = 0, mr_cols_off = 0, mr_part_off = 0, mr_part_count = 0;
+    size_t total = 0;
+    size_t total_borrowed = 0;
+};
+
+inline size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m + (m + 1) + m + (m + 1); }
+
+inline bool valid_params(const ks_params *p) {
+    if (!p) return false;
+    if (p->n < 1 || p->lda < p->n) return false;
+    if (p->method != KS_CG && p->method != KS_GMRES) return false;
+    if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
+    if (p->max_iter < 0) return false;
+    if (p->method == KS_GMRES && (p->restart < 1 || p->restart > KS_MAX_RESTART)) return false;
+    if (p->precision != KS_FP64) {
+        if (!(p->inner_tol > 0.0) || p->max_outer < 1) return false;
+    }
+    if (p->nrhs < 1 || p->nrhs > KS_MAX_NRHS) return false;
+    if (p->nrhs > 1 && (p->method != KS_CG || p->precision == KS_IR_BF16)) return false;
+    return true;
+}
+
+inline Layout make_layout(const ks_params *p) {
+    Layout L;
+    const int n = p->n;
+    L.ldv = (int)round_up(n, 64);
+    L.m = (p->method == KS_GMRES) ? p->restart : 1;
+    size_t off = 0;
+    L.st_off = off;
+    off = align_up(off + 2 * sizeof(State));
+    L.gm_off = off;
+    off = align_up(off + gm_doubles(L.m) * sizeof(double));
+    L.pg = (size_t)round_up((int64_t)gemv_blocks_max(n) * 3, 32);
+    L.pv = (size_t)round_up(2 * vec_blocks(n), 32);
+    L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
+    L.pn = (size_t)round_up(cgs_blocks(n), 32);
+    L.part_count = L.pg + L.pv + 2 * L.ph + L.pn;
+    L.part_off = off;
+    off = align_up(off + L.part_count * sizeof(double));
+    // binary64 vectors: CG r, p, q; GMRES w, V(0..m); IR adds the outer residual
+    L.nv64 = (p->method == KS_CG) ? 3 : 1 + (L.m + 1);
+    if (p->precision != KS_FP64) L.nv64 += 1;
+    L.v64_off = off;
+    off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
+    // binary32 vectors of the inner solve: rhs, d, then CG r, p, q or GMRES w, V(0..m)
+    L.nv32 = 0;
+    if (p->precision != KS_FP64) L.nv32 = 2 + ((p->method == KS_CG) ? 3 : 1 + (L.m + 1));
+    L.v32_off = off;
+    off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
+    if (p->nrhs > 1) {
+        L.sp16 = (int)round_up(p->nrhs, 16);
+        L.mr_block_elems = (size_t)L.sp16 * L.ldv;
+        const size_t es = sizeof(double);
+        L.mr_off = off;
+        // X, R, P, Q + mr_splits(n) partial products (binary64); the IR inner
+        // solve adds its binary32 D, R, P, Q and partials below
+        off = align_up(off + (4 + (size_t)mr_splits(n)) * L.mr_block_elems * es);
+        if (p->precision == KS_IR_FP32)
+            off = align_up(off + (5 + (size_t)mr_splits(n)) * L.mr_block_elems * sizeof(float));
+        L.mr_cols_off = off;
+        off = align_up(off + 2 * (size_t)KS_MAX_NRHS * sizeof(ColState));
+        L.mr_part_count = 3 * (size_t)mr_blocks(n) * KS_MAX_NRHS;
+        L.mr_part_off = off;
+        off = align_up(off + L.mr_part_count * sizeof(double));
+    }
+    L.lda_low = round_up(n, 64);
+    if (p->precision == KS_IR_FP32) {
+        L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
+    } else if (p->precision == KS_IR_BF16) {
+        L.alow_bytes = (size_t)n * L.lda_low * sizeof(uint16_t);
+        L.afb_bytes = (size_t)n * L.lda_low * sizeof(float);
+    }
+    L.alow_off = off;
+    off = align_up(off + L.alow_bytes);
+    L.afb_off = off;
+    off = align_up(off + L.afb_bytes);
+    L.total_borrowed = off;
+    L.lda_pad = round_up(n, 64);
+    L.acopy_bytes = (size_t)n * L.lda_pad * sizeof(double);
+    L.acopy_off = off;
+    off = align_up(off + L.acopy_bytes);
+    L.total = off;
+    return L;
+}
+
+inline bool a_borrowable(const double *A, int64_t lda) {
+    return ((uintptr_t)A % 16 == 0) && ((lda * 8) % 16 == 0);
+}
+
+
+// Pointers of the regions inside a workspace starting at ws.
+struct Carved {
+    State *st = nullptr;
+    GmArrays ga{};
+    Partials P{};
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+};
+
+inline Carved carve(const Layout &L, char *ws) {
+    Carved c;
+    c.st = (State *)(ws + L.st_off);
+    double *g = (double *)(ws + L.gm_off);
+    const int m = L.m;
+    c.ga.m = m;
+    c.ga.H = g;
+    g += (size_t)(m + 1) * m;
+    c.ga.R = g;
+    g += (size_t)(m + 1) * m;
+    c.ga.cs = g;
+    g += m;
+    c.ga.sn = g;
+    g += m;
+    c.ga.g = g;
+    g += m + 1;
+    c.ga.y = g;
+    g += m;
+    c.ga.h1 = g;
+    double *pp = (double *)(ws + L.part_off);
+    c.P.g = pp;
+    pp += L.pg;
+    c.P.v = pp;
+    pp += L.pv;
+    c.P.h1 = pp;
+    pp += L.ph;
+    c.P.h2 = pp;
+    pp += L.ph;
+    c.P.nrm = pp;
+    c.v64 = (double *)(ws + L.v64_off);
+    c.v32 = (float *)(ws + L.v32_off);
+    return c;
+}
+
+}  // namespace ks

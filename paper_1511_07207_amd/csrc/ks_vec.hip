@@ -16,15 +16,15 @@ namespace ks {
 
 template <typename T>
 __global__ __launch_bounds__(ONE_NT) void vec_stats_kernel(int n, const T *__restrict__ b, double tol,
-                                                           State *st) {
-    vec_stats_body<T>(n, b, tol, st);
+                                                           State *st, int eta) {
+    vec_stats_body<T>(n, b, tol, st, eta);
 }
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
                                                            const T *__restrict__ p, const T *__restrict__ q,
                                                            State *st, const double *__restrict__ psigma,
                                                            int nsigma, double *__restrict__ prho) {
-    cg_update_body<T>(n, x, r, p, q, st, psigma, nsigma, prho, blockIdx.x);
+    cg_update_body<T>(n, x, r, p, q, st, psigma, nsigma, prho, blockIdx.x, gridDim.x);
 }
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void cg_pupdate_kernel(int n, const T *__restrict__ r, T *__restrict__ p,
@@ -147,8 +147,8 @@ __global__ __launch_bounds__(256) void read_ceiling_kernel(const uint4 *__restri
 
 // ------------------------------------------------------------- launchers
 template <typename T>
-hipError_t launch_vec_stats(int n, const T *b, double tol, State *st, hipStream_t s) {
-    vec_stats_kernel<T><<<1, ONE_NT, 0, s>>>(n, b, tol, st);
+hipError_t launch_vec_stats(int n, const T *b, double tol, State *st, hipStream_t s, int eta) {
+    vec_stats_kernel<T><<<1, ONE_NT, 0, s>>>(n, b, tol, st, eta);
     return hipGetLastError();
 }
 
@@ -243,7 +243,7 @@ hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipS
 }
 
 #define KS_INST_T(T)                                                                          \
-    template hipError_t launch_vec_stats<T>(int, const T *, double, State *, hipStream_t);     \
+    template hipError_t launch_vec_stats<T>(int, const T *, double, State *, hipStream_t, int); \
     template hipError_t launch_cg_update<T>(int, T *, T *, const T *, const T *, State *,      \
                                             Partials, int, hipStream_t);                       \
     template hipError_t launch_cg_pupdate<T>(int, const T *, T *, State *, Partials, int,      \

@@ -9,8 +9,15 @@ namespace ks {
 constexpr double HAPPY_FACTOR = 1e-14;  // h(k+1,k) <= this * ||A v_k||
 
 // ------------------------------------------------- ||b||_2 and ||b||_inf
+// absolute threshold on ||r||_2: tol ||b||_2, or with backward-error stopping
+// tol (||A||_inf ||x||_inf + ||b||_inf) (which bounds eta_inf by tol)
+__device__ __forceinline__ double stop_threshold(const State *st, double xinf) {
+    return st->eta_tol > 0.0 ? st->eta_tol * (st->anorm_inf * xinf + st->binf) : st->thresh;
+}
+
 template <typename T>
-__device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, double tol, State *st) {
+__device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, double tol, State *st,
+                                               int eta) {
     __shared__ double sm[ONE_NT / WAVE];
     double s2 = 0.0, mx = 0.0;
     for (int i = threadIdx.x; i < n; i += ONE_NT) {
@@ -26,6 +33,8 @@ __device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, d
         st->bnorm = bn;
         st->binf = bm;
         st->thresh = tol * bn;
+        st->eta_tol = eta ? tol : 0.0;
+        st->xinf_it = 0.0;
         st->iters = 0;
         st->k_done = 0;
         st->flags = finite_d(bn) ? 0 : (F_TRUE_NONFIN | F_STOP);
@@ -35,11 +44,13 @@ __device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, d
 // ------------------------------------------------------------------- CG
 // x += alpha p, r -= alpha q with alpha = rho / sigma, sigma = p'q reduced
 // from the matrix-vector product's partials; r'r partials for the next kernel.
+// prho: [r'r partials (nblk)][||x||_inf partials (nblk)], nblk = vec_blocks(n)
 template <typename T>
 __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__restrict__ r,
                                                const T *__restrict__ p, const T *__restrict__ q,
                                                State *st, const double *__restrict__ psigma,
-                                               int nsigma, double *__restrict__ prho, int bid) {
+                                               int nsigma, double *__restrict__ prho, int bid,
+                                               int nblk) {
     __shared__ double sm[VEC_NT / WAVE];
     if (st->flags & F_STOP) return;
     const double sigma = reduce_partials_all<VEC_NT>(psigma, nsigma, 1);
@@ -59,19 +70,26 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
     if (!ok) return;
     const T a = (T)(rho / sigma);
     const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
-    double s2 = 0.0;
+    double s2 = 0.0, xm = 0.0;
 #pragma unroll
     for (int e = 0; e < VEC_EPT; ++e) {
         const int i = base + e * VEC_NT;
         if (i < n) {
-            x[i] = fma(a, p[i], x[i]);
+            const T xi = fma(a, p[i], x[i]);
+            x[i] = xi;
             const T ri = fma(-a, q[i], r[i]);
             r[i] = ri;
             s2 += (double)ri * (double)ri;
+            xm = fmax(xm, finite_d((double)xi) ? fabs((double)xi) : INFINITY);
         }
     }
     const double t = block_sum<VEC_NT>(s2, sm);
-    if (threadIdx.x == 0) prho[bid] = t;
+    __syncthreads();
+    const double tx = block_max<VEC_NT>(xm, sm);
+    if (threadIdx.x == 0) {
+        prho[bid] = t;
+        prho[nblk + bid] = tx;
+    }
 }
 
 // rho' = r'r; stop on the recursive residual or the iteration limit;
@@ -82,16 +100,18 @@ __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, 
                                                 int max_iter, int bid) {
     if (st->flags & F_STOP) return;
     const double rho_new = reduce_partials_all<VEC_NT>(prho, nrho, 1);
+    const double xinf = st->eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + nrho, nrho, 1) : 0.0;
     const double rho_prev = st->rho_prev;
     int stop = 0;
     if (!finite_d(rho_new))
         stop = F_NONFIN | F_STOP;
-    else if (sqrt(rho_new) <= st->thresh)
+    else if (sqrt(rho_new) <= stop_threshold(st, xinf))
         stop = F_CONV | F_STOP;
     else if (st->iters >= max_iter)
         stop = F_MAXIT | F_STOP;
     const double beta = rho_new / rho_prev;
     if (bid == 0 && threadIdx.x == 0) {
+        st->xinf_it = xinf;
         if (stop) {
             st->flags |= stop;
         } else {
@@ -267,7 +287,7 @@ __device__ __forceinline__ void gm_givens_body(int n, const T *__restrict__ w, T
         st->k_done = k + 1;
         if (hk1 <= HAPPY_FACTOR * avk)
             st->flags |= F_HAPPY | F_STOP;
-        else if (fabs(ga.g[k + 1]) <= st->thresh)
+        else if (fabs(ga.g[k + 1]) <= stop_threshold(st, st->xinf))
             st->flags |= F_CONV | F_STOP;
         else if (st->iters >= max_iter)
             st->flags |= F_MAXIT | F_STOP;

@@ -41,7 +41,7 @@ def _check_matrix(A: torch.Tensor) -> int:
 def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float = 1e-10,
                 max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
                 inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
-                timing: bool = False, nrhs: int = 1) -> N.KsParams:
+                timing: bool = False, nrhs: int = 1, stop_backward: bool = False) -> N.KsParams:
     p = N.KsParams()
     N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
     p.lda = int(lda if lda is not None else n)
@@ -53,7 +53,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
     p.inner_tol = float(inner_tol)
     p.max_outer = int(max_outer)
     p.poll_every = int(poll_every)
-    p.flags = N.KS_FLAG_TIMING if timing else 0
+    p.flags = (N.KS_FLAG_TIMING if timing else 0) | (N.KS_FLAG_STOP_BACKWARD if stop_backward else 0)
     p.nrhs = int(nrhs)
     return p
 
@@ -145,6 +145,72 @@ class Solver:
         if getattr(self, "_h", None):
             N.lib().ks_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server (binary64 CG / GMRES(m)).
+
+    submit() queues a solve and returns a ticket; step() runs one scheduling
+    tick; poll() returns the finished (ticket, x, info) triples.  The tensors
+    of a request are kept referenced here until it is returned.
+    """
+
+    def __init__(self, mem_budget_bytes: int = 64 << 30, max_inflight: int = 1024,
+                 chunk: int = 16):
+        h = ctypes.c_void_p()
+        N.check(N.lib().ks_server_create(ctypes.byref(h), int(mem_budget_bytes), int(max_inflight),
+                                         int(chunk), _stream_handle()), "ks_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, A: torch.Tensor, b: torch.Tensor, x0: torch.Tensor | None = None,
+               method: str = "cg", **kw) -> int:
+        lda = _check_matrix(A)
+        n = A.shape[0]
+        p = make_params(n, method=method, lda=lda, **kw)
+        x = torch.zeros(n, dtype=torch.float64, device=A.device)
+        if x0 is not None:
+            x.copy_(x0.reshape(-1))
+        t = ctypes.c_uint64(0)
+        N.check(N.lib().ks_server_submit(self._h, ctypes.byref(p), _ptr(A), _ptr(b), _ptr(x),
+                                         ctypes.byref(t)), "ks_server_submit")
+        self._live[t.value] = (A, b, x)
+        return t.value
+
+    def step(self):
+        a, q = ctypes.c_int32(0), ctypes.c_int32(0)
+        N.check(N.lib().ks_server_step(self._h, ctypes.byref(a), ctypes.byref(q)), "ks_server_step")
+        return a.value, q.value
+
+    def poll(self, cap: int = 4096):
+        tickets = (ctypes.c_uint64 * cap)()
+        infos = (N.KsInfo * cap)()
+        k = ctypes.c_int32(0)
+        N.check(N.lib().ks_server_poll(self._h, tickets, infos, cap, ctypes.byref(k)), "ks_server_poll")
+        out = []
+        for i in range(k.value):
+            t = tickets[i]
+            _, _, x = self._live.pop(t)
+            out.append((t, x, infos[i].as_dict()))
+        return out
+
+    def stats(self):
+        b, a, q = ctypes.c_size_t(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        N.check(N.lib().ks_server_stats(self._h, ctypes.byref(b), ctypes.byref(a), ctypes.byref(q)),
+                "ks_server_stats")
+        return dict(bytes_in_use=b.value, inflight=a.value, queued=q.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().ks_server_free(self._h)
+            self._h = None
+            self._live.clear()
 
     def __del__(self):
         try:

@@ -244,3 +244,22 @@ def test_ir_bf16_spd_high_kappa_falls_back(device):
     assert info["status"] == 0, info
     assert info["precision_used"] in ("fp32", "fp64")
     assert oracle.metrics(p.A, p.b, x.cpu().numpy())["eta_inf"] <= 1e-12
+
+
+@pytest.mark.parametrize("method", ["cg", "gmres"])
+def test_stop_on_backward_error(device, method):
+    from paper_1511_07207_amd import krylov
+
+    n = 1000
+    p = spd_problem(n, 1e4, seed=7, config_id=2) if method == "cg" else nonsym_problem(n, seed=7, config_id=2)
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method=method, tol=1e-12,
+                           stop_backward=True, restart=30, max_iter=20 * n)
+    assert info["status"] == 0, info
+    m = oracle.metrics(p.A, p.b, x.cpu().numpy())
+    assert m["eta_inf"] <= 1e-12
+    assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + np.sqrt(n) * 2.0 ** -53
+    if method == "cg":
+        # CG tracks ||x||_inf every iteration and stops as soon as eta allows,
+        # with a relative residual looser than tol; GMRES knows ||x||_inf only
+        # from its last true residual (0 in the first cycle), so it may stop later
+        assert m["rel_res"] > 1e-12
