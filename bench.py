@@ -104,6 +104,189 @@ def cpu_baseline(spd, ns, cg_iters, gm_iters, steps_done):
     }
 
 
+# ------------------------------------------------------------------ extra legs
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def leg_c1(dev):
+    """Plain CG, n = 512, kappa = 1e3, tol 1e-10, max 512 iterations."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import spd_problem
+
+    p = spd_problem(512, 1e3, seed=0, config_id=0)
+    A = torch.from_numpy(p.A).to(dev)
+    b = torch.from_numpy(p.b).to(dev)
+    s = krylov.Solver(A, method="cg", tol=1e-10, max_iter=512)
+    x = torch.zeros(512, dtype=torch.float64, device=dev)
+    s.solve(b, out=x.zero_())
+    lat, its = [], []
+    for _ in range(30):
+        (_, info), dt = _timed(lambda: s.solve(b, out=x.zero_()))
+        lat.append(dt * 1e3)
+        its.append(info["iters"])
+    s.close()
+    return {"n": 512, "kappa": 1e3, "iters": its[-1], "status": info["status_name"],
+            "rel_res": info["rel_res"], "solves_per_s": round(1e3 / statistics.mean(lat), 2),
+            "p50_ms": round(_pct(lat, 0.5), 3), "p99_ms": round(_pct(lat, 0.99), 3),
+            "us_per_iteration": round(1e3 * statistics.median(lat) / its[-1], 2)}
+
+
+def leg_c3(dev, n, kappa):
+    """Mixed precision vs binary64 at equal accuracy (backward error 1e-12)."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_swept_problem, spd_problem
+
+    out = {"n": n, "eta_target": 1e-12}
+    cases = [("spd_cg", kappa, "cg"), ("nonsym_gmres50", 1e2, "gmres")]
+    for name, kap, method in cases:
+        if method == "cg":
+            prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
+        else:
+            prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
+        res = {"kappa": kap}
+        for prec in ("fp64", "fp32", "bf16"):
+            kw = dict(method=method, tol=1e-12, restart=50, timing=True, max_iter=4 * n)
+            if prec == "fp64":
+                kw["stop_backward"] = True
+            else:
+                kw["precision"] = prec
+            (solver), tc = _timed(lambda: krylov.Solver(prob.A, **kw))
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            (_, info), dt = _timed(lambda: solver.solve(prob.b, out=x))
+            # bytes per element of the timed matrix-vector products (mixed if a
+            # bfloat16 solve fell back to binary32)
+            e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec] if info["precision_used"] == prec else None
+            r = {"solves_per_s": round(1.0 / dt, 4), "solve_ms": round(dt * 1e3, 2),
+                 "create_ms": round(tc * 1e3, 2), "status": info["status_name"],
+                 "iters": info["iters"], "outer": info["outer_iters"],
+                 "precision_used": info["precision_used"], "eta_inf": info["backward_err"],
+                 "rel_res": info["rel_res"]}
+            if e and info["gemv_calls"]:
+                r["gemv_gbs"] = round(e * n * n / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)
+            r["fwd_err_vs_x_true"] = float((x - prob.x_true).norm() / prob.x_true.norm())
+            res[prec] = r
+            solver.close()
+            del x
+        f64 = res["fp64"]["solves_per_s"]
+        for prec in ("fp32", "bf16"):
+            res[prec]["speedup_vs_fp64"] = round(res[prec]["solves_per_s"] / f64, 3)
+        out[name] = res
+        del prob
+        torch.cuda.empty_cache()
+    return out
+
+
+def leg_c4(dev, n):
+    """Lockstep CG on 64 right-hand sides (A*P on MFMA)."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import multi_rhs_problem
+
+    s = 64
+    prob = multi_rhs_problem(n, 1e4, s, seed=0, backend="torch", device="cuda")
+    out = {"n": n, "nrhs": s, "kappa": 1e4}
+    for prec, tol, peak in (("fp64", 1e-10, 78.6), ("fp32", 1e-12, 157.3)):
+        solver = krylov.Solver(prob.A, method="cg", nrhs=s, tol=tol, precision=prec, timing=True,
+                               max_iter=4 * n)
+        solver.solve(prob.b)
+        (X, info), dt = _timed(lambda: solver.solve(prob.b))
+        ms = info["gemv_ms"] / max(info["gemv_calls"], 1)
+        tf = 2.0 * n * n * s / (ms * 1e-3) / 1e12
+        out[prec] = {"solves_per_s": round(s / dt, 2), "status": info["status_name"],
+                     "lockstep_iters": info["iters"], "outer": info["outer_iters"],
+                     "max_rel_res": info["rel_res"], "max_eta_inf": info["backward_err"],
+                     "gemm_ms": round(ms, 4), "gemm_tflops": round(tf, 2),
+                     "mfma_peak_tflops": peak, "mfma_frac": round(tf / peak, 4)}
+        solver.close()
+    return out
+
+
+def leg_c5(dev, count, pool_size, seed=0):
+    """Serving: Poisson arrivals over a pool of resident systems."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem, spd_problem
+
+    rng = np.random.default_rng([seed, 4, 99])
+    pool = []
+    for i in range(pool_size):
+        n = int(round(math.exp(rng.uniform(math.log(256), math.log(8192)))))
+        if i % 2 == 0:
+            kap = float(math.exp(rng.uniform(math.log(1e2), math.log(1e5))))
+            prob = spd_problem(n, kap, seed=seed, config_id=4, key=(i,), backend="torch", device="cuda")
+            pool.append(("cg", prob, dict(method="cg", tol=1e-10)))
+        else:
+            prob = nonsym_problem(n, seed=seed, config_id=4, key=(i,), backend="torch", device="cuda")
+            pool.append(("gmres", prob, dict(method="gmres", tol=1e-10, restart=30)))
+    # request i: pool entry, fresh right-hand side b = A x_true
+    reqs = []
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed * 1000003 + 17)
+    order = rng.permutation(np.arange(count) % pool_size)
+    for i in range(count):
+        kind, prob, kw = pool[int(order[i])]
+        xt = torch.randn(prob.n, dtype=torch.float64, device=dev, generator=g)
+        reqs.append((prob, kw, prob.A @ xt))
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        srv = krylov.Server(mem_budget_bytes=64 << 30, max_inflight=1024, chunk=16)
+        t0 = time.perf_counter()
+        pending = list(range(count))
+        lat, statuses, peak_inflight = [], [], 0
+        while True:
+            now = time.perf_counter() - t0
+            while pending and arrivals[pending[0]] <= now:
+                i = pending.pop(0)
+                prob, kw, b = reqs[i]
+                srv.submit(prob.A, b, **kw)
+            a, q = srv.step()
+            peak_inflight = max(peak_inflight, a)
+            done_t = time.perf_counter() - t0
+            for t, x, info in srv.poll():
+                lat.append(done_t - arrivals[t - 1])
+                statuses.append(info["status"])
+            if not pending and a == 0 and q == 0:
+                break
+            if a == 0 and q == 0 and pending:
+                wait = arrivals[pending[0]] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+        total = time.perf_counter() - t0
+        srv.close()
+        lat_ms = [v * 1e3 for v in lat]
+        return {"requests": count, "wall_s": round(total, 3),
+                "throughput_req_per_s": round(count / total, 2),
+                "p50_ms": round(_pct(lat_ms, 0.5), 2), "p99_ms": round(_pct(lat_ms, 0.99), 2),
+                "all_ok": all(s == 0 for s in statuses) and len(statuses) == count,
+                "peak_inflight": peak_inflight}
+
+    sat = run([0.0] * count)
+    out = {"pool": pool_size, "n_range": [256, 8192], "precision": "fp64", "saturation": sat}
+    lam = sat["throughput_req_per_s"]
+    for frac in (0.5, 0.9):
+        gaps = rng.exponential(1.0 / (frac * lam), size=count)
+        arr = list(np.cumsum(gaps) - gaps[0])
+        out[f"rate_{frac}"] = dict(run(arr), offered_req_per_s=round(frac * lam, 2))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +297,12 @@ def main():
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
+    ap.add_argument("--legs", default="c1,c3,c4,c5",
+                    help="extra measurements after the timed steps (comma list of c1,c3,c4,c5; "
+                         "'none' for the main step only)")
+    ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before timing, copy A once with the library's binary64 copy kernel "
                          "(known bytes: 8 n^2 read + 8 n^2 written) to calibrate HBM counters")
@@ -256,6 +445,30 @@ def main():
         out["cpu_baseline"] = None
     cg.close()
     gm.close()
+    del spd, ns
+    torch.cuda.empty_cache()
+    legs = {}
+    wanted = [] if args.legs == "none" else [x.strip() for x in args.legs.split(",") if x.strip()]
+    for name in wanted:
+        print(f"[bench] leg {name} ...", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        try:
+            if name == "c1":
+                legs[name] = leg_c1(dev)
+            elif name == "c3":
+                legs[name] = leg_c3(dev, args.n3, 1e4)
+            elif name == "c4":
+                legs[name] = leg_c4(dev, n)
+            elif name == "c5":
+                legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool)
+            else:
+                legs[name] = {"error": "unknown leg"}
+        except Exception as e:  # a failing leg is reported, not fatal
+            legs[name] = {"error": f"{type(e).__name__}: {e}"}
+        legs.setdefault(name, {})["leg_wall_s"] = round(time.perf_counter() - t0, 1)
+        print(f"[bench] leg {name} done in {legs[name]['leg_wall_s']}s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    out["legs"] = legs
     print(json.dumps(out), flush=True)
 
 
