@@ -11,6 +11,8 @@ Functions and the passages of the paper they follow:
 * ``gmres``   restarted GMRES(m): Arnoldi step as printed in the GMRES
               pseudo-code, least squares by Givens rotations (Saad), restart
               from the current iterate
+* ``bicgstab`` BiCGSTAB as listed in the paper (omega as a quotient; the
+              residual and rho updates the listing omits restored)
 * ``arnoldi`` the Arnoldi basis and unrotated Hessenberg matrix alone
 * ``lu_factor`` / ``lu_solve``  right-looking LU with partial pivoting and the
               two triangular solves (direct methods section)
@@ -61,6 +63,8 @@ def _load():
         lib.ko_cg.restype = i
         lib.ko_gmres.argtypes = [i, pd, l, pd, pd, d, i, i, pi, pi, pd, pd, i, pd, i]
         lib.ko_gmres.restype = i
+        lib.ko_bicgstab.argtypes = [i, pd, l, pd, pd, d, i, pi, pi, pd]
+        lib.ko_bicgstab.restype = i
         lib.ko_arnoldi.argtypes = [i, pd, l, pd, i, pd, pd]
         lib.ko_arnoldi.restype = i
         lib.ko_lu_factor.argtypes = [i, pd, l, pi]
@@ -188,6 +192,20 @@ def gmres(A, b, x0=None, tol=1e-10, max_iter=None, restart=30, hist=False):
         info["est"] = est[: it.value].copy()
         info["cres"] = cres[: cy.value + 1].copy()
     return x, info
+
+
+def bicgstab(A, b, x0=None, tol=1e-10, max_iter=None):
+    """BiCGSTAB; returns (x, info). iters counts products with A (two per iteration)."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    b = _vec(b, n)
+    x = np.zeros(n) if x0 is None else _vec(x0, n).copy()
+    max_iter = 20 * n if max_iter is None else int(max_iter)
+    it, rs, rr = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _load().ko_bicgstab(n, _pd(A), lda, _pd(b), _pd(x), float(tol), max_iter,
+                             ctypes.byref(it), ctypes.byref(rs), ctypes.byref(rr))
+    return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), iters=it.value,
+                   restarts=rs.value, rel_res=rr.value)
 
 
 def arnoldi(A, v0, k):

@@ -219,6 +219,108 @@ done_noalloc:
     return status;
 }
 
+/* ---------------------------------------------------------------- BiCGSTAB
+ *
+ * BiConjugate gradient stabilised, in the order of the paper's BiCGSTAB
+ * listing (r0 the shadow residual, rho_0 = alpha = omega = 1, p = v = 0):
+ *   beta = (rho_k / rho_{k-1}) (alpha / omega);  p = r + beta (p - omega v)
+ *   v = A p;  alpha = rho_k / (r0' v);  s = r - alpha v
+ *   t = A s;  omega = (t' s) / (t' t);  x = x + alpha p + omega s
+ * The printed omega line shows a product where the quotient is meant, and the
+ * listing stops before the last two updates, taken here as r = s - omega t and
+ * rho_{k+1} = r0' r.  If ||s|| already meets the tolerance the half step
+ * x = x + alpha p ends the solve.  Stop on ||r||_2 <= tol ||b||_2 (recursive),
+ * confirmed on the true residual (restart from x if it fails).  max_iter
+ * bounds the number of products with A (two per iteration).  Breakdown: rho,
+ * r0'v or t't equal to 0, or omega = 0.
+ */
+int ko_bicgstab(int n, const double *A, long lda, const double *b, double *x, double tol,
+                int max_iter, int *iters_out, int *restarts_out, double *rel_res_out) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || max_iter < 0) return KO_EINVAL;
+    int prods = 0, restarts = 0, status = KO_MAXITER, first = 1;
+    double bnorm = ko_nrm2(n, b), res = 0.0;
+    if (!isfinite(bnorm)) {
+        if (iters_out) *iters_out = 0;
+        if (restarts_out) *restarts_out = 0;
+        if (rel_res_out) *rel_res_out = 0.0;
+        return KO_NONFINITE;
+    }
+    if (bnorm == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        if (iters_out) *iters_out = 0;
+        if (restarts_out) *restarts_out = 0;
+        if (rel_res_out) *rel_res_out = 0.0;
+        return KO_OK;
+    }
+    size_t nn = (size_t)n;
+    double *r = (double *)malloc(sizeof(double) * nn), *r0 = (double *)malloc(sizeof(double) * nn);
+    double *p = (double *)malloc(sizeof(double) * nn), *v = (double *)malloc(sizeof(double) * nn);
+    double *sv = (double *)malloc(sizeof(double) * nn), *t = (double *)malloc(sizeof(double) * nn);
+    if (!r || !r0 || !p || !v || !sv || !t) {
+        status = KO_EINVAL;
+        goto out;
+    }
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        res = ko_nrm2(n, r);
+        if (!isfinite(res)) { status = KO_NONFINITE; break; }
+        if (res <= tol * bnorm) { status = KO_OK; break; }
+        if (prods >= max_iter) { status = KO_MAXITER; break; }
+        if (!first) {
+            if (restarts >= KO_CG_MAX_RESTARTS) { status = KO_STAGNATED; break; }
+            ++restarts;
+        }
+        first = 0;
+        for (int i = 0; i < n; ++i) { r0[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+        double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+        double rho = ko_dot(n, r0, r);
+        int stop = 0;
+        while (!stop) {
+            if (rho == 0.0 || !isfinite(rho)) { status = isfinite(rho) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
+            double beta = (rho / rho_prev) * (alpha / omega);
+            for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            ko_matvec(n, A, lda, p, v);
+            ++prods;
+            double r0v = ko_dot(n, r0, v);
+            if (r0v == 0.0 || !isfinite(r0v)) { status = isfinite(r0v) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
+            alpha = rho / r0v;
+            for (int i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
+            if (ko_nrm2(n, sv) <= tol * bnorm) {          /* half-step exit */
+                for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+                stop = 1;
+                break;
+            }
+            if (prods >= max_iter) {                        /* no room for A s */
+                for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+                stop = 1;
+                break;
+            }
+            ko_matvec(n, A, lda, sv, t);
+            ++prods;
+            double tt = ko_dot(n, t, t);
+            if (tt == 0.0 || !isfinite(tt)) { status = isfinite(tt) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
+            omega = ko_dot(n, t, sv) / tt;
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i] + omega * sv[i];
+            for (int i = 0; i < n; ++i) r[i] = sv[i] - omega * t[i];
+            if (ko_nrm2(n, r) <= tol * bnorm || prods >= max_iter) { stop = 1; break; }
+            if (omega == 0.0) { status = KO_BREAKDOWN; stop = 2; break; }
+            rho_prev = rho;
+            rho = ko_dot(n, r0, r);
+        }
+        if (stop == 2) {
+            ko_residual(n, A, lda, b, x, r);
+            res = ko_nrm2(n, r);
+            break;
+        }
+    }
+out:
+    free(r); free(r0); free(p); free(v); free(sv); free(t);
+    if (iters_out) *iters_out = prods;
+    if (restarts_out) *restarts_out = restarts;
+    if (rel_res_out) *rel_res_out = res / bnorm;
+    return status;
+}
+
 /* ---------------------------------------------------------------- GMRES(m)
  *
  * Arnoldi step as the paper prints it: project A v(k) on every v(j), j <= k,

@@ -385,3 +385,62 @@ def test_backward_error_hand_worked_2x2():
     m = oracle.metrics(A, b, x)
     assert m["eta_inf"] == fx["eta_inf"][0][0]
     assert abs(m["rel_res"] ** 2 - fx["rel_res_sq"][0][0]) <= 1e-16
+
+
+# ------------------------------------------------------------ BiCGSTAB pins
+
+def _fr_vec(v):
+    return [Fraction(int(a)) for a in v]
+
+
+def test_bicgstab_first_iterate_from_its_two_defining_conditions():
+    # One BiCGSTAB step from x0 = 0 (r0 = b, p = r0) is fixed by two 1-D
+    # conditions, computed here exactly and independently of the recurrence:
+    #   alpha: the Galerkin condition r0'(r0 - alpha A r0) = 0
+    #   omega: s - omega A s has least 2-norm, s = r0 - alpha A r0
+    # and x1 = alpha r0 + omega s.
+    for seed, n in [(1, 4), (2, 5), (3, 6)]:
+        A = _int_nonsym(n, seed)
+        b = np.random.default_rng(seed + 40).integers(-5, 6, size=n)
+        Af = [[Fraction(int(a)) for a in row] for row in A]
+        r0 = _fr_vec(b)
+        Ar0 = _fr_matvec(Af, r0)
+        alpha = _fr_dot(r0, r0) / _fr_dot(r0, Ar0)
+        s = [a - alpha * c for a, c in zip(r0, Ar0)]
+        As = _fr_matvec(Af, s)
+        omega = _fr_dot(As, s) / _fr_dot(As, As)
+        x1 = np.array([float(alpha * a + omega * c) for a, c in zip(r0, s)])
+        x, info = oracle.bicgstab(A.astype(float), b.astype(float), tol=TINY, max_iter=2)
+        assert info["iters"] == 2
+        assert _rel(x, x1) <= 1e-13
+
+
+def test_bicgstab_identity_half_step():
+    b = np.random.default_rng(1).standard_normal(20)
+    x, info = oracle.bicgstab(np.eye(20), b, tol=1e-12)
+    assert info["status"] == 0 and info["iters"] == 1 and np.array_equal(x, b)
+
+
+@pytest.mark.parametrize("kind", ["spd", "nonsym"])
+def test_bicgstab_agrees_with_gepp(kind):
+    if kind == "spd":
+        p = spd_problem(80, 1e2, seed=11, config_id=97)
+    else:
+        p = nonsym_problem(80, seed=11, config_id=97)
+    x, info = oracle.bicgstab(p.A, p.b, tol=1e-12)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-12
+    xg = oracle.gepp_solve(p.A, p.b)
+    assert _rel(x, xg) <= 10 * np.linalg.cond(p.A) * 1e-12
+
+
+def test_bicgstab_special_cases():
+    A = np.eye(5) * 2.0
+    x, info = oracle.bicgstab(A, np.zeros(5), x0=np.ones(5))
+    assert info["status"] == 0 and info["iters"] == 0 and np.all(x == 0)
+    p = nonsym_problem(40, seed=3, config_id=97)
+    x, info = oracle.bicgstab(p.A, p.b, x0=p.x_true, tol=1e-10)
+    assert info["iters"] == 0 and info["status"] == 0
+    _, info = oracle.bicgstab(np.eye(3), np.array([1.0, np.nan, 0.0]))
+    assert info["status"] == 4
+    _, info = oracle.bicgstab(p.A, p.b, tol=1e-14, max_iter=6)
+    assert info["status"] == 1 and info["iters"] == 6
