@@ -3,9 +3,11 @@
  *
  * Solves A x = b for a dense n x n matrix A (the linear system of the paper's
  * Krylov section) with
- *   - conjugate gradient (CG) when A is symmetric positive definite, and
+ *   - conjugate gradient (CG) when A is symmetric positive definite,
  *   - restarted GMRES(m) otherwise (Arnoldi step of the paper's GMRES
- *     pseudo-code, restart after m steps from the current iterate),
+ *     pseudo-code, restart after m steps from the current iterate), or
+ *   - BiCGSTAB (the paper's BiCGSTAB listing: two products with A per
+ *     iteration, short recurrences, no basis kept) for any nonsingular A,
  * in binary64, or with an inner solve on a binary32 / bfloat16 copy of A and
  * binary64 iterative refinement around it.
  *
@@ -45,7 +47,8 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------- */
 #define KS_OK 0
 #define KS_MAXITER 1     /* iteration limit reached before the tolerance        */
-#define KS_BREAKDOWN 2   /* CG: p'Ap <= 0 (A not SPD); GMRES: singular H        */
+#define KS_BREAKDOWN 2   /* CG: p'Ap <= 0 (A not SPD); GMRES: singular H;
+                            BiCGSTAB: r0'r, r0'v or t't became 0, or omega = 0 */
 #define KS_STAGNATED 3   /* refinement / restarts stopped making progress       */
 #define KS_NONFINITE 4   /* a NaN or Inf appeared (in b, x0, A or an iterate)    */
 #define KS_EINVAL (-1)   /* bad argument (n <= 0, lda < n, NULL, tol <= 0, ...) */
@@ -57,6 +60,7 @@ extern "C" {
 /* ---- method / precision ---------------------------------------------- */
 #define KS_CG 0
 #define KS_GMRES 1
+#define KS_BICGSTAB 2
 
 #define KS_FP64 0        /* everything in binary64                               */
 #define KS_IR_FP32 1     /* inner solve on binary32 A, binary64 refinement       */
@@ -78,7 +82,7 @@ typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
 typedef struct {
     int32_t n;          /* order of A, >= 1                                       */
-    int32_t method;     /* KS_CG or KS_GMRES                                      */
+    int32_t method;     /* KS_CG, KS_GMRES or KS_BICGSTAB                         */
     int64_t lda;        /* leading dimension of A in elements, >= n               */
     int32_t precision;  /* KS_FP64, KS_IR_FP32 or KS_IR_BF16                      */
     int32_t max_iter;   /* FP64: A*v products in the Krylov loop over the whole
@@ -103,7 +107,8 @@ typedef struct {
 
 typedef struct {
     int32_t status;        /* KS_OK or a positive outcome                           */
-    int32_t iters;         /* A*v products inside the Krylov loops (all levels)     */
+    int32_t iters;         /* A*v products inside the Krylov loops (all levels;
+                              BiCGSTAB makes two per iteration)                     */
     int32_t outer_iters;   /* IR refinement steps (0 for KS_FP64)                   */
     int32_t restarts;      /* GMRES cycles beyond the first / CG restarts            */
     double rel_res;        /* ||b - A x||_2 / ||b||_2 of the returned x (binary64)  */

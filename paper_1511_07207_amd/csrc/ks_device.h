@@ -132,4 +132,10 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
 
+// Absolute threshold on ||r||_2: tol ||b||_2, or with backward-error stopping
+// tol (||A||_inf ||x||_inf + ||b||_inf) (which bounds eta_inf by tol).
+__device__ __forceinline__ double stop_threshold(const State *st, double xinf) {
+    return st->eta_tol > 0.0 ? st->eta_tol * (st->anorm_inf * xinf + st->binf) : st->thresh;
+}
+
 }  // namespace ks

@@ -40,6 +40,24 @@ __global__ __launch_bounds__(ONE_NT) void residual_finish_kernel(int nblocks, St
     residual_finish_body(nblocks, st, partial, gate);
 }
 
+template <typename TA>
+__global__ __launch_bounds__(GEMV_NT) void bs_vmatvec_kernel(int n, int64_t lda, const TA *__restrict__ A,
+                                                             const typename ATraits<TA>::TV *__restrict__ p,
+                                                             const typename ATraits<TA>::TV *__restrict__ r0,
+                                                             typename ATraits<TA>::TV *__restrict__ v,
+                                                             const State *st, double *partial) {
+    bs_vmatvec_body<TA>(n, lda, A, p, r0, v, st, partial, blockIdx.x);
+}
+
+template <typename TA>
+__global__ __launch_bounds__(GEMV_NT) void bs_tmatvec_kernel(int n, int64_t lda, const TA *__restrict__ A,
+                                                             const typename ATraits<TA>::TV *__restrict__ s,
+                                                             typename ATraits<TA>::TV *__restrict__ t,
+                                                             State *st, const double *__restrict__ pss,
+                                                             int nss, int max_iter, double *partial) {
+    bs_tmatvec_body<TA>(n, lda, A, s, t, st, pss, nss, max_iter, partial, blockIdx.x);
+}
+
 __global__ __launch_bounds__(GEMV_NT) void norm_inf_kernel(int n, int64_t lda, const double *__restrict__ A,
                                                            double *partial) {
     norm_inf_body(n, lda, A, partial, blockIdx.x);
@@ -96,6 +114,21 @@ hipError_t launch_gm_matvec(int n, int64_t lda, const TA *A, const T *vk, T *w, 
     return hipGetLastError();
 }
 
+template <typename TA, typename T>
+hipError_t launch_bs_vmatvec(int n, int64_t lda, const TA *A, const T *p, const T *r0, T *v,
+                             State *st, Partials P, hipStream_t s) {
+    bs_vmatvec_kernel<TA><<<gemv_blocks<TA>(n), GEMV_NT, 0, s>>>(n, lda, A, p, r0, v, st, P.g);
+    return hipGetLastError();
+}
+
+template <typename TA, typename T>
+hipError_t launch_bs_tmatvec(int n, int64_t lda, const TA *A, const T *sv, T *t, State *st,
+                             Partials P, int max_iter, hipStream_t s) {
+    bs_tmatvec_kernel<TA><<<gemv_blocks<TA>(n), GEMV_NT, 0, s>>>(n, lda, A, sv, t, st, P.v,
+                                                                 vec_blocks(n), max_iter, P.g);
+    return hipGetLastError();
+}
+
 hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,
                            hipStream_t s) {
     const int nb = gemv_blocks<double>(n);
@@ -110,7 +143,11 @@ hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Parti
     template hipError_t launch_cg_matvec<TA, T>(int, int64_t, const TA *, const T *, T *,        \
                                                 State *, Partials, hipStream_t);                 \
     template hipError_t launch_gm_matvec<TA, T>(int, int64_t, const TA *, const T *, T *,        \
-                                                State *, Partials, hipStream_t);
+                                                State *, Partials, hipStream_t);                 \
+    template hipError_t launch_bs_vmatvec<TA, T>(int, int64_t, const TA *, const T *, const T *, \
+                                                 T *, State *, Partials, hipStream_t);           \
+    template hipError_t launch_bs_tmatvec<TA, T>(int, int64_t, const TA *, const T *, T *,       \
+                                                 State *, Partials, int, hipStream_t);
 
 KS_INST_GEMV(double, double)
 KS_INST_GEMV(float, float)

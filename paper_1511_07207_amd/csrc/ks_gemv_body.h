@@ -269,6 +269,72 @@ __device__ __forceinline__ void gm_matvec_body(int n, int64_t lda, const TA *__r
     }
 }
 
+// ------------------------------------- BiCGSTAB: v = A p, r0'v partial
+template <typename TA>
+__device__ __forceinline__ void bs_vmatvec_body(int n, int64_t lda, const TA *__restrict__ A,
+                                                const typename ATraits<TA>::TV *__restrict__ p,
+                                                const typename ATraits<TA>::TV *__restrict__ r0,
+                                                typename ATraits<TA>::TV *__restrict__ v,
+                                                const State *st, double *partial, int bid) {
+    using TV = typename ATraits<TA>::TV;
+    if (st->flags & F_STOP) return;
+    const int row0 = bid * GemvShape<TA>::ROWS;
+    TV acc[GemvShape<TA>::ROWS];
+    rows_dot<TA, GemvShape<TA>::ROWS, GEMV_NT, GemvShape<TA>::UNR>(A, lda, n, row0, p, acc);
+    TV out = reduce_rows<TV, GemvShape<TA>::ROWS, GEMV_NT>(acc);
+    const int row = row0 + threadIdx.x;
+    double contrib = 0.0;
+    if (threadIdx.x < GemvShape<TA>::ROWS && row < n) {
+        v[row] = out;
+        contrib = (double)r0[row] * (double)out;
+    }
+    if (threadIdx.x < WAVE) {
+        double t = wave_sum(contrib);
+        if (threadIdx.x == 0) partial[bid] = t;
+    }
+}
+
+// ------------------------------ BiCGSTAB: t = A s, t's and t't partials
+// Every block first reduces ||s||^2 from the previous kernel's partials and
+// takes the same decision: if ||s|| already meets the threshold (or the
+// product budget is spent) the iteration ends on the half step, the product
+// is skipped and block 0 marks F_HALF (with F_CONV or F_MAXIT) for the next
+// kernels.  No block tests F_HALF here, so the mark cannot race.
+template <typename TA>
+__device__ __forceinline__ void bs_tmatvec_body(int n, int64_t lda, const TA *__restrict__ A,
+                                                const typename ATraits<TA>::TV *__restrict__ s,
+                                                typename ATraits<TA>::TV *__restrict__ t,
+                                                State *st, const double *__restrict__ pss, int nss,
+                                                int max_iter, double *partial, int bid) {
+    using TV = typename ATraits<TA>::TV;
+    if (st->flags & F_STOP) return;
+    const double ss = reduce_partials_all<GEMV_NT>(pss, nss, 1);
+    const bool conv = sqrt(ss) <= stop_threshold(st, st->xinf_it);
+    if (conv || st->iters >= max_iter) {
+        if (bid == 0 && threadIdx.x == 0) st->flags |= F_HALF | (conv ? F_CONV : F_MAXIT);
+        return;
+    }
+    const int row0 = bid * GemvShape<TA>::ROWS;
+    TV acc[GemvShape<TA>::ROWS];
+    rows_dot<TA, GemvShape<TA>::ROWS, GEMV_NT, GemvShape<TA>::UNR>(A, lda, n, row0, s, acc);
+    TV out = reduce_rows<TV, GemvShape<TA>::ROWS, GEMV_NT>(acc);
+    const int row = row0 + threadIdx.x;
+    double ts = 0.0, tt = 0.0;
+    if (threadIdx.x < GemvShape<TA>::ROWS && row < n) {
+        t[row] = out;
+        ts = (double)out * (double)s[row];
+        tt = (double)out * (double)out;
+    }
+    if (threadIdx.x < WAVE) {
+        double a = wave_sum(ts);
+        double b = wave_sum(tt);
+        if (threadIdx.x == 0) {
+            partial[2 * bid] = a;
+            partial[2 * bid + 1] = b;
+        }
+    }
+}
+
 // --------------------------------------------- true residual r = b - A x
 // gate 1: run only when the inner loop has stopped (F_STOP set).
 template <typename TA>

@@ -290,6 +290,91 @@ int run_gmres(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda
     return KS_OK;
 }
 
+// ------------------------------------------------------------- BiCGSTAB
+// Same host flow as run_cg: one pass of the recurrence from the current x,
+// then (binary64) confirmation on the true residual and a restart with a new
+// shadow residual when it fails.  vec = {r, r0, p, v, s, t}.  Each iteration
+// makes up to two products; max_iter bounds the products.
+template <typename TA, typename T>
+int run_bicgstab(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, const T *b,
+                 T *x, T *const vec[6], double tol, int max_iter, bool outer, Outcome *out,
+                 int eta = 0) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    T *r = vec[0];
+    HIPCHK(launch_vec_stats<T>(n, b, tol, st, sm, eta));
+    HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 0, sm)));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const State *h = &s->host[state_index];
+    if (h->bnorm == 0.0) {
+        HIPCHK(launch_fill<T>(n, x, T(0), sm));
+        out->status = KS_OK;
+        out->iters = 0;
+        return KS_OK;
+    }
+    int restarts = 0;
+    bool first = true;
+    for (;;) {
+        const int f = h->flags;
+        if (f & F_TRUE_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (f & F_TRUE_OK) {
+            out->status = KS_OK;
+            break;
+        }
+        if (h->iters >= max_iter) {
+            out->status = KS_MAXITER;
+            break;
+        }
+        if (!first) {
+            if (restarts >= CG_MAX_RESTARTS) {
+                out->status = KS_STAGNATED;
+                break;
+            }
+            ++restarts;
+        }
+        first = false;
+        HIPCHK(launch_bs_begin<T>(n, r, vec[1], vec[2], st, sm));
+        bool done = false;
+        while (!done) {
+            const int it0 = h->iters;
+            const int chunk = std::max(1, std::min(poll_chunk(s), div_up(max_iter - it0, 2)));
+            for (int c = 0; c < chunk; ++c) {
+                hipEvent_t ev[4];
+                if ((rc = timing_pair(s, &ev[0], &ev[1]))) return rc;
+                if ((rc = timing_pair(s, &ev[2], &ev[3]))) return rc;
+                HIPCHK((launch_bs_iteration<TA, T>(n, lda, A, x, vec, st, s->P, max_iter, sm, ev[0],
+                                                   ev[1], ev[2], ev[3])));
+            }
+            if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
+            if ((rc = sync_state(s))) return rc;
+            if ((rc = timed_collect(s, h->iters - it0))) return rc;
+            done = (h->flags & F_STOP) != 0;
+        }
+        const int f2 = h->flags;
+        if (f2 & F_BREAK) {
+            out->status = KS_BREAKDOWN;
+            break;
+        }
+        if (f2 & F_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (!outer) {
+            out->status = (f2 & F_CONV) ? KS_OK : KS_MAXITER;
+            break;
+        }
+        // F_CONV or F_MAXIT (after a full or a half step): the gated residual
+        // kernel has refreshed F_TRUE_OK
+    }
+    out->iters = h->iters;
+    out->restarts = restarts;
+    return KS_OK;
+}
+
 // Metrics of the returned x from the State the solve left behind: every exit
 // path of the drivers ends with a true-residual kernel and a sync, so the
 // host mirror holds ||b||, ||r|| and the infinity norms of r, x and b.
@@ -310,6 +395,12 @@ int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_ite
     if (s->p.method == KS_CG)
         return run_cg<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
                                       s->vec64(2), tol, max_iter, true, o, eta);
+    if (s->p.method == KS_BICGSTAB) {
+        double *const vec[6] = {s->vec64(0), s->vec64(1), s->vec64(2),
+                                s->vec64(3), s->vec64(4), s->vec64(5)};
+        return run_bicgstab<double, double>(s, s->st, 0, s->A, s->lda, b, x, vec, tol, max_iter,
+                                            true, o, eta);
+    }
     return run_gmres<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
                                      tol, max_iter, o, eta);
 }
@@ -625,6 +716,18 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
                                           (s->p.precision == KS_IR_BF16) ? s->A_fb : (const float *)s->A_low,
                                           ll, rhs, d, ri, pi, qi, s->p.inner_tol, s->p.max_iter, false,
                                           &oi);
+        } else if (s->p.method == KS_BICGSTAB) {
+            float *const vi[6] = {s->vec32(2), s->vec32(3), s->vec32(4),
+                                  s->vec32(5), s->vec32(6), s->vec32(7)};
+            if (prec == KS_IR_BF16)
+                rc = run_bicgstab<bf16_t, float>(s, s->st_in, 1, (const bf16_t *)s->A_low, ll, rhs, d,
+                                                 vi, s->p.inner_tol, s->p.max_iter, false, &oi);
+            else
+                rc = run_bicgstab<float, float>(s, s->st_in, 1,
+                                                (s->p.precision == KS_IR_BF16) ? s->A_fb
+                                                                               : (const float *)s->A_low,
+                                                ll, rhs, d, vi, s->p.inner_tol, s->p.max_iter, false,
+                                                &oi);
         } else {
             float *wi = s->vec32(2), *Vi = s->vec32(3);
             if (prec == KS_IR_BF16)
@@ -663,7 +766,8 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
 extern "C" {
 
 int ks_params_init(ks_params *p, int32_t n, int32_t method) {
-    if (!p || n < 1 || (method != KS_CG && method != KS_GMRES)) return KS_EINVAL;
+    if (!p || n < 1 || (method != KS_CG && method != KS_GMRES && method != KS_BICGSTAB))
+        return KS_EINVAL;
     std::memset(p, 0, sizeof(*p));
     p->n = n;
     p->method = method;

@@ -20,9 +20,11 @@ enum : int32_t {
     F_NONFIN = 16,      // non-finite scalar inside the Krylov loop
     F_HAPPY = 32,       // GMRES happy breakdown (exact solution in the space)
     F_TRUE_OK = 64,     // last true residual met the tolerance
-    F_TRUE_NONFIN = 128 // last true residual (or ||b||) not finite
+    F_TRUE_NONFIN = 128,// last true residual (or ||b||) not finite
+    F_HALF = 256        // BiCGSTAB ends on the half step x += alpha p (with
+                        // F_CONV or F_MAXIT; F_STOP follows one kernel later)
 };
-constexpr int32_t INNER_FLAGS = F_STOP | F_CONV | F_MAXIT | F_BREAK | F_NONFIN | F_HAPPY;
+constexpr int32_t INNER_FLAGS = F_STOP | F_CONV | F_MAXIT | F_BREAK | F_NONFIN | F_HAPPY | F_HALF;
 
 // Scalars of one solve, kept on the device so that no iteration needs the host.
 // Within one kernel a field is either read by every block or written by
@@ -37,6 +39,7 @@ struct alignas(256) State {
     double anorm_inf;          // ||A||_inf
     double eta_tol;            // > 0: stop on the backward error eta_inf <= eta_tol
     double xinf_it;            // ||x||_inf of the CG iterate (backward-error stopping)
+    double omega;              // BiCGSTAB stabilisation scalar
     int32_t iters;             // A*v products in the Krylov loop
     int32_t flags;
     int32_t k_done;            // GMRES: steps in the current cycle
@@ -58,6 +61,7 @@ struct Partials {
     double *h1;   // Gram-Schmidt pass 1: (m+1) per block
     double *h2;   // Gram-Schmidt pass 2: (m+1) per block
     double *nrm;  // ||w||^2 after pass 2: 1 per block
+    double *w;    // BiCGSTAB x/r update: 3 per vector block (r'r, r0'r, ||x||_inf)
 };
 
 // Tuning of the dense matrix-vector product: a block of GEMV_NT threads owns
@@ -167,6 +171,27 @@ hipError_t launch_gm_matvec(int n, int64_t lda, const TA *A, const T *vk, T *w, 
 template <typename T>
 hipError_t launch_gm_finish(int n, int ldv, const T *V, T *x, State *st, GmArrays ga,
                             hipStream_t s);
+
+// BiCGSTAB iteration, five kernels (two products with A):
+//   begin: r0 = p = r, inner flags cleared (rho = r'r from the residual kernel)
+//   v = A p (r0'v partials);  alpha, s = r - alpha v (s's partials);
+//   t = A s (t's, t't partials; skipped on the half-step exit);
+//   omega, x += alpha p + omega s, r = s - omega t (r'r, r0'r partials);
+//   stop tests, beta, p = r + beta (p - omega v).
+// vec = {r, r0, p, v, s, t}; ev_* (may be null) bracket the two products.
+// the two products of the iteration (first and third kernels)
+template <typename TA, typename T>
+hipError_t launch_bs_vmatvec(int n, int64_t lda, const TA *A, const T *p, const T *r0, T *v,
+                             State *st, Partials P, hipStream_t s);
+template <typename TA, typename T>
+hipError_t launch_bs_tmatvec(int n, int64_t lda, const TA *A, const T *sv, T *t, State *st,
+                             Partials P, int max_iter, hipStream_t s);
+template <typename T>
+hipError_t launch_bs_begin(int n, const T *r, T *r0, T *p, State *st, hipStream_t s);
+template <typename TA, typename T>
+hipError_t launch_bs_iteration(int n, int64_t lda, const TA *A, T *x, T *const vec[6], State *st,
+                               Partials P, int max_iter, hipStream_t s, hipEvent_t ev_v0,
+                               hipEvent_t ev_v1, hipEvent_t ev_t0, hipEvent_t ev_t1);
 
 // ||A||_inf into st->anorm_inf
 hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,

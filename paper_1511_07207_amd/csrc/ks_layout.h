@@ -22,7 +22,7 @@ struct Layout {
     size_t gm_off = 0;      // GMRES small arrays (binary64)
     size_t part_off = 0;    // block partials (regions of Partials)
     size_t part_count = 0;
-    size_t pg = 0, pv = 0, ph = 0, pn = 0;  // region sizes in doubles
+    size_t pg = 0, pv = 0, ph = 0, pn = 0, pw = 0;  // region sizes in doubles
     size_t v64_off = 0;     // binary64 vectors
     int nv64 = 0;
     size_t v32_off = 0;     // binary32 vectors (IR inner solve)
@@ -48,7 +48,7 @@ inline size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m
 inline bool valid_params(const ks_params *p) {
     if (!p) return false;
     if (p->n < 1 || p->lda < p->n) return false;
-    if (p->method != KS_CG && p->method != KS_GMRES) return false;
+    if (p->method != KS_CG && p->method != KS_GMRES && p->method != KS_BICGSTAB) return false;
     if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
     if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
     if (p->max_iter < 0) return false;
@@ -75,17 +75,20 @@ inline Layout make_layout(const ks_params *p) {
     L.pv = (size_t)round_up(2 * vec_blocks(n), 32);
     L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
     L.pn = (size_t)round_up(cgs_blocks(n), 32);
-    L.part_count = L.pg + L.pv + 2 * L.ph + L.pn;
+    L.pw = (p->method == KS_BICGSTAB) ? (size_t)round_up(3 * vec_blocks(n), 32) : 0;
+    L.part_count = L.pg + L.pv + 2 * L.ph + L.pn + L.pw;
     L.part_off = off;
     off = align_up(off + L.part_count * sizeof(double));
-    // binary64 vectors: CG r, p, q; GMRES w, V(0..m); IR adds the outer residual
-    L.nv64 = (p->method == KS_CG) ? 3 : 1 + (L.m + 1);
+    // binary64 vectors: CG r, p, q; GMRES w, V(0..m); BiCGSTAB r, r0, p, v, s, t;
+    // IR adds the outer residual
+    const int nkry = (p->method == KS_CG) ? 3 : (p->method == KS_BICGSTAB) ? 6 : 1 + (L.m + 1);
+    L.nv64 = nkry;
     if (p->precision != KS_FP64) L.nv64 += 1;
     L.v64_off = off;
     off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
-    // binary32 vectors of the inner solve: rhs, d, then CG r, p, q or GMRES w, V(0..m)
+    // binary32 vectors of the inner solve: rhs, d, then the method's vectors
     L.nv32 = 0;
-    if (p->precision != KS_FP64) L.nv32 = 2 + ((p->method == KS_CG) ? 3 : 1 + (L.m + 1));
+    if (p->precision != KS_FP64) L.nv32 = 2 + nkry;
     L.v32_off = off;
     off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
     if (p->nrhs > 1) {
@@ -167,6 +170,8 @@ inline Carved carve(const Layout &L, char *ws) {
     c.P.h2 = pp;
     pp += L.ph;
     c.P.nrm = pp;
+    pp += L.pn;
+    c.P.w = L.pw ? pp : nullptr;
     c.v64 = (double *)(ws + L.v64_off);
     c.v32 = (float *)(ws + L.v32_off);
     return c;

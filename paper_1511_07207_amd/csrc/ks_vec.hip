@@ -62,6 +62,36 @@ __global__ __launch_bounds__(CGS_NT) void gm_finish_kernel(int n, int ldv, const
     gm_finish_body<T>(n, ldv, V, x, st, ga, blockIdx.x);
 }
 
+template <typename T>
+__global__ __launch_bounds__(VEC_NT) void bs_begin_kernel(int n, const T *__restrict__ r, T *__restrict__ r0,
+                                                          T *__restrict__ p, State *st) {
+    bs_begin_body<T>(n, r, r0, p, st, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(VEC_NT) void bs_supdate_kernel(int n, const T *__restrict__ r,
+                                                            const T *__restrict__ v, T *__restrict__ sv,
+                                                            State *st, const double *__restrict__ pr0v,
+                                                            int nr0v, double *__restrict__ pss) {
+    bs_supdate_body<T>(n, r, v, sv, st, pr0v, nr0v, pss, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(VEC_NT) void bs_xrupdate_kernel(int n, T *__restrict__ x, T *__restrict__ r,
+                                                             const T *__restrict__ r0,
+                                                             const T *__restrict__ p,
+                                                             const T *__restrict__ sv,
+                                                             const T *__restrict__ t, State *st,
+                                                             const double *__restrict__ pt, int npt,
+                                                             double *__restrict__ pw) {
+    bs_xrupdate_body<T>(n, x, r, r0, p, sv, t, st, pt, npt, pw, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(VEC_NT) void bs_pupdate_kernel(int n, const T *__restrict__ r,
+                                                            const T *__restrict__ v, T *__restrict__ p,
+                                                            State *st, const double *__restrict__ pw,
+                                                            int nw, int max_iter) {
+    bs_pupdate_body<T>(n, r, v, p, st, pw, nw, max_iter, blockIdx.x);
+}
+
 // ----------------------------------------------------------- conversions
 __global__ void convert_kernel(int n, int64_t lda_src, const double *__restrict__ src,
                                int dst_dtype, int64_t lda_dst, void *__restrict__ dst) {
@@ -198,6 +228,31 @@ hipError_t launch_gm_step(int n, int64_t lda, const TA *A, int ldv, T *V, T *w, 
 }
 
 template <typename T>
+hipError_t launch_bs_begin(int n, const T *r, T *r0, T *p, State *st, hipStream_t s) {
+    bs_begin_kernel<T><<<vec_blocks(n), VEC_NT, 0, s>>>(n, r, r0, p, st);
+    return hipGetLastError();
+}
+
+template <typename TA, typename T>
+hipError_t launch_bs_iteration(int n, int64_t lda, const TA *A, T *x, T *const vec[6], State *st,
+                               Partials P, int max_iter, hipStream_t s, hipEvent_t ev_v0,
+                               hipEvent_t ev_v1, hipEvent_t ev_t0, hipEvent_t ev_t1) {
+    T *r = vec[0], *r0 = vec[1], *p = vec[2], *v = vec[3], *sv = vec[4], *t = vec[5];
+    const int nv = vec_blocks(n), ng = gemv_blocks<TA>(n);
+    hipError_t e;
+    if (ev_v0 && (e = hipEventRecord(ev_v0, s)) != hipSuccess) return e;
+    if ((e = launch_bs_vmatvec<TA, T>(n, lda, A, p, r0, v, st, P, s)) != hipSuccess) return e;
+    if (ev_v1 && (e = hipEventRecord(ev_v1, s)) != hipSuccess) return e;
+    bs_supdate_kernel<T><<<nv, VEC_NT, 0, s>>>(n, r, v, sv, st, P.g, ng, P.v);
+    if (ev_t0 && (e = hipEventRecord(ev_t0, s)) != hipSuccess) return e;
+    if ((e = launch_bs_tmatvec<TA, T>(n, lda, A, sv, t, st, P, max_iter, s)) != hipSuccess) return e;
+    if (ev_t1 && (e = hipEventRecord(ev_t1, s)) != hipSuccess) return e;
+    bs_xrupdate_kernel<T><<<nv, VEC_NT, 0, s>>>(n, x, r, r0, p, sv, t, st, P.g, ng, P.w);
+    bs_pupdate_kernel<T><<<nv, VEC_NT, 0, s>>>(n, r, v, p, st, P.w, nv, max_iter);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_gm_finish(int n, int ldv, const T *V, T *x, State *st, GmArrays ga,
                             hipStream_t s) {
     gm_finish_kernel<T><<<cgs_blocks(n), CGS_NT, 0, s>>>(n, ldv, V, x, st, ga);
@@ -253,7 +308,8 @@ hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipS
                                            hipStream_t);                                       \
     template hipError_t launch_gm_finish<T>(int, int, const T *, T *, State *, GmArrays,      \
                                             hipStream_t);                                      \
-    template hipError_t launch_fill<T>(int, T *, T, hipStream_t);
+    template hipError_t launch_fill<T>(int, T *, T, hipStream_t);                            \
+    template hipError_t launch_bs_begin<T>(int, const T *, T *, T *, State *, hipStream_t);
 
 KS_INST_T(double)
 KS_INST_T(float)
@@ -267,5 +323,14 @@ template hipError_t launch_gm_step<float, float>(int, int64_t, const float *, in
 template hipError_t launch_gm_step<bf16_t, float>(int, int64_t, const bf16_t *, int, float *,
                                                   float *, int, State *, GmArrays, Partials, int,
                                                   hipStream_t, hipEvent_t, hipEvent_t);
+
+#define KS_INST_BS(TA, T)                                                                      \
+    template hipError_t launch_bs_iteration<TA, T>(int, int64_t, const TA *, T *, T *const[6], \
+                                                   State *, Partials, int, hipStream_t,        \
+                                                   hipEvent_t, hipEvent_t, hipEvent_t,         \
+                                                   hipEvent_t);
+KS_INST_BS(double, double)
+KS_INST_BS(float, float)
+KS_INST_BS(bf16_t, float)
 
 }  // namespace ks

@@ -9,11 +9,6 @@ namespace ks {
 constexpr double HAPPY_FACTOR = 1e-14;  // h(k+1,k) <= this * ||A v_k||
 
 // ------------------------------------------------- ||b||_2 and ||b||_inf
-// absolute threshold on ||r||_2: tol ||b||_2, or with backward-error stopping
-// tol (||A||_inf ||x||_inf + ||b||_inf) (which bounds eta_inf by tol)
-__device__ __forceinline__ double stop_threshold(const State *st, double xinf) {
-    return st->eta_tol > 0.0 ? st->eta_tol * (st->anorm_inf * xinf + st->binf) : st->thresh;
-}
 
 template <typename T>
 __device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, double tol, State *st,
@@ -139,6 +134,185 @@ __device__ __forceinline__ void cg_begin_body(int n, const T *__restrict__ r, T 
         if (i < n) p[i] = r[i];
     }
     if (bid == 0 && threadIdx.x == 0) st->flags &= ~INNER_FLAGS;
+}
+
+// ------------------------------------------------------------- BiCGSTAB
+// Start of a pass from the current x: shadow residual r0 = r and p = r (the
+// first search direction of the recurrence with p = v = 0); rho = r0'r is the
+// residual kernel's r'r.
+template <typename T>
+__device__ __forceinline__ void bs_begin_body(int n, const T *__restrict__ r, T *__restrict__ r0,
+                                              T *__restrict__ p, State *st, int bid) {
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) {
+            const T ri = r[i];
+            r0[i] = ri;
+            p[i] = ri;
+        }
+    }
+    if (bid == 0 && threadIdx.x == 0) {
+        st->flags &= ~INNER_FLAGS;
+        st->xinf_it = st->xinf;
+    }
+}
+
+// alpha = rho / (r0'v) from the product's partials; s = r - alpha v; s's
+// partials for the next kernel.  Block 0 counts the product.
+template <typename T>
+__device__ __forceinline__ void bs_supdate_body(int n, const T *__restrict__ r, const T *__restrict__ v,
+                                                T *__restrict__ s, State *st,
+                                                const double *__restrict__ pr0v, int nr0v,
+                                                double *__restrict__ pss, int bid) {
+    __shared__ double sm[VEC_NT / WAVE];
+    if (st->flags & F_STOP) return;
+    const double r0v = reduce_partials_all<VEC_NT>(pr0v, nr0v, 1);
+    const double rho = st->rho;
+    const bool ok = finite_d(r0v) && r0v != 0.0;
+    if (bid == 0 && threadIdx.x == 0) {
+        st->iters += 1;
+        if (!finite_d(r0v))
+            st->flags |= F_NONFIN | F_STOP;
+        else if (r0v == 0.0)
+            st->flags |= F_BREAK | F_STOP;
+        else
+            st->alpha = rho / r0v;
+    }
+    if (!ok) return;
+    const T a = (T)(rho / r0v);
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) {
+            const T si = fma(-a, v[i], r[i]);
+            s[i] = si;
+            s2 += (double)si * (double)si;
+        }
+    }
+    const double t = block_sum<VEC_NT>(s2, sm);
+    if (threadIdx.x == 0) pss[bid] = t;
+}
+
+// Half step (F_HALF from the product kernel): x += alpha p and nothing else.
+// Otherwise omega = t's / t't, x += alpha p + omega s, r = s - omega t, and
+// partials of r'r, r0'r and ||x||_inf into pw = [nblk][nblk][nblk].  Block 0
+// counts the second product and keeps rho in rho_prev for the next kernel.
+template <typename T>
+__device__ __forceinline__ void bs_xrupdate_body(int n, T *__restrict__ x, T *__restrict__ r,
+                                                 const T *__restrict__ r0, const T *__restrict__ p,
+                                                 const T *__restrict__ s, const T *__restrict__ t,
+                                                 State *st, const double *__restrict__ pt, int npt,
+                                                 double *__restrict__ pw, int bid, int nblk) {
+    __shared__ double sm[VEC_NT / WAVE];
+    const int f = st->flags;
+    if (f & F_STOP) return;
+    const T a = (T)st->alpha;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+    if (f & F_HALF) {
+#pragma unroll
+        for (int e = 0; e < VEC_EPT; ++e) {
+            const int i = base + e * VEC_NT;
+            if (i < n) x[i] = fma(a, p[i], x[i]);
+        }
+        return;
+    }
+    const double ts = reduce_partials_all<VEC_NT>(pt, npt, 2);
+    const double tt = reduce_partials_all<VEC_NT>(pt + 1, npt, 2);
+    const bool ok = finite_d(tt) && tt != 0.0;
+    const double om = ts / tt;
+    if (bid == 0 && threadIdx.x == 0) {
+        st->iters += 1;
+        st->rho_prev = st->rho;
+        if (!finite_d(tt))
+            st->flags |= F_NONFIN | F_STOP;
+        else if (tt == 0.0)
+            st->flags |= F_BREAK | F_STOP;
+        else
+            st->omega = om;
+    }
+    if (!ok) return;
+    const T w = (T)om;
+    double rr = 0.0, r0r = 0.0, xm = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) {
+            const T si = s[i];
+            const T xi = fma(w, si, fma(a, p[i], x[i]));
+            x[i] = xi;
+            const T ri = fma(-w, t[i], si);
+            r[i] = ri;
+            rr += (double)ri * (double)ri;
+            r0r += (double)r0[i] * (double)ri;
+            xm = fmax(xm, finite_d((double)xi) ? fabs((double)xi) : INFINITY);
+        }
+    }
+    const double t0 = block_sum<VEC_NT>(rr, sm);
+    __syncthreads();
+    const double t1 = block_sum<VEC_NT>(r0r, sm);
+    __syncthreads();
+    const double t2 = block_max<VEC_NT>(xm, sm);
+    if (threadIdx.x == 0) {
+        pw[bid] = t0;
+        pw[nblk + bid] = t1;
+        pw[2 * nblk + bid] = t2;
+    }
+}
+
+// Stop tests on the recursive residual (tolerance, product budget), then the
+// breakdowns omega = 0 and r0'r = 0; otherwise beta = (rho'/rho)(alpha/omega)
+// and p = r + beta (p - omega v).  After a half step block 0 only sets F_STOP
+// (every block returns in that case, so the flag write cannot race).
+template <typename T>
+__device__ __forceinline__ void bs_pupdate_body(int n, const T *__restrict__ r, const T *__restrict__ v,
+                                                T *__restrict__ p, State *st,
+                                                const double *__restrict__ pw, int nw, int max_iter,
+                                                int bid) {
+    const int f = st->flags;
+    if (f & F_STOP) return;
+    if (f & F_HALF) {
+        if (bid == 0 && threadIdx.x == 0) st->flags = f | F_STOP;
+        return;
+    }
+    const double rr = reduce_partials_all<VEC_NT>(pw, nw, 1);
+    const double rho_new = reduce_partials_all<VEC_NT>(pw + nw, nw, 1);
+    const double xinf = st->eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(pw + 2 * nw, nw, 1) : 0.0;
+    const double rho = st->rho_prev, alpha = st->alpha, om = st->omega;
+    int stop = 0;
+    if (!finite_d(rr))
+        stop = F_NONFIN | F_STOP;
+    else if (sqrt(rr) <= stop_threshold(st, xinf))
+        stop = F_CONV | F_STOP;
+    else if (st->iters >= max_iter)
+        stop = F_MAXIT | F_STOP;
+    else if (om == 0.0)
+        stop = F_BREAK | F_STOP;
+    else if (!finite_d(rho_new))
+        stop = F_NONFIN | F_STOP;
+    else if (rho_new == 0.0)
+        stop = F_BREAK | F_STOP;
+    const double beta = (rho_new / rho) * (alpha / om);
+    if (bid == 0 && threadIdx.x == 0) {
+        st->xinf_it = xinf;
+        if (stop) {
+            st->flags |= stop;
+        } else {
+            st->beta = beta;
+            st->rho = rho_new;
+        }
+    }
+    if (stop) return;
+    const T bt = (T)beta, w = (T)om;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) p[i] = fma(bt, fma(-w, v[i], p[i]), r[i]);
+    }
 }
 
 // ---------------------------------------------------------------- GMRES

@@ -61,3 +61,27 @@ def test_host_only_entry_points_without_gpu():
     assert L.ks_strerror(0) == b"converged"
     assert L.ks_gemv(0, 0, 0, None, None, None, None) == N.KS_EINVAL
     L.ks_free(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_bicgstab_parameters_on_host():
+    # BiCGSTAB keeps six vectors (r, r0, p, v, s, t) and one State; it is a
+    # one-right-hand-side method, so nrhs > 1 is rejected
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    p = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(p), 1000, N.KS_BICGSTAB) == 0
+    assert p.method == N.KS_BICGSTAB
+    sz, szc = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+    q = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(q), 1000, N.KS_CG) == 0
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(q), ctypes.byref(szc)) == 0
+    assert sz.value >= szc.value + 3 * 1024 * 8
+    p.nrhs = 4
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.nrhs = 1
+    p.precision = N.KS_IR_BF16
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == 0
+    assert L.ks_params_init(ctypes.byref(p), 10, 3) == N.KS_EINVAL
