@@ -187,6 +187,48 @@ def leg_c3(dev, n, kappa):
     return out
 
 
+def leg_f1(dev, n):
+    """BiCGSTAB on the nonsymmetric n = 16384 system of the main step, beside
+    GMRES(30) on the same system: binary64 at relative residual 1e-10, then
+    binary64 vs binary32 / bfloat16 inner solves at backward error 1e-12."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem
+
+    prob = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    out = {"n": n, "system": "D + G/sqrt(n), D uniform in [2,4]"}
+    runs = [("bicgstab_fp64", dict(method="bicgstab", tol=1e-10)),
+            ("gmres30_fp64", dict(method="gmres", restart=30, tol=1e-10)),
+            ("bicgstab_fp64_eta", dict(method="bicgstab", tol=1e-12, stop_backward=True)),
+            ("bicgstab_fp32_eta", dict(method="bicgstab", tol=1e-12, precision="fp32")),
+            ("bicgstab_bf16_eta", dict(method="bicgstab", tol=1e-12, precision="bf16"))]
+    for name, kw in runs:
+        s = krylov.Solver(prob.A, timing=True, **kw)
+        s.solve(prob.b, out=x.zero_())
+        lat = []
+        for _ in range(5):
+            (_, info), dt = _timed(lambda: s.solve(prob.b, out=x.zero_()))
+            lat.append(dt * 1e3)
+        e = {"fp64": 8, "fp32": 4, "bf16": 2}[info["precision_used"]]
+        r = {"status": info["status_name"], "iters": info["iters"], "outer": info["outer_iters"],
+             "precision_used": info["precision_used"], "rel_res": info["rel_res"],
+             "eta_inf": info["backward_err"], "solves_per_s": round(1e3 / statistics.mean(lat), 3),
+             "p50_ms": round(_pct(lat, 0.5), 3)}
+        if info["gemv_calls"] and info["outer_iters"] == 0:
+            r["gemv_gbs"] = round((e * n * n + 16.0 * n) / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)
+        out[name] = r
+        s.close()
+    out["bicgstab_over_gmres30"] = round(out["bicgstab_fp64"]["solves_per_s"]
+                                         / out["gmres30_fp64"]["solves_per_s"], 3)
+    for prec in ("fp32", "bf16"):
+        out[f"bicgstab_{prec}_speedup_vs_fp64"] = round(
+            out[f"bicgstab_{prec}_eta"]["solves_per_s"] / out["bicgstab_fp64_eta"]["solves_per_s"], 3)
+    del prob, x
+    return out
+
+
 def leg_c4(dev, n):
     """Lockstep CG on 64 right-hand sides (A*P on MFMA)."""
     import torch
@@ -297,8 +339,8 @@ def main():
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5",
-                    help="extra measurements after the timed steps (comma list of c1,c3,c4,c5; "
+    ap.add_argument("--legs", default="c1,c3,c4,c5,f1",
+                    help="extra measurements after the timed steps (comma list of c1,c3,c4,c5,f1; "
                          "'none' for the main step only)")
     ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -461,6 +503,8 @@ def main():
                 legs[name] = leg_c4(dev, n)
             elif name == "c5":
                 legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool)
+            elif name == "f1":
+                legs[name] = leg_f1(dev, n)
             else:
                 legs[name] = {"error": "unknown leg"}
         except Exception as e:  # a failing leg is reported, not fatal
