@@ -77,6 +77,11 @@ extern "C" {
                                    error eta_inf instead of ||r||_2 / ||b||_2: stop
                                    when ||r||_2 <= tol (||A||_inf ||x||_inf +
                                    ||b||_inf), confirmed on the true residual */
+#define KS_FLAG_SYMMETRIC 4 /* CG, nrhs = 1: the binary64 products of the Krylov
+                               loop read only the lower triangle of A (i >= j),
+                               half the bytes of the general product.  A must
+                               still hold the whole symmetric matrix: the true
+                               residual and ||A||_inf read both triangles */
 
 typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
@@ -228,6 +233,16 @@ void ks_server_free(ks_server *sv);
  * d_v and d_y 16-byte aligned. */
 int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *d_A, const void *d_v,
             void *d_y, void *stream);
+
+/* Symmetric product y = A x for a symmetric binary64 A, reading only the
+ * lower triangle (elements (i, j) with i >= j; the values above the diagonal
+ * never affect y).  d_ws: device workspace of at least
+ * ks_symv_workspace_bytes(n) bytes, 16-byte aligned, owned by the caller
+ * (tile partials, overwritten).  d_A 16-byte aligned with lda * 8 a multiple
+ * of 16; d_x, d_y 16-byte aligned, not overlapping.  Enqueued on `stream`. */
+int ks_symv_workspace_bytes(int32_t n, size_t *bytes);
+int ks_symv(int32_t n, int64_t lda, const double *d_A, const double *d_x, double *d_y,
+            void *d_ws, size_t ws_bytes, void *stream);
 
 /* Convert an n x n binary64 matrix (lda_src) into dst_dtype (KS_DT_F32:
  * round to nearest even; KS_DT_BF16: round to binary32, then to bfloat16,

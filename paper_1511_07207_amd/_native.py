@@ -20,6 +20,7 @@ KS_FP64, KS_IR_FP32, KS_IR_BF16 = 0, 1, 2
 KS_DT_F64, KS_DT_F32, KS_DT_BF16 = 0, 1, 2
 KS_FLAG_TIMING = 1
 KS_FLAG_STOP_BACKWARD = 2
+KS_FLAG_SYMMETRIC = 4
 KS_MAX_RESTART = 128
 KS_MAX_NRHS = 64
 
@@ -29,7 +30,7 @@ STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfi
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
            "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
-           "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
+           "ks_symv_workspace_bytes", "ks_symv", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
            "ks_server_step", "ks_server_poll", "ks_server_stats", "ks_server_free")
 
 
@@ -113,6 +114,10 @@ def lib() -> ctypes.CDLL:
         L.ks_strerror.restype = ctypes.c_char_p
         L.ks_gemv.argtypes = [i32, i64, i32, vp, vp, vp, vp]
         L.ks_gemv.restype = ctypes.c_int
+        L.ks_symv_workspace_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        L.ks_symv_workspace_bytes.restype = ctypes.c_int
+        L.ks_symv.argtypes = [i32, i64, vp, vp, vp, vp, sz, vp]
+        L.ks_symv.restype = ctypes.c_int
         L.ks_convert.argtypes = [i32, i64, vp, i32, i64, vp, vp]
         L.ks_convert.restype = ctypes.c_int
         L.ks_read_ceiling.argtypes = [vp, sz, vp, vp]

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "ks.h"
@@ -45,6 +46,7 @@ struct ks_solver {
     GmArrays ga{};
     double *v64 = nullptr;
     float *v32 = nullptr;
+    double *sy = nullptr;     // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> tev;  // timing event pairs of A*v launches
     int tev_used = 0;
@@ -179,9 +181,19 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
                 hipEvent_t e0, e1;
                 if ((rc = timing_pair(s, &e0, &e1))) return rc;
                 if (e0) HIPCHK(hipEventRecord(e0, sm));
-                HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                int nsigma = gemv_blocks<TA>(n);
+                if constexpr (std::is_same<TA, double>::value) {
+                    if (s->sy) {
+                        HIPCHK(launch_symv(n, lda, A, p, q, s->sy, st, p, s->P.g, sm));
+                        nsigma = symv_finish_blocks(n);
+                    } else {
+                        HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                    }
+                } else {
+                    HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                }
                 if (e1) HIPCHK(hipEventRecord(e1, sm));
-                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, gemv_blocks<TA>(n), sm));
+                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, nsigma, sm));
                 HIPCHK(launch_cg_pupdate<T>(n, r, p, st, s->P, max_iter, sm));
             }
             if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
@@ -838,6 +850,7 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
         s->P = c.P;
         s->v64 = c.v64;
         s->v32 = c.v32;
+        if (L.sy_bytes) s->sy = (double *)(s->ws + L.sy_off);
     }
     if (p->nrhs > 1) {
         s->mr64 = (double *)(s->ws + L.mr_off);
@@ -1001,6 +1014,24 @@ int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *dA, const void 
     if ((uintptr_t)dA % 16 || (lda * es) % 16 || (uintptr_t)d_v % 16 || (uintptr_t)d_y % 16)
         return KS_EINVAL;
     HIPCHK(launch_gemv(n, lda, a_dtype, dA, d_v, d_y, (hipStream_t)stream));
+    return KS_OK;
+}
+
+int ks_symv_workspace_bytes(int32_t n, size_t *bytes) {
+    if (n < 1 || !bytes) return KS_EINVAL;
+    *bytes = sy_ws_doubles(n) * sizeof(double);
+    return KS_OK;
+}
+
+int ks_symv(int32_t n, int64_t lda, const double *dA, const double *d_x, double *d_y, void *d_ws,
+            size_t ws_bytes, void *stream) {
+    if (n < 1 || lda < n || !dA || !d_x || !d_y || !d_ws) return KS_EINVAL;
+    if ((uintptr_t)dA % 16 || (lda * 8) % 16 || (uintptr_t)d_x % 16 || (uintptr_t)d_y % 16 ||
+        (uintptr_t)d_ws % 16)
+        return KS_EINVAL;
+    if (ws_bytes < sy_ws_doubles(n) * sizeof(double)) return KS_ENOMEM;
+    HIPCHK(launch_symv(n, lda, dA, d_x, d_y, (double *)d_ws, nullptr, nullptr, nullptr,
+                       (hipStream_t)stream));
     return KS_OK;
 }
 

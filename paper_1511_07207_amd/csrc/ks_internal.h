@@ -109,6 +109,16 @@ __host__ __device__ inline int gemv_blocks(int n) {
 // the largest of them, for sizing the partial region
 __host__ __device__ inline int gemv_blocks_max(int n) { return div_up(n, 2); }
 
+// Symmetric product (lower triangle only): SY_T x SY_T tiles, one block of
+// SY_NT threads per tile; the workspace holds two SY_T-vectors per tile.
+constexpr int SY_T = 128;
+constexpr int SY_NT = 256;
+__host__ __device__ inline int sy_tiles(int n) {
+    const int t = div_up(n, SY_T);
+    return t * (t + 1) / 2;
+}
+__host__ __device__ inline size_t sy_ws_doubles(int n) { return (size_t)sy_tiles(n) * 2 * SY_T; }
+
 // GMRES small dense arrays (binary64 always).
 struct GmArrays {
     double *H;   // (m+1) x m unrotated Hessenberg, row-major, ld m
@@ -192,6 +202,14 @@ template <typename TA, typename T>
 hipError_t launch_bs_iteration(int n, int64_t lda, const TA *A, T *x, T *const vec[6], State *st,
                                Partials P, int max_iter, hipStream_t s, hipEvent_t ev_v0,
                                hipEvent_t ev_v1, hipEvent_t ev_t0, hipEvent_t ev_t1);
+
+// y = A x from the lower triangle of A (binary64).  W: sy_ws_doubles(n).
+// st != nullptr: return at once when st has F_STOP (CG loop).  p != nullptr:
+// partial[b] = sum of p_j y_j over finishing block b (symv_finish_blocks(n)).
+int symv_finish_blocks(int n);
+hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
+                       double *W, const State *st, const double *p, double *partial,
+                       hipStream_t s);
 
 // ||A||_inf into st->anorm_inf
 hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,

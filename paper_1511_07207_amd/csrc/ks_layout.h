@@ -39,6 +39,8 @@ struct Layout {
     // each sp16 columns of ldv elements, plus per-column states
     int sp16 = 0;
     size_t mr_off = 0, mr_block_elems = 0, mr_cols_off = 0, mr_part_off = 0, mr_part_count = 0;
+    // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
+    size_t sy_off = 0, sy_bytes = 0;
     size_t total = 0;
     size_t total_borrowed = 0;
 };
@@ -58,6 +60,7 @@ inline bool valid_params(const ks_params *p) {
     }
     if (p->nrhs < 1 || p->nrhs > KS_MAX_NRHS) return false;
     if (p->nrhs > 1 && (p->method != KS_CG || p->precision == KS_IR_BF16)) return false;
+    if ((p->flags & KS_FLAG_SYMMETRIC) && (p->method != KS_CG || p->nrhs != 1)) return false;
     return true;
 }
 
@@ -106,6 +109,11 @@ inline Layout make_layout(const ks_params *p) {
         L.mr_part_count = 3 * (size_t)mr_blocks(n) * KS_MAX_NRHS;
         L.mr_part_off = off;
         off = align_up(off + L.mr_part_count * sizeof(double));
+    }
+    if (p->flags & KS_FLAG_SYMMETRIC) {
+        L.sy_bytes = sy_ws_doubles(n) * sizeof(double);
+        L.sy_off = off;
+        off = align_up(off + L.sy_bytes);
     }
     L.lda_low = round_up(n, 64);
     if (p->precision == KS_IR_FP32) {

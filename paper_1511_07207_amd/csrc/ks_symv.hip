@@ -1,0 +1,342 @@
+// Symmetric matrix-vector product y = A x that reads only the lower triangle
+// of A (elements i >= j): half the bytes of the general product, which is the
+// whole cost of a CG iteration on a dense SPD matrix (the Krylov section
+// counts one matrix-vector product per CG iteration as its Theta(n^2) part).
+//
+// Tiling.  The lower triangle is cut into SY_T x SY_T tiles (I, J), I >= J;
+// one block of SY_NT threads (4 wave64s) reads one tile once and uses every
+// element twice:
+//   row part     y_I += A_IJ x_J      (for the rows of tile row I)
+//   column part  y_J += A_IJ' x_I     (for the columns of tile column J)
+// On a diagonal tile the row part takes the elements with c <= r and the
+// column part those with c < r, so each element of A is counted exactly as
+// often as in the full product; the tile's elements above the diagonal are
+// loaded with the rest of the tile (they are inside the matrix) and
+// discarded by a select, so their values never reach the result.
+//
+// Two tile kernels.  The interior tiles (I > J, all rows inside the matrix),
+// nearly all of the bytes, run in a kernel with no checks: A is read through
+// a buffer resource based at the tile row, so a row's address is a scalar
+// offset and the lane's byte offset (the same for every row) is one vector
+// register.  The diagonal tiles, and the last tile row when SY_T does not
+// divide n, run in a second kernel with the masks and bounds checks.  Kept
+// apart, the interior kernel's register count is not raised by the masking
+// code (a kernel's count is the maximum over its paths), which keeps more
+// waves, and so more loads, in flight per compute unit.
+//
+// Each wave reads SY_RPW rows of the tile, interleaved with the other waves;
+// one wave instruction loads one 1 KiB tile row (64 lanes x 16 bytes, two
+// columns per lane), nontemporal as in the general product.  The x values of
+// a wave's rows are wave-uniform (scalar loads), so no barrier precedes the
+// loads of A.  The column part accumulates per lane (its columns
+// are fixed) and is summed over the 4 waves through LDS.  The row part of each
+// row is a sum over the 64 lanes; a wave takes its rows in groups of U and
+// forms the U sums together by a butterfly that halves the number of values
+// per lane at each exchange, then adds within the remaining lane groups.
+//
+// Every tile writes its two partial vectors (row part, column part; SY_T
+// values each) to a workspace; a third kernel sums, for each element, the row
+// parts of its tile row and the column parts of its tile column in a fixed
+// order (deterministic, no atomics), and writes y (and, for CG, the partials
+// of p'q).  The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A
+// read, i.e. 3% of the product's bytes at SY_T = 128.
+#include "ks_device.h"
+
+namespace ks {
+
+typedef double sy_d2 __attribute__((ext_vector_type(2)));
+typedef uint32_t sy_u4 __attribute__((ext_vector_type(4)));
+
+// Word 3 of a gfx9-family buffer resource for raw (untyped) loads.
+constexpr int SY_RSRC_WORD3 = 0x00020000;
+// Cache policy of the loads of A: nt (streamed once).
+constexpr int SY_NT_POLICY = 2;
+
+constexpr int SY_WAVES = SY_NT / WAVE;
+constexpr int SY_RPW = SY_T / SY_WAVES;  // rows per wave in a tile (32)
+constexpr int SY_UNR_INT = 8;               // rows per group, interior tiles
+constexpr int SY_UNR_SPC = 8;            // rows per group, diagonal / edge tiles
+constexpr int SY_FIN = 64;               // elements per block of the finishing kernel
+constexpr int SY_FACC = 8;               // loads in flight per wave of the finishing kernel
+constexpr int SY_FWAVES = 16;            // waves per block of the finishing kernel
+static_assert(SY_T == 2 * WAVE, "one wave instruction covers one tile row");
+static_assert(SY_RPW % SY_UNR_INT == 0 && SY_RPW % SY_UNR_SPC == 0, "groups tile the rows");
+static_assert(SY_T % SY_FIN == 0, "a finishing block stays inside one tile column");
+
+// t = i (i + 1) / 2 + j, j <= i  ->  (i, j)
+__device__ __forceinline__ void sy_tri_ij(int t, int &I, int &J) {
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (i > 0 && i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+// One step of the row butterfly: the lanes whose `mask` bit is 0 keep the
+// first half of their K values, the others the second half, each adding the
+// partner's copy of the half it keeps.
+template <int K, int U>
+__device__ __forceinline__ void sy_fold(double (&v)[U], int lane, int mask) {
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+        const double keep = hi ? v[i + K / 2] : v[i];
+        const double send = hi ? v[i] : v[i + K / 2];
+        v[i] = keep + __shfl_xor(send, mask);
+    }
+}
+
+// U row sums over the 64 lanes (U = 4, 8 or 16).  Afterwards every lane of
+// the lane group g = lane / (64 / U) holds the sum of row g: the halving
+// exchanges over lane bits 5, 4, ... leave row g in the lanes whose high bits
+// spell g, and the remaining low bits are summed by plain exchanges.
+template <int U>
+__device__ __forceinline__ double sy_rows_reduce(double (&v)[U], int lane) {
+    static_assert(U == 4 || U == 8 || U == 16, "row group of 4, 8 or 16");
+    sy_fold<U, U>(v, lane, 32);
+    if constexpr (U >= 4) sy_fold<U / 2, U>(v, lane, 16);
+    if constexpr (U >= 8) sy_fold<U / 4, U>(v, lane, 8);
+    if constexpr (U >= 16) sy_fold<U / 8, U>(v, lane, 4);
+    double s = v[0];
+#pragma unroll
+    for (int m = 32 / U; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    return s;
+}
+
+// Rows of a tile are interleaved over the waves: wave w reads rows w, w + 4,
+// w + 8, ... (local row lr = w + SY_WAVES * k), so the block as a whole reads
+// consecutive rows at any moment (measured 5% faster than contiguous row
+// blocks per wave for the same bytes).
+__device__ __forceinline__ int sy_row(int w, int k) { return w + SY_WAVES * k; }
+
+// Shared set-up of a tile block.
+struct SyTile {
+    int I, J, t, lane, w, r0, c0, lc, c;
+    double xj0, xj1;
+};
+
+__device__ __forceinline__ SyTile sy_setup(int n, int I, int J, const double *__restrict__ x) {
+    SyTile T;
+    T.I = I;
+    T.J = J;
+    T.t = I * (I + 1) / 2 + J;
+    T.lane = threadIdx.x & (WAVE - 1);
+    T.w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    T.r0 = I * SY_T;
+    T.c0 = J * SY_T;
+    T.lc = 2 * T.lane;  // the lane's two columns inside the tile: lc, lc + 1
+    T.c = T.c0 + T.lc;
+    T.xj0 = T.c < n ? x[T.c] : 0.0;
+    T.xj1 = T.c + 1 < n ? x[T.c + 1] : 0.0;
+    return T;
+}
+
+// Process one group of U rows (k = k0 .. k0 + U - 1 of the wave) that are
+// already loaded: row parts reduced over the lanes into `rows` (LDS), column
+// parts accumulated.  xr[u]: x at the group's rows (wave-uniform values).
+template <int U, bool DIAG>
+__device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&a)[U],
+                                         const double (&xr)[U], double *rows, double &ca0,
+                                         double &ca1) {
+    double racc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int lr = sy_row(T.w, k0 + u);
+        double ar0 = a[u].x, ar1 = a[u].y, ac0 = a[u].x, ac1 = a[u].y;
+        if constexpr (DIAG) {
+            // row part: c <= r; column part: c < r
+            ar0 = (T.lc <= lr) ? ar0 : 0.0;
+            ar1 = (T.lc + 1 <= lr) ? ar1 : 0.0;
+            ac0 = (T.lc < lr) ? ac0 : 0.0;
+            ac1 = (T.lc + 1 < lr) ? ac1 : 0.0;
+        }
+        racc[u] = fma(ar1, T.xj1, ar0 * T.xj0);
+        ca0 = fma(ac0, xr[u], ca0);
+        ca1 = fma(ac1, xr[u], ca1);
+    }
+    const double v = sy_rows_reduce<U>(racc, T.lane);
+    constexpr int LPR = WAVE / U;  // lanes per row after the reduction
+    if ((T.lane % LPR) == 0) rows[sy_row(T.w, k0 + T.lane / LPR)] = v;
+}
+
+// The tile's output, row parts then column parts (the latter summed over the
+// waves), written by the whole block as one contiguous 2 KiB store at its end.
+// Storing once per block instead of per row group, with device-scope cache
+// policy (sc1), measured 7% faster for the whole kernel: the stores interleave
+// less with the stream of loads.
+constexpr int SY_STORE_POLICY = 16;  // sc1
+__device__ __forceinline__ void sy_store(const SyTile &T, double ca0, double ca1, const double *rows,
+                                         double (*cs)[SY_T], double *__restrict__ W) {
+    cs[T.w][T.lc] = ca0;
+    cs[T.w][T.lc + 1] = ca1;
+    __syncthreads();
+    const int q = threadIdx.x & (SY_T - 1);
+    double out;
+    if (threadIdx.x < SY_T) {
+        out = rows[q];
+    } else {
+        out = 0.0;
+#pragma unroll
+        for (int k = 0; k < SY_WAVES; ++k) out += cs[k][q];
+    }
+    static_assert(SY_NT == 2 * SY_T, "one value per thread");
+    typedef uint32_t sy_u2 __attribute__((ext_vector_type(2)));
+    const __amdgpu_buffer_rsrc_t ws = __builtin_amdgcn_make_buffer_rsrc(
+        W + (size_t)T.t * 2 * SY_T, 0, 2 * SY_T * 8, SY_RSRC_WORD3);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sy_u2, out), ws, threadIdx.x * 8, 0,
+                                          SY_STORE_POLICY);
+}
+
+// Interior tiles: (I, J) with 1 <= I < n / SY_T and J < I, enumerated as
+// b = (I - 1) I / 2 + J.  st != nullptr: return at once when the Krylov loop
+// has stopped.
+__global__ __launch_bounds__(SY_NT) void symv_interior_kernel(int n, int64_t lda,
+                                                              const double *__restrict__ A,
+                                                              const double *__restrict__ x,
+                                                              double *__restrict__ W,
+                                                              const State *st) {
+    __shared__ double rows[SY_T];
+    __shared__ double cs[SY_WAVES][SY_T];
+    if (st && (st->flags & F_STOP)) return;
+    int I, J;
+    sy_tri_ij(blockIdx.x, I, J);
+    I += 1;
+    const SyTile T = sy_setup(n, I, J, x);
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(A + (int64_t)T.r0 * lda), 0, (int)((int64_t)SY_T * lda * 8),
+        SY_RSRC_WORD3);
+    const int coff = T.c * 8;
+    const double *xi = x + T.r0;  // x_I: read at wave-uniform indices
+    double ca0 = 0.0, ca1 = 0.0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_INT) {
+        sy_d2 a[SY_UNR_INT];
+        double xr[SY_UNR_INT];
+#pragma unroll
+        for (int u = 0; u < SY_UNR_INT; ++u) {
+            const int lr = sy_row(T.w, k0 + u);
+            const sy_u4 raw = __builtin_amdgcn_raw_buffer_load_b128(
+                rsrc, coff, (int)((int64_t)lr * lda * 8), SY_NT_POLICY);
+            a[u] = __builtin_bit_cast(sy_d2, raw);
+        }
+#pragma unroll
+        for (int u = 0; u < SY_UNR_INT; ++u) xr[u] = xi[sy_row(T.w, k0 + u)];
+        sy_group<SY_UNR_INT, false>(T, k0, a, xr, rows, ca0, ca1);
+    }
+    sy_store(T, ca0, ca1, rows, cs, W);
+}
+
+// Diagonal tiles (block b < nT: tile (b, b)) and, when SY_T does not divide
+// n, the off-diagonal tiles of the last tile row (block nT + j: tile
+// (nT - 1, j)); rows and columns at or beyond n are not read.
+__global__ __launch_bounds__(SY_NT) void symv_special_kernel(int n, int64_t lda,
+                                                             const double *__restrict__ A,
+                                                             const double *__restrict__ x,
+                                                             double *__restrict__ W,
+                                                             const State *st) {
+    __shared__ double rows[SY_T];
+    __shared__ double cs[SY_WAVES][SY_T];
+    if (st && (st->flags & F_STOP)) return;
+    const int nT = div_up(n, SY_T);
+    const int b = blockIdx.x;
+    const int I = (b < nT) ? b : nT - 1;
+    const int J = (b < nT) ? b : b - nT;
+    const SyTile T = sy_setup(n, I, J, x);
+    const bool diag = (I == J);
+    double ca0 = 0.0, ca1 = 0.0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_SPC) {
+        sy_d2 a[SY_UNR_SPC];
+        double xr[SY_UNR_SPC];
+#pragma unroll
+        for (int u = 0; u < SY_UNR_SPC; ++u) {
+            const int r = T.r0 + sy_row(T.w, k0 + u);
+            const bool rin = r < n;
+            const double *row = A + (int64_t)r * lda + T.c;
+            a[u] = sy_d2{(rin && T.c < n) ? row[0] : 0.0, (rin && T.c + 1 < n) ? row[1] : 0.0};
+            xr[u] = rin ? x[r] : 0.0;
+        }
+        if (diag)
+            sy_group<SY_UNR_SPC, true>(T, k0, a, xr, rows, ca0, ca1);
+        else
+            sy_group<SY_UNR_SPC, false>(T, k0, a, xr, rows, ca0, ca1);
+    }
+    sy_store(T, ca0, ca1, rows, cs, W);
+}
+
+// y_j = (row parts of tile row J) + (column parts of tile column J), J = j / SY_T,
+// summed in a fixed order: the SY_FWAVES waves take sources w, w + SY_FWAVES,
+// ... and their sums are added in wave order.  With p != nullptr the block also leaves
+// sum_j p_j y_j in partial[block] (CG: sigma = p'q).
+__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, const double *__restrict__ W,
+                                                            double *__restrict__ y,
+                                                            const double *__restrict__ p,
+                                                            double *__restrict__ partial,
+                                                            const State *st) {
+    __shared__ double red[SY_FWAVES][SY_FIN];
+    if (st && (st->flags & F_STOP)) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int j0 = blockIdx.x * SY_FIN;
+    const int J = j0 / SY_T;
+    const int jj = j0 - J * SY_T + lane;
+    const int nT = div_up(n, SY_T);
+    const int nsrc = nT + 1;  // J + 1 row parts, nT - J column parts
+    // SY_FACC independent sums keep that many loads in flight per wave; they
+    // are added in a fixed order at the end
+    double acc[SY_FACC];
+#pragma unroll
+    for (int q = 0; q < SY_FACC; ++q) acc[q] = 0.0;
+    for (int s0 = w; s0 < nsrc; s0 += SY_FWAVES * SY_FACC) {
+#pragma unroll
+        for (int q = 0; q < SY_FACC; ++q) {
+            const int src = s0 + q * SY_FWAVES;
+            if (src < nsrc) {
+                size_t off;
+                if (src <= J) {
+                    off = ((size_t)J * (J + 1) / 2 + src) * 2 * SY_T + jj;
+                } else {
+                    const int Ib = src - 1;  // tiles (Ib, J), Ib = J .. nT - 1
+                    off = (((size_t)Ib * (Ib + 1) / 2 + J) * 2 + 1) * SY_T + jj;
+                }
+                acc[q] += W[off];
+            }
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < SY_FACC; ++q) s += acc[q];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < SY_FWAVES; ++q) v += red[q][lane];
+        const int j = j0 + lane;
+        double contrib = 0.0;
+        if (j < n) {
+            y[j] = v;
+            if (p) contrib = p[j] * v;
+        }
+        if (partial) {
+            const double tsum = wave_sum(contrib);
+            if (lane == 0) partial[blockIdx.x] = tsum;
+        }
+    }
+}
+
+int symv_finish_blocks(int n) { return div_up(n, SY_FIN); }
+
+hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
+                       double *W, const State *st, const double *p, double *partial,
+                       hipStream_t s) {
+    const int nT = div_up(n, SY_T), nTf = n / SY_T;
+    const int n_interior = nTf * (nTf - 1) / 2;
+    const int n_special = nT + (nT > nTf ? nT - 1 : 0);
+    if (n_interior > 0) symv_interior_kernel<<<n_interior, SY_NT, 0, s>>>(n, lda, A, x, W, st);
+    symv_special_kernel<<<n_special, SY_NT, 0, s>>>(n, lda, A, x, W, st);
+    symv_finish_kernel<<<symv_finish_blocks(n), SY_FWAVES * WAVE, 0, s>>>(n, W, y, p, partial, st);
+    return hipGetLastError();
+}
+
+}  // namespace ks

@@ -41,7 +41,8 @@ def _check_matrix(A: torch.Tensor) -> int:
 def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float = 1e-10,
                 max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
                 inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
-                timing: bool = False, nrhs: int = 1, stop_backward: bool = False) -> N.KsParams:
+                timing: bool = False, nrhs: int = 1, stop_backward: bool = False,
+                symmetric: bool = False) -> N.KsParams:
     p = N.KsParams()
     N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
     p.lda = int(lda if lda is not None else n)
@@ -53,7 +54,8 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
     p.inner_tol = float(inner_tol)
     p.max_outer = int(max_outer)
     p.poll_every = int(poll_every)
-    p.flags = (N.KS_FLAG_TIMING if timing else 0) | (N.KS_FLAG_STOP_BACKWARD if stop_backward else 0)
+    p.flags = ((N.KS_FLAG_TIMING if timing else 0) | (N.KS_FLAG_STOP_BACKWARD if stop_backward else 0)
+               | (N.KS_FLAG_SYMMETRIC if symmetric else 0))
     p.nrhs = int(nrhs)
     return p
 
@@ -241,6 +243,23 @@ def gemv(A: torch.Tensor, v: torch.Tensor, y: torch.Tensor | None = None,
         y = torch.empty(n, dtype=vdt, device=A.device)
     N.check(N.lib().ks_gemv(int(n), int(lda), dt, _ptr(A), _ptr(v), _ptr(y), _stream_handle()),
             "ks_gemv")
+    return y
+
+
+def symv(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
+         n: int | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x for symmetric float64 A, reading only its lower triangle."""
+    if A.dtype != torch.float64:
+        raise TypeError("symv: A must be float64")
+    n = A.shape[0] if n is None else n
+    sz = ctypes.c_size_t(0)
+    N.check(N.lib().ks_symv_workspace_bytes(int(n), ctypes.byref(sz)), "ks_symv_workspace_bytes")
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(sz.value, dtype=torch.uint8, device=A.device)
+    if y is None:
+        y = torch.empty(n, dtype=torch.float64, device=A.device)
+    N.check(N.lib().ks_symv(int(n), int(A.stride(0)), _ptr(A), _ptr(x), _ptr(y), _ptr(workspace),
+                            sz.value, _stream_handle()), "ks_symv")
     return y
 
 

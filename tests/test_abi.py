@@ -85,3 +85,29 @@ def test_bicgstab_parameters_on_host():
     p.precision = N.KS_IR_BF16
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == 0
     assert L.ks_params_init(ctypes.byref(p), 10, 3) == N.KS_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_symmetric_flag_and_symv_on_host():
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    sz = ctypes.c_size_t(0)
+    assert L.ks_symv_workspace_bytes(16384, ctypes.byref(sz)) == 0
+    tiles = 128 * 129 // 2                        # 128 x 128 tiles of the lower triangle
+    assert sz.value == tiles * 2 * 128 * 8
+    assert L.ks_symv_workspace_bytes(0, ctypes.byref(sz)) == N.KS_EINVAL
+    assert L.ks_symv(10, 10, None, None, None, None, 0, None) == N.KS_EINVAL
+    p = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(p), 16384, N.KS_CG) == 0
+    base = ctypes.c_size_t(0)
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(base)) == 0
+    p.flags = N.KS_FLAG_SYMMETRIC
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+    assert sz.value >= base.value + tiles * 2 * 128 * 8
+    p.nrhs = 4
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    q = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(q), 100, N.KS_GMRES) == 0
+    q.flags = N.KS_FLAG_SYMMETRIC
+    assert L.ks_workspace_bytes(ctypes.byref(q), ctypes.byref(sz)) == N.KS_EINVAL

@@ -1,0 +1,102 @@
+"""Symmetric product (lower triangle only) on the GPU, through the C ABI:
+the product against the oracle's binary64 product of the full symmetric
+matrix, with NaN stored above the diagonal to show it is never used; CG with
+KS_FLAG_SYMMETRIC against the CG oracle (same bars as the general CG)."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import spd_problem
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 127, 128, 129, 255, 300, 1000, 2049, 4097]
+
+
+def _t(x, device):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("pad", [0, 6])
+def test_symv_matches_full_product(device, n, pad):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    print(f"symv n={n} pad={pad}", flush=True)
+    rng = np.random.default_rng(7 * n + pad)
+    L = np.tril(rng.standard_normal((n, n)))
+    S = L + np.tril(L, -1).T                     # the symmetric matrix
+    lda = n + pad
+    lda += lda % 2
+    stored = np.full((n, lda), np.nan)           # NaN above the diagonal and in the padding
+    stored[:, :n] = np.where(np.tril(np.ones((n, n), dtype=bool)), S, np.nan)
+    x = rng.standard_normal(n)
+    y = krylov.symv(_t(stored, device), _t(x, device), n=n)
+    torch.cuda.synchronize()
+    ref = oracle.matvec(S, x)
+    bound = 2 * n * 2.0 ** -53 * (np.abs(S) @ np.abs(x)) + 1e-300
+    yh = y.cpu().numpy()
+    assert np.all(np.isfinite(yh))
+    assert np.all(np.abs(yh - ref) <= bound)
+
+
+def test_symv_deterministic(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n = 3000
+    rng = np.random.default_rng(5)
+    L = np.tril(rng.standard_normal((n, n)))
+    A = _t(L + np.tril(L, -1).T, device)
+    x = _t(rng.standard_normal(n), device)
+    y1 = krylov.symv(A, x)
+    y2 = krylov.symv(A, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("n,kappa,seed", [(512, 1e3, 0), (1000, 1e4, 1), (2049, 1e4, 2), (257, 1e2, 3)])
+def test_cg_symmetric_matches_oracle(device, n, kappa, seed):
+    from paper_1511_07207_amd import krylov
+
+    print(f"cg symmetric n={n} kappa={kappa}", flush=True)
+    p = spd_problem(n, kappa, seed=seed, config_id=0)
+    xo, io = oracle.cg(p.A, p.b, tol=1e-10, max_iter=10 * n)
+    assert io["status"] == 0
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="cg", tol=1e-10,
+                           max_iter=10 * n, symmetric=True, timing=True)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    m = oracle.metrics(p.A, p.b, x)
+    assert m["rel_res"] <= 1e-10
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    b = io["iters"]
+    tol_it = max(2, int(0.01 * b)) if b < n // 2 else max(3, int(0.05 * b))
+    assert abs(info["iters"] - b) <= tol_it, (info["iters"], b)
+    assert info["gemv_calls"] == info["iters"]
+
+
+def test_cg_symmetric_ir_and_special_cases(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n = 700
+    p = spd_problem(n, 1e3, seed=4, config_id=0)
+    A, b = _t(p.A, device), _t(p.b, device)
+    x, info = krylov.solve(A, b, method="cg", precision="fp32", tol=1e-12, symmetric=True)
+    assert info["status"] == 0
+    assert oracle.metrics(p.A, p.b, x.cpu().numpy())["eta_inf"] <= 1e-12 * (1 + 1e-6)
+    x, info = krylov.solve(A, torch.zeros(n, dtype=torch.float64, device=device),
+                           method="cg", symmetric=True)
+    assert info["status"] == 0 and info["iters"] == 0 and float(x.abs().max()) == 0.0
+    x, info = krylov.solve(A, b, x0=_t(p.x_true, device), method="cg", symmetric=True)
+    assert info["status"] == 0 and info["iters"] == 0
+    # an indefinite matrix breaks CG down with the symmetric product as well
+    x, info = krylov.solve(_t(-p.A, device), b, method="cg", symmetric=True)
+    assert info["status"] == 2
