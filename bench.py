@@ -44,20 +44,35 @@ def _pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def kernel_source_hash() -> str:
+# sources of the two CG products (general GEMV / symmetric lower-triangle product)
+_PRODUCT_SOURCES = {
+    "general": ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"),
+    "symmetric": ("ks_symv.hip", "ks_device.h", "ks_internal.h"),
+}
+_PRODUCT_PROFILE = {"general": "cg_matvec_f64_n{n}_pmc.txt", "symmetric": "symv_f64_n{n}_pmc.txt"}
+
+
+def kernel_source_hash(product: str = "general") -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"):
+    for f in _PRODUCT_SOURCES[product]:
         with open(os.path.join(ROOT, "paper_1511_07207_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(n: int):
-    """HBM bytes per GEMV launch from the committed rocprofv3 PMC summary, or
+def product_bytes(n: int, product: str) -> float:
+    """Algorithmic bytes of one CG product: A (or its lower triangle) once,
+    the input vector once, the output vector once."""
+    a = 8.0 * n * n if product == "general" else 8.0 * n * (n + 1) / 2
+    return a + 2 * 8.0 * n
+
+
+def load_traffic(n: int, product: str = "general"):
+    """HBM bytes per CG product from the committed rocprofv3 PMC summary, or
     None if there is none for this size or the kernel source changed since."""
-    path = os.path.join(PROFILES, f"cg_matvec_f64_n{n}_pmc.txt")
+    path = os.path.join(PROFILES, _PRODUCT_PROFILE[product].format(n=n))
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -65,7 +80,7 @@ def load_traffic(n: int):
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("kernel_hash") != kernel_source_hash():
+    if d.get("kernel_hash") != kernel_source_hash(product):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -229,6 +244,34 @@ def leg_f1(dev, n):
     return out
 
 
+def leg_c2p(dev, n):
+    """The CG solve of the main step with either product: general GEMV (all of
+    A per iteration) and the symmetric lower-triangle product."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import spd_problem
+
+    prob = spd_problem(n, 1e4, seed=0, config_id=1, backend="torch", device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    out = {"n": n, "kappa": 1e4}
+    for prod in ("general", "symmetric"):
+        s = krylov.Solver(prob.A, method="cg", tol=1e-10, timing=True, symmetric=(prod == "symmetric"))
+        s.solve(prob.b, out=x.zero_())
+        lat = []
+        for _ in range(3):
+            (_, info), dt = _timed(lambda: s.solve(prob.b, out=x.zero_()))
+            lat.append(dt * 1e3)
+        out[prod] = {"status": info["status_name"], "iters": info["iters"], "rel_res": info["rel_res"],
+                     "solve_ms": round(statistics.median(lat), 2),
+                     "product_ms": round(info["gemv_ms"] / max(info["gemv_calls"], 1), 4),
+                     "product_gbs_algorithmic": round(product_bytes(n, prod) / (info["gemv_ms"] / max(info["gemv_calls"], 1) * 1e-3) / 1e9, 1)}
+        s.close()
+    out["symmetric_speedup"] = round(out["general"]["solve_ms"] / out["symmetric"]["solve_ms"], 3)
+    del prob, x
+    return out
+
+
 def leg_c4(dev, n):
     """Lockstep CG on 64 right-hand sides (A*P on MFMA)."""
     import torch
@@ -339,12 +382,15 @@ def main():
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,f1",
-                    help="extra measurements after the timed steps (comma list of c1,c3,c4,c5,f1; "
-                         "'none' for the main step only)")
+    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1",
+                    help="extra measurements after the timed steps (comma list of "
+                         "c1,c2p,c3,c4,c5,f1; 'none' for the main step only)")
     ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--cg-product", choices=("symmetric", "general"), default="symmetric",
+                    help="CG product: the symmetric kernel reading the lower triangle of A "
+                         "(KS_FLAG_SYMMETRIC) or the general GEMV")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before timing, copy A once with the library's binary64 copy kernel "
                          "(known bytes: 8 n^2 read + 8 n^2 written) to calibrate HBM counters")
@@ -370,7 +416,8 @@ def main():
     print(f"[bench] generated n={n} systems in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True)
+    sym = args.cg_product == "symmetric"
+    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True, symmetric=sym)
     gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
@@ -420,15 +467,17 @@ def main():
     solves = 2 * args.steps
     value = solves / elapsed
     ms_step = elapsed * 1e3 / args.steps
-    # dominant kernel: the FP64 GEMV of the CG loop, q = A p
+    # dominant kernel: the FP64 product of the CG loop, q = A p (the symmetric
+    # product is two launches: the tiles of the lower triangle, the finishing sum)
     gemv_ms = sum(r[0]["gemv_ms"] for r in recs)
     gemv_calls = sum(r[0]["gemv_calls"] for r in recs)
     gm_gemv_ms = sum(r[1]["gemv_ms"] for r in recs)
     gm_gemv_calls = sum(r[1]["gemv_calls"] for r in recs)
-    bytes_per_launch = 8.0 * n * n + 2 * 8.0 * n   # A once, p in, q out
+    bytes_per_launch = product_bytes(n, args.cg_product)
+    gm_bytes = product_bytes(n, "general")
     avg_ms = gemv_ms / max(gemv_calls, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(n)
+    traffic = load_traffic(n, args.cg_product)
     cg_iters = recs[-1][0]["iters"]
     gm_iters = recs[-1][1]["iters"]
     out = {
@@ -448,11 +497,15 @@ def main():
             "workload": (f"CG on SPD n={n} (Q diag(lambda) Q^T, lambda log-uniform [1,1e4]) + "
                          f"GMRES(30) on D + G/sqrt(n), n={n}; x0=0, tol 1e-10; one of each per step"),
             "n": n, "kappa_spd": 1e4, "restart": 30, "tol": 1e-10, "spd_q": args.spd_form,
+            "cg_product": ("symmetric: lower triangle of A read once per iteration"
+                           if sym else "general: all of A read once per iteration"),
             "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "cg_matvec_kernel<double> (q = A p, p'q partials)",
+            "kernel": ("symv_tile_kernel + symv_finish_kernel "
+                       "(q = A p from the lower triangle, p'q partials)" if sym else
+                       "cg_matvec_kernel<double> (q = A p, p'q partials)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -474,7 +527,7 @@ def main():
                       "backward_err": recs[-1][1]["backward_err"],
                       "p50_ms": round(_pct([r[3] for r in recs], 0.5), 3),
                       "p99_ms": round(_pct([r[3] for r in recs], 0.99), 3),
-                      "gemv_gbs": round(bytes_per_launch / (gm_gemv_ms / max(gm_gemv_calls, 1) * 1e-3) / 1e9, 1)},
+                      "gemv_gbs": round(gm_bytes / (gm_gemv_ms / max(gm_gemv_calls, 1) * 1e-3) / 1e9, 1)},
         },
         "iterations_per_s": round((cg_iters + gm_iters) * args.steps / elapsed, 1),
         "create_ms": round(create_ms, 2),
@@ -505,6 +558,8 @@ def main():
                 legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool)
             elif name == "f1":
                 legs[name] = leg_f1(dev, n)
+            elif name == "c2p":
+                legs[name] = leg_c2p(dev, n)
             else:
                 legs[name] = {"error": "unknown leg"}
         except Exception as e:  # a failing leg is reported, not fatal

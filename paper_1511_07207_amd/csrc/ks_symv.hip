@@ -14,15 +14,13 @@
 // loaded with the rest of the tile (they are inside the matrix) and
 // discarded by a select, so their values never reach the result.
 //
-// Two tile kernels.  The interior tiles (I > J, all rows inside the matrix),
-// nearly all of the bytes, run in a kernel with no checks: A is read through
-// a buffer resource based at the tile row, so a row's address is a scalar
-// offset and the lane's byte offset (the same for every row) is one vector
-// register.  The diagonal tiles, and the last tile row when SY_T does not
-// divide n, run in a second kernel with the masks and bounds checks.  Kept
-// apart, the interior kernel's register count is not raised by the masking
-// code (a kernel's count is the maximum over its paths), which keeps more
-// waves, and so more loads, in flight per compute unit.
+// Tile paths.  Tiles whose rows and columns lie inside the matrix (all but
+// the last tile row when SY_T does not divide n) read A through a buffer
+// resource based at the tile row, so a row's address is a scalar offset and
+// the lane's byte offset (the same for every row) is one vector register;
+// only the ragged last tile row checks bounds.  The diagonal and edge tiles
+// are the first blocks of the launch, so that they overlap with the interior
+// tiles instead of forming a tail.
 //
 // Each wave reads SY_RPW rows of the tile, interleaved with the other waves;
 // one wave instruction loads one 1 KiB tile row (64 lanes x 16 bytes, two
@@ -187,27 +185,18 @@ __device__ __forceinline__ void sy_store(const SyTile &T, double ca0, double ca1
                                           SY_STORE_POLICY);
 }
 
-// Interior tiles: (I, J) with 1 <= I < n / SY_T and J < I, enumerated as
-// b = (I - 1) I / 2 + J.  st != nullptr: return at once when the Krylov loop
-// has stopped.
-__global__ __launch_bounds__(SY_NT) void symv_interior_kernel(int n, int64_t lda,
-                                                              const double *__restrict__ A,
-                                                              const double *__restrict__ x,
-                                                              double *__restrict__ W,
-                                                              const State *st) {
-    __shared__ double rows[SY_T];
-    __shared__ double cs[SY_WAVES][SY_T];
-    if (st && (st->flags & F_STOP)) return;
-    int I, J;
-    sy_tri_ij(blockIdx.x, I, J);
-    I += 1;
-    const SyTile T = sy_setup(n, I, J, x);
+// Rows of one tile from a buffer resource based at the tile row (tiles whose
+// rows and columns all lie inside the matrix): the row offset is a scalar,
+// the lane's byte offset one vector register.
+template <bool DIAG>
+__device__ __forceinline__ void sy_tile_full(const SyTile &T, int64_t lda, const double *__restrict__ A,
+                                             const double *__restrict__ x, double *rows, double &ca0,
+                                             double &ca1) {
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<double *>(A + (int64_t)T.r0 * lda), 0, (int)((int64_t)SY_T * lda * 8),
         SY_RSRC_WORD3);
     const int coff = T.c * 8;
     const double *xi = x + T.r0;  // x_I: read at wave-uniform indices
-    double ca0 = 0.0, ca1 = 0.0;
 #pragma unroll 1
     for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_INT) {
         sy_d2 a[SY_UNR_INT];
@@ -221,29 +210,17 @@ __global__ __launch_bounds__(SY_NT) void symv_interior_kernel(int n, int64_t lda
         }
 #pragma unroll
         for (int u = 0; u < SY_UNR_INT; ++u) xr[u] = xi[sy_row(T.w, k0 + u)];
-        sy_group<SY_UNR_INT, false>(T, k0, a, xr, rows, ca0, ca1);
+        sy_group<SY_UNR_INT, DIAG>(T, k0, a, xr, rows, ca0, ca1);
     }
-    sy_store(T, ca0, ca1, rows, cs, W);
 }
 
-// Diagonal tiles (block b < nT: tile (b, b)) and, when SY_T does not divide
-// n, the off-diagonal tiles of the last tile row (block nT + j: tile
-// (nT - 1, j)); rows and columns at or beyond n are not read.
-__global__ __launch_bounds__(SY_NT) void symv_special_kernel(int n, int64_t lda,
-                                                             const double *__restrict__ A,
-                                                             const double *__restrict__ x,
-                                                             double *__restrict__ W,
-                                                             const State *st) {
-    __shared__ double rows[SY_T];
-    __shared__ double cs[SY_WAVES][SY_T];
-    if (st && (st->flags & F_STOP)) return;
-    const int nT = div_up(n, SY_T);
-    const int b = blockIdx.x;
-    const int I = (b < nT) ? b : nT - 1;
-    const int J = (b < nT) ? b : b - nT;
-    const SyTile T = sy_setup(n, I, J, x);
-    const bool diag = (I == J);
-    double ca0 = 0.0, ca1 = 0.0;
+// The last tile row when SY_T does not divide n: rows and columns at or
+// beyond n are not read.
+__device__ __forceinline__ void sy_tile_edge(const SyTile &T, int n, int64_t lda,
+                                             const double *__restrict__ A,
+                                             const double *__restrict__ x, double *rows, double &ca0,
+                                             double &ca1) {
+    const bool diag = (T.I == T.J);
 #pragma unroll 1
     for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_SPC) {
         sy_d2 a[SY_UNR_SPC];
@@ -261,6 +238,43 @@ __global__ __launch_bounds__(SY_NT) void symv_special_kernel(int n, int64_t lda,
         else
             sy_group<SY_UNR_SPC, false>(T, k0, a, xr, rows, ca0, ca1);
     }
+}
+
+// One block per tile of the lower triangle.  Blocks are ordered so that the
+// few special tiles start first and overlap with the bulk:
+//   b < nT                       diagonal tile (b, b)
+//   nT <= b < nT + ne            (ragged n only) tile (nT - 1, b - nT) of the last tile row
+//   then the interior tiles (I, J), 1 <= I < n / SY_T, J < I, in row order.
+// st != nullptr: return at once when the Krylov loop has stopped.
+__global__ __launch_bounds__(SY_NT) void symv_tile_kernel(int n, int64_t lda,
+                                                          const double *__restrict__ A,
+                                                          const double *__restrict__ x,
+                                                          double *__restrict__ W, const State *st) {
+    __shared__ double rows[SY_T];
+    __shared__ double cs[SY_WAVES][SY_T];
+    if (st && (st->flags & F_STOP)) return;
+    const int nT = div_up(n, SY_T), nTf = n / SY_T;
+    const int ne = (nT > nTf) ? nT - 1 : 0;
+    const int b = blockIdx.x;
+    int I, J;
+    if (b < nT) {
+        I = b;
+        J = b;
+    } else if (b < nT + ne) {
+        I = nT - 1;
+        J = b - nT;
+    } else {
+        sy_tri_ij(b - nT - ne, I, J);
+        I += 1;
+    }
+    const SyTile T = sy_setup(n, I, J, x);
+    double ca0 = 0.0, ca1 = 0.0;
+    if (T.r0 + SY_T > n)
+        sy_tile_edge(T, n, lda, A, x, rows, ca0, ca1);
+    else if (I == J)
+        sy_tile_full<true>(T, lda, A, x, rows, ca0, ca1);
+    else
+        sy_tile_full<false>(T, lda, A, x, rows, ca0, ca1);
     sy_store(T, ca0, ca1, rows, cs, W);
 }
 
@@ -330,11 +344,7 @@ int symv_finish_blocks(int n) { return div_up(n, SY_FIN); }
 hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
                        double *W, const State *st, const double *p, double *partial,
                        hipStream_t s) {
-    const int nT = div_up(n, SY_T), nTf = n / SY_T;
-    const int n_interior = nTf * (nTf - 1) / 2;
-    const int n_special = nT + (nT > nTf ? nT - 1 : 0);
-    if (n_interior > 0) symv_interior_kernel<<<n_interior, SY_NT, 0, s>>>(n, lda, A, x, W, st);
-    symv_special_kernel<<<n_special, SY_NT, 0, s>>>(n, lda, A, x, W, st);
+    symv_tile_kernel<<<sy_tiles(n), SY_NT, 0, s>>>(n, lda, A, x, W, st);
     symv_finish_kernel<<<symv_finish_blocks(n), SY_FWAVES * WAVE, 0, s>>>(n, W, y, p, partial, st);
     return hipGetLastError();
 }
