@@ -233,38 +233,62 @@ hipError_t launch_fill(int n, T *x, T value, hipStream_t s);
 hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipStream_t s);
 
 // ------------------------------------------------------- batched launches
-// One in-flight binary64 solve of the request server.
-struct BatchItem {
-    const double *A;
+// One in-flight solve of the request server: A in TA, vectors in T (binary64
+// solves and refinement outer steps: double/double; inner solves of the
+// mixed-precision requests: float/float or bf16_t/float).
+template <typename TA, typename T>
+struct BatchItemT {
+    const TA *A;
     int64_t lda;
     int n, ldv, m, max_iter;
     double tol;
     int eta;            // stop on the backward error
     int pad;
-    const double *b;
-    double *x;
-    double *resid;      // r (CG) or w (GMRES): the residual kernel's output
-    double *p, *q, *V;  // CG search direction and product; GMRES basis
+    const T *b;
+    T *x;
+    T *resid;           // r (CG) or w (GMRES): the residual kernel's output
+    T *p, *q, *V;       // CG search direction and product; GMRES basis
     State *st;
     Partials P;
     GmArrays ga;
 };
+using BatchItem = BatchItemT<double, double>;
 // A subset of items for one launch: offs[i] = first block of idx[i]'s grid.
-struct BatchSet {
-    const BatchItem *items;
+template <typename Item>
+struct BatchSetT {
+    const Item *items;
     const int *idx;
     const int *offs;
     int count;
 };
+using BatchSet = BatchSetT<BatchItem>;
 enum BatchKernel {
     BK_VEC_STATS, BK_NORM_INF, BK_NORM_INF_FINISH, BK_RESIDUAL, BK_RESIDUAL_FINISH,
     BK_CG_BEGIN, BK_CG_MATVEC, BK_CG_UPDATE, BK_CG_PUPDATE,
     BK_GM_BEGIN, BK_GM_MATVEC, BK_GM_CGS0, BK_GM_CGS1, BK_GM_CGS2, BK_GM_GIVENS,
     BK_GM_ADVANCE, BK_GM_FINISH, BK_GATHER
 };
-// blocks = offs[count]; gate for the residual / finish kernels
-hipError_t batch_launch(BatchKernel kind, const BatchSet &bs, int blocks, int gate, hipStream_t s,
-                        State *staging);
+// blocks = offs[count]; gate for the residual / finish kernels.  BK_NORM_INF
+// and BK_NORM_INF_FINISH exist for binary64 items only.
+template <typename TA, typename T>
+hipError_t batch_launch(BatchKernel kind, const BatchSetT<BatchItemT<TA, T>> &bs, int blocks,
+                        int gate, hipStream_t s, State *staging);
+
+// One refinement step of a mixed-precision request (the vector work between
+// its binary64 outer residual and its inner solve).
+struct IrItem {
+    int n;
+    const double *r64;  // outer residual
+    float *rhs;         // inner right-hand side r / ||r||
+    float *d;           // inner solution (correction)
+    double *x;          // the request's iterate
+    const State *st;    // outer State (st->res = ||r||)
+};
+using IrSet = BatchSetT<IrItem>;
+enum IrKernel { IK_SCALE, IK_ZERO_D, IK_UPDATE };
+hipError_t ir_batch_launch(IrKernel kind, const IrSet &bs, int blocks, hipStream_t s);
+// staging[i] = *d_ptrs[i] (device array of State pointers)
+hipError_t gather_states(const State *const *d_ptrs, int count, State *staging, hipStream_t s);
 
 // ------------------------------------------------ multi-right-hand-side CG
 // n x s column-major blocks with leading dimension ldv; s <= KS_MAX_NRHS.

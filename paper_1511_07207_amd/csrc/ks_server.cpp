@@ -1,27 +1,34 @@
-// Request server: continuous batching of many binary64 CG / GMRES(m) solves.
+// Request server: continuous batching of many CG / GMRES(m) solves, binary64
+// or mixed precision (inner solve on a binary32 / bfloat16 copy of A with
+// binary64 iterative refinement around it).
 //
 // Requests are queued in arrival order and admitted while the memory budget
 // (resident A plus the solve's workspace) and the slot count allow; the queue
 // is served first come, first served (no request overtakes an earlier one).
 // Each call of ks_server_step is one tick:
 //   1. admit from the queue;
-//   2. one batched launch per phase advances every in-flight solve: set-up of
-//      the new ones (||A||_inf, ||b||, r0), (re)starts, then `chunk`
-//      iterations of every CG solve and `chunk` Arnoldi steps of every GMRES
-//      solve, the gated true residuals and the GMRES cycle ends;
-//   3. one gather kernel and one copy bring every solve's State to the host,
-//      which decides per request (continue, restart, new cycle, done) exactly
-//      as the single-solve drivers do, retires finished requests (latency =
+//   2. one batched launch per phase and storage type advances every in-flight
+//      solve: set-up of the new ones (||A||_inf, ||b||, r0), refinement steps
+//      (x += ||r|| d, binary64 residual; r / ||r|| as the next inner
+//      right-hand side), (re)starts, then `chunk` iterations of every CG solve
+//      and `chunk` Arnoldi steps of every GMRES solve -- binary64 and inner
+//      alike -- the gated true residuals and the GMRES cycle ends;
+//   3. one gather kernel and one copy bring the State each request's next
+//      decision needs to the host, which decides per request exactly as the
+//      single-solve drivers do (continue, restart, new cycle, refinement step,
+//      precision promotion, done), retires finished requests (latency =
 //      completion - submission) and frees their memory.
 // Requests that arrive while others run join at the next tick, so their work
 // overlaps on the device with the solves already in flight.  A solve's result
 // does not depend on what else is batched with it: every block of a batched
 // launch runs the same device body on the same data, in the same order, as
-// the single-solve kernel.
+// the single-solve kernel, and the host takes the same decisions in the same
+// order as the single-solve drivers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -83,7 +90,11 @@ class Arena {
     std::map<size_t, size_t> free_;
 };
 
-enum Phase { P_QUEUED, P_INIT, P_BEGIN, P_RUN, P_DONE };
+// Phases of a request.  Binary64 solves (and the binary64 finish of a
+// mixed-precision request after promotion) go INIT -> BEGIN -> RUN ...;
+// mixed-precision requests go INIT -> (check) -> IN_INIT -> IN_BEGIN ->
+// IN_RUN ... -> UPDATE -> (check) -> IN_INIT ...
+enum Phase { P_QUEUED, P_INIT, P_BEGIN, P_RUN, P_IN_INIT, P_IN_BEGIN, P_IN_RUN, P_UPDATE, P_DONE };
 
 struct Req {
     uint64_t ticket = 0;
@@ -97,11 +108,25 @@ struct Req {
     Phase phase = P_QUEUED;
     bool copy_a = false;
     int restarts = 0, cycles = 0;
-    BatchItem item{};
+    BatchItem item{};  // binary64: the solve, or the refinement's outer step
+    // mixed precision
+    bool ir = false;         // refinement request (until promoted to binary64)
+    bool fp64_tail = false;  // promoted: the binary64 solve stopping on the backward error
+    int prec = KS_FP64;      // precision of the next inner solve
+    int outer = 0, bad = 0, total_iters = 0;
+    double eta_prev = INFINITY;
+    bool fb_ready = false;
+    void *A_low = nullptr;
+    float *A_fb = nullptr;
+    BatchItemT<float, float> in32{};
+    BatchItemT<bf16_t, float> in16{};
+    IrItem iri{};
+    State last_outer{};  // the outer State of the last refinement check
     ks_info info{};
 };
 
 constexpr int SERVER_CG_MAX_RESTARTS = 16;
+constexpr int NO_OUTCOME = -100;
 
 }  // namespace
 
@@ -150,22 +175,24 @@ int grow_buffers(ks_server *sv, size_t tab_bytes, size_t nstage) {
     return KS_OK;
 }
 
-// Builds the per-tick table in pinned host memory: the items, then for every
-// (subset, block shape) an index array and a prefix-sum array of block counts.
+// Builds the per-tick table in pinned host memory: item arrays, then for
+// every (subset, block shape) an index array and a prefix-sum array of block
+// counts.  Device addresses mirror the host offsets (one copy per tick).
 class TableBuilder {
    public:
     TableBuilder(char *host, char *dev) : host_(host), dev_(dev) {}
-    size_t reserve_items(int count) {
-        items_off_ = off_;
-        off_ += align_up(sizeof(BatchItem) * (size_t)std::max(count, 1));
-        return items_off_;
+    template <typename T>
+    T *array(int count, const T **dev_ptr) {
+        const size_t off = off_;
+        off_ += align_up(sizeof(T) * (size_t)std::max(count, 1));
+        *dev_ptr = reinterpret_cast<const T *>(dev_ + off);
+        return reinterpret_cast<T *>(host_ + off);
     }
-    BatchItem *items() { return reinterpret_cast<BatchItem *>(host_ + items_off_); }
-    // sizes only (first pass)
+    static size_t array_bytes(size_t elem, int count) { return align_up(elem * (size_t)std::max(count, 1)); }
     static size_t set_bytes(int count) { return 2 * align_up(sizeof(int) * (size_t)(count + 1)); }
-    template <typename F>
-    BatchSet add(const std::vector<int> &idx, F blocks_of, int *total) {
-        BatchSet bs{};
+    template <typename Item, typename F>
+    BatchSetT<Item> add(const Item *dev_items, const std::vector<int> &idx, F blocks_of, int *total) {
+        BatchSetT<Item> bs{};
         const int c = (int)idx.size();
         int *hi = reinterpret_cast<int *>(host_ + off_);
         bs.idx = reinterpret_cast<const int *>(dev_ + off_);
@@ -180,7 +207,7 @@ class TableBuilder {
             acc += blocks_of(idx[i]);
         }
         ho[c] = acc;
-        bs.items = reinterpret_cast<const BatchItem *>(dev_ + items_off_);
+        bs.items = dev_items;
         bs.count = c;
         *total = acc;
         return bs;
@@ -189,13 +216,19 @@ class TableBuilder {
 
    private:
     char *host_, *dev_;
-    size_t off_ = 0, items_off_ = 0;
+    size_t off_ = 0;
 };
 
-void retire(ks_server *sv, Req *r, const State &h, int status) {
-    r->info.status = status;
-    r->info.iters = h.iters;
-    r->info.restarts = r->p.method == KS_CG ? r->restarts : std::max(0, r->cycles - 1);
+// Inner solves of one storage type: the subsets and their block counts.
+template <typename TA>
+struct InnerSets {
+    using Set = BatchSetT<BatchItemT<TA, float>>;
+    Set init_g, init_1, cgb, gmb, cg_g, cg_v, cg_1, gm_g, gm_c, gm_v, gm_1;
+    int n_init_g = 0, n_init_1 = 0, n_cgb = 0, n_gmb = 0, n_cg_g = 0, n_cg_v = 0, n_cg_1 = 0, n_gm_g = 0,
+        n_gm_c = 0, n_gm_v = 0, n_gm_1 = 0;
+};
+
+void finish_metrics(Req *r, const State &h) {
     if (h.bnorm > 0.0 && std::isfinite(h.bnorm)) {
         const double den = h.anorm_inf * h.xinf + h.binf;
         r->info.rel_res = h.res / h.bnorm;
@@ -204,12 +237,159 @@ void retire(ks_server *sv, Req *r, const State &h, int status) {
         r->info.rel_res = 0.0;
         r->info.backward_err = 0.0;
     }
+}
+
+// h: the binary64 State the outcome is read from (residual of the returned x)
+void retire(ks_server *sv, Req *r, const State &h, int status, int iters) {
+    r->info.status = status;
+    r->info.iters = iters;
+    if (r->p.precision != KS_FP64)
+        r->info.restarts = 0;  // as the single-solve refinement driver reports
+    else
+        r->info.restarts = r->p.method == KS_CG ? r->restarts : std::max(0, r->cycles - 1);
+    finish_metrics(r, h);
     r->info.elapsed_ms = now_ms() - r->t_submit;
-    r->info.precision_used = KS_FP64;
+    r->info.outer_iters = r->outer;
+    r->info.precision_used = r->prec;
     r->phase = P_DONE;
     sv->arena.release(r->ws_off, r->ws_bytes);
     sv->in_use -= r->footprint;
     sv->finished.push_back(r);
+}
+
+// Pointers of a request's inner solve (the vectors of the binary32 region of
+// its workspace; A_low, or the binary32 copy after a promotion from
+// bfloat16), and of its refinement steps.
+void setup_inner(Req *r, const Carved &c) {
+    const Layout &L = r->L;
+    auto vec32 = [&](int i) { return c.v32 + (size_t)i * L.ldv; };
+    auto fill = [&](auto &it) {
+        it.lda = L.lda_low;
+        it.n = r->p.n;
+        it.ldv = L.ldv;
+        it.m = L.m;
+        it.max_iter = r->p.max_iter;
+        it.tol = r->p.inner_tol;
+        it.eta = 0;
+        it.b = vec32(0);
+        it.x = vec32(1);
+        it.resid = vec32(2);
+        if (r->p.method == KS_CG) {
+            it.p = vec32(3);
+            it.q = vec32(4);
+            it.V = nullptr;
+        } else {
+            it.V = vec32(3);
+            it.p = it.q = nullptr;
+        }
+        it.st = c.st + 1;
+        it.P = c.P;
+        it.ga = c.ga;
+    };
+    fill(r->in32);
+    fill(r->in16);
+    r->in16.A = (const bf16_t *)r->A_low;
+    r->in32.A = (r->p.precision == KS_IR_BF16) ? r->A_fb : (const float *)r->A_low;
+    r->iri.n = r->p.n;
+    r->iri.r64 = c.v64 + (size_t)(L.nv64 - 1) * L.ldv;
+    r->iri.rhs = vec32(0);
+    r->iri.d = vec32(1);
+    r->iri.x = r->x;
+    r->iri.st = c.st;
+}
+
+// Switch a refinement request to its binary64 finish: the plain solve from
+// the current x, stopping on the backward error (as the single-solve driver).
+void to_fp64_tail(Req *r, const Carved &c) {
+    r->ir = false;
+    r->fp64_tail = true;
+    BatchItem &it = r->item;
+    it.tol = r->p.tol;
+    it.eta = 1;
+    it.max_iter = std::max(1, r->p.max_iter);
+    const int ldv = r->L.ldv;
+    if (r->p.method == KS_CG) {
+        it.resid = c.v64;
+        it.p = c.v64 + ldv;
+        it.q = c.v64 + 2 * (size_t)ldv;
+        it.V = nullptr;
+    } else {
+        it.resid = c.v64;
+        it.V = c.v64 + ldv;
+        it.p = it.q = nullptr;
+    }
+    r->restarts = 0;
+    r->cycles = 0;
+    r->phase = P_INIT;
+}
+
+// The refinement check at the head of each outer step (the loop head of the
+// single-solve refinement driver), on the outer State h.  Returns a status to
+// retire with, or NO_OUTCOME to go on (the next phase is set).
+int ir_check(ks_server *sv, Req *r, const State &h) {
+    r->last_outer = h;
+    const double den = h.anorm_inf * h.xinf + h.binf;
+    const double eta = den > 0.0 ? h.resinf / den : h.resinf;
+    if (!std::isfinite(eta) || (h.flags & F_TRUE_NONFIN)) return KS_NONFINITE;
+    if (eta <= r->p.tol) return KS_OK;
+    if (r->outer >= r->p.max_outer) return KS_STAGNATED;
+    if (eta > 0.5 * r->eta_prev) {
+        if (++r->bad >= 2 && r->prec != KS_FP64) {
+            r->prec = (r->prec == KS_IR_BF16) ? KS_IR_FP32 : KS_FP64;
+            r->bad = 0;
+        }
+    } else {
+        r->bad = 0;
+    }
+    r->eta_prev = eta;
+    const Carved c = carve(r->L, sv->arena_dev + r->ws_off);
+    if (r->prec == KS_FP64) {
+        to_fp64_tail(r, c);
+        return NO_OUTCOME;
+    }
+    if (r->prec == KS_IR_FP32 && r->p.precision == KS_IR_BF16 && !r->fb_ready) {
+        if (launch_convert(r->p.n, r->item.lda, r->item.A, KS_DT_F32, r->L.lda_low, r->A_fb,
+                           sv->stream) != hipSuccess)
+            return KS_EHIP;
+        r->fb_ready = true;
+    }
+    r->phase = P_IN_INIT;
+    return NO_OUTCOME;
+}
+
+// After an inner solve: count it, then either promote (breakdown) and check
+// again on the same outer State, or take the refinement step.
+int ir_after_inner(ks_server *sv, Req *r, int inner_status, int inner_iters) {
+    r->total_iters += inner_iters;
+    r->outer++;
+    if (inner_status == KS_BREAKDOWN || inner_status == KS_NONFINITE) {
+        r->prec = (r->prec == KS_IR_BF16) ? KS_IR_FP32 : KS_FP64;
+        r->bad = 0;
+        r->eta_prev = INFINITY;
+        return ir_check(sv, r, r->last_outer);
+    }
+    r->phase = P_UPDATE;
+    return NO_OUTCOME;
+}
+
+template <typename TA, typename F1, typename F2>
+void build_inner(TableBuilder &tb, InnerSets<TA> &S, const BatchItemT<TA, float> *dev,
+                 const std::vector<int> &init, const std::vector<int> &cgb, const std::vector<int> &gmb,
+                 const std::vector<int> &cgr, const std::vector<int> &gmr, F1 gsh, F2 vsh,
+                 const std::vector<int> &cgs_blocks_of) {
+    auto one = [](int) { return 1; };
+    auto csh = [&](int i) { return cgs_blocks_of[i]; };
+    S.init_g = tb.add(dev, init, gsh, &S.n_init_g);
+    S.init_1 = tb.add(dev, init, one, &S.n_init_1);
+    S.cgb = tb.add(dev, cgb, vsh, &S.n_cgb);
+    S.gmb = tb.add(dev, gmb, vsh, &S.n_gmb);
+    S.cg_g = tb.add(dev, cgr, gsh, &S.n_cg_g);
+    S.cg_v = tb.add(dev, cgr, vsh, &S.n_cg_v);
+    S.cg_1 = tb.add(dev, cgr, one, &S.n_cg_1);
+    S.gm_g = tb.add(dev, gmr, gsh, &S.n_gm_g);
+    S.gm_c = tb.add(dev, gmr, csh, &S.n_gm_c);
+    S.gm_v = tb.add(dev, gmr, vsh, &S.n_gm_v);
+    S.gm_1 = tb.add(dev, gmr, one, &S.n_gm_1);
 }
 
 }  // namespace
@@ -244,7 +424,8 @@ int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_infli
 int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const double *d_b,
                      double *d_x, uint64_t *ticket) {
     if (!sv || !p || !d_A || !d_b || !d_x || !ticket) return KS_EINVAL;
-    if (!valid_params(p) || p->precision != KS_FP64 || p->nrhs != 1 || p->method == KS_BICGSTAB)
+    if (!valid_params(p) || p->nrhs != 1 || p->method == KS_BICGSTAB ||
+        (p->flags & KS_FLAG_SYMMETRIC))
         return KS_EINVAL;
     if ((uintptr_t)d_b % 16 || (uintptr_t)d_x % 16) return KS_EINVAL;
     Req *r = new (std::nothrow) Req();
@@ -264,6 +445,8 @@ int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const
     r->x = d_x;
     r->ticket = sv->next_ticket++;
     r->t_submit = now_ms();
+    r->ir = p->precision != KS_FP64;
+    r->prec = p->precision;
     sv->queue.push_back(r);
     *ticket = r->ticket;
     return KS_OK;
@@ -271,6 +454,7 @@ int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const
 
 int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     if (!sv) return KS_EINVAL;
+    hipStream_t s = sv->stream;
     // 1. admission, first come first served
     while (!sv->queue.empty() && (int)sv->inflight.size() < sv->max_inflight) {
         Req *r = sv->queue.front();
@@ -279,13 +463,14 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         if (!sv->arena.alloc(r->ws_bytes, &off)) break;
         r->ws_off = off;
         sv->in_use += r->footprint;
-        const Carved c = carve(r->L, sv->arena_dev + off);
+        char *ws = sv->arena_dev + off;
+        const Carved c = carve(r->L, ws);
         BatchItem &it = r->item;
         it.A = r->A;
         it.lda = r->p.lda;
         if (r->copy_a) {
-            double *Ac = (double *)(sv->arena_dev + off + r->L.acopy_off);
-            if (launch_copy_pad(r->p.n, r->p.lda, r->A, r->L.lda_pad, Ac, sv->stream) != hipSuccess)
+            double *Ac = (double *)(ws + r->L.acopy_off);
+            if (launch_copy_pad(r->p.n, r->p.lda, r->A, r->L.lda_pad, Ac, s) != hipSuccess)
                 return KS_EHIP;
             it.A = Ac;
             it.lda = r->L.lda_pad;
@@ -293,23 +478,39 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         it.n = r->p.n;
         it.ldv = r->L.ldv;
         it.m = r->L.m;
-        it.max_iter = r->p.max_iter;
-        it.tol = r->p.tol;
-        it.eta = (r->p.flags & KS_FLAG_STOP_BACKWARD) ? 1 : 0;
         it.b = r->b;
         it.x = r->x;
         it.st = c.st;
         it.P = c.P;
         it.ga = c.ga;
-        if (r->p.method == KS_CG) {
-            it.resid = c.v64;
-            it.p = c.v64 + r->L.ldv;
-            it.q = c.v64 + 2 * (size_t)r->L.ldv;
-            it.V = nullptr;
+        if (!r->ir) {
+            it.max_iter = r->p.max_iter;
+            it.tol = r->p.tol;
+            it.eta = (r->p.flags & KS_FLAG_STOP_BACKWARD) ? 1 : 0;
+            if (r->p.method == KS_CG) {
+                it.resid = c.v64;
+                it.p = c.v64 + r->L.ldv;
+                it.q = c.v64 + 2 * (size_t)r->L.ldv;
+                it.V = nullptr;
+            } else {
+                it.resid = c.v64;
+                it.V = c.v64 + r->L.ldv;
+                it.p = it.q = nullptr;
+            }
         } else {
-            it.resid = c.v64;
-            it.V = c.v64 + r->L.ldv;
-            it.p = it.q = nullptr;
+            // the outer step of the refinement: ||b||, r = b - A x in binary64
+            it.max_iter = std::max(1, r->p.max_iter);
+            it.tol = 1.0;
+            it.eta = 0;
+            it.resid = c.v64 + (size_t)(r->L.nv64 - 1) * r->L.ldv;
+            it.p = it.q = it.V = nullptr;
+            r->A_low = ws + r->L.alow_off;
+            r->A_fb = r->L.afb_bytes ? (float *)(ws + r->L.afb_off) : nullptr;
+            if (launch_convert(r->p.n, it.lda, it.A,
+                               r->p.precision == KS_IR_FP32 ? KS_DT_F32 : KS_DT_BF16, r->L.lda_low,
+                               r->A_low, s) != hipSuccess)
+                return KS_EHIP;
+            setup_inner(r, c);
         }
         r->phase = P_INIT;
         sv->inflight.push_back(r);
@@ -321,81 +522,185 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         if (n_queued) *n_queued = (int32_t)sv->queue.size();
         return KS_OK;
     }
-    // 2. subsets of this tick
-    std::vector<int> init, cg_begin, gm_begin, cg_run, gm_run, all(nf);
+    // 2. subsets of this tick.  Binary64 items: plain solves and refinement
+    // outer steps; inner items by storage type (k = 0 binary32, 1 bfloat16).
+    std::vector<int> init, upd, cg_begin, gm_begin, cg_run, gm_run, in_init_all;
+    std::vector<int> in_init[2], in_cgb[2], in_gmb[2], in_cg[2], in_gm[2];
+    auto tix = [](const Req *r) { return r->prec == KS_IR_BF16 ? 1 : 0; };
     for (int i = 0; i < nf; ++i) {
         const Req *r = sv->inflight[i];
-        all[i] = i;
         const bool cg = r->p.method == KS_CG;
-        if (r->phase == P_INIT) init.push_back(i);
-        if (r->phase == P_BEGIN) (cg ? cg_begin : gm_begin).push_back(i);
-        if (r->phase == P_BEGIN || r->phase == P_RUN) (cg ? cg_run : gm_run).push_back(i);
+        switch (r->phase) {
+            case P_INIT: init.push_back(i); break;
+            case P_BEGIN:
+                (cg ? cg_begin : gm_begin).push_back(i);
+                (cg ? cg_run : gm_run).push_back(i);
+                break;
+            case P_RUN: (cg ? cg_run : gm_run).push_back(i); break;
+            case P_UPDATE: upd.push_back(i); break;
+            case P_IN_INIT:
+                in_init[tix(r)].push_back(i);
+                in_init_all.push_back(i);
+                break;
+            case P_IN_BEGIN:
+                (cg ? in_cgb : in_gmb)[tix(r)].push_back(i);
+                (cg ? in_cg : in_gm)[tix(r)].push_back(i);
+                break;
+            case P_IN_RUN: (cg ? in_cg : in_gm)[tix(r)].push_back(i); break;
+            default: break;
+        }
     }
-    size_t need = align_up(sizeof(BatchItem) * (size_t)nf);
-    need += 4 * TableBuilder::set_bytes((int)init.size());
+    size_t need = TableBuilder::array_bytes(sizeof(BatchItem), nf) +
+                  TableBuilder::array_bytes(sizeof(BatchItemT<float, float>), nf) +
+                  TableBuilder::array_bytes(sizeof(BatchItemT<bf16_t, float>), nf) +
+                  TableBuilder::array_bytes(sizeof(IrItem), nf) +
+                  TableBuilder::array_bytes(sizeof(State *), nf);
+    need += 2 * TableBuilder::set_bytes((int)init.size()) + 3 * TableBuilder::set_bytes((int)upd.size());
     need += TableBuilder::set_bytes((int)cg_begin.size()) + TableBuilder::set_bytes((int)gm_begin.size());
-    need += 4 * TableBuilder::set_bytes((int)cg_run.size()) + 5 * TableBuilder::set_bytes((int)gm_run.size());
-    need += TableBuilder::set_bytes(nf) + 4096;
+    need += 3 * TableBuilder::set_bytes((int)cg_run.size()) + 4 * TableBuilder::set_bytes((int)gm_run.size());
+    need += TableBuilder::set_bytes((int)in_init_all.size());
+    for (int k = 0; k < 2; ++k) {
+        need += 2 * TableBuilder::set_bytes((int)in_init[k].size());
+        need += TableBuilder::set_bytes((int)in_cgb[k].size()) + TableBuilder::set_bytes((int)in_gmb[k].size());
+        need += 3 * TableBuilder::set_bytes((int)in_cg[k].size()) + 4 * TableBuilder::set_bytes((int)in_gm[k].size());
+    }
+    need += 4096;
     int rc = grow_buffers(sv, need, (size_t)nf);
     if (rc) return rc;
     TableBuilder tb(sv->htab, sv->dtab);
-    tb.reserve_items(nf);
-    for (int i = 0; i < nf; ++i) tb.items()[i] = sv->inflight[i]->item;
+    const BatchItem *d64;
+    const BatchItemT<float, float> *d32;
+    const BatchItemT<bf16_t, float> *d16;
+    const IrItem *dir;
+    const State *const *dptrs;
+    BatchItem *h64 = tb.array<BatchItem>(nf, &d64);
+    BatchItemT<float, float> *h32 = tb.array<BatchItemT<float, float>>(nf, &d32);
+    BatchItemT<bf16_t, float> *h16 = tb.array<BatchItemT<bf16_t, float>>(nf, &d16);
+    IrItem *hir = tb.array<IrItem>(nf, &dir);
+    const State **hptrs = tb.array<const State *>(nf, &dptrs);
+    std::vector<int> cgsb(nf);
+    for (int i = 0; i < nf; ++i) {
+        const Req *r = sv->inflight[i];
+        h64[i] = r->item;
+        h32[i] = r->in32;
+        h16[i] = r->in16;
+        hir[i] = r->iri;
+        cgsb[i] = cgs_blocks(r->p.n);
+        // the State the host's next decision reads
+        const bool inner = r->phase == P_IN_INIT || r->phase == P_IN_BEGIN || r->phase == P_IN_RUN;
+        hptrs[i] = inner ? r->in32.st : r->item.st;
+    }
     auto n_of = [&](int i) { return sv->inflight[i]->p.n; };
-    auto gemv_sh = [&](int i) { return gemv_blocks<double>(n_of(i)); };
-    auto vec_sh = [&](int i) { return vec_blocks(n_of(i)); };
-    auto cgs_sh = [&](int i) { return cgs_blocks(n_of(i)); };
-    auto one_sh = [&](int) { return 1; };
-    int nb_init_g, nb_init_1, nb_cgb, nb_gmb, nb_cg_g, nb_cg_v, nb_cg_1, nb_gm_g, nb_gm_c, nb_gm_v,
-        nb_gm_1, nb_all;
-    const BatchSet s_init_g = tb.add(init, gemv_sh, &nb_init_g);
-    const BatchSet s_init_1 = tb.add(init, one_sh, &nb_init_1);
-    const BatchSet s_cgb = tb.add(cg_begin, vec_sh, &nb_cgb);
-    const BatchSet s_gmb = tb.add(gm_begin, vec_sh, &nb_gmb);
-    const BatchSet s_cg_g = tb.add(cg_run, gemv_sh, &nb_cg_g);
-    const BatchSet s_cg_v = tb.add(cg_run, vec_sh, &nb_cg_v);
-    const BatchSet s_cg_1 = tb.add(cg_run, one_sh, &nb_cg_1);
-    const BatchSet s_gm_g = tb.add(gm_run, gemv_sh, &nb_gm_g);
-    const BatchSet s_gm_c = tb.add(gm_run, cgs_sh, &nb_gm_c);
-    const BatchSet s_gm_v = tb.add(gm_run, vec_sh, &nb_gm_v);
-    const BatchSet s_gm_1 = tb.add(gm_run, one_sh, &nb_gm_1);
-    const BatchSet s_all = tb.add(all, one_sh, &nb_all);
-    hipStream_t s = sv->stream;
+    auto g64 = [&](int i) { return gemv_blocks<double>(n_of(i)); };
+    auto g32 = [&](int i) { return gemv_blocks<float>(n_of(i)); };
+    auto g16 = [&](int i) { return gemv_blocks<bf16_t>(n_of(i)); };
+    auto vsh = [&](int i) { return vec_blocks(n_of(i)); };
+    auto csh = [&](int i) { return cgsb[i]; };
+    auto one = [](int) { return 1; };
+    int nb_init_g, nb_init_1, nb_upd_v, nb_upd_g, nb_upd_1, nb_cgb, nb_gmb, nb_cg_g, nb_cg_v, nb_cg_1,
+        nb_gm_g, nb_gm_c, nb_gm_v, nb_gm_1, nb_in_v;
+    const BatchSet s_init_g = tb.add(d64, init, g64, &nb_init_g);
+    const BatchSet s_init_1 = tb.add(d64, init, one, &nb_init_1);
+    const IrSet s_upd_v = tb.add(dir, upd, vsh, &nb_upd_v);
+    const BatchSet s_upd_g = tb.add(d64, upd, g64, &nb_upd_g);
+    const BatchSet s_upd_1 = tb.add(d64, upd, one, &nb_upd_1);
+    const BatchSet s_cgb = tb.add(d64, cg_begin, vsh, &nb_cgb);
+    const BatchSet s_gmb = tb.add(d64, gm_begin, vsh, &nb_gmb);
+    const BatchSet s_cg_g = tb.add(d64, cg_run, g64, &nb_cg_g);
+    const BatchSet s_cg_v = tb.add(d64, cg_run, vsh, &nb_cg_v);
+    const BatchSet s_cg_1 = tb.add(d64, cg_run, one, &nb_cg_1);
+    const BatchSet s_gm_g = tb.add(d64, gm_run, g64, &nb_gm_g);
+    const BatchSet s_gm_c = tb.add(d64, gm_run, csh, &nb_gm_c);
+    const BatchSet s_gm_v = tb.add(d64, gm_run, vsh, &nb_gm_v);
+    const BatchSet s_gm_1 = tb.add(d64, gm_run, one, &nb_gm_1);
+    const IrSet s_in_v = tb.add(dir, in_init_all, vsh, &nb_in_v);
+    InnerSets<float> S32;
+    InnerSets<bf16_t> S16;
+    build_inner(tb, S32, d32, in_init[0], in_cgb[0], in_gmb[0], in_cg[0], in_gm[0], g32, vsh, cgsb);
+    build_inner(tb, S16, d16, in_init[1], in_cgb[1], in_gmb[1], in_cg[1], in_gm[1], g16, vsh, cgsb);
+    if (tb.bytes() > sv->tab_cap) return KS_ENOMEM;
     if (hipMemcpyAsync(sv->dtab, sv->htab, tb.bytes(), hipMemcpyHostToDevice, s) != hipSuccess)
         return KS_EHIP;
-#define BL(kind, set, nb, gate)                                                       \
-    do {                                                                              \
+#define BL(kind, set, nb, gate)                                                             \
+    do {                                                                                    \
         if (batch_launch(kind, set, nb, gate, s, sv->dstage) != hipSuccess) return KS_EHIP; \
     } while (0)
-    // set-up of the newly admitted solves
+#define IL(kind, set, nb)                                                    \
+    do {                                                                     \
+        if (ir_batch_launch(kind, set, nb, s) != hipSuccess) return KS_EHIP; \
+    } while (0)
+    // set-up of the newly admitted solves (and of a binary64 finish after promotion)
     BL(BK_NORM_INF, s_init_g, nb_init_g, 0);
     BL(BK_NORM_INF_FINISH, s_init_1, nb_init_1, 0);
     BL(BK_VEC_STATS, s_init_1, nb_init_1, 0);
     BL(BK_RESIDUAL, s_init_g, nb_init_g, 0);
     BL(BK_RESIDUAL_FINISH, s_init_1, nb_init_1, 0);
+    // refinement steps: x += ||r|| d, then the binary64 residual
+    IL(IK_UPDATE, s_upd_v, nb_upd_v);
+    BL(BK_RESIDUAL, s_upd_g, nb_upd_g, 0);
+    BL(BK_RESIDUAL_FINISH, s_upd_1, nb_upd_1, 0);
+    // inner set-up: rhs = r / ||r||, d = 0, ||rhs||, r_in = rhs - A_low d
+    IL(IK_SCALE, s_in_v, nb_in_v);
+    IL(IK_ZERO_D, s_in_v, nb_in_v);
+    BL(BK_VEC_STATS, S32.init_1, S32.n_init_1, 0);
+    BL(BK_RESIDUAL, S32.init_g, S32.n_init_g, 0);
+    BL(BK_RESIDUAL_FINISH, S32.init_1, S32.n_init_1, 0);
+    BL(BK_VEC_STATS, S16.init_1, S16.n_init_1, 0);
+    BL(BK_RESIDUAL, S16.init_g, S16.n_init_g, 0);
+    BL(BK_RESIDUAL_FINISH, S16.init_1, S16.n_init_1, 0);
     // (re)starts and new GMRES cycles
     BL(BK_CG_BEGIN, s_cgb, nb_cgb, 0);
     BL(BK_GM_BEGIN, s_gmb, nb_gmb, 0);
+    BL(BK_CG_BEGIN, S32.cgb, S32.n_cgb, 0);
+    BL(BK_GM_BEGIN, S32.gmb, S32.n_gmb, 0);
+    BL(BK_CG_BEGIN, S16.cgb, S16.n_cgb, 0);
+    BL(BK_GM_BEGIN, S16.gmb, S16.n_gmb, 0);
     // iterations of every running solve
     for (int c = 0; c < sv->chunk; ++c) {
         BL(BK_CG_MATVEC, s_cg_g, nb_cg_g, 0);
+        BL(BK_CG_MATVEC, S32.cg_g, S32.n_cg_g, 0);
+        BL(BK_CG_MATVEC, S16.cg_g, S16.n_cg_g, 0);
         BL(BK_CG_UPDATE, s_cg_v, nb_cg_v, 0);
+        BL(BK_CG_UPDATE, S32.cg_v, S32.n_cg_v, 0);
+        BL(BK_CG_UPDATE, S16.cg_v, S16.n_cg_v, 0);
         BL(BK_CG_PUPDATE, s_cg_v, nb_cg_v, 0);
+        BL(BK_CG_PUPDATE, S32.cg_v, S32.n_cg_v, 0);
+        BL(BK_CG_PUPDATE, S16.cg_v, S16.n_cg_v, 0);
         BL(BK_GM_MATVEC, s_gm_g, nb_gm_g, 0);
+        BL(BK_GM_MATVEC, S32.gm_g, S32.n_gm_g, 0);
+        BL(BK_GM_MATVEC, S16.gm_g, S16.n_gm_g, 0);
         BL(BK_GM_CGS0, s_gm_c, nb_gm_c, 0);
+        BL(BK_GM_CGS0, S32.gm_c, S32.n_gm_c, 0);
+        BL(BK_GM_CGS0, S16.gm_c, S16.n_gm_c, 0);
         BL(BK_GM_CGS1, s_gm_c, nb_gm_c, 0);
+        BL(BK_GM_CGS1, S32.gm_c, S32.n_gm_c, 0);
+        BL(BK_GM_CGS1, S16.gm_c, S16.n_gm_c, 0);
         BL(BK_GM_CGS2, s_gm_c, nb_gm_c, 0);
+        BL(BK_GM_CGS2, S32.gm_c, S32.n_gm_c, 0);
+        BL(BK_GM_CGS2, S16.gm_c, S16.n_gm_c, 0);
         BL(BK_GM_GIVENS, s_gm_v, nb_gm_v, 0);
+        BL(BK_GM_GIVENS, S32.gm_v, S32.n_gm_v, 0);
+        BL(BK_GM_GIVENS, S16.gm_v, S16.n_gm_v, 0);
         BL(BK_GM_ADVANCE, s_gm_1, nb_gm_1, 0);
+        BL(BK_GM_ADVANCE, S32.gm_1, S32.n_gm_1, 0);
+        BL(BK_GM_ADVANCE, S16.gm_1, S16.n_gm_1, 0);
     }
-    // true residual of stopped CG solves; end of finished GMRES cycles
+    // true residual of stopped binary64 CG solves (an inner CG stops on its
+    // recursive residual alone); end of finished GMRES cycles
     BL(BK_RESIDUAL, s_cg_g, nb_cg_g, 1);
     BL(BK_RESIDUAL_FINISH, s_cg_1, nb_cg_1, 1);
     BL(BK_GM_FINISH, s_gm_c, nb_gm_c, 3);
     BL(BK_RESIDUAL, s_gm_g, nb_gm_g, 3);
     BL(BK_RESIDUAL_FINISH, s_gm_1, nb_gm_1, 3);
-    BL(BK_GATHER, s_all, nb_all, 0);
+    BL(BK_GM_FINISH, S32.gm_c, S32.n_gm_c, 3);
+    BL(BK_RESIDUAL, S32.gm_g, S32.n_gm_g, 3);
+    BL(BK_RESIDUAL_FINISH, S32.gm_1, S32.n_gm_1, 3);
+    BL(BK_GM_FINISH, S16.gm_c, S16.n_gm_c, 3);
+    BL(BK_RESIDUAL, S16.gm_g, S16.n_gm_g, 3);
+    BL(BK_RESIDUAL_FINISH, S16.gm_1, S16.n_gm_1, 3);
 #undef BL
+#undef IL
+    if (gather_states(dptrs, nf, sv->dstage, s) != hipSuccess) return KS_EHIP;
     if (hipMemcpyAsync(sv->hstage, sv->dstage, (size_t)nf * sizeof(State), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -409,17 +714,80 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         const State &h = sv->hstage[i];
         const int f = h.flags;
         const bool cg = r->p.method == KS_CG;
-        int done = -100;
-        if (r->phase == P_INIT) {
-            if (h.bnorm == 0.0) {
-                if (launch_fill<double>(r->p.n, r->x, 0.0, sv->stream) != hipSuccess) return KS_EHIP;
+        int done = NO_OUTCOME;
+        State out = h;  // the binary64 State the outcome is read from
+        int iters = h.iters;
+        if (r->ir && (r->phase == P_INIT || r->phase == P_UPDATE)) {
+            // refinement check on the new outer residual
+            if (r->phase == P_INIT && h.bnorm == 0.0) {
+                if (launch_fill<double>(r->p.n, r->x, 0.0, s) != hipSuccess) return KS_EHIP;
                 zero_fill = true;
+                r->last_outer = h;
+                r->last_outer.res = r->last_outer.resinf = 0.0;
+                done = KS_OK;
+            } else {
+                done = ir_check(sv, r, h);
+            }
+            if (done == KS_EHIP) return KS_EHIP;
+            out = r->last_outer;
+            iters = r->total_iters;
+        } else if (r->phase == P_IN_INIT) {
+            // inner solve set up: the loop head of the single-solve drivers
+            int st_in = NO_OUTCOME;
+            if (h.bnorm == 0.0)
+                st_in = KS_OK;
+            else if (f & F_TRUE_NONFIN)
+                st_in = KS_NONFINITE;
+            else if (f & F_TRUE_OK)
+                st_in = KS_OK;
+            else if (h.iters >= r->p.max_iter)
+                st_in = KS_MAXITER;
+            if (st_in != NO_OUTCOME)
+                done = ir_after_inner(sv, r, st_in, h.iters);
+            else
+                r->phase = P_IN_BEGIN;
+            if (done == KS_EHIP) return KS_EHIP;
+            out = r->last_outer;
+            iters = r->total_iters;
+        } else if (r->phase == P_IN_BEGIN || r->phase == P_IN_RUN) {
+            const bool ended = cg ? (f & F_STOP) != 0 : ((f & F_STOP) != 0 || h.kcur >= r->L.m);
+            int st_in = NO_OUTCOME;
+            if (!ended) {
+                r->phase = P_IN_RUN;
+            } else if (cg) {
+                if (f & F_BREAK)
+                    st_in = KS_BREAKDOWN;
+                else if (f & F_NONFIN)
+                    st_in = KS_NONFINITE;
+                else
+                    st_in = (f & F_CONV) ? KS_OK : KS_MAXITER;
+            } else {
+                if (f & F_BREAK)
+                    st_in = KS_BREAKDOWN;
+                else if ((f & F_NONFIN) || (f & F_TRUE_NONFIN))
+                    st_in = KS_NONFINITE;
+                else if (f & F_TRUE_OK)
+                    st_in = KS_OK;
+                else if (h.iters >= r->p.max_iter)
+                    st_in = KS_MAXITER;
+                else
+                    r->phase = P_IN_BEGIN;  // next cycle of the inner GMRES
+            }
+            if (st_in != NO_OUTCOME) done = ir_after_inner(sv, r, st_in, h.iters);
+            if (done == KS_EHIP) return KS_EHIP;
+            out = r->last_outer;
+            iters = r->total_iters;
+        } else if (r->phase == P_INIT) {
+            if (h.bnorm == 0.0) {
+                if (launch_fill<double>(r->p.n, r->x, 0.0, s) != hipSuccess) return KS_EHIP;
+                zero_fill = true;
+                out.res = out.resinf = 0.0;
                 done = KS_OK;
             } else if (f & F_TRUE_NONFIN) {
                 done = KS_NONFINITE;
             } else if (f & F_TRUE_OK) {
                 done = KS_OK;
-            } else if (h.iters >= r->p.max_iter) {
+            } else if (h.iters >= r->item.max_iter) {
                 done = KS_MAXITER;
             } else {
                 r->phase = P_BEGIN;
@@ -436,7 +804,7 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
                     done = KS_NONFINITE;
                 else if (f & F_TRUE_OK)
                     done = KS_OK;
-                else if (h.iters >= r->p.max_iter)
+                else if (h.iters >= r->item.max_iter)
                     done = KS_MAXITER;
                 else if (cg && r->restarts >= SERVER_CG_MAX_RESTARTS)
                     done = KS_STAGNATED;
@@ -446,15 +814,21 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
                 }
             }
         }
-        if (done != -100) {
-            State hs = h;
-            if (r->phase == P_INIT && h.bnorm == 0.0) hs.res = hs.resinf = 0.0;
-            retire(sv, r, hs, done);
+        if (done != NO_OUTCOME && r->fp64_tail) {
+            // binary64 finish of a refinement request: one more outer step;
+            // success is judged on the backward error of the result
+            r->outer++;
+            iters = r->total_iters + h.iters;
+            finish_metrics(r, h);
+            if (r->info.backward_err <= r->p.tol) done = KS_OK;
+        }
+        if (done != NO_OUTCOME) {
+            retire(sv, r, out, done, iters);
         } else {
             keep.push_back(r);
         }
     }
-    if (zero_fill && hipStreamSynchronize(sv->stream) != hipSuccess) return KS_EHIP;
+    if (zero_fill && hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
     sv->inflight.swap(keep);
     if (n_inflight) *n_inflight = (int32_t)sv->inflight.size();
     if (n_queued) *n_queued = (int32_t)sv->queue.size();

@@ -114,35 +114,18 @@ __global__ void convert_kernel(int n, int64_t lda_src, const double *__restrict_
 __global__ __launch_bounds__(VEC_NT) void ir_scale_cast_kernel(int n, const double *__restrict__ r,
                                                                float *__restrict__ r32,
                                                                const State *st) {
-    const double s = st->res;
-    const int base = blockIdx.x * VEC_NT * VEC_EPT + threadIdx.x;
-#pragma unroll
-    for (int e = 0; e < VEC_EPT; ++e) {
-        const int i = base + e * VEC_NT;
-        if (i < n) r32[i] = (float)(r[i] / s);
-    }
+    ir_scale_body(n, r, r32, st, blockIdx.x);
 }
 
 __global__ __launch_bounds__(VEC_NT) void ir_update_kernel(int n, double *__restrict__ x,
                                                            const float *__restrict__ d,
                                                            const double *scale) {
-    const double s = *scale;
-    const int base = blockIdx.x * VEC_NT * VEC_EPT + threadIdx.x;
-#pragma unroll
-    for (int e = 0; e < VEC_EPT; ++e) {
-        const int i = base + e * VEC_NT;
-        if (i < n) x[i] = fma(s, (double)d[i], x[i]);
-    }
+    ir_update_body(n, x, d, scale, blockIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void fill_kernel(int n, T *__restrict__ x, T value) {
-    const int base = blockIdx.x * VEC_NT * VEC_EPT + threadIdx.x;
-#pragma unroll
-    for (int e = 0; e < VEC_EPT; ++e) {
-        const int i = base + e * VEC_NT;
-        if (i < n) x[i] = value;
-    }
+    fill_body<T>(n, x, value, blockIdx.x);
 }
 
 // --------------------------------------------------------- read ceiling

@@ -136,6 +136,42 @@ __device__ __forceinline__ void cg_begin_body(int n, const T *__restrict__ r, T 
     if (bid == 0 && threadIdx.x == 0) st->flags &= ~INNER_FLAGS;
 }
 
+// ------------------------------------------------ refinement and helpers
+// r32 = (float)(r / ||r||) with ||r|| = st->res (the inner right-hand side)
+__device__ __forceinline__ void ir_scale_body(int n, const double *__restrict__ r,
+                                              float *__restrict__ r32, const State *st, int bid) {
+    const double s = st->res;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) r32[i] = (float)(r[i] / s);
+    }
+}
+
+// x += (*scale) (double) d   (the refinement step, scale = ||r|| of the outer residual)
+__device__ __forceinline__ void ir_update_body(int n, double *__restrict__ x,
+                                               const float *__restrict__ d, const double *scale,
+                                               int bid) {
+    const double s = *scale;
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) x[i] = fma(s, (double)d[i], x[i]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_body(int n, T *__restrict__ x, T value, int bid) {
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = base + e * VEC_NT;
+        if (i < n) x[i] = value;
+    }
+}
+
 // ------------------------------------------------------------- BiCGSTAB
 // Start of a pass from the current x: shadow residual r0 = r and p = r (the
 // first search direction of the recurrence with p = v = 0); rho = r0'r is the

@@ -199,7 +199,9 @@ class Server:
         for i in range(k.value):
             t = tickets[i]
             _, _, x = self._live.pop(t)
-            out.append((t, x, infos[i].as_dict()))
+            d = infos[i].as_dict()
+            d["precision_used"] = _PREC_NAMES.get(d["precision_used"], d["precision_used"])
+            out.append((t, x, d))
         return out
 
     def stats(self):

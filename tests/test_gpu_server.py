@@ -152,3 +152,85 @@ def test_server_zero_rhs_and_exact_guess(device):
     assert out[t0][1]["status"] == 0 and out[t0][1]["iters"] == 0
     assert float(out[t0][0].abs().max()) == 0.0
     assert out[t1][1]["status"] == 0 and out[t1][1]["iters"] == 0
+
+
+# ------------------------------------------------ mixed-precision requests
+
+def _ir_cases():
+    # (problem, method kwargs): binary32 and bfloat16 inner solves, CG and
+    # GMRES; the SPD kappa = 1e4 system makes the bfloat16 copy lose definiteness
+    # or stagnate, which promotes it to binary32 (or further)
+    from workloads import nonsym_swept_problem
+
+    out = []
+    out.append((spd_problem(700, 1e2, seed=21, config_id=6), dict(method="cg", precision="fp32")))
+    out.append((spd_problem(513, 1e2, seed=22, config_id=6), dict(method="cg", precision="bf16")))
+    out.append((spd_problem(900, 1e4, seed=23, config_id=6), dict(method="cg", precision="bf16")))
+    out.append((nonsym_problem(800, seed=24, config_id=6), dict(method="gmres", precision="bf16", restart=30)))
+    out.append((nonsym_swept_problem(600, 1e2, seed=25, config_id=6),
+                dict(method="gmres", precision="fp32", restart=20)))
+    out.append((spd_problem(400, 1e6, seed=26, config_id=6), dict(method="cg", precision="bf16", max_outer=6)))
+    return out
+
+
+def test_server_mixed_precision_equals_single_solves(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    cases = _ir_cases()
+    srv = krylov.Server(mem_budget_bytes=8 << 30, max_inflight=64, chunk=16)
+    tickets, data = [], []
+    for p, kw in cases:
+        A, b = _t(p.A, device), _t(p.b, device)
+        kw = dict(kw, tol=1e-12)
+        tickets.append(srv.submit(A, b, **kw))
+        data.append((p, kw, A, b))
+    # binary64 requests in the same mix
+    for i, n in enumerate([300, 1200]):
+        p = spd_problem(n, 1e3, seed=30 + i, config_id=6)
+        A, b = _t(p.A, device), _t(p.b, device)
+        kw = dict(method="cg", tol=1e-12, stop_backward=True)
+        tickets.append(srv.submit(A, b, **kw))
+        data.append((p, kw, A, b))
+    out = _drain(srv)
+    srv.close()
+    promoted = 0
+    for (p, kw, A, b), t in zip(data, tickets):
+        x, info = out[t]
+        xs, inf1 = krylov.solve(A, b, **kw)
+        torch.cuda.synchronize()
+        print(f"server n={p.n} {kw} status={info['status']} iters={info['iters']} "
+              f"outer={info['outer_iters']} prec={info['precision_used']}", flush=True)
+        assert torch.equal(x, xs), (p.n, kw)
+        for key in ("status", "iters", "outer_iters", "precision_used", "restarts"):
+            assert info[key] == inf1[key], (key, info[key], inf1[key])
+        assert info["backward_err"] == inf1["backward_err"]
+        if info["status"] == 0:
+            assert oracle.metrics(p.A, p.b, x.cpu().numpy())["eta_inf"] <= 1e-12 * (1 + 1e-6)
+        if kw.get("precision") and info["precision_used"] != kw["precision"]:
+            promoted += 1
+    assert promoted >= 1   # the ill-conditioned bfloat16 requests were promoted
+
+
+def test_server_mixed_request_alone_equals_in_mix(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    cases = _ir_cases()
+    p, kw = cases[3]
+    A, b = _t(p.A, device), _t(p.b, device)
+    kw = dict(kw, tol=1e-12)
+    alone = krylov.Server(mem_budget_bytes=8 << 30, max_inflight=8)
+    t = alone.submit(A, b, **kw)
+    xa = _drain(alone)[t][0]
+    alone.close()
+    mixed = krylov.Server(mem_budget_bytes=8 << 30, max_inflight=8, chunk=4)
+    ts = []
+    for q, kq in cases:
+        ts.append(mixed.submit(_t(q.A, device), _t(q.b, device), **dict(kq, tol=1e-12)))
+    out = _drain(mixed)
+    mixed.close()
+    torch.cuda.synchronize()
+    assert torch.equal(out[ts[3]][0], xa)
