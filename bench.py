@@ -299,7 +299,10 @@ def leg_c4(dev, n):
 
 
 def leg_c5(dev, count, pool_size, seed=0):
-    """Serving: Poisson arrivals over a pool of resident systems."""
+    """Serving: binary64 against mixed-precision requests at equal accuracy
+    (normwise backward error <= 1e-12), over a pool of resident systems.
+    Saturation throughput of each, then both under the same Poisson arrivals
+    at 0.5x and 0.9x of the binary64 saturation rate (p50 / p99 latency)."""
     import math
 
     import numpy as np
@@ -315,38 +318,54 @@ def leg_c5(dev, count, pool_size, seed=0):
         if i % 2 == 0:
             kap = float(math.exp(rng.uniform(math.log(1e2), math.log(1e5))))
             prob = spd_problem(n, kap, seed=seed, config_id=4, key=(i,), backend="torch", device="cuda")
-            pool.append(("cg", prob, dict(method="cg", tol=1e-10)))
+            pool.append(("cg", prob, kap))
         else:
             prob = nonsym_problem(n, seed=seed, config_id=4, key=(i,), backend="torch", device="cuda")
-            pool.append(("gmres", prob, dict(method="gmres", tol=1e-10, restart=30)))
+            pool.append(("gmres", prob, None))
+
+    def kw_for(kind, kap, mode):
+        kw = dict(method=kind, tol=1e-12)
+        if kind == "gmres":
+            kw["restart"] = 30
+        if mode == "fp64":
+            kw["stop_backward"] = True
+        else:
+            # inner precision: bfloat16 where its copy stays usable (GMRES on
+            # D + G/sqrt(n); SPD up to kappa ~ 3e2), binary32 otherwise
+            kw["precision"] = "bf16" if (kind == "gmres" or kap <= 3e2) else "fp32"
+        return kw
+
     # request i: pool entry, fresh right-hand side b = A x_true
     reqs = []
     g = torch.Generator(device="cuda")
     g.manual_seed(seed * 1000003 + 17)
     order = rng.permutation(np.arange(count) % pool_size)
     for i in range(count):
-        kind, prob, kw = pool[int(order[i])]
+        kind, prob, kap = pool[int(order[i])]
         xt = torch.randn(prob.n, dtype=torch.float64, device=dev, generator=g)
-        reqs.append((prob, kw, prob.A @ xt))
+        reqs.append((kind, prob, kap, prob.A @ xt))
     torch.cuda.synchronize()
 
-    def run(arrivals):
+    def run(arrivals, mode):
         srv = krylov.Server(mem_budget_bytes=64 << 30, max_inflight=1024, chunk=16)
         t0 = time.perf_counter()
         pending = list(range(count))
-        lat, statuses, peak_inflight = [], [], 0
+        lat, statuses, etas, precs, peak_inflight = [], [], [], {}, 0
+        tick_of = {}
         while True:
             now = time.perf_counter() - t0
             while pending and arrivals[pending[0]] <= now:
                 i = pending.pop(0)
-                prob, kw, b = reqs[i]
-                srv.submit(prob.A, b, **kw)
+                kind, prob, kap, b = reqs[i]
+                tick_of[srv.submit(prob.A, b, **kw_for(kind, kap, mode))] = i
             a, q = srv.step()
             peak_inflight = max(peak_inflight, a)
             done_t = time.perf_counter() - t0
             for t, x, info in srv.poll():
-                lat.append(done_t - arrivals[t - 1])
+                lat.append(done_t - arrivals[tick_of[t]])
                 statuses.append(info["status"])
+                etas.append(info["backward_err"])
+                precs[info["precision_used"]] = precs.get(info["precision_used"], 0) + 1
             if not pending and a == 0 and q == 0:
                 break
             if a == 0 and q == 0 and pending:
@@ -360,15 +379,22 @@ def leg_c5(dev, count, pool_size, seed=0):
                 "throughput_req_per_s": round(count / total, 2),
                 "p50_ms": round(_pct(lat_ms, 0.5), 2), "p99_ms": round(_pct(lat_ms, 0.99), 2),
                 "all_ok": all(s == 0 for s in statuses) and len(statuses) == count,
-                "peak_inflight": peak_inflight}
+                "max_backward_err": max(etas) if etas else None,
+                "precision_used": precs, "peak_inflight": peak_inflight}
 
-    sat = run([0.0] * count)
-    out = {"pool": pool_size, "n_range": [256, 8192], "precision": "fp64", "saturation": sat}
-    lam = sat["throughput_req_per_s"]
+    out = {"pool": pool_size, "n_range": [256, 8192], "eta_target": 1e-12}
+    sat64 = run([0.0] * count, "fp64")
+    satmx = run([0.0] * count, "mixed")
+    out["saturation"] = {"fp64": sat64, "mixed": satmx,
+                         "mixed_over_fp64": round(satmx["throughput_req_per_s"]
+                                                  / sat64["throughput_req_per_s"], 3)}
+    lam = sat64["throughput_req_per_s"]
     for frac in (0.5, 0.9):
         gaps = rng.exponential(1.0 / (frac * lam), size=count)
         arr = list(np.cumsum(gaps) - gaps[0])
-        out[f"rate_{frac}"] = dict(run(arr), offered_req_per_s=round(frac * lam, 2))
+        out[f"rate_{frac}_of_fp64_saturation"] = {
+            "offered_req_per_s": round(frac * lam, 2),
+            "fp64": run(arr, "fp64"), "mixed": run(arr, "mixed")}
     return out
 
 
