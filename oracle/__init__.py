@@ -75,6 +75,8 @@ def _load():
         lib.ko_metrics.restype = i
         lib.ko_matvec.argtypes = [i, pd, l, pd, pd]
         lib.ko_matvec.restype = None
+        lib.ko_matvec_rows.argtypes = [i, pd, l, pi, i, pd, pd]
+        lib.ko_matvec_rows.restype = None
         lib.ko_residual.argtypes = [i, pd, l, pd, pd, pd]
         lib.ko_residual.restype = None
         lib.ko_norm_inf_mat.argtypes = [i, pd, l]
@@ -123,6 +125,20 @@ def matvec(A, x) -> np.ndarray:
     x = _vec(x, n)
     y = np.empty(n)
     _load().ko_matvec(n, _pd(A), lda, _pd(x), _pd(y))
+    return y
+
+
+def matvec_rows(A, rows, x) -> np.ndarray:
+    """Rows `rows` of A x (plain left-to-right sums), for sampled checks."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    x = _vec(x, n)
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.intc))
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    y = np.empty(rows.size)
+    _load().ko_matvec_rows(n, _pd(A), lda, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           int(rows.size), _pd(x), _pd(y))
     return y
 
 

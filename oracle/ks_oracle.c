@@ -77,6 +77,18 @@ void ko_matvec(int n, const double *A, long lda, const double *x, double *y) {
     }
 }
 
+/* y[k] = row rows[k] of A times x, k < m (sampled outputs of the product, for
+ * checks at sizes where the whole product is too slow on the CPU) */
+void ko_matvec_rows(int n, const double *A, long lda, const int *rows, int m, const double *x,
+                    double *y) {
+    for (int k = 0; k < m; ++k) {
+        const double *a = A + (long)rows[k] * lda;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += a[j] * x[j];
+        y[k] = s;
+    }
+}
+
 /* r = b - A x */
 void ko_residual(int n, const double *A, long lda, const double *b, const double *x,
                  double *r) {

@@ -1,0 +1,145 @@
+"""Parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark times.
+
+At these sizes the oracle cannot run whole solves in a test (a CPU product at
+n = 16384 reads 2 GiB), so the checks are the two kinds that hold at any size:
+  * sampled outputs of the GPU products (symmetric and general), each within
+    the componentwise rounding bound 2 n u (|A||x|)_i of the oracle's own row
+    sums for 64 sampled rows;
+  * properties of the returned x computed by the oracle on a host copy of A:
+    the true relative residual and the normwise backward error meet the
+    solve's tolerance, and the forward error against x_true is within
+    cond(A) times the residual bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def _sampled_product_check(A_host, x_host, y_gpu, n, seed):
+    rows = np.sort(np.random.default_rng(seed).choice(n, size=64, replace=False))
+    ref = oracle.matvec_rows(A_host, rows, x_host)
+    bound = 2 * n * U * oracle.matvec_rows(np.abs(A_host), rows, np.abs(x_host)) + 1e-300
+    err = np.abs(y_gpu[rows] - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+def test_c2_symmetric_cg_and_products_full_size(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import spd_problem
+
+    n = 16384
+    print(f"C2 SPD n={n}: generating", flush=True)
+    p = spd_problem(n, 1e4, seed=0, config_id=1, backend="torch", device="cuda")
+    A_host = p.A.cpu().numpy()
+    # products: symmetric (lower triangle) and general, on a seeded vector
+    v = torch.from_numpy(np.random.default_rng(1).standard_normal(n)).to(device)
+    ys = krylov.symv(p.A, v).cpu().numpy()
+    yg = krylov.gemv(p.A, v).cpu().numpy()
+    vh = v.cpu().numpy()
+    _sampled_product_check(A_host, vh, ys, n, 2)
+    _sampled_product_check(A_host, vh, yg, n, 3)
+    print("C2 SPD: solving (symmetric product, as timed)", flush=True)
+    x, info = krylov.solve(p.A, p.b, method="cg", tol=1e-10, symmetric=True)
+    assert info["status"] == 0, info
+    xh, bh = x.cpu().numpy(), p.b.cpu().numpy()
+    m = oracle.metrics(A_host, bh, xh)
+    print(f"C2 SPD: iters {info['iters']} rel_res {m['rel_res']:.3e} eta {m['eta_inf']:.3e}", flush=True)
+    assert m["rel_res"] <= 1e-10
+    assert abs(info["rel_res"] - m["rel_res"]) <= 1e-3 * m["rel_res"] + np.sqrt(n) * U
+    xt = p.x_true.cpu().numpy()
+    assert np.linalg.norm(xh - xt) <= 10 * 1e4 * 1e-10 * np.linalg.norm(xt)
+
+
+def test_c2_gmres_full_size(device):
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem
+
+    n = 16384
+    print(f"C2 nonsymmetric n={n}: generating", flush=True)
+    p = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    x, info = krylov.solve(p.A, p.b, method="gmres", restart=30, tol=1e-10)
+    assert info["status"] == 0, info
+    A_host, bh, xh = p.A.cpu().numpy(), p.b.cpu().numpy(), x.cpu().numpy()
+    m = oracle.metrics(A_host, bh, xh)
+    print(f"C2 GMRES: iters {info['iters']} rel_res {m['rel_res']:.3e}", flush=True)
+    assert m["rel_res"] <= 1e-10
+    xt = p.x_true.cpu().numpy()
+    assert np.linalg.norm(xh - xt) <= 10 * 10.0 * 1e-10 * np.linalg.norm(xt)  # cond < 10
+
+
+def test_c3_mixed_precision_full_size(device):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import spd_problem
+
+    n = 32768
+    print(f"C3 SPD n={n}: generating", flush=True)
+    p = spd_problem(n, 1e4, seed=0, config_id=2, backend="torch", device="cuda")
+    x, info = krylov.solve(p.A, p.b, method="cg", precision="fp32", tol=1e-12, max_iter=4 * n)
+    assert info["status"] == 0, info
+    print(f"C3: iters {info['iters']} outer {info['outer_iters']} prec {info['precision_used']}", flush=True)
+    A_host = p.A.cpu().numpy()
+    del p.A
+    torch.cuda.empty_cache()
+    m = oracle.metrics(A_host, p.b.cpu().numpy(), x.cpu().numpy())
+    print(f"C3: eta {m['eta_inf']:.3e}", flush=True)
+    assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+    assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + np.sqrt(n) * U
+
+
+def test_c4_multi_rhs_full_size(device):
+    from paper_1511_07207_amd import krylov
+    from workloads import multi_rhs_problem
+
+    n, s = 16384, 64
+    print(f"C4 n={n} s={s}: generating", flush=True)
+    p = multi_rhs_problem(n, 1e4, s, seed=0, backend="torch", device="cuda")
+    X, info = krylov.solve(p.A, p.b, method="cg", tol=1e-10, nrhs=s)
+    assert info["status"] == 0, info
+    A_host = p.A.cpu().numpy()
+    Xh, Bh, Xt = X.cpu().numpy(), p.b.cpu().numpy(), p.x_true.cpu().numpy()
+    for j in (0, 31, 63):
+        m = oracle.metrics(A_host, Bh[:, j], Xh[:, j])
+        print(f"C4 column {j}: rel_res {m['rel_res']:.3e}", flush=True)
+        assert m["rel_res"] <= 1e-10
+        assert np.linalg.norm(Xh[:, j] - Xt[:, j]) <= 10 * 1e4 * 1e-10 * np.linalg.norm(Xt[:, j])
+
+
+def test_c5_largest_requests_full_size(device):
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem, spd_problem
+
+    n = 8192
+    print(f"C5 n={n}: generating", flush=True)
+    ps = spd_problem(n, 1e5, seed=0, config_id=4, key=(9001,), backend="torch", device="cuda")
+    pn = nonsym_problem(n, seed=0, config_id=4, key=(9002,), backend="torch", device="cuda")
+    srv = krylov.Server(mem_budget_bytes=64 << 30, max_inflight=8)
+    jobs = [(ps, dict(method="cg", tol=1e-12, stop_backward=True)),
+            (ps, dict(method="cg", tol=1e-12, precision="fp32")),
+            (pn, dict(method="gmres", restart=30, tol=1e-12, stop_backward=True)),
+            (pn, dict(method="gmres", restart=30, tol=1e-12, precision="bf16"))]
+    tickets = [srv.submit(p.A, p.b, **kw) for p, kw in jobs]
+    out = {}
+    while True:
+        a, q = srv.step()
+        for t, x, info in srv.poll():
+            out[t] = (x, info)
+        if a == 0 and q == 0:
+            break
+    srv.close()
+    hosts = {id(ps): ps.A.cpu().numpy(), id(pn): pn.A.cpu().numpy()}
+    for (p, kw), t in zip(jobs, tickets):
+        x, info = out[t]
+        assert info["status"] == 0, (kw, info)
+        m = oracle.metrics(hosts[id(p)], p.b.cpu().numpy(), x.cpu().numpy())
+        print(f"C5 {kw}: eta {m['eta_inf']:.3e} prec {info['precision_used']}", flush=True)
+        assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)

@@ -444,3 +444,15 @@ def test_bicgstab_special_cases():
     assert info["status"] == 4
     _, info = oracle.bicgstab(p.A, p.b, tol=1e-14, max_iter=6)
     assert info["status"] == 1 and info["iters"] == 6
+
+
+def test_matvec_rows_is_the_product_restricted():
+    # the sampled-row product is the full product restricted to those rows,
+    # pinned by exact integer arithmetic
+    rng = np.random.default_rng(3)
+    A = rng.integers(-9, 10, size=(37, 37)).astype(float)
+    x = rng.integers(-9, 10, size=37).astype(float)
+    rows = [0, 5, 36, 17, 17]
+    y = oracle.matvec_rows(A, rows, x)
+    exact = [sum(int(A[r, j]) * int(x[j]) for j in range(37)) for r in rows]
+    assert y.tolist() == [float(v) for v in exact]
