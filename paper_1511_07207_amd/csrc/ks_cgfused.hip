@@ -1,0 +1,211 @@
+// Fused conjugate gradient for small n: one launch per iteration.
+//
+// At small n an iteration of the three-kernel CG (product, x/r update,
+// p update) costs three dependent launches of a few microseconds each while
+// moving little data.  Here each launch does a whole iteration: every block
+// forms, redundantly, the O(n) vector quantities it needs -- alpha from the
+// previous product's partials, r_{k+1}, rho', the stop test, beta and
+// p_{k+1} -- writes its own slice of x, r and p, and computes its 8 rows of
+// the next product q = A p with their p'q partials.  The vectors are tiny
+// next to A at these sizes (4 n doubles read per block against 8 n per row).
+//
+// Bitwise the same as the three-kernel path: the product uses the same
+// per-row column order and reduction tree (rows_dot), the p'q partials are
+// formed per pair of rows exactly as the product kernel forms them, and the
+// r'r sum is rebuilt from the same per-1024-element partials in the same
+// order as the update kernels form and reduce them; every update is the
+// same fma.  So ks_solve at small n and the server's batched kernels give
+// identical results.
+//
+// Races: within a launch no block may read what another block writes.  The
+// vectors r, p, q and the partials alternate between two copies (launch k
+// reads copy k % 2 and writes the other), and so do the scalars rho, iters
+// and flags (State::fz_*).  A launch after the stop copies its slot forward
+// so that the last slot is always current.
+#include "ks_gemv_body.h"
+
+namespace ks {
+
+constexpr int FZ_NT = 256;   // threads per block
+constexpr int FZ_ROWS = 8;   // rows of the product per block (4 pairs)
+constexpr int FZ_PAIRS = FZ_ROWS / GemvShape<double>::ROWS;
+static_assert(GemvShape<double>::ROWS == 2, "the p'q partials are formed per pair of rows");
+static_assert(FZ_NT == VEC_NT && FZ_NT == GEMV_NT, "same block shape as the three-kernel path");
+
+// rows row0 .. row0 + FZ_ROWS - 1 of q = A v (v in LDS or global), written to
+// q, and the p'q partial of each pair of rows into pg[row / 2]
+__device__ __forceinline__ void fz_product(int n, int64_t lda, const double *__restrict__ A,
+                                           const double *v, double *__restrict__ q,
+                                           double *__restrict__ pg, int row0) {
+    double acc[FZ_ROWS];
+    rows_dot<double, FZ_ROWS, FZ_NT, 2>(A, lda, n, row0, v, acc);
+    const double out = reduce_rows<double, FZ_ROWS, FZ_NT>(acc);
+    // lanes 0 .. FZ_ROWS - 1 of wave 0 hold the rows
+    if (threadIdx.x < WAVE) {
+        const int lane = threadIdx.x;
+        const int row = row0 + lane;
+        double contrib = 0.0;
+        if (lane < FZ_ROWS && row < n) {
+            q[row] = out;
+            contrib = v[row] * out;
+        }
+#pragma unroll
+        for (int j = 0; j < FZ_PAIRS; ++j) {
+            // the pair's two rows sit in lanes 2j, 2j + 1: summed as the
+            // product kernel sums its pair (lanes 0 and 1) over the wave
+            const bool mine = (lane >> 1) == j;
+            const double t = wave_sum(mine ? contrib : 0.0);
+            const int gb = row0 / 2 + j;
+            if (lane == 0 && 2 * gb < n) pg[gb] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(FZ_NT) void fz_start_kernel(int n, int64_t lda, const double *__restrict__ A,
+                                                         const double *__restrict__ p0,
+                                                         double *__restrict__ q0, State *st,
+                                                         double *__restrict__ pg0) {
+    if (st->flags & F_STOP) return;
+    fz_product(n, lda, A, p0, q0, pg0, blockIdx.x * FZ_ROWS);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->fz_rho[0] = st->rho;
+        st->fz_iters[0] = st->iters;
+        st->fz_flags[0] = st->flags;
+    }
+}
+
+__global__ __launch_bounds__(FZ_NT) void fz_step_kernel(int n, int64_t lda, const double *__restrict__ A,
+                                                        double *__restrict__ x,
+                                                        const double *__restrict__ rc,
+                                                        double *__restrict__ rn,
+                                                        const double *__restrict__ pc,
+                                                        double *__restrict__ pn,
+                                                        const double *__restrict__ qc,
+                                                        double *__restrict__ qn, State *st,
+                                                        const double *__restrict__ pgc,
+                                                        double *__restrict__ pgn, int cur,
+                                                        int max_iter) {
+    __shared__ double pnew[FZ_MAX_N];
+    __shared__ double vpart[FZ_MAX_N / (VEC_NT * VEC_EPT)];
+    __shared__ double sm[FZ_NT / WAVE];
+    const int nxt = 1 - cur;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double rho = st->fz_rho[cur];
+    const int iters = st->fz_iters[cur] + 1;
+    const int flags = st->fz_flags[cur];
+    if (flags & F_STOP) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters - 1;
+            st->fz_flags[nxt] = flags;
+        }
+        return;
+    }
+    // sigma = p'q from the product's partials, as the update kernel reduces them
+    const int ngemv = gemv_blocks<double>(n);
+    const double sigma = reduce_partials_all<FZ_NT>(pgc, ngemv, 1);
+    if (!(finite_d(sigma) && sigma > 0.0)) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters;
+            st->fz_flags[nxt] = flags | F_STOP | (finite_d(sigma) ? F_BREAK : F_NONFIN);
+        }
+        return;
+    }
+    const double a = rho / sigma;
+    const int row0 = blockIdx.x * FZ_ROWS;
+    // x += alpha p and r -= alpha q for the block's own rows
+    if (threadIdx.x < FZ_ROWS) {
+        const int i = row0 + threadIdx.x;
+        if (i < n) {
+            x[i] = fma(a, pc[i], x[i]);
+            rn[i] = fma(-a, qc[i], rc[i]);
+        }
+    }
+    // rho' = r'r over the whole vector, as the update kernel's blocks form
+    // their partials (element base + e * VEC_NT of thread t) and the p-update
+    // kernel sums them
+    const int nvb = vec_blocks(n);
+    for (int vb = 0; vb < nvb; ++vb) {
+        const int base = vb * VEC_NT * VEC_EPT + threadIdx.x;
+        double s2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < VEC_EPT; ++e) {
+            const int i = base + e * VEC_NT;
+            if (i < n) {
+                const double ri = fma(-a, qc[i], rc[i]);
+                s2 += ri * ri;
+            }
+        }
+        const double t = block_sum<FZ_NT>(s2, sm);
+        if (threadIdx.x == 0) vpart[vb] = t;
+        __syncthreads();
+    }
+    const double rho_new = reduce_partials_all<FZ_NT>(vpart, nvb, 1);
+    int stop = 0;
+    if (!finite_d(rho_new))
+        stop = F_NONFIN | F_STOP;
+    else if (sqrt(rho_new) <= st->thresh)
+        stop = F_CONV | F_STOP;
+    else if (iters >= max_iter)
+        stop = F_MAXIT | F_STOP;
+    if (stop) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters;
+            st->fz_flags[nxt] = flags | stop;
+        }
+        return;
+    }
+    const double beta = rho_new / rho;
+    // p' = r' + beta p for the whole vector (the product needs all of it)
+    for (int i = threadIdx.x; i < n; i += FZ_NT) {
+        const double ri = fma(-a, qc[i], rc[i]);
+        pnew[i] = fma(beta, pc[i], ri);
+    }
+    __syncthreads();
+    if (threadIdx.x < FZ_ROWS) {
+        const int i = row0 + threadIdx.x;
+        if (i < n) pn[i] = pnew[i];
+    }
+    fz_product(n, lda, A, pnew, qn, pgn, row0);
+    if (lead) {
+        st->fz_rho[nxt] = rho_new;
+        st->fz_iters[nxt] = iters;
+        st->fz_flags[nxt] = flags;
+    }
+}
+
+__global__ void fz_publish_kernel(State *st, int which) {
+    if (threadIdx.x == 0) {
+        st->rho = st->fz_rho[which];
+        st->iters = st->fz_iters[which];
+        st->flags = st->fz_flags[which];
+    }
+}
+
+static inline int fz_blocks(int n) { return div_up(n, FZ_ROWS); }
+
+hipError_t launch_fz_start(int n, int64_t lda, const double *A, const double *p0, double *q0,
+                           State *st, double *pg0, hipStream_t s) {
+    if (n > FZ_MAX_N) return hipErrorInvalidValue;
+    fz_start_kernel<<<fz_blocks(n), FZ_NT, 0, s>>>(n, lda, A, p0, q0, st, pg0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double *const vec[6],
+                          State *st, double *const pg[2], int cur, int max_iter, hipStream_t s) {
+    if (n > FZ_MAX_N || (cur != 0 && cur != 1)) return hipErrorInvalidValue;
+    const int nxt = 1 - cur;
+    fz_step_kernel<<<fz_blocks(n), FZ_NT, 0, s>>>(n, lda, A, x, vec[cur], vec[nxt], vec[2 + cur],
+                                                  vec[2 + nxt], vec[4 + cur], vec[4 + nxt], st,
+                                                  pg[cur], pg[nxt], cur, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fz_publish(State *st, int which, hipStream_t s) {
+    fz_publish_kernel<<<1, 64, 0, s>>>(st, which);
+    return hipGetLastError();
+}
+
+}  // namespace ks

@@ -47,6 +47,7 @@ struct ks_solver {
     double *v64 = nullptr;
     float *v32 = nullptr;
     double *sy = nullptr;     // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
+    bool fz = false;          // fused small-n binary64 CG (one launch per iteration)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> tev;  // timing event pairs of A*v launches
     int tev_used = 0;
@@ -174,6 +175,35 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
         first = false;
         HIPCHK(launch_cg_begin<T>(n, r, p, st, sm));
         bool done = false;
+        // binary64 at small n: one fused launch per iteration (same arithmetic)
+        bool fused = false;
+        if constexpr (std::is_same<TA, double>::value && std::is_same<T, double>::value)
+            fused = s->fz && eta == 0;
+        if (fused) {
+            if constexpr (std::is_same<TA, double>::value && std::is_same<T, double>::value) {
+                const int ng = gemv_blocks<double>(n);
+                double *const vec[6] = {r, s->vec64(3), p, s->vec64(4), q, s->vec64(5)};
+                double *const pg[2] = {s->P.g, s->P.g + ng};
+                HIPCHK(launch_fz_start(n, lda, A, p, q, st, pg[0], sm));
+                int k = 0;
+                while (!done) {
+                    const int it0 = h->iters;
+                    const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0));
+                    for (int c = 0; c < chunk; ++c, ++k) {
+                        hipEvent_t e0, e1;
+                        if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                        if (e0) HIPCHK(hipEventRecord(e0, sm));
+                        HIPCHK(launch_fz_step(n, lda, A, x, vec, st, pg, k & 1, max_iter, sm));
+                        if (e1) HIPCHK(hipEventRecord(e1, sm));
+                    }
+                    HIPCHK(launch_fz_publish(st, k & 1, sm));
+                    if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
+                    if ((rc = sync_state(s))) return rc;
+                    if ((rc = timed_collect(s, h->iters - it0))) return rc;
+                    done = (h->flags & F_STOP) != 0;
+                }
+            }
+        }
         while (!done) {
             const int it0 = h->iters;
             const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0));
@@ -851,6 +881,8 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
         s->v64 = c.v64;
         s->v32 = c.v32;
         if (L.sy_bytes) s->sy = (double *)(s->ws + L.sy_off);
+        // the layout holds the second copies of r, p, q for the fused CG
+        s->fz = p->method == KS_CG && p->nrhs == 1 && p->n <= FZ_MAX_N && !s->sy && L.nv64 >= 6;
     }
     if (p->nrhs > 1) {
         s->mr64 = (double *)(s->ws + L.mr_off);

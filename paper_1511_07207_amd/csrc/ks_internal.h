@@ -44,7 +44,14 @@ struct alignas(256) State {
     int32_t flags;
     int32_t k_done;            // GMRES: steps in the current cycle
     int32_t kcur;              // GMRES step counter of batched launches
+    // fused small-n CG: per-launch copies of rho, iters and flags, alternating
+    // between two slots so that no block reads a value another block of the
+    // same launch writes
+    double fz_rho[2];
+    int32_t fz_iters[2];
+    int32_t fz_flags[2];
 };
+static_assert(sizeof(State) == 256, "one 256-byte State per solve");
 
 // Per-column scalars of lockstep multi-right-hand-side CG (same rule as State).
 struct ColState {
@@ -210,6 +217,21 @@ int symv_finish_blocks(int n);
 hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
                        double *W, const State *st, const double *p, double *partial,
                        hipStream_t s);
+
+// Fused small-n CG (n <= FZ_MAX_N, binary64, no backward-error stopping): one
+// launch per iteration instead of three, bitwise the same arithmetic.
+//   fz_start: q0 = A p0 with the p'q partials into pg[0]; slot 0 = (rho, iters, flags)
+//   fz_step:  launch k (cur = k % 2) turns the partials of q_k = A p_k into
+//             alpha, x += alpha p_k, r_{k+1}, rho', the stop test, beta,
+//             p_{k+1} and q_{k+1} = A p_{k+1}; slot[1 - cur] for the next launch
+//   fz_publish: slot `which` -> st->rho, iters, flags
+// vec = {r0, r1, p0, p1, q0, q1}, pg = {partials 0, partials 1}
+constexpr int FZ_MAX_N = 4096;
+hipError_t launch_fz_start(int n, int64_t lda, const double *A, const double *p0, double *q0,
+                           State *st, double *pg0, hipStream_t s);
+hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double *const vec[6],
+                          State *st, double *const pg[2], int cur, int max_iter, hipStream_t s);
+hipError_t launch_fz_publish(State *st, int which, hipStream_t s);
 
 // ||A||_inf into st->anorm_inf
 hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,

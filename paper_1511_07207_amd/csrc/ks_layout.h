@@ -85,7 +85,9 @@ inline Layout make_layout(const ks_params *p) {
     // binary64 vectors: CG r, p, q; GMRES w, V(0..m); BiCGSTAB r, r0, p, v, s, t;
     // IR adds the outer residual
     const int nkry = (p->method == KS_CG) ? 3 : (p->method == KS_BICGSTAB) ? 6 : 1 + (L.m + 1);
-    L.nv64 = nkry;
+    // binary64 CG at n <= FZ_MAX_N runs the fused kernel: r, p, q twice
+    const bool fused = p->method == KS_CG && p->nrhs == 1 && n <= FZ_MAX_N;
+    L.nv64 = fused ? 6 : nkry;
     if (p->precision != KS_FP64) L.nv64 += 1;
     L.v64_off = off;
     off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
