@@ -176,6 +176,168 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_kernel(int n, int64_t lda, cons
     }
 }
 
+// The same iteration for n <= FZ_SMALL_N, written for latency: every global
+// load a thread needs (its p'q partials, its elements of r, q and p, the
+// block's own rows of x, p, q, r, and its columns of the block's 8 rows of A)
+// is issued at entry, unconditionally at clamped indices, so one memory round
+// trip precedes the arithmetic instead of four.  The arithmetic and its order
+// are those of fz_step_kernel (and so of the three-kernel path): thread t owns
+// vector elements t + 256 m, and of each row the columns 2t, 2t + 1,
+// 2t + 512, 2t + 513 -- those rows_dot gives it, in the same order (at
+// n <= 1024 there are at most two 512-column chunks, the last possibly
+// ragged).
+constexpr int FZ_SMALL_N = 1024;
+constexpr int FZ_SM_ELEM = FZ_SMALL_N / FZ_NT;       // vector elements per thread (4)
+constexpr int FZ_SM_CH = FZ_SMALL_N / (2 * FZ_NT);   // 512-column chunks (2)
+static_assert(VEC_NT * VEC_EPT >= FZ_SMALL_N, "one r'r partial covers the whole vector");
+static_assert(FZ_SMALL_N / GemvShape<double>::ROWS <= 2 * FZ_NT, "two p'q partials per thread");
+
+__global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
+    int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x,
+    const double *__restrict__ rc, double *__restrict__ rn, const double *__restrict__ pc,
+    double *__restrict__ pn, const double *__restrict__ qc, double *__restrict__ qn, State *st,
+    const double *__restrict__ pgc, double *__restrict__ pgn, int cur, int max_iter) {
+    __shared__ double pnew[FZ_SMALL_N];
+    __shared__ double sm[FZ_NT / WAVE];
+    __shared__ double bc;
+    const int nxt = 1 - cur;
+    const int t = threadIdx.x;
+    const bool lead = blockIdx.x == 0 && t == 0;
+    const int row0 = blockIdx.x * FZ_ROWS;
+    const int ngemv = gemv_blocks<double>(n);
+    // ---- all loads first
+    const double pg0 = pgc[min(t, ngemv - 1)];
+    const double pg1 = pgc[min(t + FZ_NT, ngemv - 1)];
+    double qv[FZ_SM_ELEM], rv[FZ_SM_ELEM], pv[FZ_SM_ELEM];
+#pragma unroll
+    for (int m = 0; m < FZ_SM_ELEM; ++m) {
+        const int i = min(t + m * FZ_NT, n - 1);
+        qv[m] = qc[i];
+        rv[m] = rc[i];
+        pv[m] = pc[i];
+    }
+    const int io = min(row0 + (t & (FZ_ROWS - 1)), n - 1);  // own row of threads t < FZ_ROWS
+    const double xo = x[io], po = pc[io], qo = qc[io], ro = rc[io];
+    double av[FZ_ROWS][FZ_SM_CH][2];
+#pragma unroll
+    for (int r = 0; r < FZ_ROWS; ++r) {
+        const double *rowp = A + (int64_t)min(row0 + r, n - 1) * lda;
+#pragma unroll
+        for (int ch = 0; ch < FZ_SM_CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                av[r][ch][e] = rowp[min(2 * t + ch * 2 * FZ_NT + e, n - 1)];
+    }
+    // ---- sigma, summed as reduce_partials_all sums the partials
+    double sg = 0.0;
+    if (t < ngemv) sg += pg0;
+    if (t + FZ_NT < ngemv) sg += pg1;
+    sg = block_sum<FZ_NT>(sg, sm);
+    if (t == 0) bc = sg;
+    __syncthreads();
+    // the stop test comes after the barrier so that no load above is deferred
+    // behind it; a launch after the stop only copies its slot forward
+    const double rho = st->fz_rho[cur];
+    const int iters = st->fz_iters[cur] + 1;
+    const int flags = st->fz_flags[cur];
+    if (flags & F_STOP) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters - 1;
+            st->fz_flags[nxt] = flags;
+        }
+        return;
+    }
+    const double sigma = bc;
+    if (!(finite_d(sigma) && sigma > 0.0)) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters;
+            st->fz_flags[nxt] = flags | F_STOP | (finite_d(sigma) ? F_BREAK : F_NONFIN);
+        }
+        return;
+    }
+    const double a = rho / sigma;
+    // ---- r' and r'r (one update-kernel partial holds the whole vector, its
+    // thread t summing elements t + 256 e in order of e)
+    double rr[FZ_SM_ELEM];
+    double s2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < FZ_SM_ELEM; ++m) {
+        rr[m] = fma(-a, qv[m], rv[m]);
+        if (t + m * FZ_NT < n) s2 += rr[m] * rr[m];
+    }
+    if (t < FZ_ROWS && row0 + t < n) {
+        x[io] = fma(a, po, xo);
+        rn[io] = fma(-a, qo, ro);
+    }
+    s2 = block_sum<FZ_NT>(s2, sm);
+    __syncthreads();  // every thread has read bc
+    if (t == 0) bc = s2;
+    __syncthreads();
+    // the sum over the single partial returns it unchanged (r'r >= 0)
+    const double rho_new = bc;
+    int stop = 0;
+    if (!finite_d(rho_new))
+        stop = F_NONFIN | F_STOP;
+    else if (sqrt(rho_new) <= st->thresh)
+        stop = F_CONV | F_STOP;
+    else if (iters >= max_iter)
+        stop = F_MAXIT | F_STOP;
+    if (stop) {
+        if (lead) {
+            st->fz_rho[nxt] = rho;
+            st->fz_iters[nxt] = iters;
+            st->fz_flags[nxt] = flags | stop;
+        }
+        return;
+    }
+    const double beta = rho_new / rho;
+#pragma unroll
+    for (int m = 0; m < FZ_SM_ELEM; ++m) {
+        const int i = t + m * FZ_NT;
+        if (i < n) pnew[i] = fma(beta, pv[m], rr[m]);
+    }
+    __syncthreads();
+    if (t < FZ_ROWS && row0 + t < n) pn[io] = pnew[io];
+    // ---- q' = A p' for the block's rows, each row's columns in rows_dot's order
+    double acc[FZ_ROWS];
+#pragma unroll
+    for (int r = 0; r < FZ_ROWS; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < FZ_SM_CH; ++ch)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = 2 * t + ch * 2 * FZ_NT + e;
+            if (c < n) {
+                const double ve = pnew[c];
+#pragma unroll
+                for (int r = 0; r < FZ_ROWS; ++r) acc[r] = fma(av[r][ch][e], ve, acc[r]);
+            }
+        }
+    const double out = reduce_rows<double, FZ_ROWS, FZ_NT>(acc);
+    if (t < WAVE) {
+        const int row = row0 + t;
+        double contrib = 0.0;
+        if (t < FZ_ROWS && row < n) {
+            qn[row] = out;
+            contrib = pnew[row] * out;
+        }
+#pragma unroll
+        for (int j = 0; j < FZ_PAIRS; ++j) {
+            const bool mine = (t >> 1) == j;
+            const double ts = wave_sum(mine ? contrib : 0.0);
+            const int gb = row0 / 2 + j;
+            if (t == 0 && 2 * gb < n) pgn[gb] = ts;
+        }
+    }
+    if (lead) {
+        st->fz_rho[nxt] = rho_new;
+        st->fz_iters[nxt] = iters;
+        st->fz_flags[nxt] = flags;
+    }
+}
+
 __global__ void fz_publish_kernel(State *st, int which) {
     if (threadIdx.x == 0) {
         st->rho = st->fz_rho[which];
@@ -197,9 +359,15 @@ hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double
                           State *st, double *const pg[2], int cur, int max_iter, hipStream_t s) {
     if (n > FZ_MAX_N || (cur != 0 && cur != 1)) return hipErrorInvalidValue;
     const int nxt = 1 - cur;
-    fz_step_kernel<<<fz_blocks(n), FZ_NT, 0, s>>>(n, lda, A, x, vec[cur], vec[nxt], vec[2 + cur],
-                                                  vec[2 + nxt], vec[4 + cur], vec[4 + nxt], st,
-                                                  pg[cur], pg[nxt], cur, max_iter);
+    if (n <= FZ_SMALL_N)
+        fz_step_small_kernel<<<fz_blocks(n), FZ_NT, 0, s>>>(n, lda, A, x, vec[cur], vec[nxt],
+                                                            vec[2 + cur], vec[2 + nxt], vec[4 + cur],
+                                                            vec[4 + nxt], st, pg[cur], pg[nxt], cur,
+                                                            max_iter);
+    else
+        fz_step_kernel<<<fz_blocks(n), FZ_NT, 0, s>>>(n, lda, A, x, vec[cur], vec[nxt], vec[2 + cur],
+                                                      vec[2 + nxt], vec[4 + cur], vec[4 + nxt], st,
+                                                      pg[cur], pg[nxt], cur, max_iter);
     return hipGetLastError();
 }
 
