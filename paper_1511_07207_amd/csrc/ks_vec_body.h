@@ -47,8 +47,21 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
                                                int nsigma, double *__restrict__ prho, int bid,
                                                int nblk) {
     __shared__ double sm[VEC_NT / WAVE];
-    if (st->flags & F_STOP) return;
+    // the vectors are loaded before the partials are reduced and the stop
+    // flag is tested after that barrier, so that the loads overlap with the
+    // reduction's round trip (a launch after the stop loads and discards them)
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+    T xv[VEC_EPT], rv[VEC_EPT], pv[VEC_EPT], qv[VEC_EPT];
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = min(base + e * VEC_NT, n - 1);
+        xv[e] = x[i];
+        rv[e] = r[i];
+        pv[e] = p[i];
+        qv[e] = q[i];
+    }
     const double sigma = reduce_partials_all<VEC_NT>(psigma, nsigma, 1);
+    if (st->flags & F_STOP) return;
     const double rho = st->rho;
     const bool ok = finite_d(sigma) && sigma > 0.0;
     if (bid == 0 && threadIdx.x == 0) {
@@ -64,15 +77,14 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
     }
     if (!ok) return;
     const T a = (T)(rho / sigma);
-    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
     double s2 = 0.0, xm = 0.0;
 #pragma unroll
     for (int e = 0; e < VEC_EPT; ++e) {
         const int i = base + e * VEC_NT;
         if (i < n) {
-            const T xi = fma(a, p[i], x[i]);
+            const T xi = fma(a, pv[e], xv[e]);
             x[i] = xi;
-            const T ri = fma(-a, q[i], r[i]);
+            const T ri = fma(-a, qv[e], rv[e]);
             r[i] = ri;
             s2 += (double)ri * (double)ri;
             xm = fmax(xm, finite_d((double)xi) ? fabs((double)xi) : INFINITY);
@@ -93,8 +105,18 @@ template <typename T>
 __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, T *__restrict__ p,
                                                 State *st, const double *__restrict__ prho, int nrho,
                                                 int max_iter, int bid) {
-    if (st->flags & F_STOP) return;
+    // r and p are loaded before the partials are reduced, the stop flag
+    // tested after that barrier (as in the update kernel)
+    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
+    T rv[VEC_EPT], pv[VEC_EPT];
+#pragma unroll
+    for (int e = 0; e < VEC_EPT; ++e) {
+        const int i = min(base + e * VEC_NT, n - 1);
+        rv[e] = r[i];
+        pv[e] = p[i];
+    }
     const double rho_new = reduce_partials_all<VEC_NT>(prho, nrho, 1);
+    if (st->flags & F_STOP) return;
     const double xinf = st->eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + nrho, nrho, 1) : 0.0;
     const double rho_prev = st->rho_prev;
     int stop = 0;
@@ -116,11 +138,10 @@ __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, 
     }
     if (stop) return;
     const T bt = (T)beta;
-    const int base = bid * VEC_NT * VEC_EPT + threadIdx.x;
 #pragma unroll
     for (int e = 0; e < VEC_EPT; ++e) {
         const int i = base + e * VEC_NT;
-        if (i < n) p[i] = fma(bt, p[i], r[i]);
+        if (i < n) p[i] = fma(bt, pv[e], rv[e]);
     }
 }
 
