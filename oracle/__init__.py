@@ -65,6 +65,9 @@ def _load():
         lib.ko_gmres.restype = i
         lib.ko_bicgstab.argtypes = [i, pd, l, pd, pd, d, i, pi, pi, pd]
         lib.ko_bicgstab.restype = i
+        for name in ("ko_jacobi", "ko_gauss_seidel"):
+            getattr(lib, name).argtypes = [i, pd, l, pd, pd, d, i, pi, pd]
+            getattr(lib, name).restype = i
         lib.ko_arnoldi.argtypes = [i, pd, l, pd, i, pd, pd]
         lib.ko_arnoldi.restype = i
         lib.ko_lu_factor.argtypes = [i, pd, l, pi]
@@ -222,6 +225,29 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=None):
                              ctypes.byref(it), ctypes.byref(rs), ctypes.byref(rr))
     return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), iters=it.value,
                    restarts=rs.value, rel_res=rr.value)
+
+
+def _stationary(fn, A, b, x0, tol, max_iter):
+    A, lda = _mat(A)
+    n = A.shape[0]
+    b = _vec(b, n)
+    x = np.zeros(n) if x0 is None else _vec(x0, n).copy()
+    max_iter = 20 * n if max_iter is None else int(max_iter)
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = fn(n, _pd(A), lda, _pd(b), _pd(x), float(tol), max_iter, ctypes.byref(it),
+            ctypes.byref(rr))
+    return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), iters=it.value,
+                   rel_res=rr.value)
+
+
+def jacobi(A, b, x0=None, tol=1e-10, max_iter=None):
+    """Jacobi iteration D x(k+1) = b - (L + U) x(k); returns (x, info)."""
+    return _stationary(_load().ko_jacobi, A, b, x0, tol, max_iter)
+
+
+def gauss_seidel(A, b, x0=None, tol=1e-10, max_iter=None):
+    """Gauss-Seidel forward sweeps (D + L) x(k+1) = b - U x(k); returns (x, info)."""
+    return _stationary(_load().ko_gauss_seidel, A, b, x0, tol, max_iter)
 
 
 def arnoldi(A, v0, k):

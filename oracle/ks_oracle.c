@@ -333,6 +333,111 @@ out:
     return status;
 }
 
+/* ------------------------------------------------------- stationary methods
+ *
+ * Jacobi and Gauss-Seidel, the classical stationary iterations the paper
+ * lists in its library beside the Krylov methods (introductory section and
+ * the parallel-implementation section; timed in Tables 1-2).  The paper
+ * defers their definition to the textbooks, so these are the textbook forms
+ * with the splitting A = L + D + U (strictly lower, diagonal, strictly upper):
+ *   Jacobi        D x(k+1) = b - (L + U) x(k)
+ *   Gauss-Seidel  (D + L) x(k+1) = b - U x(k)   (one forward sweep, new values
+ *                                                used as soon as computed)
+ * Both test the true residual of x(k) before forming x(k+1):
+ * ||b - A x(k)|| <= tol ||b|| stops with x(k); `iters` counts the updates
+ * made.  A zero on the diagonal is a breakdown before any update.
+ */
+
+/* shared front end: ||b||, the b = 0 and zero-diagonal cases.  Returns -2 to
+ * go on iterating, else the final status (x, counters set). */
+static int stationary_start(int n, const double *A, long lda, const double *b, double *x,
+                            double *bnorm, int *iters_out, double *rel_res_out) {
+    *bnorm = ko_nrm2(n, b);
+    if (iters_out) *iters_out = 0;
+    if (rel_res_out) *rel_res_out = 0.0;
+    if (!isfinite(*bnorm)) return KO_NONFINITE;
+    if (*bnorm == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        return KO_OK;
+    }
+    for (int i = 0; i < n; ++i)
+        if (A[(long)i * lda + i] == 0.0) return KO_BREAKDOWN;
+    return -2;
+}
+
+int ko_jacobi(int n, const double *A, long lda, const double *b, double *x, double tol,
+              int max_iter, int *iters_out, double *rel_res_out) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || max_iter < 0) return KO_EINVAL;
+    double bnorm;
+    int status = stationary_start(n, A, lda, b, x, &bnorm, iters_out, rel_res_out);
+    if (status != -2) return status;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xn = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r || !xn) {
+        free(r);
+        free(xn);
+        return KO_EINVAL;
+    }
+    int k = 0;
+    double res = 0.0;
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        res = ko_nrm2(n, r);
+        if (!isfinite(res)) { status = KO_NONFINITE; break; }
+        if (res <= tol * bnorm) { status = KO_OK; break; }
+        if (k >= max_iter) { status = KO_MAXITER; break; }
+        /* x(k+1)_i = (b_i - sum_{j != i} a_ij x(k)_j) / a_ii, all from x(k) */
+#pragma omp parallel for schedule(static) if (n >= 256)
+        for (int i = 0; i < n; ++i) {
+            const double *a = A + (long)i * lda;
+            double s = b[i];
+            for (int j = 0; j < n; ++j)
+                if (j != i) s -= a[j] * x[j];
+            xn[i] = s / a[i];
+        }
+        memcpy(x, xn, sizeof(double) * (size_t)n);
+        ++k;
+    }
+    free(r);
+    free(xn);
+    if (iters_out) *iters_out = k;
+    if (rel_res_out) *rel_res_out = res / bnorm;
+    return status;
+}
+
+int ko_gauss_seidel(int n, const double *A, long lda, const double *b, double *x, double tol,
+                    int max_iter, int *iters_out, double *rel_res_out) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || max_iter < 0) return KO_EINVAL;
+    double bnorm;
+    int status = stationary_start(n, A, lda, b, x, &bnorm, iters_out, rel_res_out);
+    if (status != -2) return status;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r) return KO_EINVAL;
+    int k = 0;
+    double res = 0.0;
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        res = ko_nrm2(n, r);
+        if (!isfinite(res)) { status = KO_NONFINITE; break; }
+        if (res <= tol * bnorm) { status = KO_OK; break; }
+        if (k >= max_iter) { status = KO_MAXITER; break; }
+        /* one forward sweep in place: x_j for j < i already holds x(k+1)_j */
+        for (int i = 0; i < n; ++i) {
+            const double *a = A + (long)i * lda;
+            double s = b[i];
+            for (int j = 0; j < n; ++j)
+                if (j != i) s -= a[j] * x[j];
+            x[i] = s / a[i];
+        }
+        ++k;
+    }
+    free(r);
+    if (iters_out) *iters_out = k;
+    if (rel_res_out) *rel_res_out = res / bnorm;
+    return status;
+}
+
+
 /* ---------------------------------------------------------------- GMRES(m)
  *
  * Arnoldi step as the paper prints it: project A v(k) on every v(j), j <= k,

@@ -456,3 +456,156 @@ def test_matvec_rows_is_the_product_restricted():
     y = oracle.matvec_rows(A, rows, x)
     exact = [sum(int(A[r, j]) * int(x[j]) for j in range(37)) for r in rows]
     assert y.tolist() == [float(v) for v in exact]
+
+
+# ---------------------------------------------------- Jacobi / Gauss-Seidel
+# The stationary iterations, pinned by exactness on diagonal and triangular
+# matrices, by SciPy's forward substitution for the sweeps, by exact rational
+# arithmetic for the iterates, and by the two convergence theorems that tell
+# the methods apart (Stein-Rosenberg; Gauss-Seidel on SPD matrices).
+
+def _fr_jacobi_step(A, b, x):
+    n = len(b)
+    return [(b[i] - sum(A[i][j] * x[j] for j in range(n) if j != i)) / A[i][i] for i in range(n)]
+
+
+def _fr_gs_sweep(A, b, x):
+    x = list(x)
+    n = len(b)
+    for i in range(n):
+        x[i] = (b[i] - sum(A[i][j] * x[j] for j in range(n) if j != i)) / A[i][i]
+    return x
+
+
+def _small_int_system(seed, n=5):
+    """Integer, strictly diagonally dominant A and integer b."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-3, 4, size=(n, n)).astype(float)
+    A[np.arange(n), np.arange(n)] = np.abs(A).sum(axis=1) + rng.integers(1, 4, size=n)
+    b = rng.integers(-9, 10, size=n).astype(float)
+    return A, b
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_jacobi_iterates_match_exact_rational_steps(steps):
+    A, b = _small_int_system(11)
+    x, info = oracle.jacobi(A, b, tol=1e-300, max_iter=steps)
+    assert info["status_name"] == "maxiter" and info["iters"] == steps
+    Af = [[Fraction(int(v)) for v in row] for row in A]
+    bf = [Fraction(int(v)) for v in b]
+    xf = [Fraction(0)] * len(b)
+    for _ in range(steps):
+        xf = _fr_jacobi_step(Af, bf, xf)
+    np.testing.assert_allclose(x, [float(v) for v in xf], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_gauss_seidel_iterates_match_exact_rational_sweeps(steps):
+    A, b = _small_int_system(12)
+    x, info = oracle.gauss_seidel(A, b, tol=1e-300, max_iter=steps)
+    assert info["status_name"] == "maxiter" and info["iters"] == steps
+    Af = [[Fraction(int(v)) for v in row] for row in A]
+    bf = [Fraction(int(v)) for v in b]
+    xf = [Fraction(0)] * len(b)
+    for _ in range(steps):
+        xf = _fr_gs_sweep(Af, bf, xf)
+    np.testing.assert_allclose(x, [float(v) for v in xf], rtol=1e-14, atol=0)
+
+
+def test_gauss_seidel_sweeps_are_forward_substitutions():
+    """x1 = tril(A)^{-1} b and x2 = tril(A)^{-1} (b - triu(A, 1) x1) (SciPy)."""
+    from scipy.linalg import solve_triangular
+
+    p = nonsym_problem(300, seed=3, config_id=0)
+    A, b = p.A, p.b
+    x1, _ = oracle.gauss_seidel(A, b, tol=1e-300, max_iter=1)
+    r1 = solve_triangular(np.tril(A), b, lower=True)
+    np.testing.assert_allclose(x1, r1, rtol=1e-12, atol=1e-14 * np.abs(r1).max())
+    x2, _ = oracle.gauss_seidel(A, b, tol=1e-300, max_iter=2)
+    r2 = solve_triangular(np.tril(A), b - np.triu(A, 1) @ r1, lower=True)
+    np.testing.assert_allclose(x2, r2, rtol=1e-12, atol=1e-14 * np.abs(r2).max())
+    # Jacobi's first two steps from zero: b / d, then (b - (A - D) x1) / d
+    d = np.diag(A)
+    j1, _ = oracle.jacobi(A, b, tol=1e-300, max_iter=1)
+    np.testing.assert_array_equal(j1, b / d)  # b_i - 0 = b_i exactly, one division
+    j2, _ = oracle.jacobi(A, b, tol=1e-300, max_iter=2)
+    np.testing.assert_allclose(j2, (b - (A - np.diag(d)) @ (b / d)) / d, rtol=1e-12)
+
+
+def test_stationary_exact_cases():
+    rng = np.random.default_rng(5)
+    n = 40
+    d = rng.uniform(1, 3, n) * rng.choice([-1, 1], n)
+    b = rng.standard_normal(n)
+    # diagonal A: Jacobi and Gauss-Seidel are exact after one update
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        x, info = fn(np.diag(d), b, tol=1e-14)
+        assert info["status_name"] == "ok" and info["iters"] == 1
+        np.testing.assert_array_equal(x, b / d)
+    # lower-triangular A: one Gauss-Seidel sweep is the exact forward solve
+    L = np.tril(rng.standard_normal((n, n)) * 0.1, -1) + np.diag(d)
+    x, info = oracle.gauss_seidel(L, b, tol=1e-12)
+    assert info["status_name"] == "ok" and info["iters"] == 1
+    # exact start and b = 0
+    A, bi = _small_int_system(13)
+    xs = np.linalg.solve(A, bi)
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        x, info = fn(A, A @ xs, x0=xs, tol=1e-12)
+        assert info["iters"] == 0 and info["status_name"] == "ok"
+        x, info = fn(A, np.zeros(5), x0=np.ones(5), tol=1e-12)
+        assert info["iters"] == 0 and info["status_name"] == "ok" and not x.any()
+
+
+def test_stationary_breakdown_and_divergence():
+    A, b = _small_int_system(14)
+    Z = A.copy()
+    Z[2, 2] = 0.0
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        _, info = fn(Z, b, tol=1e-10)
+        assert info["status_name"] == "breakdown" and info["iters"] == 0
+    # [[1, 2], [2, 1]]: Jacobi's iteration matrix has spectral radius 2
+    x, info = oracle.jacobi(np.array([[1.0, 2.0], [2.0, 1.0]]), np.array([1.0, 0.0]),
+                            tol=1e-10, max_iter=40)
+    assert info["status_name"] == "maxiter" and info["rel_res"] > 1e6
+
+
+def test_gauss_seidel_converges_on_spd_where_jacobi_diverges():
+    """SPD with unit diagonal and off-diagonal 0.9: Jacobi's iteration matrix
+    has eigenvalue -1.8, while Gauss-Seidel converges for every SPD matrix."""
+    n = 3
+    A = np.full((n, n), 0.9) + 0.1 * np.eye(n)
+    assert np.linalg.eigvalsh(A).min() > 0
+    b = np.array([1.0, -2.0, 0.5])
+    _, ij = oracle.jacobi(A, b, tol=1e-10, max_iter=200)
+    assert ij["status_name"] == "maxiter"
+    x, ig = oracle.gauss_seidel(A, b, tol=1e-10, max_iter=2000)
+    assert ig["status_name"] == "ok"
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-8)
+
+
+def test_stein_rosenberg_gauss_seidel_faster_on_m_matrix():
+    """For an M-matrix (nonpositive off-diagonals, Jacobi convergent) the
+    Gauss-Seidel spectral radius is the smaller: fewer sweeps to a tolerance."""
+    rng = np.random.default_rng(6)
+    n = 120
+    A = -rng.uniform(0, 1, (n, n)) / n
+    A[np.arange(n), np.arange(n)] = 0.0
+    A[np.arange(n), np.arange(n)] = -A.sum(axis=1) * 1.25
+    b = rng.standard_normal(n)
+    xj, ij = oracle.jacobi(A, b, tol=1e-12)
+    xg, ig = oracle.gauss_seidel(A, b, tol=1e-12)
+    assert ij["status_name"] == "ok" and ig["status_name"] == "ok"
+    assert ig["iters"] < ij["iters"]
+    xs = np.linalg.solve(A, b)
+    for x in (xj, xg):
+        np.testing.assert_allclose(x, xs, rtol=1e-9, atol=1e-9 * np.abs(xs).max())
+
+
+def test_stationary_on_the_nonsymmetric_workload():
+    p = nonsym_problem(256, seed=0, config_id=0)
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        x, info = fn(p.A, p.b, tol=1e-10)
+        assert info["status_name"] == "ok" and info["rel_res"] <= 1e-10
+        m = oracle.metrics(p.A, p.b, x)
+        assert m["rel_res"] <= 1e-10
+        np.testing.assert_allclose(x, p.x_true, rtol=1e-7, atol=1e-8)
