@@ -9,7 +9,13 @@
  *   - BiCGSTAB (the paper's BiCGSTAB listing: two products with A per
  *     iteration, short recurrences, no basis kept) for any nonsingular A,
  * in binary64, or with an inner solve on a binary32 / bfloat16 copy of A and
- * binary64 iterative refinement around it.
+ * binary64 iterative refinement around it; and with the two classical
+ * stationary iterations the paper's library lists beside them (introductory
+ * section, timed in Tables 1-2), in binary64:
+ *   - Jacobi, D x(k+1) = b - (L + U) x(k), and
+ *   - Gauss-Seidel, (D + L) x(k+1) = b - U x(k) (forward sweeps),
+ * with A = L + D + U (strictly lower, diagonal, strictly upper).  They
+ * converge for strictly diagonally dominant A (Gauss-Seidel also for SPD A).
  *
  * The call sequence follows the host flow of the paper's "parallel
  * implementation" section (allocate device memory, copy, pick the launch
@@ -48,7 +54,8 @@ extern "C" {
 #define KS_OK 0
 #define KS_MAXITER 1     /* iteration limit reached before the tolerance        */
 #define KS_BREAKDOWN 2   /* CG: p'Ap <= 0 (A not SPD); GMRES: singular H;
-                            BiCGSTAB: r0'r, r0'v or t't became 0, or omega = 0 */
+                            BiCGSTAB: r0'r, r0'v or t't became 0, or omega = 0;
+                            Jacobi / Gauss-Seidel: a zero on the diagonal      */
 #define KS_STAGNATED 3   /* refinement / restarts stopped making progress       */
 #define KS_NONFINITE 4   /* a NaN or Inf appeared (in b, x0, A or an iterate)    */
 #define KS_EINVAL (-1)   /* bad argument (n <= 0, lda < n, NULL, tol <= 0, ...) */
@@ -61,6 +68,13 @@ extern "C" {
 #define KS_CG 0
 #define KS_GMRES 1
 #define KS_BICGSTAB 2
+/* Stationary methods (binary64 only, nrhs 1).  max_iter counts updates of x;
+ * each update is one product with A: Jacobi the full A (x += D^-1 (b - A x)),
+ * Gauss-Seidel its strict upper triangle plus a forward substitution with
+ * the lower one.  The stop test is made on the residual of the current
+ * iterate, as for the Krylov methods. */
+#define KS_JACOBI 3
+#define KS_GAUSS_SEIDEL 4
 
 #define KS_FP64 0        /* everything in binary64                               */
 #define KS_IR_FP32 1     /* inner solve on binary32 A, binary64 refinement       */
@@ -87,7 +101,8 @@ typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
 typedef struct {
     int32_t n;          /* order of A, >= 1                                       */
-    int32_t method;     /* KS_CG, KS_GMRES or KS_BICGSTAB                         */
+    int32_t method;     /* KS_CG, KS_GMRES, KS_BICGSTAB, KS_JACOBI or
+                           KS_GAUSS_SEIDEL                                       */
     int64_t lda;        /* leading dimension of A in elements, >= n               */
     int32_t precision;  /* KS_FP64, KS_IR_FP32 or KS_IR_BF16                      */
     int32_t max_iter;   /* FP64: A*v products in the Krylov loop over the whole
@@ -181,8 +196,9 @@ void ks_free(ks_solver *s);
 const char *ks_strerror(int status);
 
 /* ---- request server (continuous batching) ------------------------------
- * Many binary64 CG / GMRES(m) solves of different sizes, submitted as they
- * arrive.  Each ks_server_step admits queued requests first come first served
+ * Many CG / GMRES(m) solves of different sizes, binary64 or mixed precision
+ * (KS_IR_FP32 / KS_IR_BF16 inner solves with binary64 refinement), submitted
+ * as they arrive.  Each ks_server_step admits queued requests first come first served
  * while the memory budget (8 n lda bytes of the request's A plus its solve
  * workspace) and the in-flight slot count allow, then advances every
  * in-flight solve by `chunk` iterations with one batched launch per phase (a
@@ -201,9 +217,10 @@ typedef struct ks_server ks_server;
 int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_inflight, int32_t chunk,
                      void *stream);
 
-/* Queue a solve (precision KS_FP64, nrhs 1).  d_x holds x0 and receives x.
- * *ticket identifies it in ks_server_poll.  KS_ETOOLARGE if it can never
- * fit the budget. */
+/* Queue a solve (method KS_CG or KS_GMRES, nrhs 1, no KS_FLAG_SYMMETRIC; any
+ * precision; otherwise KS_EINVAL).  d_x holds x0 and receives x.  *ticket
+ * identifies it in ks_server_poll.  KS_ETOOLARGE if it can never fit the
+ * budget. */
 int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const double *d_b,
                      double *d_x, uint64_t *ticket);
 

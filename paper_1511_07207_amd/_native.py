@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libks.so")
 
 KS_OK, KS_MAXITER, KS_BREAKDOWN, KS_STAGNATED, KS_NONFINITE = 0, 1, 2, 3, 4
 KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_EDEVICE, KS_ETOOLARGE = -1, -2, -3, -4, -5
-KS_CG, KS_GMRES, KS_BICGSTAB = 0, 1, 2
+KS_CG, KS_GMRES, KS_BICGSTAB, KS_JACOBI, KS_GAUSS_SEIDEL = 0, 1, 2, 3, 4
 KS_FP64, KS_IR_FP32, KS_IR_BF16 = 0, 1, 2
 KS_DT_F64, KS_DT_F32, KS_DT_BF16 = 0, 1, 2
 KS_FLAG_TIMING = 1

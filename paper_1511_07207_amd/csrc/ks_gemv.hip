@@ -101,6 +101,13 @@ hipError_t launch_residual(int n, int64_t lda, const TA *A, const T *b, const T 
 }
 
 template <typename TA, typename T>
+hipError_t launch_residual_rows(int n, int64_t lda, const TA *A, const T *b, const T *x, T *r,
+                                const State *st, double *partial, int gate, hipStream_t s) {
+    residual_kernel<TA><<<gemv_blocks<TA>(n), GEMV_NT, 0, s>>>(n, lda, A, b, x, r, st, partial, gate);
+    return hipGetLastError();
+}
+
+template <typename TA, typename T>
 hipError_t launch_cg_matvec(int n, int64_t lda, const TA *A, const T *p, T *q, State *st,
                             Partials P, hipStream_t s) {
     cg_matvec_kernel<TA><<<gemv_blocks<TA>(n), GEMV_NT, 0, s>>>(n, lda, A, p, q, st, P.g);
@@ -140,6 +147,9 @@ hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Parti
 #define KS_INST_GEMV(TA, T)                                                                      \
     template hipError_t launch_residual<TA, T>(int, int64_t, const TA *, const T *, const T *,  \
                                                T *, State *, Partials, int, hipStream_t);        \
+    template hipError_t launch_residual_rows<TA, T>(int, int64_t, const TA *, const T *,         \
+                                                    const T *, T *, const State *, double *, int, \
+                                                    hipStream_t);                                \
     template hipError_t launch_cg_matvec<TA, T>(int, int64_t, const TA *, const T *, T *,        \
                                                 State *, Partials, hipStream_t);                 \
     template hipError_t launch_gm_matvec<TA, T>(int, int64_t, const TA *, const T *, T *,        \

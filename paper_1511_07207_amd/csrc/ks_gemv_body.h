@@ -344,7 +344,9 @@ __device__ __forceinline__ void residual_body(int n, int64_t lda, const TA *__re
                                               typename ATraits<TA>::TV *__restrict__ r,
                                               const State *st, double *partial, int gate, int bid) {
     using TV = typename ATraits<TA>::TV;
+    // gate 0: always; 1: only once the loop has stopped; 2: only while it runs
     if (gate == 1 && !(st->flags & F_STOP)) return;
+    if (gate == 2 && (st->flags & F_STOP)) return;
     const int row0 = bid * GemvShape<TA>::ROWS;
     TV acc[GemvShape<TA>::ROWS];
     rows_dot<TA, GemvShape<TA>::ROWS, GEMV_NT, GemvShape<TA>::UNR>(A, lda, n, row0, x, acc);

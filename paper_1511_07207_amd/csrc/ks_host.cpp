@@ -417,6 +417,163 @@ int run_bicgstab(ks_solver *s, State *st, int state_index, const TA *A, int64_t 
     return KS_OK;
 }
 
+// ------------------------------------------------- Jacobi / Gauss-Seidel
+// Shared start: ||b||, diag(A) (zero -> breakdown) and the true residual of
+// x0.  Returns 1 when the solve is already decided (out filled), 0 to go on.
+int stationary_start(ks_solver *s, const double *b, double *x, double *r, double *d, double tol,
+                     int eta, Outcome *out, int *rc) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    State *st = s->st;
+    *rc = KS_OK;
+    if ((*rc = launch_vec_stats<double>(n, b, tol, st, sm, eta) ? KS_EHIP : KS_OK)) return 1;
+    if ((*rc = launch_st_diag(n, s->lda, s->A, d, st, sm) ? KS_EHIP : KS_OK)) return 1;
+    if ((*rc = launch_residual<double, double>(n, s->lda, s->A, b, x, r, st, s->P, 0, sm)
+                   ? KS_EHIP
+                   : KS_OK))
+        return 1;
+    if ((*rc = sync_state(s))) return 1;
+    const State *h = &s->host[0];
+    out->iters = 0;
+    out->restarts = 0;
+    if (h->bnorm == 0.0) {
+        if ((*rc = launch_fill<double>(n, x, 0.0, sm) ? KS_EHIP : KS_OK)) return 1;
+        out->status = KS_OK;
+        return 1;
+    }
+    if (h->flags & F_TRUE_NONFIN) {
+        out->status = KS_NONFINITE;
+        return 1;
+    }
+    if (h->flags & F_BREAK) {
+        out->status = KS_BREAKDOWN;
+        return 1;
+    }
+    return 0;
+}
+
+// status of a stopped stationary loop from its flags
+int stationary_status(int f) {
+    if (f & F_NONFIN) return KS_NONFINITE;
+    if (f & F_BREAK) return KS_BREAKDOWN;
+    if (f & F_CONV) return KS_OK;
+    return KS_MAXITER;
+}
+
+// Jacobi: [r = b - A x (partials)] -> [decide on x] -> [x += r / d], the
+// residual of each iterate being the true one.
+int run_jacobi(ks_solver *s, const double *b, double *x, double tol, int max_iter, Outcome *out,
+               int eta) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    State *st = s->st;
+    double *r = s->vec64(0), *d = s->vec64(1);
+    int rc;
+    if (stationary_start(s, b, x, r, d, tol, eta, out, &rc)) return rc;
+    const State *h = &s->host[0];
+    const int nb = gemv_blocks<double>(n);
+    HIPCHK(launch_st_begin(st, sm));
+    bool done = false;
+    while (!done) {
+        const int it0 = h->iters;
+        const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0 + 1));
+        for (int c = 0; c < chunk; ++c) {
+            HIPCHK(launch_st_decide(nb, st, s->P.g, max_iter, sm));
+            HIPCHK(launch_jacobi_update(n, x, r, d, st, sm));
+            hipEvent_t e0, e1;
+            if ((rc = timing_pair(s, &e0, &e1))) return rc;
+            if (e0) HIPCHK(hipEventRecord(e0, sm));
+            HIPCHK((launch_residual_rows<double, double>(n, s->lda, s->A, b, x, r, st, s->P.g, 2,
+                                                         sm)));
+            if (e1) HIPCHK(hipEventRecord(e1, sm));
+        }
+        if ((rc = sync_state(s))) return rc;
+        if ((rc = timed_collect(s, h->iters - it0))) return rc;
+        done = (h->flags & F_STOP) != 0;
+    }
+    out->status = stationary_status(h->flags);
+    out->iters = h->iters;
+    return KS_OK;
+}
+
+// Gauss-Seidel: [u = U x, c = b - u, residual of x as u_prev - u] ->
+// [decide on x] -> [forward substitution (D + L) x = c].  The residual from
+// the difference of products is the true one up to rounding; a stop is
+// confirmed on the true residual and the sweeps resume if it disagrees.
+int run_gauss_seidel(ks_solver *s, const double *b, double *x, double tol, int max_iter,
+                     Outcome *out, int eta) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    State *st = s->st;
+    double *r = s->vec64(0), *d = s->vec64(1), *c = s->vec64(4);
+    double *u[2] = {s->vec64(2), s->vec64(3)};
+    int rc;
+    if (stationary_start(s, b, x, r, d, tol, eta, out, &rc)) return rc;
+    const State *h = &s->host[0];
+    // a sweep is ceil(n / 64) dependent launches: poll often, so that few
+    // sweeps run (as no-ops) past the stop
+    const int poll = s->p.poll_every > 0 ? s->p.poll_every : (n >= 4096 ? 1 : n >= 1024 ? 4 : 16);
+    int restarts = 0, k = 0;
+    bool first = true;
+    for (;;) {
+        const int f = h->flags;
+        if (f & F_TRUE_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (f & F_TRUE_OK) {
+            out->status = KS_OK;
+            break;
+        }
+        if (h->iters >= max_iter) {
+            out->status = KS_MAXITER;
+            break;
+        }
+        if (!first) {
+            if (restarts >= CG_MAX_RESTARTS) {
+                out->status = KS_STAGNATED;
+                break;
+            }
+            ++restarts;
+        }
+        HIPCHK(launch_st_begin(st, sm));
+        bool with_res = false;  // the cycle's first test uses the true residual's partials
+        bool done = false;
+        while (!done) {
+            const int it0 = h->iters;
+            for (int i = 0; i < poll; ++i, ++k) {
+                hipEvent_t e0, e1;
+                if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                if (e0) HIPCHK(hipEventRecord(e0, sm));
+                HIPCHK(launch_gs_upper(n, s->lda, s->A, b, x, u[(k + 1) & 1], u[k & 1], c, st,
+                                       s->P.g, with_res ? 1 : 0, sm));
+                if (e1) HIPCHK(hipEventRecord(e1, sm));
+                HIPCHK(launch_st_decide(with_res ? gs_upper_blocks(n) : gemv_blocks<double>(n), st,
+                                        s->P.g, max_iter, sm));
+                HIPCHK(launch_gs_sweep(n, s->lda, s->A, x, c, st, sm));
+                with_res = true;
+            }
+            if ((rc = sync_state(s))) return rc;
+            // the upper product before the stopping decision ran as well
+            const bool stopped = (h->flags & F_STOP) != 0;
+            if ((rc = timed_collect(s, h->iters - it0 + (stopped ? 1 : 0)))) return rc;
+            done = stopped;
+        }
+        first = false;
+        const int f2 = h->flags;
+        if (f2 & (F_NONFIN | F_BREAK)) {
+            out->status = stationary_status(f2);
+            break;
+        }
+        // converged or at the limit by the recurrence: confirm on b - A x
+        HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r, st, s->P, 0, sm)));
+        if ((rc = sync_state(s))) return rc;
+    }
+    out->iters = h->iters;
+    out->restarts = restarts;
+    return KS_OK;
+}
+
 // Metrics of the returned x from the State the solve left behind: every exit
 // path of the drivers ends with a true-residual kernel and a sync, so the
 // host mirror holds ||b||, ||r|| and the infinity norms of r, x and b.
@@ -434,6 +591,8 @@ void metrics_from_state(const ks_solver *s, ks_info *info) {
 
 int solve_fp64(ks_solver *s, const double *b, double *x, double tol, int max_iter, Outcome *o,
                int eta) {
+    if (s->p.method == KS_JACOBI) return run_jacobi(s, b, x, tol, max_iter, o, eta);
+    if (s->p.method == KS_GAUSS_SEIDEL) return run_gauss_seidel(s, b, x, tol, max_iter, o, eta);
     if (s->p.method == KS_CG)
         return run_cg<double, double>(s, s->st, 0, s->A, s->lda, b, x, s->vec64(0), s->vec64(1),
                                       s->vec64(2), tol, max_iter, true, o, eta);
@@ -808,7 +967,9 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
 extern "C" {
 
 int ks_params_init(ks_params *p, int32_t n, int32_t method) {
-    if (!p || n < 1 || (method != KS_CG && method != KS_GMRES && method != KS_BICGSTAB))
+    if (!p || n < 1 ||
+        (method != KS_CG && method != KS_GMRES && method != KS_BICGSTAB && method != KS_JACOBI &&
+         method != KS_GAUSS_SEIDEL))
         return KS_EINVAL;
     std::memset(p, 0, sizeof(*p));
     p->n = n;

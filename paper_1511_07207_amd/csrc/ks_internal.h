@@ -155,6 +155,33 @@ template <typename TA, typename T>
 hipError_t launch_residual(int n, int64_t lda, const TA *A, const T *b, const T *x, T *r,
                            State *st, Partials P, int gate, hipStream_t s);
 
+// the product kernel of launch_residual alone (3 partials per block into
+// `partial`); gate 2: skipped once the loop has stopped
+template <typename TA, typename T>
+hipError_t launch_residual_rows(int n, int64_t lda, const TA *A, const T *b, const T *x, T *r,
+                                const State *st, double *partial, int gate, hipStream_t s);
+
+// Stationary methods (binary64).  d = diag(A), F_BREAK on a zero element;
+// decide: residual metrics of the current iterate from `nblocks` residual
+// partials, then stop or count one more update; begin: inner flags cleared.
+hipError_t launch_st_diag(int n, int64_t lda, const double *A, double *d, State *st,
+                          hipStream_t s);
+hipError_t launch_st_decide(int nblocks, State *st, const double *partial, int max_iter,
+                            hipStream_t s);
+hipError_t launch_st_begin(State *st, hipStream_t s);
+// Jacobi: x += r / d
+hipError_t launch_jacobi_update(int n, double *x, const double *r, const double *d,
+                                const State *st, hipStream_t s);
+// Gauss-Seidel: u = U x, c = b - u (+ residual partials u_prev - u when
+// with_res, gs_upper_blocks(n) blocks of 3); then the forward substitution
+// (D + L) x = c, ceil(n / 64) launches, overwriting x and c.
+int gs_upper_blocks(int n);
+hipError_t launch_gs_upper(int n, int64_t lda, const double *A, const double *b, const double *x,
+                           const double *u_prev, double *u, double *c, const State *st,
+                           double *partial, int with_res, hipStream_t s);
+hipError_t launch_gs_sweep(int n, int64_t lda, const double *A, double *x, double *c,
+                           const State *st, hipStream_t s);
+
 // CG iteration, three kernels:
 //   q = A p (sigma partials);  x += alpha p, r -= alpha q (rho' partials);
 //   convergence / limit checks, p = r + beta p.

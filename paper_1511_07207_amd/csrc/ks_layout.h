@@ -50,7 +50,13 @@ inline size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m
 inline bool valid_params(const ks_params *p) {
     if (!p) return false;
     if (p->n < 1 || p->lda < p->n) return false;
-    if (p->method != KS_CG && p->method != KS_GMRES && p->method != KS_BICGSTAB) return false;
+    if (p->method != KS_CG && p->method != KS_GMRES && p->method != KS_BICGSTAB &&
+        p->method != KS_JACOBI && p->method != KS_GAUSS_SEIDEL)
+        return false;
+    // the stationary methods: binary64, one right-hand side, general storage
+    if ((p->method == KS_JACOBI || p->method == KS_GAUSS_SEIDEL) &&
+        (p->precision != KS_FP64 || p->nrhs != 1 || (p->flags & KS_FLAG_SYMMETRIC)))
+        return false;
     if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
     if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
     if (p->max_iter < 0) return false;
@@ -83,8 +89,13 @@ inline Layout make_layout(const ks_params *p) {
     L.part_off = off;
     off = align_up(off + L.part_count * sizeof(double));
     // binary64 vectors: CG r, p, q; GMRES w, V(0..m); BiCGSTAB r, r0, p, v, s, t;
+    // Jacobi r, diag(A); Gauss-Seidel r, diag(A), U x twice, b - U x;
     // IR adds the outer residual
-    const int nkry = (p->method == KS_CG) ? 3 : (p->method == KS_BICGSTAB) ? 6 : 1 + (L.m + 1);
+    const int nkry = (p->method == KS_CG)            ? 3
+                     : (p->method == KS_BICGSTAB)    ? 6
+                     : (p->method == KS_JACOBI)      ? 2
+                     : (p->method == KS_GAUSS_SEIDEL) ? 5
+                                                     : 1 + (L.m + 1);
     // binary64 CG at n <= FZ_MAX_N runs the fused kernel: r, p, q twice
     const bool fused = p->method == KS_CG && p->nrhs == 1 && n <= FZ_MAX_N;
     L.nv64 = fused ? 6 : nkry;

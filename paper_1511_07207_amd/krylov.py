@@ -15,7 +15,8 @@ import torch
 
 from . import _native as N
 
-_METHODS = {"cg": N.KS_CG, "gmres": N.KS_GMRES, "bicgstab": N.KS_BICGSTAB}
+_METHODS = {"cg": N.KS_CG, "gmres": N.KS_GMRES, "bicgstab": N.KS_BICGSTAB,
+            "jacobi": N.KS_JACOBI, "gauss_seidel": N.KS_GAUSS_SEIDEL}
 _PRECISIONS = {"fp64": N.KS_FP64, "fp32": N.KS_IR_FP32, "bf16": N.KS_IR_BF16}
 _PREC_NAMES = {v: k for k, v in _PRECISIONS.items()}
 

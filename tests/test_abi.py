@@ -65,26 +65,53 @@ def test_host_only_entry_points_without_gpu():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
 def test_bicgstab_parameters_on_host():
-    # BiCGSTAB keeps six vectors (r, r0, p, v, s, t) and one State; it is a
-    # one-right-hand-side method, so nrhs > 1 is rejected
+    # BiCGSTAB keeps six vectors (r, r0, p, v, s, t) and one State, three more
+    # than CG above the fused small-n size (4096, where CG keeps six too); it
+    # is a one-right-hand-side method, so nrhs > 1 is rejected
     from paper_1511_07207_amd import _native as N
 
     L = N.lib()
     p = N.KsParams()
-    assert L.ks_params_init(ctypes.byref(p), 1000, N.KS_BICGSTAB) == 0
+    assert L.ks_params_init(ctypes.byref(p), 5000, N.KS_BICGSTAB) == 0
     assert p.method == N.KS_BICGSTAB
     sz, szc = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
     q = N.KsParams()
-    assert L.ks_params_init(ctypes.byref(q), 1000, N.KS_CG) == 0
+    assert L.ks_params_init(ctypes.byref(q), 5000, N.KS_CG) == 0
     assert L.ks_workspace_bytes_borrowed(ctypes.byref(q), ctypes.byref(szc)) == 0
-    assert sz.value >= szc.value + 3 * 1024 * 8
+    assert sz.value >= szc.value + 3 * 5000 * 8
     p.nrhs = 4
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
     p.nrhs = 1
     p.precision = N.KS_IR_BF16
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == 0
-    assert L.ks_params_init(ctypes.byref(p), 10, 3) == N.KS_EINVAL
+    assert L.ks_params_init(ctypes.byref(p), 10, 5) == N.KS_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_stationary_parameters_on_host():
+    # Jacobi and Gauss-Seidel: binary64 only, one right-hand side, general
+    # storage; Gauss-Seidel keeps three more vectors than Jacobi (U x twice,
+    # b - U x); the request server takes neither
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    sizes = {}
+    for m in (N.KS_JACOBI, N.KS_GAUSS_SEIDEL):
+        p = N.KsParams()
+        assert L.ks_params_init(ctypes.byref(p), 1000, m) == 0
+        assert p.method == m
+        sz = ctypes.c_size_t(0)
+        assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+        sizes[m] = sz.value
+        for field, bad in (("precision", N.KS_IR_FP32), ("precision", N.KS_IR_BF16),
+                           ("nrhs", 2), ("flags", N.KS_FLAG_SYMMETRIC)):
+            q = N.KsParams()
+            assert L.ks_params_init(ctypes.byref(q), 1000, m) == 0
+            setattr(q, field, bad)
+            assert L.ks_workspace_bytes(ctypes.byref(q), ctypes.byref(sz)) == N.KS_EINVAL, field
+    assert sizes[N.KS_GAUSS_SEIDEL] >= sizes[N.KS_JACOBI] + 3 * 1024 * 8
+    assert L.ks_params_init(ctypes.byref(N.KsParams()), 10, 5) == N.KS_EINVAL
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
