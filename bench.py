@@ -244,6 +244,58 @@ def leg_f1(dev, n):
     return out
 
 
+def leg_f3(dev, n):
+    """Jacobi and Gauss-Seidel on the nonsymmetric n = 16384 system of the main
+    step (D + G/sqrt(n), Jacobi spectral radius about 0.36), binary64 to
+    relative residual 1e-10, beside GMRES(30) on the same system; then the
+    four methods the paper times (Jacobi, Gauss-Seidel, GMRES(35), BiCGSTAB)
+    at its tolerance 1e-4 over its size range."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem
+
+    def run(prob, m, kw, reps):
+        x = torch.zeros(m, dtype=torch.float64, device=dev)
+        s = krylov.Solver(prob.A, timing=True, **kw)
+        s.solve(prob.b, out=x.zero_())
+        lat = []
+        for _ in range(reps):
+            (_, info), dt = _timed(lambda: s.solve(prob.b, out=x.zero_()))
+            lat.append(dt * 1e3)
+        s.close()
+        t = statistics.median(lat)
+        r = {"status": info["status_name"], "iters": info["iters"], "rel_res": info["rel_res"],
+             "p50_ms": round(t, 3), "solves_per_s": round(1e3 / statistics.mean(lat), 3)}
+        if kw["method"] in ("jacobi", "gauss_seidel") and info["iters"]:
+            # each update reads A once (Jacobi: the product; Gauss-Seidel: the
+            # strict upper product and the substitution's lower triangle)
+            r["ms_per_update"] = round(t / info["iters"], 4)
+            r["update_gbs"] = round(8.0 * m * m * info["iters"] / (t * 1e-3) / 1e9, 1)
+        return r
+
+    prob = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    out = {"n": n, "system": "D + G/sqrt(n), D uniform in [2,4]", "tol": 1e-10}
+    for name, kw in (("jacobi", dict(method="jacobi", tol=1e-10)),
+                     ("gauss_seidel", dict(method="gauss_seidel", tol=1e-10)),
+                     ("gmres30", dict(method="gmres", restart=30, tol=1e-10))):
+        out[name] = run(prob, n, kw, 5)
+    del prob
+    sweep = {}
+    for m in (2000, 8000, 16000):
+        prob = nonsym_problem(m, seed=0, config_id=1, backend="torch", device="cuda")
+        row = {}
+        for name, kw in (("jacobi", dict(method="jacobi")), ("gauss_seidel", dict(method="gauss_seidel")),
+                         ("gmres35", dict(method="gmres", restart=35)), ("bicgstab", dict(method="bicgstab"))):
+            r = run(prob, m, dict(kw, tol=1e-4), 5)
+            row[name] = {"iters": r["iters"], "p50_ms": r["p50_ms"], "status": r["status"]}
+        sweep[str(m)] = row
+        del prob
+    out["paper_tolerance_1e-4"] = sweep
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_c2p(dev, n):
     """The CG solve of the main step with either product: general GEMV (all of
     A per iteration) and the symmetric lower-triangle product."""
@@ -408,9 +460,9 @@ def main():
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
-    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1",
+    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1,f3",
                     help="extra measurements after the timed steps (comma list of "
-                         "c1,c2p,c3,c4,c5,f1; 'none' for the main step only)")
+                         "c1,c2p,c3,c4,c5,f1,f3; 'none' for the main step only)")
     ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -584,6 +636,8 @@ def main():
                 legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool)
             elif name == "f1":
                 legs[name] = leg_f1(dev, n)
+            elif name == "f3":
+                legs[name] = leg_f3(dev, n)
             elif name == "c2p":
                 legs[name] = leg_c2p(dev, n)
             else:

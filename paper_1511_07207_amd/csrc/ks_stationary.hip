@@ -44,7 +44,7 @@ constexpr int GS_LDT = GS_SB + 1;             // LDS row stride of the diagonal 
 constexpr int GS_ROWS = GemvShape<double>::ROWS;  // rows per block of the upper product
 constexpr int GS_UNR = GemvShape<double>::UNR;    // column chunks in flight per thread
 static_assert(GS_SB == WAVE, "one lane per row of the diagonal tile, one per panel column");
-static_assert(GS_SB % (GS_WAVES * GS_PW) == 0, "the block's waves cover its own rows in passes");
+static_assert(GS_SB % GS_WAVES == 0, "the block's waves share its rows evenly");
 
 // --------------------------------------------------------------- common
 // d = diag(A); F_BREAK | F_STOP when an element is zero (one block)
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(GEMV_NT) void gs_sweep_kernel(int n, int64_t lda,
                                                            double *__restrict__ c, const State *st,
                                                            int I) {
     __shared__ double T[GS_SB * GS_LDT];
-    __shared__ double cI[GS_SB];
+    __shared__ double cI[GS_SB];  // the block's row sums over column block I - 1
     if (st->flags & F_STOP) return;
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
@@ -257,34 +257,44 @@ __global__ __launch_bounds__(GEMV_NT) void gs_sweep_kernel(int n, int64_t lda,
     }
     const int r0 = I * GS_SB;
     const int m = min(GS_SB, n - r0);
+    // every global load of the step first (one memory round trip): the
+    // wave's rows of the diagonal tile (k = w + GS_WAVES q), its rows of the
+    // block's update by column block I - 1, and c of the block's rows
+    constexpr int TQ = GS_SB / GS_WAVES;   // tile rows per wave
+    constexpr int PQ = GS_SB / GS_WAVES;   // update rows per wave
+    double tl[TQ], pv[PQ];
+    const int cc = min(lane, m - 1);
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+        const int k = w + GS_WAVES * q;
+        tl[q] = A[(int64_t)(r0 + min(k, m - 1)) * lda + r0 + cc];
+    }
+    if (I >= 1) {
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int k = w * PQ + q;
+            pv[q] = A[(int64_t)(r0 + min(k, m - 1)) * lda + cb + lane];
+        }
+    }
+    const double cval = (w == 0 && lane < m) ? c[r0 + lane] : 0.0;
     // the diagonal tile into LDS, lower part only; rows past n get a unit
     // diagonal (their x is 0 and never written)
-    for (int k = w; k < GS_SB; k += GS_WAVES) {
-        const int kk = min(k, m - 1), cc = min(lane, m - 1);
-        const double a = A[(int64_t)(r0 + kk) * lda + r0 + cc];
-        T[k * GS_LDT + lane] = (k < m && lane < m) ? (lane <= k ? a : 0.0) : (lane == k ? 1.0 : 0.0);
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+        const int k = w + GS_WAVES * q;
+        T[k * GS_LDT + lane] =
+            (k < m && lane < m) ? (lane <= k ? tl[q] : 0.0) : (lane == k ? 1.0 : 0.0);
     }
-    // c of the block's rows less column block I - 1
+    // sums of the block's rows over column block I - 1
 #pragma unroll
-    for (int pass = 0; pass < GS_SB / (GS_WAVES * GS_PW); ++pass) {
-        const int k0 = (pass * GS_WAVES + w) * GS_PW;
-        double sums[GS_PW];
-        if (I >= 1) {
-            gs_row_sums(n, lda, A, xl, r0 + k0, cb, lane, sums);
-        } else {
-#pragma unroll
-            for (int k = 0; k < GS_PW; ++k) sums[k] = 0.0;
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < GS_PW; ++k)
-                cI[k0 + k] = (k0 + k < m) ? c[r0 + k0 + k] - sums[k] : 0.0;
-        }
+    for (int q = 0; q < PQ; ++q) {
+        const double sq = I >= 1 ? wave_sum(pv[q] * xl) : 0.0;
+        if (lane == 0) cI[w * PQ + q] = sq;
     }
     __syncthreads();
     if (w != 0) return;
     // forward substitution in wave 0: lane i holds row i
-    double acc = cI[lane];
+    double acc = lane < m ? cval - cI[lane] : 0.0;
     const double dinv = 1.0 / T[lane * GS_LDT + lane];
     double xi = 0.0;
 #pragma unroll
