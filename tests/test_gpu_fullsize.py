@@ -143,3 +143,36 @@ def test_c5_largest_requests_full_size(device):
         m = oracle.metrics(hosts[id(p)], p.b.cpu().numpy(), x.cpu().numpy())
         print(f"C5 {kw}: eta {m['eta_inf']:.3e} prec {info['precision_used']}", flush=True)
         assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+
+
+def test_c2_stationary_full_size(device):
+    """Jacobi and Gauss-Seidel on the n = 16384 nonsymmetric system, as the
+    benchmark times them.  Sampled outputs the oracle can form exactly: the
+    first Jacobi update from x0 = 0 is b / d bit for bit, and the first
+    Gauss-Seidel sweep restricted to the leading k rows depends only on the
+    leading k x k block, so the oracle's sweep of that block gives those k
+    values.  Then the converged solves by their properties."""
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem
+
+    n, k = 16384, 1024
+    print(f"C2 stationary n={n}: generating", flush=True)
+    p = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    A_host, bh = p.A.cpu().numpy(), p.b.cpu().numpy()
+    x1, info = krylov.solve(p.A, p.b, method="jacobi", tol=1e-300, max_iter=1)
+    assert info["iters"] == 1
+    np.testing.assert_array_equal(x1.cpu().numpy(), bh / np.diag(A_host))
+    g1, info = krylov.solve(p.A, p.b, method="gauss_seidel", tol=1e-300, max_iter=1)
+    assert info["iters"] == 1
+    go, _ = oracle.gauss_seidel(A_host[:k, :k].copy(), bh[:k], tol=1e-300, max_iter=1)
+    g1 = g1.cpu().numpy()
+    assert np.abs(g1[:k] - go).max() <= 1e-12 * np.abs(go).max()
+    xt = p.x_true.cpu().numpy()
+    for method in ("jacobi", "gauss_seidel"):
+        x, info = krylov.solve(p.A, p.b, method=method, tol=1e-10)
+        assert info["status"] == 0, info
+        m = oracle.metrics(A_host, bh, x.cpu().numpy())
+        print(f"C2 {method}: iters {info['iters']} rel_res {m['rel_res']:.3e}", flush=True)
+        assert m["rel_res"] <= 1e-10
+        assert abs(info["rel_res"] - m["rel_res"]) <= 1e-3 * m["rel_res"] + np.sqrt(n) * U
+        assert np.linalg.norm(x.cpu().numpy() - xt) <= 10 * 10.0 * 1e-10 * np.linalg.norm(xt)
