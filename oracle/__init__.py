@@ -65,6 +65,13 @@ def _load():
         lib.ko_gmres.restype = i
         lib.ko_bicgstab.argtypes = [i, pd, l, pd, pd, d, i, pi, pi, pd]
         lib.ko_bicgstab.restype = i
+        pf = ctypes.POINTER(ctypes.c_float)
+        lib.ko_lu32_block.argtypes = [i, pd, l, pf, l, pi, i]
+        lib.ko_lu32_block.restype = i
+        lib.ko_lu32_apply.argtypes = [i, pf, l, pi, pd, pd]
+        lib.ko_lu32_apply.restype = None
+        lib.ko_gmres_ir_lu.argtypes = [i, pd, l, pd, pd, d, i, d, i, i, i, pi, pi, pd]
+        lib.ko_gmres_ir_lu.restype = i
         for name in ("ko_jacobi", "ko_gauss_seidel"):
             getattr(lib, name).argtypes = [i, pd, l, pd, pd, d, i, pi, pd]
             getattr(lib, name).restype = i
@@ -248,6 +255,54 @@ def jacobi(A, b, x0=None, tol=1e-10, max_iter=None):
 def gauss_seidel(A, b, x0=None, tol=1e-10, max_iter=None):
     """Gauss-Seidel forward sweeps (D + L) x(k+1) = b - U x(k); returns (x, info)."""
     return _stationary(_load().ko_gauss_seidel, A, b, x0, tol, max_iter)
+
+
+def _pf(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _pi(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def lu32_block(A, b=16):
+    """The block LU in binary32 on fl32(A). Returns (LU float32 n x n, piv, singular)."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    LU = np.zeros((n, n), dtype=np.float32)
+    piv = np.zeros(n, dtype=np.int32)
+    sing = _load().ko_lu32_block(n, _pd(A), lda, _pf(LU), n, _pi(piv), int(b))
+    if sing < 0:
+        raise ValueError("ko_lu32_block: bad arguments")
+    return LU, piv, int(sing)
+
+
+def lu32_apply(LU, piv, v):
+    """U^-1 L^-1 P v in binary64 with the binary32 factors."""
+    LU = np.ascontiguousarray(LU, dtype=np.float32)
+    n = LU.shape[0]
+    piv = np.ascontiguousarray(piv, dtype=np.int32)
+    v = _vec(v, n)
+    z = np.zeros(n)
+    _load().ko_lu32_apply(n, _pf(LU), n, _pi(piv), _pd(v), _pd(z))
+    return z
+
+
+def gmres_ir_lu(A, b, x0=None, tol=1e-12, restart=30, inner_tol=1e-4, max_inner=None,
+                max_outer=30, nb=16):
+    """GMRES-IR: binary64 refinement, GMRES(restart) on the system left-
+    preconditioned by the binary32 block LU of A. Returns (x, info)."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    b = _vec(b, n)
+    x = np.zeros(n) if x0 is None else _vec(x0, n).copy()
+    max_inner = 10 * n if max_inner is None else int(max_inner)
+    o, it, eta = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _load().ko_gmres_ir_lu(n, _pd(A), lda, _pd(b), _pd(x), float(tol), int(restart),
+                                float(inner_tol), max_inner, int(max_outer), int(nb),
+                                ctypes.byref(o), ctypes.byref(it), ctypes.byref(eta))
+    return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), outer_iters=o.value,
+                   inner_iters=it.value, eta_inf=eta.value)
 
 
 def arnoldi(A, v0, k):

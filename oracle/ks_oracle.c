@@ -671,3 +671,229 @@ int ko_lu_solve(int n, const double *LU, long lda, const int *piv, const double 
     free(y);
     return 0;
 }
+
+/* ------------------------------------------- binary32 block LU, GMRES-IR
+ *
+ * The paper's block LU (direct-methods section, Figure 1, equations (1)-(4)
+ * and its block algorithm), in binary32 arithmetic on the binary32 rounding
+ * of A: for each column block of width b, the panel is factored column by
+ * column with partial pivoting (the first row of largest magnitude, whole
+ * rows interchanged), the panel's unit lower triangle solves for the block
+ * row of U to its right, and the trailing matrix takes the delayed rank-b
+ * update.  b >= n is the unblocked right-looking algorithm.  L (unit, below
+ * the diagonal) and U overwrite LU; piv[k] is the row swapped with row k at
+ * step k.  Returns 0, or 1 + the first column whose pivot is zero.
+ *
+ * The factors then precondition GMRES inside binary64 iterative refinement
+ * (GMRES-IR): r = b - A x in binary64; the correction solves
+ * M^-1 A d = M^-1 r by restarted GMRES(m) in binary64 with
+ * M^-1 v = U^-1 L^-1 P v applied with the binary32 factors widened to
+ * binary64; x += d; until the normwise backward error
+ * ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) <= tol.
+ */
+int ko_lu32_block(int n, const double *A, long lda, float *LU, long ldl, int *piv, int b) {
+    if (n <= 0 || !A || !LU || !piv || lda < n || ldl < n || b < 1) return KO_EINVAL;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) LU[(long)i * ldl + j] = (float)A[(long)i * lda + j];
+#define F(i, j) LU[(long)(i) * ldl + (j)]
+    int sing = 0;
+    for (int kb = 0; kb < n; kb += b) {
+        const int bf = kb + b < n ? kb + b : n; /* the panel's columns kb .. bf-1 */
+        for (int i = kb; i < bf; ++i) {
+            int p = i;
+            float best = fabsf(F(i, i));
+            for (int r = i + 1; r < n; ++r)
+                if (fabsf(F(r, i)) > best) { best = fabsf(F(r, i)); p = r; }
+            if (p != i)
+                for (int j = 0; j < n; ++j) { float t = F(i, j); F(i, j) = F(p, j); F(p, j) = t; }
+            piv[i] = p;
+            const float d = F(i, i);
+            if (d == 0.0f) {
+                if (!sing) sing = i + 1;
+                continue;
+            }
+            for (int r = i + 1; r < n; ++r) F(r, i) = F(r, i) / d;
+            for (int r = i + 1; r < n; ++r) {
+                const float l = F(r, i);
+                for (int j = i + 1; j < bf; ++j) F(r, j) = F(r, j) - l * F(i, j);
+            }
+        }
+        /* the block row of U: unit lower panel triangle \ A(kb:bf, bf:n) */
+        for (int c = bf; c < n; ++c)
+            for (int i = kb; i < bf; ++i) {
+                float s = F(i, c);
+                for (int j = kb; j < i; ++j) s = s - F(i, j) * F(j, c);
+                F(i, c) = s;
+            }
+        /* delayed rank-(bf - kb) update of the trailing matrix */
+        for (int r = bf; r < n; ++r)
+            for (int c = bf; c < n; ++c) {
+                float s = F(r, c);
+                for (int j = kb; j < bf; ++j) s = s - F(r, j) * F(j, c);
+                F(r, c) = s;
+            }
+    }
+#undef F
+    return sing;
+}
+
+/* z = U^-1 L^-1 P v in binary64 with the binary32 factors of ko_lu32_block */
+void ko_lu32_apply(int n, const float *LU, long ldl, const int *piv, const double *v, double *z) {
+    for (int i = 0; i < n; ++i) z[i] = v[i];
+    for (int k = 0; k < n; ++k) {
+        const int p = piv[k];
+        if (p != k) { double t = z[k]; z[k] = z[p]; z[p] = t; }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = z[i];
+        for (int j = 0; j < i; ++j) s -= (double)LU[(long)i * ldl + j] * z[j];
+        z[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int j = i + 1; j < n; ++j) s -= (double)LU[(long)i * ldl + j] * z[j];
+        z[i] = s / (double)LU[(long)i * ldl + i];
+    }
+}
+
+/* Left-preconditioned restarted GMRES(m), MGS twice + Givens as ko_gmres,
+ * on M^-1 A d = M^-1 r from d = 0; stops when the preconditioned residual
+ * estimate is <= tol ||M^-1 r||, or after max_steps products.  *steps
+ * counts products. */
+static int gmres_lu_inner(int n, const double *A, long lda, const float *LU, long ldl,
+                          const int *piv, const double *r, double *d, double tol, int m,
+                          int max_steps, int *steps_out) {
+    size_t nn = (size_t)n;
+    int steps = 0, status = KO_MAXITER;
+    double *V = (double *)calloc(nn * (size_t)(m + 1), sizeof(double));
+    double *w = (double *)malloc(sizeof(double) * nn);
+    double *t = (double *)malloc(sizeof(double) * nn);
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double *cs = (double *)calloc((size_t)m, sizeof(double));
+    double *sn = (double *)calloc((size_t)m, sizeof(double));
+    double *g = (double *)calloc((size_t)m + 1, sizeof(double));
+    double *y = (double *)calloc((size_t)m, sizeof(double));
+    if (!V || !w || !t || !H || !cs || !sn || !g || !y) {
+        status = KO_EINVAL;
+        goto out;
+    }
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    ko_lu32_apply(n, LU, ldl, piv, r, t);
+    const double pnorm = ko_nrm2(n, t);
+    if (!isfinite(pnorm)) { status = KO_NONFINITE; goto out; }
+    if (pnorm == 0.0) { status = KO_OK; goto out; }
+    for (;;) {
+        /* preconditioned residual M^-1 (r - A d) */
+        ko_residual(n, A, lda, r, d, w);
+        ko_lu32_apply(n, LU, ldl, piv, w, t);
+        const double beta = ko_nrm2(n, t);
+        if (!isfinite(beta)) { status = KO_NONFINITE; break; }
+        if (beta <= tol * pnorm) { status = KO_OK; break; }
+        if (steps >= max_steps) { status = KO_MAXITER; break; }
+        for (int i = 0; i < n; ++i) V[i] = t[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int kd = 0, fail = 0;
+        for (int k = 0; k < m; ++k) {
+            ko_matvec(n, A, lda, V + (size_t)k * nn, t);
+            ko_lu32_apply(n, LU, ldl, piv, t, w);
+            ++steps;
+            const double avk = ko_nrm2(n, w);
+            for (int j = 0; j <= k + 1; ++j) HH(j, k) = 0.0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int j = 0; j <= k; ++j) {
+                    const double *vj = V + (size_t)j * nn;
+                    const double h = ko_dot(n, vj, w);
+                    HH(j, k) += h;
+                    for (int i = 0; i < n; ++i) w[i] = w[i] - h * vj[i];
+                }
+            const double hk1 = ko_nrm2(n, w);
+            HH(k + 1, k) = hk1;
+            for (int i = 0; i < k; ++i) {
+                const double a = HH(i, k), bb = HH(i + 1, k);
+                HH(i, k) = cs[i] * a + sn[i] * bb;
+                HH(i + 1, k) = -sn[i] * a + cs[i] * bb;
+            }
+            const double rho = hypot(HH(k, k), HH(k + 1, k));
+            if (!isfinite(rho) || !isfinite(avk)) { status = KO_NONFINITE; fail = 1; break; }
+            if (rho == 0.0) { status = KO_BREAKDOWN; fail = 1; break; }
+            cs[k] = HH(k, k) / rho;
+            sn[k] = HH(k + 1, k) / rho;
+            HH(k, k) = rho;
+            HH(k + 1, k) = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            kd = k + 1;
+            if (hk1 <= KO_HAPPY * avk) break;
+            double *vn = V + (size_t)(k + 1) * nn;
+            for (int i = 0; i < n; ++i) vn[i] = w[i] / hk1;
+            if (fabs(g[k + 1]) <= tol * pnorm || steps >= max_steps) break;
+        }
+        for (int i = kd - 1; i >= 0; --i) {
+            double s2 = g[i];
+            for (int j = i + 1; j < kd; ++j) s2 -= HH(i, j) * y[j];
+            y[i] = s2 / HH(i, i);
+        }
+        for (int j = 0; j < kd; ++j) {
+            const double *vj = V + (size_t)j * nn;
+            for (int i = 0; i < n; ++i) d[i] = d[i] + y[j] * vj[i];
+        }
+        if (fail) break;
+    }
+#undef HH
+out:
+    free(V); free(w); free(t); free(H); free(cs); free(sn); free(g); free(y);
+    if (steps_out) *steps_out = steps;
+    return status;
+}
+
+int ko_gmres_ir_lu(int n, const double *A, long lda, const double *b, double *x, double tol,
+                   int m, double inner_tol, int max_inner, int max_outer, int nb, int *outer_out,
+                   int *inner_out, double *eta_out) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || m < 1 || !(inner_tol > 0.0) ||
+        max_inner < 1 || max_outer < 0 || nb < 1)
+        return KO_EINVAL;
+    size_t nn = (size_t)n;
+    float *LU = (float *)malloc(sizeof(float) * nn * nn);
+    int *piv = (int *)malloc(sizeof(int) * nn);
+    double *r = (double *)malloc(sizeof(double) * nn);
+    double *d = (double *)malloc(sizeof(double) * nn);
+    int status = KO_STAGNATED, outer = 0, inner = 0;
+    double eta = 0.0;
+    if (!LU || !piv || !r || !d) {
+        status = KO_EINVAL;
+        goto out;
+    }
+    const double anorm = ko_norm_inf_mat(n, A, lda);
+    const double binf = norm_inf_vec(n, b);
+    if (!isfinite(binf)) { status = KO_NONFINITE; goto out; }
+    if (binf == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        status = KO_OK;
+        goto out;
+    }
+    if (ko_lu32_block(n, A, lda, LU, (long)n, piv, nb)) { status = KO_BREAKDOWN; goto out; }
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        const double rinf = norm_inf_vec(n, r), xinf = norm_inf_vec(n, x);
+        const double den = anorm * xinf + binf;
+        eta = den > 0.0 ? rinf / den : rinf;
+        if (!isfinite(eta)) { status = KO_NONFINITE; break; }
+        if (eta <= tol) { status = KO_OK; break; }
+        if (outer >= max_outer) { status = KO_STAGNATED; break; }
+        int steps = 0;
+        const int st = gmres_lu_inner(n, A, lda, LU, (long)n, piv, r, d, inner_tol, m, max_inner,
+                                      &steps);
+        inner += steps;
+        ++outer;
+        if (st == KO_NONFINITE || st == KO_BREAKDOWN || st == KO_EINVAL) { status = st; break; }
+        for (int i = 0; i < n; ++i) x[i] = x[i] + d[i];
+    }
+out:
+    free(LU); free(piv); free(r); free(d);
+    if (outer_out) *outer_out = outer;
+    if (inner_out) *inner_out = inner;
+    if (eta_out) *eta_out = eta;
+    return status;
+}

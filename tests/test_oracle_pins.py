@@ -609,3 +609,109 @@ def test_stationary_on_the_nonsymmetric_workload():
         m = oracle.metrics(p.A, p.b, x)
         assert m["rel_res"] <= 1e-10
         np.testing.assert_allclose(x, p.x_true, rtol=1e-7, atol=1e-8)
+
+
+# ----------------------------------------- binary32 block LU and GMRES-IR
+# The block LU of the direct-methods section in binary32, pinned by the
+# componentwise backward-error bound of Gaussian elimination, by the pivots
+# of the binary64 GEPP (itself pinned to LAPACK above), by an exactly
+# representable factorization it must reproduce bit for bit, blocked or not;
+# its application M^-1 by SciPy's triangular solves; GMRES-IR by exactness
+# when M = A and by convergence where unpreconditioned GMRES stalls.
+
+def _lu_parts(LU, piv):
+    n = LU.shape[0]
+    L = np.tril(LU.astype(np.float64), -1) + np.eye(n)
+    U = np.triu(LU.astype(np.float64))
+    perm = np.arange(n)
+    for k, p in enumerate(piv):
+        perm[[k, p]] = perm[[p, k]]
+    return L, U, perm
+
+
+@pytest.mark.parametrize("n,b", [(1, 16), (50, 16), (200, 16), (200, 7), (200, 200)])
+def test_lu32_backward_error_bound(n, b):
+    rng = np.random.default_rng(60 + n + b)
+    A = rng.standard_normal((n, n))
+    LU, piv, sing = oracle.lu32_block(A, b=b)
+    assert sing == 0
+    L, U, perm = _lu_parts(LU, piv)
+    A32 = A.astype(np.float32).astype(np.float64)
+    u = 2.0 ** -24
+    gamma = n * u / (1 - n * u)
+    err = np.abs(A32[perm] - L @ U)
+    assert np.all(err <= gamma * (np.abs(L) @ np.abs(U)) + 1e-300)
+    assert np.abs(np.tril(LU, -1)).max(initial=0.0) <= 1.0  # partial pivoting: |l_ij| <= 1
+
+
+def test_lu32_pivots_match_binary64_gepp():
+    for seed in range(3):
+        A = np.random.default_rng(70 + seed).standard_normal((120, 120))
+        _, piv32, _ = oracle.lu32_block(A, b=16)
+        _, piv64, _ = oracle.lu_factor(A)
+        np.testing.assert_array_equal(piv32, piv64)
+
+
+def _exact_lu_system(n, seed):
+    """A = L0 U0 with dyadic |l| <= 1/2 (no row interchange) and integer U0:
+    every intermediate of elimination is exact in binary32."""
+    rng = np.random.default_rng(seed)
+    L0 = np.tril(rng.choice([-0.5, -0.25, 0.0, 0.25, 0.5], size=(n, n)), -1) + np.eye(n)
+    U0 = np.triu(rng.integers(-3, 4, size=(n, n)).astype(float), 1) + np.diag(rng.choice([-8.0, 8.0], n))
+    return L0, U0, L0 @ U0
+
+
+@pytest.mark.parametrize("b", [1, 4, 16, 24])
+def test_lu32_reproduces_an_exact_factorization(b):
+    n = 24
+    L0, U0, A = _exact_lu_system(n, 80)
+    LU, piv, sing = oracle.lu32_block(A, b=b)
+    assert sing == 0
+    np.testing.assert_array_equal(piv, np.arange(n))
+    L, U, _ = _lu_parts(LU, piv)
+    np.testing.assert_array_equal(L, L0)
+    np.testing.assert_array_equal(U, U0)
+
+
+def test_lu32_apply_is_the_two_triangular_solves():
+    from scipy.linalg import solve_triangular
+
+    n = 150
+    A = np.random.default_rng(90).standard_normal((n, n))
+    LU, piv, _ = oracle.lu32_block(A, b=16)
+    L, U, perm = _lu_parts(LU, piv)
+    v = np.random.default_rng(91).standard_normal(n)
+    z = oracle.lu32_apply(LU, piv, v)
+    ref = solve_triangular(U, solve_triangular(L, v[perm], lower=True, unit_diagonal=True))
+    np.testing.assert_allclose(z, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_gmres_ir_lu_exact_preconditioner_and_special_cases():
+    n = 24
+    _, _, A = _exact_lu_system(n, 81)
+    xs = np.random.default_rng(82).standard_normal(n)
+    b = A @ xs
+    # M = A exactly: one preconditioned GMRES step per refinement step, and
+    # the first correction already meets binary64 accuracy
+    x, info = oracle.gmres_ir_lu(A, b, tol=1e-14)
+    assert info["status_name"] == "ok" and info["outer_iters"] == 1 and info["inner_iters"] == 1
+    np.testing.assert_allclose(x, xs, rtol=1e-12)
+    x, info = oracle.gmres_ir_lu(A, np.zeros(n), x0=np.ones(n), tol=1e-12)
+    assert info["status_name"] == "ok" and info["outer_iters"] == 0 and not x.any()
+    S = A.copy()
+    S[:, 5] = 0.0
+    _, info = oracle.gmres_ir_lu(S, b, tol=1e-12)
+    assert info["status_name"] == "breakdown"
+
+
+def test_gmres_ir_lu_converges_where_gmres_stalls():
+    from workloads import nonsym_swept_problem
+
+    p = nonsym_swept_problem(300, 1e6, seed=1, config_id=2)
+    _, ig = oracle.gmres(p.A, p.b, tol=1e-10, restart=50, max_iter=1500)
+    assert ig["status_name"] == "maxiter"
+    x, info = oracle.gmres_ir_lu(p.A, p.b, tol=1e-12)
+    assert info["status_name"] == "ok" and info["outer_iters"] <= 4, info
+    assert oracle.metrics(p.A, p.b, x)["eta_inf"] <= 1e-12
+    xs = np.linalg.solve(p.A, p.b)
+    assert np.linalg.norm(x - xs) <= 1e6 * 1e-12 * 10 * np.linalg.norm(xs)
