@@ -79,6 +79,12 @@ extern "C" {
 #define KS_FP64 0        /* everything in binary64                               */
 #define KS_IR_FP32 1     /* inner solve on binary32 A, binary64 refinement       */
 #define KS_IR_BF16 2     /* inner solve on bfloat16 A (fp32 accumulation)        */
+#define KS_IR_LU32 3     /* GMRES-IR: binary64 refinement around GMRES(m) in
+                            binary64, left-preconditioned by a binary32 block LU
+                            with partial pivoting (the direct-methods section's
+                            block algorithm) computed in ks_create; method
+                            KS_GMRES, nrhs 1, n <= 4096.  A factorization with a
+                            zero pivot makes ks_solve return KS_BREAKDOWN     */
 
 /* element types for the kernel-level entry points */
 #define KS_DT_F64 0
@@ -104,7 +110,7 @@ typedef struct {
     int32_t method;     /* KS_CG, KS_GMRES, KS_BICGSTAB, KS_JACOBI or
                            KS_GAUSS_SEIDEL                                       */
     int64_t lda;        /* leading dimension of A in elements, >= n               */
-    int32_t precision;  /* KS_FP64, KS_IR_FP32 or KS_IR_BF16                      */
+    int32_t precision;  /* KS_FP64, KS_IR_FP32, KS_IR_BF16 or KS_IR_LU32           */
     int32_t max_iter;   /* FP64: A*v products in the Krylov loop over the whole
                            solve; IR: per inner solve                              */
     double tol;         /* FP64: stop at ||b - A x||_2 <= tol ||b||_2 (checked on
@@ -260,6 +266,18 @@ int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *d_A, const void
 int ks_symv_workspace_bytes(int32_t n, size_t *bytes);
 int ks_symv(int32_t n, int64_t lda, const double *d_A, const double *d_x, double *d_y,
             void *d_ws, size_t ws_bytes, void *stream);
+
+/* Binary32 block LU with partial pivoting (the direct-methods section's block
+ * algorithm, column blocks of 16; the factorization GMRES-IR uses): d_LU
+ * (n x lda_lu floats, row-major, lda_lu >= n) receives the binary32 rounding
+ * of A factored in place, L (unit diagonal implied) below the diagonal and U
+ * on and above it; d_piv[k] (n int32) is the row interchanged with row k at
+ * step k, 0-based (whole rows, so P A = L U).  1 <= n <= 4096, else KS_EINVAL.
+ * *info = 0, or 1 + the first column whose pivot is zero (the factorization
+ * goes on past it).  Allocates and frees one device word; returns after the
+ * factorization has finished on `stream`. */
+int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, float *d_LU,
+                   int32_t *d_piv, int32_t *info, void *stream);
 
 /* Convert an n x n binary64 matrix (lda_src) into dst_dtype (KS_DT_F32:
  * round to nearest even; KS_DT_BF16: round to binary32, then to bfloat16,

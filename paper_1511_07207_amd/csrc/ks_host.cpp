@@ -48,6 +48,10 @@ struct ks_solver {
     float *v32 = nullptr;
     double *sy = nullptr;     // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
     bool fz = false;          // fused small-n binary64 CG (one launch per iteration)
+    // GMRES-IR: the binary32 LU in A_low, its pivots, permutation, and the
+    // first zero pivot's column + 1 (0: nonsingular)
+    int *lu_piv = nullptr, *lu_perm = nullptr, *lu_info = nullptr;
+    int lu_sing = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> tev;  // timing event pairs of A*v launches
     int tev_used = 0;
@@ -574,6 +578,105 @@ int run_gauss_seidel(ks_solver *s, const double *b, double *x, double tol, int m
     return KS_OK;
 }
 
+// ------------------------------------------------------------ GMRES-IR
+// The binary32 block LU of A (in A_low) and the permutation of its pivots:
+// (P v)_i = v[perm[i]], composed on the host from the row interchanges.
+int lu_setup(ks_solver *s) {
+    const int n = s->n;
+    hipStream_t sm = s->stream;
+    const size_t ln = (size_t)round_up(n, 64);
+    s->lu_piv = (int *)(s->ws + s->L.lu_off);
+    s->lu_perm = s->lu_piv + ln;
+    s->lu_info = s->lu_perm + ln;
+    HIPCHK(hipMemsetAsync(s->lu_info, 0, sizeof(int), sm));
+    HIPCHK(launch_lu_factor(n, s->L.lda_low, (float *)s->A_low, s->lu_piv, s->lu_info, sm));
+    std::vector<int> piv(n), perm(n);
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(piv.data(), s->lu_piv, sizeof(int) * n, hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(&info, s->lu_info, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int k = 0; k < n; ++k) {
+        if (piv[k] < 0 || piv[k] >= n) return KS_EHIP;  // cannot happen; never trust a bad index
+        std::swap(perm[k], perm[piv[k]]);
+    }
+    HIPCHK(hipMemcpyAsync(s->lu_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    s->lu_sing = info;
+    return KS_OK;
+}
+
+// Inner solve of GMRES-IR: restarted GMRES(m) in binary64 on
+// M^-1 A d = M^-1 rhs from d = 0 (M = P^-1 L U in binary32), relative
+// tolerance tol on the preconditioned residual, at most max_iter products.
+// Every Arnoldi step is the product, M^-1 (the substitutions), then the
+// Gram-Schmidt passes and the Givens rotation of the plain GMRES.
+int run_gmres_lu(ks_solver *s, const double *rhs, double *d, double tol, int max_iter,
+                 Outcome *out) {
+    const int n = s->n, m = s->ga.m, ldv = s->L.ldv;
+    hipStream_t sm = s->stream;
+    State *st = s->st_in;
+    const float *LU = (const float *)s->A_low;
+    const int64_t ldl = s->L.lda_low;
+    double *w = s->vec64(0), *V = s->vec64(1);
+    double *t = s->vec64(s->L.nv64 - 2);
+    HIPCHK(launch_fill<double>(n, d, 0.0, sm));
+    // thresh = tol ||M^-1 rhs||; the residual of d = 0 is M^-1 rhs itself
+    HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, rhs, w, t, s->P.g, sm));
+    HIPCHK(launch_vec_stats<double>(n, w, tol, st, sm, 0));
+    HIPCHK(launch_lu_res_finish(n, st, s->P.g, sm));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const State *h = &s->host[1];
+    int cycles = 0;
+    for (;;) {
+        const int f = h->flags;
+        if (f & F_TRUE_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+        if (f & F_TRUE_OK) {
+            out->status = KS_OK;
+            break;
+        }
+        if (h->iters >= max_iter) {
+            out->status = KS_MAXITER;
+            break;
+        }
+        HIPCHK(launch_gm_begin<double>(n, w, V, st, s->ga, sm));
+        // one step per host check: a stopped step would still run the
+        // substitutions (they do not test the stop flag)
+        for (int k = 0; k < m; ++k) {
+            HIPCHK((launch_gm_matvec<double, double>(n, s->lda, s->A, V + (size_t)k * ldv, w, st,
+                                                     s->P, sm)));
+            HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, sm));
+            HIPCHK(launch_gm_ortho<double>(n, ldv, V, w, k, st, s->ga, s->P, gemv_blocks<double>(n),
+                                           max_iter, sm));
+            if ((rc = sync_state(s))) return rc;
+            if (h->flags & F_STOP) break;
+        }
+        HIPCHK(launch_gm_finish<double>(n, ldv, V, d, st, s->ga, sm));
+        // the preconditioned residual M^-1 (rhs - A d)
+        HIPCHK((launch_residual_rows<double, double>(n, s->lda, s->A, rhs, d, w, st, s->P.g, 0, sm)));
+        HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, sm));
+        HIPCHK(launch_lu_res_finish(n, st, s->P.g, sm));
+        if ((rc = sync_state(s))) return rc;
+        ++cycles;
+        const int f2 = h->flags;
+        if (f2 & F_BREAK) {
+            out->status = KS_BREAKDOWN;
+            break;
+        }
+        if (f2 & F_NONFIN) {
+            out->status = KS_NONFINITE;
+            break;
+        }
+    }
+    out->iters = h->iters;
+    out->restarts = std::max(0, cycles - 1);
+    return KS_OK;
+}
+
 // Metrics of the returned x from the State the solve left behind: every exit
 // path of the drivers ends with a true-residual kernel and a sync, so the
 // host mirror holds ||b||, ||r|| and the infinity norms of r, x and b.
@@ -855,6 +958,15 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
     }
     const double binf = h->binf, bnorm = h->bnorm;
     s->anorm_inf = h->anorm_inf;
+    if (prec == KS_IR_LU32 && s->lu_sing) {
+        // the binary32 factorization met a zero pivot
+        info->rel_res = h->res / bnorm;
+        const double den0 = s->anorm_inf * h->xinf + binf;
+        info->backward_err = den0 > 0.0 ? h->resinf / den0 : h->resinf;
+        info->precision_used = prec;
+        o->status = KS_BREAKDOWN;
+        return KS_OK;
+    }
     for (;;) {
         const double den = s->anorm_inf * h->xinf + binf;
         const double eta = den > 0.0 ? h->resinf / den : h->resinf;
@@ -897,6 +1009,24 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
             if (o->status == KS_OK && o64.status != KS_OK && info->backward_err > s->p.tol)
                 o->status = o64.status;
             break;
+        }
+        if (prec == KS_IR_LU32) {
+            // GMRES-IR: correction from the preconditioned GMRES in binary64
+            Outcome oi;
+            double *dl = s->vec64(s->L.nv64 - 3);
+            if ((rc = run_gmres_lu(s, r64, dl, s->p.inner_tol, s->p.max_iter, &oi))) return rc;
+            total_iters += oi.iters;
+            ++outer;
+            if (oi.status == KS_BREAKDOWN || oi.status == KS_NONFINITE) {
+                prec = KS_FP64;
+                bad = 0;
+                eta_prev = INFINITY;
+                continue;
+            }
+            HIPCHK(launch_lu_xupdate(n, x, dl, sm));
+            HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0, sm)));
+            if ((rc = sync_state(s))) return rc;
+            continue;
         }
         if (prec == KS_IR_FP32 && s->p.precision == KS_IR_BF16 && !s->fb_ready) {
             HIPCHK(launch_convert(n, s->lda, s->A, KS_DT_F32, s->L.lda_low, s->A_fb, sm));
@@ -1082,11 +1212,15 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
     if (p->precision != KS_FP64) {
         s->A_low = s->ws + L.alow_off;
         if (p->precision == KS_IR_BF16) s->A_fb = (float *)(s->ws + L.afb_off);
-        const int dt = (p->precision == KS_IR_FP32) ? KS_DT_F32 : KS_DT_BF16;
+        const int dt = (p->precision == KS_IR_BF16) ? KS_DT_BF16 : KS_DT_F32;
         if (launch_convert(p->n, s->lda, s->A, dt, L.lda_low, s->A_low, sm) != hipSuccess) {
             ks_free(s);
             return KS_EHIP;
         }
+    }
+    if (p->precision == KS_IR_LU32 && (rc = lu_setup(s))) {
+        ks_free(s);
+        return rc;
     }
     *out = s;
     return KS_OK;
@@ -1225,6 +1359,27 @@ int ks_symv(int32_t n, int64_t lda, const double *dA, const double *d_x, double 
     if (ws_bytes < sy_ws_doubles(n) * sizeof(double)) return KS_ENOMEM;
     HIPCHK(launch_symv(n, lda, dA, d_x, d_y, (double *)d_ws, nullptr, nullptr, nullptr,
                        (hipStream_t)stream));
+    return KS_OK;
+}
+
+int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, float *d_LU,
+                   int32_t *d_piv, int32_t *info, void *stream) {
+    if (n < 1 || n > LU_MAX_N || lda < n || lda_lu < n || !d_A || !d_LU || !d_piv || !info)
+        return KS_EINVAL;
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t sm = (hipStream_t)stream;
+    int *dinfo = nullptr;
+    HIPCHK(hipMalloc((void **)&dinfo, sizeof(int)));
+    int h = 0;
+    hipError_t e = hipMemsetAsync(dinfo, 0, sizeof(int), sm);
+    if (e == hipSuccess) e = launch_convert(n, lda, d_A, KS_DT_F32, lda_lu, d_LU, sm);
+    if (e == hipSuccess) e = launch_lu_factor(n, lda_lu, d_LU, d_piv, dinfo, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, dinfo, sizeof(int), hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    const hipError_t ef = hipFree(dinfo);
+    if (e != hipSuccess || ef != hipSuccess) return KS_EHIP;
+    *info = h;
     return KS_OK;
 }
 

@@ -182,6 +182,24 @@ hipError_t launch_gs_upper(int n, int64_t lda, const double *A, const double *b,
 hipError_t launch_gs_sweep(int n, int64_t lda, const double *A, double *x, double *c,
                            const State *st, hipStream_t s);
 
+// Binary32 block LU with partial pivoting (GMRES-IR preconditioner): column
+// blocks of LU_NB, n <= LU_MAX_N (the panel block keeps its panel in
+// registers).  factor: LU holds A in binary32 on entry, L (unit, below the
+// diagonal) and U on return, piv[k] the row swapped with row k, info[0] = 1 +
+// the first zero pivot's column (0 if none; must be 0 on entry).
+constexpr int LU_NB = 16;
+constexpr int LU_MAX_N = 4096;
+hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, int *info, hipStream_t s);
+// dst = U^-1 L^-1 P src (perm: (P v)_i = v[perm[i]]), t scratch; dst may be
+// src; the squares of dst left in `partial` as the GMRES product leaves them
+hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm, const double *src,
+                           double *dst, double *t, double *partial, hipStream_t s);
+// ||w||_2 from launch_lu_apply's partials into st->rho / res, with the
+// true-residual flags against st->thresh
+hipError_t launch_lu_res_finish(int n, State *st, const double *partial, hipStream_t s);
+// x += d
+hipError_t launch_lu_xupdate(int n, double *x, const double *d, hipStream_t s);
+
 // CG iteration, three kernels:
 //   q = A p (sigma partials);  x += alpha p, r -= alpha q (rho' partials);
 //   convergence / limit checks, p = r + beta p.
@@ -204,6 +222,12 @@ hipError_t launch_cg_begin(int n, const T *r, T *p, State *st, hipStream_t s);
 // (may be null) are recorded around the matrix-vector product.
 template <typename T>
 hipError_t launch_gm_begin(int n, const T *r, T *V, State *st, GmArrays ga, hipStream_t s);
+// The Arnoldi step after the product w = A v_k: the two Gram-Schmidt passes,
+// ||w||, the Givens rotation and v_{k+1} (launch_gm_step = product + this).
+// ngemv: the number of ||w||^2 partials the product left in P.g.
+template <typename T>
+hipError_t launch_gm_ortho(int n, int ldv, T *V, T *w, int k, State *st, GmArrays ga, Partials P,
+                           int ngemv, int max_iter, hipStream_t s);
 template <typename TA, typename T>
 hipError_t launch_gm_step(int n, int64_t lda, const TA *A, int ldv, T *V, T *w, int k,
                           State *st, GmArrays ga, Partials P, int max_iter, hipStream_t s,

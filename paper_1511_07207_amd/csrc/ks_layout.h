@@ -41,6 +41,8 @@ struct Layout {
     size_t mr_off = 0, mr_block_elems = 0, mr_cols_off = 0, mr_part_off = 0, mr_part_count = 0;
     // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
     size_t sy_off = 0, sy_bytes = 0;
+    // GMRES-IR: pivots, permutation and info of the binary32 LU
+    size_t lu_off = 0;
     size_t total = 0;
     size_t total_borrowed = 0;
 };
@@ -57,7 +59,11 @@ inline bool valid_params(const ks_params *p) {
     if ((p->method == KS_JACOBI || p->method == KS_GAUSS_SEIDEL) &&
         (p->precision != KS_FP64 || p->nrhs != 1 || (p->flags & KS_FLAG_SYMMETRIC)))
         return false;
-    if (p->precision < KS_FP64 || p->precision > KS_IR_BF16) return false;
+    if (p->precision < KS_FP64 || p->precision > KS_IR_LU32) return false;
+    // GMRES-IR with the binary32 LU: GMRES, one right-hand side, n <= LU_MAX_N
+    if (p->precision == KS_IR_LU32 &&
+        (p->method != KS_GMRES || p->nrhs != 1 || p->n > LU_MAX_N || (p->flags & KS_FLAG_SYMMETRIC)))
+        return false;
     if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return false;
     if (p->max_iter < 0) return false;
     if (p->method == KS_GMRES && (p->restart < 1 || p->restart > KS_MAX_RESTART)) return false;
@@ -100,11 +106,14 @@ inline Layout make_layout(const ks_params *p) {
     const bool fused = p->method == KS_CG && p->nrhs == 1 && n <= FZ_MAX_N;
     L.nv64 = fused ? 6 : nkry;
     if (p->precision != KS_FP64) L.nv64 += 1;
+    // GMRES-IR: the inner GMRES runs in binary64 (its w, V), plus the
+    // correction d and the preconditioner's scratch t
+    if (p->precision == KS_IR_LU32) L.nv64 += 2;
     L.v64_off = off;
     off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
     // binary32 vectors of the inner solve: rhs, d, then the method's vectors
     L.nv32 = 0;
-    if (p->precision != KS_FP64) L.nv32 = 2 + nkry;
+    if (p->precision == KS_IR_FP32 || p->precision == KS_IR_BF16) L.nv32 = 2 + nkry;
     L.v32_off = off;
     off = align_up(off + (size_t)L.nv32 * L.ldv * sizeof(float));
     if (p->nrhs > 1) {
@@ -128,8 +137,13 @@ inline Layout make_layout(const ks_params *p) {
         L.sy_off = off;
         off = align_up(off + L.sy_bytes);
     }
+    if (p->precision == KS_IR_LU32) {
+        // pivots, the permutation, the factorization's info word
+        L.lu_off = off;
+        off = align_up(off + (2 * (size_t)round_up(n, 64) + 64) * sizeof(int));
+    }
     L.lda_low = round_up(n, 64);
-    if (p->precision == KS_IR_FP32) {
+    if (p->precision == KS_IR_FP32 || p->precision == KS_IR_LU32) {
         L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
     } else if (p->precision == KS_IR_BF16) {
         L.alow_bytes = (size_t)n * L.lda_low * sizeof(uint16_t);

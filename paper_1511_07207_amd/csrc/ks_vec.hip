@@ -201,10 +201,16 @@ hipError_t launch_gm_step(int n, int64_t lda, const TA *A, int ldv, T *V, T *w, 
     if ((e = launch_gm_matvec<TA, T>(n, lda, A, V + (size_t)k * ldv, w, st, P, s)) != hipSuccess)
         return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
-    const int nb = cgs_blocks(n), ng = gemv_blocks<TA>(n);
-    gm_cgs_kernel<T, 0><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ng);
-    gm_cgs_kernel<T, 1><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ng);
-    gm_cgs_kernel<T, 2><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ng);
+    return launch_gm_ortho<T>(n, ldv, V, w, k, st, ga, P, gemv_blocks<TA>(n), max_iter, s);
+}
+
+template <typename T>
+hipError_t launch_gm_ortho(int n, int ldv, T *V, T *w, int k, State *st, GmArrays ga, Partials P,
+                           int ngemv, int max_iter, hipStream_t s) {
+    const int nb = cgs_blocks(n);
+    gm_cgs_kernel<T, 0><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ngemv);
+    gm_cgs_kernel<T, 1><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ngemv);
+    gm_cgs_kernel<T, 2><<<nb, CGS_NT, 0, s>>>(n, ldv, V, w, k, st, ga, P, ngemv);
     gm_givens_kernel<T><<<vec_blocks(n), VEC_NT, 0, s>>>(n, w, V + (size_t)(k + 1) * ldv, k, st,
                                                           ga, P.nrm, nb, max_iter);
     return hipGetLastError();
@@ -297,6 +303,10 @@ hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipS
 KS_INST_T(double)
 KS_INST_T(float)
 
+template hipError_t launch_gm_ortho<double>(int, int, double *, double *, int, State *, GmArrays,
+                                            Partials, int, int, hipStream_t);
+template hipError_t launch_gm_ortho<float>(int, int, float *, float *, int, State *, GmArrays,
+                                           Partials, int, int, hipStream_t);
 template hipError_t launch_gm_step<double, double>(int, int64_t, const double *, int, double *,
                                                    double *, int, State *, GmArrays, Partials,
                                                    int, hipStream_t, hipEvent_t, hipEvent_t);

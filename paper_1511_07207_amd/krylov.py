@@ -17,7 +17,8 @@ from . import _native as N
 
 _METHODS = {"cg": N.KS_CG, "gmres": N.KS_GMRES, "bicgstab": N.KS_BICGSTAB,
             "jacobi": N.KS_JACOBI, "gauss_seidel": N.KS_GAUSS_SEIDEL}
-_PRECISIONS = {"fp64": N.KS_FP64, "fp32": N.KS_IR_FP32, "bf16": N.KS_IR_BF16}
+_PRECISIONS = {"fp64": N.KS_FP64, "fp32": N.KS_IR_FP32, "bf16": N.KS_IR_BF16,
+               "lu32": N.KS_IR_LU32}
 _PREC_NAMES = {v: k for k, v in _PRECISIONS.items()}
 
 
@@ -264,6 +265,20 @@ def symv(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
     N.check(N.lib().ks_symv(int(n), int(A.stride(0)), _ptr(A), _ptr(x), _ptr(y), _ptr(workspace),
                             sz.value, _stream_handle()), "ks_symv")
     return y
+
+
+def lu32_factor(A: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor, int]:
+    """Binary32 block LU with partial pivoting of a float64 matrix.
+    Returns (LU float32 n x n, piv int32, info)."""
+    if A.dtype != torch.float64:
+        raise TypeError("lu32_factor: A must be float64")
+    n = A.shape[0]
+    LU = torch.empty((n, n), dtype=torch.float32, device=A.device)
+    piv = torch.empty(n, dtype=torch.int32, device=A.device)
+    info = ctypes.c_int32(0)
+    N.check(N.lib().ks_lu32_factor(int(n), int(A.stride(0)), _ptr(A), int(n), _ptr(LU), _ptr(piv),
+                                   ctypes.byref(info), _stream_handle()), "ks_lu32_factor")
+    return LU, piv, int(info.value)
 
 
 def convert(A: torch.Tensor, dtype: torch.dtype, lda_dst: int | None = None) -> torch.Tensor:

@@ -115,6 +115,37 @@ def test_stationary_parameters_on_host():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_gmres_ir_lu_parameters_on_host():
+    # GMRES-IR with the binary32 LU: GMRES only, one right-hand side,
+    # n <= 4096; the workspace holds the binary32 factors (n x round_up(n, 64))
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    p = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(p), 1000, N.KS_GMRES) == 0
+    p.precision = N.KS_IR_LU32
+    sz, sz64 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+    q = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(q), 1000, N.KS_GMRES) == 0
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(q), ctypes.byref(sz64)) == 0
+    assert sz.value >= sz64.value + 4 * 1000 * 1024
+    for method in (N.KS_CG, N.KS_BICGSTAB, N.KS_JACOBI):
+        r = N.KsParams()
+        assert L.ks_params_init(ctypes.byref(r), 1000, method) == 0
+        r.precision = N.KS_IR_LU32
+        assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == N.KS_EINVAL
+    r = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(r), 4097, N.KS_GMRES) == 0
+    r.precision = N.KS_IR_LU32
+    assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == N.KS_EINVAL
+    r.n = r.lda = 4096
+    assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == 0
+    info = ctypes.c_int32(0)
+    assert L.ks_lu32_factor(4097, 4097, None, 4097, None, None, ctypes.byref(info), None) == N.KS_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
 def test_symmetric_flag_and_symv_on_host():
     from paper_1511_07207_amd import _native as N
 
