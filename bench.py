@@ -296,6 +296,53 @@ def leg_f3(dev, n):
     return out
 
 
+def leg_f4(dev):
+    """GMRES-IR with the binary32 block LU: the factorization (in create) at
+    the paper's direct-method sizes, and solves of the nonsymmetric kappa = 1e6
+    family to backward error 1e-12, beside binary64 GMRES(50) on the same
+    systems (which stalls there)."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_swept_problem
+
+    out = {"system": "diag(lambda) + 0.25 G/sqrt(n), lambda log-uniform [1, kappa]",
+           "kappa": 1e6, "eta_target": 1e-12}
+    for m in (1000, 2000, 3000, 4096):
+        prob = nonsym_swept_problem(m, 1e6, seed=0, config_id=8, backend="torch", device="cuda")
+        x = torch.zeros(m, dtype=torch.float64, device=dev)
+        creates = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = krylov.Solver(prob.A, method="gmres", restart=30, precision="lu32", tol=1e-12)
+            torch.cuda.synchronize()
+            creates.append((time.perf_counter() - t0) * 1e3)
+            if len(creates) < 3:
+                s.close()
+        s.solve(prob.b, out=x.zero_())
+        lat = []
+        for _ in range(3):
+            (_, info), dt = _timed(lambda: s.solve(prob.b, out=x.zero_()))
+            lat.append(dt * 1e3)
+        s.close()
+        tc = statistics.median(creates)
+        r = {"create_ms": round(tc, 3),
+             "factor_gflops": round(2.0 * m ** 3 / 3.0 / (tc * 1e-3) / 1e9, 1),
+             "status": info["status_name"], "outer": info["outer_iters"], "inner": info["iters"],
+             "eta_inf": info["backward_err"], "solve_ms": round(statistics.median(lat), 3)}
+        s64 = krylov.Solver(prob.A, method="gmres", restart=50, tol=1e-12, stop_backward=True,
+                            max_iter=1500)
+        (_, i64), dt = _timed(lambda: s64.solve(prob.b, out=x.zero_()))
+        s64.close()
+        r["gmres50_fp64"] = {"status": i64["status_name"], "iters": i64["iters"],
+                             "eta_inf": i64["backward_err"], "ms": round(dt * 1e3, 3)}
+        out[str(m)] = r
+        del prob, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_c2p(dev, n):
     """The CG solve of the main step with either product: general GEMV (all of
     A per iteration) and the symmetric lower-triangle product."""
@@ -460,9 +507,9 @@ def main():
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
-    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1,f3",
+    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1,f3,f4",
                     help="extra measurements after the timed steps (comma list of "
-                         "c1,c2p,c3,c4,c5,f1,f3; 'none' for the main step only)")
+                         "c1,c2p,c3,c4,c5,f1,f3,f4; 'none' for the main step only)")
     ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -638,6 +685,8 @@ def main():
                 legs[name] = leg_f1(dev, n)
             elif name == "f3":
                 legs[name] = leg_f3(dev, n)
+            elif name == "f4":
+                legs[name] = leg_f4(dev)
             elif name == "c2p":
                 legs[name] = leg_c2p(dev, n)
             else:
