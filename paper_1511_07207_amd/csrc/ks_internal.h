@@ -118,8 +118,8 @@ __host__ __device__ inline int gemv_blocks_max(int n) { return div_up(n, 2); }
 
 // Symmetric product (lower triangle only): SY_T x SY_T tiles, one block of
 // SY_NT threads per tile; the workspace holds two SY_T-vectors per tile.
-constexpr int SY_T = 128;
-constexpr int SY_NT = 256;
+constexpr int SY_T = 256;
+constexpr int SY_NT = 512;
 __host__ __device__ inline int sy_tiles(int n) {
     const int t = div_up(n, SY_T);
     return t * (t + 1) / 2;

@@ -3,16 +3,18 @@
 // whole cost of a CG iteration on a dense SPD matrix (the Krylov section
 // counts one matrix-vector product per CG iteration as its Theta(n^2) part).
 //
-// Tiling.  The lower triangle is cut into SY_T x SY_T tiles (I, J), I >= J;
-// one block of SY_NT threads (4 wave64s) reads one tile once and uses every
-// element twice:
+// Tiling.  The lower triangle is cut into SY_T x SY_T tiles (I, J), I >= J
+// (SY_T = 256); one block of SY_NT threads (8 wave64s) reads one tile once
+// and uses every element twice:
 //   row part     y_I += A_IJ x_J      (for the rows of tile row I)
 //   column part  y_J += A_IJ' x_I     (for the columns of tile column J)
 // On a diagonal tile the row part takes the elements with c <= r and the
 // column part those with c < r, so each element of A is counted exactly as
 // often as in the full product; the tile's elements above the diagonal are
 // loaded with the rest of the tile (they are inside the matrix) and
-// discarded by a select, so their values never reach the result.
+// discarded by a select, so their values never reach the result; the
+// diagonal tile's upper-right quadrant (rows < SY_T/2, columns >= SY_T/2) lies
+// wholly above the diagonal and is not read.
 //
 // Tile paths.  Tiles whose rows and columns lie inside the matrix (all but
 // the last tile row when SY_T does not divide n) read A through a buffer
@@ -23,8 +25,9 @@
 // tiles instead of forming a tail.
 //
 // Each wave reads SY_RPW rows of the tile, interleaved with the other waves;
-// one wave instruction loads one 1 KiB tile row (64 lanes x 16 bytes, two
-// columns per lane), nontemporal as in the general product.  The x values of
+// a tile row is two 1 KiB halves, one wave instruction each (64 lanes x 16
+// bytes: lane l holds columns 2l, 2l + 1 of each half), nontemporal as in the
+// general product.  The x values of
 // a wave's rows are wave-uniform (scalar loads), so no barrier precedes the
 // loads of A.  The column part accumulates per lane (its columns
 // are fixed) and is summed over the 4 waves through LDS.  The row part of each
@@ -37,7 +40,10 @@
 // parts of its tile row and the column parts of its tile column in a fixed
 // order (deterministic, no atomics), and writes y (and, for CG, the partials
 // of p'q).  The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A
-// read, i.e. 3% of the product's bytes at SY_T = 128.
+// read, i.e. 1.6% of the product's bytes at SY_T = 256.  The workspace writes
+// are what the tile size trades against: measured on MI355X at n = 16384,
+// storing them cost ~15 us of a 173 us product with 128-wide tiles and ~6 us
+// with 256-wide ones, whose finishing sum also reads half as much.
 #include "ks_device.h"
 
 namespace ks {
@@ -52,12 +58,14 @@ constexpr int SY_NT_POLICY = 2;
 
 constexpr int SY_WAVES = SY_NT / WAVE;
 constexpr int SY_RPW = SY_T / SY_WAVES;  // rows per wave in a tile (32)
-constexpr int SY_UNR_INT = 8;               // rows per group, interior tiles
+constexpr int SY_H = 2;                  // 1 KiB halves per tile row
+constexpr int SY_HW = SY_T / SY_H;       // columns per half (128)
+constexpr int SY_UNR_INT = 8;            // rows per group, interior tiles
 constexpr int SY_UNR_SPC = 8;            // rows per group, diagonal / edge tiles
 constexpr int SY_FIN = 64;               // elements per block of the finishing kernel
 constexpr int SY_FACC = 8;               // loads in flight per wave of the finishing kernel
 constexpr int SY_FWAVES = 16;            // waves per block of the finishing kernel
-static_assert(SY_T == 2 * WAVE, "one wave instruction covers one tile row");
+static_assert(SY_HW == 2 * WAVE, "one wave instruction covers one half of a tile row");
 static_assert(SY_RPW % SY_UNR_INT == 0 && SY_RPW % SY_UNR_SPC == 0, "groups tile the rows");
 static_assert(SY_T % SY_FIN == 0, "a finishing block stays inside one tile column");
 
@@ -107,10 +115,11 @@ __device__ __forceinline__ double sy_rows_reduce(double (&v)[U], int lane) {
 // blocks per wave for the same bytes).
 __device__ __forceinline__ int sy_row(int w, int k) { return w + SY_WAVES * k; }
 
-// Shared set-up of a tile block.
+// Shared set-up of a tile block.  The lane's columns inside the tile:
+// h * SY_HW + lc and h * SY_HW + lc + 1 for the halves h = 0, 1.
 struct SyTile {
-    int I, J, t, lane, w, r0, c0, lc, c;
-    double xj0, xj1;
+    int I, J, t, lane, w, r0, c0, lc;
+    double xj[SY_H][2];
 };
 
 __device__ __forceinline__ SyTile sy_setup(int n, int I, int J, const double *__restrict__ x) {
@@ -122,10 +131,13 @@ __device__ __forceinline__ SyTile sy_setup(int n, int I, int J, const double *__
     T.w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     T.r0 = I * SY_T;
     T.c0 = J * SY_T;
-    T.lc = 2 * T.lane;  // the lane's two columns inside the tile: lc, lc + 1
-    T.c = T.c0 + T.lc;
-    T.xj0 = T.c < n ? x[T.c] : 0.0;
-    T.xj1 = T.c + 1 < n ? x[T.c + 1] : 0.0;
+    T.lc = 2 * T.lane;
+#pragma unroll
+    for (int h = 0; h < SY_H; ++h) {
+        const int c = T.c0 + h * SY_HW + T.lc;
+        T.xj[h][0] = c < n ? x[c] : 0.0;
+        T.xj[h][1] = c + 1 < n ? x[c + 1] : 0.0;
+    }
     return T;
 }
 
@@ -133,24 +145,31 @@ __device__ __forceinline__ SyTile sy_setup(int n, int I, int J, const double *__
 // already loaded: row parts reduced over the lanes into `rows` (LDS), column
 // parts accumulated.  xr[u]: x at the group's rows (wave-uniform values).
 template <int U, bool DIAG>
-__device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&a)[U],
-                                         const double (&xr)[U], double *rows, double &ca0,
-                                         double &ca1) {
+__device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&a)[U][SY_H],
+                                         const double (&xr)[U], double *rows,
+                                         double (&ca)[SY_H][2]) {
     double racc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int lr = sy_row(T.w, k0 + u);
-        double ar0 = a[u].x, ar1 = a[u].y, ac0 = a[u].x, ac1 = a[u].y;
-        if constexpr (DIAG) {
-            // row part: c <= r; column part: c < r
-            ar0 = (T.lc <= lr) ? ar0 : 0.0;
-            ar1 = (T.lc + 1 <= lr) ? ar1 : 0.0;
-            ac0 = (T.lc < lr) ? ac0 : 0.0;
-            ac1 = (T.lc + 1 < lr) ? ac1 : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int h = 0; h < SY_H; ++h) {
+            double ar0 = a[u][h].x, ar1 = a[u][h].y, ac0 = ar0, ac1 = ar1;
+            if constexpr (DIAG) {
+                // row part: c <= r; column part: c < r
+                const int c = h * SY_HW + T.lc;
+                ar0 = (c <= lr) ? ar0 : 0.0;
+                ar1 = (c + 1 <= lr) ? ar1 : 0.0;
+                ac0 = (c < lr) ? ac0 : 0.0;
+                ac1 = (c + 1 < lr) ? ac1 : 0.0;
+            }
+            s = fma(ar0, T.xj[h][0], s);
+            s = fma(ar1, T.xj[h][1], s);
+            ca[h][0] = fma(ac0, xr[u], ca[h][0]);
+            ca[h][1] = fma(ac1, xr[u], ca[h][1]);
         }
-        racc[u] = fma(ar1, T.xj1, ar0 * T.xj0);
-        ca0 = fma(ac0, xr[u], ca0);
-        ca1 = fma(ac1, xr[u], ca1);
+        racc[u] = s;
     }
     const double v = sy_rows_reduce<U>(racc, T.lane);
     constexpr int LPR = WAVE / U;  // lanes per row after the reduction
@@ -158,15 +177,19 @@ __device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&
 }
 
 // The tile's output, row parts then column parts (the latter summed over the
-// waves), written by the whole block as one contiguous 2 KiB store at its end.
+// waves), written by the whole block as one contiguous 4 KiB store at its end.
 // Storing once per block instead of per row group, with device-scope cache
 // policy (sc1), measured 7% faster for the whole kernel: the stores interleave
 // less with the stream of loads.
 constexpr int SY_STORE_POLICY = 16;  // sc1
-__device__ __forceinline__ void sy_store(const SyTile &T, double ca0, double ca1, const double *rows,
-                                         double (*cs)[SY_T], double *__restrict__ W) {
-    cs[T.w][T.lc] = ca0;
-    cs[T.w][T.lc + 1] = ca1;
+__device__ __forceinline__ void sy_store(const SyTile &T, const double (&ca)[SY_H][2],
+                                         const double *rows, double (*cs)[SY_T],
+                                         double *__restrict__ W) {
+#pragma unroll
+    for (int h = 0; h < SY_H; ++h) {
+        cs[T.w][h * SY_HW + T.lc] = ca[h][0];
+        cs[T.w][h * SY_HW + T.lc + 1] = ca[h][1];
+    }
     __syncthreads();
     const int q = threadIdx.x & (SY_T - 1);
     double out;
@@ -187,30 +210,39 @@ __device__ __forceinline__ void sy_store(const SyTile &T, double ca0, double ca1
 
 // Rows of one tile from a buffer resource based at the tile row (tiles whose
 // rows and columns all lie inside the matrix): the row offset is a scalar,
-// the lane's byte offset one vector register.
+// the lane's byte offset one vector register.  On a diagonal tile the second
+// half of the rows above the middle is never read (it lies above the
+// diagonal; its values stand as zero).
 template <bool DIAG>
 __device__ __forceinline__ void sy_tile_full(const SyTile &T, int64_t lda, const double *__restrict__ A,
-                                             const double *__restrict__ x, double *rows, double &ca0,
-                                             double &ca1) {
+                                             const double *__restrict__ x, double *rows,
+                                             double (&ca)[SY_H][2]) {
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<double *>(A + (int64_t)T.r0 * lda), 0, (int)((int64_t)SY_T * lda * 8),
         SY_RSRC_WORD3);
-    const int coff = T.c * 8;
+    const int coff = (T.c0 + T.lc) * 8;
     const double *xi = x + T.r0;  // x_I: read at wave-uniform indices
 #pragma unroll 1
     for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_INT) {
-        sy_d2 a[SY_UNR_INT];
+        sy_d2 a[SY_UNR_INT][SY_H];
         double xr[SY_UNR_INT];
 #pragma unroll
         for (int u = 0; u < SY_UNR_INT; ++u) {
             const int lr = sy_row(T.w, k0 + u);
-            const sy_u4 raw = __builtin_amdgcn_raw_buffer_load_b128(
-                rsrc, coff, (int)((int64_t)lr * lda * 8), SY_NT_POLICY);
-            a[u] = __builtin_bit_cast(sy_d2, raw);
+#pragma unroll
+            for (int h = 0; h < SY_H; ++h) {
+                if (DIAG && h * SY_HW > lr) {
+                    a[u][h] = sy_d2{0.0, 0.0};
+                    continue;
+                }
+                const sy_u4 raw = __builtin_amdgcn_raw_buffer_load_b128(
+                    rsrc, coff + h * SY_HW * 8, (int)((int64_t)lr * lda * 8), SY_NT_POLICY);
+                a[u][h] = __builtin_bit_cast(sy_d2, raw);
+            }
         }
 #pragma unroll
         for (int u = 0; u < SY_UNR_INT; ++u) xr[u] = xi[sy_row(T.w, k0 + u)];
-        sy_group<SY_UNR_INT, DIAG>(T, k0, a, xr, rows, ca0, ca1);
+        sy_group<SY_UNR_INT, DIAG>(T, k0, a, xr, rows, ca);
     }
 }
 
@@ -218,25 +250,33 @@ __device__ __forceinline__ void sy_tile_full(const SyTile &T, int64_t lda, const
 // beyond n are not read.
 __device__ __forceinline__ void sy_tile_edge(const SyTile &T, int n, int64_t lda,
                                              const double *__restrict__ A,
-                                             const double *__restrict__ x, double *rows, double &ca0,
-                                             double &ca1) {
+                                             const double *__restrict__ x, double *rows,
+                                             double (&ca)[SY_H][2]) {
     const bool diag = (T.I == T.J);
 #pragma unroll 1
     for (int k0 = 0; k0 < SY_RPW; k0 += SY_UNR_SPC) {
-        sy_d2 a[SY_UNR_SPC];
+        sy_d2 a[SY_UNR_SPC][SY_H];
         double xr[SY_UNR_SPC];
 #pragma unroll
         for (int u = 0; u < SY_UNR_SPC; ++u) {
-            const int r = T.r0 + sy_row(T.w, k0 + u);
+            const int lr = sy_row(T.w, k0 + u);
+            const int r = T.r0 + lr;
             const bool rin = r < n;
-            const double *row = A + (int64_t)r * lda + T.c;
-            a[u] = sy_d2{(rin && T.c < n) ? row[0] : 0.0, (rin && T.c + 1 < n) ? row[1] : 0.0};
+            const double *row = A + (int64_t)r * lda + T.c0 + T.lc;
+#pragma unroll
+            for (int h = 0; h < SY_H; ++h) {
+                const int c = T.c0 + h * SY_HW + T.lc;
+                // on the diagonal tile the upper-right quadrant is never read
+                const bool hin = rin && !(diag && h * SY_HW > lr);
+                a[u][h] = sy_d2{(hin && c < n) ? row[h * SY_HW] : 0.0,
+                                (hin && c + 1 < n) ? row[h * SY_HW + 1] : 0.0};
+            }
             xr[u] = rin ? x[r] : 0.0;
         }
         if (diag)
-            sy_group<SY_UNR_SPC, true>(T, k0, a, xr, rows, ca0, ca1);
+            sy_group<SY_UNR_SPC, true>(T, k0, a, xr, rows, ca);
         else
-            sy_group<SY_UNR_SPC, false>(T, k0, a, xr, rows, ca0, ca1);
+            sy_group<SY_UNR_SPC, false>(T, k0, a, xr, rows, ca);
     }
 }
 
@@ -268,14 +308,14 @@ __global__ __launch_bounds__(SY_NT) void symv_tile_kernel(int n, int64_t lda,
         I += 1;
     }
     const SyTile T = sy_setup(n, I, J, x);
-    double ca0 = 0.0, ca1 = 0.0;
+    double ca[SY_H][2] = {{0.0, 0.0}, {0.0, 0.0}};
     if (T.r0 + SY_T > n)
-        sy_tile_edge(T, n, lda, A, x, rows, ca0, ca1);
+        sy_tile_edge(T, n, lda, A, x, rows, ca);
     else if (I == J)
-        sy_tile_full<true>(T, lda, A, x, rows, ca0, ca1);
+        sy_tile_full<true>(T, lda, A, x, rows, ca);
     else
-        sy_tile_full<false>(T, lda, A, x, rows, ca0, ca1);
-    sy_store(T, ca0, ca1, rows, cs, W);
+        sy_tile_full<false>(T, lda, A, x, rows, ca);
+    sy_store(T, ca, rows, cs, W);
 }
 
 // y_j = (row parts of tile row J) + (column parts of tile column J), J = j / SY_T,

@@ -10,7 +10,7 @@ from workloads import spd_problem
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 127, 128, 129, 255, 300, 1000, 2049, 4097]
+SIZES = [1, 2, 127, 128, 129, 255, 256, 257, 300, 511, 512, 513, 1000, 2049, 4097]
 
 
 def _t(x, device):
