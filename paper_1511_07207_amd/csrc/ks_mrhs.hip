@@ -18,7 +18,10 @@
 // unchanged.  K is split S ways for parallelism (partials summed in fixed
 // order by the next kernel), and blocks are mapped to XCDs so that all blocks
 // of one split run on the same XCDs and that split's slice of P stays in
-// their L2.
+// their L2.  Each block stages P's chunks of 64 values of K in LDS (double
+// buffered), shared by its four waves: measured on MI355X at n = 16384,
+// s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the matrix-core peak),
+// binary32 0.60 -> 0.42 ms, the same sums bit for bit.
 #include <algorithm>
 
 #include "ks_device.h"
@@ -82,8 +85,12 @@ struct Mfma<float> {
 };
 
 constexpr int MR_WAVES = 4;      // waves per block
+constexpr int MR_NTHR = MR_WAVES * WAVE;
 constexpr int MR_WR = 32;        // rows of Q per wave (two 16-row tiles)
 constexpr int MR_BROWS = MR_WAVES * MR_WR;
+constexpr int MR_KC = 64;        // values of K per LDS-staged chunk of P
+constexpr int MR_KPAD = MR_KC + 2;  // padded column stride of the staged chunk (bank spread)
+static_assert(MR_NTHR == 16 * (MR_KC / 4), "each thread stages CT groups of 4 values");
 
 // Block -> (row block, split).  Work-groups are dispatched round-robin over
 // the 8 XCDs; give each split a fixed group of 8/S XCDs when the counts allow.
@@ -130,65 +137,93 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t
     const T *pcol[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) pcol[ct] = P + (size_t)(16 * ct + c16) * ldp;
-    int k0 = kb;
-    // full steps of 16: every lane loads 4 consecutive k = k0 + 4g .. k0 + 4g + 3.
-    // Binary64: software pipeline, the fragments of step k0 + 16 are loaded
-    // before the MFMAs of step k0 are issued, so each wave's memory latency
-    // overlaps its own matrix work (at two waves per SIMD the other wave
-    // alone cannot cover it; measured 0.85 -> 0.79 ms at n = 16384, s = 64).
-    // Binary32 keeps one step in flight: its extra registers would cost a
-    // wave per SIMD, which measured slower.
-    constexpr bool PIPE = sizeof(T) == 8;
-    const int kfull = kb + ((ke - kb) / 16) * 16;
+    // Whole chunks of MR_KC values of K: the block stages P's chunk (all s
+    // columns) in LDS once, double-buffered, instead of every wave fetching
+    // its own copy from L2; the next chunk is loaded into registers while the
+    // current one is multiplied.  A streams from HBM one step of 16 ahead.
+    // Every lane still takes k = k0 + 4g .. k0 + 4g + 3 per step of 16, in
+    // order, so the sums are those of the unstaged loop.
+    constexpr int NC = 16 * CT;
+    __shared__ T lp[2][NC * MR_KPAD];
+    const int nch = (ke - kb) / MR_KC;
+    const int ks_end = kb + nch * MR_KC;
     T a[2][4], p[CT][4];
-    if constexpr (PIPE) {
-        if (k0 < kfull) {
-            const int kk = k0 + 4 * g;
+    if (nch > 0) {
+        // staging: value groups of 4 consecutive k, gi = tid + MR_NTHR j
+        const int tid = threadIdx.x;
+        T stg[CT][4];
+        auto gload = [&](int c) {
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, p[ct]);
-        }
-        for (; k0 < kfull; k0 += 16) {
-            T an[2][4], pn[CT][4];
-            const bool more = k0 + 16 < kfull;
-            if (more) {
-                const int kk = k0 + 16 + 4 * g;
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, an[rt]);
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, pn[ct]);
+            for (int j = 0; j < CT; ++j) {
+                const int gi = tid + MR_NTHR * j;
+                const int col = gi / (MR_KC / 4), k4 = (gi % (MR_KC / 4)) * 4;
+                M::load4(P + (size_t)col * ldp + kb + c * MR_KC + k4, stg[j]);
             }
+        };
+        auto lstore = [&](int buf) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int j = 0; j < CT; ++j) {
+                const int gi = tid + MR_NTHR * j;
+                const int col = gi / (MR_KC / 4), k4 = (gi % (MR_KC / 4)) * 4;
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
+                for (int t = 0; t < 4; ++t) lp[buf][col * MR_KPAD + k4 + t] = stg[j][t];
+            }
+        };
+        gload(0);
+        lstore(0);
+        __syncthreads();
 #pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
-            if (more) {
+        for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kb + 4 * g, a[rt]);
+        for (int c = 0; c < nch; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nch) gload(c + 1);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+            for (int st16 = 0; st16 < MR_KC / 16; ++st16) {
+                const int k0 = kb + c * MR_KC + st16 * 16;
+                const bool more = k0 + 16 < ks_end;
+                T an[2][4];
+                if (more) {
 #pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) a[rt][t] = an[rt][t];
+                    for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + k0 + 16 + 4 * g, an[rt]);
+                }
 #pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) p[ct][t] = pn[ct][t];
+                for (int ct = 0; ct < CT; ++ct) {
+                    const T *q = &lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) p[ct][t] = q[t];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
+                if (more) {
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
                 }
             }
+            if (c + 1 < nch) lstore(buf ^ 1);
+            __syncthreads();
         }
-    } else {
-        for (; k0 < kfull; k0 += 16) {
-            const int kk = k0 + 4 * g;
+    }
+    // the rest of the range: full steps of 16 straight from P, then the tail
+    int k0 = ks_end;
+    const int kfull = k0 + ((ke - k0) / 16) * 16;
+    for (; k0 < kfull; k0 += 16) {
+        const int kk = k0 + 4 * g;
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
+        for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, p[ct]);
+        for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, p[ct]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
-        }
+                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
     }
     if (k0 < ke) {  // ragged tail of the K range, element by element
 #pragma unroll
