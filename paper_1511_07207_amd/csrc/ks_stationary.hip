@@ -17,18 +17,20 @@
 //                 lower triangle once, so an update reads A once in all.
 //
 // Forward substitution (the one sequential part).  The rows are taken in
-// steps of GS_SB = 64; launch I of a sweep
+// blocks of GS_SB = 64, two per launch: launch J
 //   - in its first block: subtracts from c = b - U x(k) the contribution of
-//     column block I - 1 (just solved) to rows of block I, then solves the
-//     64 x 64 lower-triangular diagonal tile of block I by substitution in
-//     one wave (lane i holds row i; x_j is broadcast from lane j with
-//     readlane, one fused multiply-add per lane and step), and writes x_I;
-//   - in its other blocks: subtracts the contribution of column block I - 1
-//     from the rows below block I (the panel, one wave instruction per row).
-// So column block J reaches the rows below block J + 1 in launch J + 1, and
-// block J + 1 itself in launch J + 1's first block: every row has all the
-// columns to its left subtracted before its own step.  No block of a launch
-// waits on another (no spin-waits); the steps are ordered by the stream.
+//     the two column blocks solved by launch J - 1 to rows of blocks 2J and
+//     2J + 1, solves block 2J's 64 x 64 lower-triangular diagonal tile by
+//     substitution in one wave (lane i holds row i; x_j is broadcast from
+//     lane j with readlane, one fused multiply-add per lane and step),
+//     subtracts its x from block 2J + 1's rows and solves that block too;
+//   - in its other blocks: subtracts the contribution of the previous two
+//     column blocks from the rows below (one wave instruction per row).
+// So every row has all the columns to its left subtracted before its own
+// solve.  No block of a launch waits on another (no spin-waits); the
+// launches are ordered by the stream.  Two blocks per launch halve the
+// launches, whose fixed cost (one memory round trip, start and end) was most
+// of a 64-row step.
 // The substitution multiplies by the reciprocal of the diagonal element (one
 // rounding more than a division; the division would sit on the sequential
 // path 64 times per step).
@@ -38,13 +40,10 @@ namespace ks {
 
 constexpr int GS_SB = 64;                     // rows per substitution step
 constexpr int GS_PW = 8;                      // rows per wave per pass in the row updates
-constexpr int GS_WAVES = GEMV_NT / WAVE;      // waves per block
-constexpr int GS_PR = GS_WAVES * GS_PW;       // rows per panel block (32)
 constexpr int GS_LDT = GS_SB + 1;             // LDS row stride of the diagonal tile (padded)
 constexpr int GS_ROWS = GemvShape<double>::ROWS;  // rows per block of the upper product
 constexpr int GS_UNR = GemvShape<double>::UNR;    // column chunks in flight per thread
 static_assert(GS_SB == WAVE, "one lane per row of the diagonal tile, one per panel column");
-static_assert(GS_SB % GS_WAVES == 0, "the block's waves share its rows evenly");
 
 // --------------------------------------------------------------- common
 // d = diag(A); F_BREAK | F_STOP when an element is zero (one block)
@@ -216,87 +215,25 @@ __device__ __forceinline__ double gs_readlane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// One wave: the sums over column block cb (64 columns, lane l takes column
-// cb + l) of GS_PW rows from rs on, row k's sum returned in out[k] (lane 0's
-// copy is the one used).
-__device__ __forceinline__ void gs_row_sums(int n, int64_t lda, const double *__restrict__ A,
-                                            double xl, int rs, int cb, int lane,
-                                            double (&out)[GS_PW]) {
-    double v[GS_PW];
-#pragma unroll
-    for (int k = 0; k < GS_PW; ++k) v[k] = A[(int64_t)min(rs + k, n - 1) * lda + cb + lane];
-#pragma unroll
-    for (int k = 0; k < GS_PW; ++k) out[k] = wave_sum(v[k] * xl);
-}
+// Launch J of a sweep solves the two 64-row blocks B0 = 2J and B1 = 2J + 1
+// (rows r0 = 128 J ..).  Block 0 (GS_SWT waves) issues every load first:
+// both diagonal tiles (to LDS), the 64 x 64 tile coupling B1 to B0's columns,
+// and the rows of B0 and B1 over the 128 columns solved by the launch before
+// (cb = r0 - 128 ..).  Then wave 0 solves B0, all waves apply x_B0 to B1's
+// rows through the coupling tile, and wave 0 solves B1.  The launch's other
+// blocks subtract the 128 columns cb .. from the rows below B1, GS_SWT * 8
+// rows per block, two columns per lane.
+constexpr int GS_SWT = 8;                       // waves per block
+constexpr int GS_SNT = GS_SWT * WAVE;
+constexpr int GS_SPR = GS_SWT * GS_PW;          // rows per row-update block (64)
+constexpr int GS_TQ = GS_SB * 2 / GS_SWT;       // rows of the two diagonal tiles per wave (16)
+constexpr int GS_UQ = GS_SB / GS_SWT;           // rows of B0 (and of B1) per wave (8)
 
-// Launch I of a sweep (see the head of the file).  Block 0: rows of block I;
-// blocks 1..: the rows below, GS_PR per block.
-__global__ __launch_bounds__(GEMV_NT) void gs_sweep_kernel(int n, int64_t lda,
-                                                           const double *__restrict__ A,
-                                                           double *__restrict__ x,
-                                                           double *__restrict__ c, const State *st,
-                                                           int I) {
-    __shared__ double T[GS_SB * GS_LDT];
-    __shared__ double cI[GS_SB];  // the block's row sums over column block I - 1
-    if (st->flags & F_STOP) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int w = threadIdx.x / WAVE;
-    const int cb = (I - 1) * GS_SB;  // column block just solved (I >= 1)
-    const double xl = I >= 1 ? x[cb + lane] : 0.0;
-    if (blockIdx.x > 0) {
-        // panel: rows below block I
-        const int rs = (I + 1) * GS_SB + (blockIdx.x - 1) * GS_PR + w * GS_PW;
-        double sums[GS_PW];
-        gs_row_sums(n, lda, A, xl, rs, cb, lane, sums);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < GS_PW; ++k)
-                if (rs + k < n) c[rs + k] -= sums[k];
-        }
-        return;
-    }
-    const int r0 = I * GS_SB;
-    const int m = min(GS_SB, n - r0);
-    // every global load of the step first (one memory round trip): the
-    // wave's rows of the diagonal tile (k = w + GS_WAVES q), its rows of the
-    // block's update by column block I - 1, and c of the block's rows
-    constexpr int TQ = GS_SB / GS_WAVES;   // tile rows per wave
-    constexpr int PQ = GS_SB / GS_WAVES;   // update rows per wave
-    double tl[TQ], pv[PQ];
-    const int cc = min(lane, m - 1);
-#pragma unroll
-    for (int q = 0; q < TQ; ++q) {
-        const int k = w + GS_WAVES * q;
-        tl[q] = A[(int64_t)(r0 + min(k, m - 1)) * lda + r0 + cc];
-    }
-    if (I >= 1) {
-#pragma unroll
-        for (int q = 0; q < PQ; ++q) {
-            const int k = w * PQ + q;
-            pv[q] = A[(int64_t)(r0 + min(k, m - 1)) * lda + cb + lane];
-        }
-    }
-    const double cval = (w == 0 && lane < m) ? c[r0 + lane] : 0.0;
-    // the diagonal tile into LDS, lower part only; rows past n get a unit
-    // diagonal (their x is 0 and never written)
-#pragma unroll
-    for (int q = 0; q < TQ; ++q) {
-        const int k = w + GS_WAVES * q;
-        T[k * GS_LDT + lane] =
-            (k < m && lane < m) ? (lane <= k ? tl[q] : 0.0) : (lane == k ? 1.0 : 0.0);
-    }
-    // sums of the block's rows over column block I - 1
-#pragma unroll
-    for (int q = 0; q < PQ; ++q) {
-        const double sq = I >= 1 ? wave_sum(pv[q] * xl) : 0.0;
-        if (lane == 0) cI[w * PQ + q] = sq;
-    }
-    __syncthreads();
-    if (w != 0) return;
-    // forward substitution in wave 0: lane i holds row i
-    double acc = lane < m ? cval - cI[lane] : 0.0;
-    const double dinv = 1.0 / T[lane * GS_LDT + lane];
-    double xi = 0.0;
+typedef double gs_d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void gs_solve_tile(const double *T, double acc, double dinv, int lane,
+                                              double &xi) {
+    // forward substitution in one wave: lane i holds row i
 #pragma unroll
     for (int j = 0; j < GS_SB; ++j) {
         const double xc = acc * dinv;
@@ -304,7 +241,119 @@ __global__ __launch_bounds__(GEMV_NT) void gs_sweep_kernel(int n, int64_t lda,
         xi = (lane == j) ? xc : xi;
         acc = fma(-T[lane * GS_LDT + j], xj, acc);
     }
-    if (lane < m) x[r0 + lane] = xi;
+}
+
+__global__ __launch_bounds__(GS_SNT) void gs_sweep_kernel(int n, int64_t lda,
+                                                          const double *__restrict__ A,
+                                                          double *__restrict__ x,
+                                                          double *__restrict__ c, const State *st,
+                                                          int J) {
+    __shared__ double T0[GS_SB * GS_LDT], T1[GS_SB * GS_LDT];
+    __shared__ double s0[GS_SB], s1[GS_SB], s1b[GS_SB], xb0[GS_SB];
+    if (st->flags & F_STOP) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int r0 = 2 * J * GS_SB;
+    const int cb = r0 - 2 * GS_SB;  // the 128 columns solved in launch J - 1 (J >= 1)
+    gs_d2 xl = {0.0, 0.0};
+    if (J >= 1) xl = *reinterpret_cast<const gs_d2 *>(x + cb + 2 * lane);
+    if (blockIdx.x > 0) {
+        const int rs = r0 + 2 * GS_SB + (blockIdx.x - 1) * GS_SPR + w * GS_PW;
+        gs_d2 v[GS_PW];
+#pragma unroll
+        for (int k = 0; k < GS_PW; ++k)
+            v[k] = load_a<double>(A + (int64_t)min(rs + k, n - 1) * lda + cb + 2 * lane);
+        double pv[GS_PW];
+#pragma unroll
+        for (int k = 0; k < GS_PW; ++k) pv[k] = fma(v[k].y, xl.y, v[k].x * xl.x);
+        const double sm = rows_reduce<GS_PW>(pv, lane);
+        constexpr int PLR = WAVE / GS_PW;
+        if (lane % PLR == 0 && rs + lane / PLR < n) c[rs + lane / PLR] -= sm;
+        return;
+    }
+    const int m0 = min(GS_SB, n - r0);
+    const int r1 = r0 + GS_SB;
+    const bool has1 = r1 < n;
+    const int m1 = has1 ? min(GS_SB, n - r1) : 0;
+    // ---- all loads: diagonal tiles (rows k = w + GS_SWT q: q < 8 for B0, 8.. for B1),
+    // B0 / B1 rows over the previous columns, the coupling tile
+    double tl[GS_TQ], tc[GS_UQ];
+    gs_d2 u0[GS_UQ], u1[GS_UQ];
+#pragma unroll
+    for (int q = 0; q < GS_TQ; ++q) {
+        const int k = w + GS_SWT * q;  // 0 .. 127
+        if (k < GS_SB)
+            tl[q] = A[(int64_t)(r0 + min(k, m0 - 1)) * lda + r0 + min(lane, m0 - 1)];
+        else if (has1)
+            tl[q] = A[(int64_t)(r1 + min(k - GS_SB, m1 - 1)) * lda + r1 + min(lane, m1 - 1)];
+        else
+            tl[q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < GS_UQ; ++q) {
+        const int k = w * GS_UQ + q;  // row of the block
+        if (J >= 1) {
+            u0[q] = load_a<double>(A + (int64_t)(r0 + min(k, m0 - 1)) * lda + cb + 2 * lane);
+            if (has1) u1[q] = load_a<double>(A + (int64_t)(r1 + min(k, m1 - 1)) * lda + cb + 2 * lane);
+        }
+        tc[q] = has1 ? A[(int64_t)(r1 + min(k, m1 - 1)) * lda + r0 + min(lane, m0 - 1)] : 0.0;
+    }
+    const double c0 = (w == 0 && lane < m0) ? c[r0 + lane] : 0.0;
+    const double c1 = (w == 0 && lane < m1) ? c[r1 + lane] : 0.0;
+    // ---- the diagonal tiles into LDS, lower part; rows past n get a unit diagonal
+#pragma unroll
+    for (int q = 0; q < GS_TQ; ++q) {
+        const int k = w + GS_SWT * q;
+        if (k < GS_SB) {
+            T0[k * GS_LDT + lane] = (k < m0 && lane < m0) ? (lane <= k ? tl[q] : 0.0) : (lane == k ? 1.0 : 0.0);
+        } else {
+            const int kk = k - GS_SB;
+            T1[kk * GS_LDT + lane] = (kk < m1 && lane < m1) ? (lane <= kk ? tl[q] : 0.0) : (lane == kk ? 1.0 : 0.0);
+        }
+    }
+    // ---- sums over the previous columns, the wave's 8 rows of each block at
+    // once (halving butterfly: lane group g = lane / 8 ends with row g)
+    constexpr int LPR = WAVE / GS_UQ;
+    {
+        double v0[GS_UQ], v1[GS_UQ];
+#pragma unroll
+        for (int q = 0; q < GS_UQ; ++q) {
+            v0[q] = J >= 1 ? fma(u0[q].y, xl.y, u0[q].x * xl.x) : 0.0;
+            v1[q] = (J >= 1 && has1) ? fma(u1[q].y, xl.y, u1[q].x * xl.x) : 0.0;
+        }
+        const double a0 = rows_reduce<GS_UQ>(v0, lane);
+        const double a1 = rows_reduce<GS_UQ>(v1, lane);
+        if (lane % LPR == 0) {
+            s0[w * GS_UQ + lane / LPR] = a0;
+            s1[w * GS_UQ + lane / LPR] = a1;
+        }
+    }
+    __syncthreads();
+    // ---- B0
+    if (w == 0) {
+        double xi = 0.0;
+        gs_solve_tile(T0, lane < m0 ? c0 - s0[lane] : 0.0, 1.0 / T0[lane * GS_LDT + lane], lane, xi);
+        xb0[lane] = lane < m0 ? xi : 0.0;
+        if (lane < m0) x[r0 + lane] = xi;
+    }
+    __syncthreads();
+    if (!has1) return;
+    // ---- B1's rows less the coupling tile times x_B0
+    const double xv = xb0[lane];
+    {
+        double v[GS_UQ];
+#pragma unroll
+        for (int q = 0; q < GS_UQ; ++q) v[q] = (lane < m0 ? tc[q] : 0.0) * xv;
+        const double sm = rows_reduce<GS_UQ>(v, lane);
+        if (lane % LPR == 0) s1b[w * GS_UQ + lane / LPR] = sm;
+    }
+    __syncthreads();
+    if (w == 0) {
+        double xi = 0.0;
+        gs_solve_tile(T1, lane < m1 ? (c1 - s1[lane]) - s1b[lane] : 0.0,
+                      1.0 / T1[lane * GS_LDT + lane], lane, xi);
+        if (lane < m1) x[r1 + lane] = xi;
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -343,11 +392,11 @@ hipError_t launch_gs_upper(int n, int64_t lda, const double *A, const double *b,
 
 hipError_t launch_gs_sweep(int n, int64_t lda, const double *A, double *x, double *c,
                            const State *st, hipStream_t s) {
-    const int nb = div_up(n, GS_SB);
-    for (int I = 0; I < nb; ++I) {
-        const int below = n - (I + 1) * GS_SB;
-        const int blocks = 1 + ((I >= 1 && below > 0) ? div_up(below, GS_PR) : 0);
-        gs_sweep_kernel<<<blocks, GEMV_NT, 0, s>>>(n, lda, A, x, c, st, I);
+    const int nl = div_up(n, 2 * GS_SB);
+    for (int J = 0; J < nl; ++J) {
+        const int below = n - (J + 1) * 2 * GS_SB;
+        const int blocks = 1 + ((J >= 1 && below > 0) ? div_up(below, GS_SPR) : 0);
+        gs_sweep_kernel<<<blocks, GS_SNT, 0, s>>>(n, lda, A, x, c, st, J);
     }
     return hipGetLastError();
 }

@@ -78,37 +78,6 @@ __device__ __forceinline__ void sy_tri_ij(int t, int &I, int &J) {
     J = t - i * (i + 1) / 2;
 }
 
-// One step of the row butterfly: the lanes whose `mask` bit is 0 keep the
-// first half of their K values, the others the second half, each adding the
-// partner's copy of the half it keeps.
-template <int K, int U>
-__device__ __forceinline__ void sy_fold(double (&v)[U], int lane, int mask) {
-    const bool hi = (lane & mask) != 0;
-#pragma unroll
-    for (int i = 0; i < K / 2; ++i) {
-        const double keep = hi ? v[i + K / 2] : v[i];
-        const double send = hi ? v[i] : v[i + K / 2];
-        v[i] = keep + __shfl_xor(send, mask);
-    }
-}
-
-// U row sums over the 64 lanes (U = 4, 8 or 16).  Afterwards every lane of
-// the lane group g = lane / (64 / U) holds the sum of row g: the halving
-// exchanges over lane bits 5, 4, ... leave row g in the lanes whose high bits
-// spell g, and the remaining low bits are summed by plain exchanges.
-template <int U>
-__device__ __forceinline__ double sy_rows_reduce(double (&v)[U], int lane) {
-    static_assert(U == 4 || U == 8 || U == 16, "row group of 4, 8 or 16");
-    sy_fold<U, U>(v, lane, 32);
-    if constexpr (U >= 4) sy_fold<U / 2, U>(v, lane, 16);
-    if constexpr (U >= 8) sy_fold<U / 4, U>(v, lane, 8);
-    if constexpr (U >= 16) sy_fold<U / 8, U>(v, lane, 4);
-    double s = v[0];
-#pragma unroll
-    for (int m = 32 / U; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-    return s;
-}
-
 // Rows of a tile are interleaved over the waves: wave w reads rows w, w + 4,
 // w + 8, ... (local row lr = w + SY_WAVES * k), so the block as a whole reads
 // consecutive rows at any moment (measured 5% faster than contiguous row
@@ -171,7 +140,7 @@ __device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&
         }
         racc[u] = s;
     }
-    const double v = sy_rows_reduce<U>(racc, T.lane);
+    const double v = rows_reduce<U>(racc, T.lane);
     constexpr int LPR = WAVE / U;  // lanes per row after the reduction
     if ((T.lane % LPR) == 0) rows[sy_row(T.w, k0 + T.lane / LPR)] = v;
 }

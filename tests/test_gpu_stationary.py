@@ -10,9 +10,9 @@ take one (the residual can sit on the threshold within rounding), with a true
 relative residual (oracle metrics) within the tolerance and the solution
 within 1e-8 of the oracle's.
 
-The sizes span the Gauss-Seidel substitution step (64 rows) and the product
-chunks (512 columns) with ragged tails: n = 1, 7, 64, 65, 130, 513, 1000,
-2049.
+The sizes span the Gauss-Seidel substitution blocks (64 rows, two per
+launch) and the product chunks (512 columns) with ragged tails: n = 1, 7, 64,
+65, 128, 130, 191, 513, 1000, 2049.
 """
 import numpy as np
 import pytest
@@ -41,7 +41,8 @@ def _solve(device, A, b, method, x0=None, **kw):
 
 @pytest.mark.parametrize("method", list(METHODS))
 @pytest.mark.parametrize("n,steps,seed", [(1, 1, 0), (7, 3, 1), (64, 4, 2), (65, 4, 3),
-                                          (130, 5, 4), (513, 6, 5), (1000, 3, 6), (2049, 5, 7)])
+                                          (128, 3, 8), (130, 5, 4), (191, 3, 9), (513, 6, 5),
+                                          (1000, 3, 6), (2049, 5, 7)])
 def test_iterates_match_oracle_step_by_step(device, method, n, steps, seed):
     print(f"{method} n={n} steps={steps} seed={seed}", flush=True)
     p = nonsym_problem(n, seed=seed, config_id=6)
