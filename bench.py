@@ -44,6 +44,13 @@ def _pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+# The solvers time their A*v launches with HIP event pairs on their own
+# stream; each pair costs the stream a few microseconds, so only one polling
+# chunk in TIMING_EVERY is timed (the first chunk of a solve always is): the
+# launch averages come from a sample, the solve times carry almost none of
+# the events' cost.
+TIMING_EVERY = 8
+
 # sources of the two CG products (general GEMV / symmetric lower-triangle product)
 _PRODUCT_SOURCES = {
     "general": ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"),
@@ -63,10 +70,13 @@ def kernel_source_hash(product: str = "general") -> str:
 
 
 def product_bytes(n: int, product: str) -> float:
-    """Algorithmic bytes of one CG product: A (or its lower triangle) once,
-    the input vector once, the output vector once."""
-    a = 8.0 * n * n if product == "general" else 8.0 * n * (n + 1) / 2
-    return a + 2 * 8.0 * n
+    """Algorithmic bytes of one timed CG product.  General: A once, p once, q
+    once.  Symmetric: the lower triangle once and p once; its finishing launch
+    also applies the iteration's update (x and r read and written, q never
+    stored), which the same timed pair covers."""
+    if product == "general":
+        return 8.0 * n * n + 2 * 8.0 * n
+    return 8.0 * n * (n + 1) / 2 + 5 * 8.0 * n
 
 
 def load_traffic(n: int, product: str = "general"):
@@ -171,7 +181,7 @@ def leg_c3(dev, n, kappa):
             prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
         res = {"kappa": kap}
         for prec in ("fp64", "fp32", "bf16"):
-            kw = dict(method=method, tol=1e-12, restart=50, timing=True, max_iter=4 * n)
+            kw = dict(method=method, tol=1e-12, restart=50, timing=True, timing_every=TIMING_EVERY, max_iter=4 * n)
             if prec == "fp64":
                 kw["stop_backward"] = True
             else:
@@ -220,7 +230,7 @@ def leg_f1(dev, n):
             ("bicgstab_fp32_eta", dict(method="bicgstab", tol=1e-12, precision="fp32")),
             ("bicgstab_bf16_eta", dict(method="bicgstab", tol=1e-12, precision="bf16"))]
     for name, kw in runs:
-        s = krylov.Solver(prob.A, timing=True, **kw)
+        s = krylov.Solver(prob.A, timing=True, timing_every=TIMING_EVERY, **kw)
         s.solve(prob.b, out=x.zero_())
         lat = []
         for _ in range(5):
@@ -257,7 +267,7 @@ def leg_f3(dev, n):
 
     def run(prob, m, kw, reps):
         x = torch.zeros(m, dtype=torch.float64, device=dev)
-        s = krylov.Solver(prob.A, timing=True, **kw)
+        s = krylov.Solver(prob.A, timing=True, timing_every=TIMING_EVERY, **kw)
         s.solve(prob.b, out=x.zero_())
         lat = []
         for _ in range(reps):
@@ -355,7 +365,7 @@ def leg_c2p(dev, n):
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     out = {"n": n, "kappa": 1e4}
     for prod in ("general", "symmetric"):
-        s = krylov.Solver(prob.A, method="cg", tol=1e-10, timing=True, symmetric=(prod == "symmetric"))
+        s = krylov.Solver(prob.A, method="cg", tol=1e-10, timing=True, timing_every=TIMING_EVERY, symmetric=(prod == "symmetric"))
         s.solve(prob.b, out=x.zero_())
         lat = []
         for _ in range(3):
@@ -382,7 +392,7 @@ def leg_c4(dev, n):
     prob = multi_rhs_problem(n, 1e4, s, seed=0, backend="torch", device="cuda")
     out = {"n": n, "nrhs": s, "kappa": 1e4}
     for prec, tol, peak in (("fp64", 1e-10, 78.6), ("fp32", 1e-12, 157.3)):
-        solver = krylov.Solver(prob.A, method="cg", nrhs=s, tol=tol, precision=prec, timing=True,
+        solver = krylov.Solver(prob.A, method="cg", nrhs=s, tol=tol, precision=prec, timing=True, timing_every=TIMING_EVERY,
                                max_iter=4 * n)
         solver.solve(prob.b)
         (X, info), dt = _timed(lambda: solver.solve(prob.b))
@@ -542,8 +552,8 @@ def main():
 
     t0 = time.perf_counter()
     sym = args.cg_product == "symmetric"
-    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True, symmetric=sym)
-    gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True)
+    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True, timing_every=TIMING_EVERY, symmetric=sym)
+    gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True, timing_every=TIMING_EVERY)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     xcg = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -593,7 +603,8 @@ def main():
     value = solves / elapsed
     ms_step = elapsed * 1e3 / args.steps
     # dominant kernel: the FP64 product of the CG loop, q = A p (the symmetric
-    # product is two launches: the tiles of the lower triangle, the finishing sum)
+    # product is two launches: the tiles of the lower triangle, then the
+    # finishing sum that also applies the iteration's x and r update)
     gemv_ms = sum(r[0]["gemv_ms"] for r in recs)
     gemv_calls = sum(r[0]["gemv_calls"] for r in recs)
     gm_gemv_ms = sum(r[1]["gemv_ms"] for r in recs)
@@ -628,8 +639,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("symv_tile_kernel + symv_finish_kernel "
-                       "(q = A p from the lower triangle, p'q partials)" if sym else
+            "kernel": ("symv_tile_kernel + symv_cg_finish_kernel "
+                       "(q = A p from the lower triangle, fused with x += alpha p, r -= alpha q)"
+                       if sym else
                        "cg_matvec_kernel<double> (q = A p, p'q partials)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

@@ -92,7 +92,8 @@ extern "C" {
 #define KS_DT_BF16 2
 
 /* ks_params.flags */
-#define KS_FLAG_TIMING 1 /* time every A*v launch with HIP events (info->gemv_ms) */
+#define KS_FLAG_TIMING 1 /* time the A*v launches with HIP events (info->gemv_ms;
+                            all of them, or a sample: timing_every) */
 #define KS_FLAG_STOP_BACKWARD 2 /* binary64 solves: tol bounds the normwise backward
                                    error eta_inf instead of ||r||_2 / ||b||_2: stop
                                    when ||r||_2 <= tol (||A||_inf ||x||_inf +
@@ -125,7 +126,11 @@ typedef struct {
     int32_t nrhs;       /* right-hand sides solved together (CG only): 1, or up to
                            KS_MAX_NRHS for lockstep CG with A*P on the matrix
                            cores; precision KS_FP64 or KS_IR_FP32               */
-    int32_t reserved;
+    int32_t timing_every; /* with KS_FLAG_TIMING: time the A*v launches of one
+                           polling chunk in every this many (0 or 1: all of
+                           them).  Each timed launch records two HIP events,
+                           which cost the stream a few microseconds; sampling
+                           keeps that out of a timed solve's wall time */
 } ks_params;
 
 #define KS_MAX_RESTART 128

@@ -48,7 +48,7 @@ class KsParams(ctypes.Structure):
         ("poll_every", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("nrhs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("timing_every", ctypes.c_int32),
     ]
 
 

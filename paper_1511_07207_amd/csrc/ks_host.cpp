@@ -57,6 +57,7 @@ struct ks_solver {
     int tev_used = 0;
     double gemv_ms = 0.0;
     int gemv_calls = 0;
+    int tchunk = 0;  // polling chunks collected so far in this solve (timing sample)
     double anorm_inf = 0.0;
     // multi-right-hand-side
     double *mr64 = nullptr;   // X, R, P, Q, Qpart (binary64)
@@ -90,11 +91,16 @@ int sync_state(ks_solver *s) {
     return KS_OK;
 }
 
-// Timing of A*v launches: an event pair around each; after a sync only the
+// Timing of A*v launches: an event pair around each launch of a timed
+// polling chunk (every chunk, or one in p.timing_every); after a sync only the
 // first `real` pairs of the chunk did work (the rest returned at once).
+bool chunk_timed(const ks_solver *s) {
+    return s->timing() && (s->p.timing_every <= 1 || s->tchunk % s->p.timing_every == 0);
+}
+
 int timing_pair(ks_solver *s, hipEvent_t *a, hipEvent_t *b) {
     *a = *b = nullptr;
-    if (!s->timing()) return KS_OK;
+    if (!chunk_timed(s)) return KS_OK;
     while ((int)s->tev.size() < 2 * (s->tev_used + 1)) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
@@ -108,6 +114,7 @@ int timing_pair(ks_solver *s, hipEvent_t *a, hipEvent_t *b) {
 
 int timed_collect(ks_solver *s, int real) {
     if (!s->timing()) return KS_OK;
+    s->tchunk++;
     real = std::min(real, s->tev_used);
     for (int i = 0; i < real; ++i) {
         float ms = 0.f;
@@ -124,6 +131,14 @@ int poll_chunk(const ks_solver *s) {
     if (s->n >= 8192) return 8;
     if (s->n >= 2048) return 16;
     return 32;
+}
+
+// CG and GMRES: an iteration launched after the stop costs only launches that
+// return at once, while a poll costs a host round trip, so the chunk between
+// polls is 32 iterations at every n (measured at n = 16384: CG 164.0 ms with
+// 8, 162.5 ms with 32, no better beyond; GMRES(30) unchanged)
+int poll_chunk_krylov(const ks_solver *s) {
+    return s->p.poll_every > 0 ? s->p.poll_every : 32;
 }
 
 struct Outcome {
@@ -192,7 +207,7 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
                 int k = 0;
                 while (!done) {
                     const int it0 = h->iters;
-                    const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0));
+                    const int chunk = std::max(1, std::min(poll_chunk_krylov(s), max_iter - it0));
                     for (int c = 0; c < chunk; ++c, ++k) {
                         hipEvent_t e0, e1;
                         if ((rc = timing_pair(s, &e0, &e1))) return rc;
@@ -210,25 +225,29 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
         }
         while (!done) {
             const int it0 = h->iters;
-            const int chunk = std::max(1, std::min(poll_chunk(s), max_iter - it0));
+            const int chunk = std::max(1, std::min(poll_chunk_krylov(s), max_iter - it0));
             for (int c = 0; c < chunk; ++c) {
                 hipEvent_t e0, e1;
                 if ((rc = timing_pair(s, &e0, &e1))) return rc;
                 if (e0) HIPCHK(hipEventRecord(e0, sm));
-                int nsigma = gemv_blocks<TA>(n);
-                if constexpr (std::is_same<TA, double>::value) {
+                bool symmetric = false;
+                if constexpr (std::is_same<TA, double>::value && std::is_same<T, double>::value) {
                     if (s->sy) {
-                        HIPCHK(launch_symv(n, lda, A, p, q, s->sy, st, p, s->P.g, sm));
-                        nsigma = symv_finish_blocks(n);
-                    } else {
-                        HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                        // product and update in two launches (the timed pair
+                        // covers both; the update adds 40n bytes to A's)
+                        HIPCHK(launch_symv_cg(n, lda, A, p, x, r, s->sy, st, sm));
+                        if (e1) HIPCHK(hipEventRecord(e1, sm));
+                        HIPCHK(launch_cg_pupdate_f64(n, r, p, st, symv_cg_rho_part(n, s->sy),
+                                                     symv_finish_blocks(n), max_iter, sm));
+                        symmetric = true;
                     }
-                } else {
-                    HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
                 }
-                if (e1) HIPCHK(hipEventRecord(e1, sm));
-                HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, nsigma, sm));
-                HIPCHK(launch_cg_pupdate<T>(n, r, p, st, s->P, max_iter, sm));
+                if (!symmetric) {
+                    HIPCHK((launch_cg_matvec<TA, T>(n, lda, A, p, q, st, s->P, sm)));
+                    if (e1) HIPCHK(hipEventRecord(e1, sm));
+                    HIPCHK(launch_cg_update<T>(n, x, r, p, q, st, s->P, gemv_blocks<TA>(n), sm));
+                    HIPCHK(launch_cg_pupdate<T>(n, r, p, st, s->P, max_iter, sm));
+                }
             }
             if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
             if ((rc = sync_state(s))) return rc;
@@ -288,7 +307,7 @@ int run_gmres(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda
             break;
         }
         HIPCHK(launch_gm_begin<T>(n, w, V, st, s->ga, sm));
-        const int chunk = poll_chunk(s);
+        const int chunk = poll_chunk_krylov(s);
         int k = 0;
         bool stopped = false;
         while (k < m && !stopped) {
@@ -1114,6 +1133,7 @@ int ks_params_init(ks_params *p, int32_t n, int32_t method) {
     p->poll_every = 0;
     p->flags = 0;
     p->nrhs = 1;
+    p->timing_every = 0;
     return KS_OK;
 }
 
@@ -1235,6 +1255,7 @@ int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info) {
     info->precision_used = s->p.precision;
     s->gemv_ms = 0.0;
     s->gemv_calls = 0;
+    s->tchunk = 0;
     s->tev_used = 0;
     HIPCHK(hipEventRecord(s->ev0, s->stream));
     Outcome o;

@@ -125,6 +125,12 @@ __host__ __device__ inline int sy_tiles(int n) {
     return t * (t + 1) / 2;
 }
 __host__ __device__ inline size_t sy_ws_doubles(int n) { return (size_t)sy_tiles(n) * 2 * SY_T; }
+constexpr int SY_FIN = 64;  // elements per block of the finishing kernel
+// CG with the symmetric product keeps, after W, one p'Ap share per tile and
+// the r'r and ||x||_inf partials of the finishing blocks.
+__host__ __device__ inline size_t sy_cg_doubles(int n) {
+    return (size_t)round_up(sy_tiles(n), 32) + 2 * (size_t)div_up(n, SY_FIN);
+}
 
 // GMRES small dense arrays (binary64 always).
 struct GmArrays {
@@ -213,6 +219,9 @@ hipError_t launch_cg_update(int n, T *x, T *r, const T *p, const T *q, State *st
 template <typename T>
 hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int max_iter,
                              hipStream_t s);
+// the same with the r'r and ||x||_inf partials at prho ([nrho] each), binary64
+hipError_t launch_cg_pupdate_f64(int n, const double *r, double *p, State *st, const double *prho,
+                                 int nrho, int max_iter, hipStream_t s);
 // p = r, inner flags cleared (rho comes from the residual kernel).
 template <typename T>
 hipError_t launch_cg_begin(int n, const T *r, T *p, State *st, hipStream_t s);
@@ -268,6 +277,22 @@ int symv_finish_blocks(int n);
 hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
                        double *W, const State *st, const double *p, double *partial,
                        hipStream_t s);
+
+// The product and update of one binary64 CG iteration with the symmetric
+// product, in two launches.  The tile blocks also leave their share of p'Ap,
+// p_I'(row part) + p_J'(column part), in sig[tile]; the finishing blocks sum
+// q = A p as launch_symv does, reduce sigma = p'q from the shares (the same
+// fixed order in every block), and apply alpha = rho / sigma: x += alpha p,
+// r -= alpha q on their elements (q is not stored), recording the iteration in
+// st as launch_cg_update does.  rho_part: [r'r partials][||x||_inf partials],
+// symv_finish_blocks(n) each, for launch_cg_pupdate_f64.  W, sig and rho_part
+// lie in one region of sy_ws_doubles(n) + sy_cg_doubles(n) doubles.
+hipError_t launch_symv_cg(int n, int64_t lda, const double *A, const double *p, double *x,
+                          double *r, double *region, State *st, hipStream_t s);
+// where the r'r partials of launch_symv_cg lie in that region
+inline double *symv_cg_rho_part(int n, double *region) {
+    return region + sy_ws_doubles(n) + round_up(sy_tiles(n), 32);
+}
 
 // Fused small-n CG (n <= FZ_MAX_N, binary64, no backward-error stopping): one
 // launch per iteration instead of three, bitwise the same arithmetic.

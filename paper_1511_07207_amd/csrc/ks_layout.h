@@ -51,7 +51,7 @@ inline size_t gm_doubles(int m) { return (size_t)(m + 1) * m * 2 + 2 * (size_t)m
 
 inline bool valid_params(const ks_params *p) {
     if (!p) return false;
-    if (p->n < 1 || p->lda < p->n) return false;
+    if (p->n < 1 || p->lda < p->n || p->timing_every < 0) return false;
     if (p->method != KS_CG && p->method != KS_GMRES && p->method != KS_BICGSTAB &&
         p->method != KS_JACOBI && p->method != KS_GAUSS_SEIDEL)
         return false;
@@ -133,7 +133,7 @@ inline Layout make_layout(const ks_params *p) {
         off = align_up(off + L.mr_part_count * sizeof(double));
     }
     if (p->flags & KS_FLAG_SYMMETRIC) {
-        L.sy_bytes = sy_ws_doubles(n) * sizeof(double);
+        L.sy_bytes = (sy_ws_doubles(n) + (p->method == KS_CG ? sy_cg_doubles(n) : 0)) * sizeof(double);
         L.sy_off = off;
         off = align_up(off + L.sy_bytes);
     }

@@ -36,10 +36,11 @@
 // per lane at each exchange, then adds within the remaining lane groups.
 //
 // Every tile writes its two partial vectors (row part, column part; SY_T
-// values each) to a workspace; a third kernel sums, for each element, the row
+// values each) to a workspace; a second kernel sums, for each element, the row
 // parts of its tile row and the column parts of its tile column in a fixed
-// order (deterministic, no atomics), and writes y (and, for CG, the partials
-// of p'q).  The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A
+// order (deterministic, no atomics), and writes y.  In CG the tiles also leave
+// their shares of p'Ap, and the second kernel applies the iteration's update
+// instead of writing q, so an iteration is two launches and the p update.  The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A
 // read, i.e. 1.6% of the product's bytes at SY_T = 256.  The workspace writes
 // are what the tile size trades against: measured on MI355X at n = 16384,
 // storing them cost ~15 us of a 173 us product with 128-wide tiles and ~6 us
@@ -62,7 +63,6 @@ constexpr int SY_H = 2;                  // 1 KiB halves per tile row
 constexpr int SY_HW = SY_T / SY_H;       // columns per half (128)
 constexpr int SY_UNR_INT = 8;            // rows per group, interior tiles
 constexpr int SY_UNR_SPC = 8;            // rows per group, diagonal / edge tiles
-constexpr int SY_FIN = 64;               // elements per block of the finishing kernel
 constexpr int SY_FACC = 8;               // loads in flight per wave of the finishing kernel
 constexpr int SY_FWAVES = 16;            // waves per block of the finishing kernel
 static_assert(SY_HW == 2 * WAVE, "one wave instruction covers one half of a tile row");
@@ -151,16 +151,26 @@ __device__ __forceinline__ void sy_group(const SyTile &T, int k0, const sy_d2 (&
 // policy (sc1), measured 7% faster for the whole kernel: the stores interleave
 // less with the stream of loads.
 constexpr int SY_STORE_POLICY = 16;  // sc1
-__device__ __forceinline__ void sy_store(const SyTile &T, const double (&ca)[SY_H][2],
+//
+// With sig != nullptr the block also leaves its share of x'A x (CG: sigma =
+// p'Ap), the dot product of its two outputs with x_I and x_J, in sig[tile]:
+// the 512 products summed over each wave, then the 8 wave sums in wave order.
+__device__ __forceinline__ void sy_store(const SyTile &T, int n, const double (&ca)[SY_H][2],
                                          const double *rows, double (*cs)[SY_T],
-                                         double *__restrict__ W) {
+                                         const double *__restrict__ x, double *__restrict__ W,
+                                         double *__restrict__ sig) {
+    __shared__ double sg[SY_WAVES];
+    const int q = threadIdx.x & (SY_T - 1);
+    // this thread's output is element q of the row part (threads < SY_T) or of
+    // the column part; the x value it meets in x'A x
+    const int xi = (threadIdx.x < SY_T ? T.r0 : T.c0) + q;
+    const double xo = (sig && xi < n) ? x[xi] : 0.0;
 #pragma unroll
     for (int h = 0; h < SY_H; ++h) {
         cs[T.w][h * SY_HW + T.lc] = ca[h][0];
         cs[T.w][h * SY_HW + T.lc + 1] = ca[h][1];
     }
     __syncthreads();
-    const int q = threadIdx.x & (SY_T - 1);
     double out;
     if (threadIdx.x < SY_T) {
         out = rows[q];
@@ -175,6 +185,17 @@ __device__ __forceinline__ void sy_store(const SyTile &T, const double (&ca)[SY_
         W + (size_t)T.t * 2 * SY_T, 0, 2 * SY_T * 8, SY_RSRC_WORD3);
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sy_u2, out), ws, threadIdx.x * 8, 0,
                                           SY_STORE_POLICY);
+    if (sig) {
+        const double t = wave_sum(xi < n ? out * xo : 0.0);
+        if (T.lane == 0) sg[T.w] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < SY_WAVES; ++k) v += sg[k];
+            sig[T.t] = v;
+        }
+    }
 }
 
 // Rows of one tile from a buffer resource based at the tile row (tiles whose
@@ -255,10 +276,12 @@ __device__ __forceinline__ void sy_tile_edge(const SyTile &T, int n, int64_t lda
 //   nT <= b < nT + ne            (ragged n only) tile (nT - 1, b - nT) of the last tile row
 //   then the interior tiles (I, J), 1 <= I < n / SY_T, J < I, in row order.
 // st != nullptr: return at once when the Krylov loop has stopped.
-__global__ __launch_bounds__(SY_NT) void symv_tile_kernel(int n, int64_t lda,
+// sig != nullptr: each tile's share of x'A x into sig[tile] (see sy_store).
+__global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void symv_tile_kernel(int n, int64_t lda,
                                                           const double *__restrict__ A,
                                                           const double *__restrict__ x,
-                                                          double *__restrict__ W, const State *st) {
+                                                          double *__restrict__ W, const State *st,
+                                                          double *__restrict__ sig) {
     __shared__ double rows[SY_T];
     __shared__ double cs[SY_WAVES][SY_T];
     if (st && (st->flags & F_STOP)) return;
@@ -284,22 +307,15 @@ __global__ __launch_bounds__(SY_NT) void symv_tile_kernel(int n, int64_t lda,
         sy_tile_full<true>(T, lda, A, x, rows, ca);
     else
         sy_tile_full<false>(T, lda, A, x, rows, ca);
-    sy_store(T, ca, rows, cs, W);
+    sy_store(T, n, ca, rows, cs, x, W, sig);
 }
 
 // y_j = (row parts of tile row J) + (column parts of tile column J), J = j / SY_T,
 // summed in a fixed order: the SY_FWAVES waves take sources w, w + SY_FWAVES,
-// ... and their sums are added in wave order.  With p != nullptr the block also leaves
-// sum_j p_j y_j in partial[block] (CG: sigma = p'q).
-__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, const double *__restrict__ W,
-                                                            double *__restrict__ y,
-                                                            const double *__restrict__ p,
-                                                            double *__restrict__ partial,
-                                                            const State *st) {
-    __shared__ double red[SY_FWAVES][SY_FIN];
-    if (st && (st->flags & F_STOP)) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int w = threadIdx.x / WAVE;
+// ... and their sums are added in wave order.  Every wave calls it; afterwards
+// lane l of wave 0 holds y at j0 + l (j0 = blockIdx.x * SY_FIN).
+__device__ __forceinline__ double sy_finish_sum(int n, const double *__restrict__ W,
+                                                double (*red)[SY_FIN], int lane, int w) {
     const int j0 = blockIdx.x * SY_FIN;
     const int J = j0 / SY_T;
     const int jj = j0 - J * SY_T + lane;
@@ -331,11 +347,28 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, co
     for (int q = 0; q < SY_FACC; ++q) s += acc[q];
     red[w][lane] = s;
     __syncthreads();
+    double v = 0.0;
     if (w == 0) {
-        double v = 0.0;
 #pragma unroll
         for (int q = 0; q < SY_FWAVES; ++q) v += red[q][lane];
-        const int j = j0 + lane;
+    }
+    return v;
+}
+
+// y = A x finished from the tile outputs.  With p != nullptr the block also
+// leaves sum_j p_j y_j in partial[block] (CG: sigma = p'q).
+__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, const double *__restrict__ W,
+                                                            double *__restrict__ y,
+                                                            const double *__restrict__ p,
+                                                            double *__restrict__ partial,
+                                                            const State *st) {
+    __shared__ double red[SY_FWAVES][SY_FIN];
+    if (st && (st->flags & F_STOP)) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const double v = sy_finish_sum(n, W, red, lane, w);
+    if (w == 0) {
+        const int j = blockIdx.x * SY_FIN + lane;
         double contrib = 0.0;
         if (j < n) {
             y[j] = v;
@@ -348,13 +381,94 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, co
     }
 }
 
+// CG's finishing kernel with the symmetric product: q_j as above (not stored),
+// sigma = p'q as the sum of the tiles' shares (every block adds them in the
+// same order, so all blocks hold the same sigma bit for bit), then the
+// iteration's update on the block's elements, as the general CG update does:
+// block 0 records the iteration (or the breakdown / non-finite sigma) in st,
+// x_j += alpha p_j, r_j -= alpha q_j, and the block's r'r and ||x||_inf
+// partials.  The vectors and the shares are loaded before the tile outputs
+// are summed, so their latency is hidden behind that reduction.
+__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
+    int n, const double *__restrict__ W, const double *__restrict__ sig, int ntiles,
+    const double *__restrict__ p, double *__restrict__ x, double *__restrict__ r, State *st,
+    double *__restrict__ prho, int nfb) {
+    __shared__ double red[SY_FWAVES][SY_FIN];
+    __shared__ double sm[SY_FWAVES];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int j = blockIdx.x * SY_FIN + lane;
+    const int jc = min(j, n - 1);
+    double pj = 0.0, xj = 0.0, rj = 0.0;
+    if (w == 0) {
+        pj = p[jc];
+        xj = x[jc];
+        rj = r[jc];
+    }
+    double sg = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += SY_FWAVES * WAVE) sg += sig[i];
+    // block 0 of this very launch may set F_STOP (breakdown) while other blocks
+    // start: the whole block takes one decision, so no wave leaves before a
+    // barrier that the others reach (a launch that sees the new flag would
+    // have found sigma unusable and skipped the update all the same)
+    if (__syncthreads_or((st->flags & F_STOP) != 0)) return;
+    const double qj = sy_finish_sum(n, W, red, lane, w);
+    sg = wave_sum(sg);
+    if (lane == 0) sm[w] = sg;
+    __syncthreads();
+    double sigma = 0.0;
+#pragma unroll
+    for (int k = 0; k < SY_FWAVES; ++k) sigma += sm[k];
+    const double rho = st->rho;
+    const bool ok = finite_d(sigma) && sigma > 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iters += 1;
+        st->sigma = sigma;
+        st->rho_prev = rho;
+        if (!finite_d(sigma))
+            st->flags |= F_NONFIN | F_STOP;
+        else if (sigma <= 0.0)
+            st->flags |= F_BREAK | F_STOP;
+        else
+            st->alpha = rho / sigma;
+    }
+    if (!ok || w != 0) return;
+    const double a = rho / sigma;
+    double s2 = 0.0, xm = 0.0;
+    if (j < n) {
+        const double xi = fma(a, pj, xj);
+        x[j] = xi;
+        const double ri = fma(-a, qj, rj);
+        r[j] = ri;
+        s2 = ri * ri;
+        xm = finite_d(xi) ? fabs(xi) : INFINITY;
+    }
+    s2 = wave_sum(s2);
+    xm = wave_max(xm);
+    if (lane == 0) {
+        prho[blockIdx.x] = s2;
+        prho[nfb + blockIdx.x] = xm;
+    }
+}
+
 int symv_finish_blocks(int n) { return div_up(n, SY_FIN); }
 
 hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
                        double *W, const State *st, const double *p, double *partial,
                        hipStream_t s) {
-    symv_tile_kernel<<<sy_tiles(n), SY_NT, 0, s>>>(n, lda, A, x, W, st);
+    symv_tile_kernel<<<sy_tiles(n), SY_NT, 0, s>>>(n, lda, A, x, W, st, nullptr);
     symv_finish_kernel<<<symv_finish_blocks(n), SY_FWAVES * WAVE, 0, s>>>(n, W, y, p, partial, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_symv_cg(int n, int64_t lda, const double *A, const double *p, double *x,
+                          double *r, double *region, State *st, hipStream_t s) {
+    double *W = region;
+    double *sig = region + sy_ws_doubles(n);
+    const int nfb = symv_finish_blocks(n);
+    symv_tile_kernel<<<sy_tiles(n), SY_NT, 0, s>>>(n, lda, A, p, W, st, sig);
+    symv_cg_finish_kernel<<<nfb, SY_FWAVES * WAVE, 0, s>>>(n, W, sig, sy_tiles(n), p, x, r, st,
+                                                          symv_cg_rho_part(n, region), nfb);
     return hipGetLastError();
 }
 

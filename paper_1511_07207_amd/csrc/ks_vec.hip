@@ -180,6 +180,12 @@ hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int
     return hipGetLastError();
 }
 
+hipError_t launch_cg_pupdate_f64(int n, const double *r, double *p, State *st, const double *prho,
+                                 int nrho, int max_iter, hipStream_t s) {
+    cg_pupdate_kernel<double><<<vec_blocks(n), VEC_NT, 0, s>>>(n, r, p, st, prho, nrho, max_iter);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_cg_begin(int n, const T *r, T *p, State *st, hipStream_t s) {
     cg_begin_kernel<T><<<vec_blocks(n), VEC_NT, 0, s>>>(n, r, p, st);

@@ -44,7 +44,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
                 max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
                 inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
                 timing: bool = False, nrhs: int = 1, stop_backward: bool = False,
-                symmetric: bool = False) -> N.KsParams:
+                symmetric: bool = False, timing_every: int = 0) -> N.KsParams:
     p = N.KsParams()
     N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
     p.lda = int(lda if lda is not None else n)
@@ -59,6 +59,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
     p.flags = ((N.KS_FLAG_TIMING if timing else 0) | (N.KS_FLAG_STOP_BACKWARD if stop_backward else 0)
                | (N.KS_FLAG_SYMMETRIC if symmetric else 0))
     p.nrhs = int(nrhs)
+    p.timing_every = int(timing_every)
     return p
 
 

@@ -83,6 +83,9 @@ def test_bicgstab_parameters_on_host():
     p.nrhs = 4
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
     p.nrhs = 1
+    p.timing_every = -1                           # a timing sample stride is >= 0
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.timing_every = 0
     p.precision = N.KS_IR_BF16
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == 0
     assert L.ks_params_init(ctypes.byref(p), 10, 5) == N.KS_EINVAL
@@ -152,8 +155,8 @@ def test_symmetric_flag_and_symv_on_host():
     L = N.lib()
     sz = ctypes.c_size_t(0)
     assert L.ks_symv_workspace_bytes(16384, ctypes.byref(sz)) == 0
-    tiles = 128 * 129 // 2                        # 128 x 128 tiles of the lower triangle
-    assert sz.value == tiles * 2 * 128 * 8
+    tiles = 64 * 65 // 2                          # 256 x 256 tiles of the lower triangle
+    assert sz.value == tiles * 2 * 256 * 8        # a row part and a column part per tile
     assert L.ks_symv_workspace_bytes(0, ctypes.byref(sz)) == N.KS_EINVAL
     assert L.ks_symv(10, 10, None, None, None, None, 0, None) == N.KS_EINVAL
     p = N.KsParams()
@@ -162,8 +165,12 @@ def test_symmetric_flag_and_symv_on_host():
     assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(base)) == 0
     p.flags = N.KS_FLAG_SYMMETRIC
     assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
-    assert sz.value >= base.value + tiles * 2 * 128 * 8
+    # CG also keeps a p'Ap share per tile and two partials per 64-element finishing block
+    assert sz.value >= base.value + (tiles * 2 * 256 + tiles + 2 * 16384 // 64) * 8
     p.nrhs = 4
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.nrhs = 1
+    p.timing_every = -1                           # a timing sample stride is >= 0
     assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
     q = N.KsParams()
     assert L.ks_params_init(ctypes.byref(q), 100, N.KS_GMRES) == 0

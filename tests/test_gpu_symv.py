@@ -100,3 +100,23 @@ def test_cg_symmetric_ir_and_special_cases(device):
     # an indefinite matrix breaks CG down with the symmetric product as well
     x, info = krylov.solve(_t(-p.A, device), b, method="cg", symmetric=True)
     assert info["status"] == 2
+
+
+def test_cg_symmetric_timing_sample(device):
+    """KS_FLAG_TIMING with timing_every = 3 and a polling chunk of 4: only the
+    launches of chunks 0, 3, 6, ... that did work are timed."""
+    from paper_1511_07207_amd import krylov
+
+    n = 1000
+    p = spd_problem(n, 1e3, seed=8, config_id=0)
+    A, b = _t(p.A, device), _t(p.b, device)
+    x, info = krylov.solve(A, b, method="cg", tol=1e-10, symmetric=True, timing=True,
+                           timing_every=3, poll_every=4)
+    assert info["status"] == 0 and info["restarts"] == 0, info
+    it = info["iters"]
+    expect = sum(min(4, it - 4 * c) for c in range(0, (it + 3) // 4, 3))
+    assert info["gemv_calls"] == expect, (info["gemv_calls"], expect, it)
+    assert info["gemv_ms"] > 0.0
+    _, full = krylov.solve(A, b, method="cg", tol=1e-10, symmetric=True, timing=True,
+                           poll_every=4)
+    assert full["gemv_calls"] == full["iters"] == it
