@@ -127,8 +127,19 @@ template <int NT>
 __device__ __forceinline__ double reduce_partials_all(const double *partial, int count, int stride) {
     __shared__ double sm_r[NT / WAVE];
     __shared__ double sm_out;
+    // the loads go out eight at a time ahead of the adds, which keep the
+    // order of the plain strided loop (the same sum bit for bit); a plain loop
+    // waits for each load before its add
     double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += NT) s += partial[(size_t)i * stride];
+    int i = threadIdx.x;
+    for (; i + 7 * NT < count; i += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(i + u * NT) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < count; i += NT) s += partial[(size_t)i * stride];
     s = block_sum<NT>(s, sm_r);
     if (threadIdx.x == 0) sm_out = s;
     __syncthreads();
@@ -141,7 +152,15 @@ __device__ __forceinline__ double reduce_partials_max_all(const double *partial,
     __shared__ double sm_r[NT / WAVE];
     __shared__ double sm_out;
     double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += NT) s = fmax(s, partial[(size_t)i * stride]);
+    int i = threadIdx.x;
+    for (; i + 7 * NT < count; i += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(i + u * NT) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fmax(s, v[u]);
+    }
+    for (; i < count; i += NT) s = fmax(s, partial[(size_t)i * stride]);
     s = block_max<NT>(s, sm_r);
     if (threadIdx.x == 0) sm_out = s;
     __syncthreads();

@@ -451,10 +451,15 @@ __device__ __forceinline__ void gm_cgs_body(int n, int ldv, const T *__restrict_
     }
     if constexpr (MODE <= 1) {
         double *dst = (MODE == 0) ? P.h1 : P.h2;
-        for (int j = 0; j < kk; ++j) {
-            const double prod = valid ? (double)V[(size_t)j * ldv + i] * wi : 0.0;
-            const double t = wave_sum(prod);
-            if (lane == 0) red[wv][j] = t;
+        // eight coefficients at a time: their wave sums together by the
+        // halving butterfly (lane group lane / 8 ends with coefficient j0 + g)
+        for (int j0 = 0; j0 < kk; j0 += 8) {
+            double prod[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                prod[u] = (valid && j0 + u < kk) ? (double)V[(size_t)(j0 + u) * ldv + i] * wi : 0.0;
+            const double t = rows_reduce<8>(prod, lane);
+            if (lane % 8 == 0 && j0 + lane / 8 < kk) red[wv][j0 + lane / 8] = t;
         }
         __syncthreads();
         for (int j = threadIdx.x; j < kk; j += CGS_NT) {
@@ -488,19 +493,30 @@ __device__ __forceinline__ void gm_givens_body(int n, const T *__restrict__ w, T
             if (i < n) vnext[i] = (T)((double)w[i] / hk1);
         }
     }
-    if (bid != 0 || threadIdx.x != 0) return;
+    if (bid != 0) return;
+    // block 0: column k of H and the earlier rotations go to LDS with all
+    // threads, then one thread rotates the column there (a single thread
+    // reading them from memory waits for every load in turn)
+    __shared__ double col[KS_MAX_RESTART + 1], rcs[KS_MAX_RESTART], rsn[KS_MAX_RESTART];
     const int m = ga.m;
     double *H = ga.H, *R = ga.R;
-    H[(size_t)(k + 1) * m + k] = hk1;
-    for (int j = 0; j <= k; ++j) R[(size_t)j * m + k] = H[(size_t)j * m + k];
-    R[(size_t)(k + 1) * m + k] = hk1;
-    for (int q = 0; q < k; ++q) {
-        const double a = R[(size_t)q * m + k], bb = R[(size_t)(q + 1) * m + k];
-        R[(size_t)q * m + k] = ga.cs[q] * a + ga.sn[q] * bb;
-        R[(size_t)(q + 1) * m + k] = -ga.sn[q] * a + ga.cs[q] * bb;
+    for (int j = threadIdx.x; j <= k; j += VEC_NT) col[j] = H[(size_t)j * m + k];
+    for (int q = threadIdx.x; q < k; q += VEC_NT) {
+        rcs[q] = ga.cs[q];
+        rsn[q] = ga.sn[q];
     }
-    const double akk = R[(size_t)k * m + k], bk = R[(size_t)(k + 1) * m + k];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    H[(size_t)(k + 1) * m + k] = hk1;
+    col[k + 1] = hk1;
+    for (int q = 0; q < k; ++q) {
+        const double a = col[q], bb = col[q + 1];
+        col[q] = rcs[q] * a + rsn[q] * bb;
+        col[q + 1] = -rsn[q] * a + rcs[q] * bb;
+    }
+    const double akk = col[k], bk = col[k + 1];
     const double rho = hypot(akk, bk);
+    for (int j = 0; j <= k + 1; ++j) R[(size_t)j * m + k] = col[j];
     st->hk1 = hk1;
     if (!finite_d(rho) || !finite_d(avk)) {
         st->flags |= F_NONFIN | F_STOP;
