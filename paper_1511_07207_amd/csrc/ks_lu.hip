@@ -267,6 +267,22 @@ __device__ __forceinline__ double ts_readlane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// out[q] = sum over the wave of pv[q] * xl for the wave's Q = TS_SB / TS_WAVES
+// rows, eight rows at a time by the halving butterfly (lane group g = lane / 8
+// ends with row q0 + g), instead of one wave sum per row.
+template <int Q>
+__device__ __forceinline__ void ts_rows_sums(const double (&pv)[Q], double xl, int lane, double *out) {
+    static_assert(Q % 8 == 0, "rows in groups of eight");
+#pragma unroll
+    for (int q0 = 0; q0 < Q; q0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pv[q0 + u] * xl;
+        const double s = rows_reduce<8>(v, lane);
+        if (lane % 8 == 0) out[q0 + lane / 8] = s;
+    }
+}
+
 // Step I of the forward substitution L y = t in place (L unit lower).
 __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
                                                          const float *__restrict__ LU,
@@ -281,12 +297,10 @@ __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
         double v[TS_PW];
 #pragma unroll
         for (int k = 0; k < TS_PW; ++k)
-            v[k] = (double)LU[(int64_t)min(rs + k, n - 1) * ldl + cb + lane];
-#pragma unroll
-        for (int k = 0; k < TS_PW; ++k) {
-            const double s = wave_sum(v[k] * xl);
-            if (lane == 0 && rs + k < n) t[rs + k] -= s;
-        }
+            v[k] = (double)LU[(int64_t)min(rs + k, n - 1) * ldl + cb + lane] * xl;
+        // the wave's rows summed together (lane group lane / 8 ends with row rs + g)
+        const double s = rows_reduce<TS_PW>(v, lane);
+        if (lane % (WAVE / TS_PW) == 0 && rs + lane / (WAVE / TS_PW) < n) t[rs + lane / (WAVE / TS_PW)] -= s;
         return;
     }
     const int r0 = I * TS_SB, m = min(TS_SB, n - r0);
@@ -297,7 +311,7 @@ __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
     for (int q = 0; q < Q; ++q) {
         const int k = w + TS_WAVES * q;
         tl[q] = (double)LU[(int64_t)(r0 + min(k, m - 1)) * ldl + r0 + cc];
-        if (I >= 1) pv[q] = (double)LU[(int64_t)(r0 + min(w * Q + q, m - 1)) * ldl + cb + lane];
+        pv[q] = I >= 1 ? (double)LU[(int64_t)(r0 + min(w * Q + q, m - 1)) * ldl + cb + lane] : 0.0;
     }
     const double cval = (w == 0 && lane < m) ? t[r0 + lane] : 0.0;
 #pragma unroll
@@ -306,11 +320,7 @@ __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
         // strictly lower part (the unit diagonal is implicit)
         T[k * TS_LDT + lane] = (k < m && lane < k) ? tl[q] : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double s = I >= 1 ? wave_sum(pv[q] * xl) : 0.0;
-        if (lane == 0) sI[w * Q + q] = s;
-    }
+    ts_rows_sums(pv, I >= 1 ? xl : 0.0, lane, sI + w * Q);
     __syncthreads();
     if (w != 0) return;
     double acc = lane < m ? cval - sI[lane] : 0.0;
@@ -343,12 +353,9 @@ __global__ __launch_bounds__(GEMV_NT) void lu_bwd_kernel(int n, int64_t ldl,
         double v[TS_PW];
 #pragma unroll
         for (int k = 0; k < TS_PW; ++k)
-            v[k] = lin ? (double)LU[(int64_t)min(rs + k, rend - 1) * ldl + cl] : 0.0;
-#pragma unroll
-        for (int k = 0; k < TS_PW; ++k) {
-            const double s = wave_sum(v[k] * xl);
-            if (lane == 0 && rs + k < rend) t[rs + k] -= s;
-        }
+            v[k] = (lin ? (double)LU[(int64_t)min(rs + k, rend - 1) * ldl + cl] : 0.0) * xl;
+        const double s = rows_reduce<TS_PW>(v, lane);
+        if (lane % (WAVE / TS_PW) == 0 && rs + lane / (WAVE / TS_PW) < rend) t[rs + lane / (WAVE / TS_PW)] -= s;
         return;
     }
     const int r0 = J * TS_SB, m = min(TS_SB, n - r0);
@@ -368,11 +375,7 @@ __global__ __launch_bounds__(GEMV_NT) void lu_bwd_kernel(int n, int64_t ldl,
         // upper part with the diagonal; rows past n get a unit diagonal
         T[k * TS_LDT + lane] = (k < m && lane < m) ? (lane >= k ? tl[q] : 0.0) : (lane == k ? 1.0 : 0.0);
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double s = wave_sum(pv[q] * xl);
-        if (lane == 0) sI[w * Q + q] = s;
-    }
+    ts_rows_sums(pv, xl, lane, sI + w * Q);
     __syncthreads();
     if (w != 0) return;
     double acc = lane < m ? cval - sI[lane] : 0.0;
