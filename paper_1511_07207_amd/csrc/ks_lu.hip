@@ -83,16 +83,27 @@ __device__ __forceinline__ void lu_panel_col(int n, int k0, int b, float (&p)[LU
         sh.red_i[wv] = bi;
     }
     __syncthreads();
-    if (t == 0) {
-        float v = sh.red_v[0];
-        int i = sh.red_i[0];
-        for (int w = 1; w < LU_NT / WAVE; ++w)
-            if (sh.red_v[w] > v || (sh.red_v[w] == v && sh.red_i[w] < i)) {
-                v = sh.red_v[w];
-                i = sh.red_i[w];
+    // the waves' candidates reduced by wave 0 with the same rule (the largest
+    // magnitude, the lowest row on ties: a total order, so any reduction
+    // order picks the same row)
+    if (wv == 0) {
+        constexpr int NW = LU_NT / WAVE;
+        static_assert(NW <= WAVE && (NW & (NW - 1)) == 0, "one candidate per lane");
+        float v = lane < NW ? sh.red_v[lane] : -2.0f;
+        int i = lane < NW ? sh.red_i[lane] : rj;
+#pragma unroll
+        for (int off = NW / 2; off >= 1; off >>= 1) {
+            const float ov = __shfl_xor(v, off);
+            const int oi = __shfl_xor(i, off);
+            if (ov > v || (ov == v && oi < i)) {
+                v = ov;
+                i = oi;
             }
-        sh.piv = i;
-        piv[rj] = i;
+        }
+        if (lane == 0) {
+            sh.piv = i;
+            piv[rj] = i;
+        }
     }
     __syncthreads();
     const int pr = sh.piv;
