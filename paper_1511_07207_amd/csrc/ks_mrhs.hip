@@ -21,7 +21,11 @@
 // their L2.  Each block stages P's chunks of 64 values of K in LDS (double
 // buffered), shared by its four waves: measured on MI355X at n = 16384,
 // s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the matrix-core peak),
-// binary32 0.60 -> 0.42 ms, the same sums bit for bit.
+// binary32 0.60 -> 0.42 ms, the same sums bit for bit.  In binary64 A is
+// loaded three steps ahead of its use (0.64 -> 0.61 ms in the solve, the same
+// sums; binary32 measured slower that way and keeps one step); with A held in
+// registers instead of streamed the same MFMA sequence reaches 0.82 / 0.75 of
+// the peak, so the rest of the gap is the stream of A, not the matrix cores.
 #include <algorithm>
 
 #include "ks_device.h"
@@ -86,11 +90,25 @@ struct Mfma<float> {
 
 constexpr int MR_WAVES = 4;      // waves per block
 constexpr int MR_NTHR = MR_WAVES * WAVE;
-constexpr int MR_WR = 32;        // rows of Q per wave (two 16-row tiles)
-constexpr int MR_BROWS = MR_WAVES * MR_WR;
+constexpr int MR_BROWS = MR_WAVES * 32;  // rows of the block that sizes the K splits
 constexpr int MR_KC = 64;        // values of K per LDS-staged chunk of P
 constexpr int MR_KPAD = MR_KC + 2;  // padded column stride of the staged chunk (bank spread)
+constexpr int MR_STEPS = MR_KC / 16;  // MFMA steps of 16 per chunk
+constexpr int MR_AHEAD = 3;      // steps of A in flight ahead of the one multiplied
 static_assert(MR_NTHR == 16 * (MR_KC / 4), "each thread stages CT groups of 4 values");
+static_assert(MR_AHEAD < MR_STEPS, "a ring of MR_STEPS register sets for A");
+
+// Row tiles (of 16 rows) per wave: two (each value of P read from LDS feeds
+// two MFMAs); one row tile per wave measured no faster for either precision
+// on MI355X at n = 16384, s = 64.
+template <typename T>
+constexpr int mr_row_tiles() {
+    return 2;
+}
+template <typename T>
+constexpr int mr_block_rows() {
+    return MR_WAVES * 16 * mr_row_tiles<T>();
+}
 
 // Block -> (row block, split).  Work-groups are dispatched round-robin over
 // the 8 XCDs; give each split a fixed group of 8/S XCDs when the counts allow.
@@ -109,7 +127,7 @@ __device__ __forceinline__ void mr_block_map(int nrb, int S, int &rb, int &sp) {
 
 // Qpart[sp] = A[:, K_sp] * P[K_sp, :] for the split's K range.
 template <typename T, int CT>
-__global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t lda,
+__global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(2, 8))) void mr_gemm_kernel(int n, int64_t lda,
                                                                   const T *__restrict__ A,
                                                                   const T *__restrict__ P, int ldp,
                                                                   T *__restrict__ Qpart, int ldq,
@@ -117,37 +135,41 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t
                                                                   const State *st, int gate) {
     using M = Mfma<T>;
     using Acc = typename M::Acc;
+    constexpr int RT = mr_row_tiles<T>();
+    constexpr int BROWS = mr_block_rows<T>();
     if (gate == 2 && (st->flags & F_STOP)) return;       // iteration: skip when all stopped
     if (gate == 1 && !(st->flags & F_STOP)) return;      // residual: only when all stopped
-    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    const int nrb = (n + BROWS - 1) / BROWS;
     int rb, sp;
     mr_block_map(nrb, S, rb, sp);
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int g = lane >> 4, c16 = lane & 15;
-    const int row0 = rb * MR_BROWS + w * MR_WR;
+    const int row0 = rb * BROWS + w * 16 * RT;
     const int kb = sp * kchunk, ke = min(n, kb + kchunk);
-    Acc acc[2][CT];
+    Acc acc[RT][CT];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = Acc{0, 0, 0, 0};
-    const T *arow[2];
+    const T *arow[RT];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) arow[rt] = A + (int64_t)min(row0 + 16 * rt + c16, n - 1) * lda;
+    for (int rt = 0; rt < RT; ++rt) arow[rt] = A + (int64_t)min(row0 + 16 * rt + c16, n - 1) * lda;
     const T *pcol[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) pcol[ct] = P + (size_t)(16 * ct + c16) * ldp;
     // Whole chunks of MR_KC values of K: the block stages P's chunk (all s
     // columns) in LDS once, double-buffered, instead of every wave fetching
     // its own copy from L2; the next chunk is loaded into registers while the
-    // current one is multiplied.  A streams from HBM one step of 16 ahead.
+    // current one is multiplied.  A streams from HBM MR_AHEAD steps of 16
+    // ahead through a ring of MR_STEPS register sets (step j in set j % 4).
     // Every lane still takes k = k0 + 4g .. k0 + 4g + 3 per step of 16, in
     // order, so the sums are those of the unstaged loop.
     constexpr int NC = 16 * CT;
     __shared__ T lp[2][NC * MR_KPAD];
     const int nch = (ke - kb) / MR_KC;
     const int ks_end = kb + nch * MR_KC;
-    T a[2][4], p[CT][4];
+    const int ns = nch * MR_STEPS;  // steps inside whole chunks
+    T a[RT][4], p[CT][4];
     if (nch > 0) {
         // staging: value groups of 4 consecutive k, gi = tid + MR_NTHR j
         const int tid = threadIdx.x;
@@ -172,41 +194,82 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t
         gload(0);
         lstore(0);
         __syncthreads();
+        if constexpr (sizeof(T) == 8) {
+            // binary64: A MR_AHEAD steps ahead, P one value of t at a time
+            T ar[MR_STEPS][RT][4];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kb + 4 * g, a[rt]);
-        for (int c = 0; c < nch; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < nch) gload(c + 1);
+            for (int d = 0; d < MR_AHEAD; ++d)
+                if (d < ns) {
 #pragma unroll
-            for (int st16 = 0; st16 < MR_KC / 16; ++st16) {
-                const int k0 = kb + c * MR_KC + st16 * 16;
-                const bool more = k0 + 16 < ks_end;
-                T an[2][4];
-                if (more) {
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + k0 + 16 + 4 * g, an[rt]);
+                    for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + kb + 16 * d + 4 * g, ar[d][rt]);
                 }
+            for (int c = 0; c < nch; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < nch) gload(c + 1);
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                    const T *q = &lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g];
+                for (int st16 = 0; st16 < MR_STEPS; ++st16) {
+                    const int j = MR_STEPS * c + st16;
+                    if (j + MR_AHEAD < ns) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) p[ct][t] = q[t];
+                        for (int rt = 0; rt < RT; ++rt)
+                            M::load4_nt(arow[rt] + kb + 16 * (j + MR_AHEAD) + 4 * g,
+                                        ar[(st16 + MR_AHEAD) % MR_STEPS][rt]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        T pt[CT];
+#pragma unroll
+                        for (int ct = 0; ct < CT; ++ct)
+                            pt[ct] = lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g + t];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                            for (int ct = 0; ct < CT; ++ct)
+                                acc[rt][ct] = M::mma(ar[st16][rt][t], pt[ct], acc[rt][ct]);
+                    }
                 }
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
-                if (more) {
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
-                }
+                if (c + 1 < nch) lstore(buf ^ 1);
+                __syncthreads();
             }
-            if (c + 1 < nch) lstore(buf ^ 1);
-            __syncthreads();
+        } else {
+            // binary32: A one step ahead, P's four values of t loaded together
+            // (measured faster for binary32 than the deeper ring)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + kb + 4 * g, a[rt]);
+            for (int c = 0; c < nch; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+                for (int st16 = 0; st16 < MR_STEPS; ++st16) {
+                    const int k0 = kb + c * MR_KC + st16 * 16;
+                    const bool more = k0 + 16 < ks_end;
+                    T an[RT][4];
+                    if (more) {
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + k0 + 16 + 4 * g, an[rt]);
+                    }
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        const T *q = &lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) p[ct][t] = q[t];
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
+                    if (more) {
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
+                    }
+                }
+                if (c + 1 < nch) lstore(buf ^ 1);
+                __syncthreads();
+            }
         }
     }
     // the rest of the range: full steps of 16 straight from P, then the tail
@@ -215,13 +278,13 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t
     for (; k0 < kfull; k0 += 16) {
         const int kk = k0 + 4 * g;
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
+        for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + kk, a[rt]);
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) M::load4(pcol[ct] + kk, p[ct]);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
     }
@@ -231,20 +294,20 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) void mr_gemm_kernel(int n, int64_t
             const int k = k0 + 4 * g + t;
             const bool ok = k < ke;
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) a[rt][t] = ok ? arow[rt][k] : T(0);
+            for (int rt = 0; rt < RT; ++rt) a[rt][t] = ok ? arow[rt][k] : T(0);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) p[ct][t] = ok ? pcol[ct][k] : T(0);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
     }
     T *qs = Qpart + (size_t)sp * (size_t)(16 * CT) * ldq;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
@@ -586,7 +649,7 @@ template <typename T>
 hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T *Qpart, int ldq,
                           int s, const State *st, int gate, hipStream_t strm) {
     const int S = mr_splits(n), kc = mr_kchunk(n, S);
-    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    const int nrb = div_up(n, mr_block_rows<T>());
     const int grid = nrb * S;
     switch ((s + 15) / 16) {
         case 1:
