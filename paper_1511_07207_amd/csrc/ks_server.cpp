@@ -816,7 +816,7 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         }
         if (done != NO_OUTCOME && r->fp64_tail) {
             // binary64 finish of a refinement request: one more outer step;
-            // success is judged on the backward error of the result
+            // success is decided on the backward error of the result
             r->outer++;
             iters = r->total_iters + h.iters;
             finish_metrics(r, h);
