@@ -272,6 +272,14 @@ int ks_symv_workspace_bytes(int32_t n, size_t *bytes);
 int ks_symv(int32_t n, int64_t lda, const double *d_A, const double *d_x, double *d_y,
             void *d_ws, size_t ws_bytes, void *stream);
 
+/* The same product for a symmetric binary32 A with binary32 x, y and binary32
+ * accumulation (the product of CG's binary32 inner solves under
+ * KS_FLAG_SYMMETRIC).  d_ws: at least ks_symv_workspace_bytes(n) / 2 bytes
+ * (KS_ENOMEM below that).  d_A 16-byte aligned with lda * 4 a multiple of 16;
+ * d_x, d_y, d_ws 16-byte aligned (else KS_EINVAL).  Enqueued on `stream`. */
+int ks_symv_f32(int32_t n, int64_t lda, const float *d_A, const float *d_x, float *d_y,
+                void *d_ws, size_t ws_bytes, void *stream);
+
 /* Binary32 block LU with partial pivoting (the direct-methods section's block
  * algorithm, column blocks of 16; the factorization GMRES-IR uses): d_LU
  * (n x lda_lu floats, row-major, lda_lu >= n) receives the binary32 rounding

@@ -51,17 +51,16 @@ __device__ __forceinline__ T wave_max(T x) {
     return x;
 }
 
-// Block sum; the result is valid in thread 0 only.  smem: NT/64 entries.
 // One step of the row butterfly: the lanes whose `mask` bit is 0 keep the
 // first half of their K values, the others the second half, each adding the
 // partner's copy of the half it keeps.
-template <int K, int U>
-__device__ __forceinline__ void rows_fold(double (&v)[U], int lane, int mask) {
+template <int K, int U, typename V>
+__device__ __forceinline__ void rows_fold(V (&v)[U], int lane, int mask) {
     const bool hi = (lane & mask) != 0;
 #pragma unroll
     for (int i = 0; i < K / 2; ++i) {
-        const double keep = hi ? v[i + K / 2] : v[i];
-        const double send = hi ? v[i] : v[i + K / 2];
+        const V keep = hi ? v[i + K / 2] : v[i];
+        const V send = hi ? v[i] : v[i + K / 2];
         v[i] = keep + __shfl_xor(send, mask);
     }
 }
@@ -70,19 +69,29 @@ __device__ __forceinline__ void rows_fold(double (&v)[U], int lane, int mask) {
 // the lane group g = lane / (64 / U) holds the sum of row g: the halving
 // exchanges over lane bits 5, 4, ... leave row g in the lanes whose high bits
 // spell g, and the remaining low bits are summed by plain exchanges.
-template <int U>
-__device__ __forceinline__ double rows_reduce(double (&v)[U], int lane) {
+template <int U, typename V>
+__device__ __forceinline__ V rows_reduce(V (&v)[U], int lane) {
     static_assert(U == 4 || U == 8 || U == 16, "row group of 4, 8 or 16");
     rows_fold<U, U>(v, lane, 32);
     if constexpr (U >= 4) rows_fold<U / 2, U>(v, lane, 16);
     if constexpr (U >= 8) rows_fold<U / 4, U>(v, lane, 8);
     if constexpr (U >= 16) rows_fold<U / 8, U>(v, lane, 4);
-    double s = v[0];
+    V s = v[0];
 #pragma unroll
     for (int m = 32 / U; m >= 1; m >>= 1) s += __shfl_xor(s, m);
     return s;
 }
 
+// Position in the lower triangle: t = i (i + 1) / 2 + j, j <= i  ->  (i, j)
+__device__ __forceinline__ void tri_ij(int t, int &I, int &J) {
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (i > 0 && i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+// Block sum; the result is valid in thread 0 only.  smem: NT/64 entries.
 template <int NT, typename T>
 __device__ __forceinline__ T block_sum(T v, T *smem) {
     constexpr int NW = NT / WAVE;

@@ -231,15 +231,20 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
                 if ((rc = timing_pair(s, &e0, &e1))) return rc;
                 if (e0) HIPCHK(hipEventRecord(e0, sm));
                 bool symmetric = false;
-                if constexpr (std::is_same<TA, double>::value && std::is_same<T, double>::value) {
-                    if (s->sy) {
-                        // product and update in two launches (the timed pair
-                        // covers both; the update adds 40n bytes to A's)
+                if (s->sy) {
+                    // product and update in two launches (the timed pair
+                    // covers both; the update adds 5 vector passes to A's bytes)
+                    if constexpr (std::is_same<TA, double>::value && std::is_same<T, double>::value) {
                         HIPCHK(launch_symv_cg(n, lda, A, p, x, r, s->sy, st, sm));
-                        if (e1) HIPCHK(hipEventRecord(e1, sm));
-                        HIPCHK(launch_cg_pupdate_f64(n, r, p, st, symv_cg_rho_part(n, s->sy),
-                                                     symv_finish_blocks(n), max_iter, sm));
                         symmetric = true;
+                    } else if constexpr (std::is_same<TA, float>::value && std::is_same<T, float>::value) {
+                        HIPCHK(launch_symv32_cg(n, lda, A, p, x, r, s->sy, st, sm));
+                        symmetric = true;
+                    }
+                    if (symmetric) {
+                        if (e1) HIPCHK(hipEventRecord(e1, sm));
+                        HIPCHK(launch_cg_pupdate_from<T>(n, r, p, st, symv_cg_rho_part(n, s->sy),
+                                                         symv_finish_blocks(n), max_iter, sm));
                     }
                 }
                 if (!symmetric) {
@@ -1380,6 +1385,17 @@ int ks_symv(int32_t n, int64_t lda, const double *dA, const double *d_x, double 
     if (ws_bytes < sy_ws_doubles(n) * sizeof(double)) return KS_ENOMEM;
     HIPCHK(launch_symv(n, lda, dA, d_x, d_y, (double *)d_ws, nullptr, nullptr, nullptr,
                        (hipStream_t)stream));
+    return KS_OK;
+}
+
+int ks_symv_f32(int32_t n, int64_t lda, const float *dA, const float *d_x, float *d_y, void *d_ws,
+                size_t ws_bytes, void *stream) {
+    if (n < 1 || lda < n || !dA || !d_x || !d_y || !d_ws) return KS_EINVAL;
+    if ((uintptr_t)dA % 16 || (lda * 4) % 16 || (uintptr_t)d_x % 16 || (uintptr_t)d_y % 16 ||
+        (uintptr_t)d_ws % 16)
+        return KS_EINVAL;
+    if (ws_bytes < sy_ws_doubles(n) * sizeof(float)) return KS_ENOMEM;
+    HIPCHK(launch_symv32(n, lda, dA, d_x, d_y, (float *)d_ws, (hipStream_t)stream));
     return KS_OK;
 }
 

@@ -219,9 +219,10 @@ hipError_t launch_cg_update(int n, T *x, T *r, const T *p, const T *q, State *st
 template <typename T>
 hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int max_iter,
                              hipStream_t s);
-// the same with the r'r and ||x||_inf partials at prho ([nrho] each), binary64
-hipError_t launch_cg_pupdate_f64(int n, const double *r, double *p, State *st, const double *prho,
-                                 int nrho, int max_iter, hipStream_t s);
+// the same with the r'r and ||x||_inf partials at prho ([nrho] each)
+template <typename T>
+hipError_t launch_cg_pupdate_from(int n, const T *r, T *p, State *st, const double *prho, int nrho,
+                                  int max_iter, hipStream_t s);
 // p = r, inner flags cleared (rho comes from the residual kernel).
 template <typename T>
 hipError_t launch_cg_begin(int n, const T *r, T *p, State *st, hipStream_t s);
@@ -293,6 +294,16 @@ hipError_t launch_symv_cg(int n, int64_t lda, const double *A, const double *p, 
 inline double *symv_cg_rho_part(int n, double *region) {
     return region + sy_ws_doubles(n) + round_up(sy_tiles(n), 32);
 }
+
+// The same two products for binary32 A and vectors with binary32
+// accumulation (the inner solves of refinement): y = A x from the lower
+// triangle (W: at least sy_ws_doubles(n) doubles, used as floats), and CG's
+// product and update in two launches (region as for launch_symv_cg, W as
+// floats; the shares of p'Ap and the partials binary64).
+hipError_t launch_symv32(int n, int64_t lda, const float *A, const float *x, float *y, float *W,
+                         hipStream_t s);
+hipError_t launch_symv32_cg(int n, int64_t lda, const float *A, const float *p, float *x, float *r,
+                            double *region, State *st, hipStream_t s);
 
 // Fused small-n CG (n <= FZ_MAX_N, binary64, no backward-error stopping): one
 // launch per iteration instead of three, bitwise the same arithmetic.

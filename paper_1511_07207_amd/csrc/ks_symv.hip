@@ -69,15 +69,6 @@ static_assert(SY_HW == 2 * WAVE, "one wave instruction covers one half of a tile
 static_assert(SY_RPW % SY_UNR_INT == 0 && SY_RPW % SY_UNR_SPC == 0, "groups tile the rows");
 static_assert(SY_T % SY_FIN == 0, "a finishing block stays inside one tile column");
 
-// t = i (i + 1) / 2 + j, j <= i  ->  (i, j)
-__device__ __forceinline__ void sy_tri_ij(int t, int &I, int &J) {
-    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (i > 0 && i * (i + 1) / 2 > t) --i;
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    I = i;
-    J = t - i * (i + 1) / 2;
-}
-
 // Rows of a tile are interleaved over the waves: wave w reads rows w, w + 4,
 // w + 8, ... (local row lr = w + SY_WAVES * k), so the block as a whole reads
 // consecutive rows at any moment (measured 5% faster than contiguous row
@@ -296,7 +287,7 @@ __global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         I = nT - 1;
         J = b - nT;
     } else {
-        sy_tri_ij(b - nT - ne, I, J);
+        tri_ij(b - nT - ne, I, J);
         I += 1;
     }
     const SyTile T = sy_setup(n, I, J, x);

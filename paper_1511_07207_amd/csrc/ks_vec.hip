@@ -180,9 +180,10 @@ hipError_t launch_cg_pupdate(int n, const T *r, T *p, State *st, Partials P, int
     return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate_f64(int n, const double *r, double *p, State *st, const double *prho,
-                                 int nrho, int max_iter, hipStream_t s) {
-    cg_pupdate_kernel<double><<<vec_blocks(n), VEC_NT, 0, s>>>(n, r, p, st, prho, nrho, max_iter);
+template <typename T>
+hipError_t launch_cg_pupdate_from(int n, const T *r, T *p, State *st, const double *prho, int nrho,
+                                  int max_iter, hipStream_t s) {
+    cg_pupdate_kernel<T><<<vec_blocks(n), VEC_NT, 0, s>>>(n, r, p, st, prho, nrho, max_iter);
     return hipGetLastError();
 }
 
@@ -299,6 +300,8 @@ hipError_t launch_read_ceiling(const void *src, size_t bytes, double *sink, hipS
     template hipError_t launch_cg_pupdate<T>(int, const T *, T *, State *, Partials, int,      \
                                              hipStream_t);                                     \
     template hipError_t launch_cg_begin<T>(int, const T *, T *, State *, hipStream_t);        \
+    template hipError_t launch_cg_pupdate_from<T>(int, const T *, T *, State *, const double *, \
+                                                  int, int, hipStream_t);                      \
     template hipError_t launch_gm_begin<T>(int, const T *, T *, State *, GmArrays,            \
                                            hipStream_t);                                       \
     template hipError_t launch_gm_finish<T>(int, int, const T *, T *, State *, GmArrays,      \

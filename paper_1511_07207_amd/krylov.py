@@ -253,18 +253,20 @@ def gemv(A: torch.Tensor, v: torch.Tensor, y: torch.Tensor | None = None,
 
 def symv(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
          n: int | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """y = A x for symmetric float64 A, reading only its lower triangle."""
-    if A.dtype != torch.float64:
-        raise TypeError("symv: A must be float64")
+    """y = A x for symmetric A (float64, or float32 with float32 x, y and
+    accumulation), reading only its lower triangle."""
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("symv: A must be float64 or float32")
     n = A.shape[0] if n is None else n
     sz = ctypes.c_size_t(0)
     N.check(N.lib().ks_symv_workspace_bytes(int(n), ctypes.byref(sz)), "ks_symv_workspace_bytes")
     if workspace is None or workspace.numel() < sz.value:
         workspace = torch.empty(sz.value, dtype=torch.uint8, device=A.device)
     if y is None:
-        y = torch.empty(n, dtype=torch.float64, device=A.device)
-    N.check(N.lib().ks_symv(int(n), int(A.stride(0)), _ptr(A), _ptr(x), _ptr(y), _ptr(workspace),
-                            sz.value, _stream_handle()), "ks_symv")
+        y = torch.empty(n, dtype=A.dtype, device=A.device)
+    fn = N.lib().ks_symv if A.dtype == torch.float64 else N.lib().ks_symv_f32
+    N.check(fn(int(n), int(A.stride(0)), _ptr(A), _ptr(x), _ptr(y), _ptr(workspace), sz.value,
+               _stream_handle()), "ks_symv")
     return y
 
 

@@ -120,3 +120,93 @@ def test_cg_symmetric_timing_sample(device):
     _, full = krylov.solve(A, b, method="cg", tol=1e-10, symmetric=True, timing=True,
                            poll_every=4)
     assert full["gemv_calls"] == full["iters"] == it
+
+
+# ------------------------------------------------- binary32 symmetric product
+
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("pad", [0, 4])
+def test_symv32_matches_full_product(device, n, pad):
+    """Binary32 A, x, y and accumulation: within the binary32 rounding bound
+    2 n u |A||x| of the oracle's binary64 product of the same binary32 values,
+    NaN above the diagonal and in the padding never reaching y."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    print(f"symv32 n={n} pad={pad}", flush=True)
+    rng = np.random.default_rng(11 * n + pad)
+    L = np.tril(rng.standard_normal((n, n))).astype(np.float32).astype(np.float64)
+    S = L + np.tril(L, -1).T
+    lda = n + pad
+    lda += (-lda) % 4                            # 16-byte rows
+    stored = np.full((n, lda), np.nan, dtype=np.float32)
+    stored[:, :n] = np.where(np.tril(np.ones((n, n), dtype=bool)), S, np.nan)
+    x = rng.standard_normal(n).astype(np.float32)
+    At = torch.from_numpy(stored).to(device)
+    y = krylov.symv(At, torch.from_numpy(x).to(device), n=n)
+    torch.cuda.synchronize()
+    assert y.dtype == torch.float32
+    xd = x.astype(np.float64)
+    ref = oracle.matvec(S, xd)
+    bound = 2 * n * U32 * (np.abs(S) @ np.abs(xd)) + 1e-30
+    yh = y.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(yh))
+    assert np.all(np.abs(yh - ref) <= bound)
+
+
+def test_symv32_full_size_sampled_rows(device):
+    """n = 16384 (the binary32 inner product of the main CG system's size):
+    64 sampled rows within the binary32 bound; deterministic run to run."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n = 16384
+    print(f"symv32 n={n} (sampled rows)", flush=True)
+    g = torch.Generator(device=device).manual_seed(12)
+    G = torch.randn(n, n, generator=g, device=device, dtype=torch.float32)
+    A = G + G.T                                   # exactly symmetric in binary32
+    del G
+    x = torch.randn(n, generator=g, device=device, dtype=torch.float32)
+    y1 = krylov.symv(A, x)
+    y2 = krylov.symv(A, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    rows = np.sort(np.random.default_rng(13).choice(n, 64, replace=False))
+    Ah = A.double().cpu().numpy()
+    del A
+    xd = x.double().cpu().numpy()
+    ref = oracle.matvec_rows(Ah, rows, xd)
+    bound = 2 * n * U32 * (np.abs(Ah[rows]) @ np.abs(xd))
+    assert np.all(np.abs(y1.double().cpu().numpy()[rows] - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,kappa,seed", [(300, 1e2, 0), (1000, 1e4, 1), (2049, 1e4, 2),
+                                          (777, 1e6, 3)])
+def test_cg_symmetric_fp32_refinement(device, n, kappa, seed):
+    """Binary32 inner CG on the lower triangle of the binary32 copy, binary64
+    refinement: the backward error reached, the solution within the forward
+    bound of the binary64 oracle's, and the inner iteration count within a few
+    percent of the general binary32 product's (the same iteration in another
+    rounding order)."""
+    from paper_1511_07207_amd import krylov
+
+    print(f"cg symmetric fp32 IR n={n} kappa={kappa}", flush=True)
+    p = spd_problem(n, kappa, seed=seed, config_id=2)
+    A, b = _t(p.A, device), _t(p.b, device)
+    x, info = krylov.solve(A, b, method="cg", precision="fp32", tol=1e-12, symmetric=True,
+                           max_iter=10 * n)
+    _, gen = krylov.solve(A, b, method="cg", precision="fp32", tol=1e-12, max_iter=10 * n)
+    assert info["status"] == 0 and gen["status"] == 0, (info, gen)
+    x = x.cpu().numpy()
+    m = oracle.metrics(p.A, p.b, x)
+    assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+    xo, _ = oracle.cg(p.A, p.b, tol=1e-14, max_iter=20 * n)
+    assert np.linalg.norm(x - xo) <= max(1e-8, 100 * kappa * 1e-14) * np.linalg.norm(xo)
+    if info["precision_used"] == gen["precision_used"] == "fp32":
+        assert abs(info["outer_iters"] - gen["outer_iters"]) <= 1, (info, gen)
+        assert abs(info["iters"] - gen["iters"]) <= max(3, 0.05 * gen["iters"]), (info, gen)
