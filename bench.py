@@ -45,11 +45,11 @@ def _pct(xs, q):
 
 
 # The solvers time their A*v launches with HIP event pairs on their own
-# stream; each pair costs the stream a few microseconds, so only one polling
-# chunk in TIMING_EVERY is timed (the first chunk of a solve always is): the
-# launch averages come from a sample, the solve times carry almost none of
-# the events' cost.
-TIMING_EVERY = 8
+# stream; each pair costs the stream a few microseconds, so only one launch
+# in TIMING_EVERY is timed (the first of a solve always is): the launch
+# averages come from a sample, the solve times carry almost none of the
+# events' cost.
+TIMING_EVERY = 16
 
 # sources of the two CG products (general GEMV / symmetric lower-triangle product)
 _PRODUCT_SOURCES = {

@@ -126,8 +126,8 @@ typedef struct {
     int32_t nrhs;       /* right-hand sides solved together (CG only): 1, or up to
                            KS_MAX_NRHS for lockstep CG with A*P on the matrix
                            cores; precision KS_FP64 or KS_IR_FP32               */
-    int32_t timing_every; /* with KS_FLAG_TIMING: time the A*v launches of one
-                           polling chunk in every this many (0 or 1: all of
+    int32_t timing_every; /* with KS_FLAG_TIMING: time one A*v launch in every
+                           this many, counted over the solve (0 or 1: all of
                            them).  Each timed launch records two HIP events,
                            which cost the stream a few microseconds; sampling
                            keeps that out of a timed solve's wall time */

@@ -57,7 +57,9 @@ struct ks_solver {
     int tev_used = 0;
     double gemv_ms = 0.0;
     int gemv_calls = 0;
-    int tchunk = 0;  // polling chunks collected so far in this solve (timing sample)
+    std::vector<int> tpos;  // position in the polling chunk of each timed launch
+    int tchunk_pos = 0;     // launches in the current polling chunk so far
+    long long tcall = 0;    // launches so far in this solve (timing sample)
     double anorm_inf = 0.0;
     // multi-right-hand-side
     double *mr64 = nullptr;   // X, R, P, Q, Qpart (binary64)
@@ -91,21 +93,23 @@ int sync_state(ks_solver *s) {
     return KS_OK;
 }
 
-// Timing of A*v launches: an event pair around each launch of a timed
-// polling chunk (every chunk, or one in p.timing_every); after a sync only the
-// first `real` pairs of the chunk did work (the rest returned at once).
-bool chunk_timed(const ks_solver *s) {
-    return s->timing() && (s->p.timing_every <= 1 || s->tchunk % s->p.timing_every == 0);
-}
-
+// Timing of A*v launches: an event pair around every launch, or around one
+// in p.timing_every (counted over the solve); each pair keeps its launch's
+// position in the polling chunk, and after the sync only the pairs of the
+// chunk's first `real` launches count (the rest returned at once).
 int timing_pair(ks_solver *s, hipEvent_t *a, hipEvent_t *b) {
     *a = *b = nullptr;
-    if (!chunk_timed(s)) return KS_OK;
+    if (!s->timing()) return KS_OK;
+    const int pos = s->tchunk_pos++;
+    const long long call = s->tcall++;
+    if (s->p.timing_every > 1 && call % s->p.timing_every != 0) return KS_OK;
     while ((int)s->tev.size() < 2 * (s->tev_used + 1)) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         s->tev.push_back(e);
     }
+    if ((int)s->tpos.size() < s->tev_used + 1) s->tpos.resize(s->tev_used + 1);
+    s->tpos[s->tev_used] = pos;
     *a = s->tev[2 * s->tev_used];
     *b = s->tev[2 * s->tev_used + 1];
     s->tev_used++;
@@ -114,15 +118,15 @@ int timing_pair(ks_solver *s, hipEvent_t *a, hipEvent_t *b) {
 
 int timed_collect(ks_solver *s, int real) {
     if (!s->timing()) return KS_OK;
-    s->tchunk++;
-    real = std::min(real, s->tev_used);
-    for (int i = 0; i < real; ++i) {
+    for (int i = 0; i < s->tev_used; ++i) {
+        if (s->tpos[i] >= real) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, s->tev[2 * i], s->tev[2 * i + 1]));
         s->gemv_ms += ms;
         s->gemv_calls++;
     }
     s->tev_used = 0;
+    s->tchunk_pos = 0;
     return KS_OK;
 }
 
@@ -1260,7 +1264,8 @@ int ks_solve(ks_solver *s, const double *d_b, double *d_x, ks_info *info) {
     info->precision_used = s->p.precision;
     s->gemv_ms = 0.0;
     s->gemv_calls = 0;
-    s->tchunk = 0;
+    s->tcall = 0;
+    s->tchunk_pos = 0;
     s->tev_used = 0;
     HIPCHK(hipEventRecord(s->ev0, s->stream));
     Outcome o;
