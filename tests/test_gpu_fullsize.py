@@ -87,13 +87,21 @@ def test_c3_mixed_precision_full_size(device):
     x, info = krylov.solve(p.A, p.b, method="cg", precision="fp32", tol=1e-12, max_iter=4 * n)
     assert info["status"] == 0, info
     print(f"C3: iters {info['iters']} outer {info['outer_iters']} prec {info['precision_used']}", flush=True)
+    # the same refinement with the binary32 inner solves on the lower triangle
+    xs, infs = krylov.solve(p.A, p.b, method="cg", precision="fp32", tol=1e-12, max_iter=4 * n,
+                            symmetric=True)
+    assert infs["status"] == 0, infs
+    print(f"C3 symmetric: iters {infs['iters']} outer {infs['outer_iters']}", flush=True)
     A_host = p.A.cpu().numpy()
     del p.A
     torch.cuda.empty_cache()
-    m = oracle.metrics(A_host, p.b.cpu().numpy(), x.cpu().numpy())
-    print(f"C3: eta {m['eta_inf']:.3e}", flush=True)
-    assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
-    assert abs(info["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + np.sqrt(n) * U
+    bh = p.b.cpu().numpy()
+    for xv, inf in ((x, info), (xs, infs)):
+        m = oracle.metrics(A_host, bh, xv.cpu().numpy())
+        print(f"C3: eta {m['eta_inf']:.3e}", flush=True)
+        assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+        assert abs(inf["backward_err"] - m["eta_inf"]) <= 1e-3 * m["eta_inf"] + np.sqrt(n) * U
+    assert abs(infs["iters"] - info["iters"]) <= max(3, 0.05 * info["iters"])
 
 
 def test_c4_multi_rhs_full_size(device):
