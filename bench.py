@@ -165,7 +165,7 @@ def leg_c1(dev):
             "us_per_iteration": round(1e3 * statistics.median(lat) / its[-1], 2)}
 
 
-def leg_c3(dev, n, kappa):
+def leg_c3(dev, n, kappa, spd_form="qr"):
     """Mixed precision vs binary64 at equal accuracy (backward error 1e-12)."""
     import torch
 
@@ -176,7 +176,8 @@ def leg_c3(dev, n, kappa):
     cases = [("spd_cg", kappa, "cg"), ("nonsym_gmres50", 1e2, "gmres")]
     for name, kap, method in cases:
         if method == "cg":
-            prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
+            prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda",
+                               q_form=spd_form)
         else:
             prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
         res = {"kappa": kap}
@@ -695,7 +696,7 @@ def main():
             if name == "c1":
                 legs[name] = leg_c1(dev)
             elif name == "c3":
-                legs[name] = leg_c3(dev, args.n3, 1e4)
+                legs[name] = leg_c3(dev, args.n3, 1e4, args.spd_form)
             elif name == "c4":
                 legs[name] = leg_c4(dev, n)
             elif name == "c5":
