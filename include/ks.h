@@ -99,10 +99,13 @@ extern "C" {
                                    when ||r||_2 <= tol (||A||_inf ||x||_inf +
                                    ||b||_inf), confirmed on the true residual */
 #define KS_FLAG_SYMMETRIC 4 /* CG, nrhs = 1: the binary64 products of the Krylov
-                               loop read only the lower triangle of A (i >= j),
-                               half the bytes of the general product.  A must
-                               still hold the whole symmetric matrix: the true
-                               residual and ||A||_inf read both triangles */
+                               loop, and the binary32 products of KS_IR_FP32's
+                               inner solves, read only the lower triangle of A
+                               (i >= j; of its binary32 copy), half the bytes of
+                               the general product (KS_IR_BF16 inner solves keep
+                               the general one).  A must still hold the whole
+                               symmetric matrix: the true residual and
+                               ||A||_inf read both triangles */
 
 typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
