@@ -40,11 +40,14 @@
 // parts of its tile row and the column parts of its tile column in a fixed
 // order (deterministic, no atomics), and writes y.  In CG the tiles also leave
 // their shares of p'Ap, and the second kernel applies the iteration's update
-// instead of writing q, so an iteration is two launches and the p update.  The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A
-// read, i.e. 1.6% of the product's bytes at SY_T = 256.  The workspace writes
-// are what the tile size trades against: measured on MI355X at n = 16384,
-// storing them cost ~15 us of a 173 us product with 128-wide tiles and ~6 us
-// with 256-wide ones, whose finishing sum also reads half as much.
+// instead of writing q, so an iteration is two launches and the p update.
+// The workspace traffic is 2 x 2 x 8 bytes per SY_T elements of A read, i.e.
+// 1.6% of the product's bytes at SY_T = 256, yet the workspace writes are what
+// the tile size trades against: measured on MI355X at n = 16384, storing them
+// cost ~15 us of a 173 us product with 128-wide tiles and ~11 us of the 168 us
+// tile launch with 256-wide ones (156 us without the stores), whose finishing
+// sum also reads half as much; a block of two adjacent 256-wide tiles stores
+// a quarter less but ends the launch later (189 us).
 #include "ks_device.h"
 
 namespace ks {
