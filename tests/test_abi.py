@@ -159,6 +159,8 @@ def test_symmetric_flag_and_symv_on_host():
     assert sz.value == tiles * 2 * 256 * 8        # a row part and a column part per tile
     assert L.ks_symv_workspace_bytes(0, ctypes.byref(sz)) == N.KS_EINVAL
     assert L.ks_symv(10, 10, None, None, None, None, 0, None) == N.KS_EINVAL
+    assert L.ks_symv_f32(10, 12, None, None, None, None, 0, None) == N.KS_EINVAL
+    assert L.ks_symv_f32(-1, 12, None, None, None, None, 0, None) == N.KS_EINVAL
     p = N.KsParams()
     assert L.ks_params_init(ctypes.byref(p), 16384, N.KS_CG) == 0
     base = ctypes.c_size_t(0)
