@@ -263,3 +263,26 @@ def test_stop_on_backward_error(device, method):
         # with a relative residual looser than tol; GMRES knows ||x||_inf only
         # from its last true residual (0 in the first cycle), so it may stop later
         assert m["rel_res"] > 1e-12
+
+
+def test_gmres_maximum_restart(device):
+    """GMRES(m) at the largest restart length the library takes (KS_MAX_RESTART
+    = 128) on a system that fills the basis and restarts: the Gram-Schmidt
+    passes reduce up to 129 coefficients, the Givens step rotates a column of
+    129.  Same bars as the other GMRES parity tests."""
+    from paper_1511_07207_amd import krylov
+
+    n, m = 600, 128
+    p = nonsym_swept_problem(n, 1e4, seed=9, config_id=1)
+    xo, io = oracle.gmres(p.A, p.b, tol=1e-10, restart=m, max_iter=20 * n)
+    assert io["status"] == 0 and io["cycles"] >= 2, io
+    x, info = krylov.solve(_t(p.A, device), _t(p.b, device), method="gmres", tol=1e-10,
+                           restart=m, max_iter=20 * n)
+    assert info["status"] == 0, info
+    x = x.cpu().numpy()
+    assert oracle.metrics(p.A, p.b, x)["rel_res"] <= 1e-10
+    assert _rel(x, xo) <= 1e-6
+    assert _iters_close(info["iters"], io["iters"], n), (info["iters"], io["iters"])
+    # one more than the largest is refused
+    with pytest.raises(Exception):
+        krylov.solve(_t(p.A, device), _t(p.b, device), method="gmres", restart=m + 1)
