@@ -218,6 +218,11 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
     }
     const int io = min(row0 + (t & (FZ_ROWS - 1)), n - 1);  // own row of threads t < FZ_ROWS
     const double xo = x[io], po = pc[io], qo = qc[io], ro = rc[io];
+    // this launch's slot was written by the launch before (this one writes
+    // the other), so it is read with the other loads, not after the barrier
+    const double rho = st->fz_rho[cur];
+    const int iters = st->fz_iters[cur] + 1;
+    const int flags = st->fz_flags[cur];
     double av[FZ_ROWS][FZ_SM_CH][2];
 #pragma unroll
     for (int r = 0; r < FZ_ROWS; ++r) {
@@ -237,9 +242,6 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
     __syncthreads();
     // the stop test comes after the barrier so that no load above is deferred
     // behind it; a launch after the stop only copies its slot forward
-    const double rho = st->fz_rho[cur];
-    const int iters = st->fz_iters[cur] + 1;
-    const int flags = st->fz_flags[cur];
     if (flags & F_STOP) {
         if (lead) {
             st->fz_rho[nxt] = rho;
