@@ -186,6 +186,21 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_kernel(int n, int64_t lda, cons
 // 2t + 512, 2t + 513 -- those rows_dot gives it, in the same order (at
 // n <= 1024 there are at most two 512-column chunks, the last possibly
 // ragged).
+// block_sum's sum handed to every thread: the same wave sums added in the
+// same order, each thread adding them itself after the one barrier instead
+// of thread 0 adding them and broadcasting through a second barrier.
+// smem: FZ_NT / 64 entries, not reused by a later sum of the same launch.
+__device__ __forceinline__ double fz_sum_all(double v, double *smem) {
+    constexpr int NW = FZ_NT / WAVE;
+    v = wave_sum(v);
+    if ((threadIdx.x & (WAVE - 1)) == 0) smem[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += smem[i];
+    return s;
+}
+
 constexpr int FZ_SMALL_N = 1024;
 constexpr int FZ_SM_ELEM = FZ_SMALL_N / FZ_NT;       // vector elements per thread (4)
 constexpr int FZ_SM_CH = FZ_SMALL_N / (2 * FZ_NT);   // 512-column chunks (2)
@@ -198,8 +213,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
     double *__restrict__ pn, const double *__restrict__ qc, double *__restrict__ qn, State *st,
     const double *__restrict__ pgc, double *__restrict__ pgn, int cur, int max_iter) {
     __shared__ double pnew[FZ_SMALL_N];
-    __shared__ double sm[FZ_NT / WAVE];
-    __shared__ double bc;
+    __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
     const int nxt = 1 - cur;
     const int t = threadIdx.x;
     const bool lead = blockIdx.x == 0 && t == 0;
@@ -223,6 +237,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
     const double rho = st->fz_rho[cur];
     const int iters = st->fz_iters[cur] + 1;
     const int flags = st->fz_flags[cur];
+    const double thresh = st->thresh;  // fixed for the solve
     double av[FZ_ROWS][FZ_SM_CH][2];
 #pragma unroll
     for (int r = 0; r < FZ_ROWS; ++r) {
@@ -237,9 +252,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
     double sg = 0.0;
     if (t < ngemv) sg += pg0;
     if (t + FZ_NT < ngemv) sg += pg1;
-    sg = block_sum<FZ_NT>(sg, sm);
-    if (t == 0) bc = sg;
-    __syncthreads();
+    const double sigma = fz_sum_all(sg, sm_sigma);
     // the stop test comes after the barrier so that no load above is deferred
     // behind it; a launch after the stop only copies its slot forward
     if (flags & F_STOP) {
@@ -250,7 +263,6 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         }
         return;
     }
-    const double sigma = bc;
     if (!(finite_d(sigma) && sigma > 0.0)) {
         if (lead) {
             st->fz_rho[nxt] = rho;
@@ -273,16 +285,13 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         x[io] = fma(a, po, xo);
         rn[io] = fma(-a, qo, ro);
     }
-    s2 = block_sum<FZ_NT>(s2, sm);
-    __syncthreads();  // every thread has read bc
-    if (t == 0) bc = s2;
-    __syncthreads();
-    // the sum over the single partial returns it unchanged (r'r >= 0)
-    const double rho_new = bc;
+    // the unfused path sums this block sum as its single partial, which
+    // returns it unchanged (r'r >= 0)
+    const double rho_new = fz_sum_all(s2, sm_rho);
     int stop = 0;
     if (!finite_d(rho_new))
         stop = F_NONFIN | F_STOP;
-    else if (sqrt(rho_new) <= st->thresh)
+    else if (sqrt(rho_new) <= thresh)
         stop = F_CONV | F_STOP;
     else if (iters >= max_iter)
         stop = F_MAXIT | F_STOP;
