@@ -115,16 +115,21 @@ __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, 
         rv[e] = r[i];
         pv[e] = p[i];
     }
+    // the scalars this launch does not change, read with the vectors
+    // rather than after the reduction's barriers
+    const double eta_tol = st->eta_tol, thresh = st->thresh, rho_prev = st->rho_prev;
+    const double anorm_inf = st->anorm_inf, binf = st->binf;
+    const int iters = st->iters;
     const double rho_new = reduce_partials_all<VEC_NT>(prho, nrho, 1);
     if (st->flags & F_STOP) return;
-    const double xinf = st->eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + nrho, nrho, 1) : 0.0;
-    const double rho_prev = st->rho_prev;
+    const double xinf = eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + nrho, nrho, 1) : 0.0;
+    const double threshold = eta_tol > 0.0 ? eta_tol * (anorm_inf * xinf + binf) : thresh;
     int stop = 0;
     if (!finite_d(rho_new))
         stop = F_NONFIN | F_STOP;
-    else if (sqrt(rho_new) <= stop_threshold(st, xinf))
+    else if (sqrt(rho_new) <= threshold)
         stop = F_CONV | F_STOP;
-    else if (st->iters >= max_iter)
+    else if (iters >= max_iter)
         stop = F_MAXIT | F_STOP;
     const double beta = rho_new / rho_prev;
     if (bid == 0 && threadIdx.x == 0) {
