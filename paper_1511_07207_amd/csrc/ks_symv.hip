@@ -401,6 +401,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     }
     double sg = 0.0;
     for (int i = threadIdx.x; i < ntiles; i += SY_FWAVES * WAVE) sg += sig[i];
+    const double rho = st->rho;  // written by the launch before, read with the vectors
     // block 0 of this very launch may set F_STOP (breakdown) while other blocks
     // start: the whole block takes one decision, so no wave leaves before a
     // barrier that the others reach (a launch that sees the new flag would
@@ -413,7 +414,6 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     double sigma = 0.0;
 #pragma unroll
     for (int k = 0; k < SY_FWAVES; ++k) sigma += sm[k];
-    const double rho = st->rho;
     const bool ok = finite_d(sigma) && sigma > 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iters += 1;

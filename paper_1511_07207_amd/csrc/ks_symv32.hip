@@ -265,6 +265,7 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
     }
     double sgv = 0.0;
     for (int i = threadIdx.x; i < ntiles; i += S3_FWAVES * WAVE) sgv += sig[i];
+    const double rho = st->rho;  // written by the launch before, read with the vectors
     // block 0 of this launch may set F_STOP (breakdown) while other blocks
     // start: one decision per block, so no wave leaves before a barrier
     if (__syncthreads_or((st->flags & F_STOP) != 0)) return;
@@ -275,7 +276,6 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
     double sigma = 0.0;
 #pragma unroll
     for (int k = 0; k < S3_FWAVES; ++k) sigma += sm[k];
-    const double rho = st->rho;
     const bool ok = finite_d(sigma) && sigma > 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iters += 1;

@@ -60,9 +60,9 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
         pv[e] = p[i];
         qv[e] = q[i];
     }
+    const double rho = st->rho;  // written by the launch before, read with the vectors
     const double sigma = reduce_partials_all<VEC_NT>(psigma, nsigma, 1);
     if (st->flags & F_STOP) return;
-    const double rho = st->rho;
     const bool ok = finite_d(sigma) && sigma > 0.0;
     if (bid == 0 && threadIdx.x == 0) {
         st->iters += 1;
