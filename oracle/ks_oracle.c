@@ -233,18 +233,25 @@ done_noalloc:
 
 /* ---------------------------------------------------------------- BiCGSTAB
  *
- * BiConjugate gradient stabilised, in the order of the paper's BiCGSTAB
- * listing (r0 the shadow residual, rho_0 = alpha = omega = 1, p = v = 0):
- *   beta = (rho_k / rho_{k-1}) (alpha / omega);  p = r + beta (p - omega v)
- *   v = A p;  alpha = rho_k / (r0' v);  s = r - alpha v
- *   t = A s;  omega = (t' s) / (t' t);  x = x + alpha p + omega s
- * The printed omega line shows a product where the quotient is meant, and the
- * listing stops before the last two updates, taken here as r = s - omega t and
- * rho_{k+1} = r0' r.  If ||s|| already meets the tolerance the half step
- * x = x + alpha p ends the solve.  Stop on ||r||_2 <= tol ||b||_2 (recursive),
- * confirmed on the true residual (restart from x if it fails).  max_iter
- * bounds the number of products with A (two per iteration).  Breakdown: rho,
- * r0'v or t't equal to 0, or omega = 0.
+ * BiConjugate gradient stabilised (Krylov section, BiCGSTAB paragraph).  The
+ * residual after k steps is r_k = psi_k(A) phi_k(A) r0, where phi_k is the
+ * residual polynomial of BiCG (degree k, phi_k(0) = 1, phi_k(A) r0 orthogonal
+ * to the shadow space spanned by r0h, A' r0h, ..., here with r0h = r0) and
+ * psi_k(t) = (1 - omega_1 t) ... (1 - omega_k t) a product of local
+ * minimal-residual factors.  The short recurrences that carry this, with
+ * rho = r0h' r and p the BiCG direction multiplied by psi:
+ *   v = A p;  alpha = rho / (r0h' v);  s = r - alpha v       (the BiCG step)
+ *   t = A s;  omega = (t' s) / (t' t)                         (minimises ||s - omega t||)
+ *   x = x + alpha p + omega s;  r = s - omega t
+ *   rho' = r0h' r;  beta = (rho' / rho)(alpha / omega);  p = r + beta (p - omega v)
+ * starting from p = r = b - A x.  The paper's ω line reads as the quotient
+ * above (it prints a product), and it omits the r and rho updates, which are
+ * restored.  If ||s|| already meets the tolerance, or the product budget
+ * ends after v = A p, the half step x = x + alpha p ends the pass.  Stop on
+ * ||r||_2 <= tol ||b||_2 (recursive), confirmed on the true residual (a new
+ * pass from x, with r0h the new residual, if it fails).  max_iter bounds the
+ * number of products with A (two per step).  Breakdown: rho, r0h'v or t't
+ * equal to 0, or omega = 0.
  */
 int ko_bicgstab(int n, const double *A, long lda, const double *b, double *x, double tol,
                 int max_iter, int *iters_out, int *restarts_out, double *rel_res_out) {
@@ -265,10 +272,10 @@ int ko_bicgstab(int n, const double *A, long lda, const double *b, double *x, do
         return KO_OK;
     }
     size_t nn = (size_t)n;
-    double *r = (double *)malloc(sizeof(double) * nn), *r0 = (double *)malloc(sizeof(double) * nn);
+    double *r = (double *)malloc(sizeof(double) * nn), *r0h = (double *)malloc(sizeof(double) * nn);
     double *p = (double *)malloc(sizeof(double) * nn), *v = (double *)malloc(sizeof(double) * nn);
     double *sv = (double *)malloc(sizeof(double) * nn), *t = (double *)malloc(sizeof(double) * nn);
-    if (!r || !r0 || !p || !v || !sv || !t) {
+    if (!r || !r0h || !p || !v || !sv || !t) {
         status = KO_EINVAL;
         goto out;
     }
@@ -283,41 +290,39 @@ int ko_bicgstab(int n, const double *A, long lda, const double *b, double *x, do
             ++restarts;
         }
         first = 0;
-        for (int i = 0; i < n; ++i) { r0[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
-        double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
-        double rho = ko_dot(n, r0, r);
+        for (int i = 0; i < n; ++i) { r0h[i] = r[i]; p[i] = r[i]; }
+        double rho = ko_dot(n, r0h, r);
         int stop = 0;
         while (!stop) {
             if (rho == 0.0 || !isfinite(rho)) { status = isfinite(rho) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
-            double beta = (rho / rho_prev) * (alpha / omega);
-            for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            /* BiCG step */
             ko_matvec(n, A, lda, p, v);
             ++prods;
-            double r0v = ko_dot(n, r0, v);
+            double r0v = ko_dot(n, r0h, v);
             if (r0v == 0.0 || !isfinite(r0v)) { status = isfinite(r0v) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
-            alpha = rho / r0v;
+            double alpha = rho / r0v;
             for (int i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
-            if (ko_nrm2(n, sv) <= tol * bnorm) {          /* half-step exit */
+            if (ko_nrm2(n, sv) <= tol * bnorm || prods >= max_iter) {
+                /* half step: s already small enough, or no product left for A s */
                 for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
                 stop = 1;
                 break;
             }
-            if (prods >= max_iter) {                        /* no room for A s */
-                for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
-                stop = 1;
-                break;
-            }
+            /* minimal-residual step along t = A s */
             ko_matvec(n, A, lda, sv, t);
             ++prods;
             double tt = ko_dot(n, t, t);
             if (tt == 0.0 || !isfinite(tt)) { status = isfinite(tt) ? KO_BREAKDOWN : KO_NONFINITE; stop = 2; break; }
-            omega = ko_dot(n, t, sv) / tt;
+            double omega = ko_dot(n, t, sv) / tt;
             for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i] + omega * sv[i];
             for (int i = 0; i < n; ++i) r[i] = sv[i] - omega * t[i];
             if (ko_nrm2(n, r) <= tol * bnorm || prods >= max_iter) { stop = 1; break; }
             if (omega == 0.0) { status = KO_BREAKDOWN; stop = 2; break; }
-            rho_prev = rho;
-            rho = ko_dot(n, r0, r);
+            /* next direction */
+            double rho_new = ko_dot(n, r0h, r);
+            double beta = (rho_new / rho) * (alpha / omega);
+            for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            rho = rho_new;
         }
         if (stop == 2) {
             ko_residual(n, A, lda, b, x, r);
@@ -326,7 +331,7 @@ int ko_bicgstab(int n, const double *A, long lda, const double *b, double *x, do
         }
     }
 out:
-    free(r); free(r0); free(p); free(v); free(sv); free(t);
+    free(r); free(r0h); free(p); free(v); free(sv); free(t);
     if (iters_out) *iters_out = prods;
     if (restarts_out) *restarts_out = restarts;
     if (rel_res_out) *rel_res_out = res / bnorm;
@@ -674,15 +679,20 @@ int ko_lu_solve(int n, const double *LU, long lda, const int *piv, const double 
 
 /* ------------------------------------------- binary32 block LU, GMRES-IR
  *
- * The paper's block LU (direct-methods section, Figure 1, equations (1)-(4)
- * and its block algorithm), in binary32 arithmetic on the binary32 rounding
- * of A: for each column block of width b, the panel is factored column by
- * column with partial pivoting (the first row of largest magnitude, whole
- * rows interchanged), the panel's unit lower triangle solves for the block
- * row of U to its right, and the trailing matrix takes the delayed rank-b
- * update.  b >= n is the unblocked right-looking algorithm.  L (unit, below
- * the diagonal) and U overwrite LU; piv[k] is the row swapped with row k at
- * step k.  Returns 0, or 1 + the first column whose pivot is zero.
+ * Block LU with partial pivoting (direct-methods section, Figure 1 and
+ * equations (1)-(4)), in binary32 arithmetic on the binary32 rounding of A.
+ * With the leading b columns split off, P A = L U reads
+ *   [A11 A12]   [L11  0] [U11 U12]
+ *   [A21 A22] = [L21  I] [ 0   S ]
+ * so (i) the panel [A11; A21] is factored column by column (the unblocked
+ * right-looking elimination, pivot = the first row of largest magnitude in
+ * the column, whole rows interchanged) into L11, L21 and U11; (ii) U12 solves
+ * L11 U12 = A12 (unit lower triangle); (iii) S = A22 - L21 U12 is the delayed
+ * rank-b update; and the same is repeated on S.  b >= n is the unblocked
+ * algorithm.  L (unit, below the diagonal) and U overwrite LU; piv[k] is the
+ * row swapped with row k at step k.  Returns 0, or 1 + the first column
+ * whose pivot is zero (that column is left as it is and the factorization
+ * goes on).
  *
  * The factors then precondition GMRES inside binary64 iterative refinement
  * (GMRES-IR): r = b - A x in binary64; the correction solves
@@ -699,6 +709,7 @@ int ko_lu32_block(int n, const double *A, long lda, float *LU, long ldl, int *pi
     int sing = 0;
     for (int kb = 0; kb < n; kb += b) {
         const int bf = kb + b < n ? kb + b : n; /* the panel's columns kb .. bf-1 */
+        /* (i) the panel, column by column: pivot, interchange, multipliers */
         for (int i = kb; i < bf; ++i) {
             int p = i;
             float best = fabsf(F(i, i));
@@ -718,14 +729,14 @@ int ko_lu32_block(int n, const double *A, long lda, float *LU, long ldl, int *pi
                 for (int j = i + 1; j < bf; ++j) F(r, j) = F(r, j) - l * F(i, j);
             }
         }
-        /* the block row of U: unit lower panel triangle \ A(kb:bf, bf:n) */
+        /* (ii) the block row of U: L11 U12 = A12 */
         for (int c = bf; c < n; ++c)
             for (int i = kb; i < bf; ++i) {
                 float s = F(i, c);
                 for (int j = kb; j < i; ++j) s = s - F(i, j) * F(j, c);
                 F(i, c) = s;
             }
-        /* delayed rank-(bf - kb) update of the trailing matrix */
+        /* (iii) S = A22 - L21 U12, the delayed rank-(bf - kb) update */
         for (int r = bf; r < n; ++r)
             for (int c = bf; c < n; ++c) {
                 float s = F(r, c);

@@ -415,6 +415,89 @@ def test_bicgstab_first_iterate_from_its_two_defining_conditions():
         assert _rel(x, x1) <= 1e-13
 
 
+def _fr_poly_apply(A, coeffs, v):
+    """sum_i coeffs[i] A^i v, exactly."""
+    out = [Fraction(0)] * len(v)
+    w = list(v)
+    for c in coeffs:
+        out = [o + c * wi for o, wi in zip(out, w)]
+        w = _fr_matvec(A, w)
+    return out
+
+
+def _fr_poly_mul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def exact_bicgstab_iterate(A, b, k):
+    """The k-th BiCGSTAB iterate from x0 = 0 (shadow residual r0 = b), built from
+    the two objects that define it rather than from its recurrence:
+      phi_k, the BiCG residual polynomial: degree k, phi_k(0) = 1 and
+        phi_k(A) r0 orthogonal to r0, A' r0, ..., (A')^(k-1) r0
+        (the Petrov-Galerkin conditions r0' A^j phi_k(A) r0 = 0, j < k);
+      psi_k(t) = prod_j (1 - omega_j t), where omega_j minimises the 2-norm of
+        (1 - omega A) s_j, s_j = psi_(j-1)(A) phi_j(A) r0.
+    The residual is r_k = psi_k(A) phi_k(A) r0.  Since 1 - psi_k phi_k vanishes
+    at 0, it equals t q(t) and x_k = q(A) r0 without any solve with A."""
+    Af = [[Fraction(int(a)) for a in row] for row in A]
+    r0 = _fr_vec(b)
+    K = _fr_krylov(Af, r0, 2 * k + 1)          # r0, A r0, ..., A^(2k) r0
+    mom = [_fr_dot(r0, K[i]) for i in range(2 * k + 1)]  # r0' A^i r0
+    psi = [Fraction(1)]
+    for j in range(1, k + 1):
+        # phi_j = 1 + c_1 t + ... + c_j t^j from its j orthogonality conditions
+        M = [[mom[i + m] for m in range(1, j + 1)] for i in range(j)]
+        c = _fr_solve(M, [-mom[i] for i in range(j)])
+        phi = [Fraction(1)] + c
+        s = _fr_poly_apply(Af, _fr_poly_mul(psi, phi), r0)
+        As = _fr_matvec(Af, s)
+        omega = _fr_dot(As, s) / _fr_dot(As, As)
+        psi = _fr_poly_mul(psi, [Fraction(1), -omega])
+    P = _fr_poly_mul(psi, phi)                  # residual polynomial, P(0) = 1
+    q = [-c for c in P[1:]]                      # 1 - P(t) = t q(t)
+    x = _fr_poly_apply(Af, q, r0)
+    return np.array([float(v) for v in x])
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_bicgstab_later_iterates_from_polynomial_conditions(k):
+    # Iterates past the first fix the recurrence's beta and rho: a beta
+    # without its alpha / omega factor, or rho taken as r'r instead of r0'r,
+    # changes phi_k and so x_k.
+    for seed, n in [(1, 5), (2, 6), (5, 7)]:
+        A = _int_nonsym(n, seed)
+        b = np.random.default_rng(seed + 40).integers(-5, 6, size=n)
+        xk = exact_bicgstab_iterate(A, b, k)
+        x, info = oracle.bicgstab(A.astype(float), b.astype(float), tol=TINY, max_iter=2 * k)
+        assert info["iters"] == 2 * k
+        assert _rel(x, xk) <= 1e-12
+
+
+def test_bicgstab_exact_iterate_construction_matches_first_step():
+    # the polynomial construction at k = 1 is the first iterate's two conditions
+    A = _int_nonsym(5, 9)
+    b = np.random.default_rng(49).integers(-5, 6, size=5)
+    x, _ = oracle.bicgstab(A.astype(float), b.astype(float), tol=TINY, max_iter=2)
+    assert _rel(x, exact_bicgstab_iterate(A, b, 1)) <= 1e-13
+
+
+def test_bicgstab_terminates_within_n_iterations():
+    # In exact arithmetic phi_n(A) r0 = 0 (n conditions on a degree-n
+    # polynomial with phi(0) = 1), so without breakdown the residual vanishes
+    # after at most n iterations, 2n products.
+    for seed in range(20):
+        n = 6
+        rng = np.random.default_rng(seed + 300)
+        A = np.diag(rng.uniform(2.0, 4.0, n)) + rng.standard_normal((n, n)) / np.sqrt(n)
+        b = rng.standard_normal(n)
+        _, info = oracle.bicgstab(A, b, tol=1e-10, max_iter=2 * n)
+        assert info["status"] == 0 and info["rel_res"] <= 1e-10 and info["iters"] <= 2 * n
+
+
 def test_bicgstab_identity_half_step():
     b = np.random.default_rng(1).standard_normal(20)
     x, info = oracle.bicgstab(np.eye(20), b, tol=1e-12)
