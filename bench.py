@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the dense Krylov solvers on one MI355X.
 
-One step = one pass of the binary64 hot path over one batch of synthetic
-input: a CG solve of the SPD system (n = 16384, cond_2 = 1e4) and a GMRES(30)
-solve of the nonsymmetric system A = D + G/sqrt(n) (n = 16384), both from
-x0 = 0 to relative residual 1e-10.  The matrices and right-hand sides are
-generated on the device before timing (seeded; see workloads/gen.py) and the
-solvers are created (A borrowed in place, ||A||_inf computed) before timing.
+One step = one pass of the mixed-precision refinement path over the
+refinement workload at n = 32768, cond = 1e4 (seeded, synthetic; see
+workloads/gen.py):
+  * SPD A = Q diag(lambda) Q^T, lambda log-uniform on [1, 1e4]: CG inner
+    solves on the binary32 copy of A, reading its lower triangle;
+  * nonsymmetric A = diag(lambda) + 0.25 G / sqrt(n), lambda log-uniform on
+    [1, 1e4]: GMRES(50) inner solves on the bfloat16 copy of A;
+with the residual, the update and GMRES's Givens rotations in binary64, from
+x0 = 0 to normwise backward error eta_inf <= 1e-12.  The matrices and
+right-hand sides are generated on the device and the solvers created (copies
+made, ||A||_inf computed) before timing; `value` = solves/s over the timed
+steps.  Beside it, the same two systems solved in binary64 (CG on the lower
+triangle, GMRES(50)) stopping on the same backward error.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 32768]
 
-Prints one JSON line (metric, value = solves/s, ...) with
-  roofline:      the FP64 GEMV of the CG loop (the dominant kernel):
-                 algorithmic bytes per launch / mean launch time measured with
-                 HIP events on the library's stream during the timed steps;
-  cpu_baseline:  the CPU oracle timed on a bounded sample of the same
-                 systems (a few hundred iterations), scaled to the
-                 iteration counts of a full step.
+Prints one JSON line (metric, value = mixed solves/s, ...) with
+  roofline:      the product that takes most of a step's time: algorithmic
+                 bytes per launch / mean launch time from HIP events on the
+                 library's stream during the timed steps;
+  cpu_baseline:  the binary64 CPU oracle on a bounded sample of the same two
+                 systems (products of CG and GMRES(50)), scaled to the
+                 iterations a binary64 solve to the same backward error takes.
 """
 from __future__ import annotations
 
@@ -51,12 +58,25 @@ def _pct(xs, q):
 # events' cost.
 TIMING_EVERY = 16
 
-# sources of the two CG products (general GEMV / symmetric lower-triangle product)
+# sources of the timed products, and the committed counter summaries of each
 _PRODUCT_SOURCES = {
     "general": ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"),
     "symmetric": ("ks_symv.hip", "ks_device.h", "ks_internal.h"),
+    "symmetric32": ("ks_symv32.hip", "ks_device.h", "ks_internal.h"),
+    "gmres_bf16": ("ks_gemv_body.h", "ks_gemv.hip", "ks_device.h", "ks_internal.h"),
 }
-_PRODUCT_PROFILE = {"general": "cg_matvec_f64_n{n}_pmc.txt", "symmetric": "symv_f64_n{n}_pmc.txt"}
+_PRODUCT_PROFILE = {"general": "cg_matvec_f64_n{n}_pmc.txt", "symmetric": "symv_f64_n{n}_pmc.txt",
+                    "symmetric32": "symv32_f32_n{n}_pmc.txt",
+                    "gmres_bf16": "gm_matvec_bf16_n{n}_pmc.txt"}
+_PRODUCT_KERNEL = {
+    "general": "cg_matvec_kernel<double> (q = A p, p'q partials)",
+    "symmetric": ("symv_tile_kernel + symv_cg_finish_kernel (q = A p from the lower triangle, "
+                  "fused with x += alpha p, r -= alpha q)"),
+    "symmetric32": ("symv32_tile_kernel + symv32_cg_finish_kernel (binary32 q = A p from the lower "
+                    "triangle of the binary32 copy, fused with the inner CG's x, r update)"),
+    "gmres_bf16": ("gm_matvec_kernel<bf16> (w = A v_k on the bfloat16 copy, binary32 "
+                   "accumulation, ||w||^2 partials)"),
+}
 
 
 def kernel_source_hash(product: str = "general") -> str:
@@ -70,13 +90,22 @@ def kernel_source_hash(product: str = "general") -> str:
 
 
 def product_bytes(n: int, product: str) -> float:
-    """Algorithmic bytes of one timed CG product.  General: A once, p once, q
-    once.  Symmetric: the lower triangle once and p once; its finishing launch
-    also applies the iteration's update (x and r read and written, q never
-    stored), which the same timed pair covers."""
+    """Algorithmic bytes of one timed product launch.
+    general (binary64): A once, p in, q out.
+    symmetric (binary64): the lower triangle once and p once; its finishing
+      launch also applies the iteration's update (x and r read and written,
+      q never stored), which the same timed pair covers.
+    symmetric32: the same in binary32.
+    gmres_bf16: the bfloat16 A once, v_k in and w out in binary32."""
     if product == "general":
         return 8.0 * n * n + 2 * 8.0 * n
-    return 8.0 * n * (n + 1) / 2 + 5 * 8.0 * n
+    if product == "symmetric":
+        return 8.0 * n * (n + 1) / 2 + 5 * 8.0 * n
+    if product == "symmetric32":
+        return 4.0 * n * (n + 1) / 2 + 5 * 4.0 * n
+    if product == "gmres_bf16":
+        return 2.0 * n * n + 2 * 4.0 * n
+    raise ValueError(product)
 
 
 def load_traffic(n: int, product: str = "general"):
@@ -95,10 +124,10 @@ def load_traffic(n: int, product: str = "general"):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(spd, ns, cg_iters, gm_iters, steps_done):
-    """Time the oracle on a bounded sample and scale to one step's iterations."""
-    import numpy as np
-
+def cpu_baseline(spd, ns, cg_iters, gm_iters):
+    """Time the oracle on a bounded sample of the step's two systems (CG and
+    GMRES(50) products in binary64), at all host threads and at one, and
+    scale to the products of a binary64 solve to the same backward error."""
     import oracle
 
     A1 = spd.A.cpu().numpy()
@@ -106,26 +135,36 @@ def cpu_baseline(spd, ns, cg_iters, gm_iters, steps_done):
     A2 = ns.A.cpu().numpy()
     b2 = ns.b.cpu().numpy()
     threads = oracle.get_threads()
-    # about 10 s of oracle work on a 16-core host: a whole GMRES solve and up
-    # to 1000 CG iterations
-    s_cg = max(1, min(cg_iters, 1000))
-    s_gm = max(1, gm_iters)
-    t = time.perf_counter()
-    _, i1 = oracle.cg(A1, b1, tol=1e-300, max_iter=s_cg)
-    t_cg = time.perf_counter() - t
-    t = time.perf_counter()
-    _, i2 = oracle.gmres(A2, b2, tol=1e-300, max_iter=s_gm, restart=30)
-    t_gm = time.perf_counter() - t
-    est_step = t_cg * cg_iters / i1["iters"] + t_gm * gm_iters / i2["iters"]
+    res = {}
+    for label, th, k in (("all_threads", threads, 12), ("one_thread", 1, 2)):
+        oracle.set_threads(th)
+        t = time.perf_counter()
+        _, i1 = oracle.cg(A1, b1, tol=1e-300, max_iter=k)
+        t_cg = time.perf_counter() - t
+        t = time.perf_counter()
+        _, i2 = oracle.gmres(A2, b2, tol=1e-300, max_iter=k, restart=50)
+        t_gm = time.perf_counter() - t
+        est = t_cg * cg_iters / i1["iters"] + t_gm * gm_iters / i2["iters"]
+        res[label] = {"threads": th, "cg_products": i1["iters"], "cg_s": round(t_cg, 2),
+                      "gmres_products": i2["iters"], "gmres_s": round(t_gm, 2),
+                      "est_step_s": round(est, 2), "solves_per_s": 2.0 / est}
+    oracle.set_threads(threads)
+    allt = res["all_threads"]
     return {
-        "value": 2.0 / est_step,
+        "value": allt["solves_per_s"],
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"{i1['iters']} CG iterations ({t_cg:.1f} s) and {i2['iters']} GMRES(30) "
-                   f"steps ({t_gm:.1f} s) of the same n={spd.n} systems, scaled to one step "
-                   f"({cg_iters} CG + {gm_iters} GMRES iterations)"),
-        "est_step_s": est_step,
+        "sample": (f"{allt['cg_products']} CG and {allt['gmres_products']} GMRES(50) products of the "
+                   f"step's two n={spd.n} systems in binary64 ({allt['cg_s'] + allt['gmres_s']:.1f} s "
+                   f"on {threads} threads), scaled to the {cg_iters} + {gm_iters} products a binary64 "
+                   f"solve of each to eta_inf <= 1e-12 takes"),
+        "est_step_s": allt["est_step_s"],
+        "one_thread": {"value": res["one_thread"]["solves_per_s"], "cores": 1,
+                       "sample": (f"{res['one_thread']['cg_products']} CG and "
+                                  f"{res['one_thread']['gmres_products']} GMRES(50) products, "
+                                  f"same scaling"),
+                       "est_step_s": res["one_thread"]["est_step_s"]},
     }
 
 
@@ -165,58 +204,127 @@ def leg_c1(dev):
             "us_per_iteration": round(1e3 * statistics.median(lat) / its[-1], 2)}
 
 
-def leg_c3(dev, n, kappa, spd_form="qr"):
-    """Mixed precision vs binary64 at equal accuracy (backward error 1e-12)."""
+def _solve_timed(solver, b, x, reps_fast=3, fast_s=1.0):
+    """Solve once (warm-up); if that took under fast_s seconds, time reps_fast
+    more solves and report their median, else report the first."""
+    (_, info), dt = _timed(lambda: solver.solve(b, out=x.zero_()))
+    if dt >= fast_s:
+        return info, dt, 1
+    lat = []
+    for _ in range(reps_fast):
+        (_, info), d = _timed(lambda: solver.solve(b, out=x.zero_()))
+        lat.append(d)
+    return info, statistics.median(lat), reps_fast
+
+
+def leg_c3sweep(dev, n, spd_form="qr"):
+    """The refinement workload over its condition-number sweep (n = 32768,
+    kappa in 1e2, 1e4, 1e6; SPD with CG inner solves, nonsymmetric with
+    GMRES(50) inner solves): binary64 stopping on the backward error against
+    binary32 and bfloat16 inner solves, all to eta_inf <= 1e-12.  The
+    nonsymmetric kappa = 1e6 cell stalls (restarted GMRES(50) stops making
+    progress near eta_inf = 1e-8): it runs with a capped budget and is
+    reported with the status and backward error it reached."""
     import torch
 
     from paper_1511_07207_amd import krylov
     from workloads import nonsym_swept_problem, spd_problem
 
     out = {"n": n, "eta_target": 1e-12}
-    cases = [("spd_cg", kappa, "cg"), ("nonsym_gmres50", 1e2, "gmres")]
-    for name, kap, method in cases:
-        if method == "cg":
-            prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda",
-                               q_form=spd_form)
-        else:
-            prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
-        res = {"kappa": kap}
-        # SPD: also binary64 and binary32-refined solves on the lower triangle
-        # (the symmetric products: half the bytes per product)
-        precs = ("fp64", "fp32", "bf16") + (("fp64_sym", "fp32_sym") if method == "cg" else ())
-        for key in precs:
-            prec, sym = key.split("_")[0], key.endswith("_sym")
-            kw = dict(method=method, tol=1e-12, restart=50, timing=True, timing_every=TIMING_EVERY,
-                      max_iter=4 * n, symmetric=sym)
-            if prec == "fp64":
-                kw["stop_backward"] = True
+    for kind in ("spd_cg", "nonsym_gmres50"):
+        for kap in (1e2, 1e4, 1e6):
+            if kind == "spd_cg":
+                prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda",
+                                   q_form=spd_form)
+                keys = ("fp64_sym", "fp32_sym", "bf16")
             else:
-                kw["precision"] = prec
-            (solver), tc = _timed(lambda: krylov.Solver(prob.A, **kw))
+                prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch",
+                                            device="cuda")
+                keys = ("fp64", "fp32", "bf16")
+            stall = kind == "nonsym_gmres50" and kap >= 1e6
             x = torch.zeros(n, dtype=torch.float64, device=dev)
-            (_, info), dt = _timed(lambda: solver.solve(prob.b, out=x))
-            # bytes per element of the timed matrix-vector products (mixed if a
-            # bfloat16 solve fell back to binary32)
-            e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec] if info["precision_used"] == prec else None
-            r = {"solves_per_s": round(1.0 / dt, 4), "solve_ms": round(dt * 1e3, 2),
-                 "create_ms": round(tc * 1e3, 2), "status": info["status_name"],
-                 "iters": info["iters"], "outer": info["outer_iters"],
-                 "precision_used": info["precision_used"], "eta_inf": info["backward_err"],
-                 "rel_res": info["rel_res"]}
-            if e and info["gemv_calls"]:
-                # algorithmic bytes of A per product: all of it, or the lower triangle
-                ab = e * n * (n + 1) / 2 if sym else e * n * n
-                r["gemv_gbs"] = round(ab / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)
-            r["fwd_err_vs_x_true"] = float((x - prob.x_true).norm() / prob.x_true.norm())
-            res[key] = r
-            solver.close()
-            del x
-        f64 = res["fp64"]["solves_per_s"]
-        for key in precs[1:]:
-            res[key]["speedup_vs_fp64"] = round(res[key]["solves_per_s"] / f64, 3)
-        out[name] = res
-        del prob
-        torch.cuda.empty_cache()
+            res = {}
+            for key in keys:
+                prec, sym = key.split("_")[0], key.endswith("_sym")
+                kw = dict(method="cg" if kind == "spd_cg" else "gmres", tol=1e-12, restart=50,
+                          timing=True, timing_every=TIMING_EVERY, max_iter=4 * n, symmetric=sym)
+                if stall:
+                    kw.update(max_iter=2000 if prec == "fp64" else 800, max_outer=4)
+                if prec == "fp64":
+                    kw["stop_backward"] = True
+                else:
+                    kw["precision"] = prec
+                solver = krylov.Solver(prob.A, **kw)
+                info, dt, reps = _solve_timed(solver, prob.b, x)
+                r = {"status": info["status_name"], "solve_ms": round(dt * 1e3, 2),
+                     "solves_per_s": round(1.0 / dt, 4), "timed_solves": reps,
+                     "iters": info["iters"], "outer": info["outer_iters"],
+                     "precision_used": info["precision_used"], "eta_inf": info["backward_err"],
+                     "fwd_err_vs_x_true": float((x - prob.x_true).norm() / prob.x_true.norm())}
+                if info["gemv_calls"] and info["precision_used"] == prec:
+                    e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+                    ab = e * n * (n + 1) / 2 if sym else e * n * n
+                    r["gemv_gbs"] = round(ab / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)
+                res[key] = r
+                solver.close()
+            f64 = res[keys[0]]
+            for key in keys[1:]:
+                if f64["status"] == "ok" and res[key]["status"] == "ok":
+                    res[key]["speedup_vs_fp64"] = round(res[key]["solves_per_s"] / f64["solves_per_s"], 3)
+            out[f"{kind}_kappa_{kap:g}"] = res
+            print(f"[bench]   c3 sweep {kind} kappa={kap:g} done", file=sys.stderr, flush=True)
+            del prob, x
+            torch.cuda.empty_cache()
+    return out
+
+
+def leg_c2(dev, n, steps, spd_form="qr"):
+    """Plain binary64 solves on one GPU: CG on the SPD system (n = 16384,
+    cond 1e4, lower-triangle product) and GMRES(30) on D + G/sqrt(n), x0 = 0,
+    relative residual 1e-10; `steps` timed pairs after one warm-up, with the
+    roofline of the CG product (the symmetric tiles and the finishing sum that
+    also applies the x, r update)."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_problem, spd_problem
+
+    spd = spd_problem(n, 1e4, seed=0, config_id=1, backend="torch", device="cuda", q_form=spd_form)
+    ns = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True, timing_every=TIMING_EVERY,
+                       symmetric=True)
+    gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True,
+                       timing_every=TIMING_EVERY)
+    xcg = torch.zeros(n, dtype=torch.float64, device=dev)
+    xgm = torch.zeros(n, dtype=torch.float64, device=dev)
+    cg.solve(spd.b, out=xcg.zero_())
+    gm.solve(ns.b, out=xgm.zero_())
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        (_, icg), tc = _timed(lambda: cg.solve(spd.b, out=xcg.zero_()))
+        (_, igm), tg = _timed(lambda: gm.solve(ns.b, out=xgm.zero_()))
+        recs.append((icg, igm, tc * 1e3, tg * 1e3))
+    el = time.perf_counter() - t0
+    gemv_ms = sum(r[0]["gemv_ms"] for r in recs)
+    calls = sum(r[0]["gemv_calls"] for r in recs)
+    avg = gemv_ms / max(calls, 1)
+    pb = product_bytes(n, "symmetric")
+    out = {"n": n, "solves_per_s": round(2 * steps / el, 4), "steps": steps,
+           "ok": all(r[0]["status"] == 0 and r[1]["status"] == 0 for r in recs),
+           "cg": {"iters": recs[-1][0]["iters"], "rel_res": recs[-1][0]["rel_res"],
+                  "p50_ms": round(_pct([r[2] for r in recs], 0.5), 3)},
+           "gmres30": {"iters": recs[-1][1]["iters"], "rel_res": recs[-1][1]["rel_res"],
+                       "p50_ms": round(_pct([r[3] for r in recs], 0.5), 3)},
+           "symmetric_product": {"avg_launch_ms": round(avg, 5), "bytes_per_launch": pb,
+                                 "achieved_gbs": round(pb / (avg * 1e-3) / 1e9, 1),
+                                 "frac": round(pb / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "traffic": load_traffic(n, "symmetric")}}
+    cg.close()
+    gm.close()
+    del spd, ns
+    torch.cuda.empty_cache()
     return out
 
 
@@ -263,11 +371,9 @@ def leg_f1(dev, n):
 
 
 def leg_f3(dev, n):
-    """Jacobi and Gauss-Seidel on the nonsymmetric n = 16384 system of the main
-    step (D + G/sqrt(n), Jacobi spectral radius about 0.36), binary64 to
-    relative residual 1e-10, beside GMRES(30) on the same system; then the
-    four methods the paper times (Jacobi, Gauss-Seidel, GMRES(35), BiCGSTAB)
-    at its tolerance 1e-4 over its size range."""
+    """Jacobi and Gauss-Seidel on the nonsymmetric n = 16384 system of the
+    binary64 leg (D + G/sqrt(n), Jacobi spectral radius about 0.36), binary64
+    to relative residual 1e-10, beside GMRES(30) on the same system."""
     import torch
 
     from paper_1511_07207_amd import krylov
@@ -299,17 +405,6 @@ def leg_f3(dev, n):
                      ("gmres30", dict(method="gmres", restart=30, tol=1e-10))):
         out[name] = run(prob, n, kw, 5)
     del prob
-    sweep = {}
-    for m in (2000, 8000, 16000):
-        prob = nonsym_problem(m, seed=0, config_id=1, backend="torch", device="cuda")
-        row = {}
-        for name, kw in (("jacobi", dict(method="jacobi")), ("gauss_seidel", dict(method="gauss_seidel")),
-                         ("gmres35", dict(method="gmres", restart=35)), ("bicgstab", dict(method="bicgstab"))):
-            r = run(prob, m, dict(kw, tol=1e-4), 5)
-            row[name] = {"iters": r["iters"], "p50_ms": r["p50_ms"], "status": r["status"]}
-        sweep[str(m)] = row
-        del prob
-    out["paper_tolerance_1e-4"] = sweep
     torch.cuda.empty_cache()
     return out
 
@@ -415,11 +510,14 @@ def leg_c4(dev, n):
     return out
 
 
-def leg_c5(dev, count, pool_size, seed=0):
+def leg_c5(dev, count, pool_size, seed=0, rates=(0.5, 0.9)):
     """Serving: binary64 against mixed-precision requests at equal accuracy
-    (normwise backward error <= 1e-12), over a pool of resident systems.
-    Saturation throughput of each, then both under the same Poisson arrivals
-    at 0.5x and 0.9x of the binary64 saturation rate (p50 / p99 latency)."""
+    (normwise backward error <= 1e-12), over a pool of resident systems
+    (n log-uniform on [256, 8192], half SPD CG with cond log-uniform on
+    [1e2, 1e5], half GMRES(30) on D + G/sqrt(n)), each request with its own
+    right-hand side.  Saturation throughput of each, then both under the same
+    Poisson arrivals at the given fractions of the binary64 saturation rate
+    (p50 / p99 latency)."""
     import math
 
     import numpy as np
@@ -506,7 +604,7 @@ def leg_c5(dev, count, pool_size, seed=0):
                          "mixed_over_fp64": round(satmx["throughput_req_per_s"]
                                                   / sat64["throughput_req_per_s"], 3)}
     lam = sat64["throughput_req_per_s"]
-    for frac in (0.5, 0.9):
+    for frac in rates:
         gaps = rng.exponential(1.0 / (frac * lam), size=count)
         arr = list(np.cumsum(gaps) - gaps[0])
         out[f"rate_{frac}_of_fp64_saturation"] = {
@@ -520,20 +618,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=32768, help="order of the step's two systems")
+    ap.add_argument("--kappa", type=float, default=1e4, help="condition number of both systems")
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="timed binary64 steps at the same backward error (after one warm-up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--spd-form", choices=("qr", "identity"), default="qr",
                     help="Q of the SPD matrix: QR of a Gaussian (default) or the identity "
                          "(same spectrum and bytes; for hardware-counter runs)")
-    ap.add_argument("--legs", default="c1,c2p,c3,c4,c5,f1,f3,f4",
+    ap.add_argument("--legs", default="c1,c2,c3sweep,c4,c5,f1,f3,f4",
                     help="extra measurements after the timed steps (comma list of "
-                         "c1,c2p,c3,c4,c5,f1,f3,f4; 'none' for the main step only)")
-    ap.add_argument("--n3", type=int, default=32768, help="size of the mixed-precision leg")
-    ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--serve-pool", type=int, default=32)
-    ap.add_argument("--cg-product", choices=("symmetric", "general"), default="symmetric",
-                    help="CG product: the symmetric kernel reading the lower triangle of A "
-                         "(KS_FLAG_SYMMETRIC) or the general GEMV")
+                         "c1,c2,c2p,c3sweep,c4,c5,f1,f3,f4; 'none' for the main step only)")
+    ap.add_argument("--n2", type=int, default=16384, help="size of the binary64 legs (c2, c2p, c4, f1, f3)")
+    ap.add_argument("--c2-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-rates", default="0.5,0.9",
+                    help="arrival rates of the serving leg as fractions of the binary64 saturation rate")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before timing, copy A once with the library's binary64 copy kernel "
                          "(known bytes: 8 n^2 read + 8 n^2 written) to calibrate HBM counters")
@@ -546,22 +647,25 @@ def main():
     import torch
 
     from paper_1511_07207_amd import krylov
-    from workloads import nonsym_problem, spd_problem
+    from workloads import nonsym_swept_problem, spd_problem
 
     dev = torch.device("cuda:0")
-    n = args.n
+    n, kap = args.n, args.kappa
+    ETA = 1e-12
     t0 = time.perf_counter()
-    spd = spd_problem(n, 1e4, seed=0, config_id=1, backend="torch", device="cuda",
+    spd = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda",
                       q_form=args.spd_form)
-    ns = nonsym_problem(n, seed=0, config_id=1, backend="torch", device="cuda")
+    ns = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda")
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    print(f"[bench] generated n={n} systems in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] generated the two n={n} systems in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    sym = args.cg_product == "symmetric"
-    cg = krylov.Solver(spd.A, method="cg", tol=1e-10, timing=True, timing_every=TIMING_EVERY, symmetric=sym)
-    gm = krylov.Solver(ns.A, method="gmres", restart=30, tol=1e-10, timing=True, timing_every=TIMING_EVERY)
+    common = dict(tol=ETA, max_iter=4 * n, timing=True, timing_every=TIMING_EVERY)
+    # mixed precision: binary32 CG on the lower triangle (a bfloat16 copy of
+    # this SPD matrix is indefinite), bfloat16 GMRES(50) on the nonsymmetric one
+    cg = krylov.Solver(spd.A, method="cg", precision="fp32", symmetric=True, **common)
+    gm = krylov.Solver(ns.A, method="gmres", restart=50, precision="bf16", **common)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     xcg = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -571,61 +675,101 @@ def main():
     krylov.read_ceiling(spd.A, sink)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for _ in range(10):
+    for _ in range(5):
         krylov.read_ceiling(spd.A, sink)
     ev1.record()
     torch.cuda.synchronize()
-    read_ceiling_gbs = 8.0 * n * n / (ev0.elapsed_time(ev1) / 10 * 1e-3) / 1e9
+    read_ceiling_gbs = 8.0 * n * n / (ev0.elapsed_time(ev1) / 5 * 1e-3) / 1e9
     if args.calibration_copy:
         copy = krylov.convert(spd.A, torch.float64)
         torch.cuda.synchronize()
         del copy
 
-    def step():
-        xcg.zero_()
+    def step(s1, s2):
         t = time.perf_counter()
-        _, icg = cg.solve(spd.b, out=xcg)
+        _, i1 = s1.solve(spd.b, out=xcg.zero_())
         t1 = time.perf_counter()
-        xgm.zero_()
-        _, igm = gm.solve(ns.b, out=xgm)
+        _, i2 = s2.solve(ns.b, out=xgm.zero_())
         t2 = time.perf_counter()
-        return icg, igm, (t1 - t) * 1e3, (t2 - t1) * 1e3
+        return i1, i2, (t1 - t) * 1e3, (t2 - t1) * 1e3
+
+    def ok_rec(r):
+        return (r[0]["status"] == 0 and r[1]["status"] == 0 and r[0]["backward_err"] <= ETA
+                and r[1]["backward_err"] <= ETA)
 
     for w in range(args.warmup):
-        step()
+        step(cg, gm)
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = []
     for k in range(args.steps):
-        recs.append(step())
-        print(f"[bench] step {k + 1}/{args.steps}: cg {recs[-1][2]:.1f} ms "
-              f"({recs[-1][0]['iters']} it), gmres {recs[-1][3]:.1f} ms "
-              f"({recs[-1][1]['iters']} it)", file=sys.stderr, flush=True)
+        recs.append(step(cg, gm))
+        print(f"[bench] step {k + 1}/{args.steps}: spd cg-ir {recs[-1][2]:.1f} ms "
+              f"({recs[-1][0]['iters']} inner, {recs[-1][0]['outer_iters']} outer), nonsym gmres50-ir "
+              f"{recs[-1][3]:.1f} ms ({recs[-1][1]['iters']} inner, {recs[-1][1]['outer_iters']} outer)",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-
-    ok = all(r[0]["status"] == 0 and r[1]["status"] == 0 and r[0]["rel_res"] <= 1e-10
-             and r[1]["rel_res"] <= 1e-10 for r in recs)
-    solves = 2 * args.steps
-    value = solves / elapsed
+    ok = all(ok_rec(r) for r in recs)
+    value = 2 * args.steps / elapsed
     ms_step = elapsed * 1e3 / args.steps
-    # dominant kernel: the FP64 product of the CG loop, q = A p (the symmetric
-    # product is two launches: the tiles of the lower triangle, then the
-    # finishing sum that also applies the iteration's x and r update)
-    gemv_ms = sum(r[0]["gemv_ms"] for r in recs)
-    gemv_calls = sum(r[0]["gemv_calls"] for r in recs)
-    gm_gemv_ms = sum(r[1]["gemv_ms"] for r in recs)
-    gm_gemv_calls = sum(r[1]["gemv_calls"] for r in recs)
-    bytes_per_launch = product_bytes(n, args.cg_product)
-    gm_bytes = product_bytes(n, "general")
-    avg_ms = gemv_ms / max(gemv_calls, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(n, args.cg_product)
-    cg_iters = recs[-1][0]["iters"]
-    gm_iters = recs[-1][1]["iters"]
+    xm_cg, xm_gm = xcg.clone(), xgm.clone()
+
+    # binary64 at the same backward error: CG on the lower triangle, GMRES(50)
+    cg64 = krylov.Solver(spd.A, method="cg", symmetric=True, stop_backward=True, **common)
+    gm64 = krylov.Solver(ns.A, method="gmres", restart=50, stop_backward=True, **common)
+    step(cg64, gm64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs64 = []
+    for k in range(args.fp64_steps):
+        recs64.append(step(cg64, gm64))
+        print(f"[bench] binary64 step {k + 1}/{args.fp64_steps}: cg {recs64[-1][2]:.1f} ms "
+              f"({recs64[-1][0]['iters']} it), gmres50 {recs64[-1][3]:.1f} ms "
+              f"({recs64[-1][1]['iters']} it)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    value64 = 2 * len(recs64) / el64 if recs64 else None
+    ok64 = all(ok_rec(r) for r in recs64)
+    cg64.close()
+    gm64.close()
+
+    # per-kernel accounting of the timed products: the one with most of the
+    # step's time is the roofline kernel
+    def prod_stats(idx, product):
+        ms = sum(r[idx]["gemv_ms"] for r in recs)
+        calls = sum(r[idx]["gemv_calls"] for r in recs)
+        avg = ms / max(calls, 1)
+        launches = recs[-1][idx]["iters"]
+        pb = product_bytes(n, product)
+        return {"product": product, "kernel": _PRODUCT_KERNEL[product], "avg_launch_ms": avg,
+                "launches_per_solve": launches, "ms_per_solve": avg * launches,
+                "bytes_per_launch": pb, "achieved_gbs": pb / (avg * 1e-3) / 1e9, "timed_launches": calls}
+
+    ks = [prod_stats(0, "symmetric32"), prod_stats(1, "gmres_bf16")]
+    dom = max(ks, key=lambda k: k["ms_per_solve"])
+    other = ks[1] if dom is ks[0] else ks[0]
+    traffic = load_traffic(n, dom["product"])
+
+    def solve_summary(idx, rs):
+        return {"inner_products": rs[-1][idx]["iters"], "outer_steps": rs[-1][idx]["outer_iters"],
+                "precision_used": rs[-1][idx]["precision_used"],
+                "backward_err": rs[-1][idx]["backward_err"], "rel_res": rs[-1][idx]["rel_res"],
+                "p50_ms": round(_pct([r[2 + idx] for r in rs], 0.5), 3),
+                "p99_ms": round(_pct([r[2 + idx] for r in rs], 0.99), 3)}
+
+    def prec_name(v):
+        return {0: "fp64", 1: "fp32", 2: "bf16", 3: "lu32"}.get(v, v) if isinstance(v, int) else v
+
+    for rs in (recs, recs64):
+        for r in rs:
+            for i in (0, 1):
+                r[i]["precision_used"] = prec_name(r[i]["precision_used"])
+    fwd = {"spd_cg": float((xm_cg - spd.x_true).norm() / spd.x_true.norm()),
+           "nonsym_gmres50": float((xm_gm - ns.x_true).norm() / ns.x_true.norm())}
     out = {
-        "metric": "solves/s (FP64 CG + GMRES(30), n=16384, rel. residual 1e-10)",
+        "metric": "solves/s + GEMV HBM GB/s at 1e-12 backward err, mixed vs FP64; p50/p99 latency",
         "value": round(value, 4),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -635,80 +779,87 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "mixed: f32 / bf16 inner products (f32 accumulation), f64 residual, update and Givens",
         "data": "synthetic",
         "config": {
-            "workload": (f"CG on SPD n={n} (Q diag(lambda) Q^T, lambda log-uniform [1,1e4]) + "
-                         f"GMRES(30) on D + G/sqrt(n), n={n}; x0=0, tol 1e-10; one of each per step"),
-            "n": n, "kappa_spd": 1e4, "restart": 30, "tol": 1e-10, "spd_q": args.spd_form,
-            "cg_product": ("symmetric: lower triangle of A read once per iteration"
-                           if sym else "general: all of A read once per iteration"),
-            "parallelism": "single GPU",
+            "workload": (f"mixed-precision refinement, n={n}, cond {kap:g}: CG-IR on SPD Q diag(lambda) Q^T "
+                         f"(binary32 inner CG on the lower triangle) + GMRES(50)-IR on "
+                         f"diag(lambda) + 0.25 G/sqrt(n) (bfloat16 inner GMRES), lambda log-uniform "
+                         f"[1, {kap:g}]; x0 = 0; stop at eta_inf <= 1e-12; one of each per step"),
+            "n": n, "kappa": kap, "eta_target": ETA, "restart": 50, "inner_tol": 1e-4,
+            "spd_q": args.spd_form, "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("symv_tile_kernel + symv_cg_finish_kernel "
-                       "(q = A p from the lower triangle, fused with x += alpha p, r -= alpha q)"
-                       if sym else
-                       "cg_matvec_kernel<double> (q = A p, p'q partials)"),
-            "achieved": round(achieved, 1),
+            "kernel": dom["kernel"],
+            "achieved": round(dom["achieved_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "read_ceiling_gbs": round(read_ceiling_gbs, 1),
-            "frac_of_read_ceiling": round(achieved / read_ceiling_gbs, 4),
+            "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_ms": round(avg_ms, 5),
-            "launches": gemv_calls,
+            "bytes_per_launch": dom["bytes_per_launch"],
+            "avg_launch_ms": round(dom["avg_launch_ms"], 5),
+            "timed_launches": dom["timed_launches"],
+            "read_ceiling_gbs": round(read_ceiling_gbs, 1),
+            "frac_of_read_ceiling": round(dom["achieved_gbs"] / read_ceiling_gbs, 4),
         },
+        "other_product": {"kernel": other["kernel"], "achieved_gbs": round(other["achieved_gbs"], 1),
+                          "frac": round(other["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                          "avg_launch_ms": round(other["avg_launch_ms"], 5),
+                          "bytes_per_launch": other["bytes_per_launch"],
+                          "traffic": load_traffic(n, other["product"])},
         "valid": ok,
-        "solves": {
-            "cg": {"iters": cg_iters, "rel_res": recs[-1][0]["rel_res"],
-                   "backward_err": recs[-1][0]["backward_err"],
-                   "p50_ms": round(_pct([r[2] for r in recs], 0.5), 3),
-                   "p99_ms": round(_pct([r[2] for r in recs], 0.99), 3)},
-            "gmres": {"iters": gm_iters, "rel_res": recs[-1][1]["rel_res"],
-                      "backward_err": recs[-1][1]["backward_err"],
-                      "p50_ms": round(_pct([r[3] for r in recs], 0.5), 3),
-                      "p99_ms": round(_pct([r[3] for r in recs], 0.99), 3),
-                      "gemv_gbs": round(gm_bytes / (gm_gemv_ms / max(gm_gemv_calls, 1) * 1e-3) / 1e9, 1)},
+        "solves": {"spd_cg_ir_fp32_lower": solve_summary(0, recs),
+                   "nonsym_gmres50_ir_bf16": solve_summary(1, recs)},
+        "fwd_err_vs_x_true": fwd,
+        "fp64_equal_accuracy": {
+            "solves_per_s": round(value64, 4) if value64 else None, "steps": len(recs64),
+            "valid": ok64,
+            "spd_cg_lower": solve_summary(0, recs64) if recs64 else None,
+            "nonsym_gmres50": solve_summary(1, recs64) if recs64 else None,
         },
-        "iterations_per_s": round((cg_iters + gm_iters) * args.steps / elapsed, 1),
+        "mixed_over_fp64": round(value / value64, 3) if value64 else None,
+        "iterations_per_s": round(sum(r[0]["iters"] + r[1]["iters"] for r in recs) / elapsed, 1),
         "create_ms": round(create_ms, 2),
         "generate_s": round(gen_s, 2),
     }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(spd, ns, cg_iters, gm_iters, args.steps)
-    else:
-        out["cpu_baseline"] = None
     cg.close()
     gm.close()
-    del spd, ns
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spd, ns, recs64[-1][0]["iters"] if recs64 else 1000,
+                                           recs64[-1][1]["iters"] if recs64 else 1000)
+        print("[bench] CPU oracle sample done", file=sys.stderr, flush=True)
+    else:
+        out["cpu_baseline"] = None
+    del spd, ns, xcg, xgm, xm_cg, xm_gm
     torch.cuda.empty_cache()
     legs = {}
     wanted = [] if args.legs == "none" else [x.strip() for x in args.legs.split(",") if x.strip()]
+    n2 = args.n2
     for name in wanted:
         print(f"[bench] leg {name} ...", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         try:
             if name == "c1":
                 legs[name] = leg_c1(dev)
-            elif name == "c3":
-                legs[name] = leg_c3(dev, args.n3, 1e4, args.spd_form)
+            elif name == "c2":
+                legs[name] = leg_c2(dev, n2, args.c2_steps, args.spd_form)
+            elif name == "c3sweep":
+                legs[name] = leg_c3sweep(dev, n, args.spd_form)
             elif name == "c4":
-                legs[name] = leg_c4(dev, n)
+                legs[name] = leg_c4(dev, n2)
             elif name == "c5":
-                legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool)
+                rates = [float(v) for v in args.serve_rates.split(",") if v.strip()]
+                legs[name] = leg_c5(dev, args.serve_requests, args.serve_pool, rates=rates)
             elif name == "f1":
-                legs[name] = leg_f1(dev, n)
+                legs[name] = leg_f1(dev, n2)
             elif name == "f3":
-                legs[name] = leg_f3(dev, n)
+                legs[name] = leg_f3(dev, n2)
             elif name == "f4":
                 legs[name] = leg_f4(dev)
             elif name == "c2p":
-                legs[name] = leg_c2p(dev, n)
+                legs[name] = leg_c2p(dev, n2)
             else:
                 legs[name] = {"error": "unknown leg"}
         except Exception as e:  # a failing leg is reported, not fatal

@@ -95,9 +95,14 @@ extern "C" {
 #define KS_FLAG_TIMING 1 /* time the A*v launches with HIP events (info->gemv_ms;
                             all of them, or a sample: timing_every) */
 #define KS_FLAG_STOP_BACKWARD 2 /* binary64 solves: tol bounds the normwise backward
-                                   error eta_inf instead of ||r||_2 / ||b||_2: stop
-                                   when ||r||_2 <= tol (||A||_inf ||x||_inf +
-                                   ||b||_inf), confirmed on the true residual */
+                                   error eta_inf = ||r||_inf / (||A||_inf ||x||_inf +
+                                   ||b||_inf) instead of ||r||_2 / ||b||_2.  CG and
+                                   BiCGSTAB stop when eta_inf of the recursive
+                                   residual and the current iterate meets tol;
+                                   GMRES when its 2-norm estimate does, scaled by
+                                   ||r||_2 / ||r||_inf of the cycle's starting
+                                   residual; every stop is confirmed on eta_inf of
+                                   the true residual */
 #define KS_FLAG_SYMMETRIC 4 /* CG, nrhs = 1: the binary64 products of the Krylov
                                loop, and the binary32 products of KS_IR_FP32's
                                inner solves, read only the lower triangle of A
@@ -227,7 +232,10 @@ typedef struct ks_server ks_server;
 
 /* Create a server with a device-memory admission budget (bytes), at most
  * max_inflight concurrent solves and `chunk` iterations per step (0 = 16).
- * The server allocates its own workspace arena (min(budget, 4 GiB)). */
+ * The solves' workspaces come from device segments the server allocates as
+ * admission needs them (at least 1 GiB each, never more than the budget in
+ * all), so the budget alone decides admission; they are freed by
+ * ks_server_free. */
 int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_inflight, int32_t chunk,
                      void *stream);
 

@@ -197,4 +197,17 @@ __device__ __forceinline__ double stop_threshold(const State *st, double xinf) {
     return st->eta_tol > 0.0 ? st->eta_tol * (st->anorm_inf * xinf + st->binf) : st->thresh;
 }
 
+// GMRES's threshold on its estimate |g(k+1)| = ||r||_2.  With backward-error
+// stopping the 2-norm stands in for ||r||_inf through the ratio
+// ||r||_2 / ||r||_inf of the cycle's starting (true) residual, so the cycle
+// stops near eta_inf = tol rather than ||r||_2 / (...) = tol, which for a
+// residual spread over n components is about sqrt(n / (2 ln n)) times
+// smaller; the stop is confirmed on eta_inf of the true residual at the end
+// of the cycle, and a failed check starts another cycle.
+__device__ __forceinline__ double gm_threshold(const State *st) {
+    if (!(st->eta_tol > 0.0)) return st->thresh;
+    const double ratio = st->resinf > 0.0 ? st->res / st->resinf : 1.0;
+    return st->eta_tol * (st->anorm_inf * st->xinf + st->binf) * ratio;
+}
+
 }  // namespace ks

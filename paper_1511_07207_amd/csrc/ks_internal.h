@@ -64,11 +64,12 @@ struct ColState {
 // Per-block partial results, one region per producing kernel kind.
 struct Partials {
     double *g;    // GEMV-shaped kernels: 3 per block
-    double *v;    // vector kernels: 2 per block (r'r, then ||x||_inf)
+    double *v;    // vector kernels: 3 per block (r'r, ||x||_inf, ||r||_inf)
     double *h1;   // Gram-Schmidt pass 1: (m+1) per block
     double *h2;   // Gram-Schmidt pass 2: (m+1) per block
     double *nrm;  // ||w||^2 after pass 2: 1 per block
-    double *w;    // BiCGSTAB x/r update: 3 per vector block (r'r, r0'r, ||x||_inf)
+    double *w;    // BiCGSTAB x/r update: 4 per vector block (r'r, r0'r, ||x||_inf,
+                  // ||r||_inf)
 };
 
 // Tuning of the dense matrix-vector product: a block of GEMV_NT threads owns
@@ -127,9 +128,9 @@ __host__ __device__ inline int sy_tiles(int n) {
 __host__ __device__ inline size_t sy_ws_doubles(int n) { return (size_t)sy_tiles(n) * 2 * SY_T; }
 constexpr int SY_FIN = 64;  // elements per block of the finishing kernel
 // CG with the symmetric product keeps, after W, one p'Ap share per tile and
-// the r'r and ||x||_inf partials of the finishing blocks.
+// the r'r, ||x||_inf and ||r||_inf partials of the finishing blocks.
 __host__ __device__ inline size_t sy_cg_doubles(int n) {
-    return (size_t)round_up(sy_tiles(n), 32) + 2 * (size_t)div_up(n, SY_FIN);
+    return (size_t)round_up(sy_tiles(n), 32) + 3 * (size_t)div_up(n, SY_FIN);
 }
 
 // GMRES small dense arrays (binary64 always).

@@ -87,10 +87,10 @@ inline Layout make_layout(const ks_params *p) {
     L.gm_off = off;
     off = align_up(off + gm_doubles(L.m) * sizeof(double));
     L.pg = (size_t)round_up((int64_t)gemv_blocks_max(n) * 3, 32);
-    L.pv = (size_t)round_up(2 * vec_blocks(n), 32);
+    L.pv = (size_t)round_up(3 * vec_blocks(n), 32);
     L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
     L.pn = (size_t)round_up(cgs_blocks(n), 32);
-    L.pw = (p->method == KS_BICGSTAB) ? (size_t)round_up(3 * vec_blocks(n), 32) : 0;
+    L.pw = (p->method == KS_BICGSTAB) ? (size_t)round_up(4 * vec_blocks(n), 32) : 0;
     L.part_count = L.pg + L.pv + 2 * L.ph + L.pn + L.pw;
     L.part_off = off;
     off = align_up(off + L.part_count * sizeof(double));

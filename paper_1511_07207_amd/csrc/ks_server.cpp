@@ -106,6 +106,7 @@ struct Req {
     double t_submit = 0.0;
     size_t ws_off = 0, ws_bytes = 0, footprint = 0;
     Phase phase = P_QUEUED;
+    int seg = -1;  // workspace segment
     bool copy_a = false;
     int restarts = 0, cycles = 0;
     BatchItem item{};  // binary64: the solve, or the refinement's outer step
@@ -130,14 +131,25 @@ constexpr int NO_OUTCOME = -100;
 
 }  // namespace
 
+// The workspaces live in device segments allocated as admission needs them:
+// a request goes first fit into an existing segment, else into a new one of
+// at least SEG_MIN bytes, as long as all segments together stay within the
+// memory budget (the workspaces of the admitted requests never exceed it, so
+// admission is decided by the budget, not by a fixed arena).
+constexpr size_t SEG_MIN = (size_t)1 << 30;
+struct Segment {
+    char *base = nullptr;
+    size_t bytes = 0;
+    Arena arena;
+};
+
 struct ks_server {
     hipStream_t stream = nullptr;
     size_t budget = 0, in_use = 0;
     int max_inflight = 0;
     int chunk = 16;
-    char *arena_dev = nullptr;
-    size_t arena_bytes = 0;
-    Arena arena;
+    std::vector<Segment> segs;
+    size_t seg_total = 0;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
     std::vector<Req *> inflight;
@@ -174,6 +186,35 @@ int grow_buffers(ks_server *sv, size_t tab_bytes, size_t nstage) {
     }
     return KS_OK;
 }
+
+// A workspace of `bytes` for r: first fit in the segments, else a new segment
+// if the budget allows.  Returns false (nothing allocated) when neither works.
+bool ws_alloc(ks_server *sv, Req *r) {
+    for (size_t i = 0; i < sv->segs.size(); ++i) {
+        size_t off = 0;
+        if (sv->segs[i].arena.alloc(r->ws_bytes, &off)) {
+            r->seg = (int)i;
+            r->ws_off = off;
+            return true;
+        }
+    }
+    const size_t need = align_up(r->ws_bytes);
+    if (sv->seg_total + need > sv->budget) return false;
+    const size_t bytes = std::min(std::max(need, SEG_MIN), align_up(sv->budget - sv->seg_total));
+    Segment sg;
+    if (hipMalloc((void **)&sg.base, bytes) != hipSuccess) return false;
+    sg.bytes = bytes;
+    sg.arena.init(bytes);
+    size_t off = 0;
+    sg.arena.alloc(r->ws_bytes, &off);
+    sv->segs.push_back(sg);
+    sv->seg_total += bytes;
+    r->seg = (int)sv->segs.size() - 1;
+    r->ws_off = off;
+    return true;
+}
+
+inline char *ws_base(const ks_server *sv, const Req *r) { return sv->segs[r->seg].base + r->ws_off; }
 
 // Builds the per-tick table in pinned host memory: item arrays, then for
 // every (subset, block shape) an index array and a prefix-sum array of block
@@ -252,7 +293,7 @@ void retire(ks_server *sv, Req *r, const State &h, int status, int iters) {
     r->info.outer_iters = r->outer;
     r->info.precision_used = r->prec;
     r->phase = P_DONE;
-    sv->arena.release(r->ws_off, r->ws_bytes);
+    sv->segs[r->seg].arena.release(r->ws_off, r->ws_bytes);
     sv->in_use -= r->footprint;
     sv->finished.push_back(r);
 }
@@ -342,7 +383,7 @@ int ir_check(ks_server *sv, Req *r, const State &h) {
         r->bad = 0;
     }
     r->eta_prev = eta;
-    const Carved c = carve(r->L, sv->arena_dev + r->ws_off);
+    const Carved c = carve(r->L, ws_base(sv, r));
     if (r->prec == KS_FP64) {
         to_fp64_tail(r, c);
         return NO_OUTCOME;
@@ -410,13 +451,6 @@ int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_infli
     sv->budget = mem_budget_bytes;
     sv->max_inflight = max_inflight;
     sv->chunk = chunk > 0 ? chunk : 16;
-    // workspaces only (A stays where the caller keeps it): a fraction of the budget
-    sv->arena_bytes = align_up(std::min<size_t>(mem_budget_bytes, (size_t)4 << 30));
-    if (hipMalloc((void **)&sv->arena_dev, sv->arena_bytes) != hipSuccess) {
-        delete sv;
-        return KS_ENOMEM;
-    }
-    sv->arena.init(sv->arena_bytes);
     *out = sv;
     return KS_OK;
 }
@@ -436,7 +470,7 @@ int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const
     r->copy_a = !a_borrowable(d_A, p->lda);
     r->ws_bytes = r->copy_a ? r->L.total : r->L.total_borrowed;
     r->footprint = r->ws_bytes + (size_t)8 * (size_t)p->n * (size_t)p->lda;
-    if (r->footprint > sv->budget || align_up(r->ws_bytes) > sv->arena_bytes) {
+    if (r->footprint > sv->budget) {
         delete r;
         return KS_ETOOLARGE;
     }
@@ -459,11 +493,9 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     while (!sv->queue.empty() && (int)sv->inflight.size() < sv->max_inflight) {
         Req *r = sv->queue.front();
         if (sv->in_use + r->footprint > sv->budget) break;
-        size_t off = 0;
-        if (!sv->arena.alloc(r->ws_bytes, &off)) break;
-        r->ws_off = off;
+        if (!ws_alloc(sv, r)) break;
         sv->in_use += r->footprint;
-        char *ws = sv->arena_dev + off;
+        char *ws = ws_base(sv, r);
         const Carved c = carve(r->L, ws);
         BatchItem &it = r->item;
         it.A = r->A;
@@ -863,7 +895,7 @@ void ks_server_free(ks_server *sv) {
     for (Req *r : sv->queue) delete r;
     for (Req *r : sv->inflight) delete r;
     for (Req *r : sv->finished) delete r;
-    if (sv->arena_dev) (void)hipFree(sv->arena_dev);
+    for (Segment &sg : sv->segs) (void)hipFree(sg.base);
     if (sv->dtab) (void)hipFree(sv->dtab);
     if (sv->htab) (void)hipHostFree(sv->htab);
     if (sv->dstage) (void)hipFree(sv->dstage);

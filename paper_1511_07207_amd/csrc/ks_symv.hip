@@ -30,7 +30,7 @@
 // general product.  The x values of
 // a wave's rows are wave-uniform (scalar loads), so no barrier precedes the
 // loads of A.  The column part accumulates per lane (its columns
-// are fixed) and is summed over the 4 waves through LDS.  The row part of each
+// are fixed) and is summed over the SY_WAVES (8) waves through LDS.  The row part of each
 // row is a sum over the 64 lanes; a wave takes its rows in groups of U and
 // forms the U sums together by a butterfly that halves the number of values
 // per lane at each exchange, then adds within the remaining lane groups.
@@ -72,8 +72,8 @@ static_assert(SY_HW == 2 * WAVE, "one wave instruction covers one half of a tile
 static_assert(SY_RPW % SY_UNR_INT == 0 && SY_RPW % SY_UNR_SPC == 0, "groups tile the rows");
 static_assert(SY_T % SY_FIN == 0, "a finishing block stays inside one tile column");
 
-// Rows of a tile are interleaved over the waves: wave w reads rows w, w + 4,
-// w + 8, ... (local row lr = w + SY_WAVES * k), so the block as a whole reads
+// Rows of a tile are interleaved over the waves: wave w reads rows w, w + 8,
+// w + 16, ... (local row lr = w + SY_WAVES * k), so the block as a whole reads
 // consecutive rows at any moment (measured 5% faster than contiguous row
 // blocks per wave for the same bytes).
 __device__ __forceinline__ int sy_row(int w, int k) { return w + SY_WAVES * k; }
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, co
 // iteration's update on the block's elements, as the general CG update does:
 // block 0 records the iteration (or the breakdown / non-finite sigma) in st,
 // x_j += alpha p_j, r_j -= alpha q_j, and the block's r'r and ||x||_inf
-// partials.  The vectors and the shares are loaded before the tile outputs
+// partials (and ||r||_inf when stopping on the backward error).  The vectors and the shares are loaded before the tile outputs
 // are summed, so their latency is hidden behind that reduction.
 __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     int n, const double *__restrict__ W, const double *__restrict__ sig, int ntiles,
@@ -402,6 +402,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     double sg = 0.0;
     for (int i = threadIdx.x; i < ntiles; i += SY_FWAVES * WAVE) sg += sig[i];
     const double rho = st->rho;  // written by the launch before, read with the vectors
+    const bool eta = st->eta_tol > 0.0;
     // block 0 of this very launch may set F_STOP (breakdown) while other blocks
     // start: the whole block takes one decision, so no wave leaves before a
     // barrier that the others reach (a launch that sees the new flag would
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     }
     if (!ok || w != 0) return;
     const double a = rho / sigma;
-    double s2 = 0.0, xm = 0.0;
+    double s2 = 0.0, xm = 0.0, rm = 0.0;
     if (j < n) {
         const double xi = fma(a, pj, xj);
         x[j] = xi;
@@ -436,12 +437,18 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
         r[j] = ri;
         s2 = ri * ri;
         xm = finite_d(xi) ? fabs(xi) : INFINITY;
+        rm = finite_d(ri) ? fabs(ri) : INFINITY;
     }
     s2 = wave_sum(s2);
     xm = wave_max(xm);
     if (lane == 0) {
         prho[blockIdx.x] = s2;
         prho[nfb + blockIdx.x] = xm;
+    }
+    if (eta) {
+        // ||r||_inf partials for stopping on the backward error
+        rm = wave_max(rm);
+        if (lane == 0) prho[2 * nfb + blockIdx.x] = rm;
     }
 }
 

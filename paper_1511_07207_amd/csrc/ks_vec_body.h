@@ -39,7 +39,8 @@ __device__ __forceinline__ void vec_stats_body(int n, const T *__restrict__ b, d
 // ------------------------------------------------------------------- CG
 // x += alpha p, r -= alpha q with alpha = rho / sigma, sigma = p'q reduced
 // from the matrix-vector product's partials; r'r partials for the next kernel.
-// prho: [r'r partials (nblk)][||x||_inf partials (nblk)], nblk = vec_blocks(n)
+// prho: [r'r partials (nblk)][||x||_inf partials (nblk)][||r||_inf partials
+// (nblk, only when stopping on the backward error)], nblk = vec_blocks(n)
 template <typename T>
 __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__restrict__ r,
                                                const T *__restrict__ p, const T *__restrict__ q,
@@ -61,6 +62,7 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
         qv[e] = q[i];
     }
     const double rho = st->rho;  // written by the launch before, read with the vectors
+    const double eta_tol = st->eta_tol;
     const double sigma = reduce_partials_all<VEC_NT>(psigma, nsigma, 1);
     if (st->flags & F_STOP) return;
     const bool ok = finite_d(sigma) && sigma > 0.0;
@@ -77,7 +79,7 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
     }
     if (!ok) return;
     const T a = (T)(rho / sigma);
-    double s2 = 0.0, xm = 0.0;
+    double s2 = 0.0, xm = 0.0, rm = 0.0;
 #pragma unroll
     for (int e = 0; e < VEC_EPT; ++e) {
         const int i = base + e * VEC_NT;
@@ -88,6 +90,7 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
             r[i] = ri;
             s2 += (double)ri * (double)ri;
             xm = fmax(xm, finite_d((double)xi) ? fabs((double)xi) : INFINITY);
+            rm = fmax(rm, finite_d((double)ri) ? fabs((double)ri) : INFINITY);
         }
     }
     const double t = block_sum<VEC_NT>(s2, sm);
@@ -97,10 +100,18 @@ __device__ __forceinline__ void cg_update_body(int n, T *__restrict__ x, T *__re
         prho[bid] = t;
         prho[nblk + bid] = tx;
     }
+    if (eta_tol > 0.0) {
+        __syncthreads();
+        const double tr = block_max<VEC_NT>(rm, sm);
+        if (threadIdx.x == 0) prho[2 * nblk + bid] = tr;
+    }
 }
 
 // rho' = r'r; stop on the recursive residual or the iteration limit;
-// otherwise beta = rho' / rho and p = r + beta p.
+// otherwise beta = rho' / rho and p = r + beta p.  Stopping on the backward
+// error compares ||r||_inf of the recursive residual with
+// tol (||A||_inf ||x||_inf + ||b||_inf) (the infinity norms of the iterate's
+// partials), i.e. eta_inf of the recursive residual itself.
 template <typename T>
 __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, T *__restrict__ p,
                                                 State *st, const double *__restrict__ prho, int nrho,
@@ -123,11 +134,14 @@ __device__ __forceinline__ void cg_pupdate_body(int n, const T *__restrict__ r, 
     const double rho_new = reduce_partials_all<VEC_NT>(prho, nrho, 1);
     if (st->flags & F_STOP) return;
     const double xinf = eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + nrho, nrho, 1) : 0.0;
-    const double threshold = eta_tol > 0.0 ? eta_tol * (anorm_inf * xinf + binf) : thresh;
+    const double rinf =
+        eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(prho + 2 * nrho, nrho, 1) : 0.0;
+    const bool conv = eta_tol > 0.0 ? rinf <= eta_tol * (anorm_inf * xinf + binf)
+                                    : sqrt(rho_new) <= thresh;
     int stop = 0;
     if (!finite_d(rho_new))
         stop = F_NONFIN | F_STOP;
-    else if (sqrt(rho_new) <= threshold)
+    else if (conv)
         stop = F_CONV | F_STOP;
     else if (iters >= max_iter)
         stop = F_MAXIT | F_STOP;
@@ -298,7 +312,7 @@ __device__ __forceinline__ void bs_xrupdate_body(int n, T *__restrict__ x, T *__
     }
     if (!ok) return;
     const T w = (T)om;
-    double rr = 0.0, r0r = 0.0, xm = 0.0;
+    double rr = 0.0, r0r = 0.0, xm = 0.0, rm = 0.0;
 #pragma unroll
     for (int e = 0; e < VEC_EPT; ++e) {
         const int i = base + e * VEC_NT;
@@ -311,6 +325,7 @@ __device__ __forceinline__ void bs_xrupdate_body(int n, T *__restrict__ x, T *__
             rr += (double)ri * (double)ri;
             r0r += (double)r0[i] * (double)ri;
             xm = fmax(xm, finite_d((double)xi) ? fabs((double)xi) : INFINITY);
+            rm = fmax(rm, finite_d((double)ri) ? fabs((double)ri) : INFINITY);
         }
     }
     const double t0 = block_sum<VEC_NT>(rr, sm);
@@ -322,6 +337,11 @@ __device__ __forceinline__ void bs_xrupdate_body(int n, T *__restrict__ x, T *__
         pw[bid] = t0;
         pw[nblk + bid] = t1;
         pw[2 * nblk + bid] = t2;
+    }
+    if (st->eta_tol > 0.0) {
+        __syncthreads();
+        const double t3 = block_max<VEC_NT>(rm, sm);
+        if (threadIdx.x == 0) pw[3 * nblk + bid] = t3;
     }
 }
 
@@ -342,12 +362,18 @@ __device__ __forceinline__ void bs_pupdate_body(int n, const T *__restrict__ r, 
     }
     const double rr = reduce_partials_all<VEC_NT>(pw, nw, 1);
     const double rho_new = reduce_partials_all<VEC_NT>(pw + nw, nw, 1);
-    const double xinf = st->eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(pw + 2 * nw, nw, 1) : 0.0;
+    const double eta_tol = st->eta_tol;
+    const double xinf = eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(pw + 2 * nw, nw, 1) : 0.0;
+    const double rinf = eta_tol > 0.0 ? reduce_partials_max_all<VEC_NT>(pw + 3 * nw, nw, 1) : 0.0;
     const double rho = st->rho_prev, alpha = st->alpha, om = st->omega;
+    // backward-error stopping: ||r||_inf of the recursive residual against
+    // tol (||A||_inf ||x||_inf + ||b||_inf)
+    const bool conv = eta_tol > 0.0 ? rinf <= eta_tol * (st->anorm_inf * xinf + st->binf)
+                                    : sqrt(rr) <= st->thresh;
     int stop = 0;
     if (!finite_d(rr))
         stop = F_NONFIN | F_STOP;
-    else if (sqrt(rr) <= stop_threshold(st, xinf))
+    else if (conv)
         stop = F_CONV | F_STOP;
     else if (st->iters >= max_iter)
         stop = F_MAXIT | F_STOP;
@@ -539,7 +565,7 @@ __device__ __forceinline__ void gm_givens_body(int n, const T *__restrict__ w, T
         st->k_done = k + 1;
         if (hk1 <= HAPPY_FACTOR * avk)
             st->flags |= F_HAPPY | F_STOP;
-        else if (fabs(ga.g[k + 1]) <= stop_threshold(st, st->xinf))
+        else if (fabs(ga.g[k + 1]) <= gm_threshold(st))
             st->flags |= F_CONV | F_STOP;
         else if (st->iters >= max_iter)
             st->flags |= F_MAXIT | F_STOP;

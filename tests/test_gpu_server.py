@@ -136,6 +136,37 @@ def test_server_rejects_oversize(device):
     torch.cuda.synchronize()
 
 
+def test_server_admits_mixed_requests_up_to_the_budget(device):
+    # 20 binary32-refined requests at n = 8192 carry 20 binary32 copies of A
+    # in their workspaces (about 5.4 GB together, more than any fixed 4 GiB
+    # arena holds): with a 64 GB budget all of them are admitted at once,
+    # and the budget charged is the workspaces plus the resident A's bytes.
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n, k = 8192, 20
+    print(f"server admission: {k} fp32-refined requests at n={n}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    A = torch.randn(n, n, dtype=torch.float64, device=device, generator=g) / (n ** 0.5)
+    A += 3.0 * torch.eye(n, dtype=torch.float64, device=device)
+    b = torch.randn(n, dtype=torch.float64, device=device, generator=g)
+    srv = krylov.Server(mem_budget_bytes=64 * 10 ** 9, max_inflight=64, chunk=4)
+    for _ in range(k):
+        srv.submit(A, b, method="gmres", restart=30, precision="fp32", tol=1e-12)
+    a, q = srv.step()
+    st = srv.stats()
+    print(f"  after one tick: inflight {a}, queued {q}, bytes {st['bytes_in_use'] / 1e9:.2f} GB",
+          flush=True)
+    assert q == 0 and a + len(srv.poll()) == k
+    assert st["bytes_in_use"] >= k * (8 * n * n + 4 * n * n)
+    out = _drain(srv)
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(i["status"] == 0 for _, i in out.values())
+
+
 def test_server_zero_rhs_and_exact_guess(device):
     import torch
 
