@@ -72,6 +72,12 @@ def _load():
         lib.ko_lu32_apply.restype = None
         lib.ko_gmres_ir_lu.argtypes = [i, pd, l, pd, pd, d, i, d, i, i, i, pi, pi, pd]
         lib.ko_gmres_ir_lu.restype = i
+        lib.ko_chol32_block.argtypes = [i, pd, l, pf, l, i]
+        lib.ko_chol32_block.restype = i
+        lib.ko_chol32_apply.argtypes = [i, pf, l, pd, pd]
+        lib.ko_chol32_apply.restype = None
+        lib.ko_cg_ir_chol.argtypes = [i, pd, l, pd, pd, d, d, i, i, i, pi, pi, pd]
+        lib.ko_cg_ir_chol.restype = i
         for name in ("ko_jacobi", "ko_gauss_seidel"):
             getattr(lib, name).argtypes = [i, pd, l, pd, pd, d, i, pi, pd]
             getattr(lib, name).restype = i
@@ -301,6 +307,45 @@ def gmres_ir_lu(A, b, x0=None, tol=1e-12, restart=30, inner_tol=1e-4, max_inner=
     st = _load().ko_gmres_ir_lu(n, _pd(A), lda, _pd(b), _pd(x), float(tol), int(restart),
                                 float(inner_tol), max_inner, int(max_outer), int(nb),
                                 ctypes.byref(o), ctypes.byref(it), ctypes.byref(eta))
+    return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), outer_iters=o.value,
+                   inner_iters=it.value, eta_inf=eta.value)
+
+
+def chol32_block(A, nb=64):
+    """Binary32 block Cholesky of the binary32 rounding of symmetric A (lower
+    triangle read; block width nb).  Returns (L float32 lower, not_pd) where
+    not_pd = 0, or 1 + the first column whose pivot is not positive."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    L = np.zeros((n, n), dtype=np.float32)
+    s = _load().ko_chol32_block(n, _pd(A), lda, _pf(L), n, int(nb))
+    if s < 0:
+        raise ValueError("ko_chol32_block: bad arguments")
+    return L, int(s)
+
+
+def chol32_apply(L, v):
+    """z = L^-T L^-1 v in binary64 with the binary32 factor widened."""
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    n = L.shape[0]
+    v = _vec(v, n)
+    z = np.zeros(n)
+    _load().ko_chol32_apply(n, _pf(L), n, _pd(v), _pd(z))
+    return z
+
+
+def cg_ir_chol(A, b, x0=None, tol=1e-12, inner_tol=1e-4, max_inner=None, max_outer=30, nb=64):
+    """CG-IR: binary64 refinement, CG in binary64 preconditioned with the
+    binary32 block Cholesky of A. Returns (x, info)."""
+    A, lda = _mat(A)
+    n = A.shape[0]
+    b = _vec(b, n)
+    x = np.zeros(n) if x0 is None else _vec(x0, n).copy()
+    max_inner = 10 * n if max_inner is None else int(max_inner)
+    o, it, eta = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _load().ko_cg_ir_chol(n, _pd(A), lda, _pd(b), _pd(x), float(tol), float(inner_tol),
+                               max_inner, int(max_outer), int(nb), ctypes.byref(o), ctypes.byref(it),
+                               ctypes.byref(eta))
     return x, dict(status=int(st), status_name=STATUS.get(int(st), "?"), outer_iters=o.value,
                    inner_iters=it.value, eta_inf=eta.value)
 

@@ -908,3 +908,182 @@ out:
     if (eta_out) *eta_out = eta;
     return status;
 }
+
+/* ------------------------------------------ binary32 block Cholesky, CG-IR
+ *
+ * Block Cholesky (direct-methods section, the Cholesky relations that follow
+ * the block LU), in binary32 arithmetic on the binary32 rounding of a
+ * symmetric A (only its lower triangle is read).  With the leading b columns
+ * split off, A = L L^T reads
+ *   [A11 A21^T]   [L11  0 ] [L11^T L21^T]
+ *   [A21 A22  ] = [L21 L22] [ 0    L22^T]
+ * so (i) A11 = L11 L11^T is factored column by column,
+ *   l_jj = sqrt(a_jj - sum_{k<j} l_jk^2),  l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj;
+ * (ii) L21 = A21 L11^-T, each row of A21 solved against L11^T by the same
+ * formula; (iii) S = A22 - L21 L21^T (lower triangle), and the same on S.
+ * Every sum subtracts its terms one at a time in increasing k, in whichever
+ * step they arrive, so the result does not depend on b (b >= n is the
+ * unblocked algorithm).  L (lower triangle, diagonal included) is written to
+ * L; entries above the diagonal are set to 0.  Returns 0, or 1 + the first
+ * column whose pivot a_jj - sum l_jk^2 is not positive (A is not positive
+ * definite in binary32); the factorization stops there.
+ *
+ * The factor then preconditions CG inside binary64 iterative refinement
+ * (CG-IR): r = b - A x in binary64; the correction solves A d = r by CG in
+ * binary64 preconditioned with M = L L^T (M^-1 v = L^-T L^-1 v with the
+ * binary32 factor widened to binary64), from d = 0 to ||r - A d||_2 <=
+ * inner_tol ||r||_2; x += d; until the normwise backward error
+ * ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) <= tol.
+ */
+int ko_chol32_block(int n, const double *A, long lda, float *L, long ldl, int b) {
+    if (n <= 0 || !A || !L || lda < n || ldl < n || b < 1) return KO_EINVAL;
+#define F(i, j) L[(long)(i) * ldl + (j)]
+    int notpd = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) F(i, j) = (j <= i) ? (float)A[(long)i * lda + j] : 0.0f;
+    for (int kb = 0; kb < n; kb += b) {
+        const int bf = kb + b < n ? kb + b : n; /* the block's columns kb .. bf-1 */
+        /* (i) the diagonal block: its entries already hold the updates of
+         * the columns before kb; subtract the block's own columns, in order */
+        for (int j = kb; j < bf; ++j) {
+            float d = F(j, j);
+            for (int k = kb; k < j; ++k) d = d - F(j, k) * F(j, k);
+            if (!(d > 0.0f)) {
+                notpd = j + 1;
+                goto done;
+            }
+            const float ljj = sqrtf(d);
+            F(j, j) = ljj;
+            for (int i = j + 1; i < bf; ++i) {
+                float s = F(i, j);
+                for (int k = kb; k < j; ++k) s = s - F(i, k) * F(j, k);
+                F(i, j) = s / ljj;
+            }
+        }
+        /* (ii) L21 = A21 L11^-T: row i of the panel below the block */
+        for (int i = bf; i < n; ++i)
+            for (int j = kb; j < bf; ++j) {
+                float s = F(i, j);
+                for (int k = kb; k < j; ++k) s = s - F(i, k) * F(j, k);
+                F(i, j) = s / F(j, j);
+            }
+        /* (iii) S = A22 - L21 L21^T on the lower triangle */
+        for (int i = bf; i < n; ++i)
+            for (int j = bf; j <= i; ++j) {
+                float s = F(i, j);
+                for (int k = kb; k < bf; ++k) s = s - F(i, k) * F(j, k);
+                F(i, j) = s;
+            }
+    }
+done:
+#undef F
+    return notpd;
+}
+
+/* z = L^-T L^-1 v in binary64 with the binary32 factor of ko_chol32_block */
+void ko_chol32_apply(int n, const float *L, long ldl, const double *v, double *z) {
+    for (int i = 0; i < n; ++i) {
+        double s = v[i];
+        for (int j = 0; j < i; ++j) s -= (double)L[(long)i * ldl + j] * z[j];
+        z[i] = s / (double)L[(long)i * ldl + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int j = i + 1; j < n; ++j) s -= (double)L[(long)j * ldl + i] * z[j];
+        z[i] = s / (double)L[(long)i * ldl + i];
+    }
+}
+
+/* Preconditioned CG in binary64 on A d = r from d = 0 with M = L L^T:
+ * stops when ||r - A d||_2 <= tol ||r||_2 (recursive residual) or after
+ * max_steps products.  *steps counts products. */
+static int pcg_chol_inner(int n, const double *A, long lda, const float *L, long ldl,
+                          const double *r, double *d, double tol, int max_steps,
+                          int *steps_out) {
+    size_t nn = (size_t)n;
+    int steps = 0, status = KO_MAXITER;
+    double *res = (double *)malloc(sizeof(double) * nn), *z = (double *)malloc(sizeof(double) * nn);
+    double *p = (double *)malloc(sizeof(double) * nn), *q = (double *)malloc(sizeof(double) * nn);
+    if (!res || !z || !p || !q) {
+        status = KO_EINVAL;
+        goto out;
+    }
+    for (int i = 0; i < n; ++i) { d[i] = 0.0; res[i] = r[i]; }
+    const double rnorm = ko_nrm2(n, r);
+    if (!isfinite(rnorm)) { status = KO_NONFINITE; goto out; }
+    if (rnorm == 0.0) { status = KO_OK; goto out; }
+    ko_chol32_apply(n, L, ldl, res, z);
+    for (int i = 0; i < n; ++i) p[i] = z[i];
+    double rz = ko_dot(n, res, z);
+    for (;;) {
+        const double rn = ko_nrm2(n, res);
+        if (!isfinite(rn) || !isfinite(rz)) { status = KO_NONFINITE; break; }
+        if (rn <= tol * rnorm) { status = KO_OK; break; }
+        if (steps >= max_steps) { status = KO_MAXITER; break; }
+        ko_matvec(n, A, lda, p, q);
+        ++steps;
+        const double sigma = ko_dot(n, p, q);
+        if (!isfinite(sigma)) { status = KO_NONFINITE; break; }
+        if (sigma <= 0.0 || rz <= 0.0) { status = KO_BREAKDOWN; break; }
+        const double alpha = rz / sigma;
+        for (int i = 0; i < n; ++i) d[i] = d[i] + alpha * p[i];
+        for (int i = 0; i < n; ++i) res[i] = res[i] - alpha * q[i];
+        ko_chol32_apply(n, L, ldl, res, z);
+        const double rz_new = ko_dot(n, res, z);
+        const double beta = rz_new / rz;
+        for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+out:
+    free(res); free(z); free(p); free(q);
+    if (steps_out) *steps_out = steps;
+    return status;
+}
+
+int ko_cg_ir_chol(int n, const double *A, long lda, const double *b, double *x, double tol,
+                  double inner_tol, int max_inner, int max_outer, int nb, int *outer_out,
+                  int *inner_out, double *eta_out) {
+    if (n <= 0 || !A || !b || !x || lda < n || !(tol > 0.0) || !(inner_tol > 0.0) ||
+        max_inner < 1 || max_outer < 0 || nb < 1)
+        return KO_EINVAL;
+    size_t nn = (size_t)n;
+    float *L = (float *)malloc(sizeof(float) * nn * nn);
+    double *r = (double *)malloc(sizeof(double) * nn);
+    double *d = (double *)malloc(sizeof(double) * nn);
+    int status = KO_STAGNATED, outer = 0, inner = 0;
+    double eta = 0.0;
+    if (!L || !r || !d) {
+        status = KO_EINVAL;
+        goto out;
+    }
+    const double anorm = ko_norm_inf_mat(n, A, lda);
+    const double binf = norm_inf_vec(n, b);
+    if (!isfinite(binf)) { status = KO_NONFINITE; goto out; }
+    if (binf == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        status = KO_OK;
+        goto out;
+    }
+    if (ko_chol32_block(n, A, lda, L, (long)n, nb)) { status = KO_BREAKDOWN; goto out; }
+    for (;;) {
+        ko_residual(n, A, lda, b, x, r);
+        const double rinf = norm_inf_vec(n, r), xinf = norm_inf_vec(n, x);
+        const double den = anorm * xinf + binf;
+        eta = den > 0.0 ? rinf / den : rinf;
+        if (!isfinite(eta)) { status = KO_NONFINITE; break; }
+        if (eta <= tol) { status = KO_OK; break; }
+        if (outer >= max_outer) { status = KO_STAGNATED; break; }
+        int steps = 0;
+        const int st = pcg_chol_inner(n, A, lda, L, (long)n, r, d, inner_tol, max_inner, &steps);
+        inner += steps;
+        ++outer;
+        if (st == KO_NONFINITE || st == KO_BREAKDOWN || st == KO_EINVAL) { status = st; break; }
+        for (int i = 0; i < n; ++i) x[i] = x[i] + d[i];
+    }
+out:
+    free(L); free(r); free(d);
+    if (outer_out) *outer_out = outer;
+    if (inner_out) *inner_out = inner;
+    if (eta_out) *eta_out = eta;
+    return status;
+}

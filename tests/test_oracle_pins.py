@@ -798,3 +798,130 @@ def test_gmres_ir_lu_converges_where_gmres_stalls():
     assert oracle.metrics(p.A, p.b, x)["eta_inf"] <= 1e-12
     xs = np.linalg.solve(p.A, p.b)
     assert np.linalg.norm(x - xs) <= 1e6 * 1e-12 * 10 * np.linalg.norm(xs)
+
+
+# --------------------------------------- binary32 block Cholesky and CG-IR
+# The block Cholesky of the direct-methods section in binary32, pinned by the
+# componentwise backward-error bound of the Cholesky factorization, by its
+# independence of the block width (every sum subtracts its terms in the same
+# order), by an exactly representable factor it must reproduce bit for bit,
+# by LAPACK's Cholesky of the same binary32 matrix, and by refusing a matrix
+# that is not positive definite; its application by SciPy's triangular
+# solves; CG-IR by exactness when M = A and by convergence where plain CG
+# needs thousands of iterations.
+
+def _spd32(n, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    return G @ G.T / n + 0.5 * np.eye(n)
+
+
+@pytest.mark.parametrize("n,b", [(1, 64), (70, 16), (200, 64), (200, 7), (200, 200)])
+def test_chol32_backward_error_bound(n, b):
+    A = _spd32(n, 100 + n + b)
+    L, notpd = oracle.chol32_block(A, nb=b)
+    assert notpd == 0
+    L64 = L.astype(np.float64)
+    assert not np.triu(L64, 1).any()
+    A32 = A.astype(np.float32).astype(np.float64)
+    A32 = np.tril(A32) + np.tril(A32, -1).T  # the lower triangle is what is read
+    u = 2.0 ** -24
+    gamma = (n + 1) * u / (1 - (n + 1) * u)
+    err = np.abs(A32 - L64 @ L64.T)
+    assert np.all(err <= gamma * (np.abs(L64) @ np.abs(L64).T) + 1e-300)
+    assert np.all(np.diag(L64) > 0)
+
+
+def test_chol32_independent_of_block_width_and_close_to_lapack():
+    n = 150
+    A = _spd32(n, 110)
+    L1, _ = oracle.chol32_block(A, nb=1)
+    for b in (2, 16, 64, 149, 150, 1000):
+        Lb, s = oracle.chol32_block(A, nb=b)
+        assert s == 0
+        np.testing.assert_array_equal(Lb, L1)
+    # LAPACK's Cholesky of the same binary32 matrix in binary64: the binary32
+    # factor is within the perturbation bound of the factor (forward error of
+    # order cond(A) n u32)
+    A32 = A.astype(np.float32).astype(np.float64)
+    A32 = np.tril(A32) + np.tril(A32, -1).T
+    Lr = np.linalg.cholesky(A32)
+    rel = np.linalg.norm(L1 - Lr) / np.linalg.norm(Lr)
+    assert rel <= np.linalg.cond(A32) * n * 2.0 ** -24
+
+
+def _exact_chol_system(n, seed):
+    """A = L0 L0^T with L0 lower, diagonal in {1, 2, 4} and dyadic
+    off-diagonal entries small enough that every partial sum is exact in
+    binary32: the factorization must return L0 exactly."""
+    rng = np.random.default_rng(seed)
+    d = rng.choice([1.0, 2.0, 4.0], n)
+    L0 = np.tril(rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0], size=(n, n)), -1) * d[None, :] + np.diag(d)
+    return L0, L0 @ L0.T
+
+
+@pytest.mark.parametrize("b", [1, 4, 16, 24])
+def test_chol32_reproduces_an_exact_factor(b):
+    n = 24
+    L0, A = _exact_chol_system(n, 120)
+    L, s = oracle.chol32_block(A, nb=b)
+    assert s == 0
+    np.testing.assert_array_equal(L.astype(np.float64), L0)
+
+
+def test_chol32_refuses_indefinite_and_reads_the_lower_triangle():
+    n = 40
+    A = _spd32(n, 130)
+    A[17, 17] = -1.0
+    _, s = oracle.chol32_block(A, nb=16)
+    assert s >= 1 and s <= 18
+    # the upper triangle is never read
+    B = _spd32(n, 131)
+    Bn = B.copy()
+    Bn[np.triu_indices(n, 1)] = np.nan
+    L1, _ = oracle.chol32_block(B, nb=8)
+    L2, _ = oracle.chol32_block(Bn, nb=8)
+    np.testing.assert_array_equal(L1, L2)
+
+
+def test_chol32_apply_is_the_two_triangular_solves():
+    from scipy.linalg import solve_triangular
+
+    n = 150
+    A = _spd32(n, 140)
+    L, _ = oracle.chol32_block(A, nb=32)
+    L64 = L.astype(np.float64)
+    v = np.random.default_rng(141).standard_normal(n)
+    z = oracle.chol32_apply(L, v)
+    ref = solve_triangular(L64.T, solve_triangular(L64, v, lower=True), lower=False)
+    np.testing.assert_allclose(z, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_cg_ir_chol_exact_preconditioner_and_special_cases():
+    n = 24
+    _, A = _exact_chol_system(n, 150)
+    xs = np.random.default_rng(151).standard_normal(n)
+    b = A @ xs
+    # M = A exactly: the preconditioned residual z = A^-1 r makes the first
+    # PCG step exact, and the first correction meets binary64 accuracy
+    x, info = oracle.cg_ir_chol(A, b, tol=1e-14)
+    assert info["status_name"] == "ok" and info["outer_iters"] == 1 and info["inner_iters"] == 1
+    assert _rel(x, xs) <= np.linalg.cond(A) * 2.0 ** -52
+    x, info = oracle.cg_ir_chol(A, np.zeros(n), x0=np.ones(n), tol=1e-12)
+    assert info["status_name"] == "ok" and info["outer_iters"] == 0 and not x.any()
+    S = A.copy()
+    S[3, 3] = -5.0
+    _, info = oracle.cg_ir_chol(S, b, tol=1e-12)
+    assert info["status_name"] == "breakdown"
+
+
+def test_cg_ir_chol_converges_in_few_steps_at_high_condition():
+    p = spd_problem(300, 1e6, seed=2, config_id=2)
+    _, ic = oracle.cg(p.A, p.b, tol=1e-10, max_iter=300)
+    assert ic["status_name"] == "maxiter"
+    x, info = oracle.cg_ir_chol(p.A, p.b, tol=1e-12)
+    assert info["status_name"] == "ok" and info["outer_iters"] <= 5, info
+    assert info["inner_iters"] <= 60, info
+    assert oracle.metrics(p.A, p.b, x)["eta_inf"] <= 1e-12
+    xs = np.linalg.solve(p.A, p.b)
+    assert np.linalg.norm(x - xs) <= 1e6 * 1e-12 * 10 * np.linalg.norm(xs)
