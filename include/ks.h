@@ -291,6 +291,20 @@ int ks_symv(int32_t n, int64_t lda, const double *d_A, const double *d_x, double
 int ks_symv_f32(int32_t n, int64_t lda, const float *d_A, const float *d_x, float *d_y,
                 void *d_ws, size_t ws_bytes, void *stream);
 
+/* ks_symv without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): it calls no allocating routine.  The tile partials
+ * go to a fixed device array the library holds on every GPU it runs on until
+ * the process ends (sized for n <= KS_SYMV_NOALLOC_MAX_N: 33.8 MB); a larger
+ * n returns KS_ETOOLARGE before any device call.  Same kernels as ks_symv, so
+ * the same y bit for bit.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other host threads) race and must
+ * be serialized by the caller.  Argument rules and errors otherwise as
+ * ks_symv.  Enqueued on `stream`. */
+#define KS_SYMV_NOALLOC_MAX_N 32768
+int ks_symv_noalloc(int32_t n, int64_t lda, const double *d_A, const double *d_x, double *d_y,
+                    void *stream);
+
 /* Binary32 block LU with partial pivoting (the direct-methods section's block
  * algorithm, column blocks of 16; the factorization GMRES-IR uses): d_LU
  * (n x lda_lu floats, row-major, lda_lu >= n) receives the binary32 rounding

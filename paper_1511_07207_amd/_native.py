@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfi
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
            "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
-           "ks_symv_workspace_bytes", "ks_symv", "ks_symv_f32", "ks_lu32_factor", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
+           "ks_symv_workspace_bytes", "ks_symv", "ks_symv_f32", "ks_symv_noalloc", "ks_lu32_factor", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
            "ks_server_step", "ks_server_poll", "ks_server_stats", "ks_server_free")
 
 
@@ -120,6 +120,8 @@ def lib() -> ctypes.CDLL:
         L.ks_symv.restype = ctypes.c_int
         L.ks_symv_f32.argtypes = [i32, i64, vp, vp, vp, vp, sz, vp]
         L.ks_symv_f32.restype = ctypes.c_int
+        L.ks_symv_noalloc.argtypes = [i32, i64, vp, vp, vp, vp]
+        L.ks_symv_noalloc.restype = ctypes.c_int
         L.ks_lu32_factor.argtypes = [i32, i64, vp, i64, vp, vp, ctypes.POINTER(i32), vp]
         L.ks_lu32_factor.restype = ctypes.c_int
         L.ks_convert.argtypes = [i32, i64, vp, i32, i64, vp, vp]

@@ -270,6 +270,21 @@ def symv(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
     return y
 
 
+def symv_noalloc(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
+                 n: int | None = None) -> torch.Tensor:
+    """y = A x for symmetric float64 A from its lower triangle, with the tile
+    partials in the library's fixed device array instead of a workspace
+    (n <= KS_SYMV_NOALLOC_MAX_N; calls on one GPU must not overlap)."""
+    if A.dtype != torch.float64:
+        raise TypeError("symv_noalloc: A must be float64")
+    n = A.shape[0] if n is None else n
+    if y is None:
+        y = torch.empty(n, dtype=A.dtype, device=A.device)
+    N.check(N.lib().ks_symv_noalloc(int(n), int(A.stride(0)), _ptr(A), _ptr(x), _ptr(y),
+                                    _stream_handle()), "ks_symv_noalloc")
+    return y
+
+
 def lu32_factor(A: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor, int]:
     """Binary32 block LU with partial pivoting of a float64 matrix.
     Returns (LU float32 n x n, piv int32, info)."""

@@ -178,3 +178,17 @@ def test_symmetric_flag_and_symv_on_host():
     assert L.ks_params_init(ctypes.byref(q), 100, N.KS_GMRES) == 0
     q.flags = N.KS_FLAG_SYMMETRIC
     assert L.ks_workspace_bytes(ctypes.byref(q), ctypes.byref(sz)) == N.KS_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_symv_noalloc_limits_on_host():
+    """The fixed-array product refuses an order beyond its array and bad
+    arguments before any device call."""
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    assert L.ks_symv_noalloc(32769, 32769, 16, 16, 16, None) == N.KS_ETOOLARGE
+    assert L.ks_symv_noalloc(0, 1, 16, 16, 16, None) == N.KS_EINVAL
+    assert L.ks_symv_noalloc(100, 99, 16, 16, 16, None) == N.KS_EINVAL
+    assert L.ks_symv_noalloc(100, 100, None, 16, 16, None) == N.KS_EINVAL
+    assert L.ks_symv_noalloc(100, 101, 16, 16, 16, None) == N.KS_EINVAL  # rows not 16-byte aligned
