@@ -180,7 +180,9 @@ def _timed(fn):
 
 
 def leg_c1(dev):
-    """Plain CG, n = 512, kappa = 1e3, tol 1e-10, max 512 iterations."""
+    """Plain CG, n = 512, kappa = 1e3, tol 1e-10, max 512 iterations: the
+    persistent form (one cooperative launch per solve) and, beside it, one
+    launch per iteration (same iterates)."""
     import torch
 
     from paper_1511_07207_amd import krylov
@@ -189,19 +191,26 @@ def leg_c1(dev):
     p = spd_problem(512, 1e3, seed=0, config_id=0)
     A = torch.from_numpy(p.A).to(dev)
     b = torch.from_numpy(p.b).to(dev)
-    s = krylov.Solver(A, method="cg", tol=1e-10, max_iter=512)
-    x = torch.zeros(512, dtype=torch.float64, device=dev)
-    s.solve(b, out=x.zero_())
-    lat, its = [], []
-    for _ in range(30):
-        (_, info), dt = _timed(lambda: s.solve(b, out=x.zero_()))
-        lat.append(dt * 1e3)
-        its.append(info["iters"])
-    s.close()
-    return {"n": 512, "kappa": 1e3, "iters": its[-1], "status": info["status_name"],
-            "rel_res": info["rel_res"], "solves_per_s": round(1e3 / statistics.mean(lat), 2),
-            "p50_ms": round(_pct(lat, 0.5), 3), "p99_ms": round(_pct(lat, 0.99), 3),
-            "us_per_iteration": round(1e3 * statistics.median(lat) / its[-1], 2)}
+    out = {"n": 512, "kappa": 1e3}
+    for persist in (True, False):
+        s = krylov.Solver(A, method="cg", tol=1e-10, max_iter=512, persist=persist)
+        x = torch.zeros(512, dtype=torch.float64, device=dev)
+        s.solve(b, out=x.zero_())
+        lat, its = [], []
+        for _ in range(50):
+            (_, info), dt = _timed(lambda: s.solve(b, out=x.zero_()))
+            lat.append(dt * 1e3)
+            its.append(info["iters"])
+        s.close()
+        rec = {"iters": its[-1], "status": info["status_name"], "rel_res": info["rel_res"],
+               "solves_per_s": round(1e3 / statistics.mean(lat), 2),
+               "p50_ms": round(_pct(lat, 0.5), 3), "p99_ms": round(_pct(lat, 0.99), 3),
+               "us_per_iteration": round(1e3 * statistics.median(lat) / its[-1], 2)}
+        if persist:
+            out.update(rec)
+        else:
+            out["one_launch_per_iteration"] = rec
+    return out
 
 
 def _solve_timed(solver, b, x, reps_fast=3, fast_s=1.0):
@@ -236,7 +245,7 @@ def leg_c3sweep(dev, n, spd_form="qr"):
             if kind == "spd_cg":
                 prob = spd_problem(n, kap, seed=0, config_id=2, backend="torch", device="cuda",
                                    q_form=spd_form)
-                keys = ("fp64_sym", "fp32_sym", "bf16")
+                keys = ("fp64_sym", "fp32_sym", "bf16", "chol32")
             else:
                 prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch",
                                             device="cuda")
@@ -254,14 +263,25 @@ def leg_c3sweep(dev, n, spd_form="qr"):
                     kw["stop_backward"] = True
                 else:
                     kw["precision"] = prec
+                if prec == "chol32":
+                    kw["symmetric"] = False
+                    kw["max_iter"] = 2000
+                torch.cuda.synchronize()
+                tc0 = time.perf_counter()
                 solver = krylov.Solver(prob.A, **kw)
+                torch.cuda.synchronize()
+                create_ms = (time.perf_counter() - tc0) * 1e3
                 info, dt, reps = _solve_timed(solver, prob.b, x)
                 r = {"status": info["status_name"], "solve_ms": round(dt * 1e3, 2),
                      "solves_per_s": round(1.0 / dt, 4), "timed_solves": reps,
                      "iters": info["iters"], "outer": info["outer_iters"],
                      "precision_used": info["precision_used"], "eta_inf": info["backward_err"],
                      "fwd_err_vs_x_true": float((x - prob.x_true).norm() / prob.x_true.norm())}
-                if info["gemv_calls"] and info["precision_used"] == prec:
+                if prec == "chol32":
+                    # the binary32 block Cholesky in ks_create: n^3 / 3 flops
+                    r["factor_ms"] = round(create_ms, 2)
+                    r["factor_tflops"] = round(n ** 3 / 3.0 / (create_ms * 1e-3) / 1e12, 2)
+                if info["gemv_calls"] and info["precision_used"] == prec and prec != "chol32":
                     e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
                     ab = e * n * (n + 1) / 2 if sym else e * n * n
                     r["gemv_gbs"] = round(ab / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)

@@ -85,6 +85,16 @@ extern "C" {
                             block algorithm) computed in ks_create; method
                             KS_GMRES, nrhs 1, n <= 4096.  A factorization with a
                             zero pivot makes ks_solve return KS_BREAKDOWN     */
+#define KS_IR_CHOL32 4   /* CG-IR: binary64 refinement around preconditioned CG
+                            in binary64 with M = L L^T, L the binary32 block
+                            Cholesky factor of A (the direct-methods section's
+                            Cholesky relations, computed in ks_create with the
+                            trailing updates on the matrix cores); method
+                            KS_CG, nrhs 1, no KS_FLAG_SYMMETRIC.  Each inner
+                            solve starts from d = 0 and stops at relative
+                            residual inner_tol or max_iter products; a
+                            non-positive pivot makes ks_solve return
+                            KS_BREAKDOWN                                        */
 
 /* element types for the kernel-level entry points */
 #define KS_DT_F64 0
@@ -111,6 +121,12 @@ extern "C" {
                                the general one).  A must still hold the whole
                                symmetric matrix: the true residual and
                                ||A||_inf read both triangles */
+#define KS_FLAG_NO_PERSIST 8 /* binary64 CG at n <= 1024 (not stopping on the
+                                backward error) normally runs every iteration
+                                of a polling interval in one cooperative
+                                launch with a grid barrier between iterations;
+                                this flag runs one launch per iteration instead
+                                (the same iterates bit for bit) */
 
 typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 
@@ -316,6 +332,18 @@ int ks_symv_noalloc(int32_t n, int64_t lda, const double *d_A, const double *d_x
  * factorization has finished on `stream`. */
 int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, float *d_LU,
                    int32_t *d_piv, int32_t *info, void *stream);
+
+/* Binary32 block Cholesky (the direct-methods section's Cholesky relations,
+ * column blocks of 64, trailing updates on the matrix cores; the
+ * factorization KS_IR_CHOL32 uses): d_L (n x ldl floats, row-major,
+ * ldl >= n, ldl a multiple of 4, 16-byte aligned) receives the binary32
+ * rounding of the symmetric A factored as L L^T, L on and below the diagonal
+ * and L^T strictly above it.  *info = 0, or 1 + the first column whose pivot
+ * is not positive (the factorization stops there; d_L is then partly
+ * factored).  Allocates and frees one device word; returns after the
+ * factorization has finished on `stream`. */
+int ks_chol32_factor(int32_t n, int64_t lda, const double *d_A, int64_t ldl, float *d_L,
+                     int32_t *info, void *stream);
 
 /* Convert an n x n binary64 matrix (lda_src) into dst_dtype (KS_DT_F32:
  * round to nearest even; KS_DT_BF16: round to binary32, then to bfloat16,

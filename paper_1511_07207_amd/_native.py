@@ -16,11 +16,12 @@ LIB_PATH = os.path.join(_HERE, "libks.so")
 KS_OK, KS_MAXITER, KS_BREAKDOWN, KS_STAGNATED, KS_NONFINITE = 0, 1, 2, 3, 4
 KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_EDEVICE, KS_ETOOLARGE = -1, -2, -3, -4, -5
 KS_CG, KS_GMRES, KS_BICGSTAB, KS_JACOBI, KS_GAUSS_SEIDEL = 0, 1, 2, 3, 4
-KS_FP64, KS_IR_FP32, KS_IR_BF16, KS_IR_LU32 = 0, 1, 2, 3
+KS_FP64, KS_IR_FP32, KS_IR_BF16, KS_IR_LU32, KS_IR_CHOL32 = 0, 1, 2, 3, 4
 KS_DT_F64, KS_DT_F32, KS_DT_BF16 = 0, 1, 2
 KS_FLAG_TIMING = 1
 KS_FLAG_STOP_BACKWARD = 2
 KS_FLAG_SYMMETRIC = 4
+KS_FLAG_NO_PERSIST = 8
 KS_MAX_RESTART = 128
 KS_MAX_NRHS = 64
 
@@ -30,7 +31,7 @@ STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfi
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
            "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
-           "ks_symv_workspace_bytes", "ks_symv", "ks_symv_f32", "ks_symv_noalloc", "ks_lu32_factor", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
+           "ks_symv_workspace_bytes", "ks_symv", "ks_symv_f32", "ks_symv_noalloc", "ks_lu32_factor", "ks_chol32_factor", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
            "ks_server_step", "ks_server_poll", "ks_server_stats", "ks_server_free")
 
 
@@ -124,6 +125,8 @@ def lib() -> ctypes.CDLL:
         L.ks_symv_noalloc.restype = ctypes.c_int
         L.ks_lu32_factor.argtypes = [i32, i64, vp, i64, vp, vp, ctypes.POINTER(i32), vp]
         L.ks_lu32_factor.restype = ctypes.c_int
+        L.ks_chol32_factor.argtypes = [i32, i64, vp, i64, vp, ctypes.POINTER(i32), vp]
+        L.ks_chol32_factor.restype = ctypes.c_int
         L.ks_convert.argtypes = [i32, i64, vp, i32, i64, vp, vp]
         L.ks_convert.restype = ctypes.c_int
         L.ks_read_ceiling.argtypes = [vp, sz, vp, vp]

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libks.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["ks_gemv.hip", "ks_vec.hip", "ks_symv.hip", "ks_symv32.hip", "ks_cgfused.hip", "ks_stationary.hip", "ks_lu.hip", "ks_mrhs.hip", "ks_batch.hip", "ks_noalloc.hip",
+SOURCES = ["ks_gemv.hip", "ks_vec.hip", "ks_symv.hip", "ks_symv32.hip", "ks_cgfused.hip", "ks_stationary.hip", "ks_lu.hip", "ks_chol.hip", "ks_mrhs.hip", "ks_batch.hip", "ks_noalloc.hip",
            "ks_host.cpp", "ks_server.cpp"]
 
 # Packed-FP32 instructions are switched off for all device code.

@@ -207,69 +207,98 @@ constexpr int FZ_SM_CH = FZ_SMALL_N / (2 * FZ_NT);   // 512-column chunks (2)
 static_assert(VEC_NT * VEC_EPT >= FZ_SMALL_N, "one r'r partial covers the whole vector");
 static_assert(FZ_SMALL_N / GemvShape<double>::ROWS <= 2 * FZ_NT, "two p'q partials per thread");
 
-__global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
-    int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x,
-    const double *__restrict__ rc, double *__restrict__ rn, const double *__restrict__ pc,
-    double *__restrict__ pn, const double *__restrict__ qc, double *__restrict__ qn, State *st,
-    const double *__restrict__ pgc, double *__restrict__ pgn, int cur, int max_iter) {
-    __shared__ double pnew[FZ_SMALL_N];
-    __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
-    const int nxt = 1 - cur;
+// A rows of the block (rows row0 .. row0 + 7), the columns rows_dot gives
+// thread t: 2t, 2t + 1, 2t + 512, 2t + 513, clamped into the matrix.
+typedef double fz_rows_t[FZ_ROWS][FZ_SM_CH][2];
+
+__device__ __forceinline__ void fz_load_rows(int n, int64_t lda, const double *__restrict__ A, int row0,
+                                             fz_rows_t &av) {
     const int t = threadIdx.x;
-    const bool lead = blockIdx.x == 0 && t == 0;
-    const int row0 = blockIdx.x * FZ_ROWS;
-    const int ngemv = gemv_blocks<double>(n);
-    // ---- all loads first
-    const double pg0 = pgc[min(t, ngemv - 1)];
-    const double pg1 = pgc[min(t + FZ_NT, ngemv - 1)];
-    double qv[FZ_SM_ELEM], rv[FZ_SM_ELEM], pv[FZ_SM_ELEM];
-#pragma unroll
-    for (int m = 0; m < FZ_SM_ELEM; ++m) {
-        const int i = min(t + m * FZ_NT, n - 1);
-        qv[m] = qc[i];
-        rv[m] = rc[i];
-        pv[m] = pc[i];
-    }
-    const int io = min(row0 + (t & (FZ_ROWS - 1)), n - 1);  // own row of threads t < FZ_ROWS
-    const double xo = x[io], po = pc[io], qo = qc[io], ro = rc[io];
-    // this launch's slot was written by the launch before (this one writes
-    // the other), so it is read with the other loads, not after the barrier
-    const double rho = st->fz_rho[cur];
-    const int iters = st->fz_iters[cur] + 1;
-    const int flags = st->fz_flags[cur];
-    const double thresh = st->thresh;  // fixed for the solve
-    double av[FZ_ROWS][FZ_SM_CH][2];
 #pragma unroll
     for (int r = 0; r < FZ_ROWS; ++r) {
         const double *rowp = A + (int64_t)min(row0 + r, n - 1) * lda;
 #pragma unroll
         for (int ch = 0; ch < FZ_SM_CH; ++ch)
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
-                av[r][ch][e] = rowp[min(2 * t + ch * 2 * FZ_NT + e, n - 1)];
+            for (int e = 0; e < 2; ++e) av[r][ch][e] = rowp[min(2 * t + ch * 2 * FZ_NT + e, n - 1)];
     }
+}
+
+// Loads and stores of what other blocks read or wrote: plain (COH = false,
+// across a launch boundary) or agent-scope relaxed atomics (COH = true: the
+// persistent launch, whose barrier has no cache writeback or invalidate).
+template <bool COH, typename T>
+__device__ __forceinline__ T fz_ld(const T *p) {
+    if constexpr (COH)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+template <bool COH, typename T>
+__device__ __forceinline__ void fz_st(T *p, T v) {
+    if constexpr (COH)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+// One iteration k (slot cur = k % 2) of the small-n fused CG on the block's
+// rows of A held in registers.  Returns true when the solve has stopped
+// (in this iteration or before): the block then wrote slot 1 - cur and,
+// from a live iteration, x and r of its rows, but no p, q or partials.
+template <bool COH>
+__device__ __forceinline__ bool fz_small_iteration(
+    int n, const fz_rows_t &av, double *__restrict__ x, const double *__restrict__ rc,
+    double *__restrict__ rn, const double *__restrict__ pc, double *__restrict__ pn,
+    const double *__restrict__ qc, double *__restrict__ qn, State *st, const double *__restrict__ pgc,
+    double *__restrict__ pgn, int cur, int max_iter, double *pnew, double *sm_sigma, double *sm_rho) {
+    const int nxt = 1 - cur;
+    const int t = threadIdx.x;
+    const bool lead = blockIdx.x == 0 && t == 0;
+    const int row0 = blockIdx.x * FZ_ROWS;
+    const int ngemv = gemv_blocks<double>(n);
+    // ---- all loads first
+    const double pg0 = fz_ld<COH>(&pgc[min(t, ngemv - 1)]);
+    const double pg1 = fz_ld<COH>(&pgc[min(t + FZ_NT, ngemv - 1)]);
+    double qv[FZ_SM_ELEM], rv[FZ_SM_ELEM], pv[FZ_SM_ELEM];
+#pragma unroll
+    for (int m = 0; m < FZ_SM_ELEM; ++m) {
+        const int i = min(t + m * FZ_NT, n - 1);
+        qv[m] = fz_ld<COH>(&qc[i]);
+        rv[m] = fz_ld<COH>(&rc[i]);
+        pv[m] = fz_ld<COH>(&pc[i]);
+    }
+    const int io = min(row0 + (t & (FZ_ROWS - 1)), n - 1);  // own row of threads t < FZ_ROWS
+    const double xo = fz_ld<COH>(&x[io]), po = fz_ld<COH>(&pc[io]), qo = fz_ld<COH>(&qc[io]),
+                 ro = fz_ld<COH>(&rc[io]);
+    // this iteration's slot was written by the iteration before (this one
+    // writes the other), so it is read with the other loads, not after the barrier
+    const double rho = fz_ld<COH>(&st->fz_rho[cur]);
+    const int iters = fz_ld<COH>(&st->fz_iters[cur]) + 1;
+    const int flags = fz_ld<COH>(&st->fz_flags[cur]);
+    const double thresh = st->thresh;  // fixed for the solve, written before the launch
     // ---- sigma, summed as reduce_partials_all sums the partials
     double sg = 0.0;
     if (t < ngemv) sg += pg0;
     if (t + FZ_NT < ngemv) sg += pg1;
     const double sigma = fz_sum_all(sg, sm_sigma);
     // the stop test comes after the barrier so that no load above is deferred
-    // behind it; a launch after the stop only copies its slot forward
+    // behind it; an iteration after the stop only copies its slot forward
     if (flags & F_STOP) {
         if (lead) {
-            st->fz_rho[nxt] = rho;
-            st->fz_iters[nxt] = iters - 1;
-            st->fz_flags[nxt] = flags;
+            fz_st<COH>(&st->fz_rho[nxt], rho);
+            fz_st<COH>(&st->fz_iters[nxt], iters - 1);
+            fz_st<COH>(&st->fz_flags[nxt], flags);
         }
-        return;
+        return true;
     }
     if (!(finite_d(sigma) && sigma > 0.0)) {
         if (lead) {
-            st->fz_rho[nxt] = rho;
-            st->fz_iters[nxt] = iters;
-            st->fz_flags[nxt] = flags | F_STOP | (finite_d(sigma) ? F_BREAK : F_NONFIN);
+            fz_st<COH>(&st->fz_rho[nxt], rho);
+            fz_st<COH>(&st->fz_iters[nxt], iters);
+            fz_st<COH>(&st->fz_flags[nxt], flags | F_STOP | (finite_d(sigma) ? F_BREAK : F_NONFIN));
         }
-        return;
+        return true;
     }
     const double a = rho / sigma;
     // ---- r' and r'r (one update-kernel partial holds the whole vector, its
@@ -282,8 +311,8 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         if (t + m * FZ_NT < n) s2 += rr[m] * rr[m];
     }
     if (t < FZ_ROWS && row0 + t < n) {
-        x[io] = fma(a, po, xo);
-        rn[io] = fma(-a, qo, ro);
+        fz_st<COH>(&x[io], fma(a, po, xo));
+        fz_st<COH>(&rn[io], fma(-a, qo, ro));
     }
     // the unfused path sums this block sum as its single partial, which
     // returns it unchanged (r'r >= 0)
@@ -297,11 +326,11 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         stop = F_MAXIT | F_STOP;
     if (stop) {
         if (lead) {
-            st->fz_rho[nxt] = rho;
-            st->fz_iters[nxt] = iters;
-            st->fz_flags[nxt] = flags | stop;
+            fz_st<COH>(&st->fz_rho[nxt], rho);
+            fz_st<COH>(&st->fz_iters[nxt], iters);
+            fz_st<COH>(&st->fz_flags[nxt], flags | stop);
         }
-        return;
+        return true;
     }
     const double beta = rho_new / rho;
 #pragma unroll
@@ -310,7 +339,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         if (i < n) pnew[i] = fma(beta, pv[m], rr[m]);
     }
     __syncthreads();
-    if (t < FZ_ROWS && row0 + t < n) pn[io] = pnew[io];
+    if (t < FZ_ROWS && row0 + t < n) fz_st<COH>(&pn[io], pnew[io]);
     // ---- q' = A p' for the block's rows, each row's columns in rows_dot's order
     double acc[FZ_ROWS];
 #pragma unroll
@@ -331,7 +360,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
         const int row = row0 + t;
         double contrib = 0.0;
         if (t < FZ_ROWS && row < n) {
-            qn[row] = out;
+            fz_st<COH>(&qn[row], out);
             contrib = pnew[row] * out;
         }
 #pragma unroll
@@ -339,14 +368,122 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
             const bool mine = (t >> 1) == j;
             const double ts = wave_sum(mine ? contrib : 0.0);
             const int gb = row0 / 2 + j;
-            if (t == 0 && 2 * gb < n) pgn[gb] = ts;
+            if (t == 0 && 2 * gb < n) fz_st<COH>(&pgn[gb], ts);
         }
     }
     if (lead) {
-        st->fz_rho[nxt] = rho_new;
-        st->fz_iters[nxt] = iters;
-        st->fz_flags[nxt] = flags;
+        fz_st<COH>(&st->fz_rho[nxt], rho_new);
+        fz_st<COH>(&st->fz_iters[nxt], iters);
+        fz_st<COH>(&st->fz_flags[nxt], flags);
     }
+    return false;
+}
+
+__global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
+    int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x,
+    const double *__restrict__ rc, double *__restrict__ rn, const double *__restrict__ pc,
+    double *__restrict__ pn, const double *__restrict__ qc, double *__restrict__ qn, State *st,
+    const double *__restrict__ pgc, double *__restrict__ pgn, int cur, int max_iter) {
+    __shared__ double pnew[FZ_SMALL_N];
+    __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
+    fz_rows_t av;
+    fz_load_rows(n, lda, A, blockIdx.x * FZ_ROWS, av);
+    (void)fz_small_iteration<false>(n, av, x, rc, rn, pc, pn, qc, qn, st, pgc, pgn, cur, max_iter, pnew,
+                             sm_sigma, sm_rho);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form (n <= FZ_SMALL_N): one cooperative launch runs up to
+// `nsteps` iterations of fz_small_iteration, the blocks meeting at a grid
+// barrier between iterations instead of at a launch boundary.  The block's
+// eight rows of A are read once per launch and stay in registers.  Each
+// iteration reads and writes exactly what one fz_step_small launch does, so
+// the iterates, the slots and the vectors are bit for bit those of the
+// per-launch path after the same number of iterations.
+//
+// Barrier without cache maintenance.  An agent-scope release or acquire
+// fence on gfx950 writes back or invalidates the XCD's L2 (buffer_wbl2 /
+// buffer_inv), and measured at about 0.13 us per block per barrier (8.5 us
+// for 64 blocks) it made the persistent form slower than a launch per
+// iteration.  Here everything one block writes for another (its rows of x,
+// r, p, q, its p'q partials, block 0's slot) is stored with agent-scope
+// relaxed atomics (coherent at device scope) and read back the same way;
+// block b then waits for its own stores to complete (vmcnt(0)), meets its
+// threads at a block barrier and publishes the number of iterations it has
+// finished in bar[b]; thread t < gridDim.x polls bar[t] until it reaches
+// that number.  So no block starts iteration k + 1 before every block's
+// writes of iteration k are visible to it.  The two copies of every vector
+// and partial array alternate by iteration, so a block that runs ahead never
+// overwrites what a slower block still reads.  All blocks take the same stop
+// decision in the same iteration (they reduce the same values in the same
+// order), so none waits for a block that has left.  Every wait is bounded:
+// past `spin_limit` polls the block records FZ_SYNC_TIMEOUT in st->sync_fail
+// and leaves (the host reports an error); co-residency of the grid is
+// guaranteed by the cooperative launch.
+constexpr int FZ_SYNC_TIMEOUT = 1;
+constexpr int FZ_WAIT_VMEM = 0x0F70;  // s_waitcnt vmcnt(0) (gfx9 encoding: expcnt, lgkmcnt not waited)
+
+__device__ __forceinline__ bool fz_grid_barrier(uint32_t *bar, uint32_t done, uint32_t spin_limit) {
+    __builtin_amdgcn_s_waitcnt(FZ_WAIT_VMEM);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&bar[blockIdx.x * FZ_BAR_STRIDE], done, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    int late = 0;
+    if (threadIdx.x < gridDim.x) {
+        uint32_t polls = 0;
+        while (__hip_atomic_load(&bar[threadIdx.x * FZ_BAR_STRIDE], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) < done) {
+            if (++polls > spin_limit) {
+                late = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    late = __syncthreads_or(late);
+    return late == 0;
+}
+
+__global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
+    int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x, double *r0, double *r1,
+    double *p0, double *p1, double *q0, double *q1, State *st, double *pg0, double *pg1, int cur0,
+    int nsteps, int max_iter, uint32_t *bar, uint32_t spin_limit) {
+    __shared__ double pnew[FZ_SMALL_N];
+    __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
+    fz_rows_t av;
+    fz_load_rows(n, lda, A, blockIdx.x * FZ_ROWS, av);
+    int cur = cur0;
+    bool stopped = false;
+    for (int k = 0; k < nsteps; ++k) {
+        double *rc = cur ? r1 : r0, *rn = cur ? r0 : r1;
+        double *pc = cur ? p1 : p0, *pn = cur ? p0 : p1;
+        double *qc = cur ? q1 : q0, *qn = cur ? q0 : q1;
+        double *pgc = cur ? pg1 : pg0, *pgn = cur ? pg0 : pg1;
+        stopped = fz_small_iteration<true>(n, av, x, rc, rn, pc, pn, qc, qn, st, pgc, pgn, cur,
+                                           max_iter, pnew, sm_sigma, sm_rho);
+        cur = 1 - cur;
+        if (stopped || k + 1 == nsteps) break;
+        if (!fz_grid_barrier(bar, (uint32_t)(k + 1), spin_limit)) {
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
+    // the per-launch path would copy the final slot forward in the launches
+    // after a stop: the host publishes slot (cur0 + nsteps) % 2, so both
+    // slots hold the final values (block 0 wrote the one read here)
+    if (stopped && blockIdx.x == 0 && threadIdx.x == 0) {
+        st->fz_rho[1 - cur] = st->fz_rho[cur];
+        st->fz_iters[1 - cur] = st->fz_iters[cur];
+        st->fz_flags[1 - cur] = st->fz_flags[cur];
+    }
+}
+
+__global__ void fz_bar_reset_kernel(uint32_t *bar, int count, State *st) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) bar[i] = 0u;
+    if (threadIdx.x == 0) st->sync_fail = 0;
 }
 
 __global__ void fz_publish_kernel(State *st, int which) {
@@ -380,6 +517,28 @@ hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double
                                                       vec[2 + nxt], vec[4 + cur], vec[4 + nxt], st,
                                                       pg[cur], pg[nxt], cur, max_iter);
     return hipGetLastError();
+}
+
+int fz_persist_max_n() { return FZ_SMALL_N; }
+
+size_t fz_bar_words(int n) { return (size_t)fz_blocks(n) * FZ_BAR_STRIDE; }
+
+hipError_t launch_fz_persist(int n, int64_t lda, const double *A, double *x, double *const vec[6],
+                             State *st, double *const pg[2], int cur, int nsteps, int max_iter,
+                             uint32_t *bar, uint32_t spin_limit, hipStream_t s) {
+    if (n > FZ_SMALL_N || (cur != 0 && cur != 1) || nsteps < 1) return hipErrorInvalidValue;
+    const int G = fz_blocks(n);
+    if (G > FZ_NT) return hipErrorInvalidValue;  // one waiting thread per block
+    const int words = (int)fz_bar_words(n);
+    if (words > FZ_BAR_MAX_WORDS) return hipErrorInvalidValue;
+    fz_bar_reset_kernel<<<1, 256, 0, s>>>(bar, words, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double *r0 = vec[0], *r1 = vec[1], *p0 = vec[2], *p1 = vec[3], *q0 = vec[4], *q1 = vec[5];
+    double *pg0 = pg[0], *pg1 = pg[1];
+    void *args[] = {&n, &lda, &A, &x, &r0, &r1, &p0, &p1, &q0, &q1, &st, &pg0, &pg1, &cur, &nsteps,
+                    &max_iter, &bar, &spin_limit};
+    return hipLaunchCooperativeKernel((const void *)fz_persist_kernel, dim3(G), dim3(FZ_NT), args, 0, s);
 }
 
 hipError_t launch_fz_publish(State *st, int which, hipStream_t s) {

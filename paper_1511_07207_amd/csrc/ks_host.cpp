@@ -48,10 +48,12 @@ struct ks_solver {
     float *v32 = nullptr;
     double *sy = nullptr;     // tile partials of the symmetric product (KS_FLAG_SYMMETRIC)
     bool fz = false;          // fused small-n binary64 CG (one launch per iteration)
+    uint32_t *fzbar = nullptr;  // grid-barrier flags of its persistent launch
     // GMRES-IR: the binary32 LU in A_low, its pivots, permutation, and the
     // first zero pivot's column + 1 (0: nonsingular)
     int *lu_piv = nullptr, *lu_perm = nullptr, *lu_info = nullptr;
     int lu_sing = 0;
+    int chol_notpd = 0;  // CG-IR: 1 + the first column with a non-positive pivot
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> tev;  // timing event pairs of A*v launches
     int tev_used = 0;
@@ -141,6 +143,10 @@ int poll_chunk(const ks_solver *s) {
 // return at once, while a poll costs a host round trip, so the chunk between
 // polls is 32 iterations at every n (measured at n = 16384: CG 164.0 ms with
 // 8, 162.5 ms with 32, no better beyond; GMRES(30) unchanged)
+// polls of one bounded grid-barrier wait of a persistent launch (each a
+// memory round trip and a short sleep: about a second in all)
+constexpr uint32_t FZ_SPIN_LIMIT = 1u << 20;
+
 int poll_chunk_krylov(const ks_solver *s) {
     return s->p.poll_every > 0 ? s->p.poll_every : 32;
 }
@@ -208,20 +214,32 @@ int run_cg(ks_solver *s, State *st, int state_index, const TA *A, int64_t lda, c
                 double *const vec[6] = {r, s->vec64(3), p, s->vec64(4), q, s->vec64(5)};
                 double *const pg[2] = {s->P.g, s->P.g + ng};
                 HIPCHK(launch_fz_start(n, lda, A, p, q, st, pg[0], sm));
+                // n <= fz_persist_max_n(): the iterations up to the stop (or
+                // max_iter) in one cooperative launch, grid barriers between them
+                const bool persist = n <= fz_persist_max_n() && s->fzbar &&
+                                     !(s->p.flags & KS_FLAG_NO_PERSIST);
                 int k = 0;
                 while (!done) {
                     const int it0 = h->iters;
-                    const int chunk = std::max(1, std::min(poll_chunk_krylov(s), max_iter - it0));
-                    for (int c = 0; c < chunk; ++c, ++k) {
-                        hipEvent_t e0, e1;
-                        if ((rc = timing_pair(s, &e0, &e1))) return rc;
-                        if (e0) HIPCHK(hipEventRecord(e0, sm));
-                        HIPCHK(launch_fz_step(n, lda, A, x, vec, st, pg, k & 1, max_iter, sm));
-                        if (e1) HIPCHK(hipEventRecord(e1, sm));
+                    if (persist) {
+                        const int steps = std::max(1, max_iter - it0);
+                        HIPCHK(launch_fz_persist(n, lda, A, x, vec, st, pg, k & 1, steps, max_iter,
+                                                 s->fzbar, FZ_SPIN_LIMIT, sm));
+                        k += steps;
+                    } else {
+                        const int chunk = std::max(1, std::min(poll_chunk_krylov(s), max_iter - it0));
+                        for (int c = 0; c < chunk; ++c, ++k) {
+                            hipEvent_t e0, e1;
+                            if ((rc = timing_pair(s, &e0, &e1))) return rc;
+                            if (e0) HIPCHK(hipEventRecord(e0, sm));
+                            HIPCHK(launch_fz_step(n, lda, A, x, vec, st, pg, k & 1, max_iter, sm));
+                            if (e1) HIPCHK(hipEventRecord(e1, sm));
+                        }
                     }
                     HIPCHK(launch_fz_publish(st, k & 1, sm));
                     if (outer) HIPCHK((launch_residual<TA, T>(n, lda, A, b, x, r, st, s->P, 1, sm)));
                     if ((rc = sync_state(s))) return rc;
+                    if (h->sync_fail) return KS_EHIP;
                     if ((rc = timed_collect(s, h->iters - it0))) return rc;
                     done = (h->flags & F_STOP) != 0;
                 }
@@ -705,6 +723,74 @@ int run_gmres_lu(ks_solver *s, const double *rhs, double *d, double tol, int max
     return KS_OK;
 }
 
+// ------------------------------------------------------------- CG-IR
+// The binary32 block Cholesky factor of A (in A_low: L below, L^T above).
+int chol_setup(ks_solver *s) {
+    hipStream_t sm = s->stream;
+    int *info = (int *)(s->ws + s->L.lu_off);
+    HIPCHK(hipMemsetAsync(info, 0, sizeof(int), sm));
+    HIPCHK(launch_chol_factor(s->n, s->L.lda_low, (float *)s->A_low, info, sm));
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    s->chol_notpd = h;
+    return KS_OK;
+}
+
+// Inner solve of CG-IR: CG in binary64 on A d = rhs from d = 0,
+// preconditioned by M = L L^T (binary32 factor), stopping at
+// ||rhs - A d||_2 <= tol ||rhs||_2 on the recursive residual or after
+// max_iter products.  The state is polled after every iteration: the
+// substitutions of an iteration launched after the stop would still run.
+int run_pcg_chol(ks_solver *s, const double *rhs, double *d, double tol, int max_iter, Outcome *out) {
+    const int n = s->n, nv = s->L.nv64;
+    hipStream_t sm = s->stream;
+    State *st = s->st_in;
+    const float *L = (const float *)s->A_low;
+    const int64_t ldl = s->L.lda_low;
+    double *r = s->vec64(0), *p = s->vec64(1), *q = s->vec64(2), *z = s->vec64(nv - 2);
+    double *rz_part = s->P.w;
+    HIPCHK(launch_fill<double>(n, d, 0.0, sm));
+    HIPCHK(launch_vec_stats<double>(n, rhs, tol, st, sm, 0));
+    HIPCHK(launch_chol_apply(n, ldl, L, rhs, z, sm));
+    HIPCHK(launch_pcg_dot(n, rhs, z, st, rz_part, sm));
+    HIPCHK(launch_cg_begin<double>(n, rhs, r, st, sm));  // r = rhs, flags cleared
+    HIPCHK(launch_pcg_begin(n, z, p, st, rz_part, sm));
+    int rc = sync_state(s);
+    if (rc) return rc;
+    const State *h = &s->host[1];
+    if (h->bnorm == 0.0) {
+        out->status = KS_OK;
+        out->iters = 0;
+        return KS_OK;
+    }
+    if (h->flags & F_TRUE_NONFIN) {
+        out->status = KS_NONFINITE;
+        out->iters = 0;
+        return KS_OK;
+    }
+    while (!(h->flags & F_STOP)) {
+        if (h->iters >= max_iter) break;
+        HIPCHK((launch_cg_matvec<double, double>(n, s->lda, s->A, p, q, st, s->P, sm)));
+        HIPCHK(launch_cg_update<double>(n, d, r, p, q, st, s->P, gemv_blocks<double>(n), sm));
+        HIPCHK(launch_chol_apply(n, ldl, L, r, z, sm));
+        HIPCHK(launch_pcg_dot(n, r, z, st, rz_part, sm));
+        HIPCHK(launch_pcg_pupdate(n, z, p, st, s->P.v, rz_part, max_iter, sm));
+        if ((rc = sync_state(s))) return rc;
+    }
+    const int f = h->flags;
+    if (f & F_NONFIN)
+        out->status = KS_NONFINITE;
+    else if (f & F_BREAK)
+        out->status = KS_BREAKDOWN;
+    else if (f & F_CONV)
+        out->status = KS_OK;
+    else
+        out->status = KS_MAXITER;
+    out->iters = h->iters;
+    return KS_OK;
+}
+
 // Metrics of the returned x from the State the solve left behind: every exit
 // path of the drivers ends with a true-residual kernel and a sync, so the
 // host mirror holds ||b||, ||r|| and the infinity norms of r, x and b.
@@ -986,8 +1072,8 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
     }
     const double binf = h->binf, bnorm = h->bnorm;
     s->anorm_inf = h->anorm_inf;
-    if (prec == KS_IR_LU32 && s->lu_sing) {
-        // the binary32 factorization met a zero pivot
+    if ((prec == KS_IR_LU32 && s->lu_sing) || (prec == KS_IR_CHOL32 && s->chol_notpd)) {
+        // the binary32 factorization met a zero (LU) or non-positive (Cholesky) pivot
         info->rel_res = h->res / bnorm;
         const double den0 = s->anorm_inf * h->xinf + binf;
         info->backward_err = den0 > 0.0 ? h->resinf / den0 : h->resinf;
@@ -1043,6 +1129,24 @@ int solve_ir(ks_solver *s, const double *b, double *x, ks_info *info, Outcome *o
             Outcome oi;
             double *dl = s->vec64(s->L.nv64 - 3);
             if ((rc = run_gmres_lu(s, r64, dl, s->p.inner_tol, s->p.max_iter, &oi))) return rc;
+            total_iters += oi.iters;
+            ++outer;
+            if (oi.status == KS_BREAKDOWN || oi.status == KS_NONFINITE) {
+                prec = KS_FP64;
+                bad = 0;
+                eta_prev = INFINITY;
+                continue;
+            }
+            HIPCHK(launch_lu_xupdate(n, x, dl, sm));
+            HIPCHK((launch_residual<double, double>(n, s->lda, s->A, b, x, r64, s->st, s->P, 0, sm)));
+            if ((rc = sync_state(s))) return rc;
+            continue;
+        }
+        if (prec == KS_IR_CHOL32) {
+            // CG-IR: correction from the preconditioned CG in binary64
+            Outcome oi;
+            double *dl = s->vec64(s->L.nv64 - 3);
+            if ((rc = run_pcg_chol(s, r64, dl, s->p.inner_tol, s->p.max_iter, &oi))) return rc;
             total_iters += oi.iters;
             ++outer;
             if (oi.status == KS_BREAKDOWN || oi.status == KS_NONFINITE) {
@@ -1203,6 +1307,7 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
         if (L.sy_bytes) s->sy = (double *)(s->ws + L.sy_off);
         // the layout holds the second copies of r, p, q for the fused CG
         s->fz = p->method == KS_CG && p->nrhs == 1 && p->n <= FZ_MAX_N && !s->sy && L.nv64 >= 6;
+        if (s->fz && L.bar_off) s->fzbar = (uint32_t *)(s->ws + L.bar_off);
     }
     if (p->nrhs > 1) {
         s->mr64 = (double *)(s->ws + L.mr_off);
@@ -1246,6 +1351,10 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
             ks_free(s);
             return KS_EHIP;
         }
+    }
+    if (p->precision == KS_IR_CHOL32 && (rc = chol_setup(s))) {
+        ks_free(s);
+        return rc;
     }
     if (p->precision == KS_IR_LU32 && (rc = lu_setup(s))) {
         ks_free(s);
@@ -1417,6 +1526,27 @@ int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, fl
     hipError_t e = hipMemsetAsync(dinfo, 0, sizeof(int), sm);
     if (e == hipSuccess) e = launch_convert(n, lda, d_A, KS_DT_F32, lda_lu, d_LU, sm);
     if (e == hipSuccess) e = launch_lu_factor(n, lda_lu, d_LU, d_piv, dinfo, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, dinfo, sizeof(int), hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    const hipError_t ef = hipFree(dinfo);
+    if (e != hipSuccess || ef != hipSuccess) return KS_EHIP;
+    *info = h;
+    return KS_OK;
+}
+
+int ks_chol32_factor(int32_t n, int64_t lda, const double *d_A, int64_t ldl, float *d_L,
+                     int32_t *info, void *stream) {
+    if (n < 1 || lda < n || ldl < n || ldl % 4 || !d_A || !d_L || !info || (uintptr_t)d_L % 16)
+        return KS_EINVAL;
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t sm = (hipStream_t)stream;
+    int *dinfo = nullptr;
+    HIPCHK(hipMalloc((void **)&dinfo, sizeof(int)));
+    int h = 0;
+    hipError_t e = hipMemsetAsync(dinfo, 0, sizeof(int), sm);
+    if (e == hipSuccess) e = launch_convert(n, lda, d_A, KS_DT_F32, ldl, d_L, sm);
+    if (e == hipSuccess) e = launch_chol_factor(n, ldl, d_L, dinfo, sm);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, dinfo, sizeof(int), hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     const hipError_t ef = hipFree(dinfo);

@@ -50,6 +50,7 @@ struct alignas(256) State {
     double fz_rho[2];
     int32_t fz_iters[2];
     int32_t fz_flags[2];
+    int32_t sync_fail;  // persistent kernels: a bounded grid-barrier wait gave up
 };
 static_assert(sizeof(State) == 256, "one 256-byte State per solve");
 
@@ -207,6 +208,25 @@ hipError_t launch_lu_res_finish(int n, State *st, const double *partial, hipStre
 // x += d
 hipError_t launch_lu_xupdate(int n, double *x, const double *d, hipStream_t s);
 
+// Binary32 block Cholesky (CG-IR preconditioner): column blocks of CH_NB,
+// the trailing update on the matrix cores.  factor: L holds the binary32 A
+// on entry (both triangles), L in the lower triangle and L^T in the strict
+// upper one on return; info[0] = 1 + the first column with a non-positive
+// pivot (0 if none; must be 0 on entry).
+constexpr int CH_NB = 64;
+hipError_t launch_chol_factor(int n, int64_t ldl, float *L, int *info, hipStream_t s);
+// dst = L^-T L^-1 src (binary64 vectors, the factor widened); dst may be src
+hipError_t launch_chol_apply(int n, int64_t ldl, const float *L, const double *src, double *dst,
+                             hipStream_t s);
+// preconditioned CG pieces: r'z partials (one per vector block), p = z with
+// rho = r'z, and the stop test with p = z + beta p
+hipError_t launch_pcg_dot(int n, const double *r, const double *z, const State *st, double *partial,
+                          hipStream_t s);
+hipError_t launch_pcg_begin(int n, const double *z, double *p, State *st, const double *rz_part,
+                            hipStream_t s);
+hipError_t launch_pcg_pupdate(int n, const double *z, double *p, State *st, const double *rr_part,
+                              const double *rz_part, int max_iter, hipStream_t s);
+
 // CG iteration, three kernels:
 //   q = A p (sigma partials);  x += alpha p, r -= alpha q (rho' partials);
 //   convergence / limit checks, p = r + beta p.
@@ -320,6 +340,19 @@ hipError_t launch_fz_start(int n, int64_t lda, const double *A, const double *p0
 hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double *const vec[6],
                           State *st, double *const pg[2], int cur, int max_iter, hipStream_t s);
 hipError_t launch_fz_publish(State *st, int which, hipStream_t s);
+// The same iterations in one cooperative launch for n <= fz_persist_max_n():
+// up to nsteps iterations from slot `cur` with a grid barrier between them
+// (the blocks' rows of A read once per launch).  bar: fz_bar_words(n) words
+// (reset by the launcher, with st->sync_fail).  Slot (cur + nsteps) % 2 holds
+// the result, as after nsteps fz_step launches.  A bounded barrier wait that
+// gives up sets st->sync_fail.
+constexpr int FZ_BAR_STRIDE = 1;       // words between two blocks' barrier flags
+constexpr int FZ_BAR_MAX_WORDS = 256 * 32;
+int fz_persist_max_n();
+size_t fz_bar_words(int n);
+hipError_t launch_fz_persist(int n, int64_t lda, const double *A, double *x, double *const vec[6],
+                             State *st, double *const pg[2], int cur, int nsteps, int max_iter,
+                             uint32_t *bar, uint32_t spin_limit, hipStream_t s);
 
 // ||A||_inf into st->anorm_inf
 hipError_t launch_norm_inf(int n, int64_t lda, const double *A, State *st, Partials P,

@@ -43,6 +43,8 @@ struct Layout {
     size_t sy_off = 0, sy_bytes = 0;
     // GMRES-IR: pivots, permutation and info of the binary32 LU
     size_t lu_off = 0;
+    // fused small-n CG: grid-barrier flags of its persistent launch
+    size_t bar_off = 0;
     size_t total = 0;
     size_t total_borrowed = 0;
 };
@@ -59,7 +61,11 @@ inline bool valid_params(const ks_params *p) {
     if ((p->method == KS_JACOBI || p->method == KS_GAUSS_SEIDEL) &&
         (p->precision != KS_FP64 || p->nrhs != 1 || (p->flags & KS_FLAG_SYMMETRIC)))
         return false;
-    if (p->precision < KS_FP64 || p->precision > KS_IR_LU32) return false;
+    if (p->precision < KS_FP64 || p->precision > KS_IR_CHOL32) return false;
+    // CG-IR with the binary32 Cholesky factor: CG, one right-hand side
+    if (p->precision == KS_IR_CHOL32 &&
+        (p->method != KS_CG || p->nrhs != 1 || (p->flags & KS_FLAG_SYMMETRIC)))
+        return false;
     // GMRES-IR with the binary32 LU: GMRES, one right-hand side, n <= LU_MAX_N
     if (p->precision == KS_IR_LU32 &&
         (p->method != KS_GMRES || p->nrhs != 1 || p->n > LU_MAX_N || (p->flags & KS_FLAG_SYMMETRIC)))
@@ -90,7 +96,10 @@ inline Layout make_layout(const ks_params *p) {
     L.pv = (size_t)round_up(3 * vec_blocks(n), 32);
     L.ph = (size_t)round_up((size_t)cgs_blocks(n) * (L.m + 1), 32);
     L.pn = (size_t)round_up(cgs_blocks(n), 32);
-    L.pw = (p->method == KS_BICGSTAB) ? (size_t)round_up(4 * vec_blocks(n), 32) : 0;
+    // BiCGSTAB's x/r update partials; CG-IR's r'z partials
+    L.pw = (p->method == KS_BICGSTAB || p->precision == KS_IR_CHOL32)
+               ? (size_t)round_up(4 * vec_blocks(n), 32)
+               : 0;
     L.part_count = L.pg + L.pv + 2 * L.ph + L.pn + L.pw;
     L.part_off = off;
     off = align_up(off + L.part_count * sizeof(double));
@@ -109,6 +118,9 @@ inline Layout make_layout(const ks_params *p) {
     // GMRES-IR: the inner GMRES runs in binary64 (its w, V), plus the
     // correction d and the preconditioner's scratch t
     if (p->precision == KS_IR_LU32) L.nv64 += 2;
+    // CG-IR with the Cholesky factor: the inner PCG runs in binary64 on the
+    // CG vectors (r, p, q) plus the correction d and z = M^-1 r
+    if (p->precision == KS_IR_CHOL32) L.nv64 += 2;
     L.v64_off = off;
     off = align_up(off + (size_t)L.nv64 * L.ldv * sizeof(double));
     // binary32 vectors of the inner solve: rhs, d, then the method's vectors
@@ -137,13 +149,18 @@ inline Layout make_layout(const ks_params *p) {
         L.sy_off = off;
         off = align_up(off + L.sy_bytes);
     }
-    if (p->precision == KS_IR_LU32) {
-        // pivots, the permutation, the factorization's info word
+    if (fused) {
+        L.bar_off = off;
+        off = align_up(off + (size_t)FZ_BAR_MAX_WORDS * sizeof(uint32_t));
+    }
+    if (p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {
+        // pivots, the permutation, the factorization's info word (the
+        // Cholesky factorization uses the info word only)
         L.lu_off = off;
         off = align_up(off + (2 * (size_t)round_up(n, 64) + 64) * sizeof(int));
     }
     L.lda_low = round_up(n, 64);
-    if (p->precision == KS_IR_FP32 || p->precision == KS_IR_LU32) {
+    if (p->precision == KS_IR_FP32 || p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {
         L.alow_bytes = (size_t)n * L.lda_low * sizeof(float);
     } else if (p->precision == KS_IR_BF16) {
         L.alow_bytes = (size_t)n * L.lda_low * sizeof(uint16_t);

@@ -294,7 +294,9 @@ __device__ __forceinline__ void ts_rows_sums(const double (&pv)[Q], double xl, i
     }
 }
 
-// Step I of the forward substitution L y = t in place (L unit lower).
+// Step I of the forward substitution L y = t in place: L unit lower (the LU
+// factor, UNIT) or lower with its diagonal (the Cholesky factor).
+template <bool UNIT>
 __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
                                                          const float *__restrict__ LU,
                                                          double *__restrict__ t, int I) {
@@ -328,19 +330,36 @@ __global__ __launch_bounds__(GEMV_NT) void lu_fwd_kernel(int n, int64_t ldl,
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int k = w + TS_WAVES * q;
-        // strictly lower part (the unit diagonal is implicit)
-        T[k * TS_LDT + lane] = (k < m && lane < k) ? tl[q] : 0.0;
+        if constexpr (UNIT) {
+            // strictly lower part (the unit diagonal is implicit)
+            T[k * TS_LDT + lane] = (k < m && lane < k) ? tl[q] : 0.0;
+        } else {
+            // lower part with the diagonal; rows past n get a unit diagonal
+            T[k * TS_LDT + lane] = (k < m && lane < m) ? (lane <= k ? tl[q] : 0.0) : (lane == k ? 1.0 : 0.0);
+        }
     }
     ts_rows_sums(pv, I >= 1 ? xl : 0.0, lane, sI + w * Q);
     __syncthreads();
     if (w != 0) return;
     double acc = lane < m ? cval - sI[lane] : 0.0;
     double xi = 0.0;
+    if constexpr (UNIT) {
 #pragma unroll
-    for (int j = 0; j < TS_SB; ++j) {
-        const double xj = ts_readlane(acc, j);
-        xi = (lane == j) ? acc : xi;
-        acc = fma(-T[lane * TS_LDT + j], xj, acc);
+        for (int j = 0; j < TS_SB; ++j) {
+            const double xj = ts_readlane(acc, j);
+            xi = (lane == j) ? acc : xi;
+            acc = fma(-T[lane * TS_LDT + j], xj, acc);
+        }
+    } else {
+        const double dinv = 1.0 / T[lane * TS_LDT + lane];
+#pragma unroll
+        for (int j = 0; j < TS_SB; ++j) {
+            const double xc = acc * dinv;
+            const double xj = ts_readlane(xc, j);
+            xi = (lane == j) ? xc : xi;
+            // rows i > j take L(i, j) x_j; the diagonal and above are zero here
+            acc = fma(lane > j ? -T[lane * TS_LDT + j] : 0.0, xj, acc);
+        }
     }
     if (lane < m) t[r0 + lane] = xi;
 }
@@ -466,7 +485,7 @@ hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm,
     for (int I = 0; I < nb; ++I) {
         const int below = n - (I + 1) * TS_SB;
         const int blocks = 1 + ((I >= 1 && below > 0) ? div_up(below, TS_PR) : 0);
-        lu_fwd_kernel<<<blocks, GEMV_NT, 0, s>>>(n, ldl, LU, t, I);
+        lu_fwd_kernel<true><<<blocks, GEMV_NT, 0, s>>>(n, ldl, LU, t, I);
     }
     for (int J = nb - 1; J >= 0; --J) {
         const int above = J * TS_SB;
@@ -474,6 +493,30 @@ hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm,
         lu_bwd_kernel<<<blocks, GEMV_NT, 0, s>>>(n, ldl, LU, t, J, nb);
     }
     lu_pc_copy_kernel<<<gemv_blocks<double>(n), WAVE, 0, s>>>(n, t, dst, partial);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(VEC_NT) void ch_copy_kernel(int n, const double *__restrict__ v,
+                                                         double *__restrict__ z) {
+    const int i = blockIdx.x * VEC_NT + threadIdx.x;
+    if (i < n) z[i] = v[i];
+}
+
+hipError_t launch_chol_apply(int n, int64_t ldl, const float *L, const double *src, double *dst,
+                             hipStream_t s) {
+    if (dst != src) ch_copy_kernel<<<div_up(n, VEC_NT), VEC_NT, 0, s>>>(n, src, dst);
+    const int nb = div_up(n, TS_SB);
+    for (int I = 0; I < nb; ++I) {
+        const int below = n - (I + 1) * TS_SB;
+        const int blocks = 1 + ((I >= 1 && below > 0) ? div_up(below, TS_PR) : 0);
+        lu_fwd_kernel<false><<<blocks, GEMV_NT, 0, s>>>(n, ldl, L, dst, I);
+    }
+    // L^T is held in the strict upper triangle (and the shared diagonal)
+    for (int J = nb - 1; J >= 0; --J) {
+        const int above = J * TS_SB;
+        const int blocks = 1 + ((J + 1 < nb && above > 0) ? div_up(above, TS_PR) : 0);
+        lu_bwd_kernel<<<blocks, GEMV_NT, 0, s>>>(n, ldl, L, dst, J, nb);
+    }
     return hipGetLastError();
 }
 

@@ -459,7 +459,7 @@ int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const
                      double *d_x, uint64_t *ticket) {
     if (!sv || !p || !d_A || !d_b || !d_x || !ticket) return KS_EINVAL;
     if (!valid_params(p) || p->nrhs != 1 || (p->method != KS_CG && p->method != KS_GMRES) ||
-        (p->flags & KS_FLAG_SYMMETRIC))
+        (p->flags & KS_FLAG_SYMMETRIC) || p->precision > KS_IR_BF16)
         return KS_EINVAL;
     if ((uintptr_t)d_b % 16 || (uintptr_t)d_x % 16) return KS_EINVAL;
     Req *r = new (std::nothrow) Req();

@@ -18,7 +18,7 @@ from . import _native as N
 _METHODS = {"cg": N.KS_CG, "gmres": N.KS_GMRES, "bicgstab": N.KS_BICGSTAB,
             "jacobi": N.KS_JACOBI, "gauss_seidel": N.KS_GAUSS_SEIDEL}
 _PRECISIONS = {"fp64": N.KS_FP64, "fp32": N.KS_IR_FP32, "bf16": N.KS_IR_BF16,
-               "lu32": N.KS_IR_LU32}
+               "lu32": N.KS_IR_LU32, "chol32": N.KS_IR_CHOL32}
 _PREC_NAMES = {v: k for k, v in _PRECISIONS.items()}
 
 
@@ -44,7 +44,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
                 max_iter: int | None = None, restart: int = 30, precision: str = "fp64",
                 inner_tol: float = 1e-4, max_outer: int = 30, poll_every: int = 0,
                 timing: bool = False, nrhs: int = 1, stop_backward: bool = False,
-                symmetric: bool = False, timing_every: int = 0) -> N.KsParams:
+                symmetric: bool = False, timing_every: int = 0, persist: bool = True) -> N.KsParams:
     p = N.KsParams()
     N.check(N.lib().ks_params_init(ctypes.byref(p), int(n), _METHODS[method]), "ks_params_init")
     p.lda = int(lda if lda is not None else n)
@@ -57,7 +57,7 @@ def make_params(n: int, method: str = "cg", lda: int | None = None, tol: float =
     p.max_outer = int(max_outer)
     p.poll_every = int(poll_every)
     p.flags = ((N.KS_FLAG_TIMING if timing else 0) | (N.KS_FLAG_STOP_BACKWARD if stop_backward else 0)
-               | (N.KS_FLAG_SYMMETRIC if symmetric else 0))
+               | (N.KS_FLAG_SYMMETRIC if symmetric else 0) | (0 if persist else N.KS_FLAG_NO_PERSIST))
     p.nrhs = int(nrhs)
     p.timing_every = int(timing_every)
     return p
@@ -297,6 +297,21 @@ def lu32_factor(A: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor, int]:
     N.check(N.lib().ks_lu32_factor(int(n), int(A.stride(0)), _ptr(A), int(n), _ptr(LU), _ptr(piv),
                                    ctypes.byref(info), _stream_handle()), "ks_lu32_factor")
     return LU, piv, int(info.value)
+
+
+def chol32_factor(A: torch.Tensor) -> tuple[torch.Tensor, int]:
+    """Binary32 block Cholesky of a symmetric float64 matrix.
+    Returns (F float32 n x ldl with L on and below the diagonal and L^T above
+    it, info); ldl = n rounded up to a multiple of 4."""
+    if A.dtype != torch.float64:
+        raise TypeError("chol32_factor: A must be float64")
+    n = A.shape[0]
+    ldl = (n + 3) // 4 * 4
+    F = torch.empty((n, ldl), dtype=torch.float32, device=A.device)
+    info = ctypes.c_int32(0)
+    N.check(N.lib().ks_chol32_factor(int(n), int(A.stride(0)), _ptr(A), int(ldl), _ptr(F),
+                                     ctypes.byref(info), _stream_handle()), "ks_chol32_factor")
+    return F, int(info.value)
 
 
 def convert(A: torch.Tensor, dtype: torch.dtype, lda_dst: int | None = None) -> torch.Tensor:

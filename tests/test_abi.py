@@ -181,6 +181,40 @@ def test_symmetric_flag_and_symv_on_host():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_cholesky_refinement_parameters_on_host():
+    """KS_IR_CHOL32 is CG with one right-hand side and the general product;
+    the factorization entry point validates its arguments before any device
+    call."""
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    sz = ctypes.c_size_t(0)
+    p = N.KsParams()
+    assert L.ks_params_init(ctypes.byref(p), 32768, N.KS_CG) == 0
+    p.precision = N.KS_IR_CHOL32
+    assert L.ks_workspace_bytes_borrowed(ctypes.byref(p), ctypes.byref(sz)) == 0
+    # the binary32 factor (n x round_up(n, 64) floats) dominates
+    assert sz.value >= 32768 * 32768 * 4
+    for method in (N.KS_GMRES, N.KS_BICGSTAB):
+        q = N.KsParams()
+        assert L.ks_params_init(ctypes.byref(q), 100, method) == 0
+        q.precision = N.KS_IR_CHOL32
+        assert L.ks_workspace_bytes(ctypes.byref(q), ctypes.byref(sz)) == N.KS_EINVAL
+    p.flags = N.KS_FLAG_SYMMETRIC
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.flags = 0
+    p.nrhs = 2
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    p.nrhs = 1
+    p.precision = N.KS_IR_CHOL32 + 1
+    assert L.ks_workspace_bytes(ctypes.byref(p), ctypes.byref(sz)) == N.KS_EINVAL
+    info = ctypes.c_int32(0)
+    assert L.ks_chol32_factor(0, 1, None, 1, None, ctypes.byref(info), None) == N.KS_EINVAL
+    assert L.ks_chol32_factor(10, 10, 16, 9, 16, ctypes.byref(info), None) == N.KS_EINVAL  # ldl < n
+    assert L.ks_chol32_factor(10, 10, 16, 10, 16, ctypes.byref(info), None) == N.KS_EINVAL  # ldl % 4
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
 def test_symv_noalloc_limits_on_host():
     """The fixed-array product refuses an order beyond its array and bad
     arguments before any device call."""
