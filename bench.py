@@ -476,6 +476,46 @@ def leg_f4(dev):
     return out
 
 
+def leg_chol(dev, n, spd_form="qr"):
+    """CG-IR with the binary32 block Cholesky preconditioner on the refinement
+    workload's hardest SPD cell (n = 32768, cond 1e6), beside binary32-refined
+    CG on the lower triangle (the headline's SPD solver) at the same backward
+    error: factorization time and TFLOP/s (n^3 / 3 flops, in ks_create) and
+    solve time after the factorization."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import spd_problem
+
+    prob = spd_problem(n, 1e6, seed=0, config_id=2, backend="torch", device="cuda", q_form=spd_form)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    out = {"n": n, "kappa": 1e6, "eta_target": 1e-12}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = krylov.Solver(prob.A, method="cg", precision="chol32", tol=1e-12, max_iter=2000)
+    torch.cuda.synchronize()
+    fact_ms = (time.perf_counter() - t0) * 1e3
+    info, dt, reps = _solve_timed(s, prob.b, x)
+    s.close()
+    out["chol32"] = {"factor_ms": round(fact_ms, 2),
+                     "factor_tflops": round(n ** 3 / 3.0 / (fact_ms * 1e-3) / 1e12, 2),
+                     "status": info["status_name"], "outer": info["outer_iters"],
+                     "inner": info["iters"], "eta_inf": info["backward_err"],
+                     "solve_ms": round(dt * 1e3, 2), "timed_solves": reps,
+                     "factor_plus_solve_ms": round(fact_ms + dt * 1e3, 2),
+                     "fwd_err_vs_x_true": float((x - prob.x_true).norm() / prob.x_true.norm())}
+    s = krylov.Solver(prob.A, method="cg", precision="fp32", symmetric=True, tol=1e-12,
+                      max_iter=4 * n)
+    info, dt, reps = _solve_timed(s, prob.b, x)
+    s.close()
+    out["fp32_sym"] = {"status": info["status_name"], "outer": info["outer_iters"],
+                       "inner": info["iters"], "eta_inf": info["backward_err"],
+                       "solve_ms": round(dt * 1e3, 2), "timed_solves": reps}
+    del prob, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_c2p(dev, n):
     """The CG solve of the main step with either product: general GEMV (all of
     A per iteration) and the symmetric lower-triangle product."""
@@ -532,7 +572,8 @@ def leg_c4(dev, n):
 
 def leg_c5(dev, count, pool_size, seed=0, rates=(0.5, 0.9)):
     """Serving: binary64 against mixed-precision requests at equal accuracy
-    (normwise backward error <= 1e-12), over a pool of resident systems
+    (normwise backward error <= 1e-12; SPD requests with the lower-triangle
+    product), over a pool of resident systems
     (n log-uniform on [256, 8192], half SPD CG with cond log-uniform on
     [1e2, 1e5], half GMRES(30) on D + G/sqrt(n)), each request with its own
     right-hand side.  Saturation throughput of each, then both under the same
@@ -562,6 +603,10 @@ def leg_c5(dev, count, pool_size, seed=0, rates=(0.5, 0.9)):
         kw = dict(method=kind, tol=1e-12)
         if kind == "gmres":
             kw["restart"] = 30
+        else:
+            # SPD requests on the lower triangle (the binary64 products and the
+            # binary32 inner products; bfloat16 inner solves keep the general one)
+            kw["symmetric"] = True
         if mode == "fp64":
             kw["stop_backward"] = True
         else:
@@ -648,7 +693,7 @@ def main():
                          "(same spectrum and bytes; for hardware-counter runs)")
     ap.add_argument("--legs", default="c1,c2,c3sweep,c4,c5,f1,f3,f4",
                     help="extra measurements after the timed steps (comma list of "
-                         "c1,c2,c2p,c3sweep,c4,c5,f1,f3,f4; 'none' for the main step only)")
+                         "c1,c2,c2p,c3sweep,c4,c5,f1,f3,f4,chol; 'none' for the main step only)")
     ap.add_argument("--n2", type=int, default=16384, help="size of the binary64 legs (c2, c2p, c4, f1, f3)")
     ap.add_argument("--c2-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=1024)
@@ -880,6 +925,8 @@ def main():
                 legs[name] = leg_f4(dev)
             elif name == "c2p":
                 legs[name] = leg_c2p(dev, n2)
+            elif name == "chol":
+                legs[name] = leg_chol(dev, n, args.spd_form)
             else:
                 legs[name] = {"error": "unknown leg"}
         except Exception as e:  # a failing leg is reported, not fatal

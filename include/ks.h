@@ -255,15 +255,20 @@ typedef struct ks_server ks_server;
 int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_inflight, int32_t chunk,
                      void *stream);
 
-/* Queue a solve (method KS_CG or KS_GMRES, nrhs 1, no KS_FLAG_SYMMETRIC; any
- * precision; otherwise KS_EINVAL).  d_x holds x0 and receives x.  *ticket
- * identifies it in ks_server_poll.  KS_ETOOLARGE if it can never fit the
- * budget. */
+/* Queue a solve (method KS_CG or KS_GMRES, nrhs 1, precision KS_FP64,
+ * KS_IR_FP32 or KS_IR_BF16; KS_FLAG_SYMMETRIC for CG as in ks_solve;
+ * otherwise KS_EINVAL).  d_x holds x0 and receives x.  *ticket identifies it
+ * in ks_server_poll.  KS_ETOOLARGE if it can never fit the budget. */
 int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const double *d_b,
                      double *d_x, uint64_t *ticket);
 
 /* One scheduling tick (admit, advance all in-flight solves, retire); waits
- * for the tick's device work.  Optional outputs: solves in flight and queued. */
+ * for the tick's device work.  Within a tick a solve's set-up, start and
+ * steps run back to back, and a refinement request's check of the backward
+ * error is taken on the device, which starts its next inner solve in the same
+ * tick (precision promotions are left to the host's next tick).  Every
+ * request's arithmetic is that of ks_solve with the same parameters.
+ * Optional outputs: solves in flight and queued. */
 int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued);
 
 /* Up to cap finished requests: their tickets and infos (elapsed_ms = time

@@ -210,4 +210,22 @@ __device__ __forceinline__ double gm_threshold(const State *st) {
     return st->eta_tol * (st->anorm_inf * st->xinf + st->binf) * ratio;
 }
 
+// The request server's batched launches: the item of block `bid` in a set
+// (offs[i] <= bid < offs[i+1]), its local block index and block count.
+template <typename Item>
+__device__ __forceinline__ const Item &batch_item(const BatchSetT<Item> &bs, int bid, int &local,
+                                                  int &nblk) {
+    int lo = 0, hi = bs.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bs.offs[mid] <= bid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    local = bid - bs.offs[lo];
+    nblk = bs.offs[lo + 1] - bs.offs[lo];
+    return bs.items[bs.idx[lo]];
+}
+
 }  // namespace ks

@@ -21,8 +21,11 @@ enum : int32_t {
     F_HAPPY = 32,       // GMRES happy breakdown (exact solution in the space)
     F_TRUE_OK = 64,     // last true residual met the tolerance
     F_TRUE_NONFIN = 128,// last true residual (or ||b||) not finite
-    F_HALF = 256        // BiCGSTAB ends on the half step x += alpha p (with
+    F_HALF = 256,       // BiCGSTAB ends on the half step x += alpha p (with
                         // F_CONV or F_MAXIT; F_STOP follows one kernel later)
+    F_SETUP_END = 512   // server: the set-up ended the solve before its first
+                        // step (b = 0, a non-finite or already small residual,
+                        // no iterations allowed); no Krylov kernel ran
 };
 constexpr int32_t INNER_FLAGS = F_STOP | F_CONV | F_MAXIT | F_BREAK | F_NONFIN | F_HAPPY | F_HALF;
 
@@ -44,6 +47,9 @@ struct alignas(256) State {
     int32_t flags;
     int32_t k_done;            // GMRES: steps in the current cycle
     int32_t kcur;              // GMRES step counter of batched launches
+    int32_t kcur_odd;          // the same counter for odd steps of a server tick
+                               // (step c reads kcur / kcur_odd by parity, its
+                               // Givens stage writes the other one)
     // fused small-n CG: per-launch copies of rho, iters and flags, alternating
     // between two slots so that no block reads a value another block of the
     // same launch writes
@@ -51,6 +57,7 @@ struct alignas(256) State {
     int32_t fz_iters[2];
     int32_t fz_flags[2];
     int32_t sync_fail;  // persistent kernels: a bounded grid-barrier wait gave up
+    int32_t ir_next;    // server: the device's refinement check of this outer State (IR_*)
 };
 static_assert(sizeof(State) == 256, "one 256-byte State per solve");
 
@@ -312,7 +319,7 @@ hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, dou
 hipError_t launch_symv_cg(int n, int64_t lda, const double *A, const double *p, double *x,
                           double *r, double *region, State *st, hipStream_t s);
 // where the r'r partials of launch_symv_cg lie in that region
-inline double *symv_cg_rho_part(int n, double *region) {
+__host__ __device__ inline double *symv_cg_rho_part(int n, double *region) {
     return region + sy_ws_doubles(n) + round_up(sy_tiles(n), 32);
 }
 
@@ -394,6 +401,14 @@ struct BatchItemT {
     State *st;
     Partials P;
     GmArrays ga;
+    // server: an inner solve whose refinement check ran on the device in
+    // this tick (the outer State); its kernels run only if that check said
+    // IR_GO.  nullptr otherwise.
+    const State *outer;
+    // CG with the symmetric product (KS_FLAG_SYMMETRIC): the region of its
+    // tile partials, shares of p'Ap and r'r partials (binary32 solves keep
+    // their tile partials as floats in it); nullptr for the general product
+    double *sy;
 };
 using BatchItem = BatchItemT<double, double>;
 // A subset of items for one launch: offs[i] = first block of idx[i]'s grid.
@@ -407,9 +422,7 @@ struct BatchSetT {
 using BatchSet = BatchSetT<BatchItem>;
 enum BatchKernel {
     BK_VEC_STATS, BK_NORM_INF, BK_NORM_INF_FINISH, BK_RESIDUAL, BK_RESIDUAL_FINISH,
-    BK_CG_BEGIN, BK_CG_MATVEC, BK_CG_UPDATE, BK_CG_PUPDATE,
-    BK_GM_BEGIN, BK_GM_MATVEC, BK_GM_CGS0, BK_GM_CGS1, BK_GM_CGS2, BK_GM_GIVENS,
-    BK_GM_ADVANCE, BK_GM_FINISH, BK_GATHER
+    BK_CG_BEGIN, BK_GM_BEGIN, BK_GM_FINISH, BK_GATHER
 };
 // blocks = offs[count]; gate for the residual / finish kernels.  BK_NORM_INF
 // and BK_NORM_INF_FINISH exist for binary64 items only.
@@ -417,18 +430,69 @@ template <typename TA, typename T>
 hipError_t batch_launch(BatchKernel kind, const BatchSetT<BatchItemT<TA, T>> &bs, int blocks,
                         int gate, hipStream_t s, State *staging);
 
+// One stage of a server tick: the same position of one Krylov step for the
+// CG and GMRES items of every storage type, in one launch (blocks of 256
+// threads; each entry = one item's grid for its kernel kind).
+//   stage 1: CG q = A p            | GMRES w = A v_k
+//   stage 2: CG x, r update        | GMRES Gram-Schmidt pass 0
+//   stage 3: CG p update           | GMRES pass 1
+//   stage 4:                       | GMRES pass 2
+//   stage 5:                       | GMRES Givens rotation (and the step counter)
+//   (CG with the symmetric product: its tiles and finishing sum with the
+//   update run as the batched launches below, between stages 1 and 2 and
+//   between stages 2 and 3; its p update in stage 3)
+enum StageKind : int32_t {
+    SK_CG_MATVEC, SK_CG_UPDATE, SK_CG_PUPDATE, SK_GM_MATVEC, SK_GM_CGS0, SK_GM_CGS1, SK_GM_CGS2,
+    SK_GM_GIVENS, SK_SY_PUPDATE
+};
+struct StageSet {
+    const BatchItemT<double, double> *i64;  // the items' binary64 views (index = slot)
+    const BatchItemT<float, float> *i32;    // binary32 inner solves
+    const BatchItemT<bf16_t, float> *i16;   // bfloat16 inner solves
+    const int *idx;    // slot of entry e
+    const int *kind;   // StageKind | (storage << 8), storage 0 binary64, 1 binary32, 2 bfloat16
+    const int *offs;   // first block of entry e (offs[count] = blocks)
+    int count;
+};
+// stage 2..5, or 10 + storage for the product stage (one launch per
+// storage); step: the step's index in the tick (its parity selects the
+// GMRES step counter); blocks = offs[count]
+hipError_t stage_launch(const StageSet &ss, int stage, int blocks, int step, hipStream_t s);
+
+// The symmetric CG product of a set of solves (items with sy != nullptr):
+// the tiles (which = 0; blocks = sum of sy_tiles(n)) or the finishing sum with
+// the x, r update (which = 1; blocks = sum of symv_finish_blocks(n)), binary64
+// or, for binary32 inner solves, binary32.
+hipError_t batch_symv(int which, const BatchSetT<BatchItemT<double, double>> &bs, int blocks,
+                      hipStream_t s);
+hipError_t batch_symv32(int which, const BatchSetT<BatchItemT<float, float>> &bs, int blocks,
+                        hipStream_t s);
+
 // One refinement step of a mixed-precision request (the vector work between
-// its binary64 outer residual and its inner solve).
+// its binary64 outer residual and its inner solve), and the inputs of its
+// refinement check on the device: the host's counters as of the tick.
 struct IrItem {
     int n;
     const double *r64;  // outer residual
     float *rhs;         // inner right-hand side r / ||r||
     float *d;           // inner solution (correction)
     double *x;          // the request's iterate
-    const State *st;    // outer State (st->res = ||r||)
+    State *st;          // outer State (st->res = ||r||)
+    State *inner;       // the inner solve's State
+    double tol;         // backward-error target
+    double eta_prev;    // backward error of the previous check (inf at first)
+    int outer_steps, max_outer, bad, prec;
+    int first;          // the first check (after the set-up of b and r0)
+    int gated;          // the check ran on the device in this tick: the inner
+                        // set-up runs only if it said IR_GO
 };
 using IrSet = BatchSetT<IrItem>;
-enum IrKernel { IK_SCALE, IK_ZERO_D, IK_UPDATE };
+enum IrKernel { IK_SCALE, IK_ZERO_D, IK_UPDATE, IK_DECIDE };
+// Outcomes of the device refinement check (State::ir_next), the host's
+// check in the same arithmetic: go on with an inner solve; stop (backward
+// error met, b = 0, the step limit, non-finite); or a precision promotion,
+// which the host carries out.
+enum IrNext : int32_t { IR_NONE = 0, IR_GO, IR_DONE, IR_ZERO, IR_STAG, IR_NONFIN, IR_PROMOTE };
 hipError_t ir_batch_launch(IrKernel kind, const IrSet &bs, int blocks, hipStream_t s);
 // staging[i] = *d_ptrs[i] (device array of State pointers)
 hipError_t gather_states(const State *const *d_ptrs, int count, State *staging, hipStream_t s);

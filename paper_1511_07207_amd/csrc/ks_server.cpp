@@ -107,6 +107,7 @@ struct Req {
     size_t ws_off = 0, ws_bytes = 0, footprint = 0;
     Phase phase = P_QUEUED;
     int seg = -1;  // workspace segment
+    double *sy = nullptr;  // symmetric CG product region (KS_FLAG_SYMMETRIC)
     bool copy_a = false;
     int restarts = 0, cycles = 0;
     BatchItem item{};  // binary64: the solve, or the refinement's outer step
@@ -253,6 +254,38 @@ class TableBuilder {
         *total = acc;
         return bs;
     }
+    // A stage set over (slot, kind) entries, blocks_of(slot, kind) blocks each.
+    template <typename F>
+    StageSet stage(const BatchItem *d64, const BatchItemT<float, float> *d32,
+                   const BatchItemT<bf16_t, float> *d16, const std::vector<std::pair<int, int>> &e,
+                   F blocks_of, int *total) {
+        StageSet ss{};
+        const int c = (int)e.size();
+        int *hi = reinterpret_cast<int *>(host_ + off_);
+        ss.idx = reinterpret_cast<const int *>(dev_ + off_);
+        off_ += align_up(sizeof(int) * (size_t)(c + 1));
+        int *hk = reinterpret_cast<int *>(host_ + off_);
+        ss.kind = reinterpret_cast<const int *>(dev_ + off_);
+        off_ += align_up(sizeof(int) * (size_t)(c + 1));
+        int *ho = reinterpret_cast<int *>(host_ + off_);
+        ss.offs = reinterpret_cast<const int *>(dev_ + off_);
+        off_ += align_up(sizeof(int) * (size_t)(c + 1));
+        int acc = 0;
+        for (int i = 0; i < c; ++i) {
+            hi[i] = e[i].first;
+            hk[i] = e[i].second;
+            ho[i] = acc;
+            acc += blocks_of(e[i].first, e[i].second);
+        }
+        ho[c] = acc;
+        ss.i64 = d64;
+        ss.i32 = d32;
+        ss.i16 = d16;
+        ss.count = c;
+        *total = acc;
+        return ss;
+    }
+    static size_t stage_bytes(int count) { return 3 * align_up(sizeof(int) * (size_t)(count + 1)); }
     size_t bytes() const { return off_; }
 
    private:
@@ -264,9 +297,9 @@ class TableBuilder {
 template <typename TA>
 struct InnerSets {
     using Set = BatchSetT<BatchItemT<TA, float>>;
-    Set init_g, init_1, cgb, gmb, cg_g, cg_v, cg_1, gm_g, gm_c, gm_v, gm_1;
-    int n_init_g = 0, n_init_1 = 0, n_cgb = 0, n_gmb = 0, n_cg_g = 0, n_cg_v = 0, n_cg_1 = 0, n_gm_g = 0,
-        n_gm_c = 0, n_gm_v = 0, n_gm_1 = 0;
+    // set-up, (re)starts and the GMRES cycle ends; the steps run as stages
+    Set init_g, init_1, cgb, gmb, gm_g, gm_c, gm_1;
+    int n_init_g = 0, n_init_1 = 0, n_cgb = 0, n_gmb = 0, n_gm_g = 0, n_gm_c = 0, n_gm_1 = 0;
 };
 
 void finish_metrics(Req *r, const State &h) {
@@ -329,6 +362,8 @@ void setup_inner(Req *r, const Carved &c) {
     };
     fill(r->in32);
     fill(r->in16);
+    r->in32.sy = r->sy;      // binary32 inner CG on the lower triangle
+    r->in16.sy = nullptr;    // bfloat16 inner solves keep the general product
     r->in16.A = (const bf16_t *)r->A_low;
     r->in32.A = (r->p.precision == KS_IR_BF16) ? r->A_fb : (const float *)r->A_low;
     r->iri.n = r->p.n;
@@ -359,6 +394,7 @@ void to_fp64_tail(Req *r, const Carved &c) {
         it.V = c.v64 + ldv;
         it.p = it.q = nullptr;
     }
+    it.sy = r->sy;
     r->restarts = 0;
     r->cycles = 0;
     r->phase = P_INIT;
@@ -416,7 +452,7 @@ int ir_after_inner(ks_server *sv, Req *r, int inner_status, int inner_iters) {
 template <typename TA, typename F1, typename F2>
 void build_inner(TableBuilder &tb, InnerSets<TA> &S, const BatchItemT<TA, float> *dev,
                  const std::vector<int> &init, const std::vector<int> &cgb, const std::vector<int> &gmb,
-                 const std::vector<int> &cgr, const std::vector<int> &gmr, F1 gsh, F2 vsh,
+                 const std::vector<int> &gmr, F1 gsh, F2 vsh,
                  const std::vector<int> &cgs_blocks_of) {
     auto one = [](int) { return 1; };
     auto csh = [&](int i) { return cgs_blocks_of[i]; };
@@ -424,12 +460,8 @@ void build_inner(TableBuilder &tb, InnerSets<TA> &S, const BatchItemT<TA, float>
     S.init_1 = tb.add(dev, init, one, &S.n_init_1);
     S.cgb = tb.add(dev, cgb, vsh, &S.n_cgb);
     S.gmb = tb.add(dev, gmb, vsh, &S.n_gmb);
-    S.cg_g = tb.add(dev, cgr, gsh, &S.n_cg_g);
-    S.cg_v = tb.add(dev, cgr, vsh, &S.n_cg_v);
-    S.cg_1 = tb.add(dev, cgr, one, &S.n_cg_1);
     S.gm_g = tb.add(dev, gmr, gsh, &S.n_gm_g);
     S.gm_c = tb.add(dev, gmr, csh, &S.n_gm_c);
-    S.gm_v = tb.add(dev, gmr, vsh, &S.n_gm_v);
     S.gm_1 = tb.add(dev, gmr, one, &S.n_gm_1);
 }
 
@@ -450,7 +482,9 @@ int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_infli
     sv->stream = (hipStream_t)stream;
     sv->budget = mem_budget_bytes;
     sv->max_inflight = max_inflight;
-    sv->chunk = chunk > 0 ? chunk : 16;
+    // an even number of steps per tick: the GMRES step counter alternates
+    // between two State fields by step parity and ends each tick in kcur
+    sv->chunk = chunk > 0 ? chunk + (chunk & 1) : 16;
     *out = sv;
     return KS_OK;
 }
@@ -459,7 +493,7 @@ int ks_server_submit(ks_server *sv, const ks_params *p, const double *d_A, const
                      double *d_x, uint64_t *ticket) {
     if (!sv || !p || !d_A || !d_b || !d_x || !ticket) return KS_EINVAL;
     if (!valid_params(p) || p->nrhs != 1 || (p->method != KS_CG && p->method != KS_GMRES) ||
-        (p->flags & KS_FLAG_SYMMETRIC) || p->precision > KS_IR_BF16)
+        p->precision > KS_IR_BF16)
         return KS_EINVAL;
     if ((uintptr_t)d_b % 16 || (uintptr_t)d_x % 16) return KS_EINVAL;
     Req *r = new (std::nothrow) Req();
@@ -497,6 +531,7 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         sv->in_use += r->footprint;
         char *ws = ws_base(sv, r);
         const Carved c = carve(r->L, ws);
+        r->sy = r->L.sy_bytes ? (double *)(ws + r->L.sy_off) : nullptr;
         BatchItem &it = r->item;
         it.A = r->A;
         it.lda = r->p.lda;
@@ -515,6 +550,7 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
         it.st = c.st;
         it.P = c.P;
         it.ga = c.ga;
+        it.sy = r->ir ? nullptr : r->sy;  // a refinement's outer step makes no CG product
         if (!r->ir) {
             it.max_iter = r->p.max_iter;
             it.tol = r->p.tol;
@@ -556,48 +592,66 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     }
     // 2. subsets of this tick.  Binary64 items: plain solves and refinement
     // outer steps; inner items by storage type (k = 0 binary32, 1 bfloat16).
-    std::vector<int> init, upd, cg_begin, gm_begin, cg_run, gm_run, in_init_all;
+    // A solve's set-up, its start and its steps run in the same tick (the
+    // start kernels take the set-up's own decision, F_SETUP_END); so do a
+    // refinement request's outer residual, its refinement check (on the
+    // device, IK_DECIDE) and, when the check says go on, the set-up, start
+    // and steps of its next inner solve.
+    std::vector<int> init, upd, dec, cg_begin, gm_begin, cg_run, gm_run, in_init_all;
     std::vector<int> in_init[2], in_cgb[2], in_gmb[2], in_cg[2], in_gm[2];
+    std::vector<char> gated(nf, 0);
     auto tix = [](const Req *r) { return r->prec == KS_IR_BF16 ? 1 : 0; };
     for (int i = 0; i < nf; ++i) {
         const Req *r = sv->inflight[i];
         const bool cg = r->p.method == KS_CG;
+        const bool inner_next = r->ir && (r->phase == P_INIT || r->phase == P_UPDATE);
+        if (r->phase == P_INIT) init.push_back(i);
+        if (r->phase == P_UPDATE) upd.push_back(i);
+        if (inner_next) {
+            dec.push_back(i);
+            gated[i] = 1;
+        }
         switch (r->phase) {
-            case P_INIT: init.push_back(i); break;
+            case P_INIT:
+                if (r->ir) break;  // the inner solve below
+                // fall through: binary64 set-up, start and steps
             case P_BEGIN:
                 (cg ? cg_begin : gm_begin).push_back(i);
                 (cg ? cg_run : gm_run).push_back(i);
                 break;
             case P_RUN: (cg ? cg_run : gm_run).push_back(i); break;
-            case P_UPDATE: upd.push_back(i); break;
-            case P_IN_INIT:
-                in_init[tix(r)].push_back(i);
-                in_init_all.push_back(i);
-                break;
-            case P_IN_BEGIN:
-                (cg ? in_cgb : in_gmb)[tix(r)].push_back(i);
-                (cg ? in_cg : in_gm)[tix(r)].push_back(i);
-                break;
-            case P_IN_RUN: (cg ? in_cg : in_gm)[tix(r)].push_back(i); break;
             default: break;
         }
+        if (inner_next || r->phase == P_IN_INIT) {
+            in_init[tix(r)].push_back(i);
+            in_init_all.push_back(i);
+        }
+        if (inner_next || r->phase == P_IN_INIT || r->phase == P_IN_BEGIN) {
+            (cg ? in_cgb : in_gmb)[tix(r)].push_back(i);
+            (cg ? in_cg : in_gm)[tix(r)].push_back(i);
+        }
+        if (r->phase == P_IN_RUN) (cg ? in_cg : in_gm)[tix(r)].push_back(i);
     }
     size_t need = TableBuilder::array_bytes(sizeof(BatchItem), nf) +
                   TableBuilder::array_bytes(sizeof(BatchItemT<float, float>), nf) +
                   TableBuilder::array_bytes(sizeof(BatchItemT<bf16_t, float>), nf) +
                   TableBuilder::array_bytes(sizeof(IrItem), nf) +
-                  TableBuilder::array_bytes(sizeof(State *), nf);
+                  TableBuilder::array_bytes(sizeof(State *), 2 * nf);
+    need += TableBuilder::set_bytes((int)dec.size());
     need += 2 * TableBuilder::set_bytes((int)init.size()) + 3 * TableBuilder::set_bytes((int)upd.size());
     need += TableBuilder::set_bytes((int)cg_begin.size()) + TableBuilder::set_bytes((int)gm_begin.size());
-    need += 3 * TableBuilder::set_bytes((int)cg_run.size()) + 4 * TableBuilder::set_bytes((int)gm_run.size());
+    need += 2 * TableBuilder::set_bytes((int)cg_run.size()) + 3 * TableBuilder::set_bytes((int)gm_run.size());
     need += TableBuilder::set_bytes((int)in_init_all.size());
     for (int k = 0; k < 2; ++k) {
         need += 2 * TableBuilder::set_bytes((int)in_init[k].size());
         need += TableBuilder::set_bytes((int)in_cgb[k].size()) + TableBuilder::set_bytes((int)in_gmb[k].size());
-        need += 3 * TableBuilder::set_bytes((int)in_cg[k].size()) + 4 * TableBuilder::set_bytes((int)in_gm[k].size());
+        need += 3 * TableBuilder::set_bytes((int)in_gm[k].size());
     }
+    // the step stages: at most one entry per running item in each; the
+    // symmetric products' four sets
+    need += 7 * TableBuilder::stage_bytes(nf) + 4 * TableBuilder::set_bytes(nf);
     need += 4096;
-    int rc = grow_buffers(sv, need, (size_t)nf);
+    int rc = grow_buffers(sv, need, 2 * (size_t)nf);
     if (rc) return rc;
     TableBuilder tb(sv->htab, sv->dtab);
     const BatchItem *d64;
@@ -609,18 +663,32 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     BatchItemT<float, float> *h32 = tb.array<BatchItemT<float, float>>(nf, &d32);
     BatchItemT<bf16_t, float> *h16 = tb.array<BatchItemT<bf16_t, float>>(nf, &d16);
     IrItem *hir = tb.array<IrItem>(nf, &dir);
-    const State **hptrs = tb.array<const State *>(nf, &dptrs);
+    const State **hptrs = tb.array<const State *>(2 * nf, &dptrs);
     std::vector<int> cgsb(nf);
     for (int i = 0; i < nf; ++i) {
         const Req *r = sv->inflight[i];
         h64[i] = r->item;
+        h64[i].outer = nullptr;
         h32[i] = r->in32;
         h16[i] = r->in16;
+        h32[i].outer = h16[i].outer = gated[i] ? r->item.st : nullptr;
         hir[i] = r->iri;
+        if (r->ir) {
+            hir[i].inner = r->in32.st;
+            hir[i].tol = r->p.tol;
+            hir[i].eta_prev = r->eta_prev;
+            hir[i].outer_steps = r->outer;
+            hir[i].max_outer = r->p.max_outer;
+            hir[i].bad = r->bad;
+            hir[i].prec = r->prec;
+            hir[i].first = r->phase == P_INIT;
+            hir[i].gated = gated[i];
+        }
         cgsb[i] = cgs_blocks(r->p.n);
-        // the State the host's next decision reads
-        const bool inner = r->phase == P_IN_INIT || r->phase == P_IN_BEGIN || r->phase == P_IN_RUN;
-        hptrs[i] = inner ? r->in32.st : r->item.st;
+        // the States the host's next decisions read: the outer (or only)
+        // one and the inner one
+        hptrs[2 * i] = r->item.st;
+        hptrs[2 * i + 1] = r->ir ? r->in32.st : r->item.st;
     }
     auto n_of = [&](int i) { return sv->inflight[i]->p.n; };
     auto g64 = [&](int i) { return gemv_blocks<double>(n_of(i)); };
@@ -629,8 +697,8 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     auto vsh = [&](int i) { return vec_blocks(n_of(i)); };
     auto csh = [&](int i) { return cgsb[i]; };
     auto one = [](int) { return 1; };
-    int nb_init_g, nb_init_1, nb_upd_v, nb_upd_g, nb_upd_1, nb_cgb, nb_gmb, nb_cg_g, nb_cg_v, nb_cg_1,
-        nb_gm_g, nb_gm_c, nb_gm_v, nb_gm_1, nb_in_v;
+    int nb_init_g, nb_init_1, nb_upd_v, nb_upd_g, nb_upd_1, nb_cgb, nb_gmb, nb_cg_g, nb_cg_1, nb_gm_g,
+        nb_gm_c, nb_gm_1, nb_in_v;
     const BatchSet s_init_g = tb.add(d64, init, g64, &nb_init_g);
     const BatchSet s_init_1 = tb.add(d64, init, one, &nb_init_1);
     const IrSet s_upd_v = tb.add(dir, upd, vsh, &nb_upd_v);
@@ -639,17 +707,73 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     const BatchSet s_cgb = tb.add(d64, cg_begin, vsh, &nb_cgb);
     const BatchSet s_gmb = tb.add(d64, gm_begin, vsh, &nb_gmb);
     const BatchSet s_cg_g = tb.add(d64, cg_run, g64, &nb_cg_g);
-    const BatchSet s_cg_v = tb.add(d64, cg_run, vsh, &nb_cg_v);
     const BatchSet s_cg_1 = tb.add(d64, cg_run, one, &nb_cg_1);
     const BatchSet s_gm_g = tb.add(d64, gm_run, g64, &nb_gm_g);
     const BatchSet s_gm_c = tb.add(d64, gm_run, csh, &nb_gm_c);
-    const BatchSet s_gm_v = tb.add(d64, gm_run, vsh, &nb_gm_v);
     const BatchSet s_gm_1 = tb.add(d64, gm_run, one, &nb_gm_1);
     const IrSet s_in_v = tb.add(dir, in_init_all, vsh, &nb_in_v);
+    int nb_dec;
+    const IrSet s_dec = tb.add(dir, dec, one, &nb_dec);
     InnerSets<float> S32;
     InnerSets<bf16_t> S16;
-    build_inner(tb, S32, d32, in_init[0], in_cgb[0], in_gmb[0], in_cg[0], in_gm[0], g32, vsh, cgsb);
-    build_inner(tb, S16, d16, in_init[1], in_cgb[1], in_gmb[1], in_cg[1], in_gm[1], g16, vsh, cgsb);
+    build_inner(tb, S32, d32, in_init[0], in_cgb[0], in_gmb[0], in_gm[0], g32, vsh, cgsb);
+    build_inner(tb, S16, d16, in_init[1], in_cgb[1], in_gmb[1], in_gm[1], g16, vsh, cgsb);
+    // the step stages (one launch per stage position for the CG and GMRES
+    // items of every storage type; the products one launch per storage)
+    std::vector<std::pair<int, int>> e1[3], e2, e3, e4, e5;
+    // CG on the lower triangle (binary64 solves, binary32 inner solves):
+    // product and update in the batched symmetric launches, p update in stage 3
+    std::vector<int> sy64, sy32;
+    auto add_cg = [&](const std::vector<int> &v, int dt) {
+        for (int i : v) {
+            const Req *r = sv->inflight[i];
+            const bool sym = (dt == 0 && r->item.sy) || (dt == 1 && r->in32.sy);
+            if (sym) {
+                (dt == 0 ? sy64 : sy32).push_back(i);
+                e3.push_back({i, SK_SY_PUPDATE | dt << 8});
+                continue;
+            }
+            e1[dt].push_back({i, SK_CG_MATVEC | dt << 8});
+            e2.push_back({i, SK_CG_UPDATE | dt << 8});
+            e3.push_back({i, SK_CG_PUPDATE | dt << 8});
+        }
+    };
+    auto add_gm = [&](const std::vector<int> &v, int dt) {
+        for (int i : v) {
+            e1[dt].push_back({i, SK_GM_MATVEC | dt << 8});
+            e2.push_back({i, SK_GM_CGS0 | dt << 8});
+            e3.push_back({i, SK_GM_CGS1 | dt << 8});
+            e4.push_back({i, SK_GM_CGS2 | dt << 8});
+            e5.push_back({i, SK_GM_GIVENS | dt << 8});
+        }
+    };
+    add_cg(cg_run, 0);
+    add_cg(in_cg[0], 1);
+    add_cg(in_cg[1], 2);
+    add_gm(gm_run, 0);
+    add_gm(in_gm[0], 1);
+    add_gm(in_gm[1], 2);
+    auto stage_blocks = [&](int i, int kind) {
+        const int sk = kind & 255, dt = kind >> 8;
+        if (sk == SK_CG_MATVEC || sk == SK_GM_MATVEC)
+            return dt == 0 ? g64(i) : dt == 1 ? g32(i) : g16(i);
+        if (sk == SK_GM_CGS0 || sk == SK_GM_CGS1 || sk == SK_GM_CGS2) return cgsb[i];
+        return vec_blocks(n_of(i));
+    };
+    StageSet ss1[3];
+    int nb1[3], nb2, nb3, nb4, nb5;
+    for (int k = 0; k < 3; ++k) ss1[k] = tb.stage(d64, d32, d16, e1[k], stage_blocks, &nb1[k]);
+    const StageSet ss2 = tb.stage(d64, d32, d16, e2, stage_blocks, &nb2);
+    const StageSet ss3 = tb.stage(d64, d32, d16, e3, stage_blocks, &nb3);
+    const StageSet ss4 = tb.stage(d64, d32, d16, e4, stage_blocks, &nb4);
+    const StageSet ss5 = tb.stage(d64, d32, d16, e5, stage_blocks, &nb5);
+    auto tiles_of = [&](int i) { return sy_tiles(n_of(i)); };
+    auto fin_of = [&](int i) { return symv_finish_blocks(n_of(i)); };
+    int nb_sy64t, nb_sy64f, nb_sy32t, nb_sy32f;
+    const BatchSet s_sy64t = tb.add(d64, sy64, tiles_of, &nb_sy64t);
+    const BatchSet s_sy64f = tb.add(d64, sy64, fin_of, &nb_sy64f);
+    const BatchSetT<BatchItemT<float, float>> s_sy32t = tb.add(d32, sy32, tiles_of, &nb_sy32t);
+    const BatchSetT<BatchItemT<float, float>> s_sy32f = tb.add(d32, sy32, fin_of, &nb_sy32f);
     if (tb.bytes() > sv->tab_cap) return KS_ENOMEM;
     if (hipMemcpyAsync(sv->dtab, sv->htab, tb.bytes(), hipMemcpyHostToDevice, s) != hipSuccess)
         return KS_EHIP;
@@ -671,6 +795,8 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     IL(IK_UPDATE, s_upd_v, nb_upd_v);
     BL(BK_RESIDUAL, s_upd_g, nb_upd_g, 0);
     BL(BK_RESIDUAL_FINISH, s_upd_1, nb_upd_1, 0);
+    // the refinement check on the new outer residual (device)
+    IL(IK_DECIDE, s_dec, nb_dec);
     // inner set-up: rhs = r / ||r||, d = 0, ||rhs||, r_in = rhs - A_low d
     IL(IK_SCALE, s_in_v, nb_in_v);
     IL(IK_ZERO_D, s_in_v, nb_in_v);
@@ -680,43 +806,37 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     BL(BK_VEC_STATS, S16.init_1, S16.n_init_1, 0);
     BL(BK_RESIDUAL, S16.init_g, S16.n_init_g, 0);
     BL(BK_RESIDUAL_FINISH, S16.init_1, S16.n_init_1, 0);
-    // (re)starts and new GMRES cycles
+    // (re)starts, new GMRES cycles and the starts after a set-up
     BL(BK_CG_BEGIN, s_cgb, nb_cgb, 0);
     BL(BK_GM_BEGIN, s_gmb, nb_gmb, 0);
     BL(BK_CG_BEGIN, S32.cgb, S32.n_cgb, 0);
     BL(BK_GM_BEGIN, S32.gmb, S32.n_gmb, 0);
     BL(BK_CG_BEGIN, S16.cgb, S16.n_cgb, 0);
     BL(BK_GM_BEGIN, S16.gmb, S16.n_gmb, 0);
-    // iterations of every running solve
+    // iterations of every running solve: per step, the products (one launch
+    // per storage), then the four stages of the updates and Gram-Schmidt /
+    // Givens work of every CG and GMRES solve
+#define SL(set, stage, nb, step)                                                      \
+    do {                                                                              \
+        if (stage_launch(set, stage, nb, step, s) != hipSuccess) return KS_EHIP;      \
+    } while (0)
+#define SY(fn, which, set, nb)                                                     \
+    do {                                                                           \
+        if (fn(which, set, nb, s) != hipSuccess) return KS_EHIP;                    \
+    } while (0)
     for (int c = 0; c < sv->chunk; ++c) {
-        BL(BK_CG_MATVEC, s_cg_g, nb_cg_g, 0);
-        BL(BK_CG_MATVEC, S32.cg_g, S32.n_cg_g, 0);
-        BL(BK_CG_MATVEC, S16.cg_g, S16.n_cg_g, 0);
-        BL(BK_CG_UPDATE, s_cg_v, nb_cg_v, 0);
-        BL(BK_CG_UPDATE, S32.cg_v, S32.n_cg_v, 0);
-        BL(BK_CG_UPDATE, S16.cg_v, S16.n_cg_v, 0);
-        BL(BK_CG_PUPDATE, s_cg_v, nb_cg_v, 0);
-        BL(BK_CG_PUPDATE, S32.cg_v, S32.n_cg_v, 0);
-        BL(BK_CG_PUPDATE, S16.cg_v, S16.n_cg_v, 0);
-        BL(BK_GM_MATVEC, s_gm_g, nb_gm_g, 0);
-        BL(BK_GM_MATVEC, S32.gm_g, S32.n_gm_g, 0);
-        BL(BK_GM_MATVEC, S16.gm_g, S16.n_gm_g, 0);
-        BL(BK_GM_CGS0, s_gm_c, nb_gm_c, 0);
-        BL(BK_GM_CGS0, S32.gm_c, S32.n_gm_c, 0);
-        BL(BK_GM_CGS0, S16.gm_c, S16.n_gm_c, 0);
-        BL(BK_GM_CGS1, s_gm_c, nb_gm_c, 0);
-        BL(BK_GM_CGS1, S32.gm_c, S32.n_gm_c, 0);
-        BL(BK_GM_CGS1, S16.gm_c, S16.n_gm_c, 0);
-        BL(BK_GM_CGS2, s_gm_c, nb_gm_c, 0);
-        BL(BK_GM_CGS2, S32.gm_c, S32.n_gm_c, 0);
-        BL(BK_GM_CGS2, S16.gm_c, S16.n_gm_c, 0);
-        BL(BK_GM_GIVENS, s_gm_v, nb_gm_v, 0);
-        BL(BK_GM_GIVENS, S32.gm_v, S32.n_gm_v, 0);
-        BL(BK_GM_GIVENS, S16.gm_v, S16.n_gm_v, 0);
-        BL(BK_GM_ADVANCE, s_gm_1, nb_gm_1, 0);
-        BL(BK_GM_ADVANCE, S32.gm_1, S32.n_gm_1, 0);
-        BL(BK_GM_ADVANCE, S16.gm_1, S16.n_gm_1, 0);
+        for (int k = 0; k < 3; ++k) SL(ss1[k], 10 + k, nb1[k], c);
+        SY(batch_symv, 0, s_sy64t, nb_sy64t);
+        SY(batch_symv32, 0, s_sy32t, nb_sy32t);
+        SL(ss2, 2, nb2, c);
+        SY(batch_symv, 1, s_sy64f, nb_sy64f);
+        SY(batch_symv32, 1, s_sy32f, nb_sy32f);
+        SL(ss3, 3, nb3, c);
+        SL(ss4, 4, nb4, c);
+        SL(ss5, 5, nb5, c);
     }
+#undef SL
+#undef SY
     // true residual of stopped binary64 CG solves (an inner CG stops on its
     // recursive residual alone); end of finished GMRES cycles
     BL(BK_RESIDUAL, s_cg_g, nb_cg_g, 1);
@@ -732,85 +852,97 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     BL(BK_RESIDUAL_FINISH, S16.gm_1, S16.n_gm_1, 3);
 #undef BL
 #undef IL
-    if (gather_states(dptrs, nf, sv->dstage, s) != hipSuccess) return KS_EHIP;
-    if (hipMemcpyAsync(sv->hstage, sv->dstage, (size_t)nf * sizeof(State), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
+    if (gather_states(dptrs, 2 * nf, sv->dstage, s) != hipSuccess) return KS_EHIP;
+    if (hipMemcpyAsync(sv->hstage, sv->dstage, 2 * (size_t)nf * sizeof(State), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return KS_EHIP;
-    // 3. decisions, as in the single-solve drivers
+    // 3. decisions, as in the single-solve drivers: ho is a request's outer
+    // (or only) State, hi its inner solve's
     std::vector<Req *> keep;
     keep.reserve(nf);
     bool zero_fill = false;
     for (int i = 0; i < nf; ++i) {
         Req *r = sv->inflight[i];
-        const State &h = sv->hstage[i];
-        const int f = h.flags;
+        const State &ho = sv->hstage[2 * i], &hi = sv->hstage[2 * i + 1];
         const bool cg = r->p.method == KS_CG;
+        const Phase ph = r->phase;
         int done = NO_OUTCOME;
-        State out = h;  // the binary64 State the outcome is read from
-        int iters = h.iters;
-        if (r->ir && (r->phase == P_INIT || r->phase == P_UPDATE)) {
-            // refinement check on the new outer residual
-            if (r->phase == P_INIT && h.bnorm == 0.0) {
-                if (launch_fill<double>(r->p.n, r->x, 0.0, s) != hipSuccess) return KS_EHIP;
-                zero_fill = true;
-                r->last_outer = h;
-                r->last_outer.res = r->last_outer.resinf = 0.0;
-                done = KS_OK;
-            } else {
-                done = ir_check(sv, r, h);
-            }
-            if (done == KS_EHIP) return KS_EHIP;
-            out = r->last_outer;
-            iters = r->total_iters;
-        } else if (r->phase == P_IN_INIT) {
-            // inner solve set up: the loop head of the single-solve drivers
+        State out = ho;  // the binary64 State the outcome is read from
+        int iters = ho.iters;
+        // the inner solve after its set-up and the steps of this tick: the
+        // loop head of the single-solve drivers when the set-up ended it,
+        // else the end of its pass (or of a GMRES cycle)
+        auto inner_after = [&]() -> int {
+            const int f = hi.flags;
             int st_in = NO_OUTCOME;
-            if (h.bnorm == 0.0)
-                st_in = KS_OK;
-            else if (f & F_TRUE_NONFIN)
-                st_in = KS_NONFINITE;
-            else if (f & F_TRUE_OK)
-                st_in = KS_OK;
-            else if (h.iters >= r->p.max_iter)
-                st_in = KS_MAXITER;
-            if (st_in != NO_OUTCOME)
-                done = ir_after_inner(sv, r, st_in, h.iters);
-            else
-                r->phase = P_IN_BEGIN;
-            if (done == KS_EHIP) return KS_EHIP;
-            out = r->last_outer;
-            iters = r->total_iters;
-        } else if (r->phase == P_IN_BEGIN || r->phase == P_IN_RUN) {
-            const bool ended = cg ? (f & F_STOP) != 0 : ((f & F_STOP) != 0 || h.kcur >= r->L.m);
-            int st_in = NO_OUTCOME;
-            if (!ended) {
-                r->phase = P_IN_RUN;
-            } else if (cg) {
-                if (f & F_BREAK)
-                    st_in = KS_BREAKDOWN;
-                else if (f & F_NONFIN)
-                    st_in = KS_NONFINITE;
-                else
-                    st_in = (f & F_CONV) ? KS_OK : KS_MAXITER;
-            } else {
-                if (f & F_BREAK)
-                    st_in = KS_BREAKDOWN;
-                else if ((f & F_NONFIN) || (f & F_TRUE_NONFIN))
+            if (f & F_SETUP_END) {
+                if (hi.bnorm == 0.0)
+                    st_in = KS_OK;
+                else if (f & F_TRUE_NONFIN)
                     st_in = KS_NONFINITE;
                 else if (f & F_TRUE_OK)
                     st_in = KS_OK;
-                else if (h.iters >= r->p.max_iter)
-                    st_in = KS_MAXITER;
                 else
-                    r->phase = P_IN_BEGIN;  // next cycle of the inner GMRES
+                    st_in = KS_MAXITER;
+            } else {
+                const bool ended = cg ? (f & F_STOP) != 0 : ((f & F_STOP) != 0 || hi.kcur >= r->L.m);
+                if (!ended) {
+                    r->phase = P_IN_RUN;
+                } else if (cg) {
+                    if (f & F_BREAK)
+                        st_in = KS_BREAKDOWN;
+                    else if (f & F_NONFIN)
+                        st_in = KS_NONFINITE;
+                    else
+                        st_in = (f & F_CONV) ? KS_OK : KS_MAXITER;
+                } else {
+                    if (f & F_BREAK)
+                        st_in = KS_BREAKDOWN;
+                    else if ((f & F_NONFIN) || (f & F_TRUE_NONFIN))
+                        st_in = KS_NONFINITE;
+                    else if (f & F_TRUE_OK)
+                        st_in = KS_OK;
+                    else if (hi.iters >= r->p.max_iter)
+                        st_in = KS_MAXITER;
+                    else
+                        r->phase = P_IN_BEGIN;  // next cycle of the inner GMRES
+                }
             }
-            if (st_in != NO_OUTCOME) done = ir_after_inner(sv, r, st_in, h.iters);
+            return st_in != NO_OUTCOME ? ir_after_inner(sv, r, st_in, hi.iters) : NO_OUTCOME;
+        };
+        if (r->ir && (ph == P_INIT || ph == P_UPDATE)) {
+            // the refinement check on the new outer residual ran on the
+            // device; the host repeats it (same arithmetic) to keep its
+            // counters, and the two must agree
+            if (ph == P_INIT && ho.bnorm == 0.0) {
+                if (ho.ir_next != IR_ZERO) return KS_EHIP;
+                if (launch_fill<double>(r->p.n, r->x, 0.0, s) != hipSuccess) return KS_EHIP;
+                zero_fill = true;
+                r->last_outer = ho;
+                r->last_outer.res = r->last_outer.resinf = 0.0;
+                done = KS_OK;
+            } else {
+                const int prec0 = r->prec;
+                done = ir_check(sv, r, ho);
+                if (done == KS_EHIP) return KS_EHIP;
+                const bool go = done == NO_OUTCOME && r->prec == prec0 && r->phase == P_IN_INIT;
+                if (go != (ho.ir_next == IR_GO)) return KS_EHIP;
+                // on go, the inner set-up, start and steps ran in this tick
+                if (go) done = inner_after();
+            }
             if (done == KS_EHIP) return KS_EHIP;
             out = r->last_outer;
             iters = r->total_iters;
-        } else if (r->phase == P_INIT) {
-            if (h.bnorm == 0.0) {
+        } else if (ph == P_IN_INIT || ph == P_IN_BEGIN || ph == P_IN_RUN) {
+            done = inner_after();
+            if (done == KS_EHIP) return KS_EHIP;
+            out = r->last_outer;
+            iters = r->total_iters;
+        } else if (ph == P_INIT && (ho.flags & F_SETUP_END)) {
+            // binary64 set-up that ended the solve (the drivers' loop head)
+            const int f = ho.flags;
+            if (ho.bnorm == 0.0) {
                 if (launch_fill<double>(r->p.n, r->x, 0.0, s) != hipSuccess) return KS_EHIP;
                 zero_fill = true;
                 out.res = out.resinf = 0.0;
@@ -819,13 +951,13 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
                 done = KS_NONFINITE;
             } else if (f & F_TRUE_OK) {
                 done = KS_OK;
-            } else if (h.iters >= r->item.max_iter) {
-                done = KS_MAXITER;
             } else {
-                r->phase = P_BEGIN;
+                done = KS_MAXITER;
             }
         } else {
-            const bool ended = cg ? (f & F_STOP) != 0 : ((f & F_STOP) != 0 || h.kcur >= r->L.m);
+            // a binary64 solve's steps (after its set-up, a restart or a new cycle)
+            const int f = ho.flags;
+            const bool ended = cg ? (f & F_STOP) != 0 : ((f & F_STOP) != 0 || ho.kcur >= r->L.m);
             if (!ended) {
                 r->phase = P_RUN;
             } else {
@@ -836,7 +968,7 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
                     done = KS_NONFINITE;
                 else if (f & F_TRUE_OK)
                     done = KS_OK;
-                else if (h.iters >= r->item.max_iter)
+                else if (ho.iters >= r->item.max_iter)
                     done = KS_MAXITER;
                 else if (cg && r->restarts >= SERVER_CG_MAX_RESTARTS)
                     done = KS_STAGNATED;
@@ -850,8 +982,8 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
             // binary64 finish of a refinement request: one more outer step;
             // success is decided on the backward error of the result
             r->outer++;
-            iters = r->total_iters + h.iters;
-            finish_metrics(r, h);
+            iters = r->total_iters + ho.iters;
+            finish_metrics(r, ho);
             if (r->info.backward_err <= r->p.tol) done = KS_OK;
         }
         if (done != NO_OUTCOME) {

@@ -271,17 +271,16 @@ __device__ __forceinline__ void sy_tile_edge(const SyTile &T, int n, int64_t lda
 //   then the interior tiles (I, J), 1 <= I < n / SY_T, J < I, in row order.
 // st != nullptr: return at once when the Krylov loop has stopped.
 // sig != nullptr: each tile's share of x'A x into sig[tile] (see sy_store).
-__global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void symv_tile_kernel(int n, int64_t lda,
-                                                          const double *__restrict__ A,
-                                                          const double *__restrict__ x,
-                                                          double *__restrict__ W, const State *st,
-                                                          double *__restrict__ sig) {
+// b: the block's index in the launch (the request server's batched launches
+// pass a solve's local block index).
+__device__ __forceinline__ void symv_tile_body(int n, int64_t lda, const double *__restrict__ A,
+                                               const double *__restrict__ x, double *__restrict__ W,
+                                               const State *st, double *__restrict__ sig, int b) {
     __shared__ double rows[SY_T];
     __shared__ double cs[SY_WAVES][SY_T];
     if (st && (st->flags & F_STOP)) return;
     const int nT = div_up(n, SY_T), nTf = n / SY_T;
     const int ne = (nT > nTf) ? nT - 1 : 0;
-    const int b = blockIdx.x;
     int I, J;
     if (b < nT) {
         I = b;
@@ -304,13 +303,19 @@ __global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     sy_store(T, n, ca, rows, cs, x, W, sig);
 }
 
+__global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void symv_tile_kernel(
+    int n, int64_t lda, const double *__restrict__ A, const double *__restrict__ x,
+    double *__restrict__ W, const State *st, double *__restrict__ sig) {
+    symv_tile_body(n, lda, A, x, W, st, sig, blockIdx.x);
+}
+
 // y_j = (row parts of tile row J) + (column parts of tile column J), J = j / SY_T,
 // summed in a fixed order: the SY_FWAVES waves take sources w, w + SY_FWAVES,
 // ... and their sums are added in wave order.  Every wave calls it; afterwards
-// lane l of wave 0 holds y at j0 + l (j0 = blockIdx.x * SY_FIN).
+// lane l of wave 0 holds y at j0 + l (j0 = fb * SY_FIN, fb the finishing block).
 __device__ __forceinline__ double sy_finish_sum(int n, const double *__restrict__ W,
-                                                double (*red)[SY_FIN], int lane, int w) {
-    const int j0 = blockIdx.x * SY_FIN;
+                                                double (*red)[SY_FIN], int lane, int w, int fb) {
+    const int j0 = fb * SY_FIN;
     const int J = j0 / SY_T;
     const int jj = j0 - J * SY_T + lane;
     const int nT = div_up(n, SY_T);
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, co
     if (st && (st->flags & F_STOP)) return;
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
-    const double v = sy_finish_sum(n, W, red, lane, w);
+    const double v = sy_finish_sum(n, W, red, lane, w, blockIdx.x);
     if (w == 0) {
         const int j = blockIdx.x * SY_FIN + lane;
         double contrib = 0.0;
@@ -383,15 +388,16 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_finish_kernel(int n, co
 // x_j += alpha p_j, r_j -= alpha q_j, and the block's r'r and ||x||_inf
 // partials (and ||r||_inf when stopping on the backward error).  The vectors and the shares are loaded before the tile outputs
 // are summed, so their latency is hidden behind that reduction.
-__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
-    int n, const double *__restrict__ W, const double *__restrict__ sig, int ntiles,
-    const double *__restrict__ p, double *__restrict__ x, double *__restrict__ r, State *st,
-    double *__restrict__ prho, int nfb) {
+__device__ __forceinline__ void symv_cg_finish_body(int n, const double *__restrict__ W,
+                                                    const double *__restrict__ sig, int ntiles,
+                                                    const double *__restrict__ p, double *__restrict__ x,
+                                                    double *__restrict__ r, State *st,
+                                                    double *__restrict__ prho, int nfb, int fb) {
     __shared__ double red[SY_FWAVES][SY_FIN];
     __shared__ double sm[SY_FWAVES];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
-    const int j = blockIdx.x * SY_FIN + lane;
+    const int j = fb * SY_FIN + lane;
     const int jc = min(j, n - 1);
     double pj = 0.0, xj = 0.0, rj = 0.0;
     if (w == 0) {
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     // barrier that the others reach (a launch that sees the new flag would
     // have found sigma unusable and skipped the update all the same)
     if (__syncthreads_or((st->flags & F_STOP) != 0)) return;
-    const double qj = sy_finish_sum(n, W, red, lane, w);
+    const double qj = sy_finish_sum(n, W, red, lane, w, fb);
     sg = wave_sum(sg);
     if (lane == 0) sm[w] = sg;
     __syncthreads();
@@ -416,7 +422,7 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
 #pragma unroll
     for (int k = 0; k < SY_FWAVES; ++k) sigma += sm[k];
     const bool ok = finite_d(sigma) && sigma > 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (fb == 0 && threadIdx.x == 0) {
         st->iters += 1;
         st->sigma = sigma;
         st->rho_prev = rho;
@@ -442,17 +448,51 @@ __global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
     s2 = wave_sum(s2);
     xm = wave_max(xm);
     if (lane == 0) {
-        prho[blockIdx.x] = s2;
-        prho[nfb + blockIdx.x] = xm;
+        prho[fb] = s2;
+        prho[nfb + fb] = xm;
     }
     if (eta) {
         // ||r||_inf partials for stopping on the backward error
         rm = wave_max(rm);
-        if (lane == 0) prho[2 * nfb + blockIdx.x] = rm;
+        if (lane == 0) prho[2 * nfb + fb] = rm;
     }
 }
 
+__global__ __launch_bounds__(SY_FWAVES * WAVE) void symv_cg_finish_kernel(
+    int n, const double *__restrict__ W, const double *__restrict__ sig, int ntiles,
+    const double *__restrict__ p, double *__restrict__ x, double *__restrict__ r, State *st,
+    double *__restrict__ prho, int nfb) {
+    symv_cg_finish_body(n, W, sig, ntiles, p, x, r, st, prho, nfb, blockIdx.x);
+}
+
 int symv_finish_blocks(int n) { return div_up(n, SY_FIN); }
+
+// The request server's batched launches: the same bodies with each solve's
+// local block index.
+__global__ __launch_bounds__(SY_NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void b_symv_tile_kernel(
+    BatchSetT<BatchItemT<double, double>> bs) {
+    int l, nb;
+    const auto &it = batch_item(bs, blockIdx.x, l, nb);
+    symv_tile_body(it.n, it.lda, it.A, it.p, it.sy, it.st, it.sy + sy_ws_doubles(it.n), l);
+}
+
+__global__ __launch_bounds__(SY_FWAVES * WAVE) void b_symv_cg_finish_kernel(
+    BatchSetT<BatchItemT<double, double>> bs) {
+    int l, nb;
+    const auto &it = batch_item(bs, blockIdx.x, l, nb);
+    symv_cg_finish_body(it.n, it.sy, it.sy + sy_ws_doubles(it.n), sy_tiles(it.n), it.p, it.x, it.resid,
+                        it.st, symv_cg_rho_part(it.n, it.sy), nb, l);
+}
+
+hipError_t batch_symv(int which, const BatchSetT<BatchItemT<double, double>> &bs, int blocks,
+                      hipStream_t s) {
+    if (bs.count <= 0 || blocks <= 0) return hipSuccess;
+    if (which == 0)
+        b_symv_tile_kernel<<<blocks, SY_NT, 0, s>>>(bs);
+    else
+        b_symv_cg_finish_kernel<<<blocks, SY_FWAVES * WAVE, 0, s>>>(bs);
+    return hipGetLastError();
+}
 
 hipError_t launch_symv(int n, int64_t lda, const double *A, const double *x, double *y,
                        double *W, const State *st, const double *p, double *partial,

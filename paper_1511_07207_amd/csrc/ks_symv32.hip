@@ -73,18 +73,17 @@ __device__ __forceinline__ void s3_group(int lane, int w, int k0, const s3_f4 (&
 // tiles, then (ragged n) the last tile row's other tiles, then the interior
 // tiles in row order.  st != nullptr: return at once after the Krylov loop
 // stopped.  sig != nullptr: the tile's share of x'A x (binary64) in sig[tile].
-__global__ __launch_bounds__(SY_NT) void symv32_tile_kernel(int n, int64_t lda,
-                                                            const float *__restrict__ A,
-                                                            const float *__restrict__ x,
-                                                            float *__restrict__ W, const State *st,
-                                                            double *__restrict__ sig) {
+// b: the block's index in the launch (or a solve's local block index in the
+// request server's batched launches).
+__device__ __forceinline__ void symv32_tile_body(int n, int64_t lda, const float *__restrict__ A,
+                                                 const float *__restrict__ x, float *__restrict__ W,
+                                                 const State *st, double *__restrict__ sig, int b) {
     __shared__ float rows[SY_T];
     __shared__ float cs[S3_WAVES][SY_T];
     __shared__ double sg[S3_WAVES];
     if (st && (st->flags & F_STOP)) return;
     const int nT = div_up(n, SY_T), nTf = n / SY_T;
     const int ne = (nT > nTf) ? nT - 1 : 0;
-    const int b = blockIdx.x;
     int I, J;
     if (b < nT) {
         I = b;
@@ -188,13 +187,20 @@ __global__ __launch_bounds__(SY_NT) void symv32_tile_kernel(int n, int64_t lda,
     }
 }
 
+__global__ __launch_bounds__(SY_NT) void symv32_tile_kernel(int n, int64_t lda, const float *__restrict__ A,
+                                                            const float *__restrict__ x,
+                                                            float *__restrict__ W, const State *st,
+                                                            double *__restrict__ sig) {
+    symv32_tile_body(n, lda, A, x, W, st, sig, blockIdx.x);
+}
+
 // y_j = (row parts of tile row J) + (column parts of tile column J) in a
 // fixed order: wave w takes sources w, w + S3_FWAVES, ..., and the waves'
 // sums are added in wave order.  Every wave calls it; afterwards lane l of
-// wave 0 holds y at blockIdx.x * SY_FIN + l.
+// wave 0 holds y at fb * SY_FIN + l (fb the finishing block).
 __device__ __forceinline__ float s3_finish_sum(int n, const float *__restrict__ W,
-                                               float (*red)[SY_FIN], int lane, int w) {
-    const int j0 = blockIdx.x * SY_FIN;
+                                               float (*red)[SY_FIN], int lane, int w, int fb) {
+    const int j0 = fb * SY_FIN;
     const int J = j0 / SY_T;
     const int jj = j0 - J * SY_T + lane;
     const int nT = div_up(n, SY_T);
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_finish_kernel(int n, 
     __shared__ float red[S3_FWAVES][SY_FIN];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
-    const float v = s3_finish_sum(n, W, red, lane, w);
+    const float v = s3_finish_sum(n, W, red, lane, w, blockIdx.x);
     const int j = blockIdx.x * SY_FIN + lane;
     if (w == 0 && j < n) y[j] = v;
 }
@@ -247,15 +253,16 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_finish_kernel(int n, 
 // update does in binary32: block 0 records the iteration (or the breakdown /
 // non-finite sigma) in st; x_j += alpha p_j, r_j -= alpha q_j with alpha
 // rounded to binary32; the block's r'r and ||x||_inf partials (binary64).
-__global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
-    int n, const float *__restrict__ W, const double *__restrict__ sig, int ntiles,
-    const float *__restrict__ p, float *__restrict__ x, float *__restrict__ r, State *st,
-    double *__restrict__ prho, int nfb) {
+__device__ __forceinline__ void symv32_cg_finish_body(int n, const float *__restrict__ W,
+                                                      const double *__restrict__ sig, int ntiles,
+                                                      const float *__restrict__ p, float *__restrict__ x,
+                                                      float *__restrict__ r, State *st,
+                                                      double *__restrict__ prho, int nfb, int fb) {
     __shared__ float red[S3_FWAVES][SY_FIN];
     __shared__ double sm[S3_FWAVES];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
-    const int j = blockIdx.x * SY_FIN + lane;
+    const int j = fb * SY_FIN + lane;
     const int jc = min(j, n - 1);
     float pj = 0.0f, xj = 0.0f, rj = 0.0f;
     if (w == 0) {
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
     // block 0 of this launch may set F_STOP (breakdown) while other blocks
     // start: one decision per block, so no wave leaves before a barrier
     if (__syncthreads_or((st->flags & F_STOP) != 0)) return;
-    const float qj = s3_finish_sum(n, W, red, lane, w);
+    const float qj = s3_finish_sum(n, W, red, lane, w, fb);
     sgv = wave_sum(sgv);
     if (lane == 0) sm[w] = sgv;
     __syncthreads();
@@ -277,7 +284,7 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
 #pragma unroll
     for (int k = 0; k < S3_FWAVES; ++k) sigma += sm[k];
     const bool ok = finite_d(sigma) && sigma > 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (fb == 0 && threadIdx.x == 0) {
         st->iters += 1;
         st->sigma = sigma;
         st->rho_prev = rho;
@@ -302,9 +309,43 @@ __global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
     s2 = wave_sum(s2);
     xm = wave_max(xm);
     if (lane == 0) {
-        prho[blockIdx.x] = s2;
-        prho[nfb + blockIdx.x] = xm;
+        prho[fb] = s2;
+        prho[nfb + fb] = xm;
     }
+}
+
+__global__ __launch_bounds__(S3_FWAVES * WAVE) void symv32_cg_finish_kernel(
+    int n, const float *__restrict__ W, const double *__restrict__ sig, int ntiles,
+    const float *__restrict__ p, float *__restrict__ x, float *__restrict__ r, State *st,
+    double *__restrict__ prho, int nfb) {
+    symv32_cg_finish_body(n, W, sig, ntiles, p, x, r, st, prho, nfb, blockIdx.x);
+}
+
+// The request server's batched launches (binary32 inner CG solves).
+__global__ __launch_bounds__(SY_NT) void b_symv32_tile_kernel(BatchSetT<BatchItemT<float, float>> bs) {
+    int l, nb;
+    const auto &it = batch_item(bs, blockIdx.x, l, nb);
+    symv32_tile_body(it.n, it.lda, it.A, it.p, reinterpret_cast<float *>(it.sy), it.st,
+                     it.sy + sy_ws_doubles(it.n), l);
+}
+
+__global__ __launch_bounds__(S3_FWAVES * WAVE) void b_symv32_cg_finish_kernel(
+    BatchSetT<BatchItemT<float, float>> bs) {
+    int l, nb;
+    const auto &it = batch_item(bs, blockIdx.x, l, nb);
+    symv32_cg_finish_body(it.n, reinterpret_cast<const float *>(it.sy), it.sy + sy_ws_doubles(it.n),
+                          sy_tiles(it.n), it.p, it.x, it.resid, it.st, symv_cg_rho_part(it.n, it.sy), nb,
+                          l);
+}
+
+hipError_t batch_symv32(int which, const BatchSetT<BatchItemT<float, float>> &bs, int blocks,
+                        hipStream_t s) {
+    if (bs.count <= 0 || blocks <= 0) return hipSuccess;
+    if (which == 0)
+        b_symv32_tile_kernel<<<blocks, SY_NT, 0, s>>>(bs);
+    else
+        b_symv32_cg_finish_kernel<<<blocks, S3_FWAVES * WAVE, 0, s>>>(bs);
+    return hipGetLastError();
 }
 
 hipError_t launch_symv32(int n, int64_t lda, const float *A, const float *x, float *y, float *W,

@@ -265,3 +265,49 @@ def test_server_mixed_request_alone_equals_in_mix(device):
     mixed.close()
     torch.cuda.synchronize()
     assert torch.equal(out[ts[3]][0], xa)
+
+
+def test_server_symmetric_requests_equal_single_solves(device):
+    """CG requests on the lower triangle (KS_FLAG_SYMMETRIC): binary64, and
+    binary32-refined with the binary32 symmetric product, batched with
+    general-product CG, GMRES and bfloat16 requests (whose inner solves keep
+    the general product); each result bit for bit the one-solve path's.  A
+    holds the whole matrix: the true residual reads both triangles."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    cases = [
+        (spd_problem(300, 1e3, seed=41, config_id=6), dict(method="cg", symmetric=True, tol=1e-10)),
+        (spd_problem(1031, 1e4, seed=42, config_id=6), dict(method="cg", symmetric=True, tol=1e-12,
+                                                              stop_backward=True)),
+        (spd_problem(777, 1e3, seed=43, config_id=6), dict(method="cg", symmetric=True,
+                                                             precision="fp32", tol=1e-12)),
+        (spd_problem(257, 1e2, seed=44, config_id=6), dict(method="cg", symmetric=True,
+                                                             precision="bf16", tol=1e-12)),
+        (spd_problem(600, 1e3, seed=45, config_id=6), dict(method="cg", tol=1e-10)),
+        (nonsym_problem(500, seed=46, config_id=6), dict(method="gmres", restart=20, tol=1e-10)),
+    ]
+    srv = krylov.Server(mem_budget_bytes=8 << 30, max_inflight=16, chunk=6)
+    tickets, data = [], []
+    for p, kw in cases:
+        A, b = _t(p.A, device), _t(p.b, device)
+        tickets.append(srv.submit(A, b, **kw))
+        data.append((p, kw, A, b))
+    out = _drain(srv)
+    srv.close()
+    for (p, kw, A, b), t in zip(data, tickets):
+        x, info = out[t]
+        xs, inf1 = krylov.solve(A, b, **kw)
+        torch.cuda.synchronize()
+        print(f"server symmetric n={p.n} {kw} status={info['status']} iters={info['iters']} "
+              f"outer={info['outer_iters']}", flush=True)
+        assert info["status"] == 0, info
+        assert torch.equal(x, xs), (p.n, kw)
+        for key in ("iters", "outer_iters", "precision_used", "restarts"):
+            assert info[key] == inf1[key], (key, info[key], inf1[key])
+        m = oracle.metrics(p.A, p.b, x.cpu().numpy())
+        if kw.get("precision") or kw.get("stop_backward"):
+            assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+        else:
+            assert m["rel_res"] <= kw["tol"]
