@@ -230,10 +230,13 @@ def leg_c3sweep(dev, n, spd_form="qr"):
     """The refinement workload over its condition-number sweep (n = 32768,
     kappa in 1e2, 1e4, 1e6; SPD with CG inner solves, nonsymmetric with
     GMRES(50) inner solves): binary64 stopping on the backward error against
-    binary32 and bfloat16 inner solves, all to eta_inf <= 1e-12.  The
-    nonsymmetric kappa = 1e6 cell stalls (restarted GMRES(50) stops making
-    progress near eta_inf = 1e-8): it runs with a capped budget and is
-    reported with the status and backward error it reached."""
+    binary32 and bfloat16 inner solves, all to eta_inf <= 1e-12, and the
+    factored preconditioners: CG-IR with the binary32 Cholesky factor (SPD)
+    and GMRES(50)-IR with the binary32 LU (nonsymmetric), factorization in
+    create timed apart.  In the nonsymmetric kappa = 1e6 cell the
+    unpreconditioned solves stall (restarted GMRES(50) stops making progress
+    near eta_inf = 1e-8): they run with a capped budget and are reported with
+    the status and backward error they reached."""
     import torch
 
     from paper_1511_07207_amd import krylov
@@ -249,7 +252,7 @@ def leg_c3sweep(dev, n, spd_form="qr"):
             else:
                 prob = nonsym_swept_problem(n, kap, seed=0, config_id=2, backend="torch",
                                             device="cuda")
-                keys = ("fp64", "fp32", "bf16")
+                keys = ("fp64", "fp32", "bf16", "lu32")
             stall = kind == "nonsym_gmres50" and kap >= 1e6
             x = torch.zeros(n, dtype=torch.float64, device=dev)
             res = {}
@@ -257,13 +260,13 @@ def leg_c3sweep(dev, n, spd_form="qr"):
                 prec, sym = key.split("_")[0], key.endswith("_sym")
                 kw = dict(method="cg" if kind == "spd_cg" else "gmres", tol=1e-12, restart=50,
                           timing=True, timing_every=TIMING_EVERY, max_iter=4 * n, symmetric=sym)
-                if stall:
+                if stall and prec != "lu32":
                     kw.update(max_iter=2000 if prec == "fp64" else 800, max_outer=4)
                 if prec == "fp64":
                     kw["stop_backward"] = True
                 else:
                     kw["precision"] = prec
-                if prec == "chol32":
+                if prec in ("chol32", "lu32"):
                     kw["symmetric"] = False
                     kw["max_iter"] = 2000
                 torch.cuda.synchronize()
@@ -277,11 +280,14 @@ def leg_c3sweep(dev, n, spd_form="qr"):
                      "iters": info["iters"], "outer": info["outer_iters"],
                      "precision_used": info["precision_used"], "eta_inf": info["backward_err"],
                      "fwd_err_vs_x_true": float((x - prob.x_true).norm() / prob.x_true.norm())}
-                if prec == "chol32":
-                    # the binary32 block Cholesky in ks_create: n^3 / 3 flops
+                if prec in ("chol32", "lu32"):
+                    # the binary32 factorization in ks_create: n^3 / 3 flops
+                    # (Cholesky), 2 n^3 / 3 (LU)
+                    fl = n ** 3 / 3.0 if prec == "chol32" else 2.0 * n ** 3 / 3.0
                     r["factor_ms"] = round(create_ms, 2)
-                    r["factor_tflops"] = round(n ** 3 / 3.0 / (create_ms * 1e-3) / 1e12, 2)
-                if info["gemv_calls"] and info["precision_used"] == prec and prec != "chol32":
+                    r["factor_tflops"] = round(fl / (create_ms * 1e-3) / 1e12, 2)
+                    r["factor_plus_solve_ms"] = round(create_ms + dt * 1e3, 2)
+                if info["gemv_calls"] and info["precision_used"] == prec and prec not in ("chol32", "lu32"):
                     e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
                     ab = e * n * (n + 1) / 2 if sym else e * n * n
                     r["gemv_gbs"] = round(ab / (info["gemv_ms"] / info["gemv_calls"] * 1e-3) / 1e9, 1)
@@ -431,7 +437,7 @@ def leg_f3(dev, n):
 
 def leg_f4(dev):
     """GMRES-IR with the binary32 block LU: the factorization (in create) at
-    the paper's direct-method sizes, and solves of the nonsymmetric kappa = 1e6
+    the paper's direct-method sizes and up to n = 16384, and solves of the nonsymmetric kappa = 1e6
     family to backward error 1e-12, beside binary64 GMRES(50) on the same
     systems (which stalls there)."""
     import torch
@@ -441,7 +447,7 @@ def leg_f4(dev):
 
     out = {"system": "diag(lambda) + 0.25 G/sqrt(n), lambda log-uniform [1, kappa]",
            "kappa": 1e6, "eta_target": 1e-12}
-    for m in (1000, 2000, 3000, 4096):
+    for m in (1000, 2000, 4096, 8192, 16384):
         prob = nonsym_swept_problem(m, 1e6, seed=0, config_id=8, backend="torch", device="cuda")
         x = torch.zeros(m, dtype=torch.float64, device=dev)
         creates = []

@@ -83,7 +83,7 @@ extern "C" {
                             binary64, left-preconditioned by a binary32 block LU
                             with partial pivoting (the direct-methods section's
                             block algorithm) computed in ks_create; method
-                            KS_GMRES, nrhs 1, n <= 4096.  A factorization with a
+                            KS_GMRES, nrhs 1, n <= 32768.  A factorization with a
                             zero pivot makes ks_solve return KS_BREAKDOWN     */
 #define KS_IR_CHOL32 4   /* CG-IR: binary64 refinement around preconditioned CG
                             in binary64 with M = L L^T, L the binary32 block
@@ -327,14 +327,16 @@ int ks_symv_noalloc(int32_t n, int64_t lda, const double *d_A, const double *d_x
                     void *stream);
 
 /* Binary32 block LU with partial pivoting (the direct-methods section's block
- * algorithm, column blocks of 16; the factorization GMRES-IR uses): d_LU
+ * algorithm, panels of 16 columns inside column blocks of 256 whose trailing
+ * update runs on the matrix cores; the factorization GMRES-IR uses): d_LU
  * (n x lda_lu floats, row-major, lda_lu >= n) receives the binary32 rounding
  * of A factored in place, L (unit diagonal implied) below the diagonal and U
  * on and above it; d_piv[k] (n int32) is the row interchanged with row k at
- * step k, 0-based (whole rows, so P A = L U).  1 <= n <= 4096, else KS_EINVAL.
- * *info = 0, or 1 + the first column whose pivot is zero (the factorization
- * goes on past it).  Allocates and frees one device word; returns after the
- * factorization has finished on `stream`. */
+ * step k, 0-based (whole rows, so P A = L U).  1 <= n <= 32768, else
+ * KS_EINVAL.  *info = 0, or 1 + the first column whose pivot is zero (the
+ * factorization goes on past it).  Allocates and frees an 8 KiB device work
+ * area; returns after the factorization has finished on `stream` (KS_EHIP if
+ * a panel's bounded grid-barrier wait gave up). */
 int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, float *d_LU,
                    int32_t *d_piv, int32_t *info, void *stream);
 

@@ -401,49 +401,17 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
 // the iterates, the slots and the vectors are bit for bit those of the
 // per-launch path after the same number of iterations.
 //
-// Barrier without cache maintenance.  An agent-scope release or acquire
-// fence on gfx950 writes back or invalidates the XCD's L2 (buffer_wbl2 /
-// buffer_inv), and measured at about 0.13 us per block per barrier (8.5 us
-// for 64 blocks) it made the persistent form slower than a launch per
-// iteration.  Here everything one block writes for another (its rows of x,
-// r, p, q, its p'q partials, block 0's slot) is stored with agent-scope
-// relaxed atomics (coherent at device scope) and read back the same way;
-// block b then waits for its own stores to complete (vmcnt(0)), meets its
-// threads at a block barrier and publishes the number of iterations it has
-// finished in bar[b]; thread t < gridDim.x polls bar[t] until it reaches
-// that number.  So no block starts iteration k + 1 before every block's
-// writes of iteration k are visible to it.  The two copies of every vector
-// and partial array alternate by iteration, so a block that runs ahead never
-// overwrites what a slower block still reads.  All blocks take the same stop
-// decision in the same iteration (they reduce the same values in the same
-// order), so none waits for a block that has left.  Every wait is bounded:
-// past `spin_limit` polls the block records FZ_SYNC_TIMEOUT in st->sync_fail
-// and leaves (the host reports an error); co-residency of the grid is
-// guaranteed by the cooperative launch.
+// The blocks meet at grid_barrier (the barrier without cache maintenance):
+// everything one block writes for another (its rows of x, r, p, q, its p'q
+// partials, block 0's slot) is stored with agent-scope relaxed atomics and
+// read back the same way.  The two copies of every vector and partial array
+// alternate by iteration, so a block that runs ahead never overwrites what a
+// slower block still reads.  All blocks take the same stop decision in the
+// same iteration (they reduce the same values in the same order), so none
+// waits for a block that has left.  A wait past `spin_limit` polls records
+// FZ_SYNC_TIMEOUT in st->sync_fail and the blocks leave (the host reports an
+// error); co-residency of the grid is guaranteed by the cooperative launch.
 constexpr int FZ_SYNC_TIMEOUT = 1;
-constexpr int FZ_WAIT_VMEM = 0x0F70;  // s_waitcnt vmcnt(0) (gfx9 encoding: expcnt, lgkmcnt not waited)
-
-__device__ __forceinline__ bool fz_grid_barrier(uint32_t *bar, uint32_t done, uint32_t spin_limit) {
-    __builtin_amdgcn_s_waitcnt(FZ_WAIT_VMEM);
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&bar[blockIdx.x * FZ_BAR_STRIDE], done, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    int late = 0;
-    if (threadIdx.x < gridDim.x) {
-        uint32_t polls = 0;
-        while (__hip_atomic_load(&bar[threadIdx.x * FZ_BAR_STRIDE], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) < done) {
-            if (++polls > spin_limit) {
-                late = 1;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    late = __syncthreads_or(late);
-    return late == 0;
-}
 
 __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
     int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x, double *r0, double *r1,
@@ -464,7 +432,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
                                            max_iter, pnew, sm_sigma, sm_rho);
         cur = 1 - cur;
         if (stopped || k + 1 == nsteps) break;
-        if (!fz_grid_barrier(bar, (uint32_t)(k + 1), spin_limit)) {
+        if (!grid_barrier(bar, (uint32_t)(k + 1), spin_limit)) {
             if (threadIdx.x == 0)
                 __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);

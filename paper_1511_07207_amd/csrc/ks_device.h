@@ -9,6 +9,54 @@
 
 namespace ks {
 
+// ------------------------------------------------------------ grid barrier
+// A barrier across the blocks of a cooperative launch without cache
+// maintenance.  An agent-scope release or acquire fence on gfx950 writes back
+// or invalidates the XCD's L2 (buffer_wbl2 / buffer_inv) and costs about
+// 0.13 us per block per barrier; instead, whatever a block writes for another
+// block before the barrier is stored with agent-scope relaxed atomics
+// (coherent at device scope) and read back the same way after it.  Block b
+// waits for its own stores to complete (vmcnt(0)), meets its threads at a
+// block barrier and publishes `done` in bar[b * BAR_STRIDE]; thread t <
+// gridDim.x then polls bar[t] until it reaches `done`.  So no block passes
+// before every block's coherent writes made before the barrier are visible
+// to it.  `done` must grow from one barrier to the next (the words start at
+// zero).  Every wait is bounded: false when some poll gave up after
+// `spin_limit` tries (the same answer in every thread of the block).
+constexpr int WAIT_VMEM = 0x0F70;  // s_waitcnt vmcnt(0) (gfx9 encoding: expcnt, lgkmcnt not waited)
+
+__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t done, uint32_t spin_limit) {
+    __builtin_amdgcn_s_waitcnt(WAIT_VMEM);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&bar[blockIdx.x * FZ_BAR_STRIDE], done, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    int late = 0;
+    if (threadIdx.x < gridDim.x) {
+        uint32_t polls = 0;
+        while (__hip_atomic_load(&bar[threadIdx.x * FZ_BAR_STRIDE], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) < done) {
+            if (++polls > spin_limit) {
+                late = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    late = __syncthreads_or(late);
+    return late == 0;
+}
+
+// coherent (agent-scope relaxed) loads and stores of what crosses a grid barrier
+template <typename T>
+__device__ __forceinline__ T coh_load(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void coh_store(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- DPP moves
 // dpp_ctrl encodings (GFX9 DPP): quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
 // row_ror:4 = 0x124, row_ror:8 = 0x128.  Every source lane is valid for these

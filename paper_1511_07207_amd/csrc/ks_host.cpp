@@ -633,14 +633,14 @@ int lu_setup(ks_solver *s) {
     const size_t ln = (size_t)round_up(n, 64);
     s->lu_piv = (int *)(s->ws + s->L.lu_off);
     s->lu_perm = s->lu_piv + ln;
-    s->lu_info = s->lu_perm + ln;
-    HIPCHK(hipMemsetAsync(s->lu_info, 0, sizeof(int), sm));
+    s->lu_info = s->lu_perm + ln;  // the factorization's work area
     HIPCHK(launch_lu_factor(n, s->L.lda_low, (float *)s->A_low, s->lu_piv, s->lu_info, sm));
     std::vector<int> piv(n), perm(n);
-    int info = 0;
+    int info[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(piv.data(), s->lu_piv, sizeof(int) * n, hipMemcpyDeviceToHost, sm));
-    HIPCHK(hipMemcpyAsync(&info, s->lu_info, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(info, s->lu_info, sizeof(info), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipStreamSynchronize(sm));
+    if (info[1]) return KS_EHIP;  // a panel's grid barrier timed out
     for (int i = 0; i < n; ++i) perm[i] = i;
     for (int k = 0; k < n; ++k) {
         if (piv[k] < 0 || piv[k] >= n) return KS_EHIP;  // cannot happen; never trust a bad index
@@ -648,7 +648,7 @@ int lu_setup(ks_solver *s) {
     }
     HIPCHK(hipMemcpyAsync(s->lu_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, sm));
     HIPCHK(hipStreamSynchronize(sm));
-    s->lu_sing = info;
+    s->lu_sing = info[0];
     return KS_OK;
 }
 
@@ -1520,17 +1520,16 @@ int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, fl
     int rc = check_device();
     if (rc) return rc;
     hipStream_t sm = (hipStream_t)stream;
-    int *dinfo = nullptr;
-    HIPCHK(hipMalloc((void **)&dinfo, sizeof(int)));
-    int h = 0;
-    hipError_t e = hipMemsetAsync(dinfo, 0, sizeof(int), sm);
-    if (e == hipSuccess) e = launch_convert(n, lda, d_A, KS_DT_F32, lda_lu, d_LU, sm);
-    if (e == hipSuccess) e = launch_lu_factor(n, lda_lu, d_LU, d_piv, dinfo, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, dinfo, sizeof(int), hipMemcpyDeviceToHost, sm);
+    void *work = nullptr;
+    HIPCHK(hipMalloc(&work, LU_WORK_BYTES));
+    int h[2] = {0, 0};
+    hipError_t e = launch_convert(n, lda, d_A, KS_DT_F32, lda_lu, d_LU, sm);
+    if (e == hipSuccess) e = launch_lu_factor(n, lda_lu, d_LU, d_piv, work, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
-    const hipError_t ef = hipFree(dinfo);
-    if (e != hipSuccess || ef != hipSuccess) return KS_EHIP;
-    *info = h;
+    const hipError_t ef = hipFree(work);
+    if (e != hipSuccess || ef != hipSuccess || h[1]) return KS_EHIP;
+    *info = h[0];
     return KS_OK;
 }
 

@@ -197,14 +197,20 @@ hipError_t launch_gs_upper(int n, int64_t lda, const double *A, const double *b,
 hipError_t launch_gs_sweep(int n, int64_t lda, const double *A, double *x, double *c,
                            const State *st, hipStream_t s);
 
-// Binary32 block LU with partial pivoting (GMRES-IR preconditioner): column
-// blocks of LU_NB, n <= LU_MAX_N (the panel block keeps its panel in
-// registers).  factor: LU holds A in binary32 on entry, L (unit, below the
-// diagonal) and U on return, piv[k] the row swapped with row k, info[0] = 1 +
-// the first zero pivot's column (0 if none; must be 0 on entry).
+// Binary32 block LU with partial pivoting (GMRES-IR preconditioner): outer
+// column blocks of 256, panels of LU_NB columns, n <= LU_MAX_N (a panel is
+// held in the registers of at most LU_PANEL_MAX_BLOCKS blocks of
+// LU_PANEL_ROWS rows).  factor: LU holds A in binary32 on entry, L (unit,
+// below the diagonal) and U on return, piv[k] the row swapped with row k.
+// work: LU_WORK_BYTES of device memory (4-byte aligned), owned by the call
+// while it runs; on return its word 0 is 1 + the first zero pivot's column
+// (0 if none) and word 1 is nonzero if a panel's grid barrier timed out.
 constexpr int LU_NB = 16;
-constexpr int LU_MAX_N = 4096;
-hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, int *info, hipStream_t s);
+constexpr int LU_MAX_N = 32768;
+constexpr int LU_PANEL_ROWS = 1024;
+constexpr int LU_PANEL_MAX_BLOCKS = LU_MAX_N / LU_PANEL_ROWS;
+constexpr size_t LU_WORK_BYTES = 8192;
+hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s);
 // dst = U^-1 L^-1 P src (perm: (P v)_i = v[perm[i]]), t scratch; dst may be
 // src; the squares of dst left in `partial` as the GMRES product leaves them
 hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm, const double *src,

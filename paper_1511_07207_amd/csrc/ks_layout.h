@@ -154,10 +154,11 @@ inline Layout make_layout(const ks_params *p) {
         off = align_up(off + (size_t)FZ_BAR_MAX_WORDS * sizeof(uint32_t));
     }
     if (p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {
-        // pivots, the permutation, the factorization's info word (the
-        // Cholesky factorization uses the info word only)
+        // pivots, the permutation, the LU factorization's work area (whose
+        // first word is its info word; the Cholesky factorization uses one
+        // info word at the start of the region)
         L.lu_off = off;
-        off = align_up(off + (2 * (size_t)round_up(n, 64) + 64) * sizeof(int));
+        off = align_up(off + 2 * (size_t)round_up(n, 64) * sizeof(int) + LU_WORK_BYTES);
     }
     L.lda_low = round_up(n, 64);
     if (p->precision == KS_IR_FP32 || p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {

@@ -3,17 +3,36 @@
 // refinement (GMRES-IR).
 //
 // Factorization: the block algorithm of the paper's direct-methods section
-// (Figure 1, equations (1)-(4)), column blocks of LU_NB = 16:
+// (Figure 1, equations (1)-(4)) in two levels.  Outer column blocks of
+// LU_NBO = 256 columns; inside one, panels of LU_NB = 16 columns:
 //   lu_panel_kernel   the panel A(k0:n, k0:k0+16) factored column by column
 //                     with partial pivoting (largest magnitude, first row on
-//                     ties), in one block of 1024 threads that keeps the panel
-//                     in registers (4 rows of 16 per thread: n <= 4096);
-//   lu_swap_kernel    the panel's row interchanges applied to the other columns;
-//   lu_trsm_kernel    the block row of U: unit-lower panel triangle \ A(k0:k0+16, k0+16:n);
-//   lu_update_kernel  the delayed rank-16 update of the trailing matrix.
-// The update has 16 multiply-adds per element read and written (8 bytes),
-// so it is bound by memory traffic, not by arithmetic: a tiled vector-ALU
-// kernel rather than matrix cores.
+//                     ties) by a cooperative grid of up to 32 blocks, each
+//                     holding 1024 rows of the panel in registers; per
+//                     column the blocks publish their candidates (magnitude,
+//                     row, the row's 16 values) and meet once at a grid
+//                     barrier, then every block picks the same pivot and
+//                     eliminates its rows;
+//   lu_swap_kernel    the panel's row interchanges applied to every other
+//                     column (so every row of A(K0:n, K1:n) stays in the same
+//                     state: none of the outer block's updates applied yet);
+//   lu_trsm_kernel    rows k0:k0+16 of U in the outer block's columns: the
+//                     unit-lower panel triangle \ A(k0:k0+16, k0+16:K1);
+//   lu_update_kernel  the panel's rank-16 update of the rest of the outer
+//                     block's columns, A(k0+16:n, k0+16:K1), which the next
+//                     panels read;
+// and once the outer block K0:K1 is factored:
+//   U12 = L11^-1 A(K0:K1, K1:n), row block by row block: lu_trsm_kernel on
+//                     the block's 16 rows, then lu_update_kernel's rank-16
+//                     update of the rows below it in the outer block;
+//   lu_gemm_kernel    the rank-256 update of the trailing matrix
+//                     A(K1:n, K1:n) -= L21 U12 on the matrix cores
+//                     (v_mfma_f32_16x16x4f32).
+// The rank-16 updates have 16 multiply-adds per element read and written (8
+// bytes), bound by memory traffic: a tiled vector-ALU kernel.  The rank-256
+// update has 256 per element, 64 flops per byte of the trailing matrix: a
+// contraction for the matrix cores.  The grouping of the delayed updates
+// changes only the order in which each element's sum is rounded.
 //
 // Application (binary64 vectors, binary32 factors widened): a gather by the
 // permutation, then the forward (unit lower) and backward (upper)
@@ -27,48 +46,67 @@
 
 namespace ks {
 
-constexpr int LU_NT = 1024;              // threads of the panel block
-constexpr int LU_R = LU_MAX_N / LU_NT;   // panel rows per thread
-constexpr int LU_TILE = 64;              // trailing-update tile (rows and columns)
+constexpr int LU_NBO = 256;              // outer column block: K of the trailing update
+constexpr int LU_TILE = 64;              // rank-16 update tile (rows and columns)
 constexpr int TS_SB = 64;                // rows per substitution step
 constexpr int TS_PW = 8;                 // rows per wave in the row updates
 constexpr int TS_WAVES = GEMV_NT / WAVE;
 constexpr int TS_PR = TS_WAVES * TS_PW;  // rows per row-update block
 constexpr int TS_LDT = TS_SB + 1;        // padded LDS row stride of a diagonal tile
-static_assert(LU_R * LU_NT == LU_MAX_N, "the panel fits the block's registers");
 static_assert(LU_NB <= WAVE && LU_NB * LU_NB <= GEMV_NT, "panel width");
+static_assert(LU_NBO % LU_NB == 0, "outer blocks hold whole panels");
 
-// ------------------------------------------------------------ factorization
-struct LuPanelShared {
-    float rowA[LU_NB], rowB[LU_NB];
-    float red_v[LU_NT / WAVE];
-    int red_i[LU_NT / WAVE];
-    int piv;
+// ------------------------------------------------------------------- panel
+constexpr int LP_NT = 256;                       // threads of a panel block
+constexpr int LP_R = LU_PANEL_ROWS / LP_NT;      // panel rows per thread
+constexpr int LP_SLOT = LU_NB + 2;               // a candidate: |a|, row, the row's values
+constexpr uint32_t LP_SPIN_LIMIT = 1u << 20;     // polls before a barrier wait gives up
+static_assert(LP_R * LP_NT == LU_PANEL_ROWS, "rows per block");
+static_assert(LU_PANEL_MAX_BLOCKS <= WAVE, "one candidate per lane");
+// the work area (LU_WORK_BYTES, 32-bit words): [0] info, [1] barrier
+// timeout, [64, 64 + LU_PANEL_MAX_BLOCKS) barrier flags, then from word 128
+// the candidate slots of the two column parities and the two copies of row rj
+constexpr int LW_BAR = 64;
+constexpr int LW_SLOTS = 128;
+constexpr int LW_ROWA = LW_SLOTS + 2 * LU_PANEL_MAX_BLOCKS * LP_SLOT;
+static_assert(LW_BAR + LU_PANEL_MAX_BLOCKS <= LW_SLOTS, "barrier flags");
+static_assert((LW_ROWA + 2 * LU_NB) * 4 <= LU_WORK_BYTES, "work area");
+
+struct LpShared {
+    float red_v[LP_NT / WAVE];
+    int red_i[LP_NT / WAVE];
+    float cand[LU_PANEL_MAX_BLOCKS * LP_SLOT];  // every block's candidate, after the barrier
+    float rowA[LU_NB];                          // row rj before the interchange
+    int bi, piv, gw;
 };
 
 // Column J of the panel (J a template parameter, so that the panel stays in
-// registers: every index into p is a compile-time constant).
+// registers: every index into p is a compile-time constant).  False when the
+// grid barrier timed out.
 template <int J>
-__device__ __forceinline__ void lu_panel_col(int n, int k0, int b, float (&p)[LU_R][LU_NB],
-                                             LuPanelShared &sh, int *__restrict__ piv,
-                                             int *__restrict__ info) {
-    if (J >= b) return;  // uniform: the last panel may be narrower
+__device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
+                                             LpShared &sh, int *__restrict__ piv, uint32_t *work) {
+    if (J >= b) return true;  // uniform: the last panel may be narrower
     const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
     const int rj = k0 + J;
-    // pivot: largest |a(r, J)| over rows r >= rj, the first such row; the
-    // search starts from row rj, so the pivot is a row of the panel even when
-    // no magnitude compares greater (a column of NaNs)
+    float *slots = reinterpret_cast<float *>(work + LW_SLOTS) + (J & 1) * LU_PANEL_MAX_BLOCKS * LP_SLOT;
+    float *rowAg = reinterpret_cast<float *>(work + LW_ROWA) + (J & 1) * LU_NB;
+    // the block's candidate: largest |a(r, J)| over its rows r >= rj, the
+    // first such row; the search starts from row rj, so the pivot is a row of
+    // the panel even when no magnitude compares greater (a column of NaNs)
     float bv = -1.0f;
     int bi = rj;
 #pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-        const int r = k0 + t + LU_NT * q;
+    for (int q = 0; q < LP_R; ++q) {
+        const int r = row0 + t + LP_NT * q;
         const float a = fabsf(p[q][J]);
         if (r >= rj && r < n && a > bv) {
             bv = a;
             bi = r;
         }
     }
+    // (largest magnitude, lowest row on ties: a total order, so any reduction
+    // order picks the same row)
 #pragma unroll
     for (int off = WAVE / 2; off >= 1; off >>= 1) {
         const float ov = __shfl_xor(bv, off);
@@ -83,12 +121,9 @@ __device__ __forceinline__ void lu_panel_col(int n, int k0, int b, float (&p)[LU
         sh.red_i[wv] = bi;
     }
     __syncthreads();
-    // the waves' candidates reduced by wave 0 with the same rule (the largest
-    // magnitude, the lowest row on ties: a total order, so any reduction
-    // order picks the same row)
+    float *myslot = slots + blockIdx.x * LP_SLOT;
     if (wv == 0) {
-        constexpr int NW = LU_NT / WAVE;
-        static_assert(NW <= WAVE && (NW & (NW - 1)) == 0, "one candidate per lane");
+        constexpr int NW = LP_NT / WAVE;
         float v = lane < NW ? sh.red_v[lane] : -2.0f;
         int i = lane < NW ? sh.red_i[lane] : rj;
 #pragma unroll
@@ -101,89 +136,132 @@ __device__ __forceinline__ void lu_panel_col(int n, int k0, int b, float (&p)[LU
             }
         }
         if (lane == 0) {
+            sh.bi = i;
+            coh_store(myslot, v);
+            coh_store(myslot + 1, __int_as_float(i));
+        }
+    }
+    __syncthreads();
+    // publish the candidate row's values and (block 0) row rj's
+    const int cb = sh.bi;
+#pragma unroll
+    for (int q = 0; q < LP_R; ++q) {
+        const int r = row0 + t + LP_NT * q;
+        if (r == cb && r < n) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; ++c) coh_store(myslot + 2 + c, p[q][c]);
+        }
+        if (r == rj) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; ++c) coh_store(rowAg + c, p[q][c]);
+        }
+    }
+    if (!grid_barrier(work + LW_BAR, (uint32_t)(rj + 1), LP_SPIN_LIMIT)) return false;
+    const int G = gridDim.x;
+    for (int e = t; e < G * LP_SLOT; e += LP_NT) sh.cand[e] = coh_load(slots + e);
+    if (t < LU_NB) sh.rowA[t] = coh_load(rowAg + t);
+    __syncthreads();
+    if (wv == 0) {
+        float v = lane < G ? sh.cand[lane * LP_SLOT] : -2.0f;
+        int i = lane < G ? __float_as_int(sh.cand[lane * LP_SLOT + 1]) : rj;
+        int gw = lane < G ? lane : 0;
+#pragma unroll
+        for (int off = WAVE / 2; off >= 1; off >>= 1) {
+            const float ov = __shfl_xor(v, off);
+            const int oi = __shfl_xor(i, off);
+            const int og = __shfl_xor(gw, off);
+            if (ov > v || (ov == v && (oi < i || (oi == i && og < gw)))) {
+                v = ov;
+                i = oi;
+                gw = og;
+            }
+        }
+        if (lane == 0) {
             sh.piv = i;
-            piv[rj] = i;
+            sh.gw = gw;
+            if (blockIdx.x == 0) piv[rj] = i;
         }
     }
     __syncthreads();
     const int pr = sh.piv;
-    // interchange rows rj and pr through LDS, each register row matched by
-    // its row index
+    // the pivot row: published by the block that holds it (row rj itself
+    // when no other row won)
+    const float *rowB = pr == rj ? sh.rowA : sh.cand + sh.gw * LP_SLOT + 2;
+    if (pr != rj) {
 #pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-        const int r = k0 + t + LU_NT * q;
-        if (r == rj) {
+        for (int q = 0; q < LP_R; ++q) {
+            const int r = row0 + t + LP_NT * q;
+            if (r == rj) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c) sh.rowA[c] = p[q][c];
-        }
-        if (r == pr) {
+                for (int c = 0; c < LU_NB; ++c) p[q][c] = rowB[c];
+            } else if (r == pr) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c) sh.rowB[c] = p[q][c];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-        const int r = k0 + t + LU_NT * q;
-        if (pr != rj && r == rj) {
-#pragma unroll
-            for (int c = 0; c < LU_NB; ++c) p[q][c] = sh.rowB[c];
-        } else if (pr != rj && r == pr) {
-#pragma unroll
-            for (int c = 0; c < LU_NB; ++c) p[q][c] = sh.rowA[c];
+                for (int c = 0; c < LU_NB; ++c) p[q][c] = sh.rowA[c];
+            }
         }
     }
-    // eliminate below the pivot (the pivot row is now rowB)
-    const float d = sh.rowB[J];
+    // eliminate below the pivot
+    const float d = rowB[J];
     if (d != 0.0f) {
 #pragma unroll
-        for (int q = 0; q < LU_R; ++q) {
-            const int r = k0 + t + LU_NT * q;
+        for (int q = 0; q < LP_R; ++q) {
+            const int r = row0 + t + LP_NT * q;
             if (r > rj && r < n) {
                 const float l = p[q][J] / d;
                 p[q][J] = l;
 #pragma unroll
-                for (int c = J + 1; c < LU_NB; ++c) p[q][c] = p[q][c] - l * sh.rowB[c];
+                for (int c = J + 1; c < LU_NB; ++c) p[q][c] = p[q][c] - l * rowB[c];
             }
         }
-    } else if (t == 0 && info[0] == 0) {
-        info[0] = rj + 1;
+    } else if (blockIdx.x == 0 && t == 0 && work[0] == 0) {
+        work[0] = rj + 1;  // the first zero pivot (block 0 alone writes the info word)
     }
-    __syncthreads();
+    return true;
 }
 
 template <int... J>
-__device__ __forceinline__ void lu_panel_cols(int n, int k0, int b, float (&p)[LU_R][LU_NB],
-                                              LuPanelShared &sh, int *__restrict__ piv,
-                                              int *__restrict__ info,
+__device__ __forceinline__ bool lu_panel_cols(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
+                                              LpShared &sh, int *__restrict__ piv, uint32_t *work,
                                               std::integer_sequence<int, J...>) {
-    (lu_panel_col<J>(n, k0, b, p, sh, piv, info), ...);
+    return (lu_panel_col<J>(n, k0, b, row0, p, sh, piv, work) && ...);
 }
 
-__global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int n, int64_t ldl, float *__restrict__ LU,
+// Block g holds rows k0 + 1024 g + t + 256 q (q < 4) of the panel.  The
+// barrier flags count the columns finished, rj + 1, which grows from one
+// panel launch to the next.
+__global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, float *__restrict__ LU,
                                                          int k0, int *__restrict__ piv,
-                                                         int *__restrict__ info) {
-    __shared__ LuPanelShared sh;
+                                                         uint32_t *__restrict__ work) {
+    __shared__ LpShared sh;
     const int t = threadIdx.x;
     const int b = min(LU_NB, n - k0);
-    float p[LU_R][LU_NB];
+    const int row0 = k0 + blockIdx.x * LU_PANEL_ROWS;
+    float p[LP_R][LU_NB];
 #pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-        const int r = k0 + t + LU_NT * q;
+    for (int q = 0; q < LP_R; ++q) {
+        const int r = row0 + t + LP_NT * q;
 #pragma unroll
         for (int c = 0; c < LU_NB; ++c)
             p[q][c] = (r < n && c < b) ? LU[(int64_t)r * ldl + k0 + c] : 0.0f;
     }
-    lu_panel_cols(n, k0, b, p, sh, piv, info, std::make_integer_sequence<int, LU_NB>{});
+    if (!lu_panel_cols(n, k0, b, row0, p, sh, piv, work, std::make_integer_sequence<int, LU_NB>{})) {
+        if (t == 0) coh_store(work + 1, 1u);
+        return;
+    }
 #pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-        const int r = k0 + t + LU_NT * q;
+    for (int q = 0; q < LP_R; ++q) {
+        const int r = row0 + t + LP_NT * q;
         if (r < n) {
 #pragma unroll
             for (int c = 0; c < LU_NB; ++c)
                 if (c < b) LU[(int64_t)r * ldl + k0 + c] = p[q][c];
         }
     }
+}
+
+// info, the timeout word and the barrier flags start at zero
+__global__ void lu_work_reset_kernel(uint32_t *work) {
+    for (int i = threadIdx.x; i < LW_SLOTS; i += blockDim.x) work[i] = 0u;
 }
 
 // the panel's interchanges, in order, on every column outside the panel
@@ -202,17 +280,17 @@ __global__ __launch_bounds__(GEMV_NT) void lu_swap_kernel(int n, int64_t ldl, fl
     }
 }
 
-// the block row of U: z = L00^-1 A(k0:k0+b, c), one column per thread
+// rows k0:k0+b of U in columns [cs, ce): z = L00^-1 A(k0:k0+b, c), one column per thread
 __global__ __launch_bounds__(GEMV_NT) void lu_trsm_kernel(int n, int64_t ldl, float *__restrict__ LU,
-                                                          int k0, int b) {
+                                                          int k0, int b, int cs, int ce) {
     __shared__ float L00[LU_NB][LU_NB];
     {
         const int i = threadIdx.x / LU_NB, j = threadIdx.x % LU_NB;
         if (i < LU_NB) L00[i][j] = (i < b && j < b) ? LU[(int64_t)(k0 + i) * ldl + k0 + j] : 0.0f;
     }
     __syncthreads();
-    const int c = k0 + b + blockIdx.x * GEMV_NT + threadIdx.x;
-    if (c >= n) return;
+    const int c = cs + blockIdx.x * GEMV_NT + threadIdx.x;
+    if (c >= ce) return;
     float z[LU_NB];
 #pragma unroll
     for (int i = 0; i < LU_NB; ++i) z[i] = (i < b) ? LU[(int64_t)(k0 + i) * ldl + c] : 0.0f;
@@ -228,40 +306,185 @@ __global__ __launch_bounds__(GEMV_NT) void lu_trsm_kernel(int n, int64_t ldl, fl
         if (i < b) LU[(int64_t)(k0 + i) * ldl + c] = z[i];
 }
 
-// A(k1:n, k1:n) -= A(k1:n, k0:k1) A(k0:k1, k1:n), k1 = k0 + b; 64 x 64 tiles,
-// each thread 4 x 4 (rows tr + 16 i, columns tc + 16 j)
+// A(r, c) -= sum_{j < b} A(r, k0 + j) A(k0 + j, c), k1 = k0 + b, on two
+// regions: rows [k1, n) x columns [k1, kend) (the rest of the outer block's
+// columns) and rows [k1, kend) x columns [kend, n) (the rest of its rows).
+// 64 x 64 tiles, each thread 4 x 4 (rows tr + 16 i, columns tc + 16 j); the
+// first t1r x t1c blocks take region one, the others region two (t2c tile
+// columns).
 __global__ __launch_bounds__(GEMV_NT) void lu_update_kernel(int n, int64_t ldl, float *__restrict__ LU,
-                                                            int k0, int b) {
+                                                            int k0, int b, int kend, int t1r, int t1c,
+                                                            int t2c) {
     __shared__ float Ls[LU_TILE][LU_NB + 1];
     __shared__ float Us[LU_NB][LU_TILE];
     const int k1 = k0 + b;
-    const int r0 = k1 + blockIdx.y * LU_TILE, c0 = k1 + blockIdx.x * LU_TILE;
+    int r0, c0, rlim, clim;
+    const int bx = blockIdx.x;
+    if (bx < t1r * t1c) {
+        r0 = k1 + (bx / t1c) * LU_TILE, c0 = k1 + (bx % t1c) * LU_TILE;
+        rlim = n, clim = kend;
+    } else {
+        const int e = bx - t1r * t1c;
+        r0 = k1 + (e / t2c) * LU_TILE, c0 = kend + (e % t2c) * LU_TILE;
+        rlim = kend, clim = n;
+    }
 #pragma unroll
     for (int e = 0; e < LU_TILE * LU_NB / GEMV_NT; ++e) {
         const int idx = threadIdx.x + GEMV_NT * e;
         const int rr = idx / LU_NB, jj = idx % LU_NB;
         const int r = r0 + rr;
-        Ls[rr][jj] = (r < n && jj < b) ? LU[(int64_t)r * ldl + k0 + jj] : 0.0f;
+        Ls[rr][jj] = (r < rlim && jj < b) ? LU[(int64_t)r * ldl + k0 + jj] : 0.0f;
         const int j2 = idx / LU_TILE, cc = idx % LU_TILE;
         const int c = c0 + cc;
-        Us[j2][cc] = (c < n && j2 < b) ? LU[(int64_t)(k0 + j2) * ldl + c] : 0.0f;
+        Us[j2][cc] = (c < clim && j2 < b) ? LU[(int64_t)(k0 + j2) * ldl + c] : 0.0f;
     }
     __syncthreads();
     const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int rr = tr + 16 * i, r = r0 + rr;
-        if (r >= n) continue;
+        if (r >= rlim) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int cc = tc + 16 * j, c = c0 + cc;
-            if (c >= n) continue;
+            if (c >= clim) continue;
             float s = LU[(int64_t)r * ldl + c];
 #pragma unroll
             for (int jj = 0; jj < LU_NB; ++jj) s = s - Ls[rr][jj] * Us[jj][cc];
             LU[(int64_t)r * ldl + c] = s;
         }
     }
+}
+
+// ------------------------------------------------- trailing update (MFMA)
+// A(K1:n, K1:n) -= A(K1:n, K0:K1) A(K0:K1, K1:n), K = K1 - K0 a multiple of
+// LG_BK.  A block of four waves owns a 128 x 128 tile, each wave a 64 x 64
+// quarter as 4 x 4 tiles of v_mfma_f32_16x16x4f32.  K streams through LDS in
+// chunks of 32 (double-buffered: the next chunk's global loads are in flight
+// while the matrix cores work on the current one).  Lane l of a wave (g = l /
+// 16, c = l % 16) feeds step s of a chunk with k = 8 g + s: A operand row c
+// of a row tile, B operand column c of a column tile (the sum over k is the
+// same, in the matrix core's order); accumulator item v of lane l is
+// C[4 g + v][c].  Blocks are numbered round-robin over the eight XCDs, so
+// block b takes logical tile (b % 8) q + b / 8 (q tiles per XCD), and the
+// logical tiles run down groups of 8 tile rows: the tiles in flight on one
+// XCD share rows of L21 and columns of U12 in its L2.
+constexpr int LG_BM = 128, LG_BN = 128, LG_BK = 32, LG_NT = 256;
+constexpr int LG_LDA = LG_BK + 4;  // LDS row stride of the L21 chunk (16-byte aligned rows)
+constexpr int LG_LDB = LG_BN + 4;  // LDS row stride of the U12 chunk
+constexpr int LG_GROUP = 8;
+constexpr int LG_XCD = 8;
+static_assert(LU_NBO % LG_BK == 0, "K in whole chunks");
+
+typedef float lg_f4 __attribute__((ext_vector_type(4)));
+
+template <bool VEC>
+__device__ __forceinline__ lg_f4 lg_load4(const float *p, int valid) {
+    if (VEC && valid >= 4) return *reinterpret_cast<const lg_f4 *>(p);
+    lg_f4 v;
+    v.x = valid > 0 ? p[0] : 0.0f;
+    v.y = valid > 1 ? p[1] : 0.0f;
+    v.z = valid > 2 ? p[2] : 0.0f;
+    v.w = valid > 3 ? p[3] : 0.0f;
+    return v;
+}
+
+__device__ __forceinline__ bool lg_tile(int bid, int tiles_r, int tiles_c, int &tr, int &tc) {
+    const int total = tiles_r * tiles_c;
+    const int per_xcd = div_up(total, LG_XCD);
+    const int L = (bid % LG_XCD) * per_xcd + bid / LG_XCD;
+    if (L >= total) return false;
+    const int per_group = LG_GROUP * tiles_c;
+    const int first = (L / per_group) * LG_GROUP;
+    const int gm = min(tiles_r - first, LG_GROUP);
+    const int l = L % per_group;
+    tr = first + l % gm;
+    tc = l / gm;
+    return true;
+}
+
+// VEC: 16-byte loads (LU 16-byte aligned, ldl a multiple of 4)
+template <bool VEC>
+__global__ __launch_bounds__(LG_NT) void lu_gemm_kernel(int n, int64_t ldl, float *__restrict__ LU, int K0,
+                                                        int K1, int tiles_r, int tiles_c) {
+    __shared__ __attribute__((aligned(16))) float As[2][LG_BM * LG_LDA];
+    __shared__ __attribute__((aligned(16))) float Bs[2][LG_BK * LG_LDB];
+    int tr, tc;
+    if (!lg_tile(blockIdx.x, tiles_r, tiles_c, tr, tc)) return;
+    const int r0 = K1 + tr * LG_BM, c0 = K1 + tc * LG_BN;
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    const int g = lane >> 4, c = lane & 15;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int nch = (K1 - K0) / LG_BK;
+    // staging: L21 rows t / 8 + 32 i, k = 4 (t % 8); U12 rows t / 32 + 8 i, columns 4 (t % 32)
+    const int ar = t / 8, ak = 4 * (t % 8);
+    const int bk = t / 32, bc = 4 * (t % 32);
+    lg_f4 ra[4], rb[4];
+    auto gload = [&](int ch) {
+        const int kb = K0 + ch * LG_BK;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + ar + 32 * i;
+            ra[i] = lg_load4<VEC>(LU + (int64_t)min(r, n - 1) * ldl + kb + ak, r < n ? 4 : 0);
+            rb[i] = lg_load4<VEC>(LU + (int64_t)(kb + bk + 8 * i) * ldl + c0 + bc, n - (c0 + bc));
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<lg_f4 *>(&As[buf][(ar + 32 * i) * LG_LDA + ak]) = ra[i];
+            *reinterpret_cast<lg_f4 *>(&Bs[buf][(bk + 8 * i) * LG_LDB + bc]) = rb[i];
+        }
+    };
+    lg_f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = lg_f4{0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) gload(ch + 1);
+        const float *as = As[buf];
+        const float *bs = Bs[buf];
+        float a[4][8], bq[4][8];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const lg_f4 *pa = reinterpret_cast<const lg_f4 *>(as + (wr + 16 * rt + c) * LG_LDA + 8 * g);
+            const lg_f4 x = pa[0], y = pa[1];
+            a[rt][0] = x.x, a[rt][1] = x.y, a[rt][2] = x.z, a[rt][3] = x.w;
+            a[rt][4] = y.x, a[rt][5] = y.y, a[rt][6] = y.z, a[rt][7] = y.w;
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) bq[ct][s] = bs[(8 * g + s) * LG_LDB + wc + 16 * ct + c];
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][s], bq[ct][s], acc[rt][ct], 0, 0, 0);
+        if (ch + 1 < nch) sstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = c0 + wc + 16 * ct + c;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + wr + 16 * rt + 4 * g + v;
+                if (row < n && col < n) {
+                    float *pc = LU + (int64_t)row * ldl + col;
+                    *pc = *pc - acc[rt][ct][v];
+                }
+            }
+        }
 }
 
 // ------------------------------------------------------------- application
@@ -463,16 +686,47 @@ __global__ __launch_bounds__(VEC_NT) void lu_xupdate_kernel(int n, double *__res
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, int *info, hipStream_t s) {
-    for (int k0 = 0; k0 < n; k0 += LU_NB) {
-        const int b = min(LU_NB, n - k0);
-        lu_panel_kernel<<<1, LU_NT, 0, s>>>(n, ldl, LU, k0, piv, info);
-        lu_swap_kernel<<<div_up(n, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, piv);
-        const int rest = n - k0 - b;
-        if (rest > 0) {
-            lu_trsm_kernel<<<div_up(rest, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b);
-            const dim3 grid(div_up(rest, LU_TILE), div_up(rest, LU_TILE));
-            lu_update_kernel<<<grid, GEMV_NT, 0, s>>>(n, ldl, LU, k0, b);
+hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s) {
+    if (n < 1 || n > LU_MAX_N) return hipErrorInvalidValue;
+    uint32_t *w = static_cast<uint32_t *>(work);
+    lu_work_reset_kernel<<<1, WAVE, 0, s>>>(w);
+    const bool vec = ldl % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
+    for (int K0 = 0; K0 < n; K0 += LU_NBO) {
+        const int K1 = min(K0 + LU_NBO, n);
+        for (int k0 = K0; k0 < K1; k0 += LU_NB) {
+            const int b = min(LU_NB, n - k0), k1 = k0 + b;
+            const int G = div_up(n - k0, LU_PANEL_ROWS);
+            int an = n, ak0 = k0;
+            int64_t aldl = ldl;
+            float *aLU = LU;
+            int *apiv = piv;
+            void *args[] = {&an, &aldl, &aLU, &ak0, &apiv, &w};
+            const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(lu_panel_kernel),
+                                                            dim3(G), dim3(LP_NT), args, 0, s);
+            if (e != hipSuccess) return e;
+            lu_swap_kernel<<<div_up(n, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, piv);
+            if (k1 < K1) {
+                lu_trsm_kernel<<<div_up(K1 - k1, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, k1, K1);
+                const int t1r = div_up(n - k1, LU_TILE), t1c = div_up(K1 - k1, LU_TILE);
+                lu_update_kernel<<<t1r * t1c, GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, K1, t1r, t1c, 1);
+            }
+        }
+        if (K1 < n) {
+            // U12, row block by row block (region two of lu_update_kernel only)
+            for (int k0 = K0; k0 < K1; k0 += LU_NB) {
+                const int k1 = k0 + LU_NB;
+                lu_trsm_kernel<<<div_up(n - K1, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, LU_NB, K1, n);
+                if (k1 < K1) {
+                    const int t2r = div_up(K1 - k1, LU_TILE), t2c = div_up(n - K1, LU_TILE);
+                    lu_update_kernel<<<t2r * t2c, GEMV_NT, 0, s>>>(n, ldl, LU, k0, LU_NB, K1, 0, 1, t2c);
+                }
+            }
+            const int tr = div_up(n - K1, LG_BM), tc = div_up(n - K1, LG_BN);
+            const int grid = LG_XCD * div_up(tr * tc, LG_XCD);
+            if (vec)
+                lu_gemm_kernel<true><<<grid, LG_NT, 0, s>>>(n, ldl, LU, K0, K1, tr, tc);
+            else
+                lu_gemm_kernel<false><<<grid, LG_NT, 0, s>>>(n, ldl, LU, K0, K1, tr, tc);
         }
     }
     return hipGetLastError();

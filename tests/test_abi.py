@@ -139,13 +139,16 @@ def test_gmres_ir_lu_parameters_on_host():
         r.precision = N.KS_IR_LU32
         assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == N.KS_EINVAL
     r = N.KsParams()
-    assert L.ks_params_init(ctypes.byref(r), 4097, N.KS_GMRES) == 0
+    assert L.ks_params_init(ctypes.byref(r), 32769, N.KS_GMRES) == 0
     r.precision = N.KS_IR_LU32
     assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == N.KS_EINVAL
-    r.n = r.lda = 4096
+    r.n = r.lda = 32768
     assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == 0
+    # the binary64 A, its binary32 copy holding the factors, and the 8 KiB
+    # work area of the factorization beside the pivots
+    assert sz.value >= 32768 * 32768 * (8 + 4) + 8192
     info = ctypes.c_int32(0)
-    assert L.ks_lu32_factor(4097, 4097, None, 4097, None, None, ctypes.byref(info), None) == N.KS_EINVAL
+    assert L.ks_lu32_factor(32769, 32769, None, 32769, None, None, ctypes.byref(info), None) == N.KS_EINVAL
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")

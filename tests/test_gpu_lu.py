@@ -52,7 +52,7 @@ def _gpu_lu(A, device):
     return LU.cpu().numpy(), piv.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("n", [1, 5, 16, 17, 100, 257, 300])
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 100, 257, 300, 520])
 def test_lu32_factor_matches_oracle(device, n):
     print(f"lu32 n={n}", flush=True)
     A = np.random.default_rng(100 + n).standard_normal((n, n))
@@ -68,7 +68,7 @@ def test_lu32_factor_matches_oracle(device, n):
     assert np.all(np.abs(L @ Uf - Lo @ Uo) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("n", [64, 1000, 2049])
+@pytest.mark.parametrize("n", [64, 1000, 1500, 2049, 2600])
 def test_lu32_backward_error_bound(device, n):
     print(f"lu32 bound n={n}", flush=True)
     A = np.random.default_rng(200 + n).standard_normal((n, n))
@@ -81,23 +81,41 @@ def test_lu32_backward_error_bound(device, n):
     assert np.abs(np.tril(LU, -1)).max(initial=0.0) <= 1.0
 
 
-def test_lu32_maximum_size_sampled_rows(device):
-    n = 4096
-    print(f"lu32 n={n} (sampled rows)", flush=True)
+@pytest.mark.parametrize("n", [4096, 32768])
+def test_lu32_large_sampled_rows(device, n):
+    """64 sampled rows of P A32 - L U against the bound, the pivots valid
+    (row k or below at step k) and every multiplier at most 1 in magnitude;
+    n = 32768 is the largest size (32 panel blocks at the first panel)."""
+    print(f"lu32 n={n} (sampled rows): generating", flush=True)
     A = np.random.default_rng(300).standard_normal((n, n))
     LU, piv, info = _gpu_lu(A, device)
+    print("  factored", flush=True)
     assert info == 0
-    L, Uf, perm = _parts(LU, piv)
-    rows = np.sort(np.random.default_rng(301).choice(n, 64, replace=False))
-    A32 = A.astype(np.float32).astype(np.float64)
-    gamma = n * U32 / (1 - n * U32)
-    lhs = np.abs(A32[perm[rows]] - L[rows] @ Uf)
-    assert np.all(lhs <= gamma * (np.abs(L[rows]) @ np.abs(Uf)) + 1e-300)
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
     assert np.abs(np.tril(LU, -1)).max() <= 1.0
+    perm = np.arange(n)
+    for k, p in enumerate(piv):
+        perm[[k, p]] = perm[[p, k]]
+    rows = np.sort(np.random.default_rng(301).choice(n, 64, replace=False))
+    # rows `rows` of the unit lower L (columns left of each row's own index)
+    Lr = np.where(np.arange(n)[None, :] < rows[:, None], LU[rows].astype(np.float64), 0.0)
+    Lr[np.arange(64), rows] = 1.0
+    Uf = np.triu(LU).astype(np.float64)
+    del LU
+    A32 = A[perm[rows]].astype(np.float32).astype(np.float64)
+    del A
+    gamma = n * U32 / (1 - n * U32)
+    lhs = np.abs(A32 - Lr @ Uf)
+    np.abs(Uf, out=Uf)
+    assert np.all(lhs <= gamma * (np.abs(Lr) @ Uf) + 1e-300)
 
 
-def test_lu32_exact_factorization_bitwise(device):
-    n = 40
+@pytest.mark.parametrize("n,zero_col", [(40, 7), (1100, 20)])
+def test_lu32_exact_factorization_bitwise(device, n, zero_col):
+    """An exactly representable L0 U0 (every partial sum exact, so any order
+    of summation gives L0 and U0); n = 1100 crosses the rank-256 trailing
+    updates on the matrix cores and a two-block panel."""
+    print(f"lu32 exact n={n}", flush=True)
     rng = np.random.default_rng(310)
     L0 = np.tril(rng.choice([-0.5, -0.25, 0.0, 0.25, 0.5], size=(n, n)), -1) + np.eye(n)
     U0 = np.triu(rng.integers(-3, 4, size=(n, n)).astype(float), 1) + np.diag(rng.choice([-8.0, 8.0], n))
@@ -107,12 +125,14 @@ def test_lu32_exact_factorization_bitwise(device):
     assert info == 0
     np.testing.assert_array_equal(piv, np.arange(n))
     np.testing.assert_array_equal(LU, LUo)
+    np.testing.assert_array_equal(np.tril(LU, -1), np.tril(L0, -1))
+    np.testing.assert_array_equal(np.triu(LU), U0)
     # a zero column: reported, as the oracle's first zero pivot
     S = A.copy()
-    S[:, 7] = 0.0
+    S[:, zero_col] = 0.0
     _, _, info = _gpu_lu(S, device)
     _, _, sing = oracle.lu32_block(S, b=16)
-    assert info == sing == 8
+    assert info == sing == zero_col + 1
 
 
 @pytest.mark.parametrize("n,kappa,seed", [(100, 1e6, 0), (300, 1e6, 1), (1000, 1e4, 2),
@@ -169,3 +189,32 @@ def test_gmres_ir_lu_special_cases(device):
     x, info = krylov.solve(_t(np.array([[4.0]]), device), _t(np.array([2.0]), device),
                            method="gmres", precision="lu32", tol=1e-14)
     assert info["status_name"] == "ok" and x.cpu().numpy()[0] == 0.5
+
+def test_gmres_ir_lu_full_size_kappa_1e6(device):
+    """The refinement workload's hardest nonsymmetric cell, n = 32768, cond
+    1e6, where GMRES(50) in binary64 and the binary32 and bfloat16 inner
+    solves stagnate: the LU-preconditioned GMRES-IR reaches eta_inf <= 1e-12
+    (checked by the oracle's residual) in a few refinement steps."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n, kappa = 32768, 1e6
+    print(f"gmres-ir lu32 n={n} kappa=1e6: generating", flush=True)
+    p = nonsym_swept_problem(n, kappa, seed=0, config_id=2, backend="torch", device="cuda")
+    x, info = krylov.solve(p.A, p.b, method="gmres", restart=50, precision="lu32", tol=1e-12,
+                           inner_tol=1e-4)
+    print(f"  status {info['status_name']} outer {info['outer_iters']} inner {info['iters']} "
+          f"eta {info['backward_err']:.2e}", flush=True)
+    assert info["status_name"] == "ok", info
+    assert info["outer_iters"] <= 6, info
+    xh = x.cpu().numpy()
+    del x
+    A_host = p.A.cpu().numpy()
+    bh, xt = p.b.cpu().numpy(), p.x_true.cpu().numpy()
+    del p
+    torch.cuda.empty_cache()
+    m = oracle.metrics(A_host, bh, xh)
+    print(f"  eta (oracle) {m['eta_inf']:.3e}", flush=True)
+    assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
+    assert np.linalg.norm(xh - xt) <= 4 * kappa * np.sqrt(n) * 1e-12 * np.linalg.norm(xt) + 1e-12
