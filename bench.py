@@ -522,6 +522,38 @@ def leg_chol(dev, n, spd_form="qr"):
     return out
 
 
+def leg_lu(dev, n):
+    """GMRES(50)-IR with the binary32 block LU preconditioner on the
+    refinement workload's hardest nonsymmetric cell (n = 32768, cond 1e6),
+    where the unpreconditioned solves stall: factorization time and TFLOP/s
+    (2 n^3 / 3 flops, in ks_create) and solve time after the factorization."""
+    import torch
+
+    from paper_1511_07207_amd import krylov
+    from workloads import nonsym_swept_problem
+
+    prob = nonsym_swept_problem(n, 1e6, seed=0, config_id=2, backend="torch", device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    out = {"n": n, "kappa": 1e6, "eta_target": 1e-12}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = krylov.Solver(prob.A, method="gmres", restart=50, precision="lu32", tol=1e-12, max_iter=2000)
+    torch.cuda.synchronize()
+    fact_ms = (time.perf_counter() - t0) * 1e3
+    info, dt, reps = _solve_timed(s, prob.b, x)
+    s.close()
+    out["lu32"] = {"factor_ms": round(fact_ms, 2),
+                   "factor_tflops": round(2.0 * n ** 3 / 3.0 / (fact_ms * 1e-3) / 1e12, 2),
+                   "status": info["status_name"], "outer": info["outer_iters"],
+                   "inner": info["iters"], "eta_inf": info["backward_err"],
+                   "solve_ms": round(dt * 1e3, 2), "timed_solves": reps,
+                   "factor_plus_solve_ms": round(fact_ms + dt * 1e3, 2),
+                   "fwd_err_vs_x_true": float((x - prob.x_true).norm() / prob.x_true.norm())}
+    del prob, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_c2p(dev, n):
     """The CG solve of the main step with either product: general GEMV (all of
     A per iteration) and the symmetric lower-triangle product."""
@@ -699,7 +731,7 @@ def main():
                          "(same spectrum and bytes; for hardware-counter runs)")
     ap.add_argument("--legs", default="c1,c2,c3sweep,c4,c5,f1,f3,f4",
                     help="extra measurements after the timed steps (comma list of "
-                         "c1,c2,c2p,c3sweep,c4,c5,f1,f3,f4,chol; 'none' for the main step only)")
+                         "c1,c2,c2p,c3sweep,c4,c5,f1,f3,f4,chol,lu; 'none' for the main step only)")
     ap.add_argument("--n2", type=int, default=16384, help="size of the binary64 legs (c2, c2p, c4, f1, f3)")
     ap.add_argument("--c2-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=1024)
@@ -933,6 +965,8 @@ def main():
                 legs[name] = leg_c2p(dev, n2)
             elif name == "chol":
                 legs[name] = leg_chol(dev, n, args.spd_form)
+            elif name == "lu":
+                legs[name] = leg_lu(dev, n)
             else:
                 legs[name] = {"error": "unknown leg"}
         except Exception as e:  # a failing leg is reported, not fatal

@@ -334,9 +334,9 @@ int ks_symv_noalloc(int32_t n, int64_t lda, const double *d_A, const double *d_x
  * on and above it; d_piv[k] (n int32) is the row interchanged with row k at
  * step k, 0-based (whole rows, so P A = L U).  1 <= n <= 32768, else
  * KS_EINVAL.  *info = 0, or 1 + the first column whose pivot is zero (the
- * factorization goes on past it).  Allocates and frees an 8 KiB device work
+ * factorization goes on past it).  Allocates and frees a 16 KiB device work
  * area; returns after the factorization has finished on `stream` (KS_EHIP if
- * a panel's bounded grid-barrier wait gave up). */
+ * a panel's bounded wait for its other blocks gave up). */
 int ks_lu32_factor(int32_t n, int64_t lda, const double *d_A, int64_t lda_lu, float *d_LU,
                    int32_t *d_piv, int32_t *info, void *stream);
 

@@ -204,12 +204,12 @@ hipError_t launch_gs_sweep(int n, int64_t lda, const double *A, double *x, doubl
 // below the diagonal) and U on return, piv[k] the row swapped with row k.
 // work: LU_WORK_BYTES of device memory (4-byte aligned), owned by the call
 // while it runs; on return its word 0 is 1 + the first zero pivot's column
-// (0 if none) and word 1 is nonzero if a panel's grid barrier timed out.
+// (0 if none) and word 1 is nonzero if a panel's bounded wait gave up.
 constexpr int LU_NB = 16;
 constexpr int LU_MAX_N = 32768;
 constexpr int LU_PANEL_ROWS = 1024;
 constexpr int LU_PANEL_MAX_BLOCKS = LU_MAX_N / LU_PANEL_ROWS;
-constexpr size_t LU_WORK_BYTES = 8192;
+constexpr size_t LU_WORK_BYTES = 16384;
 hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s);
 // dst = U^-1 L^-1 P src (perm: (P v)_i = v[perm[i]]), t scratch; dst may be
 // src; the squares of dst left in `partial` as the GMRES product leaves them

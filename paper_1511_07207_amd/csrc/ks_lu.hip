@@ -56,41 +56,63 @@ constexpr int TS_LDT = TS_SB + 1;        // padded LDS row stride of a diagonal 
 static_assert(LU_NB <= WAVE && LU_NB * LU_NB <= GEMV_NT, "panel width");
 static_assert(LU_NBO % LU_NB == 0, "outer blocks hold whole panels");
 
+typedef float lg_f4 __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------------------- panel
+// Per column the blocks of a panel exchange packets: block g publishes its
+// candidate (|a|, row, the row's 16 values) and block 0 also row rj, as
+// 64-bit words whose high half is the column's tag rj + 1 and whose low half
+// is the value, with agent-scope relaxed (device-coherent) atomic stores.
+// Every block loads every packet word the same way until each shows the
+// tag: so one device-scope round trip both synchronizes the blocks and
+// carries the data (a word is written and read whole, so a matching tag
+// means its value is that column's).  The packets of odd and even columns
+// alternate: a block writes column J + 2's packet only after reading every
+// block's packet of J + 1, which each block writes only after reading all of
+// column J's, so no packet is overwritten before every block has read it.
+// Tags grow through the factorization (the work area starts zeroed), so a
+// word left from an earlier column never matches.  Every wait is bounded.
 constexpr int LP_NT = 256;                       // threads of a panel block
 constexpr int LP_R = LU_PANEL_ROWS / LP_NT;      // panel rows per thread
 constexpr int LP_SLOT = LU_NB + 2;               // a candidate: |a|, row, the row's values
-constexpr uint32_t LP_SPIN_LIMIT = 1u << 20;     // polls before a barrier wait gives up
+constexpr uint32_t LP_SPIN_LIMIT = 1u << 20;     // polls before a wait gives up
+constexpr int LP_WORDS = LU_PANEL_MAX_BLOCKS * LP_SLOT + LU_NB;  // packet words per column
+constexpr int LP_WPT = (LP_WORDS + LP_NT - 1) / LP_NT;          // words loaded per thread
 static_assert(LP_R * LP_NT == LU_PANEL_ROWS, "rows per block");
 static_assert(LU_PANEL_MAX_BLOCKS <= WAVE, "one candidate per lane");
-// the work area (LU_WORK_BYTES, 32-bit words): [0] info, [1] barrier
-// timeout, [64, 64 + LU_PANEL_MAX_BLOCKS) barrier flags, then from word 128
-// the candidate slots of the two column parities and the two copies of row rj
-constexpr int LW_BAR = 64;
-constexpr int LW_SLOTS = 128;
-constexpr int LW_ROWA = LW_SLOTS + 2 * LU_PANEL_MAX_BLOCKS * LP_SLOT;
-static_assert(LW_BAR + LU_PANEL_MAX_BLOCKS <= LW_SLOTS, "barrier flags");
-static_assert((LW_ROWA + 2 * LU_NB) * 4 <= LU_WORK_BYTES, "work area");
+// the work area (LU_WORK_BYTES): 32-bit words [0] info, [1] timeout; from
+// byte 512 the packet words (64-bit) of the two column parities, each
+// LU_PANEL_MAX_BLOCKS candidate slots then row rj
+constexpr int LW_PACKETS = 512 / 8;  // in 64-bit words
+static_assert((LW_PACKETS + 2 * LP_WORDS) * 8 <= (int)LU_WORK_BYTES, "work area");
 
 struct LpShared {
     float red_v[LP_NT / WAVE];
     int red_i[LP_NT / WAVE];
-    float cand[LU_PANEL_MAX_BLOCKS * LP_SLOT];  // every block's candidate, after the barrier
-    float rowA[LU_NB];                          // row rj before the interchange
-    int bi, piv, gw;
+    float cand[LP_WORDS];  // every block's candidate slot, then row rj
 };
 
+__device__ __forceinline__ uint64_t lp_word(uint32_t tag, float v) {
+    return ((uint64_t)tag << 32) | (uint32_t)__float_as_uint(v);
+}
+
+// the better of two candidates: larger magnitude, then lower row (a total
+// order, so any reduction order picks the same row)
+__device__ __forceinline__ bool lp_better(float ov, int oi, float v, int i) {
+    return ov > v || (ov == v && oi < i);
+}
+
 // Column J of the panel (J a template parameter, so that the panel stays in
-// registers: every index into p is a compile-time constant).  False when the
-// grid barrier timed out.
+// registers: every index into p is a compile-time constant).  False when a
+// wait timed out.
 template <int J>
 __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
                                              LpShared &sh, int *__restrict__ piv, uint32_t *work) {
     if (J >= b) return true;  // uniform: the last panel may be narrower
     const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
     const int rj = k0 + J;
-    float *slots = reinterpret_cast<float *>(work + LW_SLOTS) + (J & 1) * LU_PANEL_MAX_BLOCKS * LP_SLOT;
-    float *rowAg = reinterpret_cast<float *>(work + LW_ROWA) + (J & 1) * LU_NB;
+    const uint32_t tag = (uint32_t)(rj + 1);
+    uint64_t *pk = reinterpret_cast<uint64_t *>(work) + LW_PACKETS + (J & 1) * LP_WORDS;
     // the block's candidate: largest |a(r, J)| over its rows r >= rj, the
     // first such row; the search starts from row rj, so the pivot is a row of
     // the panel even when no magnitude compares greater (a column of NaNs)
@@ -105,13 +127,11 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
             bi = r;
         }
     }
-    // (largest magnitude, lowest row on ties: a total order, so any reduction
-    // order picks the same row)
 #pragma unroll
     for (int off = WAVE / 2; off >= 1; off >>= 1) {
         const float ov = __shfl_xor(bv, off);
         const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) {
+        if (lp_better(ov, oi, bv, bi)) {
             bv = ov;
             bi = oi;
         }
@@ -121,72 +141,98 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
         sh.red_i[wv] = bi;
     }
     __syncthreads();
-    float *myslot = slots + blockIdx.x * LP_SLOT;
-    if (wv == 0) {
-        constexpr int NW = LP_NT / WAVE;
-        float v = lane < NW ? sh.red_v[lane] : -2.0f;
-        int i = lane < NW ? sh.red_i[lane] : rj;
+    // every thread reduces the waves' candidates (the same order everywhere)
+    float cv = sh.red_v[0];
+    int ci = sh.red_i[0];
 #pragma unroll
-        for (int off = NW / 2; off >= 1; off >>= 1) {
-            const float ov = __shfl_xor(v, off);
-            const int oi = __shfl_xor(i, off);
-            if (ov > v || (ov == v && oi < i)) {
-                v = ov;
-                i = oi;
-            }
-        }
-        if (lane == 0) {
-            sh.bi = i;
-            coh_store(myslot, v);
-            coh_store(myslot + 1, __int_as_float(i));
+    for (int w2 = 1; w2 < LP_NT / WAVE; ++w2) {
+        if (lp_better(sh.red_v[w2], sh.red_i[w2], cv, ci)) {
+            cv = sh.red_v[w2];
+            ci = sh.red_i[w2];
         }
     }
-    __syncthreads();
-    // publish the candidate row's values and (block 0) row rj's
-    const int cb = sh.bi;
+    // publish: |a| and row (thread 0), the row's values (the thread holding
+    // it, or zeros from thread 0 when the candidate is row rj held by block
+    // 0), row rj (the thread of block 0 holding it)
+    uint64_t *slot = pk + blockIdx.x * LP_SLOT;
+    if (t == 0) {
+        coh_store(slot, lp_word(tag, cv));
+        coh_store(slot + 1, lp_word(tag, __int_as_float(ci)));
+    }
+    const bool held = ci >= row0 && ci < row0 + LU_PANEL_ROWS && ci < n;
+    if (!held && t == 0) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) coh_store(slot + 2 + c, lp_word(tag, 0.0f));
+    }
 #pragma unroll
     for (int q = 0; q < LP_R; ++q) {
         const int r = row0 + t + LP_NT * q;
-        if (r == cb && r < n) {
+        if (held && r == ci) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c) coh_store(myslot + 2 + c, p[q][c]);
+            for (int c = 0; c < LU_NB; ++c) coh_store(slot + 2 + c, lp_word(tag, p[q][c]));
         }
         if (r == rj) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c) coh_store(rowAg + c, p[q][c]);
+            for (int c = 0; c < LU_NB; ++c)
+                coh_store(pk + LU_PANEL_MAX_BLOCKS * LP_SLOT + c, lp_word(tag, p[q][c]));
         }
     }
-    if (!grid_barrier(work + LW_BAR, (uint32_t)(rj + 1), LP_SPIN_LIMIT)) return false;
+    // every block's packet (G slots, then row rj): the thread's words are
+    // loaded together and those without this column's tag loaded again,
+    // together, until all carry it
     const int G = gridDim.x;
-    for (int e = t; e < G * LP_SLOT; e += LP_NT) sh.cand[e] = coh_load(slots + e);
-    if (t < LU_NB) sh.rowA[t] = coh_load(rowAg + t);
-    __syncthreads();
-    if (wv == 0) {
-        float v = lane < G ? sh.cand[lane * LP_SLOT] : -2.0f;
-        int i = lane < G ? __float_as_int(sh.cand[lane * LP_SLOT + 1]) : rj;
-        int gw = lane < G ? lane : 0;
+    const int nw = G * LP_SLOT;
+    int late = 0;
+    uint64_t wv8[LP_WPT];
+    const uint64_t *src[LP_WPT];
 #pragma unroll
-        for (int off = WAVE / 2; off >= 1; off >>= 1) {
-            const float ov = __shfl_xor(v, off);
-            const int oi = __shfl_xor(i, off);
-            const int og = __shfl_xor(gw, off);
-            if (ov > v || (ov == v && (oi < i || (oi == i && og < gw)))) {
-                v = ov;
-                i = oi;
-                gw = og;
-            }
+    for (int u = 0; u < LP_WPT; ++u) {
+        const int e = t + LP_NT * u;
+        src[u] = e < nw ? pk + e : (e < nw + LU_NB ? pk + LU_PANEL_MAX_BLOCKS * LP_SLOT + (e - nw) : nullptr);
+        wv8[u] = src[u] ? coh_load(src[u]) : lp_word(tag, 0.0f);
+    }
+    for (uint32_t polls = 0;; ++polls) {
+        bool all = true;
+#pragma unroll
+        for (int u = 0; u < LP_WPT; ++u) all = all && (uint32_t)(wv8[u] >> 32) == tag;
+        if (all) break;
+        if (polls >= LP_SPIN_LIMIT) {
+            late = 1;
+            break;
         }
-        if (lane == 0) {
-            sh.piv = i;
-            sh.gw = gw;
-            if (blockIdx.x == 0) piv[rj] = i;
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int u = 0; u < LP_WPT; ++u)
+            if ((uint32_t)(wv8[u] >> 32) != tag) wv8[u] = coh_load(src[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < LP_WPT; ++u) {
+        const int e = t + LP_NT * u;
+        if (src[u]) sh.cand[e < nw ? e : LU_PANEL_MAX_BLOCKS * LP_SLOT + (e - nw)] = __uint_as_float((uint32_t)wv8[u]);
+    }
+    if (__syncthreads_or(late)) return false;
+    // every wave reduces the G candidates the same way
+    float v = lane < G ? sh.cand[lane * LP_SLOT] : -2.0f;
+    int i = lane < G ? __float_as_int(sh.cand[lane * LP_SLOT + 1]) : rj;
+    int gw = lane < G ? lane : 0;
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        const float ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(i, off);
+        const int og = __shfl_xor(gw, off);
+        if (ov > v || (ov == v && (oi < i || (oi == i && og < gw)))) {
+            v = ov;
+            i = oi;
+            gw = og;
         }
     }
-    __syncthreads();
-    const int pr = sh.piv;
+    const int pr = __shfl(i, 0);
+    gw = __shfl(gw, 0);
+    if (blockIdx.x == 0 && t == 0) piv[rj] = pr;
     // the pivot row: published by the block that holds it (row rj itself
     // when no other row won)
-    const float *rowB = pr == rj ? sh.rowA : sh.cand + sh.gw * LP_SLOT + 2;
+    const float *rowA = sh.cand + LU_PANEL_MAX_BLOCKS * LP_SLOT;
+    const float *rowB = pr == rj ? rowA : sh.cand + gw * LP_SLOT + 2;
     if (pr != rj) {
 #pragma unroll
         for (int q = 0; q < LP_R; ++q) {
@@ -196,7 +242,7 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
                 for (int c = 0; c < LU_NB; ++c) p[q][c] = rowB[c];
             } else if (r == pr) {
 #pragma unroll
-                for (int c = 0; c < LU_NB; ++c) p[q][c] = sh.rowA[c];
+                for (int c = 0; c < LU_NB; ++c) p[q][c] = rowA[c];
             }
         }
     }
@@ -226,9 +272,7 @@ __device__ __forceinline__ bool lu_panel_cols(int n, int k0, int b, int row0, fl
     return (lu_panel_col<J>(n, k0, b, row0, p, sh, piv, work) && ...);
 }
 
-// Block g holds rows k0 + 1024 g + t + 256 q (q < 4) of the panel.  The
-// barrier flags count the columns finished, rj + 1, which grows from one
-// panel launch to the next.
+// Block g holds rows k0 + 1024 g + t + 256 q (q < 4) of the panel.
 __global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, float *__restrict__ LU,
                                                          int k0, int *__restrict__ piv,
                                                          uint32_t *__restrict__ work) {
@@ -237,12 +281,22 @@ __global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, flo
     const int b = min(LU_NB, n - k0);
     const int row0 = k0 + blockIdx.x * LU_PANEL_ROWS;
     float p[LP_R][LU_NB];
+    // whole 16-byte pieces of full panels when aligned (vec), else element by element
+    const bool vec = b == LU_NB && ldl % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
 #pragma unroll
     for (int q = 0; q < LP_R; ++q) {
         const int r = row0 + t + LP_NT * q;
+        const float *src = LU + (int64_t)min(r, n - 1) * ldl + k0;
+        if (vec) {
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c)
-            p[q][c] = (r < n && c < b) ? LU[(int64_t)r * ldl + k0 + c] : 0.0f;
+            for (int c4 = 0; c4 < LU_NB / 4; ++c4) {
+                const lg_f4 v = r < n ? reinterpret_cast<const lg_f4 *>(src)[c4] : lg_f4{0.f, 0.f, 0.f, 0.f};
+                p[q][4 * c4] = v.x, p[q][4 * c4 + 1] = v.y, p[q][4 * c4 + 2] = v.z, p[q][4 * c4 + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < LU_NB; ++c) p[q][c] = (r < n && c < b) ? src[c] : 0.0f;
+        }
     }
     if (!lu_panel_cols(n, k0, b, row0, p, sh, piv, work, std::make_integer_sequence<int, LU_NB>{})) {
         if (t == 0) coh_store(work + 1, 1u);
@@ -252,16 +306,23 @@ __global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, flo
     for (int q = 0; q < LP_R; ++q) {
         const int r = row0 + t + LP_NT * q;
         if (r < n) {
+            float *dst = LU + (int64_t)r * ldl + k0;
+            if (vec) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c)
-                if (c < b) LU[(int64_t)r * ldl + k0 + c] = p[q][c];
+                for (int c4 = 0; c4 < LU_NB / 4; ++c4)
+                    reinterpret_cast<lg_f4 *>(dst)[c4] = lg_f4{p[q][4 * c4], p[q][4 * c4 + 1], p[q][4 * c4 + 2], p[q][4 * c4 + 3]};
+            } else {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c)
+                    if (c < b) dst[c] = p[q][c];
+            }
         }
     }
 }
 
-// info, the timeout word and the barrier flags start at zero
-__global__ void lu_work_reset_kernel(uint32_t *work) {
-    for (int i = threadIdx.x; i < LW_SLOTS; i += blockDim.x) work[i] = 0u;
+// the whole work area starts at zero: info, the timeout word, every packet tag
+__global__ __launch_bounds__(LP_NT) void lu_work_reset_kernel(uint32_t *work) {
+    for (int i = threadIdx.x; i < (int)(LU_WORK_BYTES / 4); i += LP_NT) work[i] = 0u;
 }
 
 // the panel's interchanges, in order, on every column outside the panel
@@ -375,8 +436,6 @@ constexpr int LG_LDB = LG_BN + 4;  // LDS row stride of the U12 chunk
 constexpr int LG_GROUP = 8;
 constexpr int LG_XCD = 8;
 static_assert(LU_NBO % LG_BK == 0, "K in whole chunks");
-
-typedef float lg_f4 __attribute__((ext_vector_type(4)));
 
 template <bool VEC>
 __device__ __forceinline__ lg_f4 lg_load4(const float *p, int valid) {
@@ -689,7 +748,7 @@ __global__ __launch_bounds__(VEC_NT) void lu_xupdate_kernel(int n, double *__res
 hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s) {
     if (n < 1 || n > LU_MAX_N) return hipErrorInvalidValue;
     uint32_t *w = static_cast<uint32_t *>(work);
-    lu_work_reset_kernel<<<1, WAVE, 0, s>>>(w);
+    lu_work_reset_kernel<<<1, LP_NT, 0, s>>>(w);
     const bool vec = ldl % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
     for (int K0 = 0; K0 < n; K0 += LU_NBO) {
         const int K1 = min(K0 + LU_NBO, n);

@@ -144,9 +144,9 @@ def test_gmres_ir_lu_parameters_on_host():
     assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == N.KS_EINVAL
     r.n = r.lda = 32768
     assert L.ks_workspace_bytes(ctypes.byref(r), ctypes.byref(sz)) == 0
-    # the binary64 A, its binary32 copy holding the factors, and the 8 KiB
+    # the binary64 A, its binary32 copy holding the factors, and the 16 KiB
     # work area of the factorization beside the pivots
-    assert sz.value >= 32768 * 32768 * (8 + 4) + 8192
+    assert sz.value >= 32768 * 32768 * (8 + 4) + 16384
     info = ctypes.c_int32(0)
     assert L.ks_lu32_factor(32769, 32769, None, 32769, None, None, ctypes.byref(info), None) == N.KS_EINVAL
 

@@ -110,29 +110,37 @@ def test_lu32_large_sampled_rows(device, n):
     assert np.all(lhs <= gamma * (np.abs(Lr) @ Uf) + 1e-300)
 
 
-@pytest.mark.parametrize("n,zero_col", [(40, 7), (1100, 20)])
+@pytest.mark.parametrize("n,zero_col", [(40, 7), (1100, 20), (4501, 1500)])
 def test_lu32_exact_factorization_bitwise(device, n, zero_col):
     """An exactly representable L0 U0 (every partial sum exact, so any order
-    of summation gives L0 and U0); n = 1100 crosses the rank-256 trailing
-    updates on the matrix cores and a two-block panel."""
+    of summation gives L0 and U0, and partial pivoting keeps the diagonal:
+    |u_kk| = 8 > |l_ik u_kk|); n = 1100 crosses the rank-256 trailing updates
+    on the matrix cores and a two-block panel, n = 4501 five-block panels and
+    ragged trailing tiles with rows not 16-byte aligned.  Against the oracle
+    where it finishes in seconds, else against L0 and U0 themselves."""
     print(f"lu32 exact n={n}", flush=True)
     rng = np.random.default_rng(310)
     L0 = np.tril(rng.choice([-0.5, -0.25, 0.0, 0.25, 0.5], size=(n, n)), -1) + np.eye(n)
     U0 = np.triu(rng.integers(-3, 4, size=(n, n)).astype(float), 1) + np.diag(rng.choice([-8.0, 8.0], n))
     A = L0 @ U0
     LU, piv, info = _gpu_lu(A, device)
-    LUo, pivo, _ = oracle.lu32_block(A, b=16)
     assert info == 0
     np.testing.assert_array_equal(piv, np.arange(n))
-    np.testing.assert_array_equal(LU, LUo)
     np.testing.assert_array_equal(np.tril(LU, -1), np.tril(L0, -1))
     np.testing.assert_array_equal(np.triu(LU), U0)
-    # a zero column: reported, as the oracle's first zero pivot
+    with_oracle = n <= 2000
+    if with_oracle:
+        LUo, pivo, _ = oracle.lu32_block(A, b=16)
+        np.testing.assert_array_equal(LU, LUo)
+    # a zero column: reported as the first zero pivot (the columns before it
+    # factor exactly as above, and it stays zero)
     S = A.copy()
     S[:, zero_col] = 0.0
     _, _, info = _gpu_lu(S, device)
-    _, _, sing = oracle.lu32_block(S, b=16)
-    assert info == sing == zero_col + 1
+    assert info == zero_col + 1
+    if with_oracle:
+        _, _, sing = oracle.lu32_block(S, b=16)
+        assert sing == info
 
 
 @pytest.mark.parametrize("n,kappa,seed", [(100, 1e6, 0), (300, 1e6, 1), (1000, 1e4, 2),
