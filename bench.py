@@ -684,6 +684,9 @@ def leg_c5(dev, count, pool_size, seed=0, rates=(0.5, 0.9)):
                 statuses.append(info["status"])
                 etas.append(info["backward_err"])
                 precs[info["precision_used"]] = precs.get(info["precision_used"], 0) + 1
+                if len(lat) % 512 == 0:
+                    print(f"[bench]     c5 {mode}: {len(lat)}/{count} requests done at {done_t:.1f} s",
+                          file=sys.stderr, flush=True)
             if not pending and a == 0 and q == 0:
                 break
             if a == 0 and q == 0 and pending:

@@ -7,11 +7,12 @@
 // LU_NBO = 256 columns; inside one, panels of LU_NB = 16 columns:
 //   lu_panel_kernel   the panel A(k0:n, k0:k0+16) factored column by column
 //                     with partial pivoting (largest magnitude, first row on
-//                     ties) by a cooperative grid of up to 32 blocks, each
-//                     holding 1024 rows of the panel in registers; per
-//                     column the blocks publish their candidates (magnitude,
-//                     row, the row's 16 values) and meet once at a grid
-//                     barrier, then every block picks the same pivot and
+//                     ties), the panel in registers: one block of 1024
+//                     threads when it has at most 4096 rows, else a
+//                     cooperative grid of up to 32 blocks of 1024 rows; per
+//                     column the blocks exchange their candidates (magnitude,
+//                     row, the row's 16 values) in one device-scope round
+//                     trip, then every block picks the same pivot and
 //                     eliminates its rows;
 //   lu_swap_kernel    the panel's row interchanges applied to every other
 //                     column (so every row of A(K0:n, K1:n) stays in the same
@@ -72,13 +73,17 @@ typedef float lg_f4 __attribute__((ext_vector_type(4)));
 // column J's, so no packet is overwritten before every block has read it.
 // Tags grow through the factorization (the work area starts zeroed), so a
 // word left from an earlier column never matches.  Every wait is bounded.
-constexpr int LP_NT = 256;                       // threads of a panel block
-constexpr int LP_R = LU_PANEL_ROWS / LP_NT;      // panel rows per thread
+// A panel block of NT threads holds 4 NT rows: NT = 1024 when one block
+// holds the whole panel (n - k0 <= 4096; the exchange goes through LDS and
+// the launch is an ordinary one), NT = 256 for the cooperative grid of up to
+// LU_PANEL_MAX_BLOCKS blocks of LU_PANEL_ROWS rows (more, smaller blocks:
+// measured faster per column than fewer large ones)
+constexpr int LP_R = 4;                          // panel rows per thread
+constexpr int LP_NT_ONE = 1024, LP_NT_GRID = LU_PANEL_ROWS / LP_R;
 constexpr int LP_SLOT = LU_NB + 2;               // a candidate: |a|, row, the row's values
 constexpr uint32_t LP_SPIN_LIMIT = 1u << 20;     // polls before a wait gives up
 constexpr int LP_WORDS = LU_PANEL_MAX_BLOCKS * LP_SLOT + LU_NB;  // packet words per column
-constexpr int LP_WPT = (LP_WORDS + LP_NT - 1) / LP_NT;          // words loaded per thread
-static_assert(LP_R * LP_NT == LU_PANEL_ROWS, "rows per block");
+static_assert(LP_R * LP_NT_GRID == LU_PANEL_ROWS, "rows per block");
 static_assert(LU_PANEL_MAX_BLOCKS <= WAVE, "one candidate per lane");
 // the work area (LU_WORK_BYTES): 32-bit words [0] info, [1] timeout; from
 // byte 512 the packet words (64-bit) of the two column parities, each
@@ -86,9 +91,10 @@ static_assert(LU_PANEL_MAX_BLOCKS <= WAVE, "one candidate per lane");
 constexpr int LW_PACKETS = 512 / 8;  // in 64-bit words
 static_assert((LW_PACKETS + 2 * LP_WORDS) * 8 <= (int)LU_WORK_BYTES, "work area");
 
+template <int NT>
 struct LpShared {
-    float red_v[LP_NT / WAVE];
-    int red_i[LP_NT / WAVE];
+    float red_v[NT / WAVE];
+    int red_i[NT / WAVE];
     float cand[LP_WORDS];  // every block's candidate slot, then row rj
 };
 
@@ -102,55 +108,13 @@ __device__ __forceinline__ bool lp_better(float ov, int oi, float v, int i) {
     return ov > v || (ov == v && oi < i);
 }
 
-// Column J of the panel (J a template parameter, so that the panel stays in
-// registers: every index into p is a compile-time constant).  False when a
-// wait timed out.
-template <int J>
-__device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
-                                             LpShared &sh, int *__restrict__ piv, uint32_t *work) {
-    if (J >= b) return true;  // uniform: the last panel may be narrower
-    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
-    const int rj = k0 + J;
-    const uint32_t tag = (uint32_t)(rj + 1);
-    uint64_t *pk = reinterpret_cast<uint64_t *>(work) + LW_PACKETS + (J & 1) * LP_WORDS;
-    // the block's candidate: largest |a(r, J)| over its rows r >= rj, the
-    // first such row; the search starts from row rj, so the pivot is a row of
-    // the panel even when no magnitude compares greater (a column of NaNs)
-    float bv = -1.0f;
-    int bi = rj;
-#pragma unroll
-    for (int q = 0; q < LP_R; ++q) {
-        const int r = row0 + t + LP_NT * q;
-        const float a = fabsf(p[q][J]);
-        if (r >= rj && r < n && a > bv) {
-            bv = a;
-            bi = r;
-        }
-    }
-#pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1) {
-        const float ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (lp_better(ov, oi, bv, bi)) {
-            bv = ov;
-            bi = oi;
-        }
-    }
-    if (lane == 0) {
-        sh.red_v[wv] = bv;
-        sh.red_i[wv] = bi;
-    }
-    __syncthreads();
-    // every thread reduces the waves' candidates (the same order everywhere)
-    float cv = sh.red_v[0];
-    int ci = sh.red_i[0];
-#pragma unroll
-    for (int w2 = 1; w2 < LP_NT / WAVE; ++w2) {
-        if (lp_better(sh.red_v[w2], sh.red_i[w2], cv, ci)) {
-            cv = sh.red_v[w2];
-            ci = sh.red_i[w2];
-        }
-    }
+// the packet exchange of column J between the blocks of a panel; false when
+// a wait timed out
+template <int J, int NT>
+__device__ __forceinline__ bool lu_panel_exchange(int n, int row0, float (&p)[LP_R][LU_NB], LpShared<NT> &sh,
+                                                  uint32_t *work, uint32_t tag, uint64_t *pk, float cv,
+                                                  int ci, int rj) {
+    const int t = threadIdx.x;
     // publish: |a| and row (thread 0), the row's values (the thread holding
     // it, or zeros from thread 0 when the candidate is row rj held by block
     // 0), row rj (the thread of block 0 holding it)
@@ -159,14 +123,14 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
         coh_store(slot, lp_word(tag, cv));
         coh_store(slot + 1, lp_word(tag, __int_as_float(ci)));
     }
-    const bool held = ci >= row0 && ci < row0 + LU_PANEL_ROWS && ci < n;
+    const bool held = ci >= row0 && ci < row0 + (LP_R * NT) && ci < n;
     if (!held && t == 0) {
 #pragma unroll
         for (int c = 0; c < LU_NB; ++c) coh_store(slot + 2 + c, lp_word(tag, 0.0f));
     }
 #pragma unroll
     for (int q = 0; q < LP_R; ++q) {
-        const int r = row0 + t + LP_NT * q;
+        const int r = row0 + t + NT * q;
         if (held && r == ci) {
 #pragma unroll
             for (int c = 0; c < LU_NB; ++c) coh_store(slot + 2 + c, lp_word(tag, p[q][c]));
@@ -183,18 +147,19 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
     const int G = gridDim.x;
     const int nw = G * LP_SLOT;
     int late = 0;
-    uint64_t wv8[LP_WPT];
-    const uint64_t *src[LP_WPT];
+    constexpr int WPT = (LP_WORDS + NT - 1) / NT;  // words loaded per thread
+    uint64_t wv8[WPT];
+    const uint64_t *src[WPT];
 #pragma unroll
-    for (int u = 0; u < LP_WPT; ++u) {
-        const int e = t + LP_NT * u;
+    for (int u = 0; u < WPT; ++u) {
+        const int e = t + NT * u;
         src[u] = e < nw ? pk + e : (e < nw + LU_NB ? pk + LU_PANEL_MAX_BLOCKS * LP_SLOT + (e - nw) : nullptr);
         wv8[u] = src[u] ? coh_load(src[u]) : lp_word(tag, 0.0f);
     }
     for (uint32_t polls = 0;; ++polls) {
         bool all = true;
 #pragma unroll
-        for (int u = 0; u < LP_WPT; ++u) all = all && (uint32_t)(wv8[u] >> 32) == tag;
+        for (int u = 0; u < WPT; ++u) all = all && (uint32_t)(wv8[u] >> 32) == tag;
         if (all) break;
         if (polls >= LP_SPIN_LIMIT) {
             late = 1;
@@ -202,15 +167,25 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
         }
         __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-        for (int u = 0; u < LP_WPT; ++u)
+        for (int u = 0; u < WPT; ++u)
             if ((uint32_t)(wv8[u] >> 32) != tag) wv8[u] = coh_load(src[u]);
     }
 #pragma unroll
-    for (int u = 0; u < LP_WPT; ++u) {
-        const int e = t + LP_NT * u;
+    for (int u = 0; u < WPT; ++u) {
+        const int e = t + NT * u;
         if (src[u]) sh.cand[e < nw ? e : LU_PANEL_MAX_BLOCKS * LP_SLOT + (e - nw)] = __uint_as_float((uint32_t)wv8[u]);
     }
-    if (__syncthreads_or(late)) return false;
+    return __syncthreads_or(late) == 0;
+}
+
+// pivot choice (every wave reduces the G candidates the same way), the
+// interchange and the elimination of column J
+template <int J, int NT>
+__device__ __forceinline__ bool lu_panel_eliminate(int n, int k0, int row0, float (&p)[LP_R][LU_NB],
+                                                   LpShared<NT> &sh, int *__restrict__ piv, uint32_t *work,
+                                                   int rj) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
+    const int G = gridDim.x;
     // every wave reduces the G candidates the same way
     float v = lane < G ? sh.cand[lane * LP_SLOT] : -2.0f;
     int i = lane < G ? __float_as_int(sh.cand[lane * LP_SLOT + 1]) : rj;
@@ -236,7 +211,7 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
     if (pr != rj) {
 #pragma unroll
         for (int q = 0; q < LP_R; ++q) {
-            const int r = row0 + t + LP_NT * q;
+            const int r = row0 + t + NT * q;
             if (r == rj) {
 #pragma unroll
                 for (int c = 0; c < LU_NB; ++c) p[q][c] = rowB[c];
@@ -251,7 +226,7 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
     if (d != 0.0f) {
 #pragma unroll
         for (int q = 0; q < LP_R; ++q) {
-            const int r = row0 + t + LP_NT * q;
+            const int r = row0 + t + NT * q;
             if (r > rj && r < n) {
                 const float l = p[q][J] / d;
                 p[q][J] = l;
@@ -265,27 +240,103 @@ __device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, flo
     return true;
 }
 
-template <int... J>
-__device__ __forceinline__ bool lu_panel_cols(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
-                                              LpShared &sh, int *__restrict__ piv, uint32_t *work,
-                                              std::integer_sequence<int, J...>) {
-    return (lu_panel_col<J>(n, k0, b, row0, p, sh, piv, work) && ...);
+// Column J of the panel (J a template parameter, so that the panel stays in
+// registers: every index into p is a compile-time constant).  False when a
+// wait timed out.
+template <int J, int NT>
+__device__ __forceinline__ bool lu_panel_col(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
+                                             LpShared<NT> &sh, int *__restrict__ piv, uint32_t *work) {
+    if (J >= b) return true;  // uniform: the last panel may be narrower
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    const int rj = k0 + J;
+    const uint32_t tag = (uint32_t)(rj + 1);
+    uint64_t *pk = reinterpret_cast<uint64_t *>(work) + LW_PACKETS + (J & 1) * LP_WORDS;
+    // the block's candidate: largest |a(r, J)| over its rows r >= rj, the
+    // first such row; the search starts from row rj, so the pivot is a row of
+    // the panel even when no magnitude compares greater (a column of NaNs)
+    float bv = -1.0f;
+    int bi = rj;
+#pragma unroll
+    for (int q = 0; q < LP_R; ++q) {
+        const int r = row0 + t + NT * q;
+        const float a = fabsf(p[q][J]);
+        if (r >= rj && r < n && a > bv) {
+            bv = a;
+            bi = r;
+        }
+    }
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        const float ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (lp_better(ov, oi, bv, bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        sh.red_v[wv] = bv;
+        sh.red_i[wv] = bi;
+    }
+    __syncthreads();
+    // every thread reduces the waves' candidates (the same order everywhere)
+    float cv = sh.red_v[0];
+    int ci = sh.red_i[0];
+#pragma unroll
+    for (int w2 = 1; w2 < NT / WAVE; ++w2) {
+        if (lp_better(sh.red_v[w2], sh.red_i[w2], cv, ci)) {
+            cv = sh.red_v[w2];
+            ci = sh.red_i[w2];
+        }
+    }
+    const int G = gridDim.x;
+    if (G == 1) {
+        // one block holds the whole panel: its candidate and row rj through LDS
+#pragma unroll
+        for (int q = 0; q < LP_R; ++q) {
+            const int r = row0 + t + NT * q;
+            if (r == ci) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) sh.cand[2 + c] = p[q][c];
+            }
+            if (r == rj) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) sh.cand[LU_PANEL_MAX_BLOCKS * LP_SLOT + c] = p[q][c];
+            }
+        }
+        if (t == 0) {
+            sh.cand[0] = cv;
+            sh.cand[1] = __int_as_float(ci);
+        }
+        __syncthreads();
+    } else if (!lu_panel_exchange<J, NT>(n, row0, p, sh, work, tag, pk, cv, ci, rj)) {
+        return false;
+    }
+    return lu_panel_eliminate<J, NT>(n, k0, row0, p, sh, piv, work, rj);
 }
 
-// Block g holds rows k0 + 1024 g + t + 256 q (q < 4) of the panel.
-__global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, float *__restrict__ LU,
+template <int NT, int... J>
+__device__ __forceinline__ bool lu_panel_cols(int n, int k0, int b, int row0, float (&p)[LP_R][LU_NB],
+                                              LpShared<NT> &sh, int *__restrict__ piv, uint32_t *work,
+                                              std::integer_sequence<int, J...>) {
+    return (lu_panel_col<J, NT>(n, k0, b, row0, p, sh, piv, work) && ...);
+}
+
+// Block g holds rows k0 + 4 NT g + t + NT q (q < 4) of the panel.
+template <int NT>
+__global__ __launch_bounds__(NT) void lu_panel_kernel(int n, int64_t ldl, float *__restrict__ LU,
                                                          int k0, int *__restrict__ piv,
                                                          uint32_t *__restrict__ work) {
-    __shared__ LpShared sh;
+    __shared__ LpShared<NT> sh;
     const int t = threadIdx.x;
     const int b = min(LU_NB, n - k0);
-    const int row0 = k0 + blockIdx.x * LU_PANEL_ROWS;
+    const int row0 = k0 + blockIdx.x * (LP_R * NT);
     float p[LP_R][LU_NB];
     // whole 16-byte pieces of full panels when aligned (vec), else element by element
     const bool vec = b == LU_NB && ldl % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
 #pragma unroll
     for (int q = 0; q < LP_R; ++q) {
-        const int r = row0 + t + LP_NT * q;
+        const int r = row0 + t + NT * q;
         const float *src = LU + (int64_t)min(r, n - 1) * ldl + k0;
         if (vec) {
 #pragma unroll
@@ -298,13 +349,13 @@ __global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, flo
             for (int c = 0; c < LU_NB; ++c) p[q][c] = (r < n && c < b) ? src[c] : 0.0f;
         }
     }
-    if (!lu_panel_cols(n, k0, b, row0, p, sh, piv, work, std::make_integer_sequence<int, LU_NB>{})) {
+    if (!lu_panel_cols<NT>(n, k0, b, row0, p, sh, piv, work, std::make_integer_sequence<int, LU_NB>{})) {
         if (t == 0) coh_store(work + 1, 1u);
         return;
     }
 #pragma unroll
     for (int q = 0; q < LP_R; ++q) {
-        const int r = row0 + t + LP_NT * q;
+        const int r = row0 + t + NT * q;
         if (r < n) {
             float *dst = LU + (int64_t)r * ldl + k0;
             if (vec) {
@@ -321,8 +372,8 @@ __global__ __launch_bounds__(LP_NT) void lu_panel_kernel(int n, int64_t ldl, flo
 }
 
 // the whole work area starts at zero: info, the timeout word, every packet tag
-__global__ __launch_bounds__(LP_NT) void lu_work_reset_kernel(uint32_t *work) {
-    for (int i = threadIdx.x; i < (int)(LU_WORK_BYTES / 4); i += LP_NT) work[i] = 0u;
+__global__ __launch_bounds__(WAVE * 4) void lu_work_reset_kernel(uint32_t *work) {
+    for (int i = threadIdx.x; i < (int)(LU_WORK_BYTES / 4); i += WAVE * 4) work[i] = 0u;
 }
 
 // the panel's interchanges, in order, on every column outside the panel
@@ -748,21 +799,27 @@ __global__ __launch_bounds__(VEC_NT) void lu_xupdate_kernel(int n, double *__res
 hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s) {
     if (n < 1 || n > LU_MAX_N) return hipErrorInvalidValue;
     uint32_t *w = static_cast<uint32_t *>(work);
-    lu_work_reset_kernel<<<1, LP_NT, 0, s>>>(w);
+    lu_work_reset_kernel<<<1, WAVE * 4, 0, s>>>(w);
     const bool vec = ldl % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
     for (int K0 = 0; K0 < n; K0 += LU_NBO) {
         const int K1 = min(K0 + LU_NBO, n);
         for (int k0 = K0; k0 < K1; k0 += LU_NB) {
             const int b = min(LU_NB, n - k0), k1 = k0 + b;
-            const int G = div_up(n - k0, LU_PANEL_ROWS);
-            int an = n, ak0 = k0;
-            int64_t aldl = ldl;
-            float *aLU = LU;
-            int *apiv = piv;
-            void *args[] = {&an, &aldl, &aLU, &ak0, &apiv, &w};
-            const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(lu_panel_kernel),
-                                                            dim3(G), dim3(LP_NT), args, 0, s);
-            if (e != hipSuccess) return e;
+            if (n - k0 <= LP_R * LP_NT_ONE) {
+                // one block holds the panel: nothing to be co-resident with
+                lu_panel_kernel<LP_NT_ONE><<<1, LP_NT_ONE, 0, s>>>(n, ldl, LU, k0, piv, w);
+            } else {
+                const int G = div_up(n - k0, LU_PANEL_ROWS);
+                int an = n, ak0 = k0;
+                int64_t aldl = ldl;
+                float *aLU = LU;
+                int *apiv = piv;
+                void *args[] = {&an, &aldl, &aLU, &ak0, &apiv, &w};
+                const hipError_t e = hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void *>(lu_panel_kernel<LP_NT_GRID>), dim3(G), dim3(LP_NT_GRID),
+                    args, 0, s);
+                if (e != hipSuccess) return e;
+            }
             lu_swap_kernel<<<div_up(n, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, piv);
             if (k1 < K1) {
                 lu_trsm_kernel<<<div_up(K1 - k1, GEMV_NT), GEMV_NT, 0, s>>>(n, ldl, LU, k0, b, k1, K1);

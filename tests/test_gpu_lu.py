@@ -68,7 +68,7 @@ def test_lu32_factor_matches_oracle(device, n):
     assert np.all(np.abs(L @ Uf - Lo @ Uo) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("n", [64, 1000, 1500, 2049, 2600])
+@pytest.mark.parametrize("n", [64, 1000, 1500, 2049, 2600, 5000])
 def test_lu32_backward_error_bound(device, n):
     print(f"lu32 bound n={n}", flush=True)
     A = np.random.default_rng(200 + n).standard_normal((n, n))
