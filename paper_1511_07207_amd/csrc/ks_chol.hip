@@ -2,22 +2,27 @@
 // symmetric positive definite A, the preconditioner of CG-IR (binary64
 // refinement around preconditioned CG, M = L L^T).
 //
-// The direct-methods section's block relations for the symmetric case, with
-// column blocks of CH_NB = 64, right-looking:
+// The direct-methods section's block relations for the symmetric case, right
+// looking, in two levels: outer column blocks of CH_NBO = 256 columns, inside
+// each block columns of CH_NB = 64:
 //   ch_diag_kernel    the diagonal block A11 = L11 L11^T, factored column by
 //                     column in LDS by one block (the block's entries already
 //                     carry the updates of the columns before it);
 //   ch_panel_kernel   the block column below it, L21 = A21 L11^-T: one row
 //                     per thread, forward substitution against L11 in LDS;
-//   ch_update_kernel  the delayed update of the trailing lower triangle,
-//                     A22 -= L21 L21^T, on the matrix cores.
-// The update is a dense contraction with CH_NB multiply-adds per element of
-// A22 read and written, so it runs on v_mfma_f32_16x16x4f32: a block of four
-// waves owns a 64 x 64 tile of A22 (tiles on and below the diagonal only),
-// each wave a 32 x 32 quarter as 2 x 2 MFMA tiles, K = the block column's 64
-// values in steps of 16.  The rows of L21 a tile needs are the same for every
-// tile of its tile row, so they come from L2 after the first read; A22 itself
-// streams once per block column.
+//   ch_update_kernel  the block column's rank-64 update of the rest of the
+//                     outer block's columns (all rows below), which the next
+//                     block columns read: 64 x 64 tiles on the matrix cores,
+//                     each wave a 32 x 32 quarter as 2 x 2 MFMA tiles, K = 64
+//                     in steps of 16;
+//   ch_syrk_kernel    once the outer block K0:K1 is factored, the rank-256
+//                     update of the trailing lower triangle A(K1:n, K1:n) -=
+//                     L21 L21^T (L21 = L(K1:n, K0:K1)), 128 x 128 tiles on
+//                     and below the diagonal, K = 256 through LDS.
+// Each element of the trailing triangle is read and written once per outer
+// block with 256 multiply-adds (64 flops per byte): a contraction for the
+// matrix cores (v_mfma_f32_16x16x4f32).  The grouping changes only the order
+// in which each element's sum is rounded.
 //
 // After the last block, ch_mirror_kernel copies L^T into the strict upper
 // triangle, so that the backward substitution L^T z = y reads rows (the
@@ -113,19 +118,20 @@ __global__ __launch_bounds__(CH_PANEL_ROWS) void ch_panel_kernel(int n, int64_t 
 }
 
 // ---------------------------------------------------------- trailing update
-// Tile (I, J), I >= J, of the trailing triangle A(k1:n, k1:n), k1 = k0 + b:
+// Tile (I, J), I >= J, J < tj, of the trailing triangle A(k1:n, k1:n), k1 =
+// k0 + b (block bx takes I = bx / tj, J = bx % tj; blocks with I < J leave):
 // C -= L21(I rows) L21(J rows)^T.  Lane l of a wave (g = l / 16, c = l % 16)
 // feeds the MFMA's A operand with row c of a row tile and its B operand with
 // row c of a column tile, taking k = 16 s + 4 g + u in MFMA u of step s (the
 // sum over k is the same, in the matrix core's order); accumulator item v of
 // lane l holds C[4 g + v][c].
 __global__ __launch_bounds__(256) void ch_update_kernel(int n, int64_t ldl, float *__restrict__ L, int k0,
-                                                        const int *__restrict__ info) {
+                                                        int tj, const int *__restrict__ info) {
     if (*info) return;
     const int b = min(CH_NB, n - k0);
     const int k1 = k0 + b;
-    int I, J;
-    tri_ij(blockIdx.x, I, J);
+    const int I = blockIdx.x / tj, J = blockIdx.x % tj;
+    if (I < J) return;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int g = lane >> 4, c = lane & 15;
     const int rbase = k1 + I * CH_TILE + (w >> 1) * 32;  // the wave's 32 rows
@@ -184,6 +190,102 @@ __global__ __launch_bounds__(256) void ch_update_kernel(int n, int64_t ldl, floa
         }
 }
 
+// ------------------------------------------------------------ rank-256 update
+// Tile (I, J), I >= J, of A(K1:n, K1:n) -= L(K1:n, K0:K1) L(K1:n, K0:K1)^T:
+// a block of four waves per 128 x 128 tile, each wave a 64 x 64 quarter as
+// 4 x 4 MFMA tiles; K in LDS chunks of 32 (double-buffered, the next chunk's
+// loads in flight while the matrix cores work).  Both operands are rows of
+// L21 with k contiguous, staged alike; lane (g, c) takes k = 8 g + s in step
+// s, so each fragment is two 16-byte LDS reads.  Blocks are numbered
+// round-robin over the eight XCDs: block b takes logical tile (b % 8) q + b /
+// 8 of the T (T + 1) / 2 lower tiles in row order (q per XCD), so the tiles
+// in flight on one XCD share rows of L21 in its L2.  Only elements on and
+// below the diagonal are written.
+constexpr int CH_NBO = 256;           // outer column block: K of this update
+constexpr int CS_T = 128, CS_BK = 32, CS_LD = CS_BK + 4, CS_XCD = 8;
+static_assert(CH_NBO % CH_NB == 0 && CH_NBO % CS_BK == 0, "outer blocks of whole block columns and chunks");
+
+__global__ __launch_bounds__(256) void ch_syrk_kernel(int n, int64_t ldl, float *__restrict__ L, int K0, int K1,
+                                                      int T, const int *__restrict__ info) {
+    __shared__ __attribute__((aligned(16))) float As[2][CS_T * CS_LD];
+    __shared__ __attribute__((aligned(16))) float Bs[2][CS_T * CS_LD];
+    if (*info) return;
+    const int total = T * (T + 1) / 2;
+    const int per_xcd = div_up(total, CS_XCD);
+    const int lt = (blockIdx.x % CS_XCD) * per_xcd + blockIdx.x / CS_XCD;
+    if (lt >= total) return;
+    int I, J;
+    tri_ij(lt, I, J);
+    const int r0 = K1 + I * CS_T, c0 = K1 + J * CS_T;
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    const int g = lane >> 4, c = lane & 15;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int nch = (K1 - K0) / CS_BK;
+    // staging: rows t / 8 + 32 i of both row tiles, k = 4 (t % 8)
+    const int ar = t / 8, ak = 4 * (t % 8);
+    ch_f4 ra[4], rb[4];
+    auto gload = [&](int ch) {
+        const int kb = K0 + ch * CS_BK + ak;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + ar + 32 * i, q = c0 + ar + 32 * i;
+            ra[i] = r < n ? *reinterpret_cast<const ch_f4 *>(L + (int64_t)r * ldl + kb) : ch_f4{0.f, 0.f, 0.f, 0.f};
+            rb[i] = q < n ? *reinterpret_cast<const ch_f4 *>(L + (int64_t)q * ldl + kb) : ch_f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<ch_f4 *>(&As[buf][(ar + 32 * i) * CS_LD + ak]) = ra[i];
+            *reinterpret_cast<ch_f4 *>(&Bs[buf][(ar + 32 * i) * CS_LD + ak]) = rb[i];
+        }
+    };
+    ch_f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = ch_f4{0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) gload(ch + 1);
+        ch_f4 a[4][2], bq[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const ch_f4 *pa = reinterpret_cast<const ch_f4 *>(&As[buf][(wr + 16 * rt + c) * CS_LD + 8 * g]);
+            const ch_f4 *pb = reinterpret_cast<const ch_f4 *>(&Bs[buf][(wc + 16 * rt + c) * CS_LD + 8 * g]);
+            a[rt][0] = pa[0], a[rt][1] = pa[1];
+            bq[rt][0] = pb[0], bq[rt][1] = pb[1];
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][s / 4][s % 4], bq[ct][s / 4][s % 4],
+                                                                       acc[rt][ct], 0, 0, 0);
+        if (ch + 1 < nch) sstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = c0 + wc + 16 * ct + c;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + wr + 16 * rt + 4 * g + v;
+                if (row < n && col <= row) {
+                    float *pc = L + (int64_t)row * ldl + col;
+                    *pc = *pc - acc[rt][ct][v];
+                }
+            }
+        }
+}
+
 // ------------------------------------------------------------------ mirror
 // upper(i, j) = L(j, i) for j > i, through a 64 x 64 LDS tile per block pair
 // (tile (I, J) of the lower triangle, I >= J, written transposed to (J, I)).
@@ -208,14 +310,24 @@ __global__ __launch_bounds__(256) void ch_mirror_kernel(int n, int64_t ldl, floa
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_chol_factor(int n, int64_t ldl, float *L, int *info, hipStream_t s) {
-    for (int k0 = 0; k0 < n; k0 += CH_NB) {
-        const int b = min(CH_NB, n - k0);
-        ch_diag_kernel<<<1, 256, 0, s>>>(n, ldl, L, k0, info);
-        const int rest = n - k0 - b;
-        if (rest > 0) {
-            ch_panel_kernel<<<div_up(rest, CH_PANEL_ROWS), CH_PANEL_ROWS, 0, s>>>(n, ldl, L, k0, info);
-            const int T = div_up(rest, CH_TILE);
-            ch_update_kernel<<<T * (T + 1) / 2, 256, 0, s>>>(n, ldl, L, k0, info);
+    for (int K0 = 0; K0 < n; K0 += CH_NBO) {
+        const int K1 = min(K0 + CH_NBO, n);
+        for (int k0 = K0; k0 < K1; k0 += CH_NB) {
+            const int b = min(CH_NB, n - k0), k1 = k0 + b;
+            ch_diag_kernel<<<1, 256, 0, s>>>(n, ldl, L, k0, info);
+            const int rest = n - k1;
+            if (rest > 0) {
+                ch_panel_kernel<<<div_up(rest, CH_PANEL_ROWS), CH_PANEL_ROWS, 0, s>>>(n, ldl, L, k0, info);
+                if (k1 < K1) {
+                    const int tj = div_up(K1 - k1, CH_TILE), ti = div_up(rest, CH_TILE);
+                    ch_update_kernel<<<tj * ti, 256, 0, s>>>(n, ldl, L, k0, tj, info);
+                }
+            }
+        }
+        if (K1 < n) {
+            const int T = div_up(n - K1, CS_T);
+            const int grid = CS_XCD * div_up(T * (T + 1) / 2, CS_XCD);
+            ch_syrk_kernel<<<grid, 256, 0, s>>>(n, ldl, L, K0, K1, T, info);
         }
     }
     const int T = div_up(n, CH_TILE);

@@ -8,7 +8,8 @@ rounding of the oracle's factor, L^T mirrored exactly into the upper
 triangle, bit for bit on an exactly representable factor (every partial sum
 exact, so any summation order gives L0), and the first non-positive pivot of
 an indefinite matrix.  Sizes cross the 64-column blocks and the 64 x 64
-update tiles with ragged tails.
+update tiles with ragged tails, and (past 256) the 256-column outer blocks
+whose rank-256 updates run in 128 x 128 tiles.
 
 CG-IR: eta_inf <= 1e-12 checked by the oracle's residual, the forward error
 against the binary64 oracle run to its attainable accuracy, outer steps
@@ -47,7 +48,7 @@ def _factor(A, device):
     return F, info
 
 
-@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 127, 129, 200, 300, 513])
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 127, 129, 200, 300, 513, 1500])
 def test_chol32_factor_backward_error_and_oracle(device, n):
     print(f"chol32 factor n={n}", flush=True)
     A = _spd(n, 200 + n)
@@ -71,7 +72,7 @@ def test_chol32_factor_backward_error_and_oracle(device, n):
     assert rel <= np.linalg.cond(A32) * n * U32
 
 
-@pytest.mark.parametrize("n,seed", [(24, 120), (130, 121), (257, 122)])
+@pytest.mark.parametrize("n,seed", [(24, 120), (130, 121), (257, 122), (1100, 123)])
 def test_chol32_factor_exact_system_bitwise(device, n, seed):
     print(f"chol32 exact factor n={n}", flush=True)
     rng = np.random.default_rng(seed)
