@@ -38,6 +38,7 @@
 #include "ks.h"
 #include "ks_internal.h"
 #include "ks_layout.h"
+#include "ks_sched.h"
 
 using namespace ks;
 
@@ -47,48 +48,6 @@ double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator over a device arena, in 256-byte units, with
-// coalescing of neighbouring free ranges.
-class Arena {
-   public:
-    void init(size_t size) {
-        free_.clear();
-        free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = align_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rem = it->second - bytes, noff = it->first + bytes;
-                free_.erase(it);
-                if (rem) free_[noff] = rem;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align_up(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-   private:
-    std::map<size_t, size_t> free_;
-};
 
 // Phases of a request.  Binary64 solves (and the binary64 finish of a
 // mixed-precision request after promotion) go INIT -> BEGIN -> RUN ...;
@@ -132,25 +91,18 @@ constexpr int NO_OUTCOME = -100;
 
 }  // namespace
 
-// The workspaces live in device segments allocated as admission needs them:
-// a request goes first fit into an existing segment, else into a new one of
-// at least SEG_MIN bytes, as long as all segments together stay within the
-// memory budget (the workspaces of the admitted requests never exceed it, so
-// admission is decided by the budget, not by a fixed arena).
-constexpr size_t SEG_MIN = (size_t)1 << 30;
-struct Segment {
-    char *base = nullptr;
-    size_t bytes = 0;
-    Arena arena;
-};
-
+// The workspaces live in device segments allocated as admission needs them
+// (SchedPool): a request goes first fit into an existing segment, else into a
+// new one of at least SCHED_SEG_MIN bytes, as long as all segments together
+// stay within the memory budget (the workspaces of the admitted requests
+// never exceed it, so admission is decided by the budget, not by a fixed
+// arena).
 struct ks_server {
     hipStream_t stream = nullptr;
     size_t budget = 0, in_use = 0;
     int max_inflight = 0;
     int chunk = 16;
-    std::vector<Segment> segs;
-    size_t seg_total = 0;
+    SchedPool pool;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
     std::vector<Req *> inflight;
@@ -188,34 +140,19 @@ int grow_buffers(ks_server *sv, size_t tab_bytes, size_t nstage) {
     return KS_OK;
 }
 
-// A workspace of `bytes` for r: first fit in the segments, else a new segment
-// if the budget allows.  Returns false (nothing allocated) when neither works.
+// A workspace for r in the pool (device segments from hipMalloc).  Returns
+// false (nothing allocated) when none can be placed within the budget.
 bool ws_alloc(ks_server *sv, Req *r) {
-    for (size_t i = 0; i < sv->segs.size(); ++i) {
-        size_t off = 0;
-        if (sv->segs[i].arena.alloc(r->ws_bytes, &off)) {
-            r->seg = (int)i;
-            r->ws_off = off;
-            return true;
-        }
-    }
-    const size_t need = align_up(r->ws_bytes);
-    if (sv->seg_total + need > sv->budget) return false;
-    const size_t bytes = std::min(std::max(need, SEG_MIN), align_up(sv->budget - sv->seg_total));
-    Segment sg;
-    if (hipMalloc((void **)&sg.base, bytes) != hipSuccess) return false;
-    sg.bytes = bytes;
-    sg.arena.init(bytes);
-    size_t off = 0;
-    sg.arena.alloc(r->ws_bytes, &off);
-    sv->segs.push_back(sg);
-    sv->seg_total += bytes;
-    r->seg = (int)sv->segs.size() - 1;
-    r->ws_off = off;
-    return true;
+    auto dev_alloc = [](size_t bytes) -> char * {
+        char *p = nullptr;
+        return hipMalloc((void **)&p, bytes) == hipSuccess ? p : nullptr;
+    };
+    auto dev_free = [](char *p) { (void)hipFree(p); };
+    return sv->pool.place_or_reset(r->ws_bytes, sv->inflight.empty(), dev_alloc, dev_free, &r->seg,
+                                   &r->ws_off);
 }
 
-inline char *ws_base(const ks_server *sv, const Req *r) { return sv->segs[r->seg].base + r->ws_off; }
+inline char *ws_base(const ks_server *sv, const Req *r) { return sv->pool.base(r->seg) + r->ws_off; }
 
 // Builds the per-tick table in pinned host memory: item arrays, then for
 // every (subset, block shape) an index array and a prefix-sum array of block
@@ -326,7 +263,7 @@ void retire(ks_server *sv, Req *r, const State &h, int status, int iters) {
     r->info.outer_iters = r->outer;
     r->info.precision_used = r->prec;
     r->phase = P_DONE;
-    sv->segs[r->seg].arena.release(r->ws_off, r->ws_bytes);
+    sv->pool.release(r->seg, r->ws_off, r->ws_bytes);
     sv->in_use -= r->footprint;
     sv->finished.push_back(r);
 }
@@ -481,6 +418,7 @@ int ks_server_create(ks_server **out, size_t mem_budget_bytes, int32_t max_infli
     if (!sv) return KS_ENOMEM;
     sv->stream = (hipStream_t)stream;
     sv->budget = mem_budget_bytes;
+    sv->pool.set_budget(mem_budget_bytes);
     sv->max_inflight = max_inflight;
     // an even number of steps per tick: the GMRES step counter alternates
     // between two State fields by step parity and ends each tick in kcur
@@ -524,9 +462,10 @@ int ks_server_step(ks_server *sv, int32_t *n_inflight, int32_t *n_queued) {
     if (!sv) return KS_EINVAL;
     hipStream_t s = sv->stream;
     // 1. admission, first come first served
-    while (!sv->queue.empty() && (int)sv->inflight.size() < sv->max_inflight) {
+    while (!sv->queue.empty()) {
         Req *r = sv->queue.front();
-        if (sv->in_use + r->footprint > sv->budget) break;
+        if (!sched_admits(sv->in_use, r->footprint, sv->budget, (int)sv->inflight.size(), sv->max_inflight))
+            break;
         if (!ws_alloc(sv, r)) break;
         sv->in_use += r->footprint;
         char *ws = ws_base(sv, r);
@@ -1027,7 +966,7 @@ void ks_server_free(ks_server *sv) {
     for (Req *r : sv->queue) delete r;
     for (Req *r : sv->inflight) delete r;
     for (Req *r : sv->finished) delete r;
-    for (Segment &sg : sv->segs) (void)hipFree(sg.base);
+    for (const SchedSegment &sg : sv->pool.segments()) (void)hipFree(sg.base);
     if (sv->dtab) (void)hipFree(sv->dtab);
     if (sv->htab) (void)hipHostFree(sv->htab);
     if (sv->dstage) (void)hipFree(sv->dstage);
