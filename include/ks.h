@@ -124,9 +124,12 @@ extern "C" {
 #define KS_FLAG_NO_PERSIST 8 /* binary64 CG at n <= 1024 (not stopping on the
                                 backward error) normally runs every iteration
                                 of a polling interval in one cooperative
-                                launch with a grid barrier between iterations;
-                                this flag runs one launch per iteration instead
-                                (the same iterates bit for bit) */
+                                launch with a grid barrier between iterations,
+                                and the substitutions of the LU and Cholesky
+                                preconditioners (KS_IR_LU32, KS_IR_CHOL32) one
+                                cooperative launch per sweep; this flag runs
+                                one launch per iteration and one per 64-row
+                                step instead (the same results bit for bit) */
 
 typedef struct ks_solver ks_solver; /* opaque, library-owned handle */
 

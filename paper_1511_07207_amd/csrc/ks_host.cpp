@@ -52,6 +52,9 @@ struct ks_solver {
     // GMRES-IR: the binary32 LU in A_low, its pivots, permutation, and the
     // first zero pivot's column + 1 (0: nonsingular)
     int *lu_piv = nullptr, *lu_perm = nullptr, *lu_info = nullptr;
+    // the persistent substitutions' exchange words (null: one launch per
+    // 64-row step, KS_FLAG_NO_PERSIST)
+    uint64_t *ts_xw = nullptr;
     int lu_sing = 0;
     int chol_notpd = 0;  // CG-IR: 1 + the first column with a non-positive pivot
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -92,6 +95,9 @@ int check_device() {
 int sync_state(ks_solver *s) {
     HIPCHK(hipMemcpyAsync(s->host, s->st, 2 * sizeof(State), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    // a persistent kernel's bounded wait gave up (the fused CG, the
+    // preconditioner's substitutions): its results are not to be used
+    if (s->host[0].sync_fail || s->host[1].sync_fail) return KS_EHIP;
     return KS_OK;
 }
 
@@ -668,7 +674,7 @@ int run_gmres_lu(ks_solver *s, const double *rhs, double *d, double tol, int max
     double *t = s->vec64(s->L.nv64 - 2);
     HIPCHK(launch_fill<double>(n, d, 0.0, sm));
     // thresh = tol ||M^-1 rhs||; the residual of d = 0 is M^-1 rhs itself
-    HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, rhs, w, t, s->P.g, sm));
+    HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, rhs, w, t, s->P.g, s->ts_xw, &st->sync_fail, sm));
     HIPCHK(launch_vec_stats<double>(n, w, tol, st, sm, 0));
     HIPCHK(launch_lu_res_finish(n, st, s->P.g, sm));
     int rc = sync_state(s);
@@ -695,7 +701,7 @@ int run_gmres_lu(ks_solver *s, const double *rhs, double *d, double tol, int max
         for (int k = 0; k < m; ++k) {
             HIPCHK((launch_gm_matvec<double, double>(n, s->lda, s->A, V + (size_t)k * ldv, w, st,
                                                      s->P, sm)));
-            HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, sm));
+            HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, s->ts_xw, &st->sync_fail, sm));
             HIPCHK(launch_gm_ortho<double>(n, ldv, V, w, k, st, s->ga, s->P, gemv_blocks<double>(n),
                                            max_iter, sm));
             if ((rc = sync_state(s))) return rc;
@@ -704,7 +710,7 @@ int run_gmres_lu(ks_solver *s, const double *rhs, double *d, double tol, int max
         HIPCHK(launch_gm_finish<double>(n, ldv, V, d, st, s->ga, sm));
         // the preconditioned residual M^-1 (rhs - A d)
         HIPCHK((launch_residual_rows<double, double>(n, s->lda, s->A, rhs, d, w, st, s->P.g, 0, sm)));
-        HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, sm));
+        HIPCHK(launch_lu_apply(n, ldl, LU, s->lu_perm, w, w, t, s->P.g, s->ts_xw, &st->sync_fail, sm));
         HIPCHK(launch_lu_res_finish(n, st, s->P.g, sm));
         if ((rc = sync_state(s))) return rc;
         ++cycles;
@@ -752,7 +758,7 @@ int run_pcg_chol(ks_solver *s, const double *rhs, double *d, double tol, int max
     double *rz_part = s->P.w;
     HIPCHK(launch_fill<double>(n, d, 0.0, sm));
     HIPCHK(launch_vec_stats<double>(n, rhs, tol, st, sm, 0));
-    HIPCHK(launch_chol_apply(n, ldl, L, rhs, z, sm));
+    HIPCHK(launch_chol_apply(n, ldl, L, rhs, z, s->ts_xw, &st->sync_fail, sm));
     HIPCHK(launch_pcg_dot(n, rhs, z, st, rz_part, sm));
     HIPCHK(launch_cg_begin<double>(n, rhs, r, st, sm));  // r = rhs, flags cleared
     HIPCHK(launch_pcg_begin(n, z, p, st, rz_part, sm));
@@ -773,7 +779,7 @@ int run_pcg_chol(ks_solver *s, const double *rhs, double *d, double tol, int max
         if (h->iters >= max_iter) break;
         HIPCHK((launch_cg_matvec<double, double>(n, s->lda, s->A, p, q, st, s->P, sm)));
         HIPCHK(launch_cg_update<double>(n, d, r, p, q, st, s->P, gemv_blocks<double>(n), sm));
-        HIPCHK(launch_chol_apply(n, ldl, L, r, z, sm));
+        HIPCHK(launch_chol_apply(n, ldl, L, r, z, s->ts_xw, &st->sync_fail, sm));
         HIPCHK(launch_pcg_dot(n, r, z, st, rz_part, sm));
         HIPCHK(launch_pcg_pupdate(n, z, p, st, s->P.v, rz_part, max_iter, sm));
         if ((rc = sync_state(s))) return rc;
@@ -1352,6 +1358,8 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
             return KS_EHIP;
         }
     }
+    if ((p->precision == KS_IR_CHOL32 || p->precision == KS_IR_LU32) && !(p->flags & KS_FLAG_NO_PERSIST))
+        s->ts_xw = (uint64_t *)(s->ws + L.lu_off + 2 * (size_t)round_up(p->n, 64) * sizeof(int) + LU_WORK_BYTES);
     if (p->precision == KS_IR_CHOL32 && (rc = chol_setup(s))) {
         ks_free(s);
         return rc;

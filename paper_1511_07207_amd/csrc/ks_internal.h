@@ -216,8 +216,13 @@ constexpr size_t LU_WORK_BYTES = 16384;
 hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work, hipStream_t s);
 // dst = U^-1 L^-1 P src (perm: (P v)_i = v[perm[i]]), t scratch; dst may be
 // src; the squares of dst left in `partial` as the GMRES product leaves them
+// xw: ts_persist_words(n) words of device memory for the persistent sweeps
+// (one cooperative launch per substitution; the per-launch form, n/64
+// launches per substitution, when xw is null), fail: set nonzero if one of
+// their bounded waits gave up (cleared by each application)
+size_t ts_persist_words(int n);
 hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm, const double *src,
-                           double *dst, double *t, double *partial, hipStream_t s);
+                           double *dst, double *t, double *partial, uint64_t *xw, int *fail, hipStream_t s);
 // ||w||_2 from launch_lu_apply's partials into st->rho / res, with the
 // true-residual flags against st->thresh
 hipError_t launch_lu_res_finish(int n, State *st, const double *partial, hipStream_t s);
@@ -233,7 +238,7 @@ constexpr int CH_NB = 64;
 hipError_t launch_chol_factor(int n, int64_t ldl, float *L, int *info, hipStream_t s);
 // dst = L^-T L^-1 src (binary64 vectors, the factor widened); dst may be src
 hipError_t launch_chol_apply(int n, int64_t ldl, const float *L, const double *src, double *dst,
-                             hipStream_t s);
+                             uint64_t *xw, int *fail, hipStream_t s);
 // preconditioned CG pieces: r'z partials (one per vector block), p = z with
 // rho = r'z, and the stop test with p = z + beta p
 hipError_t launch_pcg_dot(int n, const double *r, const double *z, const State *st, double *partial,

@@ -156,9 +156,11 @@ inline Layout make_layout(const ks_params *p) {
     if (p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {
         // pivots, the permutation, the LU factorization's work area (whose
         // first word is its info word; the Cholesky factorization uses one
-        // info word at the start of the region)
+        // info word at the start of the region), then the words the
+        // persistent substitutions exchange
         L.lu_off = off;
-        off = align_up(off + 2 * (size_t)round_up(n, 64) * sizeof(int) + LU_WORK_BYTES);
+        off = align_up(off + 2 * (size_t)round_up(n, 64) * sizeof(int) + LU_WORK_BYTES +
+                       ts_persist_words(n) * sizeof(uint64_t));
     }
     L.lda_low = round_up(n, 64);
     if (p->precision == KS_IR_FP32 || p->precision == KS_IR_LU32 || p->precision == KS_IR_CHOL32) {

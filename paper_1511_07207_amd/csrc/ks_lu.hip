@@ -755,6 +755,220 @@ __global__ __launch_bounds__(GEMV_NT) void lu_bwd_kernel(int n, int64_t ldl,
     if (lane < m) t[r0 + lane] = xi;
 }
 
+// ------------------------------------------- persistent substitutions
+// One cooperative launch per substitution (instead of n/64): row block J of
+// 64 rows belongs to block J mod G of the grid, which applies every solved
+// column block to it and solves its diagonal tile when its turn comes.  In
+// sweep order (forward: row block 0 first; backward: the last first), at
+// position s with row block I solved: the block owning the next position
+// applies x_I to that row block first and solves it at once (the critical
+// path), then every block applies x_I to its other row blocks still ahead.
+// The owner of a row block publishes its x (64 words) with agent-scope
+// relaxed stores, waits for them to complete (vmcnt(0)) and then stores the
+// row block's flag word; in every other block one thread polls that flag
+// (agent-scope relaxed loads, backing off between polls: a flag polled by
+// every thread of every block measured slower than the launches it
+// replaces), and then the block loads x the same way.  The flags start at
+// zero (tp_reset_kernel); the forward sweep sets 1, the backward sweep 2, so
+// a flag left by the other sweep never matches.  The owner of the
+// next position loads that row block's tile of the solved column and its
+// diagonal tile before it waits, so the wait overlaps those loads.  Each
+// column block's contribution to a row is the same butterfly sum as in the
+// per-launch kernels (rows_reduce over eight rows), applied in the same
+// order, so the results are the same bit for bit.  Every wait is bounded;
+// a block that gives up sets *fail and leaves (the other blocks' waits then
+// give up too).
+//
+// Measured per solve (GMRES-IR with the LU, 2 refinement steps): n = 2000
+// 3.09 ms against 3.85 with a launch per step, 4096 6.59 / 8.07, 8192
+// 13.3 / 15.6, 16384 38.8 / 40.8, but 32768 122 / 87.5 (a block per row
+// block, 512 blocks): each step's chain of device-scope round trips (x,
+// its flag, the reads of x and t) costs about as much as a launch does, and
+// at 512 row blocks more.  So the sweeps run persistent up to TP_MAX_NB row
+// blocks and as launches per step beyond.
+constexpr int TP_NT = GEMV_NT;             // threads of a block (4 waves)
+constexpr int TP_MAX_BLOCKS = 256;
+constexpr int TP_MAX_NB = 256;             // row blocks up to which the sweeps are persistent
+constexpr uint32_t TP_SPIN_LIMIT = 1u << 21;
+constexpr int TP_WORDS = 2 * TS_SB;        // words per row block: x (64), the flag (word 64)
+constexpr int TP_BACKOFF = 4;              // s_sleep units between polls of a flag
+static_assert(TP_NT == TS_WAVES * WAVE, "four waves of 16 rows");
+
+size_t ts_persist_words(int n) { return (size_t)div_up(n, TS_SB) * TP_WORDS; }
+
+__global__ __launch_bounds__(VEC_NT) void tp_reset_kernel(uint64_t *xw, size_t count, int *fail) {
+    const size_t i = (size_t)blockIdx.x * VEC_NT + threadIdx.x;
+    if (i < count) xw[i] = 0u;
+    if (i == 0) *fail = 0;
+}
+
+// The diagonal tile of row block J (rows r0 .. r0 + m) into T, widened, with
+// the mask of the sweep: forward unit-lower (strict lower part), forward
+// lower with its diagonal, backward upper with its diagonal; rows past n get
+// a unit diagonal.
+template <bool FWD, bool UNIT>
+__device__ __forceinline__ void tp_load_diag(int n, int64_t ldl, const float *__restrict__ F, int r0, int m,
+                                             double *T) {
+    constexpr int Q = TS_SB / TS_WAVES;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int cc = min(lane, m - 1);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = w + TS_WAVES * q;
+        const double tl = (double)F[(int64_t)(r0 + min(k, m - 1)) * ldl + r0 + cc];
+        double v;
+        if constexpr (FWD && UNIT)
+            v = (k < m && lane < k) ? tl : 0.0;
+        else if constexpr (FWD)
+            v = (k < m && lane < m) ? (lane <= k ? tl : 0.0) : (lane == k ? 1.0 : 0.0);
+        else
+            v = (k < m && lane < m) ? (lane >= k ? tl : 0.0) : (lane == k ? 1.0 : 0.0);
+        T[k * TS_LDT + lane] = v;
+    }
+}
+
+// Wave 0: x of the diagonal tile from acc (the row's right-hand side with
+// every earlier column block applied), as in the per-launch kernels.
+template <bool FWD, bool UNIT>
+__device__ __forceinline__ double tp_diag_solve(const double *T, double acc, int lane) {
+    double xi = 0.0;
+    if constexpr (FWD && UNIT) {
+#pragma unroll
+        for (int j = 0; j < TS_SB; ++j) {
+            const double xj = ts_readlane(acc, j);
+            xi = (lane == j) ? acc : xi;
+            acc = fma(-T[lane * TS_LDT + j], xj, acc);
+        }
+    } else if constexpr (FWD) {
+        const double dinv = 1.0 / T[lane * TS_LDT + lane];
+#pragma unroll
+        for (int j = 0; j < TS_SB; ++j) {
+            const double xc = acc * dinv;
+            const double xj = ts_readlane(xc, j);
+            xi = (lane == j) ? xc : xi;
+            acc = fma(lane > j ? -T[lane * TS_LDT + j] : 0.0, xj, acc);
+        }
+    } else {
+        const double dinv = 1.0 / T[lane * TS_LDT + lane];
+#pragma unroll
+        for (int j = TS_SB - 1; j >= 0; --j) {
+            const double xc = acc * dinv;
+            const double xj = ts_readlane(xc, j);
+            xi = (lane == j) ? xc : xi;
+            acc = fma(lane < j ? -T[lane * TS_LDT + j] : 0.0, xj, acc);
+        }
+    }
+    return xi;
+}
+
+template <bool FWD, bool UNIT>
+__global__ __launch_bounds__(TP_NT) void tp_sweep_kernel(int n, int64_t ldl, const float *__restrict__ F,
+                                                         double *__restrict__ t, uint64_t *__restrict__ xw,
+                                                         int *__restrict__ fail, uint32_t spin_limit) {
+    constexpr int Q = TS_SB / TS_WAVES;  // rows of a tile per wave
+    __shared__ double T[TS_SB * TS_LDT];
+    __shared__ double xs[2][TS_SB];
+    __shared__ double sI[TS_SB];
+    const int nb = div_up(n, TS_SB), G = gridDim.x, b = blockIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const uint32_t tag = FWD ? 1u : 2u;
+    auto blk = [&](int s) { return FWD ? s : nb - 1 - s; };
+    // the block's last sweep position
+    int last = -1;
+    for (int s = nb - 1; s >= 0; --s)
+        if (blk(s) % G == b) {
+            last = s;
+            break;
+        }
+    if (last < 0) return;
+    // t_J -= F(J rows, I columns) x_I for the rows of row block J, with the
+    // tile's values already in pv (wave w rows w Q .. w Q + Q - 1)
+    auto apply = [&](int J, const double (&pv)[Q], const double *x) {
+        const double xl = x[lane];
+        ts_rows_sums(pv, xl, lane, sI + w * Q);
+        __syncthreads();
+        const int rj = J * TS_SB + threadIdx.x;
+        if (threadIdx.x < TS_SB && rj < n) t[rj] -= sI[threadIdx.x];
+        __syncthreads();
+    };
+    auto load_tile = [&](int J, int I, double (&pv)[Q]) {
+        const int r0 = J * TS_SB, m = min(TS_SB, n - r0);
+        const int c = I * TS_SB + lane;
+        const bool cin = c < n;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            pv[q] = cin ? (double)F[(int64_t)(r0 + min(w * Q + q, m - 1)) * ldl + c] : 0.0;
+    };
+    // solve row block J (its t has every earlier column applied), keep x in
+    // xs[buf], write it to t and publish it
+    auto solve = [&](int J, int buf) {
+        const int r0 = J * TS_SB, m = min(TS_SB, n - r0);
+        __syncthreads();
+        if (w == 0) {
+            const double acc = lane < m ? t[r0 + lane] : 0.0;
+            const double xi = tp_diag_solve<FWD, UNIT>(T, acc, lane);
+            const double xv = lane < m ? xi : 0.0;
+            if (lane < m) t[r0 + lane] = xi;
+            xs[buf][lane] = xv;
+            uint64_t *dst = xw + (size_t)J * TP_WORDS;
+            coh_store(dst + lane, __builtin_bit_cast(uint64_t, xv));
+            __builtin_amdgcn_s_waitcnt(WAIT_VMEM);  // x stored before the flag
+            if (lane == 0) coh_store(dst + TS_SB, (uint64_t)tag);
+        }
+        __syncthreads();
+    };
+    // position 0
+    if (blk(0) % G == b) {
+        const int J = blk(0);
+        tp_load_diag<FWD, UNIT>(n, ldl, F, J * TS_SB, min(TS_SB, n - J * TS_SB), T);
+        solve(J, 0);
+    }
+    for (int s = 0; s < last; ++s) {
+        const int I = blk(s), buf = s & 1;
+        const bool mine = I % G == b;
+        const int nx = blk(s + 1);
+        const bool next_mine = nx % G == b;
+        double pv[Q];
+        if (next_mine) {
+            // the critical row block's tile and diagonal tile, before the wait
+            load_tile(nx, I, pv);
+            tp_load_diag<FWD, UNIT>(n, ldl, F, nx * TS_SB, min(TS_SB, n - nx * TS_SB), T);
+        }
+        if (!mine) {
+            // x_I from its owner: thread 0 waits for the flag, then x
+            int late = 0;
+            const uint64_t *src = xw + (size_t)I * TP_WORDS;
+            if (threadIdx.x == 0) {
+                uint32_t polls = 0;
+                while (coh_load(src + TS_SB) != (uint64_t)tag) {
+                    if (++polls > spin_limit) {
+                        late = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(TP_BACKOFF);
+                }
+            }
+            if (__syncthreads_or(late)) {
+                if (threadIdx.x == 0) coh_store(fail, 1);
+                return;
+            }
+            if (threadIdx.x < TS_SB) xs[buf][threadIdx.x] = __builtin_bit_cast(double, coh_load(src + threadIdx.x));
+            __syncthreads();
+        }
+        if (next_mine) {
+            apply(nx, pv, xs[buf]);
+            solve(nx, buf ^ 1);
+        }
+        // the block's other row blocks still ahead of the sweep
+        for (int p = s + 2; p <= last; ++p) {
+            const int J = blk(p);
+            if (J % G != b) continue;
+            load_tile(J, I, pv);
+            apply(J, pv, xs[buf]);
+        }
+    }
+}
+
 // w = t, and the squares of w in the partials the GMRES product leaves (one
 // per pair of rows), so that the Arnoldi step sees ||M^-1 A v||
 __global__ __launch_bounds__(WAVE) void lu_pc_copy_kernel(int n, const double *__restrict__ t,
@@ -848,9 +1062,39 @@ hipError_t launch_lu_factor(int n, int64_t ldl, float *LU, int *piv, void *work,
     return hipGetLastError();
 }
 
+// the two persistent sweeps on t: forward (unit lower or lower with its
+// diagonal), then backward (upper with its diagonal)
+template <bool UNIT>
+static hipError_t launch_tp_sweeps(int n, int64_t ldl, const float *F, double *t, uint64_t *xw, int *fail,
+                                   hipStream_t s) {
+    const int nb = div_up(n, TS_SB);
+    const size_t words = ts_persist_words(n);
+    tp_reset_kernel<<<(unsigned)div_up((int)words, VEC_NT), VEC_NT, 0, s>>>(xw, words, fail);
+    int an = n;
+    int64_t aldl = ldl;
+    const float *aF = F;
+    double *at = t;
+    uint64_t *axw = xw;
+    int *afail = fail;
+    uint32_t spin = TP_SPIN_LIMIT;
+    void *args[] = {&an, &aldl, &aF, &at, &axw, &afail, &spin};
+    const int G = min(nb, TP_MAX_BLOCKS);
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(tp_sweep_kernel<true, UNIT>), dim3(G),
+                                              dim3(TP_NT), args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(tp_sweep_kernel<false, false>), dim3(G),
+                                      dim3(TP_NT), args, 0, s);
+}
+
 hipError_t launch_lu_apply(int n, int64_t ldl, const float *LU, const int *perm, const double *src,
-                           double *dst, double *t, double *partial, hipStream_t s) {
+                           double *dst, double *t, double *partial, uint64_t *xw, int *fail, hipStream_t s) {
     lu_gather_kernel<<<div_up(n, VEC_NT), VEC_NT, 0, s>>>(n, perm, src, t);
+    if (xw && div_up(n, TS_SB) <= TP_MAX_NB) {
+        const hipError_t e = launch_tp_sweeps<true>(n, ldl, LU, t, xw, fail, s);
+        if (e != hipSuccess) return e;
+        lu_pc_copy_kernel<<<gemv_blocks<double>(n), WAVE, 0, s>>>(n, t, dst, partial);
+        return hipGetLastError();
+    }
     const int nb = div_up(n, TS_SB);
     for (int I = 0; I < nb; ++I) {
         const int below = n - (I + 1) * TS_SB;
@@ -873,8 +1117,9 @@ __global__ __launch_bounds__(VEC_NT) void ch_copy_kernel(int n, const double *__
 }
 
 hipError_t launch_chol_apply(int n, int64_t ldl, const float *L, const double *src, double *dst,
-                             hipStream_t s) {
+                             uint64_t *xw, int *fail, hipStream_t s) {
     if (dst != src) ch_copy_kernel<<<div_up(n, VEC_NT), VEC_NT, 0, s>>>(n, src, dst);
+    if (xw && div_up(n, TS_SB) <= TP_MAX_NB) return launch_tp_sweeps<false>(n, ldl, L, dst, xw, fail, s);
     const int nb = div_up(n, TS_SB);
     for (int I = 0; I < nb; ++I) {
         const int below = n - (I + 1) * TS_SB;

@@ -161,3 +161,21 @@ def test_cg_ir_chol_full_size_kappa_1e6(device):
     print(f"  eta (oracle) {m['eta_inf']:.3e}", flush=True)
     assert m["eta_inf"] <= ETA * (1 + 1e-6)
     assert np.linalg.norm(xh - xt) <= 4 * kappa * np.sqrt(n) * ETA * np.linalg.norm(xt) + 1e-12
+
+
+@pytest.mark.parametrize("n", [70, 777, 2048, 16383])
+def test_cg_ir_chol_persistent_substitutions_bitwise(device, n):
+    """The substitutions with L and L^T in one cooperative launch per sweep
+    give the same solve, bit for bit, as one launch per 64-row step."""
+    from paper_1511_07207_amd import krylov
+
+    print(f"cg-ir chol32 persistent vs per-launch substitutions n={n}", flush=True)
+    p = spd_problem(n, 1e5, seed=12, config_id=2, backend="torch", device="cuda")
+    out = []
+    for persist in (True, False):
+        x, info = krylov.solve(p.A, p.b, method="cg", precision="chol32", tol=ETA, max_iter=n,
+                               persist=persist)
+        assert info["status"] == 0, info
+        out.append((x.cpu().numpy(), info["iters"], info["outer_iters"]))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:]

@@ -226,3 +226,22 @@ def test_gmres_ir_lu_full_size_kappa_1e6(device):
     print(f"  eta (oracle) {m['eta_inf']:.3e}", flush=True)
     assert m["eta_inf"] <= 1e-12 * (1 + 1e-6)
     assert np.linalg.norm(xh - xt) <= 4 * kappa * np.sqrt(n) * 1e-12 * np.linalg.norm(xt) + 1e-12
+
+
+@pytest.mark.parametrize("n", [70, 777, 2049, 16384])
+def test_gmres_ir_lu_persistent_substitutions_bitwise(device, n):
+    """The preconditioner's substitutions in one cooperative launch per sweep
+    (a block per row block, up to the 256 row blocks of n = 16384) give the
+    same solve, bit for bit, as one launch per 64-row step."""
+    from paper_1511_07207_amd import krylov
+
+    print(f"gmres-ir lu32 persistent vs per-launch substitutions n={n}", flush=True)
+    p = nonsym_swept_problem(n, 1e6, seed=11, config_id=7, backend="torch", device="cuda")
+    out = []
+    for persist in (True, False):
+        x, info = krylov.solve(p.A, p.b, method="gmres", restart=30, precision="lu32", tol=1e-12,
+                               persist=persist)
+        assert info["status_name"] == "ok", info
+        out.append((x.cpu().numpy(), info["iters"], info["outer_iters"]))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:]
