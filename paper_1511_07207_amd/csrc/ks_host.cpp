@@ -1317,7 +1317,7 @@ int ks_create(ks_solver **out, const ks_params *p, const double *dA, void *d_ws,
     }
     if (p->nrhs > 1) {
         s->mr64 = (double *)(s->ws + L.mr_off);
-        s->mr32 = (float *)(s->ws + L.mr_off + (4 + (size_t)mr_splits(p->n)) * L.mr_block_elems * sizeof(double));
+        s->mr32 = (float *)(s->ws + L.mr_off + (4 + (size_t)mr_splits(p->n, 8)) * L.mr_block_elems * sizeof(double));
         s->cols = (ColState *)(s->ws + L.mr_cols_off);
         s->cols_in = s->cols + KS_MAX_NRHS;
         s->mr_part = (double *)(s->ws + L.mr_part_off);

@@ -513,7 +513,7 @@ hipError_t gather_states(const State *const *d_ptrs, int count, State *staging, 
 
 // ------------------------------------------------ multi-right-hand-side CG
 // n x s column-major blocks with leading dimension ldv; s <= KS_MAX_NRHS.
-int mr_splits(int n);          // K splits of the contraction
+int mr_splits(int n, int elem_bytes);  // K splits of the contraction (8: binary64, 4: binary32)
 int mr_blocks(int n);          // blocks of the per-column kernels
 template <typename T>
 hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T *Qpart, int ldq,

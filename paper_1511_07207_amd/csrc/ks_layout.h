@@ -133,11 +133,11 @@ inline Layout make_layout(const ks_params *p) {
         L.mr_block_elems = (size_t)L.sp16 * L.ldv;
         const size_t es = sizeof(double);
         L.mr_off = off;
-        // X, R, P, Q + mr_splits(n) partial products (binary64); the IR inner
-        // solve adds its binary32 D, R, P, Q and partials below
-        off = align_up(off + (4 + (size_t)mr_splits(n)) * L.mr_block_elems * es);
+        // X, R, P, Q + mr_splits(n, 8) partial products (binary64); the IR
+        // inner solve adds its binary32 D, R, P, Q, rhs and partials below
+        off = align_up(off + (4 + (size_t)mr_splits(n, 8)) * L.mr_block_elems * es);
         if (p->precision == KS_IR_FP32)
-            off = align_up(off + (5 + (size_t)mr_splits(n)) * L.mr_block_elems * sizeof(float));
+            off = align_up(off + (5 + (size_t)mr_splits(n, 4)) * L.mr_block_elems * sizeof(float));
         L.mr_cols_off = off;
         off = align_up(off + 2 * (size_t)KS_MAX_NRHS * sizeof(ColState));
         L.mr_part_count = 3 * (size_t)mr_blocks(n) * KS_MAX_NRHS;

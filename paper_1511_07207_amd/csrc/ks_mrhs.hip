@@ -11,21 +11,25 @@
 //
 // The contraction (binary64: v_mfma_f64_16x16x4f64; binary32 for the refined
 // inner solve: v_mfma_f32_16x16x4f32): a wave owns 32 rows of Q and all s
-// columns (2 x (s/16) accumulator tiles), walks K in steps of 16 and feeds
-// four MFMAs per tile per step.  K is permuted inside each step of 16 so
-// that every lane loads 4 consecutive elements of a row of A and of a column
-// of P (32 contiguous bytes) instead of 4 strided ones; the sum over K is
-// unchanged.  K is split S ways for parallelism (partials summed in fixed
-// order by the next kernel), and blocks are mapped to XCDs so that all blocks
-// of one split run on the same XCDs and that split's slice of P stays in
-// their L2.  Each block stages P's chunks of 64 values of K in LDS (double
-// buffered), shared by its four waves: measured on MI355X at n = 16384,
-// s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the matrix-core peak),
-// binary32 0.60 -> 0.42 ms, the same sums bit for bit.  In binary64 A is
-// loaded three steps ahead of its use (0.64 -> 0.61 ms in the solve, the same
-// sums; binary32 measured slower that way and keeps one step); with A held in
-// registers instead of streamed the same MFMA sequence reaches 0.82 / 0.75 of
-// the peak, so the rest of the gap is the stream of A, not the matrix cores.
+// columns (2 x (s/16) accumulator tiles).  In one MFMA the four lane groups g
+// supply four values of K; which four is free, since the sum over K is the
+// same whatever the order, so K is permuted to make each lane's loads
+// contiguous: binary64 walks K in steps of 16 with lane group g on
+// k = 4g + t (4 doubles = 32 bytes per lane, a whole 128-byte line per row),
+// binary32 in steps of 32 with g on k = 8g + t (8 floats: again a whole line
+// per row in each pair of 16-byte loads).  K is split S ways for parallelism
+// (partials summed in fixed order by the next kernel), and blocks are mapped
+// to XCDs so that all blocks of one split run on the same XCDs and that
+// split's slice of P stays in their L2.  Each block stages P's chunks of 64
+// values of K in LDS (double buffered), shared by its four waves: measured on
+// MI355X at n = 16384, s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the
+// matrix-core peak), the same sums bit for bit.  A streams from HBM a few
+// steps ahead of its use through a queue of registers: binary64 three steps
+// of 16, binary32 four steps of 32.  The binary32 kernel keeps one block per
+// CU (S = 2 at n = 16384) and relies on that queue for its loads in flight:
+// measured 0.39 ms (one step of 16 ahead, S = 8) -> 0.30-0.31 ms (0.70-0.72
+// of the peak); binary64 is fastest at two blocks per CU (S = 4: 0.60 ->
+// 0.57 ms, 0.77 of the peak).
 #include <algorithm>
 
 #include "ks_device.h"
@@ -94,9 +98,11 @@ constexpr int MR_BROWS = MR_WAVES * 32;  // rows of the block that sizes the K s
 constexpr int MR_KC = 64;        // values of K per LDS-staged chunk of P
 constexpr int MR_KPAD = MR_KC + 2;  // padded column stride of the staged chunk (bank spread)
 constexpr int MR_STEPS = MR_KC / 16;  // MFMA steps of 16 per chunk
-constexpr int MR_AHEAD = 3;      // steps of A in flight ahead of the one multiplied
+constexpr int MR_AHEAD = 3;      // binary64: steps of 16 of A in flight ahead of the one multiplied
+constexpr int MR_AHEAD32 = 4;    // binary32: steps of 32 of A in flight ahead
 static_assert(MR_NTHR == 16 * (MR_KC / 4), "each thread stages CT groups of 4 values");
 static_assert(MR_AHEAD < MR_STEPS, "a ring of MR_STEPS register sets for A");
+static_assert(MR_KC % 32 == 0, "binary32 steps of 32 inside a chunk");
 
 // Row tiles (of 16 rows) per wave: two (each value of P read from LDS feeds
 // two MFMAs); one row tile per wave measured no faster for either precision
@@ -165,7 +171,10 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
     // Every lane still takes k = k0 + 4g .. k0 + 4g + 3 per step of 16, in
     // order, so the sums are those of the unstaged loop.
     constexpr int NC = 16 * CT;
-    __shared__ T lp[2][NC * MR_KPAD];
+    // column stride of the staged chunk: binary64 padded by 2 (bank spread),
+    // binary32 by 4 (16-byte aligned columns for 16-byte LDS reads)
+    constexpr int KPAD = sizeof(T) == 8 ? MR_KPAD : MR_KC + 4;
+    __shared__ __attribute__((aligned(16))) T lp[2][NC * KPAD];
     const int nch = (ke - kb) / MR_KC;
     const int ks_end = kb + nch * MR_KC;
     const int ns = nch * MR_STEPS;  // steps inside whole chunks
@@ -187,8 +196,13 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
             for (int j = 0; j < CT; ++j) {
                 const int gi = tid + MR_NTHR * j;
                 const int col = gi / (MR_KC / 4), k4 = (gi % (MR_KC / 4)) * 4;
+                if constexpr (sizeof(T) == 4) {
+                    *reinterpret_cast<mr_f4 *>(&lp[buf][col * KPAD + k4]) =
+                        mr_f4{stg[j][0], stg[j][1], stg[j][2], stg[j][3]};
+                } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) lp[buf][col * MR_KPAD + k4 + t] = stg[j][t];
+                    for (int t = 0; t < 4; ++t) lp[buf][col * KPAD + k4 + t] = stg[j][t];
+                }
             }
         };
         gload(0);
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
                         T pt[CT];
 #pragma unroll
                         for (int ct = 0; ct < CT; ++ct)
-                            pt[ct] = lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g + t];
+                            pt[ct] = lp[buf][(16 * ct + c16) * KPAD + st16 * 16 + 4 * g + t];
 #pragma unroll
                         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -232,40 +246,50 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
                 __syncthreads();
             }
         } else {
-            // binary32: A one step ahead, P's four values of t loaded together
-            // (measured faster for binary32 than the deeper ring)
+            // binary32: steps of 32 values of K, lane group g on k = 8g + t;
+            // A MR_AHEAD32 steps ahead through a queue of register sets
+            // (a[0] is multiplied, a[MR_AHEAD32] receives the newest load)
+            constexpr int SPC = MR_KC / 32;  // steps per chunk
+            const int nsteps = nch * SPC;
+            auto aload = [&](int j, mr_f4 (&dst)[RT][2]) {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + kb + 4 * g, a[rt]);
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        dst[rt][h] = __builtin_nontemporal_load(
+                            reinterpret_cast<const mr_f4 *>(arow[rt] + kb + 32 * j + 8 * g + 4 * h));
+            };
+            mr_f4 aq[MR_AHEAD32 + 1][RT][2];
+#pragma unroll
+            for (int d = 0; d < MR_AHEAD32; ++d)
+                if (d < nsteps) aload(d, aq[d]);
             for (int c = 0; c < nch; ++c) {
                 const int buf = c & 1;
                 if (c + 1 < nch) gload(c + 1);
 #pragma unroll
-                for (int st16 = 0; st16 < MR_STEPS; ++st16) {
-                    const int k0 = kb + c * MR_KC + st16 * 16;
-                    const bool more = k0 + 16 < ks_end;
-                    T an[RT][4];
-                    if (more) {
+                for (int hs = 0; hs < SPC; ++hs) {
+                    const int j = c * SPC + hs;
+                    if (j + MR_AHEAD32 < nsteps) aload(j + MR_AHEAD32, aq[MR_AHEAD32]);
+                    mr_f4 pq[CT][2];
 #pragma unroll
-                        for (int rt = 0; rt < RT; ++rt) M::load4_nt(arow[rt] + k0 + 16 + 4 * g, an[rt]);
-                    }
+                    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) {
-                        const T *q = &lp[buf][(16 * ct + c16) * MR_KPAD + st16 * 16 + 4 * g];
+                        for (int h = 0; h < 2; ++h)
+                            pq[ct][h] = *reinterpret_cast<const mr_f4 *>(
+                                &lp[buf][(16 * ct + c16) * KPAD + 32 * hs + 8 * g + 4 * h]);
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) p[ct][t] = q[t];
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
+                    for (int t = 0; t < 8; ++t)
 #pragma unroll
                         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = M::mma(a[rt][t], p[ct][t], acc[rt][ct]);
-                    if (more) {
+                            for (int ct = 0; ct < CT; ++ct)
+                                acc[rt][ct] = M::mma(aq[0][rt][t / 4][t % 4], pq[ct][t / 4][t % 4], acc[rt][ct]);
+#pragma unroll
+                    for (int d = 0; d < MR_AHEAD32; ++d)
 #pragma unroll
                         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
-                    }
+                            for (int h = 0; h < 2; ++h) aq[d][rt][h] = aq[d + 1][rt][h];
                 }
                 if (c + 1 < nch) lstore(buf ^ 1);
                 __syncthreads();
@@ -318,22 +342,31 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
 }
 
 // ------------------------------------------------------- per-column kernels
-// One thread per row, looping over the s columns; per-column block partials
-// [block][KS_MAX_NRHS] reduced by the next kernel.
+// A block takes MR_NT rows and a group of MR_CG columns (grid rows x column
+// groups): at n = 16384, s = 64 that is 64 x 16 blocks instead of 64 blocks
+// that each walk all s columns.  Each thread handles one row of the group's
+// columns; per-column block partials [row block][KS_MAX_NRHS] are reduced by
+// the next kernel.  A column's partial is the same sum, in the same order,
+// whatever the grouping: the sums do not depend on MR_CG.
 constexpr int MR_NT = 256;
+constexpr int MR_CG = 4;  // columns per block
 
-// per-column sums of `val` over the block's rows, written to part[blockIdx][j]
+__device__ __forceinline__ int mr_j0() { return blockIdx.y * MR_CG; }
+__device__ __forceinline__ int mr_j1(int s) { return min(s, (int)(blockIdx.y + 1) * MR_CG); }
+
+// per-column sums of `val` over the block's rows: one wave sum per wave into red[wave][j]
 __device__ __forceinline__ void mr_col_partial(double val, int j, double (*red)[KS_MAX_NRHS],
-                                               double *part, bool is_max) {
+                                               bool is_max) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const double t = is_max ? wave_max(val) : wave_sum(val);
     if (lane == 0) red[w][j] = t;
 }
 
-__device__ __forceinline__ void mr_col_flush(int s, double (*red)[KS_MAX_NRHS], double *part,
-                                             bool is_max) {
+// the waves' sums of columns [j0, j1), in wave order, to part[blockIdx.x][j]
+__device__ __forceinline__ void mr_col_flush(int j0, int j1, double (*red)[KS_MAX_NRHS],
+                                             double *part, bool is_max) {
     __syncthreads();
-    for (int j = threadIdx.x; j < s; j += MR_NT) {
+    for (int j = j0 + threadIdx.x; j < j1; j += MR_NT) {
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < MR_NT / WAVE; ++q) acc = is_max ? fmax(acc, red[q][j]) : acc + red[q][j];
@@ -342,11 +375,11 @@ __device__ __forceinline__ void mr_col_flush(int s, double (*red)[KS_MAX_NRHS], 
     __syncthreads();
 }
 
-// per-column totals of the partials of the previous kernel, into LDS (all threads)
-__device__ __forceinline__ void mr_col_reduce(int s, const double *part, int nblk, double *out,
-                                              bool is_max) {
+// totals over the nblk row blocks of columns [j0, j1), into LDS (all threads)
+__device__ __forceinline__ void mr_col_reduce(int j0, int j1, const double *part, int nblk,
+                                              double *out, bool is_max) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    for (int j = w; j < s; j += MR_NT / WAVE) {
+    for (int j = j0 + w; j < j1; j += MR_NT / WAVE) {
         double acc = 0.0;
         for (int b = lane; b < nblk; b += WAVE) {
             const double v = part[(size_t)b * KS_MAX_NRHS + j];
@@ -400,8 +433,9 @@ __global__ __launch_bounds__(MR_NT) void mr_resid_kernel(int n, int s, const T *
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     const bool valid = i < n;
     const int sp16 = (s + 15) / 16 * 16;
+    const int j0 = mr_j0(), j1 = mr_j1(s);
     for (int pass = 0; pass < 3; ++pass) {
-        for (int j = 0; j < s; ++j) {
+        for (int j = j0; j < j1; ++j) {
             double val = 0.0;
             if (valid) {
                 if (pass == 2) {
@@ -416,9 +450,9 @@ __global__ __launch_bounds__(MR_NT) void mr_resid_kernel(int n, int s, const T *
                                       : (finite_d((double)r) ? fabs((double)r) : INFINITY);
                 }
             }
-            mr_col_partial(val, j, red, part, pass != 0);
+            mr_col_partial(val, j, red, pass != 0);
         }
-        mr_col_flush(s, red, part + (size_t)pass * gridDim.x * KS_MAX_NRHS, pass != 0);
+        mr_col_flush(j0, j1, red, part + (size_t)pass * gridDim.x * KS_MAX_NRHS, pass != 0);
     }
 }
 
@@ -428,9 +462,9 @@ __global__ __launch_bounds__(MR_NT) void mr_resid_finish_kernel(int s, const dou
                                                                 int gate) {
     __shared__ double v2[KS_MAX_NRHS], vr[KS_MAX_NRHS], vx[KS_MAX_NRHS];
     if (gate == 1 && !(st->flags & F_STOP)) return;
-    mr_col_reduce(s, part, nblk, v2, false);
-    mr_col_reduce(s, part + (size_t)nblk * KS_MAX_NRHS, nblk, vr, true);
-    mr_col_reduce(s, part + (size_t)2 * nblk * KS_MAX_NRHS, nblk, vx, true);
+    mr_col_reduce(0, s, part, nblk, v2, false);
+    mr_col_reduce(0, s, part + (size_t)nblk * KS_MAX_NRHS, nblk, vr, true);
+    mr_col_reduce(0, s, part + (size_t)2 * nblk * KS_MAX_NRHS, nblk, vx, true);
     for (int j = threadIdx.x; j < s; j += MR_NT) {
         ColState &c = cols[j];
         const double res = sqrt(v2[j]);
@@ -454,10 +488,11 @@ __global__ __launch_bounds__(MR_NT) void mr_begin_kernel(int n, int s, const T *
                                                          ColState *cols, State *st,
                                                          uint64_t mask) {
     const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const int j1 = mr_j1(s);
     if (i < n)
-        for (int j = 0; j < s; ++j)
+        for (int j = mr_j0(); j < j1; ++j)
             if ((mask >> j) & 1ull) P[(size_t)j * ldv + i] = R[(size_t)j * ldv + i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         for (int j = 0; j < s; ++j)
             if ((mask >> j) & 1ull) cols[j].flags &= ~INNER_FLAGS;
         st->flags = mask ? 0 : F_STOP;
@@ -475,7 +510,8 @@ __global__ __launch_bounds__(MR_NT) void mr_sigma_kernel(int n, int s, const T *
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     const bool valid = i < n;
     const int sp16 = (s + 15) / 16 * 16;
-    for (int j = 0; j < s; ++j) {
+    const int j0 = mr_j0(), j1 = mr_j1(s);
+    for (int j = j0; j < j1; ++j) {
         double val = 0.0;
         if (valid) {
             T q = 0;
@@ -483,13 +519,16 @@ __global__ __launch_bounds__(MR_NT) void mr_sigma_kernel(int n, int s, const T *
             Q[(size_t)j * ldv + i] = q;
             val = (double)P[(size_t)j * ldv + i] * (double)q;
         }
-        mr_col_partial(val, j, red, part, false);
+        mr_col_partial(val, j, red, false);
     }
-    mr_col_flush(s, red, part, false);
+    mr_col_flush(j0, j1, red, part, false);
 }
 
 // sigma_j from the partials, alpha_j = rho_j / sigma_j; x_j += alpha_j p_j,
-// r_j -= alpha_j q_j for the active columns; r_j' r_j partials.
+// r_j -= alpha_j q_j for the active columns; r_j' r_j partials.  The blocks of
+// row block 0 write their columns' state (rho_prev and sigma, which no block
+// of this kernel reads, and stop flags only where every block finds the
+// column stopped anyway).
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_update_kernel(int n, int s, T *__restrict__ X,
                                                           T *__restrict__ R,
@@ -502,8 +541,9 @@ __global__ __launch_bounds__(MR_NT) void mr_update_kernel(int n, int s, T *__res
     __shared__ double sig[KS_MAX_NRHS], alpha[KS_MAX_NRHS];
     __shared__ int act[KS_MAX_NRHS];
     if (st->flags & F_STOP) return;
-    mr_col_reduce(s, psig, nblk, sig, false);
-    for (int j = threadIdx.x; j < s; j += MR_NT) {
+    const int j0 = mr_j0(), j1 = mr_j1(s);
+    mr_col_reduce(j0, j1, psig, nblk, sig, false);
+    for (int j = j0 + threadIdx.x; j < j1; j += MR_NT) {
         const ColState &c = cols[j];
         const bool active = !(c.flags & F_STOP);
         const bool ok = finite_d(sig[j]) && sig[j] > 0.0;
@@ -520,11 +560,11 @@ __global__ __launch_bounds__(MR_NT) void mr_update_kernel(int n, int s, T *__res
                 cw.flags |= F_BREAK | F_STOP;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->iters += 1;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->iters += 1;
     __syncthreads();
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     const bool valid = i < n;
-    for (int j = 0; j < s; ++j) {
+    for (int j = j0; j < j1; ++j) {
         double val = 0.0;
         if (valid && act[j]) {
             const T a = (T)alpha[j];
@@ -534,12 +574,14 @@ __global__ __launch_bounds__(MR_NT) void mr_update_kernel(int n, int s, T *__res
             R[o] = r;
             val = (double)r * (double)r;
         }
-        mr_col_partial(val, j, red, prho, false);
+        mr_col_partial(val, j, red, false);
     }
-    mr_col_flush(s, red, prho, false);
+    mr_col_flush(j0, j1, red, prho, false);
 }
 
-// rho'_j; per-column stop tests; beta_j and p_j = r_j + beta_j p_j.
+// rho'_j; per-column stop tests; beta_j and p_j = r_j + beta_j p_j.  Block
+// (0, 0) also tests every other column, to set the solve's stop flag when no
+// column is left; the blocks of row block 0 write their own columns' state.
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_pupdate_kernel(int n, int s, const T *__restrict__ R,
                                                            T *__restrict__ P, int ldv,
@@ -549,9 +591,12 @@ __global__ __launch_bounds__(MR_NT) void mr_pupdate_kernel(int n, int s, const T
     __shared__ double rn[KS_MAX_NRHS], beta[KS_MAX_NRHS];
     __shared__ int act[KS_MAX_NRHS];
     if (st->flags & F_STOP) return;
-    mr_col_reduce(s, prho, nblk, rn, false);
+    const int j0 = mr_j0(), j1 = mr_j1(s);
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    const int c0 = lead ? 0 : j0, c1 = lead ? s : j1;
+    mr_col_reduce(c0, c1, prho, nblk, rn, false);
     int mine = 0;
-    for (int j = threadIdx.x; j < s; j += MR_NT) {
+    for (int j = c0 + threadIdx.x; j < c1; j += MR_NT) {
         const ColState &c = cols[j];
         int stop = 0;
         const bool active = !(c.flags & F_STOP);
@@ -566,7 +611,7 @@ __global__ __launch_bounds__(MR_NT) void mr_pupdate_kernel(int n, int s, const T
         act[j] = active && !stop;
         beta[j] = rn[j] / c.rho_prev;
         mine |= act[j];
-        if (blockIdx.x == 0 && active) {
+        if (blockIdx.x == 0 && active && j >= j0 && j < j1) {
             ColState &cw = cols[j];
             if (stop)
                 cw.flags |= stop;
@@ -575,10 +620,10 @@ __global__ __launch_bounds__(MR_NT) void mr_pupdate_kernel(int n, int s, const T
         }
     }
     const int any_active = __syncthreads_or(mine);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && !any_active) st->flags |= F_STOP;
+    if (lead && threadIdx.x == 0 && !any_active) st->flags |= F_STOP;
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     if (i < n)
-        for (int j = 0; j < s; ++j)
+        for (int j = j0; j < j1; ++j)
             if (act[j]) {
                 const size_t o = (size_t)j * ldv + i;
                 P[o] = fma((T)beta[j], P[o], R[o]);
@@ -590,8 +635,9 @@ template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_copy_kernel(int n, int s, const T *__restrict__ src,
                                                         int lds, T *__restrict__ dst, int ldd) {
     const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const int j1 = mr_j1(s);
     if (i < n)
-        for (int j = 0; j < s; ++j) dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
+        for (int j = mr_j0(); j < j1; ++j) dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
 }
 
 // Refinement: inner right-hand sides r_j / ||r_j|| in binary32 (masked
@@ -601,7 +647,8 @@ __global__ __launch_bounds__(MR_NT) void mr_ir_scale_kernel(int n, int s, const 
                                                             const ColState *cols, uint64_t mask) {
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     if (i >= n) return;
-    for (int j = 0; j < s; ++j) {
+    const int j1 = mr_j1(s);
+    for (int j = mr_j0(); j < j1; ++j) {
         const size_t o = (size_t)j * ldv + i;
         rhs[o] = ((mask >> j) & 1ull) ? (float)(R[o] / cols[j].res) : 0.0f;
     }
@@ -612,7 +659,8 @@ __global__ __launch_bounds__(MR_NT) void mr_ir_update_kernel(int n, int s, doubl
                                                              const ColState *cols, uint64_t mask) {
     const int i = blockIdx.x * MR_NT + threadIdx.x;
     if (i >= n) return;
-    for (int j = 0; j < s; ++j)
+    const int j1 = mr_j1(s);
+    for (int j = mr_j0(); j < j1; ++j)
         if ((mask >> j) & 1ull) {
             const size_t o = (size_t)j * ldv + i;
             X[o] = fma(cols[j].res, (double)D[o], X[o]);
@@ -620,24 +668,30 @@ __global__ __launch_bounds__(MR_NT) void mr_ir_update_kernel(int n, int s, doubl
 }
 
 // ------------------------------------------------------------- launchers
+// row blocks x column groups of the per-column kernels
+static dim3 mr_grid(int n, int s) { return dim3(div_up(n, MR_NT), div_up(s, MR_CG)); }
+
 hipError_t launch_mr_ir_scale(int n, int s, const double *R, int ldv, float *rhs,
                               const ColState *cols, uint64_t mask, hipStream_t strm) {
-    mr_ir_scale_kernel<<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, R, ldv, rhs, cols, mask);
+    mr_ir_scale_kernel<<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, R, ldv, rhs, cols, mask);
     return hipGetLastError();
 }
 
 hipError_t launch_mr_ir_update(int n, int s, double *X, const float *D, int ldv,
                                const ColState *cols, uint64_t mask, hipStream_t strm) {
-    mr_ir_update_kernel<<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, X, D, ldv, cols, mask);
+    mr_ir_update_kernel<<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, X, D, ldv, cols, mask);
     return hipGetLastError();
 }
 
-int mr_splits(int n) {
-    // enough work-groups for 256 CUs (>= ~1024) while keeping each split's
-    // slice of K long
+int mr_splits(int n, int elem_bytes) {
+    // Work-groups per CU of the contraction: binary64 two (1024 blocks at
+    // n = 16384 measured slower than 512), binary32 one, its loads in flight
+    // coming from the queue of A steps instead; each split's slice of K is kept
+    // at least 512 long.
+    const int target = elem_bytes == 8 ? 512 : 256;
     const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
     int S = 1;
-    while (S < 8 && nrb * S < 1024 && n / (2 * S) >= 512) S *= 2;
+    while (S < 8 && nrb * S * 2 <= target && n / (2 * S) >= 512) S *= 2;
     return S;
 }
 
@@ -648,7 +702,7 @@ int mr_blocks(int n) { return div_up(n, MR_NT); }
 template <typename T>
 hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T *Qpart, int ldq,
                           int s, const State *st, int gate, hipStream_t strm) {
-    const int S = mr_splits(n), kc = mr_kchunk(n, S);
+    const int S = mr_splits(n, (int)sizeof(T)), kc = mr_kchunk(n, S);
     const int nrb = div_up(n, mr_block_rows<T>());
     const int grid = nrb * S;
     switch ((s + 15) / 16) {
@@ -684,7 +738,7 @@ hipError_t launch_mr_residual(int n, int64_t lda, const T *A, int s, const T *B,
     hipError_t e = launch_mr_gemm<T>(n, lda, A, X, ldv, Qpart, ldv, s, st, gate, strm);
     if (e != hipSuccess) return e;
     const int nb = mr_blocks(n);
-    mr_resid_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, B, ldb, X, Qpart, mr_splits(n), ldv, R, part,
+    mr_resid_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, B, ldb, X, Qpart, mr_splits(n, (int)sizeof(T)), ldv, R, part,
                                                st, gate);
     mr_resid_finish_kernel<<<1, MR_NT, 0, strm>>>(s, part, nb, cols, st, gate);
     return hipGetLastError();
@@ -693,7 +747,7 @@ hipError_t launch_mr_residual(int n, int64_t lda, const T *A, int s, const T *B,
 template <typename T>
 hipError_t launch_mr_begin(int n, int s, const T *R, T *P, int ldv, ColState *cols, State *st,
                            uint64_t mask, hipStream_t strm) {
-    mr_begin_kernel<T><<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, mask);
+    mr_begin_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, mask);
     return hipGetLastError();
 }
 
@@ -706,16 +760,16 @@ hipError_t launch_mr_iteration(int n, int64_t lda, const T *A, int s, T *X, T *R
     if (e0 && (e = hipEventRecord(e0, strm)) != hipSuccess) return e;
     if ((e = launch_mr_gemm<T>(n, lda, A, P, ldv, Qpart, ldv, s, st, 2, strm)) != hipSuccess) return e;
     if (e1 && (e = hipEventRecord(e1, strm)) != hipSuccess) return e;
-    const int nb = mr_blocks(n), S = mr_splits(n);
-    mr_sigma_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, P, Qpart, S, ldv, Q, part_a, st);
-    mr_update_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, X, R, P, Q, ldv, cols, st, part_a, nb, part_b);
-    mr_pupdate_kernel<T><<<nb, MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, part_b, nb, max_iter);
+    const int nb = mr_blocks(n), S = mr_splits(n, (int)sizeof(T));
+    mr_sigma_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, P, Qpart, S, ldv, Q, part_a, st);
+    mr_update_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, X, R, P, Q, ldv, cols, st, part_a, nb, part_b);
+    mr_pupdate_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, R, P, ldv, cols, st, part_b, nb, max_iter);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, hipStream_t strm) {
-    mr_copy_kernel<T><<<mr_blocks(n), MR_NT, 0, strm>>>(n, s, src, lds, dst, ldd);
+    mr_copy_kernel<T><<<mr_grid(n, s), MR_NT, 0, strm>>>(n, s, src, lds, dst, ldd);
     return hipGetLastError();
 }
 
