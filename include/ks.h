@@ -297,6 +297,25 @@ void ks_server_free(ks_server *sv);
 int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *d_A, const void *d_v,
             void *d_y, void *stream);
 
+/* Q = A P for s <= KS_MAX_NRHS columns: the product that the lockstep CG for
+ * many right-hand sides (the Krylov section's CG, one recurrence per column)
+ * shares each iteration, on the matrix cores.  A: n x n row-major, element
+ * type a_dtype: KS_DT_F64 (P, Q binary64, binary64 MFMA) or KS_DT_F32 (P, Q
+ * binary32, binary32 MFMA with binary32 accumulation).  P and Q: column-major
+ * n x s with leading dimension ldv >= n (column j at j * ldv), caller-owned,
+ * Q not overlapping P; only columns 0 .. s-1 and rows 0 .. n-1 of them are
+ * touched.  d_ws: caller-owned device workspace of at least
+ * ks_gemm_mr_workspace_bytes(n, s, a_dtype) bytes (a padded copy of P and the
+ * K-split partial products; overwritten), KS_ENOMEM below that.  d_A and d_ws
+ * 16-byte aligned and lda * sizeof(element) a multiple of 16, else KS_EINVAL
+ * (also for s outside 1 .. KS_MAX_NRHS or another a_dtype).  The sums over K
+ * run in a fixed order: the same inputs give the same Q bit for bit.
+ * Enqueued on `stream`. */
+int ks_gemm_mr_workspace_bytes(int32_t n, int32_t s, int32_t a_dtype, size_t *bytes);
+int ks_gemm_mr(int32_t n, int64_t lda, int32_t a_dtype, const void *d_A, int32_t s,
+               const void *d_P, int64_t ldv, void *d_Q, void *d_ws, size_t ws_bytes,
+               void *stream);
+
 /* Symmetric product y = A x for a symmetric binary64 A, reading only the
  * lower triangle (elements (i, j) with i >= j; the values above the diagonal
  * never affect y).  d_ws: device workspace of at least

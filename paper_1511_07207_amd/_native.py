@@ -31,6 +31,7 @@ STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "breakdown", 3: "stagnated", 4: "nonfi
 # every symbol declared in include/ks.h
 EXPORTS = ("ks_params_init", "ks_workspace_bytes", "ks_workspace_bytes_borrowed", "ks_create",
            "ks_solve", "ks_column_info", "ks_arnoldi", "ks_free", "ks_strerror", "ks_gemv",
+           "ks_gemm_mr_workspace_bytes", "ks_gemm_mr",
            "ks_symv_workspace_bytes", "ks_symv", "ks_symv_f32", "ks_symv_noalloc", "ks_lu32_factor", "ks_chol32_factor", "ks_convert", "ks_read_ceiling", "ks_server_create", "ks_server_submit",
            "ks_server_step", "ks_server_poll", "ks_server_stats", "ks_server_free")
 
@@ -115,6 +116,10 @@ def lib() -> ctypes.CDLL:
         L.ks_strerror.restype = ctypes.c_char_p
         L.ks_gemv.argtypes = [i32, i64, i32, vp, vp, vp, vp]
         L.ks_gemv.restype = ctypes.c_int
+        L.ks_gemm_mr_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+        L.ks_gemm_mr_workspace_bytes.restype = ctypes.c_int
+        L.ks_gemm_mr.argtypes = [i32, i64, i32, vp, i32, vp, i64, vp, vp, sz, vp]
+        L.ks_gemm_mr.restype = ctypes.c_int
         L.ks_symv_workspace_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ks_symv_workspace_bytes.restype = ctypes.c_int
         L.ks_symv.argtypes = [i32, i64, vp, vp, vp, vp, sz, vp]

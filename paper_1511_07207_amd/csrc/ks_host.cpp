@@ -1492,6 +1492,31 @@ int ks_gemv(int32_t n, int64_t lda, int32_t a_dtype, const void *dA, const void 
     return KS_OK;
 }
 
+int ks_gemm_mr_workspace_bytes(int32_t n, int32_t s, int32_t a_dtype, size_t *bytes) {
+    const int es = (a_dtype == KS_DT_F64) ? 8 : (a_dtype == KS_DT_F32) ? 4 : 0;
+    if (n < 1 || s < 1 || s > KS_MAX_NRHS || !es || !bytes) return KS_EINVAL;
+    *bytes = mr_product_ws_bytes(n, s, es);
+    return KS_OK;
+}
+
+int ks_gemm_mr(int32_t n, int64_t lda, int32_t a_dtype, const void *dA, int32_t s, const void *d_P,
+               int64_t ldv, void *d_Q, void *d_ws, size_t ws_bytes, void *stream) {
+    const int es = (a_dtype == KS_DT_F64) ? 8 : (a_dtype == KS_DT_F32) ? 4 : 0;
+    if (n < 1 || lda < n || ldv < n || s < 1 || s > KS_MAX_NRHS || !es || !dA || !d_P || !d_Q ||
+        !d_ws)
+        return KS_EINVAL;
+    if ((uintptr_t)dA % 16 || (lda * es) % 16 || (uintptr_t)d_ws % 16) return KS_EINVAL;
+    if (ws_bytes < mr_product_ws_bytes(n, s, es)) return KS_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    if (es == 8)
+        HIPCHK(launch_mr_product<double>(n, lda, (const double *)dA, s, (const double *)d_P, ldv,
+                                         (double *)d_Q, d_ws, st));
+    else
+        HIPCHK(launch_mr_product<float>(n, lda, (const float *)dA, s, (const float *)d_P, ldv,
+                                        (float *)d_Q, d_ws, st));
+    return KS_OK;
+}
+
 int ks_symv_workspace_bytes(int32_t n, size_t *bytes) {
     if (n < 1 || !bytes) return KS_EINVAL;
     *bytes = sy_ws_doubles(n) * sizeof(double);

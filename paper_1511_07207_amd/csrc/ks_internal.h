@@ -537,6 +537,10 @@ hipError_t launch_mr_iteration(int n, int64_t lda, const T *A, int s, T *X, T *R
                                hipEvent_t e1);
 template <typename T>
 hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, hipStream_t strm);
+size_t mr_product_ws_bytes(int n, int s, int elem_bytes);
+template <typename T>
+hipError_t launch_mr_product(int n, int64_t lda, const T *A, int s, const T *P, int64_t ldv, T *Q,
+                             void *ws, hipStream_t strm);
 hipError_t launch_mr_ir_scale(int n, int s, const double *R, int ldv, float *rhs,
                               const ColState *cols, uint64_t mask, hipStream_t strm);
 hipError_t launch_mr_ir_update(int n, int s, double *X, const float *D, int ldv,

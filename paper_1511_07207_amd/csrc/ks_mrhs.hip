@@ -667,6 +667,29 @@ __global__ __launch_bounds__(MR_NT) void mr_ir_update_kernel(int n, int s, doubl
         }
 }
 
+// The contraction on its own (ks_gemm_mr): the caller's P (s columns,
+// leading dimension ldv) copied to a zero-padded block of sp16 columns with
+// leading dimension ldw, and Q summed from the K-split partials.
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_stage_kernel(int n, int s, int sp16, const T *__restrict__ P,
+                                                         int64_t ldv, T *__restrict__ Pw, int ldw) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < n && j < sp16) Pw[(size_t)j * ldw + i] = j < s ? P[(size_t)j * ldv + i] : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(MR_NT) void mr_qsum_kernel(int n, int s, int sp16, int S,
+                                                        const T *__restrict__ Qpart, int ldw,
+                                                        T *__restrict__ Q, int64_t ldv) {
+    const int i = blockIdx.x * MR_NT + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= n || j >= s) return;
+    T q = 0;
+    for (int k = 0; k < S; ++k) q += Qpart[((size_t)k * sp16 + j) * ldw + i];
+    Q[(size_t)j * ldv + i] = q;
+}
+
 // ------------------------------------------------------------- launchers
 // row blocks x column groups of the per-column kernels
 static dim3 mr_grid(int n, int s) { return dim3(div_up(n, MR_NT), div_up(s, MR_CG)); }
@@ -773,6 +796,26 @@ hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, 
     return hipGetLastError();
 }
 
+// ks_gemm_mr's workspace: the padded P block and the S partial products
+size_t mr_product_ws_bytes(int n, int s, int elem_bytes) {
+    const size_t ldw = round_up(n, 64), sp16 = round_up(s, 16);
+    return (1 + (size_t)mr_splits(n, elem_bytes)) * sp16 * ldw * (size_t)elem_bytes;
+}
+
+template <typename T>
+hipError_t launch_mr_product(int n, int64_t lda, const T *A, int s, const T *P, int64_t ldv, T *Q,
+                             void *ws, hipStream_t strm) {
+    const int ldw = (int)round_up(n, 64), sp16 = (int)round_up(s, 16);
+    const int S = mr_splits(n, (int)sizeof(T));
+    T *Pw = (T *)ws;
+    T *Qpart = Pw + (size_t)sp16 * ldw;
+    mr_stage_kernel<T><<<dim3(div_up(n, MR_NT), sp16), MR_NT, 0, strm>>>(n, s, sp16, P, ldv, Pw, ldw);
+    hipError_t e = launch_mr_gemm<T>(n, lda, A, Pw, ldw, Qpart, ldw, s, nullptr, 0, strm);
+    if (e != hipSuccess) return e;
+    mr_qsum_kernel<T><<<dim3(div_up(n, MR_NT), s), MR_NT, 0, strm>>>(n, s, sp16, S, Qpart, ldw, Q, ldv);
+    return hipGetLastError();
+}
+
 #define KS_INST_MR(T)                                                                           \
     template hipError_t launch_mr_gemm<T>(int, int64_t, const T *, const T *, int, T *, int, int, \
                                           const State *, int, hipStream_t);                      \
@@ -786,7 +829,9 @@ hipError_t launch_mr_copy(int n, int s, const T *src, int lds, T *dst, int ldd, 
     template hipError_t launch_mr_iteration<T>(int, int64_t, const T *, int, T *, T *, T *, T *,  \
                                                T *, int, double *, double *, ColState *, State *, \
                                                int, hipStream_t, hipEvent_t, hipEvent_t);        \
-    template hipError_t launch_mr_copy<T>(int, int, const T *, int, T *, int, hipStream_t);
+    template hipError_t launch_mr_copy<T>(int, int, const T *, int, T *, int, hipStream_t);      \
+    template hipError_t launch_mr_product<T>(int, int64_t, const T *, int, const T *, int64_t, T *, \
+                                             void *, hipStream_t);
 
 KS_INST_MR(double)
 KS_INST_MR(float)

@@ -251,6 +251,32 @@ def gemv(A: torch.Tensor, v: torch.Tensor, y: torch.Tensor | None = None,
     return y
 
 
+def gemm_mr(A: torch.Tensor, P: torch.Tensor, Q: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Q = A P on the matrix cores (the lockstep CG's product).  A: float64 or
+    float32 n x n row-major; P: n x s of A's dtype, s <= 64, stored column by
+    column (P.t() contiguous, as Q is returned)."""
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("gemm_mr: A must be float64 or float32")
+    if P.dtype != A.dtype or P.dim() != 2:
+        raise TypeError("gemm_mr: P must be an n x s matrix of A's dtype")
+    n, s = P.shape
+    Pc = P.t().contiguous()  # s x n: column j of P contiguous
+    dt = N.KS_DT_F64 if A.dtype == torch.float64 else N.KS_DT_F32
+    sz = ctypes.c_size_t(0)
+    N.check(N.lib().ks_gemm_mr_workspace_bytes(int(n), int(s), dt, ctypes.byref(sz)),
+            "ks_gemm_mr_workspace_bytes")
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(sz.value, dtype=torch.uint8, device=A.device)
+    Qc = torch.empty((s, n), dtype=A.dtype, device=A.device)
+    N.check(N.lib().ks_gemm_mr(int(n), int(A.stride(0)), dt, _ptr(A), int(s), _ptr(Pc), int(n),
+                               _ptr(Qc), _ptr(workspace), sz.value, _stream_handle()), "ks_gemm_mr")
+    if Q is None:
+        return Qc.t()
+    Q.copy_(Qc.t())
+    return Q
+
+
 def symv(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
          n: int | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """y = A x for symmetric A (float64, or float32 with float32 x, y and

@@ -229,3 +229,34 @@ def test_symv_noalloc_limits_on_host():
     assert L.ks_symv_noalloc(100, 99, 16, 16, 16, None) == N.KS_EINVAL
     assert L.ks_symv_noalloc(100, 100, None, 16, 16, None) == N.KS_EINVAL
     assert L.ks_symv_noalloc(100, 101, 16, 16, 16, None) == N.KS_EINVAL  # rows not 16-byte aligned
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
+def test_gemm_mr_limits_on_host():
+    """The lockstep contraction entry point: its workspace (a zero-padded copy
+    of P plus one partial product per split of K: 4 for binary64, 2 for
+    binary32 at n = 16384) and its argument checks, all before any device
+    call."""
+    from paper_1511_07207_amd import _native as N
+
+    L = N.lib()
+    sz = ctypes.c_size_t(0)
+    assert L.ks_gemm_mr_workspace_bytes(16384, 64, N.KS_DT_F64, ctypes.byref(sz)) == 0
+    assert sz.value == (1 + 4) * 64 * 16384 * 8
+    assert L.ks_gemm_mr_workspace_bytes(16384, 64, N.KS_DT_F32, ctypes.byref(sz)) == 0
+    assert sz.value == (1 + 2) * 64 * 16384 * 4
+    assert L.ks_gemm_mr_workspace_bytes(777, 5, N.KS_DT_F32, ctypes.byref(sz)) == 0
+    assert sz.value == (1 + 1) * 16 * 832 * 4     # s padded to 16, rows to 64; one split
+    for s in (0, 65):
+        assert L.ks_gemm_mr_workspace_bytes(100, s, N.KS_DT_F64, ctypes.byref(sz)) == N.KS_EINVAL
+    assert L.ks_gemm_mr_workspace_bytes(100, 4, N.KS_DT_BF16, ctypes.byref(sz)) == N.KS_EINVAL
+    big = 1 << 40
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 16, 0, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 16, 65, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 99, N.KS_DT_F64, 16, 4, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 16, 4, 16, 99, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 102, N.KS_DT_F32, 16, 4, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 8, 4, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_BF16, 16, 4, 16, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 16, 4, None, 100, 16, 16, big, None) == N.KS_EINVAL
+    assert L.ks_gemm_mr(100, 100, N.KS_DT_F64, 16, 4, 16, 100, 16, 16, 1024, None) == N.KS_ENOMEM

@@ -112,3 +112,97 @@ def test_lockstep_repeatable(device):
     X2, _ = solver.solve(_t(p.b, device))
     torch.cuda.synchronize()
     assert torch.equal(X1, X2)
+
+
+# ---- the contraction Q = A P on its own (ks_gemm_mr) -------------------------
+# Integer entries small enough that every product and every partial sum is an
+# integer below 2^24: binary32 and binary64 arithmetic are then exact in any
+# summation order, so the product must equal the oracle's column by column
+# bit for bit (a dropped, repeated or misplaced term changes it).  The sizes
+# cover one split of K with a ragged end (777, 1000), several splits with
+# and without the XCD grouping (2100, 4100, 4096) and 1 .. 4 tiles of 16
+# columns.
+
+def _padded(A, device, tdt):
+    """A on the device with its rows 64-element aligned (the entry point wants
+    16-byte row strides); a view of the n x n part."""
+    import torch
+
+    n = A.shape[0]
+    lda = (n + 63) // 64 * 64
+    buf = torch.zeros((n, lda), dtype=tdt, device=device)
+    buf[:, :n] = _t(A, device).to(tdt)
+    return buf[:, :n]
+
+
+def _int_problem(n, s, amax, pmax, seed):
+    rng = np.random.default_rng([seed, n, s])
+    A = rng.integers(-amax, amax + 1, size=(n, n)).astype(np.float64)
+    P = rng.integers(-pmax, pmax + 1, size=(n, s)).astype(np.float64)
+    return A, P
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,s", [(777, 5), (1000, 33), (2100, 64), (4100, 17), (4096, 64)])
+def test_gemm_mr_exact_on_integers(device, dtype, n, s):
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    print(f"gemm_mr exact n={n} s={s} {dtype}", flush=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    A, P = _int_problem(n, s, 2, 3, seed=11)
+    Q = krylov.gemm_mr(_padded(A, device, tdt), _t(P, device).to(tdt)).double().cpu().numpy()
+    for j in range(s):
+        np.testing.assert_array_equal(Q[:, j], oracle.matvec(A, P[:, j]), err_msg=f"column {j}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gemm_mr_rounding_within_bound_and_repeatable(device, dtype):
+    # random values: |q - q_exact| <= gamma_n sum_k |a_ik| |p_kj| for any
+    # summation order (gamma_n = n u / (1 - n u), u the unit roundoff), the
+    # exact value approximated by the oracle's binary64 sums of the same inputs
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n, s = 2100, 40
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((n, n))
+    P = rng.standard_normal((n, s))
+    Ad, Pd = _padded(A, device, tdt), _t(P, device).to(tdt)
+    A_in, P_in = Ad.double().cpu().numpy(), Pd.double().cpu().numpy()  # the values multiplied
+    Q1 = krylov.gemm_mr(Ad, Pd)
+    Q2 = krylov.gemm_mr(Ad, Pd)
+    torch.cuda.synchronize()
+    assert torch.equal(Q1, Q2)
+    Q = Q1.double().cpu().numpy()
+    gamma = n * u / (1 - n * u)
+    gamma64 = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)   # the oracle's own sums
+    absA = np.abs(A_in)
+    for j in range(s):
+        ref = oracle.matvec(A_in, P_in[:, j])
+        bound = (gamma + gamma64) * oracle.matvec(absA, np.abs(P_in[:, j])) * (1 + 1e-9)
+        assert np.all(np.abs(Q[:, j] - ref) <= bound), j
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gemm_mr_full_size_sampled_rows(device, dtype):
+    # the lockstep benchmark's shape (n = 16384, 64 columns) in the launch
+    # configuration the solver uses, entries in {-1, 0, 1}: exact, sampled rows
+    import torch
+
+    from paper_1511_07207_amd import krylov
+
+    n, s = 16384, 64
+    print(f"gemm_mr full size {dtype}", flush=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    A, P = _int_problem(n, s, 1, 1, seed=13)
+    Q = krylov.gemm_mr(_t(A, device).to(tdt), _t(P, device).to(tdt)).double().cpu().numpy()
+    rows = np.sort(np.random.default_rng(14).choice(n, 96, replace=False))
+    rows[-1] = n - 1
+    for j in range(s):
+        np.testing.assert_array_equal(Q[rows, j], oracle.matvec_rows(A, rows, P[:, j]),
+                                      err_msg=f"column {j}")
