@@ -394,55 +394,262 @@ __global__ __launch_bounds__(FZ_NT) void fz_step_small_kernel(
 
 // ---------------------------------------------------------------------------
 // Persistent form (n <= FZ_SMALL_N): one cooperative launch runs up to
-// `nsteps` iterations of fz_small_iteration, the blocks meeting at a grid
-// barrier between iterations instead of at a launch boundary.  The block's
-// eight rows of A are read once per launch and stay in registers.  Each
-// iteration reads and writes exactly what one fz_step_small launch does, so
-// the iterates, the slots and the vectors are bit for bit those of the
-// per-launch path after the same number of iterations.
+// `nsteps` iterations, with the arithmetic of fz_small_iteration in the same
+// order, so the iterates, the slots and the vectors are bit for bit those of
+// the per-launch path after the same number of iterations.  The block's
+// eight rows of A are read once per launch and stay in registers.
 //
-// The blocks meet at grid_barrier (the barrier without cache maintenance):
-// everything one block writes for another (its rows of x, r, p, q, its p'q
-// partials, block 0's slot) is stored with agent-scope relaxed atomics and
-// read back the same way.  The two copies of every vector and partial array
-// alternate by iteration, so a block that runs ahead never overwrites what a
-// slower block still reads.  All blocks take the same stop decision in the
-// same iteration (they reduce the same values in the same order), so none
-// waits for a block that has left.  A wait past `spin_limit` polls records
-// FZ_SYNC_TIMEOUT in st->sync_fail and the blocks leave (the host reports an
-// error); co-residency of the grid is guaranteed by the cooperative launch.
+// Between iterations the blocks depend on each other only through q = A p
+// (each block forms its 8 rows) and the p'q partials (its 4 pairs of rows):
+// r, p, alpha, beta, rho and the stop decision every block forms itself from
+// the same values in the same order, so after the first iteration (whose
+// inputs earlier launches wrote) a block keeps its elements of r and p, and
+// x at its rows, in registers.  q and the partials cross between blocks as
+// tagged 64-bit words, the tag (the iteration) in the high half and one half
+// of the double in the low half, stored and loaded with agent-scope relaxed
+// atomics: a block loads every word it needs until each carries the
+// iteration's tag, so one device-scope round trip both synchronizes the
+// blocks and carries the data (a barrier followed by the loads would take
+// two).  The words of odd and even iterations alternate: a block writes
+// iteration k + 2's words only after reading every block's words of k + 1,
+// which each block writes only after reading all of k's, so none is
+// overwritten before it has been read; the launcher zeroes them, and tags
+// start at 1, so a word of an earlier launch never matches.  The block's
+// rows of x, r, p, q, its partials and block 0's slot are still written every
+// iteration, for whatever reads them after the launch.  All blocks take the
+// same stop decision in the same iteration, so none waits for a block that
+// has left.  A wait past `spin_limit` polls records FZ_SYNC_TIMEOUT in
+// st->sync_fail and the blocks leave (the host reports an error);
+// co-residency of the grid is guaranteed by the cooperative launch.
 constexpr int FZ_SYNC_TIMEOUT = 1;
+
+__device__ __forceinline__ uint64_t fz_word(uint32_t tag, uint32_t half) {
+    return ((uint64_t)tag << 32) | half;
+}
+
+// a double as its two tagged words (low half first)
+__device__ __forceinline__ void fz_publish(uint64_t *dst, uint32_t tag, double v) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    coh_store(dst, fz_word(tag, (uint32_t)bits));
+    coh_store(dst + 1, fz_word(tag, (uint32_t)(bits >> 32)));
+}
 
 __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
     int n, int64_t lda, const double *__restrict__ A, double *__restrict__ x, double *r0, double *r1,
     double *p0, double *p1, double *q0, double *q1, State *st, double *pg0, double *pg1, int cur0,
-    int nsteps, int max_iter, uint32_t *bar, uint32_t spin_limit) {
+    int nsteps, int max_iter, uint32_t *xwords, uint32_t spin_limit) {
+    constexpr int E = FZ_SM_ELEM;
     __shared__ double pnew[FZ_SMALL_N];
     __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
+    const int t = threadIdx.x;
+    const bool lead = blockIdx.x == 0 && t == 0;
+    const int row0 = blockIdx.x * FZ_ROWS;
+    const int ngemv = gemv_blocks<double>(n);
+    const int nd = n + ngemv;  // doubles exchanged per iteration: q, then the partials
+    uint64_t *xw = reinterpret_cast<uint64_t *>(xwords);
     fz_rows_t av;
-    fz_load_rows(n, lda, A, blockIdx.x * FZ_ROWS, av);
+    fz_load_rows(n, lda, A, row0, av);
     int cur = cur0;
+    // the first iteration's inputs, written by earlier launches
+    double rv[E], pv[E], qv[E], xv[E];
+    double pga, pgb;
+    {
+        const double *rc = cur ? r1 : r0, *pc = cur ? p1 : p0, *qc = cur ? q1 : q0;
+        const double *pgc = cur ? pg1 : pg0;
+        pga = fz_ld<true>(&pgc[min(t, ngemv - 1)]);
+        pgb = fz_ld<true>(&pgc[min(t + FZ_NT, ngemv - 1)]);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = min(t + m * FZ_NT, n - 1);
+            rv[m] = fz_ld<true>(&rc[i]);
+            pv[m] = fz_ld<true>(&pc[i]);
+            qv[m] = fz_ld<true>(&qc[i]);
+            xv[m] = fz_ld<true>(&x[i]);
+        }
+    }
+    double rho = fz_ld<true>(&st->fz_rho[cur]);
+    int iters = fz_ld<true>(&st->fz_iters[cur]);
+    const int flags = fz_ld<true>(&st->fz_flags[cur]);
+    const double thresh = st->thresh;
     bool stopped = false;
     for (int k = 0; k < nsteps; ++k) {
-        double *rc = cur ? r1 : r0, *rn = cur ? r0 : r1;
-        double *pc = cur ? p1 : p0, *pn = cur ? p0 : p1;
-        double *qc = cur ? q1 : q0, *qn = cur ? q0 : q1;
-        double *pgc = cur ? pg1 : pg0, *pgn = cur ? pg0 : pg1;
-        stopped = fz_small_iteration<true>(n, av, x, rc, rn, pc, pn, qc, qn, st, pgc, pgn, cur,
-                                           max_iter, pnew, sm_sigma, sm_rho);
-        cur = 1 - cur;
-        if (stopped || k + 1 == nsteps) break;
-        if (!grid_barrier(bar, (uint32_t)(k + 1), spin_limit)) {
-            if (threadIdx.x == 0)
-                __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            return;
+        const int nxt = 1 - cur;
+        double *rn = nxt ? r1 : r0, *pn = nxt ? p1 : p0, *qn = nxt ? q1 : q0;
+        double *pgn = nxt ? pg1 : pg0;
+        if (k > 0) {
+            // q and the partials of iteration k - 1: the thread's elements
+            // t + 256 m of q and partials t, t + 256, until all carry tag k
+            const uint64_t *src = xw + (size_t)(k & 1) * 2 * nd;
+            const uint32_t tag = (uint32_t)k;
+            constexpr int D = E + 2;
+            const uint64_t *wp[D];
+#pragma unroll
+            for (int m = 0; m < E; ++m) wp[m] = t + m * FZ_NT < n ? src + 2 * (t + m * FZ_NT) : nullptr;
+            wp[E] = t < ngemv ? src + 2 * (n + t) : nullptr;
+            wp[E + 1] = t + FZ_NT < ngemv ? src + 2 * (n + t + FZ_NT) : nullptr;
+            uint64_t wv[D][2];
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) wv[d][h] = wp[d] ? coh_load(wp[d] + h) : fz_word(tag, 0u);
+            int late = 0;
+            for (uint32_t polls = 0;; ++polls) {
+                bool all = true;
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) all = all && (uint32_t)(wv[d][h] >> 32) == tag;
+                if (all) break;
+                if (polls >= spin_limit) {
+                    late = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        if ((uint32_t)(wv[d][h] >> 32) != tag) wv[d][h] = coh_load(wp[d] + h);
+            }
+            if (__syncthreads_or(late)) {
+                if (t == 0)
+                    __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            double dv[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                dv[d] = __longlong_as_double((long long)(((wv[d][1] & 0xffffffffull) << 32) |
+                                                         (wv[d][0] & 0xffffffffull)));
+#pragma unroll
+            for (int m = 0; m < E; ++m) qv[m] = dv[m];
+            pga = dv[E];
+            pgb = dv[E + 1];
         }
+        const int it = iters + 1;
+        // ---- sigma, summed as reduce_partials_all sums the partials
+        double sg = 0.0;
+        if (t < ngemv) sg += pga;
+        if (t + FZ_NT < ngemv) sg += pgb;
+        const double sigma = fz_sum_all(sg, sm_sigma);
+        if (flags & F_STOP) {
+            if (lead) {
+                fz_st<true>(&st->fz_rho[nxt], rho);
+                fz_st<true>(&st->fz_iters[nxt], iters);
+                fz_st<true>(&st->fz_flags[nxt], flags);
+            }
+            stopped = true;
+            cur = nxt;
+            break;
+        }
+        if (!(finite_d(sigma) && sigma > 0.0)) {
+            if (lead) {
+                fz_st<true>(&st->fz_rho[nxt], rho);
+                fz_st<true>(&st->fz_iters[nxt], it);
+                fz_st<true>(&st->fz_flags[nxt], flags | F_STOP | (finite_d(sigma) ? F_BREAK : F_NONFIN));
+            }
+            stopped = true;
+            cur = nxt;
+            break;
+        }
+        const double a = rho / sigma;
+        // ---- r' and r'r; x and r' at the block's rows
+        double rr[E];
+        double s2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = t + m * FZ_NT;
+            rr[m] = fma(-a, qv[m], rv[m]);
+            if (i < n) s2 += rr[m] * rr[m];
+            if (i >= row0 && i < row0 + FZ_ROWS && i < n) {
+                xv[m] = fma(a, pv[m], xv[m]);
+                fz_st<true>(&x[i], xv[m]);
+                fz_st<true>(&rn[i], rr[m]);
+            }
+        }
+        const double rho_new = fz_sum_all(s2, sm_rho);
+        int stop = 0;
+        if (!finite_d(rho_new))
+            stop = F_NONFIN | F_STOP;
+        else if (sqrt(rho_new) <= thresh)
+            stop = F_CONV | F_STOP;
+        else if (it >= max_iter)
+            stop = F_MAXIT | F_STOP;
+        if (stop) {
+            if (lead) {
+                fz_st<true>(&st->fz_rho[nxt], rho);
+                fz_st<true>(&st->fz_iters[nxt], it);
+                fz_st<true>(&st->fz_flags[nxt], flags | stop);
+            }
+            stopped = true;
+            cur = nxt;
+            break;
+        }
+        const double beta = rho_new / rho;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = t + m * FZ_NT;
+            pv[m] = fma(beta, pv[m], rr[m]);
+            rv[m] = rr[m];
+            if (i < n) pnew[i] = pv[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = t + m * FZ_NT;
+            if (i >= row0 && i < row0 + FZ_ROWS && i < n) fz_st<true>(&pn[i], pv[m]);
+        }
+        // ---- q' = A p' for the block's rows, each row's columns in rows_dot's order
+        double acc[FZ_ROWS];
+#pragma unroll
+        for (int r = 0; r < FZ_ROWS; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < FZ_SM_CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * t + ch * 2 * FZ_NT + e;
+                if (c < n) {
+                    const double ve = pnew[c];
+#pragma unroll
+                    for (int r = 0; r < FZ_ROWS; ++r) acc[r] = fma(av[r][ch][e], ve, acc[r]);
+                }
+            }
+        const double out = reduce_rows<double, FZ_ROWS, FZ_NT>(acc);
+        uint64_t *dst = xw + (size_t)((k + 1) & 1) * 2 * nd;
+        const uint32_t tag = (uint32_t)(k + 1);
+        if (t < WAVE) {
+            const int row = row0 + t;
+            double contrib = 0.0;
+            if (t < FZ_ROWS && row < n) {
+                fz_st<true>(&qn[row], out);
+                fz_publish(dst + 2 * row, tag, out);
+                contrib = pnew[row] * out;
+            }
+#pragma unroll
+            for (int j = 0; j < FZ_PAIRS; ++j) {
+                const bool mine = (t >> 1) == j;
+                const double ts = wave_sum(mine ? contrib : 0.0);
+                const int gb = row0 / 2 + j;
+                if (t == 0 && 2 * gb < n) {
+                    fz_st<true>(&pgn[gb], ts);
+                    fz_publish(dst + 2 * (n + gb), tag, ts);
+                }
+            }
+        }
+        if (lead) {
+            fz_st<true>(&st->fz_rho[nxt], rho_new);
+            fz_st<true>(&st->fz_iters[nxt], it);
+            fz_st<true>(&st->fz_flags[nxt], flags);
+        }
+        rho = rho_new;
+        iters = it;
+        cur = nxt;
     }
     // the per-launch path would copy the final slot forward in the launches
     // after a stop: the host publishes slot (cur0 + nsteps) % 2, so both
     // slots hold the final values (block 0 wrote the one read here)
-    if (stopped && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (stopped && lead) {
         st->fz_rho[1 - cur] = st->fz_rho[cur];
         st->fz_iters[1 - cur] = st->fz_iters[cur];
         st->fz_flags[1 - cur] = st->fz_flags[cur];
@@ -489,14 +696,14 @@ hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double
 
 int fz_persist_max_n() { return FZ_SMALL_N; }
 
-size_t fz_bar_words(int n) { return (size_t)fz_blocks(n) * FZ_BAR_STRIDE; }
+// the exchange words: two parities of 2 (n + ngemv) 64-bit words
+size_t fz_bar_words(int n) { return (size_t)8 * (n + gemv_blocks<double>(n)); }
 
 hipError_t launch_fz_persist(int n, int64_t lda, const double *A, double *x, double *const vec[6],
                              State *st, double *const pg[2], int cur, int nsteps, int max_iter,
                              uint32_t *bar, uint32_t spin_limit, hipStream_t s) {
     if (n > FZ_SMALL_N || (cur != 0 && cur != 1) || nsteps < 1) return hipErrorInvalidValue;
     const int G = fz_blocks(n);
-    if (G > FZ_NT) return hipErrorInvalidValue;  // one waiting thread per block
     const int words = (int)fz_bar_words(n);
     if (words > FZ_BAR_MAX_WORDS) return hipErrorInvalidValue;
     fz_bar_reset_kernel<<<1, 256, 0, s>>>(bar, words, st);

@@ -362,13 +362,14 @@ hipError_t launch_fz_step(int n, int64_t lda, const double *A, double *x, double
                           State *st, double *const pg[2], int cur, int max_iter, hipStream_t s);
 hipError_t launch_fz_publish(State *st, int which, hipStream_t s);
 // The same iterations in one cooperative launch for n <= fz_persist_max_n():
-// up to nsteps iterations from slot `cur` with a grid barrier between them
-// (the blocks' rows of A read once per launch).  bar: fz_bar_words(n) words
+// up to nsteps iterations from slot `cur`, the blocks exchanging each
+// iteration's q and p'q partials as tagged words (the blocks' rows of A read
+// once per launch).  bar: fz_bar_words(n) 32-bit words for that exchange
 // (reset by the launcher, with st->sync_fail).  Slot (cur + nsteps) % 2 holds
-// the result, as after nsteps fz_step launches.  A bounded barrier wait that
-// gives up sets st->sync_fail.
-constexpr int FZ_BAR_STRIDE = 1;       // words between two blocks' barrier flags
-constexpr int FZ_BAR_MAX_WORDS = 256 * 32;
+// the result, as after nsteps fz_step launches.  A bounded wait that gives up
+// sets st->sync_fail.
+constexpr int FZ_BAR_STRIDE = 1;       // words between two blocks' flags of grid_barrier
+constexpr int FZ_BAR_MAX_WORDS = 256 * 48;
 int fz_persist_max_n();
 size_t fz_bar_words(int n);
 hipError_t launch_fz_persist(int n, int64_t lda, const double *A, double *x, double *const vec[6],
