@@ -441,11 +441,13 @@ __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
     constexpr int E = FZ_SM_ELEM;
     __shared__ double pnew[FZ_SMALL_N];
     __shared__ double sm_sigma[FZ_NT / WAVE], sm_rho[FZ_NT / WAVE];
+    __shared__ int sm_late[FZ_NT / WAVE];  // a wave's wait gave up (read after sigma's barrier)
     const int t = threadIdx.x;
     const bool lead = blockIdx.x == 0 && t == 0;
     const int row0 = blockIdx.x * FZ_ROWS;
     const int ngemv = gemv_blocks<double>(n);
     const int nd = n + ngemv;  // doubles exchanged per iteration: q, then the partials
+    if ((t & (WAVE - 1)) == 0) sm_late[t / WAVE] = 0;
     uint64_t *xw = reinterpret_cast<uint64_t *>(xwords);
     fz_rows_t av;
     fz_load_rows(n, lda, A, row0, av);
@@ -511,12 +513,10 @@ __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
                     for (int h = 0; h < 2; ++h)
                         if ((uint32_t)(wv[d][h] >> 32) != tag) wv[d][h] = coh_load(wp[d] + h);
             }
-            if (__syncthreads_or(late)) {
-                if (t == 0)
-                    __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                return;
-            }
+            // the wave's verdict, read by every thread after the barrier of
+            // sigma's sum below (no barrier of its own)
+            const int wlate = __any(late);
+            if ((t & (WAVE - 1)) == 0) sm_late[t / WAVE] = wlate;
             double dv[D];
 #pragma unroll
             for (int d = 0; d < D; ++d)
@@ -533,6 +533,17 @@ __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
         if (t < ngemv) sg += pga;
         if (t + FZ_NT < ngemv) sg += pgb;
         const double sigma = fz_sum_all(sg, sm_sigma);
+        {
+            int any_late = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < FZ_NT / WAVE; ++w2) any_late |= sm_late[w2];
+            if (any_late) {
+                if (t == 0)
+                    __hip_atomic_store(&st->sync_fail, FZ_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+        }
         if (flags & F_STOP) {
             if (lead) {
                 fz_st<true>(&st->fz_rho[nxt], rho);
