@@ -659,6 +659,8 @@ def leg_c5(dev, count, pool_size, seed=0, rates=(0.5, 0.9)):
             # inner precision: bfloat16 where its copy stays usable (GMRES on
             # D + G/sqrt(n); SPD up to kappa ~ 3e2), binary32 otherwise
             kw["precision"] = "bf16" if (kind == "gmres" or kap <= 3e2) else "fp32"
+            if kw["precision"] == "bf16":
+                kw["inner_tol"] = BF16_INNER_TOL
         return kw
 
     # request i: pool entry, fresh right-hand side b = A x_true
