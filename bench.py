@@ -378,7 +378,8 @@ def leg_f1(dev, n):
             ("gmres30_fp64", dict(method="gmres", restart=30, tol=1e-10)),
             ("bicgstab_fp64_eta", dict(method="bicgstab", tol=1e-12, stop_backward=True)),
             ("bicgstab_fp32_eta", dict(method="bicgstab", tol=1e-12, precision="fp32")),
-            ("bicgstab_bf16_eta", dict(method="bicgstab", tol=1e-12, precision="bf16"))]
+            ("bicgstab_bf16_eta", dict(method="bicgstab", tol=1e-12, precision="bf16",
+                                       inner_tol=BF16_INNER_TOL))]
     for name, kw in runs:
         s = krylov.Solver(prob.A, timing=True, timing_every=TIMING_EVERY, **kw)
         s.solve(prob.b, out=x.zero_())
