@@ -24,8 +24,10 @@
 // values of K in LDS (double buffered), shared by its four waves: measured on
 // MI355X at n = 16384, s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the
 // matrix-core peak), the same sums bit for bit.  A streams from HBM a few
-// steps ahead of its use through a queue of registers: binary64 three steps
-// of 16, binary32 four steps of 32.  The binary32 kernel keeps one block per
+// steps ahead of its use: binary64 three steps of 16 ahead through a ring of
+// four register sets, binary32 four steps of 32 ahead through a queue of
+// five (measured faster, each, than the other's scheme for that precision).
+// The binary32 kernel keeps one block per
 // CU (S = 2 at n = 16384) and relies on that queue for its loads in flight:
 // measured 0.39 ms (one step of 16 ahead, S = 8) -> 0.30-0.31 ms (0.70-0.72
 // of the peak); binary64 is fastest at two blocks per CU (S = 4: 0.60 ->
