@@ -21,17 +21,18 @@
 // (partials summed in fixed order by the next kernel), and blocks are mapped
 // to XCDs so that all blocks of one split run on the same XCDs and that
 // split's slice of P stays in their L2.  Each block stages P's chunks of 64
-// values of K in LDS (double buffered), shared by its four waves: measured on
+// values of K in LDS (double buffered), shared by its waves (four in
+// binary64, eight in binary32): measured on
 // MI355X at n = 16384, s = 64, binary64 0.84 -> 0.66 ms (0.52 -> 0.67 of the
 // matrix-core peak), the same sums bit for bit.  A streams from HBM a few
 // steps ahead of its use: binary64 three steps of 16 ahead through a ring of
 // four register sets, binary32 four steps of 32 ahead through a queue of
 // five (measured faster, each, than the other's scheme for that precision).
-// The binary32 kernel keeps one block per
-// CU (S = 2 at n = 16384) and relies on that queue for its loads in flight:
-// measured 0.39 ms (one step of 16 ahead, S = 8) -> 0.30-0.31 ms (0.70-0.72
-// of the peak); binary64 is fastest at two blocks per CU (S = 4: 0.60 ->
-// 0.57 ms, 0.77 of the peak).
+// The binary32 kernel keeps one block of eight waves per CU (S = 4 at
+// n = 16384) and relies on that queue for its loads in flight: measured
+// 0.39 ms (one step of 16 ahead, four-wave blocks, S = 8) -> 0.30-0.31 ms
+// (0.70-0.72 of the peak); binary64 is fastest at two four-wave blocks per
+// CU (S = 4: 0.60 -> 0.57 ms, 0.77 of the peak).
 #include <algorithm>
 
 #include "ks_device.h"
@@ -94,15 +95,11 @@ struct Mfma<float> {
     }
 };
 
-constexpr int MR_WAVES = 4;      // waves per block
-constexpr int MR_NTHR = MR_WAVES * WAVE;
-constexpr int MR_BROWS = MR_WAVES * 32;  // rows of the block that sizes the K splits
 constexpr int MR_KC = 64;        // values of K per LDS-staged chunk of P
 constexpr int MR_KPAD = MR_KC + 2;  // padded column stride of the staged chunk (bank spread)
 constexpr int MR_STEPS = MR_KC / 16;  // MFMA steps of 16 per chunk
 constexpr int MR_AHEAD = 3;      // binary64: steps of 16 of A in flight ahead of the one multiplied
 constexpr int MR_AHEAD32 = 4;    // binary32: steps of 32 of A in flight ahead
-static_assert(MR_NTHR == 16 * (MR_KC / 4), "each thread stages CT groups of 4 values");
 static_assert(MR_AHEAD < MR_STEPS, "a ring of MR_STEPS register sets for A");
 static_assert(MR_KC % 32 == 0, "binary32 steps of 32 inside a chunk");
 
@@ -113,9 +110,20 @@ template <typename T>
 constexpr int mr_row_tiles() {
     return 2;
 }
+// Waves per block: binary64 four; binary32 eight (two per SIMD at one block
+// per CU, sharing each staged chunk of P: measured 7% faster than four at
+// n = 16384, s = 64, with the same number of blocks).
+template <typename T>
+constexpr int mr_waves() {
+    return sizeof(T) == 4 ? 8 : 4;
+}
+template <typename T>
+constexpr int mr_nthr() {
+    return mr_waves<T>() * WAVE;
+}
 template <typename T>
 constexpr int mr_block_rows() {
-    return MR_WAVES * 16 * mr_row_tiles<T>();
+    return mr_waves<T>() * 16 * mr_row_tiles<T>();
 }
 
 // Block -> (row block, split).  Work-groups are dispatched round-robin over
@@ -135,7 +143,7 @@ __device__ __forceinline__ void mr_block_map(int nrb, int S, int &rb, int &sp) {
 
 // Qpart[sp] = A[:, K_sp] * P[K_sp, :] for the split's K range.
 template <typename T, int CT>
-__global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(2, 8))) void mr_gemm_kernel(int n, int64_t lda,
+__global__ __launch_bounds__(mr_nthr<T>()) __attribute__((amdgpu_waves_per_eu(2, 8))) void mr_gemm_kernel(int n, int64_t lda,
                                                                   const T *__restrict__ A,
                                                                   const T *__restrict__ P, int ldp,
                                                                   T *__restrict__ Qpart, int ldq,
@@ -182,21 +190,27 @@ __global__ __launch_bounds__(MR_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu
     const int ns = nch * MR_STEPS;  // steps inside whole chunks
     T a[RT][4], p[CT][4];
     if (nch > 0) {
-        // staging: value groups of 4 consecutive k, gi = tid + MR_NTHR j
+        // staging: the chunk's NG value groups of 4 consecutive k, group
+        // gi = tid + NTHR j of thread tid
+        constexpr int NTHR = mr_nthr<T>();
+        constexpr int NG = NC * (MR_KC / 4);
+        constexpr int GPT = (NG + NTHR - 1) / NTHR;
         const int tid = threadIdx.x;
-        T stg[CT][4];
+        T stg[GPT][4];
         auto gload = [&](int c) {
 #pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int gi = tid + MR_NTHR * j;
+            for (int j = 0; j < GPT; ++j) {
+                const int gi = tid + NTHR * j;
+                if (NG % NTHR != 0 && gi >= NG) continue;
                 const int col = gi / (MR_KC / 4), k4 = (gi % (MR_KC / 4)) * 4;
                 M::load4(P + (size_t)col * ldp + kb + c * MR_KC + k4, stg[j]);
             }
         };
         auto lstore = [&](int buf) {
 #pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int gi = tid + MR_NTHR * j;
+            for (int j = 0; j < GPT; ++j) {
+                const int gi = tid + NTHR * j;
+                if (NG % NTHR != 0 && gi >= NG) continue;
                 const int col = gi / (MR_KC / 4), k4 = (gi % (MR_KC / 4)) * 4;
                 if constexpr (sizeof(T) == 4) {
                     *reinterpret_cast<mr_f4 *>(&lp[buf][col * KPAD + k4]) =
@@ -714,7 +728,8 @@ int mr_splits(int n, int elem_bytes) {
     // coming from the queue of A steps instead; each split's slice of K is kept
     // at least 512 long.
     const int target = elem_bytes == 8 ? 512 : 256;
-    const int nrb = (n + MR_BROWS - 1) / MR_BROWS;
+    const int brows = elem_bytes == 8 ? mr_block_rows<double>() : mr_block_rows<float>();
+    const int nrb = (n + brows - 1) / brows;
     int S = 1;
     while (S < 8 && nrb * S * 2 <= target && n / (2 * S) >= 512) S *= 2;
     return S;
@@ -732,16 +747,16 @@ hipError_t launch_mr_gemm(int n, int64_t lda, const T *A, const T *P, int ldp, T
     const int grid = nrb * S;
     switch ((s + 15) / 16) {
         case 1:
-            mr_gemm_kernel<T, 1><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            mr_gemm_kernel<T, 1><<<grid, mr_nthr<T>(), 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
             break;
         case 2:
-            mr_gemm_kernel<T, 2><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            mr_gemm_kernel<T, 2><<<grid, mr_nthr<T>(), 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
             break;
         case 3:
-            mr_gemm_kernel<T, 3><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            mr_gemm_kernel<T, 3><<<grid, mr_nthr<T>(), 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
             break;
         case 4:
-            mr_gemm_kernel<T, 4><<<grid, MR_WAVES * WAVE, 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
+            mr_gemm_kernel<T, 4><<<grid, mr_nthr<T>(), 0, strm>>>(n, lda, A, P, ldp, Qpart, ldq, S, kc, st, gate);
             break;
         default:
             return hipErrorInvalidValue;

@@ -234,9 +234,8 @@ def test_symv_noalloc_limits_on_host():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libks.so not built")
 def test_gemm_mr_limits_on_host():
     """The lockstep contraction entry point: its workspace (a zero-padded copy
-    of P plus one partial product per split of K: 4 for binary64, 2 for
-    binary32 at n = 16384) and its argument checks, all before any device
-    call."""
+    of P plus one partial product per split of K: 4 at n = 16384 in either
+    precision) and its argument checks, all before any device call."""
     from paper_1511_07207_amd import _native as N
 
     L = N.lib()
@@ -244,7 +243,7 @@ def test_gemm_mr_limits_on_host():
     assert L.ks_gemm_mr_workspace_bytes(16384, 64, N.KS_DT_F64, ctypes.byref(sz)) == 0
     assert sz.value == (1 + 4) * 64 * 16384 * 8
     assert L.ks_gemm_mr_workspace_bytes(16384, 64, N.KS_DT_F32, ctypes.byref(sz)) == 0
-    assert sz.value == (1 + 2) * 64 * 16384 * 4
+    assert sz.value == (1 + 4) * 64 * 16384 * 4
     assert L.ks_gemm_mr_workspace_bytes(777, 5, N.KS_DT_F32, ctypes.byref(sz)) == 0
     assert sz.value == (1 + 1) * 16 * 832 * 4     # s padded to 16, rows to 64; one split
     for s in (0, 65):
