@@ -513,7 +513,7 @@ __global__ __launch_bounds__(FZ_NT) void fz_persist_kernel(
                     for (int h = 0; h < 2; ++h)
                         if ((uint32_t)(wv[d][h] >> 32) != tag) wv[d][h] = coh_load(wp[d] + h);
             }
-            // the wave's verdict, read by every thread after the barrier of
+            // the wave's timeout flag, read by every thread after the barrier of
             // sigma's sum below (no barrier of its own)
             const int wlate = __any(late);
             if ((t & (WAVE - 1)) == 0) sm_late[t / WAVE] = wlate;
